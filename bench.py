@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark: k-variant combinations scored per second on one MI355X.
+
+One step = the whole search on one dataset already resident in device memory
+(class partition, bit packing, counting + FP32 scoring + filtering, candidate
+selection, FP64 rescoring, final ordering) through fiuncho_scan_batch on a
+stream.  Prints ONE JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+Workloads (seeded synthetic data, see paper_2201_03331_amd/synth.py):
+  order3-1000x6400 (default), order2-100x1600, order2-4000x16000,
+  order4-200x4000, order5-200x4000, batch64 (64 uneven datasets in one call),
+  batch64-plain (the same 64 datasets, one call each).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "k-SNP combinations scored/s (×samples) at order 2/3/4, 1 MI355X, batched vs plain"
+
+# gfx950: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 32-bit VALU lane-ops/s
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+
+def workloads():
+    from paper_2201_03331_amd import synth
+    return {
+        "order3-1000x6400": lambda: [synth.order3_main()],
+        "order2-100x1600": lambda: [synth.order2_small()],
+        "order2-4000x16000": lambda: [synth.order2_dense()],
+        "order4-200x4000": lambda: [synth.high_order(4)],
+        "order5-200x4000": lambda: [synth.high_order(5)],
+        "batch64": lambda: synth.batch_jobs(64),
+        "batch64-plain": lambda: synth.batch_jobs(64),
+    }
+
+
+def word_ops_per_combination(k: int, m0: int, m1: int) -> int:
+    """64-bit AND+popcount operations the counting kernel must execute per
+    combination: 4 per word at order 2 (rows g=0,1 of both variants), 2*3^(k-1)
+    per word at order >= 3 (rows g=0,1 of the last variant against every row of
+    the prefix), over ceil(m0/64) + ceil(m1/64) words."""
+    W = (m0 + 63) // 64 + (m1 + 63) // 64
+    if k == 1:
+        return 0
+    if k == 2:
+        return 4 * W
+    return 2 * 3 ** (k - 1) * W
+
+
+def cpu_baseline(d, budget_s: float = 15.0):
+    """The oracle (plain per-sample counting, FP64 MI) timed on the host cores
+    over a contiguous sample of ranks of the same workload."""
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    total = math.comb(d.n, d.order)
+    probe = min(total, 20000)
+    t0 = time.perf_counter()
+    oracle.scan_range(d.genotypes, d.phenotype, d.order, d.top_n, 0, probe, nthreads=threads)
+    dt = max(time.perf_counter() - t0, 1e-6)
+    count = min(total, max(probe, int(probe * budget_s / dt)))
+    t0 = time.perf_counter()
+    oracle.scan_range(d.genotypes, d.phenotype, d.order, d.top_n, 0, count, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": count / dt, "unit": "combinations/s", "cores": threads, "kind": "oracle",
+            "sample": f"lexicographic ranks [0, {count}) of the same dataset "
+                      f"({count / total:.3g} of C({d.n},{d.order})), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="order3-1000x6400", choices=sorted(workloads().keys()))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of this many MiB (for counter scaling)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the scan would shard by (k-1)-prefix; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2201_03331_amd import fiuncho
+
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        a = torch.ones(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "launches": 5}))
+        return
+
+    datasets = workloads()[args.workload]()
+    plain = args.workload.endswith("-plain")
+    batches = [fiuncho.DeviceBatch([d]) for d in datasets] if plain else [fiuncho.DeviceBatch(datasets)]
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for b in batches:
+            b.run(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    fiuncho.set_profiling(True)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        step()
+    end.record(stream)
+    torch.cuda.synchronize()
+    fiuncho.set_profiling(False)
+    prof = fiuncho.get_profile()
+    ms = start.elapsed_time(end) / args.steps
+
+    # results of the last step: status and the top hit
+    res = [r for b in batches for r in b.results()]
+    ok = all(s == 0 for s, _ in res)
+    combos = sum(math.comb(d.n, d.order) for d in datasets)
+    combos_m = sum(math.comb(d.n, d.order) * d.m for d in datasets)
+    value = combos / (ms / 1e3)
+
+    # roofline of the counting kernel (the dominant one): algorithmic 32-bit
+    # lane-ops (4 per 64-bit AND+popcount) per launch over its measured time
+    lane_ops = 0
+    for d in datasets:
+        m1 = int(d.phenotype.sum())
+        lane_ops += 4 * word_ops_per_combination(d.order, d.m - m1, m1) * math.comb(d.n, d.order)
+    scan_ms = prof["scan_ms"] if not plain else prof["scan_ms"] * len(batches)
+    achieved = lane_ops / (scan_ms / 1e3) / 1e12
+    peak = VALU_PEAK_LANE_OPS / 1e12
+
+    d0 = datasets[0]
+    planted_first = None
+    if len(datasets) == 1 and res[0][1].size:
+        planted = [p for p in d0.planted if len(p) == d0.order]
+        if planted:
+            planted_first = tuple(int(v) for v in res[0][1][0]["snp"][: d0.order]) == planted[0]
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "combinations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "datasets": len(datasets),
+            "snps": d0.n if len(datasets) == 1 else None,
+            "samples": d0.m if len(datasets) == 1 else None,
+            "order": d0.order if len(datasets) == 1 else "2+3",
+            "top_n": d0.top_n,
+            "combinations": combos,
+            "calls_per_step": len(batches),
+        },
+        "combinations_x_samples_per_s": combos_m / (ms / 1e3),
+        "arithmetic": "u64 bitsets, u32 popcount counts, f32 compensated MI, f64 rescoring of the kept",
+        "phases_ms": {k: round(prof[k], 4) for k in ("pack_ms", "scan_ms", "select_ms", "total_ms")},
+        "candidates": prof["candidates"],
+        "rescored": prof["kept"],
+        "status_ok": ok,
+        "planted_first": planted_first,
+        "roofline": {"bound": "alu", "kernel": "scan_kernel (counting + FP32 MI + filter)",
+                     "achieved": achieved, "peak": peak, "unit": "T int32 lane-op/s",
+                     "frac": achieved / peak, "traffic": None},
+    }
+    if not args.no_cpu_baseline and len(datasets) == 1:
+        out["cpu_baseline"] = cpu_baseline(d0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

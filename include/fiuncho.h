@@ -1,0 +1,180 @@
+/*
+ * fiuncho.h -- C ABI of libfiuncho.so, an MI355X (gfx950) implementation of the
+ * exhaustive mutual-information epistasis scan described in
+ *   C. Ponte-Fernandez, J. Gonzalez-Dominguez, M. J. Martin,
+ *   "Fiuncho: a program for any-order epistasis detection in CPU clusters",
+ *   arXiv 2201.03331.
+ *
+ * Problem (section 4, first paragraph; Algorithm 1): given genotypes of n
+ * variants for m samples split into cases and controls, test every combination
+ * of `order` variants for association with the class and report the best.
+ *   - genotype tables / contingency tables: section 3.1 (Fig. 2) and 3.2 (Fig. 3);
+ *   - association score: mutual information, section 3.3 (Eq. 1-3), in nats;
+ *   - result: the `top_n` best combinations (Algorithm 1's output list of S).
+ *
+ * Conventions shared by every entry point
+ *   - genotypes: uint8, row-major [snps][samples], values 0, 1, 2 (number of
+ *     minor alleles); any other value is an error (no missing-data code).
+ *   - phenotype: uint8 [samples], 0 = control, 1 = case; anything else is an error.
+ *   - a combination is a strictly increasing list of 0-based variant indices;
+ *     its rank is its position in lexicographic order among all C(snps, order)
+ *     combinations (the enumeration order of Algorithm 1).
+ *   - contingency table of a combination: 3^order cells x 2 classes, uint32,
+ *     laid out [cell][class]; cell = sum_i g_i * 3^(order-1-i), so the first
+ *     (lowest-index) variant is the most significant digit -- the row order of
+ *     Fig. 2/3.  Class index = phenotype value (Fig. 3 prints cases first).
+ *   - results are ordered by (mi descending, rank ascending); this total order
+ *     makes the kept set unique when scores tie.
+ *   - every call returns FIUNCHO_OK (0) or a negative FIUNCHO_E_* code;
+ *     fiuncho_last_error() then describes the failure.  No C++ exception
+ *     crosses the ABI.  On error *n_out is set to 0 and `out` is not written.
+ *   - the caller owns every buffer; the library keeps no pointer after a call
+ *     returns (plain calls) or after the stream has finished the call's work
+ *     (asynchronous batch calls).
+ *   - the library works on the calling thread's current HIP device.
+ */
+#ifndef FIUNCHO_H
+#define FIUNCHO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FIUNCHO_MAX_ORDER 8
+
+enum {
+  FIUNCHO_OK = 0,
+  FIUNCHO_E_NULL = -1,      /* a required pointer is NULL */
+  FIUNCHO_E_SHAPE = -2,     /* snps == 0, samples == 0 or samples >= 2^24 */
+  FIUNCHO_E_GENOTYPE = -3,  /* a genotype value is not 0, 1 or 2 */
+  FIUNCHO_E_PHENOTYPE = -4, /* a phenotype value is not 0 or 1 */
+  FIUNCHO_E_ORDER = -5,     /* order < 1, order > 8 or order > snps */
+  FIUNCHO_E_TOPN = -6,      /* top_n == 0 or top_n > FIUNCHO_MAX_TOPN */
+  FIUNCHO_E_OVERFLOW = -7,  /* C(snps, order) >= 2^63 */
+  FIUNCHO_E_WORKSPACE = -8, /* workspace too small, or more near-ties at the
+                               cut-off than the candidate buffers hold */
+  FIUNCHO_E_DEVICE = -9     /* a HIP runtime error or no usable gfx950 device */
+};
+
+/* Largest supported top_n. */
+#define FIUNCHO_MAX_TOPN 2048u
+
+/* One reported combination. */
+typedef struct {
+  uint32_t snp[FIUNCHO_MAX_ORDER]; /* ascending variant indices; unused = UINT32_MAX */
+  uint64_t rank;                   /* lexicographic rank in [0, C(snps, order)) */
+  double mi;                       /* mutual information, IEEE double, nats */
+  float mi32;                      /* the single-precision score used for selection */
+  float rel_err;                   /* |mi32 - mi| / mi, 0 when mi == 0 */
+} fiuncho_hit;
+
+/*
+ * fiuncho_scan -- the whole exhaustive search on one dataset (Fig. 1,
+ * Algorithm 1), synchronous.
+ *   genotypes  host pointer, [snps][samples] uint8 (see conventions)
+ *   phenotype  host pointer, [samples] uint8
+ *   order      interaction order k, 1..8
+ *   top_n      how many combinations to report, 1..FIUNCHO_MAX_TOPN
+ *   out        host array of at least top_n hits, written best first
+ *   n_out      receives min(top_n, C(snps, order))
+ * All inputs are validated on the host before any device work.  A dataset with
+ * an empty class has MI = 0 for every combination; the result is then the
+ * first top_n combinations by rank.
+ */
+int fiuncho_scan(const uint8_t *genotypes, const uint8_t *phenotype,
+                 uint32_t snps, uint32_t samples, int order, uint32_t top_n,
+                 fiuncho_hit *out, uint32_t *n_out);
+
+/* One dataset of a batched call. */
+typedef struct {
+  const uint8_t *genotypes; /* [snps][samples]; device pointer with FIUNCHO_DEVICE_PTRS */
+  const uint8_t *phenotype; /* [samples]; device pointer with FIUNCHO_DEVICE_PTRS */
+  uint32_t snps, samples;
+  int order;
+  uint32_t top_n;
+  fiuncho_hit *out;   /* >= top_n hits; device pointer with FIUNCHO_DEVICE_PTRS */
+  uint32_t *n_out;    /* device pointer with FIUNCHO_DEVICE_PTRS */
+  int32_t *status;    /* optional (may be NULL): per-job FIUNCHO_* code; device
+                         pointer with FIUNCHO_DEVICE_PTRS */
+} fiuncho_job;
+
+/* Flags of fiuncho_scan_batch. */
+#define FIUNCHO_DEVICE_PTRS 1u /* all job pointers are device pointers and the
+                                  call returns as soon as the work is queued */
+
+/*
+ * fiuncho_workspace_bytes -- device workspace needed by fiuncho_scan_batch for
+ * these jobs (bitsets, tables, candidate buffers, plan).  Depends only on the
+ * shapes (snps, samples, order, top_n) of the jobs.  Returns 0 for invalid
+ * shapes.
+ */
+size_t fiuncho_workspace_bytes(const fiuncho_job *jobs, uint32_t n_jobs);
+
+/*
+ * fiuncho_scan_batch -- many independent searches in one persistent kernel
+ * launch (the datasets may differ in size, class split and order).
+ *   workspace   device memory of at least fiuncho_workspace_bytes(jobs, n_jobs),
+ *               256-byte aligned, owned by the caller; must not be shared by
+ *               calls that overlap in time
+ *   hip_stream  hipStream_t to queue the work on (NULL = default stream)
+ * Without FIUNCHO_DEVICE_PTRS, the inputs are host arrays, validated on the
+ * host, and the call returns after the results are in the host arrays.
+ * With FIUNCHO_DEVICE_PTRS, inputs and outputs live on the device, genotype and
+ * phenotype values are validated by the kernels (an invalid job reports its
+ * code through job.status and *n_out = 0), and the call only queues work.  The
+ * first call with a given workspace and job set uploads a plan (lookup tables,
+ * tile tables) synchronously; later calls with the same workspace and job set
+ * queue kernels only, so they can be captured into a HIP graph and replayed.
+ */
+int fiuncho_scan_batch(const fiuncho_job *jobs, uint32_t n_jobs, uint32_t flags,
+                       void *workspace, size_t ws_bytes, void *hip_stream);
+
+/*
+ * fiuncho_contingency -- contingency tables of explicit combinations
+ * (section 3.2, Fig. 3).
+ *   genotypes, phenotype  host arrays as in fiuncho_scan
+ *   ranks      host array of n_ranks lexicographic ranks, each < C(snps, order)
+ *   tables     host array of n_ranks * 3^order * 2 uint32, [rank][cell][class]
+ * Synchronous.  Counts come from the same bit-packed genotype tables and
+ * AND/popcount device code as the search.
+ */
+int fiuncho_contingency(const uint8_t *genotypes, const uint8_t *phenotype,
+                        uint32_t snps, uint32_t samples, int order,
+                        const uint64_t *ranks, uint64_t n_ranks, uint32_t *tables);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *fiuncho_last_error(void);
+
+/* Per-phase device times (milliseconds), averaged over the fiuncho_scan_batch
+ * calls made on this thread with profiling enabled since the last
+ * fiuncho_get_profile; see fiuncho_set_profiling. */
+typedef struct {
+  float pack_ms;      /* class partition + bit packing */
+  float scan_ms;      /* counting + FP32 scoring + candidate filter (one kernel) */
+  float select_ms;    /* candidate selection, FP64 rescoring, final order */
+  float total_ms;     /* all of the above, first kernel start to last kernel end */
+  uint32_t calls;        /* profiled calls averaged */
+  uint32_t flags;        /* 4 = some |mi32 - mi| exceeded 1e-5 mi + 1e-10 (last call, first job) */
+  uint64_t combinations; /* sum of C(snps, order) over the jobs of the last call */
+  uint64_t candidates;   /* candidates the scan appended (last call, first job) */
+  uint32_t kept;         /* candidates rescored in double precision (last call, first job) */
+  uint32_t reserved;
+} fiuncho_profile;
+
+/* Enable (1) or disable (0) HIP-event timing of the phases of later
+ * fiuncho_scan_batch calls on this thread (four events per call, recorded on
+ * the call's stream). */
+void fiuncho_set_profiling(int enable);
+
+/* Collects (synchronising on their events) and clears the timings of the
+ * profiled calls; FIUNCHO_E_NULL when there is none. */
+int fiuncho_get_profile(fiuncho_profile *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIUNCHO_H */

@@ -1,0 +1,702 @@
+// api.hip -- the C ABI of libfiuncho: validation, workspace layout, the plan
+// (lookup and tile tables), kernel sequencing and result hand-back.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using fiuncho::Cand;
+using fiuncho::Globals;
+using fiuncho::JobDesc;
+using fiuncho::JobState;
+using fiuncho::Rescored;
+
+namespace {
+
+typedef unsigned long long u64;
+
+thread_local std::string t_err;
+thread_local bool t_profiling = false;
+
+int fail(int code, const std::string &msg) {
+  t_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(FIUNCHO_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+u64 binom_host(u64 n, u64 k) {
+  if (k > n) return 0;
+  if (k > n - k) k = n - k;
+  unsigned __int128 r = 1;
+  for (u64 i = 1; i <= k; ++i) {
+    r = r * (unsigned __int128)(n - k + i) / i;
+    if (r > (unsigned __int128)~0ull) return ~0ull;
+  }
+  return (u64)r;
+}
+
+u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------------------
+// validation of one job's shape (values are checked separately)
+// ---------------------------------------------------------------------------
+int check_shape(const fiuncho_job &j, bool need_ptrs) {
+  if (need_ptrs && (!j.genotypes || !j.phenotype || !j.out || !j.n_out))
+    return fail(FIUNCHO_E_NULL, "a required pointer is NULL");
+  if (j.snps == 0 || j.samples == 0) return fail(FIUNCHO_E_SHAPE, "snps and samples must be positive");
+  if (j.samples >= (1u << 24)) return fail(FIUNCHO_E_SHAPE, "samples must be below 2^24");
+  if (j.order < 1 || j.order > FIUNCHO_MAX_ORDER || (uint32_t)j.order > j.snps)
+    return fail(FIUNCHO_E_ORDER, "order must be in [1, min(snps, 8)]");
+  if (j.top_n == 0 || j.top_n > FIUNCHO_MAX_TOPN)
+    return fail(FIUNCHO_E_TOPN, "top_n must be in [1, " + std::to_string(FIUNCHO_MAX_TOPN) + "]");
+  if (binom_host(j.snps, (u64)j.order) >= (1ull << 63))
+    return fail(FIUNCHO_E_OVERFLOW, "C(snps, order) must be below 2^63");
+  return FIUNCHO_OK;
+}
+
+int check_values(const uint8_t *G, const uint8_t *y, uint32_t n, uint32_t m) {
+  const size_t total = (size_t)n * m;
+  for (size_t i = 0; i < total; ++i)
+    if (G[i] > 2)
+      return fail(FIUNCHO_E_GENOTYPE, "genotype value " + std::to_string(G[i]) + " at variant " +
+                                          std::to_string(i / m) + ", sample " + std::to_string(i % m));
+  for (uint32_t s = 0; s < m; ++s)
+    if (y[s] > 1)
+      return fail(FIUNCHO_E_PHENOTYPE, "phenotype value " + std::to_string(y[s]) + " at sample " +
+                                           std::to_string(s));
+  return FIUNCHO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tile tables: rows and tiles per row, as the scan kernel decodes them
+// ---------------------------------------------------------------------------
+void build_rows(uint32_t n, uint32_t k, std::vector<u64> &row_start) {
+  row_start.clear();
+  row_start.push_back(0);
+  u64 acc = 0;
+  if (k == 1) {
+    acc = ceil_div(n, (u64)fiuncho::kScanWaves * 64);
+    row_start.push_back(acc);
+    return;
+  }
+  if (k == 2) {
+    const u64 S = (u64)fiuncho::kScanWaves * fiuncho::kOrder2Prefixes;
+    const u64 rows = ceil_div(n - 1, S);
+    for (u64 r = 0; r < rows; ++r) {
+      const u64 a_first = r * S;
+      acc += ceil_div(n - 1 - a_first, 64);
+      row_start.push_back(acc);
+    }
+    return;
+  }
+  for (u64 b = k - 2; b + 2 <= n; ++b) {
+    const u64 groups = ceil_div(binom_host(b, k - 2), fiuncho::kScanWaves);
+    acc += groups * ceil_div(n - 1 - b, 64);
+    row_start.push_back(acc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+struct JobLayout {
+  uint32_t n, m, k, top_n, n_pad, wcap, nrows;
+  u64 total;
+  uint32_t cand_cap, l1_cap, l2_cap;
+  size_t off_G, off_y, off_idx, off_Bv, off_Bs, off_marg, off_hist, off_cand, off_l1, off_l2,
+      off_state, off_out, off_nout, off_status;
+  // plan (uploaded)
+  size_t off_rows, off_F32, off_P64;
+  std::vector<u64> row_start;
+  u64 tiles;
+  double cost;  // per-tile cost estimate, for ordering
+};
+
+struct Layout {
+  std::vector<JobLayout> jobs;
+  std::vector<uint32_t> order;  // tile-space order of the jobs (costliest first)
+  uint32_t nmax, kmax, max_n_pad, max_cand_cap, max_l2_cap;
+  size_t plan_begin, plan_end;  // uploaded region
+  size_t off_desc, off_jts, off_binom, off_counter;
+  size_t total;
+  int ksel;
+};
+
+int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint32_t cap_mult,
+                Layout &L) {
+  if (!jobs || n_jobs == 0) return fail(FIUNCHO_E_NULL, "no jobs");
+  L.jobs.assign(n_jobs, JobLayout());
+  L.nmax = 0;
+  L.kmax = 0;
+  L.max_n_pad = 0;
+  L.max_cand_cap = 0;
+  L.max_l2_cap = 0;
+  size_t off = 0;
+  // per-job data
+  for (uint32_t i = 0; i < n_jobs; ++i) {
+    int st = check_shape(jobs[i], false);
+    if (st) return st;
+    JobLayout &J = L.jobs[i];
+    J.n = jobs[i].snps;
+    J.m = jobs[i].samples;
+    J.k = (uint32_t)jobs[i].order;
+    J.top_n = jobs[i].top_n;
+    J.total = binom_host(J.n, J.k);
+    J.n_pad = (uint32_t)((J.n + 63) / 64 * 64 + 64);
+    J.wcap = (J.m + 63) / 64 + 2;
+    u64 cap = std::max<u64>(1ull << 20, 256ull * J.top_n) * cap_mult;
+    cap = std::min<u64>(cap, J.total);
+    cap = std::min<u64>(cap, 1ull << 31);
+    J.cand_cap = (uint32_t)std::max<u64>(cap, 1);
+    J.l1_cap = J.cand_cap;
+    J.l2_cap = fiuncho::kSortMax;
+    build_rows(J.n, J.k, J.row_start);
+    J.nrows = (uint32_t)(J.row_start.size() - 1);
+    J.tiles = J.row_start.back();
+    const double words = (double)J.wcap;
+    J.cost = J.k == 1 ? 1.0 : J.k == 2 ? words * 4 * fiuncho::kOrder2Prefixes
+                                        : words * 18 * std::pow(3.0, (double)J.k - 3);
+    L.nmax = std::max(L.nmax, J.n);
+    L.kmax = std::max(L.kmax, J.k);
+    L.max_n_pad = std::max(L.max_n_pad, J.n_pad);
+    L.max_cand_cap = std::max(L.max_cand_cap, J.cand_cap);
+    L.max_l2_cap = std::max(L.max_l2_cap, J.l2_cap);
+
+    auto take = [&](size_t bytes) {
+      size_t o = off;
+      off = align256(off + bytes);
+      return o;
+    };
+    J.off_G = host_inputs ? take((size_t)J.n * J.m) : 0;
+    J.off_y = host_inputs ? take(J.m) : 0;
+    J.off_idx = take(sizeof(uint32_t) * J.m);
+    J.off_Bv = take(sizeof(u64) * (size_t)J.wcap * J.n_pad * 2);
+    J.off_Bs = take(sizeof(u64) * (size_t)J.n * 4 * J.wcap);
+    J.off_marg = take(sizeof(uint32_t) * (size_t)J.n * 6);
+    J.off_hist = take(sizeof(uint32_t) * fiuncho::kHistBins);
+    J.off_cand = take(sizeof(Cand) * (size_t)J.cand_cap);
+    J.off_l1 = take(sizeof(Cand) * (size_t)J.l1_cap);
+    J.off_l2 = take(sizeof(Rescored) * (size_t)J.l2_cap);
+    J.off_state = take(sizeof(JobState));
+    J.off_out = host_inputs ? take(sizeof(fiuncho_hit) * J.top_n) : 0;
+    J.off_nout = host_inputs ? take(sizeof(uint32_t)) : 0;
+    J.off_status = host_inputs ? take(sizeof(int32_t)) : 0;
+  }
+  // plan region
+  L.plan_begin = off;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.off_desc = take(sizeof(JobDesc) * n_jobs);
+  L.off_jts = take(sizeof(u64) * (n_jobs + 1));
+  L.off_binom = take(sizeof(u64) * ((size_t)L.nmax + 1) * fiuncho::kBinomStride);
+  for (uint32_t i = 0; i < n_jobs; ++i) {
+    JobLayout &J = L.jobs[i];
+    J.off_rows = take(sizeof(u64) * J.row_start.size());
+    J.off_F32 = take(sizeof(float2) * ((size_t)J.m + 1));
+    J.off_P64 = take(sizeof(double) * ((size_t)J.m + 1));
+  }
+  L.plan_end = off;
+  L.off_counter = take(sizeof(u64));
+  L.total = off;
+  // tile-space order: costliest tiles first, so that cheap ones fill the tail
+  L.order.resize(n_jobs);
+  for (uint32_t i = 0; i < n_jobs; ++i) L.order[i] = i;
+  std::stable_sort(L.order.begin(), L.order.end(),
+                   [&](uint32_t a, uint32_t b) { return L.jobs[a].cost > L.jobs[b].cost; });
+  L.ksel = (int)L.jobs[0].k;
+  for (auto &J : L.jobs)
+    if ((int)J.k != L.ksel) L.ksel = 0;
+  if (L.ksel > 5) L.ksel = 0;
+  return FIUNCHO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// plan: descriptors and lookup tables, built on the host
+// ---------------------------------------------------------------------------
+struct PlanCache {
+  std::vector<uint8_t> bytes;  // last uploaded plan region
+};
+std::mutex g_plan_mu;
+std::map<std::pair<int, const void *>, PlanCache> g_plans;
+
+void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host_inputs,
+                std::vector<uint8_t> &plan) {
+  plan.assign(L.plan_end - L.plan_begin, 0);
+  auto at = [&](size_t off) { return plan.data() + (off - L.plan_begin); };
+  const uint32_t n_jobs = (uint32_t)L.jobs.size();
+  // binomial table
+  u64 *bt = reinterpret_cast<u64 *>(at(L.off_binom));
+  for (uint32_t a = 0; a <= L.nmax; ++a)
+    for (int r = 0; r < fiuncho::kBinomStride; ++r)
+      bt[(size_t)a * fiuncho::kBinomStride + r] = binom_host(a, (u64)r);
+  // job tile starts, in tile-space order
+  u64 *jts = reinterpret_cast<u64 *>(at(L.off_jts));
+  std::vector<u64> begin(n_jobs);
+  u64 acc = 0;
+  for (uint32_t p = 0; p < n_jobs; ++p) {
+    const uint32_t i = L.order[p];
+    jts[p] = acc;
+    begin[i] = acc;
+    acc += L.jobs[i].tiles;
+  }
+  jts[n_jobs] = acc;
+  JobDesc *desc = reinterpret_cast<JobDesc *>(at(L.off_desc));
+  for (uint32_t p = 0; p < n_jobs; ++p) {
+    const uint32_t i = L.order[p];
+    const JobLayout &J = L.jobs[i];
+    JobDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.n = J.n;
+    d.m = J.m;
+    d.k = J.k;
+    d.top_n = J.top_n;
+    d.n_pad = J.n_pad;
+    d.wcap = J.wcap;
+    d.nrows = J.nrows;
+    d.flags = host_inputs ? 0u : 1u;
+    d.total = J.total;
+    d.tile_begin = begin[i];
+    d.tile_count = J.tiles;
+    d.G = host_inputs ? ws + J.off_G : jobs[i].genotypes;
+    d.y = host_inputs ? ws + J.off_y : jobs[i].phenotype;
+    d.idx = reinterpret_cast<uint32_t *>(ws + J.off_idx);
+    d.Bv = reinterpret_cast<u64 *>(ws + J.off_Bv);
+    d.Bs = reinterpret_cast<u64 *>(ws + J.off_Bs);
+    d.marg = reinterpret_cast<uint32_t *>(ws + J.off_marg);
+    d.F32 = reinterpret_cast<const float2 *>(ws + J.off_F32);
+    d.P64 = reinterpret_cast<const double *>(ws + J.off_P64);
+    d.row_start = reinterpret_cast<const u64 *>(ws + J.off_rows);
+    d.hist = reinterpret_cast<uint32_t *>(ws + J.off_hist);
+    d.cand = reinterpret_cast<Cand *>(ws + J.off_cand);
+    d.cand_cap = J.cand_cap;
+    d.l1_cap = J.l1_cap;
+    d.l1 = reinterpret_cast<Cand *>(ws + J.off_l1);
+    d.l2 = reinterpret_cast<Rescored *>(ws + J.off_l2);
+    d.l2_cap = J.l2_cap;
+    d.state = reinterpret_cast<JobState *>(ws + J.off_state);
+    d.out = host_inputs ? reinterpret_cast<fiuncho_hit *>(ws + J.off_out) : jobs[i].out;
+    d.n_out = host_inputs ? reinterpret_cast<uint32_t *>(ws + J.off_nout) : jobs[i].n_out;
+    d.status_out = host_inputs ? reinterpret_cast<int32_t *>(ws + J.off_status) : jobs[i].status;
+    std::memcpy(&desc[p], &d, sizeof(d));
+    // tile rows
+    std::memcpy(at(J.off_rows), J.row_start.data(), sizeof(u64) * J.row_start.size());
+    // f(t) = t ln t as a float pair, and (t/m) ln(t/m) in double
+    float2 *F = reinterpret_cast<float2 *>(at(J.off_F32));
+    double *P = reinterpret_cast<double *>(at(J.off_P64));
+    F[0] = make_float2(0.f, 0.f);
+    P[0] = 0.0;
+    for (uint32_t t = 1; t <= J.m; ++t) {
+      const double f = (double)t * std::log((double)t);
+      const float hi = (float)f;
+      const float lo = (float)(f - (double)hi);
+      F[t] = make_float2(hi, lo);
+      const double p = (double)t / (double)J.m;
+      P[t] = p * std::log(p);
+    }
+  }
+}
+
+Globals make_globals(const Layout &L, uint8_t *ws) {
+  Globals g;
+  g.binom = reinterpret_cast<const u64 *>(ws + L.off_binom);
+  g.nmax = L.nmax;
+  g.n_jobs = (uint32_t)L.jobs.size();
+  g.jobs = reinterpret_cast<const JobDesc *>(ws + L.off_desc);
+  g.job_tile_start = reinterpret_cast<const u64 *>(ws + L.off_jts);
+  g.total_tiles = 0;
+  for (auto &J : L.jobs) g.total_tiles += J.tiles;
+  g.tile_counter = reinterpret_cast<u64 *>(ws + L.off_counter);
+  return g;
+}
+
+int upload_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host_inputs,
+                hipStream_t stream) {
+  std::vector<uint8_t> plan;
+  build_plan(L, jobs, ws, host_inputs, plan);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  PlanCache &pc = g_plans[std::make_pair(dev, (const void *)ws)];
+  if (pc.bytes == plan) return FIUNCHO_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(stream, &cs));
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(FIUNCHO_E_WORKSPACE,
+                "the plan for this workspace and job set is not uploaded yet: call once "
+                "before capturing the stream");
+  HIP_TRY(hipMemcpyAsync(ws + L.plan_begin, plan.data(), plan.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  pc.bytes.swap(plan);
+  return FIUNCHO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device check
+// ---------------------------------------------------------------------------
+int check_device() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(FIUNCHO_E_DEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return fail(FIUNCHO_E_DEVICE, hipGetErrorString(e));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(FIUNCHO_E_DEVICE, std::string("libfiuncho is built for gfx950, device is ") + prop.gcnArchName);
+  return FIUNCHO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// profiling events
+// ---------------------------------------------------------------------------
+// one profiled call: events before pack, before scan, before select, at end
+struct ProfCall {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  u64 combos = 0;
+  JobState *state0 = nullptr;
+};
+thread_local std::vector<ProfCall> t_calls;   // recorded, not yet collected
+thread_local std::vector<hipEvent_t> t_free;  // event pool
+thread_local ProfCall *t_cur = nullptr;
+
+int prof_begin(u64 combos, JobState *state0) {
+  t_cur = nullptr;
+  if (!t_profiling) return FIUNCHO_OK;
+  t_calls.emplace_back();
+  ProfCall &c = t_calls.back();
+  for (int i = 0; i < 4; ++i) {
+    if (!t_free.empty()) {
+      c.ev[i] = t_free.back();
+      t_free.pop_back();
+    } else {
+      HIP_TRY(hipEventCreate(&c.ev[i]));
+    }
+  }
+  c.combos = combos;
+  c.state0 = state0;
+  t_cur = &c;
+  return FIUNCHO_OK;
+}
+
+int prof_record(int i, hipStream_t s) {
+  if (!t_cur) return FIUNCHO_OK;
+  HIP_TRY(hipEventRecord(t_cur->ev[i], s));
+  return FIUNCHO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the pipeline on an uploaded plan
+// ---------------------------------------------------------------------------
+int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
+  const Globals g = make_globals(L, ws);
+  int st;
+  u64 combos = 0;
+  for (auto &J : L.jobs) combos += J.total;
+  if ((st = prof_begin(combos, reinterpret_cast<JobState *>(ws + L.jobs[0].off_state)))) return st;
+  if ((st = prof_record(0, s))) return st;
+  fiuncho::launch_init(g, s);
+  fiuncho::launch_pack(g, L.max_n_pad, s);
+  if ((st = prof_record(1, s))) return st;
+  int grid = fiuncho::scan_grid_size(L.ksel);
+  if ((u64)grid > g.total_tiles) grid = (int)std::max<u64>(g.total_tiles, 1);
+  fiuncho::launch_scan(g, L.ksel, grid, s);
+  if ((st = prof_record(2, s))) return st;
+  fiuncho::launch_select(g, L.max_cand_cap, s);
+  fiuncho::launch_rescore(g, L.max_l2_cap, L.kmax, s);
+  fiuncho::launch_finish(g, s);
+  if ((st = prof_record(3, s))) return st;
+  HIP_TRY(hipGetLastError());
+  return FIUNCHO_OK;
+}
+
+int batch_impl(const fiuncho_job *jobs, uint32_t n_jobs, uint32_t flags, void *workspace,
+               size_t ws_bytes, hipStream_t stream, uint32_t cap_mult, bool *cand_overflow) {
+  if (cand_overflow) *cand_overflow = false;
+  if (!jobs || n_jobs == 0) return fail(FIUNCHO_E_NULL, "no jobs");
+  if (!workspace) return fail(FIUNCHO_E_NULL, "workspace is NULL");
+  if (((uintptr_t)workspace) & 255) return fail(FIUNCHO_E_WORKSPACE, "workspace must be 256-byte aligned");
+  const bool host_inputs = !(flags & FIUNCHO_DEVICE_PTRS);
+  for (uint32_t i = 0; i < n_jobs; ++i) {
+    int st = check_shape(jobs[i], true);
+    if (st) return st;
+    if (host_inputs) {
+      st = check_values(jobs[i].genotypes, jobs[i].phenotype, jobs[i].snps, jobs[i].samples);
+      if (st) return st;
+    }
+  }
+  int st = check_device();
+  if (st) return st;
+  Layout L;
+  st = make_layout(jobs, n_jobs, host_inputs, cap_mult, L);
+  if (st) return st;
+  if (ws_bytes < L.total)
+    return fail(FIUNCHO_E_WORKSPACE, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
+                                         std::to_string(L.total));
+  uint8_t *ws = static_cast<uint8_t *>(workspace);
+  st = upload_plan(L, jobs, ws, host_inputs, stream);
+  if (st) return st;
+  if (host_inputs) {
+    for (uint32_t i = 0; i < n_jobs; ++i) {
+      const JobLayout &J = L.jobs[i];
+      HIP_TRY(hipMemcpyAsync(ws + J.off_G, jobs[i].genotypes, (size_t)J.n * J.m, hipMemcpyHostToDevice, stream));
+      HIP_TRY(hipMemcpyAsync(ws + J.off_y, jobs[i].phenotype, J.m, hipMemcpyHostToDevice, stream));
+    }
+  }
+  st = run_pipeline(L, ws, stream);
+  if (st) return st;
+  if (!host_inputs) return FIUNCHO_OK;
+  // bring the results back
+  std::vector<uint32_t> nout(n_jobs);
+  std::vector<int32_t> status(n_jobs);
+  std::vector<JobState> states(n_jobs);
+  for (uint32_t i = 0; i < n_jobs; ++i) {
+    const JobLayout &J = L.jobs[i];
+    HIP_TRY(hipMemcpyAsync(&nout[i], ws + J.off_nout, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(&status[i], ws + J.off_status, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(&states[i], ws + J.off_state, sizeof(JobState), hipMemcpyDeviceToHost, stream));
+  }
+  HIP_TRY(hipStreamSynchronize(stream));
+  int first_err = FIUNCHO_OK;
+  for (uint32_t i = 0; i < n_jobs; ++i) {
+    const JobLayout &J = L.jobs[i];
+    if (status[i] != 0) {
+      *jobs[i].n_out = 0;
+      if (jobs[i].status) *jobs[i].status = status[i];
+      if (states[i].flags & fiuncho::kFlagCandOverflow) {
+        if (cand_overflow) *cand_overflow = true;
+      }
+      if (first_err == FIUNCHO_OK) {
+        first_err = status[i];
+        if (states[i].flags & fiuncho::kFlagCandOverflow)
+          fail(status[i], "candidate buffer overflow in job " + std::to_string(i));
+        else if (states[i].flags & fiuncho::kFlagTieOverflow)
+          fail(status[i], "more than " + std::to_string(fiuncho::kSortMax) +
+                              " candidates tie within tolerance at the cut-off in job " + std::to_string(i));
+        else
+          fail(status[i], "job " + std::to_string(i) + " failed on the device");
+      }
+      continue;
+    }
+    if (nout[i] > J.top_n) return fail(FIUNCHO_E_DEVICE, "device returned too many results");
+    HIP_TRY(hipMemcpy(jobs[i].out, ws + J.off_out, sizeof(fiuncho_hit) * nout[i], hipMemcpyDeviceToHost));
+    *jobs[i].n_out = nout[i];
+    if (jobs[i].status) *jobs[i].status = 0;
+  }
+  return first_err;
+}
+
+// library-owned workspace for the plain (synchronous, host pointer) calls
+struct OwnedWs {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+std::map<int, OwnedWs> g_ws;
+
+int owned_workspace(size_t need, void **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  OwnedWs &w = g_ws[dev];
+  if (w.bytes < need) {
+    if (w.ptr) {
+      // drop the plan cache entry of the old buffer
+      {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        g_plans.erase(std::make_pair(dev, (const void *)w.ptr));
+      }
+      HIP_TRY(hipFree(w.ptr));
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    HIP_TRY(hipMalloc(&w.ptr, need));
+    w.bytes = need;
+  }
+  *out = w.ptr;
+  return FIUNCHO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fiuncho_last_error(void) { return t_err.c_str(); }
+
+void fiuncho_set_profiling(int enable) { t_profiling = enable != 0; }
+
+int fiuncho_get_profile(fiuncho_profile *out) {
+  if (!out) return fail(FIUNCHO_E_NULL, "out is NULL");
+  if (t_calls.empty()) return fail(FIUNCHO_E_NULL, "no profiled call on this thread");
+  double a = 0, b = 0, c = 0, d = 0;
+  for (ProfCall &pc : t_calls) {
+    HIP_TRY(hipEventSynchronize(pc.ev[3]));
+    float x = 0;
+    HIP_TRY(hipEventElapsedTime(&x, pc.ev[0], pc.ev[1]));
+    a += x;
+    HIP_TRY(hipEventElapsedTime(&x, pc.ev[1], pc.ev[2]));
+    b += x;
+    HIP_TRY(hipEventElapsedTime(&x, pc.ev[2], pc.ev[3]));
+    c += x;
+    HIP_TRY(hipEventElapsedTime(&x, pc.ev[0], pc.ev[3]));
+    d += x;
+  }
+  const double n = (double)t_calls.size();
+  const ProfCall &last = t_calls.back();
+  JobState s0;
+  HIP_TRY(hipMemcpy(&s0, last.state0, sizeof(JobState), hipMemcpyDeviceToHost));
+  out->pack_ms = (float)(a / n);
+  out->scan_ms = (float)(b / n);
+  out->select_ms = (float)(c / n);
+  out->total_ms = (float)(d / n);
+  out->calls = (uint32_t)t_calls.size();
+  out->combinations = last.combos;
+  out->candidates = s0.cand_count;
+  out->kept = s0.l2_count;
+  out->flags = s0.flags;
+  for (ProfCall &pc : t_calls)
+    for (int i = 0; i < 4; ++i) t_free.push_back(pc.ev[i]);
+  t_calls.clear();
+  t_cur = nullptr;
+  return FIUNCHO_OK;
+}
+
+size_t fiuncho_workspace_bytes(const fiuncho_job *jobs, uint32_t n_jobs) {
+  Layout L;
+  if (make_layout(jobs, n_jobs, false, 1, L) != FIUNCHO_OK) return 0;
+  return L.total;
+}
+
+int fiuncho_scan_batch(const fiuncho_job *jobs, uint32_t n_jobs, uint32_t flags, void *workspace,
+                       size_t ws_bytes, void *hip_stream) {
+  t_err.clear();
+  try {
+    return batch_impl(jobs, n_jobs, flags, workspace, ws_bytes, (hipStream_t)hip_stream, 1, nullptr);
+  } catch (const std::exception &e) {
+    return fail(FIUNCHO_E_DEVICE, std::string("internal error: ") + e.what());
+  } catch (...) {
+    return fail(FIUNCHO_E_DEVICE, "internal error");
+  }
+}
+
+int fiuncho_scan(const uint8_t *genotypes, const uint8_t *phenotype, uint32_t snps,
+                 uint32_t samples, int order, uint32_t top_n, fiuncho_hit *out,
+                 uint32_t *n_out) {
+  t_err.clear();
+  if (n_out) *n_out = 0;
+  try {
+    fiuncho_job job;
+    job.genotypes = genotypes;
+    job.phenotype = phenotype;
+    job.snps = snps;
+    job.samples = samples;
+    job.order = order;
+    job.top_n = top_n;
+    job.out = out;
+    job.n_out = n_out;
+    job.status = nullptr;
+    int st = check_shape(job, true);
+    if (st) return st;
+    st = check_values(genotypes, phenotype, snps, samples);
+    if (st) return st;
+    st = check_device();
+    if (st) return st;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    for (uint32_t mult = 1; mult <= 64; mult *= 8) {
+      Layout L;
+      st = make_layout(&job, 1, true, mult, L);
+      if (st) return st;
+      void *ws = nullptr;
+      st = owned_workspace(L.total, &ws);
+      if (st) return st;
+      bool overflow = false;
+      st = batch_impl(&job, 1, 0, ws, L.total, nullptr, mult, &overflow);
+      if (!(st == FIUNCHO_E_WORKSPACE && overflow)) return st;
+    }
+    return st;
+  } catch (const std::exception &e) {
+    return fail(FIUNCHO_E_DEVICE, std::string("internal error: ") + e.what());
+  } catch (...) {
+    return fail(FIUNCHO_E_DEVICE, "internal error");
+  }
+}
+
+int fiuncho_contingency(const uint8_t *genotypes, const uint8_t *phenotype, uint32_t snps,
+                        uint32_t samples, int order, const uint64_t *ranks, uint64_t n_ranks,
+                        uint32_t *tables) {
+  t_err.clear();
+  try {
+    fiuncho_job job;
+    std::memset(&job, 0, sizeof(job));
+    job.genotypes = genotypes;
+    job.phenotype = phenotype;
+    job.snps = snps;
+    job.samples = samples;
+    job.order = order;
+    job.top_n = 1;
+    if (!genotypes || !phenotype || (n_ranks && (!ranks || !tables)))
+      return fail(FIUNCHO_E_NULL, "a required pointer is NULL");
+    int st = check_shape(job, false);
+    if (st) return st;
+    st = check_values(genotypes, phenotype, snps, samples);
+    if (st) return st;
+    const u64 total = binom_host(snps, (u64)order);
+    for (uint64_t i = 0; i < n_ranks; ++i)
+      if (ranks[i] >= total)
+        return fail(FIUNCHO_E_SHAPE, "rank " + std::to_string(ranks[i]) + " is not below C(snps, order)");
+    if (n_ranks == 0) return FIUNCHO_OK;
+    st = check_device();
+    if (st) return st;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Layout L;
+    st = make_layout(&job, 1, true, 1, L);
+    if (st) return st;
+    uint64_t cells = 1;
+    for (int q = 0; q < order; ++q) cells *= 3;
+    const size_t rank_off = align256(L.total);
+    const size_t tab_off = align256(rank_off + sizeof(u64) * n_ranks);
+    const size_t need = tab_off + sizeof(uint32_t) * 2 * cells * n_ranks;
+    void *wsv = nullptr;
+    st = owned_workspace(need, &wsv);
+    if (st) return st;
+    uint8_t *ws = static_cast<uint8_t *>(wsv);
+    hipStream_t s = nullptr;
+    // outputs of the scan part are unused; point them into the workspace
+    fiuncho_job j2 = job;
+    st = upload_plan(L, &j2, ws, true, s);
+    if (st) return st;
+    const JobLayout &J = L.jobs[0];
+    HIP_TRY(hipMemcpyAsync(ws + J.off_G, genotypes, (size_t)snps * samples, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ws + J.off_y, phenotype, samples, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ws + rank_off, ranks, sizeof(u64) * n_ranks, hipMemcpyHostToDevice, s));
+    const Globals g = make_globals(L, ws);
+    fiuncho::launch_init(g, s);
+    fiuncho::launch_pack(g, L.max_n_pad, s);
+    fiuncho::launch_tables(g, reinterpret_cast<const u64 *>(ws + rank_off), n_ranks,
+                           reinterpret_cast<uint32_t *>(ws + tab_off), s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(tables, ws + tab_off, sizeof(uint32_t) * 2 * cells * n_ranks,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return FIUNCHO_OK;
+  } catch (const std::exception &e) {
+    return fail(FIUNCHO_E_DEVICE, std::string("internal error: ") + e.what());
+  } catch (...) {
+    return fail(FIUNCHO_E_DEVICE, "internal error");
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// device_common.hpp -- small device helpers shared by the libfiuncho kernels.
+#pragma once
+
+#include "internal.hpp"
+
+namespace fiuncho {
+
+typedef unsigned long long u64;
+
+// Address-space qualified views.  Data that no kernel writes while the scan
+// runs (bitsets, tables) is read through the constant address space, so that
+// wave-uniform addresses become scalar loads into scalar registers; per-lane
+// data is read through the global address space (no flat-address checks).
+#define FI_CONST __attribute__((address_space(4)))
+#define FI_GLOBAL __attribute__((address_space(1)))
+typedef const FI_CONST u64 *cu64p;
+typedef const FI_CONST uint32_t *cu32p;
+typedef const FI_GLOBAL u64 *gu64p;
+
+template <typename T>
+__device__ __forceinline__ const FI_CONST T *as_const(const T *p) {
+  return (const FI_CONST T *)p;
+}
+template <typename T>
+__device__ __forceinline__ const FI_GLOBAL T *as_global(const T *p) {
+  return (const FI_GLOBAL T *)p;
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ u64 uni64(u64 v) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((u64)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ u64 ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint32_t popc64(u64 x) { return (uint32_t)__popcll(x); }
+
+// acc + popcount(x) as two v_bcnt_u32_b32, each taking the running count as
+// its addend (the compiler otherwise reassociates into bcnt, bcnt, add3)
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+  uint32_t r;
+  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+  return r;
+}
+__device__ __forceinline__ uint32_t add_popc64(uint32_t acc, u64 x) {
+  return bcnt_acc((uint32_t)(x >> 32), bcnt_acc((uint32_t)x, acc));
+}
+
+// C(a, r) from the host-built table; 0 when a < r
+__device__ __forceinline__ u64 binom(const Globals &g, uint32_t a, uint32_t r) {
+  return g.binom[(size_t)a * kBinomStride + r];
+}
+
+// relaxed loads that read the device-coherent copy (other workgroups update it)
+__device__ __forceinline__ uint32_t load_relaxed(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Lexicographic rank -> ascending combination (same numbering as the header
+// describes): position i takes the value v whose block of combinations
+// contains the remaining rank; the blocks before v hold
+// C(n - prev - 1, r + 1) - C(n - v, r + 1) combinations (hockey-stick sum).
+__device__ inline void lex_unrank(const Globals &g, uint32_t n, uint32_t k, u64 rank,
+                                  uint32_t *c) {
+  int64_t prev = -1;
+  for (uint32_t i = 0; i < k; ++i) {
+    uint32_t r = k - 1 - i;
+    u64 top = binom(g, (uint32_t)(n - prev - 1), r + 1);
+    // largest v in [prev+1, n-1-r] with top - C(n - v, r + 1) <= rank
+    uint32_t lo = (uint32_t)(prev + 1), hi = n - 1 - r;
+    while (lo < hi) {
+      uint32_t mid = (lo + hi + 1) >> 1;
+      if (top - binom(g, n - mid, r + 1) <= rank) lo = mid;
+      else hi = mid - 1;
+    }
+    rank -= top - binom(g, n - lo, r + 1);
+    c[i] = lo;
+    prev = lo;
+  }
+}
+
+// Lexicographic rank of the part contributed by the first k-1 elements of a
+// combination whose (k-1)-prefix is p[0..k-2]; the full rank is this plus
+// (j - p[k-2] - 1) for last element j.
+__device__ inline u64 lex_rank_prefix(const Globals &g, uint32_t n, uint32_t k,
+                                      const uint32_t *p) {
+  u64 r = 0;
+  int64_t prev = -1;
+  for (uint32_t i = 0; i + 1 < k; ++i) {
+    r += binom(g, (uint32_t)(n - prev - 1), k - i) - binom(g, n - p[i], k - i);
+    prev = p[i];
+  }
+  return r;
+}
+
+// Compensated single-precision accumulation (Knuth's TwoSum): s + e carries
+// the running sum with the rounding error of every addition kept in e.
+__device__ __forceinline__ void two_sum_add(float &s, float &e, float v) {
+  float t = s + v;
+  float bp = t - s;
+  e += (s - (t - bp)) + (v - bp);
+  s = t;
+}
+
+}  // namespace fiuncho

@@ -1,0 +1,113 @@
+// internal.hpp -- data structures shared by the host orchestration and the
+// gfx950 kernels of libfiuncho.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "fiuncho.h"
+
+namespace fiuncho {
+
+constexpr int kMaxOrder = FIUNCHO_MAX_ORDER;
+constexpr int kBinomStride = kMaxOrder + 2;   // C(a, r) for r in [0, 9]
+constexpr int kWave = 64;                     // gfx950 wavefront
+constexpr int kJBlock = 64;                   // last variants per tile (one per lane)
+constexpr int kHistShift = 20;                // survivor histogram bin = key >> 20
+constexpr int kHistBins = 1 << (31 - kHistShift);
+constexpr uint32_t kSortMax = 4096;           // candidates ordered in one LDS sort
+constexpr int kScanWaves = 4;                 // waves per workgroup in the scan
+constexpr int kOrder2Prefixes = 8;            // first variants per wave at order 2
+
+// state the device writes during one run of a job (cleared at the start)
+struct JobState {
+  uint32_t m0, m1;            // class sizes
+  uint32_t W0, W1;            // 64-bit words per class
+  int32_t status;             // FIUNCHO_OK or a negative code
+  uint32_t tau_key;           // float bits of the running N-th-best lower bound
+  unsigned long long cand_count;  // candidates appended (may exceed the capacity)
+  unsigned long long nsurv;       // appended survivors, for histogram refreshes
+  uint32_t l1_count;          // candidates above the final running bound
+  uint32_t l2_count;          // candidates within the tolerance of the N-th best
+  uint32_t kth_key;           // exact N-th largest FP32 key among candidates
+  uint32_t flags;             // kFlag* bits
+  uint32_t pad[4];
+};
+
+constexpr uint32_t kFlagCandOverflow = 1u;    // candidate buffer too small
+constexpr uint32_t kFlagTieOverflow = 2u;     // too many near-ties for the final sort
+constexpr uint32_t kFlagBound = 4u;           // |mi32 - mi| exceeded the stated bound
+
+struct Cand {                 // one appended candidate
+  unsigned long long rank;
+  uint32_t key;               // float bits of max(mi32, 0)
+  float mi32;
+};
+
+struct Rescored {             // candidate after FP64 rescoring
+  unsigned long long rank;
+  double mi;
+  float mi32;
+  float rel_err;
+  uint32_t snp[kMaxOrder];
+};
+
+// everything the kernels need about one job; built by the host, uploaded once
+struct JobDesc {
+  uint32_t n, m, k, top_n;
+  uint32_t n_pad;             // n rounded up to a multiple of 64
+  uint32_t wcap;              // word stride of the bitsets (>= W0 + W1)
+  uint32_t nrows;             // rows of the tile table
+  uint32_t flags;             // bit0: outputs are device pointers
+  unsigned long long total;   // C(n, k)
+  unsigned long long tile_begin;  // first global tile of this job
+  unsigned long long tile_count;
+  // inputs (device)
+  const uint8_t *G;
+  const uint8_t *y;
+  // derived data (device, workspace)
+  uint32_t *idx;              // [m]: sample index of each class position
+  unsigned long long *Bv;     // [wcap][n_pad][2] planes g=0,1; variant fastest
+  unsigned long long *Bs;     // [n][wcap][4] planes g=0,1,2 and a zero word
+  uint32_t *marg;             // [n][3][2] per-variant class marginals
+  const float2 *F32;          // (hi, lo) of t ln t for t in [0, m]
+  const double *P64;          // (t/m) ln(t/m) for t in [0, m]
+  const unsigned long long *row_start;  // [nrows + 1] tile offsets
+  uint32_t *hist;             // [kHistBins]
+  Cand *cand;
+  uint32_t cand_cap;
+  uint32_t l1_cap;
+  Cand *l1;
+  Rescored *l2;
+  uint32_t l2_cap;
+  uint32_t pad0;
+  JobState *state;
+  // outputs
+  fiuncho_hit *out;
+  uint32_t *n_out;
+  int32_t *status_out;
+};
+
+struct Globals {
+  const unsigned long long *binom;       // [(nmax + 1) * kBinomStride]
+  uint32_t nmax;
+  uint32_t n_jobs;
+  const JobDesc *jobs;
+  const unsigned long long *job_tile_start;  // [n_jobs + 1]
+  unsigned long long total_tiles;
+  unsigned long long *tile_counter;
+};
+
+// launchers (kernels.hip)
+void launch_init(const Globals &g, hipStream_t s);
+void launch_pack(const Globals &g, uint32_t max_n_pad, hipStream_t s);
+void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s);
+void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
+void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s);
+void launch_finish(const Globals &g, hipStream_t s);
+void launch_tables(const Globals &g, const unsigned long long *ranks, uint64_t n_ranks,
+                   uint32_t *tables, hipStream_t s);
+int scan_grid_size(int ksel);
+
+}  // namespace fiuncho

@@ -1,0 +1,190 @@
+// pack.hip -- per-run initialisation, class partition and bit packing.
+//
+// Genotype tables (section 3.1, Fig. 2): one binary row per genotype value and
+// variant, columns = samples segregated into controls then cases, 64 samples
+// per 64-bit word (section 4, data/bit-level parallelism).  Bit b of word w of
+// class c is the sample at class position 64 w + b.  Padding bits are zero in
+// every row, so the third row is stored as valid & ~(row0 | row1).
+#include "device_common.hpp"
+
+namespace fiuncho {
+
+// Clears every job's run state and survivor histogram, and the tile counter.
+// (A fill kernel rather than hipMemsetAsync, so that the sequence can be
+// captured into a graph and replayed.)
+__global__ void init_kernel(Globals g) {
+  const JobDesc &J = g.jobs[blockIdx.x];
+  for (uint32_t i = threadIdx.x; i < (uint32_t)kHistBins; i += blockDim.x) J.hist[i] = 0;
+  if (threadIdx.x == 0) {
+    JobState *st = J.state;
+    st->m0 = st->m1 = st->W0 = st->W1 = 0;
+    st->status = 0;
+    st->tau_key = 0;
+    st->cand_count = 0;
+    st->nsurv = 0;
+    st->l1_count = 0;
+    st->l2_count = 0;
+    st->kth_key = 0;
+    st->flags = 0;
+    if (blockIdx.x == 0) *g.tile_counter = 0;
+  }
+}
+
+// One workgroup per job: class sizes and the stable class partition
+// idx[0..m0) = controls, idx[m0..m) = cases, each in sample order.
+__global__ __launch_bounds__(1024) void partition_kernel(Globals g) {
+  const JobDesc &J = g.jobs[blockIdx.x];
+  JobState *st = J.state;
+  const uint32_t m = J.m;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ uint32_t s_wave[16];
+  __shared__ uint32_t s_base1;
+  __shared__ uint32_t s_bad;
+  if (tid == 0) {
+    s_base1 = 0;
+    s_bad = 0;
+  }
+  __syncthreads();
+  // pass 1: number of cases
+  uint32_t mine = 0;
+  for (uint32_t s = tid; s < m; s += blockDim.x) {
+    uint8_t v = J.y[s];
+    mine += (v == 1);
+    if (v > 1) s_bad = 1;
+  }
+  for (int off = 32; off > 0; off >>= 1) mine += __shfl_down(mine, off);
+  if (lane == 0) atomicAdd(&s_base1, mine);
+  __syncthreads();
+  const uint32_t m1 = s_base1;
+  const uint32_t m0 = m - m1;
+  if (s_bad) {
+    if (tid == 0) st->status = FIUNCHO_E_PHENOTYPE;
+    return;
+  }
+  __syncthreads();
+  // pass 2: stable scatter, chunk by chunk
+  uint32_t base0 = 0, base1 = 0;
+  for (uint32_t c0 = 0; c0 < m; c0 += blockDim.x) {
+    uint32_t s = c0 + tid;
+    bool valid = s < m;
+    bool isc = valid && J.y[s] == 1;
+    u64 bc = ballot(isc), bv = ballot(valid);
+    u64 lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t pre1 = popc64(bc & lt);
+    uint32_t pre0 = popc64(bv & ~bc & lt);
+    if (lane == 0) s_wave[wave] = popc64(bc) | (popc64(bv & ~bc) << 16);
+    __syncthreads();
+    uint32_t off1 = 0, off0 = 0, tot1 = 0, tot0 = 0;
+    for (uint32_t w = 0; w < blockDim.x / 64; ++w) {
+      uint32_t v = s_wave[w];
+      if (w < wave) {
+        off1 += v & 0xffff;
+        off0 += v >> 16;
+      }
+      tot1 += v & 0xffff;
+      tot0 += v >> 16;
+    }
+    if (valid) {
+      if (isc) J.idx[m0 + base1 + off1 + pre1] = s;
+      else J.idx[base0 + off0 + pre0] = s;
+    }
+    base1 += tot1;
+    base0 += tot0;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    st->m0 = m0;
+    st->m1 = m1;
+    st->W0 = (m0 + 63) / 64;
+    st->W1 = (m1 + 63) / 64;
+  }
+}
+
+// One wave per (job, variant): builds the three rows of the variant's genotype
+// table for both classes, in the two layouts the scan reads, plus the
+// per-class genotype counts (the order-1 contingency table).
+// Bv[w][j][g] (g = 0, 1) serves lanes that each own a different variant j;
+// Bs[j][w][g] (g = 0, 1, 2, then a zero word) serves wave-uniform (scalar)
+// reads of one variant.
+__global__ __launch_bounds__(256) void pack_kernel(Globals g) {
+  const JobDesc &J = g.jobs[blockIdx.y];
+  const JobState *st = J.state;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t j = uni(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (j >= J.n_pad) return;
+  if (st->status != 0) return;
+  const uint32_t m0 = st->m0, m1 = st->m1;
+  const uint32_t W0 = st->W0, W1 = st->W1, W = W0 + W1;
+  const uint32_t n_pad = J.n_pad, wcap = J.wcap;
+  if (j >= J.n) {
+    // padding variants read by the last lanes of a tile: all-zero rows
+    for (uint32_t w = lane; w < W; w += 64) {
+      J.Bv[((size_t)w * n_pad + j) * 2 + 0] = 0;
+      J.Bv[((size_t)w * n_pad + j) * 2 + 1] = 0;
+    }
+    return;
+  }
+  const uint8_t *row = J.G + (size_t)j * J.m;
+  uint32_t cnt[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  bool bad = false;
+  u64 keep0 = 0, keep1 = 0, keep2 = 0;
+  // 8 words at a time so that 8 independent gathers per lane are in flight
+  for (uint32_t w0 = 0; w0 < W; w0 += 8) {
+    uint32_t gv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t w = w0 + u;
+      const uint32_t cls = (w >= W0);
+      const uint32_t p = (w - (cls ? W0 : 0)) * 64 + lane;
+      const bool valid = w < W && p < (cls ? m1 : m0);
+      gv[u] = valid ? (uint32_t)row[J.idx[(cls ? m0 : 0) + p]] : 0xffffffffu;
+      bad |= valid && gv[u] > 2;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t w = w0 + u;
+      if (w >= W) break;
+      const uint32_t cls = (w >= W0);
+      const u64 b0 = ballot(gv[u] == 0), b1 = ballot(gv[u] == 1), b2 = ballot(gv[u] == 2);
+      cnt[0][cls] += popc64(b0);
+      cnt[1][cls] += popc64(b1);
+      cnt[2][cls] += popc64(b2);
+      // lane (w % 64) keeps word w; every 64 words (and at the end) all lanes store
+      if (lane == (w & 63)) {
+        keep0 = b0;
+        keep1 = b1;
+        keep2 = b2;
+      }
+      if ((w & 63) == 63 || w + 1 == W) {
+        const uint32_t wl = (w & ~63u) + lane;
+        if (wl <= w) {
+          J.Bv[((size_t)wl * n_pad + j) * 2 + 0] = keep0;
+          J.Bv[((size_t)wl * n_pad + j) * 2 + 1] = keep1;
+          u64 *bs = J.Bs + ((size_t)j * wcap + wl) * 4;
+          bs[0] = keep0;
+          bs[1] = keep1;
+          bs[2] = keep2;
+          bs[3] = 0;
+        }
+      }
+    }
+  }
+  if (ballot(bad)) {
+    if (lane == 0) atomicMin(&J.state->status, (int32_t)FIUNCHO_E_GENOTYPE);
+  }
+  if (lane == 0) {
+    for (int gg = 0; gg < 3; ++gg)
+      for (int c = 0; c < 2; ++c) J.marg[((size_t)j * 3 + gg) * 2 + c] = cnt[gg][c];
+  }
+}
+
+void launch_init(const Globals &g, hipStream_t s) {
+  hipLaunchKernelGGL(init_kernel, dim3(g.n_jobs), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(partition_kernel, dim3(g.n_jobs), dim3(1024), 0, s, g);
+}
+
+void launch_pack(const Globals &g, uint32_t max_n_pad, hipStream_t s) {
+  hipLaunchKernelGGL(pack_kernel, dim3((max_n_pad + 3) / 4, g.n_jobs), dim3(256), 0, s, g);
+}
+
+}  // namespace fiuncho

@@ -1,0 +1,521 @@
+// scan.hip -- the exhaustive search: for every k-combination, its contingency
+// table (section 3.2) by AND + population count of genotype-table rows
+// (section 3.1), its mutual information (section 3.3, Eq. 1-3) in compensated
+// single precision, and a filter that keeps every combination that can still
+// be among the best top_n (Algorithm 1's sorted list).
+//
+// Work decomposition (section 4.1 reuses the genotype table of a (k-1)-prefix
+// for every last variant j after it; here a wave does exactly that):
+//   * a wave owns one (k-1)-prefix (order >= 3) or a run of first variants
+//     (order 2); its 64 lanes own 64 consecutive last variants j;
+//   * the prefix rows are wave-uniform, so they are loaded with scalar loads
+//     and combined in scalar registers; each lane ANDs them with its own
+//     variant's rows and accumulates population counts;
+//   * only rows g = 0, 1 of the last variant are counted: the g = 2 count of a
+//     prefix row is that row's own population count minus the other two
+//     (every sample has exactly one genotype);
+//   * at order 2 the first variant's g = 2 row is likewise derived from the
+//     per-variant class counts, so 4 of the 9 cells are counted directly.
+// Tiles (workgroups of kScanWaves waves sharing the same 64 last variants)
+// are pulled from a device-wide counter by a persistent grid.
+#include "device_common.hpp"
+
+namespace fiuncho {
+
+struct Ulong2 {
+  u64 x, y;
+};
+
+// Wave-uniform copy of what a tile needs from its job (every field is read
+// into scalar registers once per tile).
+struct JV {
+  uint32_t n, m, k, top_n, n_pad, wcap, cand_cap, m0, m1, W0, W1;
+  u64 total;
+  const u64 *Bv;
+  const u64 *Bs;
+  const uint32_t *marg;
+  const float2 *F32;
+  uint32_t *hist;
+  Cand *cand;
+  JobState *st;
+};
+
+template <typename T>
+__device__ __forceinline__ T *uni_ptr(T *p) {
+  return reinterpret_cast<T *>(uni64(reinterpret_cast<u64>(p)));
+}
+
+__device__ __forceinline__ JV load_view(const JobDesc *jd) {
+  const FI_CONST JobDesc *J = as_const(jd);
+  JV v;
+  v.n = uni(J->n);
+  v.m = uni(J->m);
+  v.k = uni(J->k);
+  v.top_n = uni(J->top_n);
+  v.n_pad = uni(J->n_pad);
+  v.wcap = uni(J->wcap);
+  v.cand_cap = uni(J->cand_cap);
+  v.total = uni64(J->total);
+  v.Bv = uni_ptr(J->Bv);
+  v.Bs = uni_ptr(J->Bs);
+  v.marg = uni_ptr(J->marg);
+  v.F32 = uni_ptr(J->F32);
+  v.hist = uni_ptr(J->hist);
+  v.cand = uni_ptr(J->cand);
+  v.st = uni_ptr(J->state);
+  return v;
+}
+
+// m * MI = [f(m) - f(m0) - f(m1)] + sum_x [f(n_x0) + f(n_x1) - f(n_x0 + n_x1)]
+// with f(t) = t ln t: Eq. 1-3 with plug-in probabilities, multiplied out.
+// F holds f(t) as an unevaluated sum hi + lo of two floats.
+// one table entry: (hi, lo) floats packed in 8 bytes
+__device__ __forceinline__ void f_entry(const FI_GLOBAL u64 *F, uint32_t t, float &hi, float &lo) {
+  const u64 x = F[t];
+  hi = __uint_as_float((uint32_t)x);
+  lo = __uint_as_float((uint32_t)(x >> 32));
+}
+
+__device__ __forceinline__ void mi_cell(const FI_GLOBAL u64 *F, uint32_t n0, uint32_t n1,
+                                        float &s, float &e) {
+  float ah, al, bh, bl, ch, cl;
+  f_entry(F, n0, ah, al);
+  f_entry(F, n1, bh, bl);
+  f_entry(F, n0 + n1, ch, cl);
+  two_sum_add(s, e, ah);
+  two_sum_add(s, e, bh);
+  two_sum_add(s, e, -ch);
+  e += (al + bl) - cl;
+}
+
+__device__ __forceinline__ void mi_start(const JV &v, float &s, float &e) {
+  const FI_CONST u64 *F = as_const(reinterpret_cast<const u64 *>(v.F32));
+  const u64 fm = F[v.m], f0 = F[v.m0], f1 = F[v.m1];
+  s = __uint_as_float((uint32_t)fm);
+  e = 0.f;
+  two_sum_add(s, e, -__uint_as_float((uint32_t)f0));
+  two_sum_add(s, e, -__uint_as_float((uint32_t)f1));
+  e += (__uint_as_float((uint32_t)(fm >> 32)) - __uint_as_float((uint32_t)(f0 >> 32))) -
+       __uint_as_float((uint32_t)(f1 >> 32));
+}
+
+// Lower bound of the top_n-th best score from the survivor histogram: the bin
+// where the count from the top reaches top_n holds the top_n-th largest
+// appended score, so its lower edge is a valid bound.  One wave.
+__device__ __noinline__ void refresh_tau(uint32_t *hist, JobState *st, uint32_t top_n,
+                                         uint32_t lane) {
+  constexpr int PER = kHistBins / 64;
+  const uint32_t *bins = hist + lane * PER;
+  uint32_t tot = 0;
+  for (int i = 0; i < PER; ++i) tot += load_relaxed(&bins[i]);
+  uint32_t suf = tot;  // sum over lanes >= this lane
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t o = __shfl_down(suf, off);
+    if (lane + off < 64) suf += o;
+  }
+  const u64 ok = ballot(suf >= top_n);
+  if (ok == 0) return;
+  const uint32_t L = 63 - __clzll((long long)ok);
+  if (lane == L) {
+    uint32_t run = suf - tot;
+    uint32_t bin = L * PER;
+    for (int i = PER - 1; i >= 0; --i) {
+      run += load_relaxed(&bins[i]);
+      if (run >= top_n) {
+        bin = L * PER + i;
+        break;
+      }
+    }
+    atomicMax(&st->tau_key, bin << kHistShift);
+  }
+}
+
+__device__ __forceinline__ float current_threshold(const JobState *st) {
+  const float tau = __uint_as_float(uni(load_relaxed(&st->tau_key)));
+  return tau * (1.0f - 2e-5f) - 2e-10f;
+}
+
+// Appends every active lane whose score clears the threshold.
+__device__ __forceinline__ void emit(const JV &v, bool active, float mi32, u64 rank, float thr,
+                                     uint32_t lane) {
+  const bool keep = active && mi32 >= thr;
+  const u64 mask = ballot(keep);
+  if (mask == 0) return;
+  const uint32_t cnt = popc64(mask);
+  const uint32_t leader = __ffsll((long long)mask) - 1;
+  u64 base = 0, old = 0;
+  if (lane == leader) {
+    base = atomicAdd(&v.st->cand_count, (u64)cnt);
+    old = atomicAdd(&v.st->nsurv, (u64)cnt);
+  }
+  base = __shfl(base, leader);
+  old = __shfl(old, leader);
+  if (keep) {
+    const u64 lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const u64 idx = base + popc64(mask & lt);
+    const uint32_t key = mi32 > 0.f ? __float_as_uint(mi32) : 0u;
+    if (idx < v.cand_cap) {
+      Cand c;
+      c.rank = rank;
+      c.key = key;
+      c.mi32 = mi32;
+      v.cand[idx] = c;
+    }
+    atomicAdd(&v.hist[key >> kHistShift], 1u);
+  }
+  const u64 qs = v.top_n > 64 ? v.top_n : 64;
+  if ((old + cnt) / qs != old / qs) refresh_tau(v.hist, v.st, v.top_n, lane);
+}
+
+// ---------------------------------------------------------------------------
+// order 1: the contingency table of one variant is its class counts
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void tile_order1(const JV &v, u64 lt, uint32_t wave, uint32_t lane) {
+  const uint32_t j = (uint32_t)lt * (kScanWaves * 64) + wave * 64 + lane;
+  const bool active = j < v.n;
+  const uint32_t jj = active ? j : 0;
+  const FI_GLOBAL uint32_t *mg = as_global(v.marg) + (size_t)jj * 6;
+  float s, e;
+  mi_start(v, s, e);
+  const FI_GLOBAL u64 *F = as_global(reinterpret_cast<const u64 *>(v.F32));
+#pragma unroll
+  for (int gg = 0; gg < 3; ++gg) mi_cell(F, mg[2 * gg], mg[2 * gg + 1], s, e);
+  const float mi32 = (s + e) / (float)v.m;
+  emit(v, active, mi32, (u64)j, current_threshold(v.st), lane);
+}
+
+// ---------------------------------------------------------------------------
+// order 2: a wave holds P consecutive first variants a (rows g = 0, 1 in
+// scalar registers) against 64 last variants j (one per lane)
+// ---------------------------------------------------------------------------
+template <int P, int CLS>
+__device__ __forceinline__ void count_order2(cu64p Bv, const FI_GLOBAL Ulong2 *col,
+                                             uint32_t n_pad, uint32_t a_first, uint32_t wbeg,
+                                             uint32_t wend, uint32_t (&acc)[P][2][2][2]) {
+  for (uint32_t w = wbeg; w < wend; ++w) {
+    Ulong2 L;
+    L.x = col[(size_t)w * n_pad].x;
+    L.y = col[(size_t)w * n_pad].y;
+    // rows g = 0, 1 of the P consecutive first variants: 16 P contiguous bytes
+    cu64p rows = Bv + ((size_t)w * n_pad + a_first) * 2;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const u64 A0 = rows[2 * p], A1 = rows[2 * p + 1];
+      acc[p][CLS][0][0] = add_popc64(acc[p][CLS][0][0], A0 & L.x);
+      acc[p][CLS][0][1] = add_popc64(acc[p][CLS][0][1], A0 & L.y);
+      acc[p][CLS][1][0] = add_popc64(acc[p][CLS][1][0], A1 & L.x);
+      acc[p][CLS][1][1] = add_popc64(acc[p][CLS][1][1], A1 & L.y);
+    }
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void tile_order2(const Globals &g, const JV &v, uint32_t a_first,
+                                            uint32_t j0, uint32_t lane) {
+  const uint32_t n = v.n;
+  if (a_first > n - 2) return;
+  if (a_first + 1 >= j0 + 64) return;  // every lane has j <= a for all prefixes
+  const uint32_t j = j0 + lane;
+  const FI_GLOBAL Ulong2 *col = as_global(reinterpret_cast<const Ulong2 *>(v.Bv)) + j;
+  uint32_t acc[P][2][2][2];
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int x = 0; x < 2; ++x) acc[p][c][x][0] = acc[p][c][x][1] = 0;
+  cu64p Bvc = as_const(v.Bv);
+  count_order2<P, 0>(Bvc, col, v.n_pad, a_first, 0, v.W0, acc);
+  count_order2<P, 1>(Bvc, col, v.n_pad, a_first, v.W0, v.W0 + v.W1, acc);
+
+  const float thr = current_threshold(v.st);
+  const uint32_t jj = j < n ? j : n - 1;
+  const FI_GLOBAL uint32_t *mj = as_global(v.marg) + (size_t)jj * 6;
+  uint32_t Mj[2][2];
+#pragma unroll
+  for (int gg = 0; gg < 2; ++gg)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) Mj[gg][c] = mj[2 * gg + c];
+  float s0, e0;
+  mi_start(v, s0, e0);
+  const u64 cn2 = binom(g, n, 2);
+  const float inv_m = 1.0f / (float)v.m;
+  const FI_GLOBAL u64 *F = as_global(reinterpret_cast<const u64 *>(v.F32));
+  cu32p marg = as_const(v.marg);
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const uint32_t ap = a_first + p;
+    const bool pvalid = ap <= n - 2;
+    const bool active = pvalid && j < n && j > ap;
+    const uint32_t apc = pvalid ? ap : n - 2;
+    uint32_t t[3][3][2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const uint32_t Ma0 = marg[(size_t)apc * 6 + 0 + c];
+      const uint32_t Ma1 = marg[(size_t)apc * 6 + 2 + c];
+      const uint32_t Ma2 = marg[(size_t)apc * 6 + 4 + c];
+      t[0][0][c] = acc[p][c][0][0];
+      t[0][1][c] = acc[p][c][0][1];
+      t[1][0][c] = acc[p][c][1][0];
+      t[1][1][c] = acc[p][c][1][1];
+      t[0][2][c] = Ma0 - t[0][0][c] - t[0][1][c];
+      t[1][2][c] = Ma1 - t[1][0][c] - t[1][1][c];
+      t[2][0][c] = Mj[0][c] - t[0][0][c] - t[1][0][c];
+      t[2][1][c] = Mj[1][c] - t[0][1][c] - t[1][1][c];
+      t[2][2][c] = Ma2 - t[2][0][c] - t[2][1][c];
+    }
+    float s = s0, e = e0;
+    if (active) {
+#pragma unroll
+      for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) mi_cell(F, t[x][y][0], t[x][y][1], s, e);
+    }
+    const float mi32 = (s + e) * inv_m;
+    const u64 rank = cn2 - binom(g, n - apc, 2) + (u64)(j - apc - 1);
+    emit(v, active, mi32, rank, thr, lane);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// order k >= 3: a wave holds one (k-1)-prefix.  Its 3^(k-1) rows are visited
+// 9 at a time (one "pass" per genotype assignment of the first k-3 prefix
+// variants); the 9 rows of a pass are lead & row_a[ga] & row_b[gb] for the
+// last two prefix variants a, b.  Scores are separable over cells, so each
+// pass adds its 27 cells to the compensated sum and drops its counters.
+// ---------------------------------------------------------------------------
+// Bs holds, per variant and word, the rows g = 0, 1, 2 and a zero pad word
+// (32 bytes), so one scalar load brings a variant's three rows of a word.
+template <int K, int CLS>
+__device__ __forceinline__ void count_word(cu64p ra, cu64p rb, const cu64p (&rl)[K - 2],
+                                           const uint32_t (&lg)[K - 2], uint32_t w,
+                                           const FI_GLOBAL Ulong2 *col, uint32_t n_pad,
+                                           uint32_t (&acc)[2][9][2], uint32_t (&pc)[2][9]) {
+  u64 lead = ~0ull;
+#pragma unroll
+  for (int i = 0; i < K - 3; ++i) lead &= rl[i][(size_t)w * 4 + lg[i]];
+  u64 A[3], B[3];
+#pragma unroll
+  for (int gg = 0; gg < 3; ++gg) {
+    A[gg] = lead & ra[(size_t)w * 4 + gg];
+    B[gg] = rb[(size_t)w * 4 + gg];
+  }
+  Ulong2 L;
+  L.x = col[(size_t)w * n_pad].x;
+  L.y = col[(size_t)w * n_pad].y;
+#pragma unroll
+  for (int ga = 0; ga < 3; ++ga)
+#pragma unroll
+    for (int gb = 0; gb < 3; ++gb) {
+      const u64 R = A[ga] & B[gb];
+      pc[CLS][ga * 3 + gb] += popc64(R);
+      acc[CLS][ga * 3 + gb][0] = add_popc64(acc[CLS][ga * 3 + gb][0], R & L.x);
+      acc[CLS][ga * 3 + gb][1] = add_popc64(acc[CLS][ga * 3 + gb][1], R & L.y);
+    }
+}
+
+template <int K, int CLS>
+__device__ __forceinline__ void count_orderk(cu64p Bs, const FI_GLOBAL Ulong2 *col,
+                                             uint32_t n_pad, uint32_t wcap,
+                                             const uint32_t (&pre)[K - 1],
+                                             const uint32_t (&lg)[K - 2], uint32_t wbeg,
+                                             uint32_t wend, uint32_t (&acc)[2][9][2],
+                                             uint32_t (&pc)[2][9]) {
+  cu64p ra = Bs + (size_t)pre[K - 3] * 4 * wcap;
+  cu64p rb = Bs + (size_t)pre[K - 2] * 4 * wcap;
+  cu64p rl[K - 2];
+#pragma unroll
+  for (int i = 0; i < K - 2; ++i) rl[i] = Bs + (size_t)pre[i < K - 3 ? i : 0] * 4 * wcap;
+  uint32_t w = wbeg;
+  for (; w + 1 < wend; w += 2) {
+    count_word<K, CLS>(ra, rb, rl, lg, w, col, n_pad, acc, pc);
+    count_word<K, CLS>(ra, rb, rl, lg, w + 1, col, n_pad, acc, pc);
+  }
+  if (w < wend) count_word<K, CLS>(ra, rb, rl, lg, w, col, n_pad, acc, pc);
+}
+
+template <int K>
+__device__ __forceinline__ void tile_orderk(const Globals &g, const JV &v,
+                                            const uint32_t (&pre)[K - 1], uint32_t j0,
+                                            uint32_t lane) {
+  constexpr int NLEAD = K - 3;
+  int npass = 1;
+#pragma unroll
+  for (int i = 0; i < NLEAD; ++i) npass *= 3;
+  const uint32_t n = v.n;
+  const uint32_t b = pre[K - 2];
+  const uint32_t j = j0 + lane;
+  const bool active = j < n;
+  const FI_GLOBAL Ulong2 *col = as_global(reinterpret_cast<const Ulong2 *>(v.Bv)) + j;
+  cu64p Bsc = as_const(v.Bs);
+  const FI_GLOBAL u64 *F = as_global(reinterpret_cast<const u64 *>(v.F32));
+  float s, e;
+  mi_start(v, s, e);
+  for (int pass = 0; pass < npass; ++pass) {
+    uint32_t lg[K - 2];
+    {
+      int rem = pass;
+#pragma unroll
+      for (int i = NLEAD - 1; i >= 0; --i) {
+        lg[i] = (uint32_t)(rem % 3);
+        rem /= 3;
+      }
+      lg[K - 3] = 0;
+    }
+    uint32_t acc[2][9][2], pc[2][9];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int r = 0; r < 9; ++r) acc[c][r][0] = acc[c][r][1] = pc[c][r] = 0;
+    count_orderk<K, 0>(Bsc, col, v.n_pad, v.wcap, pre, lg, 0, v.W0, acc, pc);
+    count_orderk<K, 1>(Bsc, col, v.n_pad, v.wcap, pre, lg, v.W0, v.W0 + v.W1, acc, pc);
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        const uint32_t a0 = acc[0][r][0], a1 = acc[0][r][1];
+        const uint32_t c0 = acc[1][r][0], c1 = acc[1][r][1];
+        mi_cell(F, a0, c0, s, e);
+        mi_cell(F, a1, c1, s, e);
+        mi_cell(F, pc[0][r] - a0 - a1, pc[1][r] - c0 - c1, s, e);
+      }
+    }
+  }
+  const float mi32 = (s + e) / (float)v.m;
+  const u64 rank = lex_rank_prefix(g, n, K, pre) + (u64)(j - b - 1);
+  emit(v, active, mi32, rank, current_threshold(v.st), lane);
+}
+
+// ---------------------------------------------------------------------------
+// persistent driver
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ void run_orderk(const Globals &g, const JV &v, uint32_t rho, u64 local,
+                                           uint32_t wave, uint32_t lane) {
+  const uint32_t n = v.n;
+  const uint32_t b = rho + (K - 2);
+  const uint32_t nj = (n - 1 - b + 63) / 64;
+  const u64 grp = local / nj;
+  const uint32_t jb = (uint32_t)(local - grp * nj);
+  u64 q = grp * kScanWaves + wave;
+  if (q >= binom(g, b, K - 2)) return;
+  uint32_t pre[K - 1];
+  pre[K - 2] = b;
+  // colex unrank of the (k-2)-subset of [0, b) with index q
+  uint32_t hi = b;
+#pragma unroll
+  for (int r = K - 2; r >= 1; --r) {
+    uint32_t lo = (uint32_t)(r - 1), top = hi - 1;
+    while (lo < top) {
+      const uint32_t mid = (lo + top + 1) >> 1;
+      if (binom(g, mid, r) <= q) lo = mid;
+      else top = mid - 1;
+    }
+    q -= binom(g, lo, r);
+    pre[r - 1] = uni(lo);
+    hi = lo;
+  }
+  tile_orderk<K>(g, v, pre, b + 1 + jb * 64, lane);
+}
+
+template <int KSEL>
+__global__ __launch_bounds__(kScanWaves * 64) void scan_kernel(Globals g) {
+  __shared__ u64 s_tile;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = uni(threadIdx.x >> 6);
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(g.tile_counter, 1ull);
+    __syncthreads();
+    const u64 t = uni64(s_tile);
+    __syncthreads();
+    if (t >= g.total_tiles) break;
+    cu64p jts = as_const(g.job_tile_start);
+    uint32_t lo = 0, hi = g.n_jobs - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (jts[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    lo = uni(lo);
+    JV v = load_view(g.jobs + lo);
+    {
+      const JobState *st = v.st;
+      if (uni((uint32_t)st->status) != 0) continue;
+      v.m0 = uni(st->m0);
+      v.m1 = uni(st->m1);
+      v.W0 = uni(st->W0);
+      v.W1 = uni(st->W1);
+      if (v.m0 == 0 || v.m1 == 0) continue;
+    }
+    const FI_CONST JobDesc *jd = as_const(g.jobs) + lo;
+    const u64 lt = t - uni64(jd->tile_begin);
+    const int k = KSEL ? KSEL : (int)v.k;
+    if (k == 1) {
+      if (KSEL == 0 || KSEL == 1) tile_order1(v, lt, wave, lane);
+      continue;
+    }
+    cu64p rows = as_const(uni_ptr(jd->row_start));
+    uint32_t rl = 0, rh = uni(jd->nrows) - 1;
+    while (rl < rh) {
+      const uint32_t mid = (rl + rh + 1) >> 1;
+      if (rows[mid] <= lt) rl = mid;
+      else rh = mid - 1;
+    }
+    rl = uni(rl);
+    const u64 local = uni64(lt - rows[rl]);
+    if (k == 2) {
+      if (KSEL == 0 || KSEL == 2) {
+        const uint32_t a_first = rl * (kScanWaves * kOrder2Prefixes);
+        const uint32_t j0 = a_first + 1 + (uint32_t)local * 64;
+        tile_order2<kOrder2Prefixes>(g, v, a_first + wave * kOrder2Prefixes, j0, lane);
+      }
+      continue;
+    }
+    switch (k) {
+      case 3: if (KSEL == 0 || KSEL == 3) run_orderk<3>(g, v, rl, local, wave, lane); break;
+      case 4: if (KSEL == 0 || KSEL == 4) run_orderk<4>(g, v, rl, local, wave, lane); break;
+      case 5: if (KSEL == 0 || KSEL == 5) run_orderk<5>(g, v, rl, local, wave, lane); break;
+      case 6: if (KSEL == 0 || KSEL == 6) run_orderk<6>(g, v, rl, local, wave, lane); break;
+      case 7: if (KSEL == 0 || KSEL == 7) run_orderk<7>(g, v, rl, local, wave, lane); break;
+      case 8: if (KSEL == 0 || KSEL == 8) run_orderk<8>(g, v, rl, local, wave, lane); break;
+      default: break;
+    }
+  }
+}
+
+template <int KSEL>
+static int occupancy_grid() {
+  int dev = 0, cus = 0, per = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, scan_kernel<KSEL>,
+                                                     kScanWaves * 64, 0);
+  if (cus <= 0) cus = 256;
+  if (per <= 0) per = 1;
+  return cus * per;
+}
+
+int scan_grid_size(int ksel) {
+  switch (ksel) {
+    case 1: return occupancy_grid<1>();
+    case 2: return occupancy_grid<2>();
+    case 3: return occupancy_grid<3>();
+    case 4: return occupancy_grid<4>();
+    case 5: return occupancy_grid<5>();
+    default: return occupancy_grid<0>();
+  }
+}
+
+void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s) {
+  dim3 gd(grid), bd(kScanWaves * 64);
+  switch (ksel) {
+    case 1: hipLaunchKernelGGL(scan_kernel<1>, gd, bd, 0, s, g); break;
+    case 2: hipLaunchKernelGGL(scan_kernel<2>, gd, bd, 0, s, g); break;
+    case 3: hipLaunchKernelGGL(scan_kernel<3>, gd, bd, 0, s, g); break;
+    case 4: hipLaunchKernelGGL(scan_kernel<4>, gd, bd, 0, s, g); break;
+    case 5: hipLaunchKernelGGL(scan_kernel<5>, gd, bd, 0, s, g); break;
+    default: hipLaunchKernelGGL(scan_kernel<0>, gd, bd, 0, s, g); break;
+  }
+}
+
+}  // namespace fiuncho

@@ -1,0 +1,360 @@
+// select.hip -- from the scan's candidates to the exact best top_n.
+//
+// Algorithm 1 keeps a sorted list of the S best scores; its threads' and
+// processes' lists are then joined, sorted and truncated (section 4.2, last
+// paragraph).  Here the scan leaves an unordered candidate buffer that
+// provably holds every combination that can be among the best top_n, and:
+//   1. compact:  drop candidates below the final running bound (all blocks);
+//   2. select:   exact top_n-th largest FP32 score by radix selection, then keep
+//                every candidate within the FP32 error tolerance of it;
+//   3. rescore:  recount each kept combination's table and evaluate Eq. 1-3 in
+//                IEEE double, term by term in a fixed order;
+//   4. finish:   order by (MI descending, rank ascending), write top_n hits.
+// A combination is dropped only when its FP32 score is more than twice the
+// tolerance below a score that top_n other combinations reach, so with
+// |mi32 - mi| <= tolerance it cannot belong to the exact result.
+#include <algorithm>
+
+#include "device_common.hpp"
+
+namespace fiuncho {
+
+__device__ __forceinline__ float tol_threshold(float tau) {
+  return tau * (1.0f - 2e-5f) - 2e-10f;
+}
+
+// 1. all workgroups, grid-stride over one job's candidates (blockIdx.y = job)
+__global__ __launch_bounds__(256) void compact_kernel(Globals g) {
+  const JobDesc &J = g.jobs[blockIdx.y];
+  JobState *st = J.state;
+  if (st->status != 0 || st->m0 == 0 || st->m1 == 0) return;
+  const u64 count = st->cand_count;
+  if (count > J.cand_cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&st->flags, kFlagCandOverflow);
+    return;
+  }
+  const float thr = tol_threshold(__uint_as_float(st->tau_key));
+  const uint32_t lane = lane_id();
+  for (u64 i0 = (u64)blockIdx.x * blockDim.x; i0 < count; i0 += (u64)gridDim.x * blockDim.x) {
+    const u64 i = i0 + threadIdx.x;
+    bool keep = false;
+    Cand c;
+    if (i < count) {
+      c = J.cand[i];
+      keep = c.mi32 >= thr;
+    }
+    const u64 mask = ballot(keep);
+    if (mask == 0) continue;
+    const uint32_t leader = __ffsll((long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&st->l1_count, (uint32_t)popc64(mask));
+    base = __shfl(base, leader);
+    if (keep) {
+      const u64 lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+      const uint32_t at = base + popc64(mask & lt);
+      if (at < J.l1_cap) J.l1[at] = c;
+    }
+  }
+}
+
+// 2. one workgroup per job: radix selection of the top_n-th largest key over
+// the compacted candidates (12 + 12 + 7 bits of a non-negative float), then
+// the final candidate set.
+__global__ __launch_bounds__(1024) void select_kernel(Globals g) {
+  const JobDesc &J = g.jobs[blockIdx.x];
+  JobState *st = J.state;
+  if (st->status != 0 || st->m0 == 0 || st->m1 == 0) return;
+  if (st->flags & kFlagCandOverflow) return;
+  __shared__ uint32_t hist[4096];
+  __shared__ uint32_t s_prefix, s_need, s_count;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t M = min(st->l1_count, J.l1_cap);
+  const uint32_t N = J.top_n;
+  float thr2;
+  if (M <= N) {
+    thr2 = -INFINITY;  // every candidate is kept
+  } else {
+    if (tid == 0) {
+      s_prefix = 0;
+      s_need = N;  // rank (1-based, from the top) still to locate
+    }
+    const int shifts[3] = {19, 7, 0};
+    const int widths[3] = {12, 12, 7};
+    uint32_t known_mask = 0;
+    for (int pass = 0; pass < 3; ++pass) {
+      for (uint32_t i = tid; i < 4096; i += blockDim.x) hist[i] = 0;
+      __syncthreads();
+      const uint32_t prefix = s_prefix;
+      const uint32_t bins = 1u << widths[pass];
+      for (uint32_t i = tid; i < M; i += blockDim.x) {
+        const uint32_t key = J.l1[i].key;
+        if ((key & known_mask) == prefix) atomicAdd(&hist[(key >> shifts[pass]) & (bins - 1)], 1u);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t need = s_need, run = 0;
+        int bin = (int)bins - 1;
+        for (; bin > 0; --bin) {
+          if (run + hist[bin] >= need) break;
+          run += hist[bin];
+        }
+        s_need = need - run;
+        s_prefix = prefix | ((uint32_t)bin << shifts[pass]);
+      }
+      known_mask |= (bins - 1) << shifts[pass];
+      __syncthreads();
+    }
+    const uint32_t kth = s_prefix;
+    if (tid == 0) st->kth_key = kth;
+    thr2 = tol_threshold(__uint_as_float(kth));
+  }
+  if (tid == 0) s_count = 0;
+  __syncthreads();
+  for (uint32_t i = tid; i < M; i += blockDim.x) {
+    const Cand c = J.l1[i];
+    if (c.mi32 >= thr2) {
+      const uint32_t at = atomicAdd(&s_count, 1u);
+      if (at < J.l2_cap) {
+        Rescored r;
+        r.rank = c.rank;
+        r.mi32 = c.mi32;
+        r.mi = 0.0;
+        r.rel_err = 0.f;
+        J.l2[at] = r;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    st->l2_count = s_count;
+    if (s_count > J.l2_cap) st->flags |= kFlagTieOverflow;
+  }
+}
+
+// 3. one wave per kept candidate: recount the contingency table with one lane
+// per genotype cell (AND of the cell's rows, popcount per class), then MI in
+// double precision.  Also used for explicit tables (fiuncho_contingency).
+template <bool WRITE_TABLE>
+__device__ void count_cells(const JobDesc &J, const JobState *st, const uint32_t *c,
+                            uint32_t k, uint32_t lane, uint32_t *lds_t,
+                            uint32_t *table_out) {
+  uint32_t cells = 1;
+  for (uint32_t i = 0; i < k; ++i) cells *= 3;
+  const uint32_t W0 = st->W0, W = st->W0 + st->W1, wcap = J.wcap;
+  for (uint32_t x0 = 0; x0 < cells; x0 += 64) {
+    const uint32_t x = x0 + lane;
+    const bool on = x < cells;
+    const u64 *rows[kMaxOrder];
+    uint32_t rem = on ? x : 0;
+    for (int i = (int)k - 1; i >= 0; --i) {
+      rows[i] = J.Bs + (size_t)c[i] * 4 * wcap + rem % 3;
+      rem /= 3;
+    }
+    uint32_t n0 = 0, n1 = 0;
+    for (uint32_t w = 0; w < W; ++w) {
+      u64 r = ~0ull;
+      for (uint32_t i = 0; i < k; ++i) r &= rows[i][(size_t)w * 4];
+      if (w < W0) n0 += popc64(r);
+      else n1 += popc64(r);
+    }
+    if (on) {
+      if (lds_t) {
+        lds_t[2 * x] = n0;
+        lds_t[2 * x + 1] = n1;
+      }
+      if (WRITE_TABLE) {
+        table_out[2 * x] = n0;
+        table_out[2 * x + 1] = n1;
+      }
+    }
+  }
+}
+
+// H(X) + H(Y) - H(X,Y) with plug-in probabilities (Eq. 1-3), evaluated as
+// running differences in a fixed order (cells ascending, then classes); P64
+// holds (t/m) ln(t/m) computed on the host.
+__device__ double mi64_of_table(const double *__restrict__ P64, const uint32_t *t,
+                                uint32_t cells, uint32_t m0, uint32_t m1) {
+  double hx = 0.0, hy = 0.0, hxy = 0.0;
+  for (uint32_t x = 0; x < cells; ++x) hx = hx - P64[t[2 * x] + t[2 * x + 1]];
+  hy = hy - P64[m0];
+  hy = hy - P64[m1];
+  for (uint32_t x = 0; x < cells; ++x) {
+    hxy = hxy - P64[t[2 * x]];
+    hxy = hxy - P64[t[2 * x + 1]];
+  }
+  return (hx + hy) - hxy;
+}
+
+constexpr int kMaxCells = 6561;  // 3^8
+
+__global__ __launch_bounds__(64) void rescore_kernel(Globals g) {
+  const JobDesc &J = g.jobs[blockIdx.y];
+  JobState *st = J.state;
+  if (st->status != 0 || st->m0 == 0 || st->m1 == 0) return;
+  if (st->flags & (kFlagCandOverflow | kFlagTieOverflow)) return;
+  extern __shared__ uint32_t lds_t[];
+  const uint32_t lane = lane_id();
+  const uint32_t count = min(st->l2_count, J.l2_cap);
+  uint32_t cells = 1;
+  for (uint32_t q = 0; q < J.k; ++q) cells *= 3;
+  for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+    Rescored r = J.l2[i];
+    uint32_t c[kMaxOrder];
+    lex_unrank(g, J.n, J.k, r.rank, c);
+    count_cells<false>(J, st, c, J.k, lane, lds_t, nullptr);
+    __syncthreads();
+    if (lane == 0) {
+      const double mi = mi64_of_table(J.P64, lds_t, cells, st->m0, st->m1);
+      r.mi = mi;
+      const double d = fabs((double)r.mi32 - mi);
+      r.rel_err = mi != 0.0 ? (float)(d / fabs(mi)) : (float)d;
+      // the filters assumed |mi32 - mi| <= 1e-5 mi + 1e-10
+      if (d > 1e-5 * fabs(mi) + 1e-10) atomicOr(&st->flags, kFlagBound);
+      for (uint32_t q = 0; q < kMaxOrder; ++q) r.snp[q] = q < J.k ? c[q] : 0xffffffffu;
+      J.l2[i] = r;
+    }
+    __syncthreads();
+  }
+}
+
+// 4. one workgroup per job: bitonic sort of the rescored candidates in LDS by
+// (mi descending, rank ascending) and output of the first top_n.
+__global__ __launch_bounds__(1024) void finish_kernel(Globals g) {
+  const JobDesc &J = g.jobs[blockIdx.x];
+  JobState *st = J.state;
+  const uint32_t tid = threadIdx.x;
+  __shared__ double s_mi[kSortMax];
+  __shared__ u64 s_rank[kSortMax];
+  __shared__ uint16_t s_idx[kSortMax];
+  int32_t status = st->status;
+  if (status == 0 && (st->flags & kFlagCandOverflow)) status = FIUNCHO_E_WORKSPACE;
+  if (status == 0 && (st->flags & kFlagTieOverflow)) status = FIUNCHO_E_WORKSPACE;
+  const u64 want64 = J.total < (u64)J.top_n ? J.total : (u64)J.top_n;
+  const uint32_t want = (uint32_t)want64;
+  if (status != 0) {
+    if (tid == 0) {
+      *J.n_out = 0;
+      if (J.status_out) *J.status_out = status;
+    }
+    return;
+  }
+  if (st->m0 == 0 || st->m1 == 0) {
+    // an empty class: every table is independent of the class, MI = 0, and the
+    // total order makes the result the first top_n ranks
+    for (uint32_t i = tid; i < want; i += blockDim.x) {
+      fiuncho_hit h;
+      uint32_t c[kMaxOrder];
+      lex_unrank(g, J.n, J.k, (u64)i, c);
+      for (uint32_t q = 0; q < kMaxOrder; ++q) h.snp[q] = q < J.k ? c[q] : 0xffffffffu;
+      h.rank = i;
+      h.mi = 0.0;
+      h.mi32 = 0.f;
+      h.rel_err = 0.f;
+      J.out[i] = h;
+    }
+    if (tid == 0) {
+      *J.n_out = want;
+      if (J.status_out) *J.status_out = 0;
+    }
+    return;
+  }
+  const uint32_t M = min(st->l2_count, J.l2_cap);
+  uint32_t P = 1;
+  while (P < M) P <<= 1;
+  for (uint32_t i = tid; i < P; i += blockDim.x) {
+    if (i < M) {
+      s_mi[i] = J.l2[i].mi;
+      s_rank[i] = J.l2[i].rank;
+    } else {
+      s_mi[i] = -INFINITY;
+      s_rank[i] = ~0ull;
+    }
+    s_idx[i] = (uint16_t)i;
+  }
+  __syncthreads();
+  // ascending in "badness": element a precedes b when a.mi > b.mi, or equal
+  // mi and a.rank < b.rank
+  for (uint32_t size = 2; size <= P; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = tid; i < P; i += blockDim.x) {
+        const uint32_t jx = i ^ stride;
+        if (jx > i) {
+          const bool up = (i & size) == 0;
+          const bool i_first = s_mi[i] > s_mi[jx] || (s_mi[i] == s_mi[jx] && s_rank[i] < s_rank[jx]);
+          if (i_first != up) {
+            const double tm = s_mi[i];
+            s_mi[i] = s_mi[jx];
+            s_mi[jx] = tm;
+            const u64 tr = s_rank[i];
+            s_rank[i] = s_rank[jx];
+            s_rank[jx] = tr;
+            const uint16_t ti = s_idx[i];
+            s_idx[i] = s_idx[jx];
+            s_idx[jx] = ti;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const uint32_t outn = min(want, M);
+  for (uint32_t i = tid; i < outn; i += blockDim.x) {
+    const Rescored r = J.l2[s_idx[i]];
+    fiuncho_hit h;
+    for (uint32_t q = 0; q < kMaxOrder; ++q) h.snp[q] = r.snp[q];
+    h.rank = r.rank;
+    h.mi = r.mi;
+    h.mi32 = r.mi32;
+    h.rel_err = r.rel_err;
+    J.out[i] = h;
+  }
+  if (tid == 0) {
+    *J.n_out = outn;
+    if (J.status_out) *J.status_out = 0;
+  }
+}
+
+// explicit tables of given ranks (single job 0)
+__global__ __launch_bounds__(64) void tables_kernel(Globals g, const u64 *ranks, u64 n_ranks,
+                                                    uint32_t *tables) {
+  const JobDesc &J = g.jobs[0];
+  const JobState *st = J.state;
+  if (st->status != 0) return;
+  const u64 i = blockIdx.x + (u64)blockIdx.y * gridDim.x;
+  if (i >= n_ranks) return;
+  uint32_t cells = 1;
+  for (uint32_t q = 0; q < J.k; ++q) cells *= 3;
+  uint32_t c[kMaxOrder];
+  lex_unrank(g, J.n, J.k, ranks[i], c);
+  count_cells<true>(J, st, c, J.k, lane_id(), nullptr, tables + i * 2 * cells);
+}
+
+void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s) {
+  uint32_t blocks = (max_cand_cap + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(compact_kernel, dim3(blocks, g.n_jobs), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(select_kernel, dim3(g.n_jobs), dim3(1024), 0, s, g);
+}
+
+void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s) {
+  uint32_t cells = 1;
+  for (uint32_t q = 0; q < max_k; ++q) cells *= 3;
+  const size_t lds = sizeof(uint32_t) * 2 * cells;
+  hipLaunchKernelGGL(rescore_kernel, dim3(std::min<uint32_t>(max_l2_cap, 512), g.n_jobs), dim3(64), lds, s, g);
+}
+
+void launch_finish(const Globals &g, hipStream_t s) {
+  hipLaunchKernelGGL(finish_kernel, dim3(g.n_jobs), dim3(1024), 0, s, g);
+}
+
+void launch_tables(const Globals &g, const unsigned long long *ranks, uint64_t n_ranks,
+                   uint32_t *tables, hipStream_t s) {
+  const uint64_t gx = n_ranks < 65535 ? (n_ranks ? n_ranks : 1) : 65535;
+  const uint64_t gy = (n_ranks + gx - 1) / gx;
+  hipLaunchKernelGGL(tables_kernel, dim3((uint32_t)gx, (uint32_t)(gy ? gy : 1)), dim3(64), 0, s,
+                     g, ranks, (u64)n_ranks, tables);
+}
+
+}  // namespace fiuncho

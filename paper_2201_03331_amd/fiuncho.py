@@ -1,0 +1,237 @@
+"""Python binding of libfiuncho.so (argument marshalling only).
+
+Every step of the search runs in the library's gfx950 kernels; this module
+loads the in-tree shared library, converts arguments and returns numpy arrays.
+It fails loudly when the library is missing: there is no CPU fallback.
+PyTorch is used only for device memory and streams (``DeviceBatch``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfiuncho.so")
+
+OK = 0
+E_NULL = -1
+E_SHAPE = -2
+E_GENOTYPE = -3
+E_PHENOTYPE = -4
+E_ORDER = -5
+E_TOPN = -6
+E_OVERFLOW = -7
+E_WORKSPACE = -8
+E_DEVICE = -9
+MAX_ORDER = 8
+MAX_TOPN = 2048
+DEVICE_PTRS = 1
+
+# every entry point declared in include/fiuncho.h
+EXPORTS = (
+    "fiuncho_scan",
+    "fiuncho_workspace_bytes",
+    "fiuncho_scan_batch",
+    "fiuncho_contingency",
+    "fiuncho_last_error",
+    "fiuncho_set_profiling",
+    "fiuncho_get_profile",
+)
+
+HIT_DTYPE = np.dtype([("snp", "<u4", (MAX_ORDER,)), ("rank", "<u8"), ("mi", "<f8"),
+                      ("mi32", "<f4"), ("rel_err", "<f4")])
+assert HIT_DTYPE.itemsize == 56
+
+
+class Job(ctypes.Structure):
+    _fields_ = [
+        ("genotypes", ctypes.c_void_p),
+        ("phenotype", ctypes.c_void_p),
+        ("snps", ctypes.c_uint32),
+        ("samples", ctypes.c_uint32),
+        ("order", ctypes.c_int),
+        ("top_n", ctypes.c_uint32),
+        ("out", ctypes.c_void_p),
+        ("n_out", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
+    ]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [
+        ("pack_ms", ctypes.c_float),
+        ("scan_ms", ctypes.c_float),
+        ("select_ms", ctypes.c_float),
+        ("total_ms", ctypes.c_float),
+        ("calls", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("combinations", ctypes.c_uint64),
+        ("candidates", ctypes.c_uint64),
+        ("kept", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class FiunchoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fiuncho error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2201_03331_amd.build` "
+                "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        u8p = ctypes.c_void_p
+        L.fiuncho_scan.restype = ctypes.c_int
+        L.fiuncho_scan.argtypes = [u8p, u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                   ctypes.c_uint32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]
+        L.fiuncho_workspace_bytes.restype = ctypes.c_size_t
+        L.fiuncho_workspace_bytes.argtypes = [ctypes.POINTER(Job), ctypes.c_uint32]
+        L.fiuncho_scan_batch.restype = ctypes.c_int
+        L.fiuncho_scan_batch.argtypes = [ctypes.POINTER(Job), ctypes.c_uint32, ctypes.c_uint32,
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.fiuncho_contingency.restype = ctypes.c_int
+        L.fiuncho_contingency.argtypes = [u8p, u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+        L.fiuncho_last_error.restype = ctypes.c_char_p
+        L.fiuncho_last_error.argtypes = []
+        L.fiuncho_set_profiling.restype = None
+        L.fiuncho_set_profiling.argtypes = [ctypes.c_int]
+        L.fiuncho_get_profile.restype = ctypes.c_int
+        L.fiuncho_get_profile.argtypes = [ctypes.POINTER(Profile)]
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().fiuncho_last_error().decode()
+
+
+def _check(code: int):
+    if code != OK:
+        raise FiunchoError(code, last_error())
+
+
+def _host_arrays(G, y):
+    G = np.ascontiguousarray(G, dtype=np.uint8)
+    y = np.ascontiguousarray(y, dtype=np.uint8)
+    if G.ndim != 2 or y.ndim != 1 or G.shape[1] != y.shape[0]:
+        raise ValueError("genotypes must be [snps][samples] and phenotype [samples]")
+    return G, y
+
+
+def scan(G, y, order: int, top_n: int) -> np.ndarray:
+    """Exhaustive search on host arrays (fiuncho_scan); hits best first."""
+    G, y = _host_arrays(G, y)
+    out = np.zeros(max(top_n, 1), dtype=HIT_DTYPE)
+    n_out = ctypes.c_uint32(0)
+    _check(lib().fiuncho_scan(G.ctypes.data, y.ctypes.data, G.shape[0], G.shape[1], order, top_n,
+                              out.ctypes.data, ctypes.byref(n_out)))
+    return out[: n_out.value]
+
+
+def scan_code(G, y, order: int, top_n: int) -> int:
+    """Return code of fiuncho_scan (for error-path checks)."""
+    G = np.ascontiguousarray(G, dtype=np.uint8)
+    y = np.ascontiguousarray(y, dtype=np.uint8)
+    out = np.zeros(max(top_n, 1), dtype=HIT_DTYPE)
+    n_out = ctypes.c_uint32(7)
+    n = G.shape[0] if G.ndim == 2 else 0
+    m = G.shape[1] if G.ndim == 2 else 0
+    code = lib().fiuncho_scan(G.ctypes.data, y.ctypes.data, n, m, order, top_n, out.ctypes.data,
+                              ctypes.byref(n_out))
+    if code != OK:
+        assert n_out.value == 0
+    return code
+
+
+def contingency(G, y, order: int, ranks) -> np.ndarray:
+    """Contingency tables [len(ranks)][3**order][2] (fiuncho_contingency)."""
+    G, y = _host_arrays(G, y)
+    r = np.ascontiguousarray(ranks, dtype=np.uint64)
+    tabs = np.zeros((len(r), 3 ** order, 2), dtype=np.uint32)
+    _check(lib().fiuncho_contingency(G.ctypes.data, y.ctypes.data, G.shape[0], G.shape[1], order,
+                                     r.ctypes.data, len(r), tabs.ctypes.data))
+    return tabs
+
+
+def set_profiling(enable: bool):
+    lib().fiuncho_set_profiling(1 if enable else 0)
+
+
+def get_profile() -> dict:
+    p = Profile()
+    _check(lib().fiuncho_get_profile(ctypes.byref(p)))
+    return {f: getattr(p, f) for f, _ in Profile._fields_}
+
+
+def _job_shapes(shapes):
+    arr = (Job * len(shapes))()
+    for i, (n, m, k, top) in enumerate(shapes):
+        arr[i].snps, arr[i].samples, arr[i].order, arr[i].top_n = n, m, k, top
+    return arr
+
+
+def workspace_bytes(shapes) -> int:
+    """Workspace for jobs given as (snps, samples, order, top_n) tuples."""
+    arr = _job_shapes(shapes)
+    return int(lib().fiuncho_workspace_bytes(arr, len(shapes)))
+
+
+class DeviceBatch:
+    """Inputs, outputs and workspace of a batched search held in device memory
+    (torch tensors); ``run`` queues fiuncho_scan_batch on a stream."""
+
+    def __init__(self, datasets, device="cuda"):
+        import torch
+
+        self.torch = torch
+        self.shapes = [(d.n, d.m, d.order, d.top_n) for d in datasets]
+        self.G = [torch.from_numpy(np.ascontiguousarray(d.genotypes)).to(device) for d in datasets]
+        self.y = [torch.from_numpy(np.ascontiguousarray(d.phenotype)).to(device) for d in datasets]
+        self.out = [torch.zeros(d.top_n * HIT_DTYPE.itemsize, dtype=torch.uint8, device=device)
+                    for d in datasets]
+        self.n_out = torch.zeros(len(datasets), dtype=torch.int32, device=device)
+        self.status = torch.zeros(len(datasets), dtype=torch.int32, device=device)
+        self.jobs = (Job * len(datasets))()
+        for i, d in enumerate(datasets):
+            J = self.jobs[i]
+            J.genotypes = self.G[i].data_ptr()
+            J.phenotype = self.y[i].data_ptr()
+            J.snps, J.samples, J.order, J.top_n = d.n, d.m, d.order, d.top_n
+            J.out = self.out[i].data_ptr()
+            J.n_out = self.n_out.data_ptr() + 4 * i
+            J.status = self.status.data_ptr() + 4 * i
+        self.ws_bytes = int(lib().fiuncho_workspace_bytes(self.jobs, len(datasets)))
+        if self.ws_bytes == 0:
+            raise FiunchoError(E_SHAPE, last_error())
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        self.ws_ptr = (self.ws.data_ptr() + 255) & ~255
+
+    def run(self, stream=None):
+        s = stream if stream is not None else self.torch.cuda.current_stream()
+        _check(lib().fiuncho_scan_batch(self.jobs, len(self.shapes), DEVICE_PTRS, self.ws_ptr,
+                                        self.ws_bytes, s.cuda_stream))
+
+    def results(self):
+        """Per job: (status, hits) after the stream has finished."""
+        self.torch.cuda.synchronize()
+        n_out = self.n_out.cpu().numpy()
+        status = self.status.cpu().numpy()
+        res = []
+        for i in range(len(self.shapes)):
+            raw = self.out[i].cpu().numpy()
+            hits = raw.view(HIT_DTYPE)[: int(n_out[i])].copy()
+            res.append((int(status[i]), hits))
+        return res

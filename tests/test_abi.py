@@ -1,0 +1,97 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects invalid input on the host before any device work
+(no GPU is touched by these tests)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2201_03331_amd import fiuncho
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "fiuncho.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fiuncho_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = fiuncho.lib()
+    decl = declared_functions()
+    assert decl == sorted(fiuncho.EXPORTS)
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+def test_hit_layout_matches_header():
+    # snp[8] (32 B) + rank (8 B) + mi (8 B) + mi32 + rel_err (8 B)
+    assert fiuncho.HIT_DTYPE.itemsize == 56
+    assert ctypes.sizeof(fiuncho.Job) == 56
+
+
+def _data(n=6, m=40, seed=0):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 3, (n, m), dtype=np.uint8), (rng.random(m) < 0.5).astype(np.uint8)
+
+
+def test_host_validation_codes():
+    G, y = _data()
+    Gb = G.copy()
+    Gb[2, 5] = 3
+    assert fiuncho.scan_code(Gb, y, 2, 5) == fiuncho.E_GENOTYPE
+    assert "variant 2, sample 5" in fiuncho.last_error()
+    yb = y.copy()
+    yb[3] = 2
+    assert fiuncho.scan_code(G, yb, 2, 5) == fiuncho.E_PHENOTYPE
+    assert fiuncho.scan_code(G, y, 0, 5) == fiuncho.E_ORDER
+    assert fiuncho.scan_code(G, y, 7, 5) == fiuncho.E_ORDER
+    assert fiuncho.scan_code(G, y, 9, 5) == fiuncho.E_ORDER
+    assert fiuncho.scan_code(G, y, 2, 0) == fiuncho.E_TOPN
+    assert fiuncho.scan_code(G, y, 2, fiuncho.MAX_TOPN + 1) == fiuncho.E_TOPN
+
+
+def test_overflow_and_shape_codes():
+    # C(2^20, 8) does not fit in 63 bits; samples is irrelevant to the check
+    big = np.zeros((1, 1), np.uint8)
+    L = fiuncho.lib()
+    n_out = ctypes.c_uint32(0)
+    out = np.zeros(4, fiuncho.HIT_DTYPE)
+    y = np.zeros(1, np.uint8)
+    code = L.fiuncho_scan(big.ctypes.data, y.ctypes.data, 1 << 20, 1, 8, 4, out.ctypes.data,
+                          ctypes.byref(n_out))
+    assert code == fiuncho.E_OVERFLOW
+    code = L.fiuncho_scan(big.ctypes.data, y.ctypes.data, 4, 1 << 24, 2, 4, out.ctypes.data,
+                          ctypes.byref(n_out))
+    assert code == fiuncho.E_SHAPE
+    code = L.fiuncho_scan(None, y.ctypes.data, 4, 4, 2, 4, out.ctypes.data, ctypes.byref(n_out))
+    assert code == fiuncho.E_NULL
+
+
+def test_workspace_bytes_depends_on_shape_only():
+    a = fiuncho.workspace_bytes([(100, 1600, 2, 10)])
+    b = fiuncho.workspace_bytes([(100, 1600, 2, 10)])
+    c = fiuncho.workspace_bytes([(100, 1600, 2, 10), (50, 999, 3, 7)])
+    assert a == b > 0 and c > a
+    assert fiuncho.workspace_bytes([(100, 1600, 0, 10)]) == 0
+
+
+def test_contingency_rejects_bad_rank():
+    G, y = _data()
+    with pytest.raises(fiuncho.FiunchoError) as e:
+        fiuncho.contingency(G, y, 2, [15])   # C(6, 2) = 15
+    assert e.value.code == fiuncho.E_SHAPE
+
+
+def test_no_cpu_fallback_in_product():
+    """The product package never imports or calls the reference."""
+    pkg = os.path.join(ROOT, "paper_2201_03331_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "liboracle" not in text, f

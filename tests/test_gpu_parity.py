@@ -1,0 +1,235 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: contingency tables and the top-N set (ranks, order) bit-exact; the FP64
+score of every hit bit-identical to the oracle's (same table, same Eq. 1-3
+evaluation order); the FP32 score within 1e-5 relative + 1e-10 absolute of
+the FP64 one.  Full-size workloads are checked on sampled ranks the oracle
+scores one by one, plus a necessary condition of the top-N set on them.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_03331_amd import fiuncho, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_REL = 1e-5
+TOL_ABS = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def check_hits_against_oracle(G, y, k, top_n, hits, nthreads=0):
+    """Full oracle scan and element-by-element comparison."""
+    r_or, m_or = oracle.scan(G, y, k, top_n, nthreads=nthreads)
+    assert len(hits) == len(r_or)
+    np.testing.assert_array_equal(hits["rank"], r_or)
+    np.testing.assert_array_equal(hits["mi"], m_or)          # bit-identical FP64
+    err = np.abs(hits["mi32"].astype(np.float64) - m_or)
+    assert np.all(err <= TOL_REL * np.abs(m_or) + TOL_ABS), err.max()
+    n = G.shape[0]
+    for h in hits:
+        assert tuple(h["snp"][:k]) == oracle.unrank(n, k, int(h["rank"]))
+        assert np.all(h["snp"][k:] == 0xFFFFFFFF)
+
+
+def random_dataset(seed, n, m, frac, mono=0, dup=0):
+    rng = np.random.default_rng(seed)
+    G = rng.binomial(2, rng.uniform(0.05, 0.5, size=(n, 1)), size=(n, m)).astype(np.uint8)
+    y = (rng.random(m) < frac).astype(np.uint8)
+    if y.sum() == 0 and frac > 0:
+        y[0] = 1
+    for i in range(mono):
+        G[i] = 1
+    for i in range(dup):
+        G[n - 1 - i] = G[i + mono]
+    return G, y
+
+
+# ---------------------------------------------------------------------------
+# order-2 workload (100 variants x 1600 samples): every table, and the result
+# ---------------------------------------------------------------------------
+
+def test_order2_small_all_tables():
+    d = synth.order2_small()
+    say("case: order2 100x1600 all tables")
+    total = math.comb(d.n, 2)
+    ranks = np.arange(total, dtype=np.uint64)
+    gpu = fiuncho.contingency(d.genotypes, d.phenotype, 2, ranks)
+    _, ref = oracle.score_ranks(d.genotypes, d.phenotype, 2, ranks, want_tables=True)
+    np.testing.assert_array_equal(gpu, ref)
+
+
+def test_order2_small_scan():
+    d = synth.order2_small()
+    say("case: order2 100x1600 scan top-10")
+    hits = fiuncho.scan(d.genotypes, d.phenotype, 2, d.top_n)
+    check_hits_against_oracle(d.genotypes, d.phenotype, 2, d.top_n, hits)
+    assert tuple(hits[0]["snp"][:2]) == d.planted[0]
+
+
+# ---------------------------------------------------------------------------
+# small ragged cases, every order, full oracle comparison
+# ---------------------------------------------------------------------------
+
+CASES = [
+    # seed, n, m, case fraction, order, top_n, monomorphic, duplicated
+    (1, 30, 130, 0.5, 1, 5, 0, 0),
+    (2, 40, 64, 0.5, 2, 7, 0, 0),
+    (3, 70, 200, 0.3, 2, 50, 2, 3),
+    (4, 31, 1, 1.0, 2, 3, 0, 0),           # a single sample (one empty class)
+    (5, 45, 257, 0.7, 3, 20, 1, 2),
+    (6, 25, 65, 0.02, 3, 40, 0, 0),        # one or two cases only
+    (7, 18, 300, 0.5, 4, 15, 0, 1),
+    (8, 14, 190, 0.4, 5, 10, 1, 1),
+    (9, 10, 77, 0.5, 6, 9, 0, 0),
+    (10, 9, 50, 0.5, 8, 5, 0, 0),
+    (11, 12, 129, 0.5, 3, 300, 0, 0),      # top_n > C(n, k)
+    (12, 5, 99, 0.5, 5, 4, 0, 0),          # n == k: a single combination
+    (13, 130, 70, 0.5, 2, 2048, 0, 0),     # largest top_n
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"seed{c[0]}-n{c[1]}-m{c[2]}-k{c[4]}" for c in CASES])
+def test_small_cases(case):
+    seed, n, m, frac, k, top, mono, dup = case
+    say(f"case: {case}")
+    G, y = random_dataset(seed, n, m, frac, mono, dup)
+    hits = fiuncho.scan(G, y, k, top)
+    check_hits_against_oracle(G, y, k, top, hits)
+    # tables of every hit
+    if len(hits):
+        gpu = fiuncho.contingency(G, y, k, hits["rank"])
+        _, ref = oracle.score_ranks(G, y, k, hits["rank"], want_tables=True)
+        np.testing.assert_array_equal(gpu, ref)
+
+
+def test_empty_class_returns_first_ranks():
+    say("case: empty class")
+    G, _ = random_dataset(20, 12, 90, 0.5)
+    y = np.zeros(90, np.uint8)
+    hits = fiuncho.scan(G, y, 3, 25)
+    np.testing.assert_array_equal(hits["rank"], np.arange(25))
+    assert np.all(hits["mi"] == 0.0)
+    check_hits_against_oracle(G, y, 3, 25, hits)
+
+
+def test_all_monomorphic_ties_go_to_lowest_ranks():
+    say("case: monomorphic ties")
+    G = np.ones((20, 150), np.uint8)
+    y = (np.arange(150) % 3 == 0).astype(np.uint8)
+    hits = fiuncho.scan(G, y, 2, 30)
+    np.testing.assert_array_equal(hits["rank"], np.arange(30))
+    check_hits_against_oracle(G, y, 2, 30, hits)
+
+
+def test_duplication_gives_zero_mi():
+    """Every sample once as a control and once as a case: MI = 0 exactly in
+    real arithmetic for every combination."""
+    say("case: duplication")
+    G, _ = random_dataset(21, 16, 120, 0.5)
+    G2 = np.concatenate([G, G], axis=1)
+    y2 = np.array([0] * 120 + [1] * 120, np.uint8)
+    hits = fiuncho.scan(G2, y2, 3, 20)
+    assert np.all(np.abs(hits["mi"]) <= 1e-14)
+    assert np.all(np.abs(hits["mi32"]) <= 1e-9)
+    check_hits_against_oracle(G2, y2, 3, 20, hits)
+
+
+def test_deterministic():
+    G, y = random_dataset(22, 60, 333, 0.4, 0, 4)
+    a = fiuncho.scan(G, y, 3, 64)
+    b = fiuncho.scan(G, y, 3, 64)
+    assert a.tobytes() == b.tobytes()
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads: sampled parity and top-N necessary conditions
+# ---------------------------------------------------------------------------
+
+def full_size_check(d, n_sample, seed):
+    k = d.order
+    G, y = d.genotypes, d.phenotype
+    say(f"case: {d.name} full scan")
+    hits = fiuncho.scan(G, y, k, d.top_n)
+    assert len(hits) == d.top_n
+    # hits: tables and FP64 scores equal the oracle's, in the total order
+    mi_or, tab_or = oracle.score_ranks(G, y, k, hits["rank"], want_tables=True)
+    np.testing.assert_array_equal(hits["mi"], mi_or)
+    np.testing.assert_array_equal(fiuncho.contingency(G, y, k, hits["rank"]), tab_or)
+    order = np.lexsort((hits["rank"], -hits["mi"]))
+    np.testing.assert_array_equal(order, np.arange(len(hits)))
+    err = np.abs(hits["mi32"].astype(np.float64) - hits["mi"])
+    assert np.all(err <= TOL_REL * np.abs(hits["mi"]) + TOL_ABS)
+    # the planted interaction of this order ranks first
+    planted = [p for p in d.planted if len(p) == k]
+    if planted:
+        assert tuple(hits[0]["snp"][:k]) == planted[0]
+    # sampled combinations: tables equal; none beats the last hit
+    total = math.comb(d.n, k)
+    rng = np.random.default_rng(seed)
+    ranks = np.unique(rng.integers(0, total, size=n_sample, dtype=np.uint64))
+    say(f"case: {d.name} sampled {len(ranks)} ranks")
+    mi_s, tab_s = oracle.score_ranks(G, y, k, ranks, want_tables=True)
+    np.testing.assert_array_equal(fiuncho.contingency(G, y, k, ranks), tab_s)
+    last_mi, last_rank = hits[-1]["mi"], hits[-1]["rank"]
+    in_hits = np.isin(ranks, hits["rank"])
+    beats = (mi_s > last_mi) | ((mi_s == last_mi) & (ranks < last_rank))
+    assert not np.any(beats & ~in_hits)
+    return hits
+
+
+def test_order3_main_workload():
+    full_size_check(synth.order3_main(), 20000, 31)
+
+
+def test_order2_dense_workload():
+    full_size_check(synth.order2_dense(), 20000, 32)
+
+
+def test_order4_high_order_workload():
+    full_size_check(synth.high_order(4), 20000, 34)
+
+
+# ---------------------------------------------------------------------------
+# batched form on device pointers
+# ---------------------------------------------------------------------------
+
+def test_batch_matches_oracle_per_job():
+    import torch
+
+    jobs = synth.batch_jobs(12, scale=0.04)
+    say("case: batch of", len(jobs), [(j.n, j.m, j.order) for j in jobs])
+    b = fiuncho.DeviceBatch(jobs)
+    b.run()
+    res = b.results()
+    for d, (status, hits) in zip(jobs, res):
+        assert status == 0
+        check_hits_against_oracle(d.genotypes, d.phenotype, d.order, d.top_n, hits)
+    # a second run on the same workspace gives the same bytes
+    b.run()
+    res2 = b.results()
+    for (s1, h1), (s2, h2) in zip(res, res2):
+        assert s1 == s2 and h1.tobytes() == h2.tobytes()
+    torch.cuda.synchronize()
+
+
+def test_batch_device_validation():
+    import torch
+
+    d = synth.generate(20, 100, seed=5, order=2, top_n=5)
+    bad = synth.generate(20, 100, seed=6, order=2, top_n=5)
+    bad.genotypes[3, 17] = 7
+    b = fiuncho.DeviceBatch([d, bad])
+    b.run()
+    res = b.results()
+    assert res[0][0] == 0 and len(res[0][1]) == 5
+    assert res[1][0] == fiuncho.E_GENOTYPE and len(res[1][1]) == 0
+    torch.cuda.synchronize()
