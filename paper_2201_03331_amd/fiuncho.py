@@ -87,6 +87,13 @@ def lib() -> ctypes.CDLL:
     """The loaded library (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # PyTorch ships its own HIP runtime under the same soname; loading it
+        # first makes this library bind to it, so that torch tensors, torch
+        # streams and these kernels share one runtime in the process.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(
                 f"{LIB_PATH} is missing: build it with `python -m paper_2201_03331_amd.build` "
