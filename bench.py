@@ -60,7 +60,7 @@ def word_ops_per_combination(k: int, m0: int, m1: int) -> int:
     return 2 * 3 ** (k - 1) * W
 
 
-def cpu_baseline(d, budget_s: float = 15.0):
+def cpu_baseline(d, budget_s: float = 20.0):
     """The oracle (plain per-sample counting, FP64 MI) timed on the host cores
     over a contiguous sample of ranks of the same workload."""
     import oracle
