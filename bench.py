@@ -10,8 +10,9 @@ stream.  Prints ONE JSON line.
 
 Workloads (seeded synthetic data, see paper_2201_03331_amd/synth.py):
   order3-1000x6400 (default), order2-100x1600, order2-4000x16000,
-  order4-200x4000, order5-200x4000, batch64 (64 uneven datasets in one call),
-  batch64-plain (the same 64 datasets, one call each).
+  order4-200x4000, order5-200x4000, batch64 (64 uneven datasets in one
+  persistent launch, replayed from a HIP graph), batch64-plain (the same 64
+  datasets, one call each).
 """
 from __future__ import annotations
 
@@ -112,8 +113,14 @@ def main():
     plain = args.workload.endswith("-plain")
     batches = [fiuncho.DeviceBatch([d]) for d in datasets] if plain else [fiuncho.DeviceBatch(datasets)]
     stream = torch.cuda.current_stream()
+    graph = args.workload == "batch64"
+    if graph:
+        batches[0].capture()
 
     def step():
+        if graph:
+            batches[0].replay()
+            return
         for b in batches:
             b.run(stream)
 

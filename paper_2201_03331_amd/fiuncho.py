@@ -231,6 +231,22 @@ class DeviceBatch:
         _check(lib().fiuncho_scan_batch(self.jobs, len(self.shapes), DEVICE_PTRS, self.ws_ptr,
                                         self.ws_bytes, s.cuda_stream))
 
+    def capture(self):
+        """Capture one ``run`` into a HIP graph (torch.cuda.CUDAGraph).  The
+        first eager ``run`` uploads the plan; the captured call then queues
+        kernels only (no allocation, no memset, no host synchronisation)."""
+        torch = self.torch
+        self.run()
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.run(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        return self.graph
+
+    def replay(self):
+        self.graph.replay()
+
     def results(self):
         """Per job: (status, hits) after the stream has finished."""
         self.torch.cuda.synchronize()

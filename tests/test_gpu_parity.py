@@ -233,3 +233,33 @@ def test_batch_device_validation():
     assert res[0][0] == 0 and len(res[0][1]) == 5
     assert res[1][0] == fiuncho.E_GENOTYPE and len(res[1][1]) == 0
     torch.cuda.synchronize()
+
+
+def test_batch_graph_replay():
+    """The batched call captured in a HIP graph and replayed several times,
+    with eager work and synchronisations in between: every replay equals the
+    eager result (and the oracle)."""
+    import torch
+
+    jobs = synth.batch_jobs(6, scale=0.05)
+    say("case: graph replay", [(j.n, j.m, j.order) for j in jobs])
+    b = fiuncho.DeviceBatch(jobs)
+    b.run()
+    eager = b.results()
+    for d, (status, hits) in zip(jobs, eager):
+        assert status == 0
+        check_hits_against_oracle(d.genotypes, d.phenotype, d.order, d.top_n, hits)
+    b.capture()
+    for rep in range(3):
+        for o in b.out:
+            o.zero_()
+        b.n_out.zero_()
+        b.status.fill_(99)
+        torch.cuda.synchronize()
+        b.replay()
+        got = b.results()
+        for (s1, h1), (s2, h2) in zip(eager, got):
+            assert s1 == s2 and h1.tobytes() == h2.tobytes(), rep
+        # unrelated eager work between replays
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
