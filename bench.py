@@ -115,7 +115,7 @@ def main():
     stream = torch.cuda.current_stream()
     graph = args.workload == "batch64"
     if graph:
-        batches[0].capture()
+        batches[0].capture(profile=True)
 
     def step():
         if graph:
@@ -127,7 +127,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    fiuncho.set_profiling(True)
+    fiuncho.set_profiling(not graph)
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record(stream)

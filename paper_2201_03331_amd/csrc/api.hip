@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -83,7 +84,7 @@ int check_values(const uint8_t *G, const uint8_t *y, uint32_t n, uint32_t m) {
 // ---------------------------------------------------------------------------
 // tile tables: rows and tiles per row, as the scan kernel decodes them
 // ---------------------------------------------------------------------------
-void build_rows(uint32_t n, uint32_t k, std::vector<u64> &row_start) {
+void build_rows(uint32_t n, uint32_t k, uint32_t path, std::vector<u64> &row_start) {
   row_start.clear();
   row_start.push_back(0);
   u64 acc = 0;
@@ -102,6 +103,15 @@ void build_rows(uint32_t n, uint32_t k, std::vector<u64> &row_start) {
     }
     return;
   }
+  if (path == fiuncho::kPathPairs) {
+    // rows b = 1 .. n-2; groups of kScanWaves * kOrder3Prefixes first variants
+    for (u64 b = 1; b + 2 <= n; ++b) {
+      const u64 groups = ceil_div(b, (u64)fiuncho::kScanWaves * fiuncho::kOrder3Prefixes);
+      acc += groups * ceil_div(n - 1 - b, 64);
+      row_start.push_back(acc);
+    }
+    return;
+  }
   for (u64 b = k - 2; b + 2 <= n; ++b) {
     const u64 groups = ceil_div(binom_host(b, k - 2), fiuncho::kScanWaves);
     acc += groups * ceil_div(n - 1 - b, 64);
@@ -113,11 +123,11 @@ void build_rows(uint32_t n, uint32_t k, std::vector<u64> &row_start) {
 // workspace layout
 // ---------------------------------------------------------------------------
 struct JobLayout {
-  uint32_t n, m, k, top_n, n_pad, wcap, nrows;
+  uint32_t n, m, k, top_n, n_pad, wcap, nrows, path;
   u64 total;
   uint32_t cand_cap, l1_cap, l2_cap;
   size_t off_G, off_y, off_idx, off_Bv, off_Bs, off_marg, off_hist, off_cand, off_l1, off_l2,
-      off_state, off_out, off_nout, off_status;
+      off_state, off_out, off_nout, off_status, off_pairs;
   // plan (uploaded)
   size_t off_rows, off_F32, off_P64;
   std::vector<u64> row_start;
@@ -128,7 +138,7 @@ struct JobLayout {
 struct Layout {
   std::vector<JobLayout> jobs;
   std::vector<uint32_t> order;  // tile-space order of the jobs (costliest first)
-  uint32_t nmax, kmax, max_n_pad, max_cand_cap, max_l2_cap;
+  uint32_t nmax, kmax, max_n_pad, max_cand_cap, max_l2_cap, max_pairs_n;
   size_t plan_begin, plan_end;  // uploaded region
   size_t off_desc, off_jts, off_binom, off_counter;
   size_t total;
@@ -144,6 +154,9 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
   L.max_n_pad = 0;
   L.max_cand_cap = 0;
   L.max_l2_cap = 0;
+  L.max_pairs_n = 0;
+  const char *env_pairs = std::getenv("FIUNCHO_ORDER3_PAIRS");
+  const bool use_pairs = !(env_pairs && env_pairs[0] == '0');
   size_t off = 0;
   // per-job data
   for (uint32_t i = 0; i < n_jobs; ++i) {
@@ -163,12 +176,16 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     J.cand_cap = (uint32_t)std::max<u64>(cap, 1);
     J.l1_cap = J.cand_cap;
     J.l2_cap = fiuncho::kSortMax;
-    build_rows(J.n, J.k, J.row_start);
+    J.path = (J.k == 3 && J.n >= 3 && use_pairs) ? fiuncho::kPathPairs : fiuncho::kPathGeneric;
+    build_rows(J.n, J.k, J.path, J.row_start);
     J.nrows = (uint32_t)(J.row_start.size() - 1);
     J.tiles = J.row_start.back();
     const double words = (double)J.wcap;
-    J.cost = J.k == 1 ? 1.0 : J.k == 2 ? words * 4 * fiuncho::kOrder2Prefixes
-                                        : words * 18 * std::pow(3.0, (double)J.k - 3);
+    J.cost = J.k == 1 ? 1.0
+             : J.k == 2 ? words * 4 * fiuncho::kOrder2Prefixes
+             : J.path == fiuncho::kPathPairs ? words * 8 * fiuncho::kOrder3Prefixes
+                                             : words * 18 * std::pow(3.0, (double)J.k - 3);
+    if (J.path == fiuncho::kPathPairs) L.max_pairs_n = std::max(L.max_pairs_n, J.n);
     L.nmax = std::max(L.nmax, J.n);
     L.kmax = std::max(L.kmax, J.k);
     L.max_n_pad = std::max(L.max_n_pad, J.n_pad);
@@ -194,6 +211,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     J.off_out = host_inputs ? take(sizeof(fiuncho_hit) * J.top_n) : 0;
     J.off_nout = host_inputs ? take(sizeof(uint32_t)) : 0;
     J.off_status = host_inputs ? take(sizeof(int32_t)) : 0;
+    J.off_pairs = J.path == fiuncho::kPathPairs ? take(sizeof(uint32_t) * 8 * (size_t)J.n * J.n_pad) : 0;
   }
   // plan region
   L.plan_begin = off;
@@ -219,10 +237,12 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
   for (uint32_t i = 0; i < n_jobs; ++i) L.order[i] = i;
   std::stable_sort(L.order.begin(), L.order.end(),
                    [&](uint32_t a, uint32_t b) { return L.jobs[a].cost > L.jobs[b].cost; });
-  L.ksel = (int)L.jobs[0].k;
+  auto sel = [](const JobLayout &J) {
+    return J.path == fiuncho::kPathPairs ? fiuncho::kSelPairs : (J.k <= 5 ? (int)J.k : 0);
+  };
+  L.ksel = sel(L.jobs[0]);
   for (auto &J : L.jobs)
-    if ((int)J.k != L.ksel) L.ksel = 0;
-  if (L.ksel > 5) L.ksel = 0;
+    if (sel(J) != L.ksel) L.ksel = 0;
   return FIUNCHO_OK;
 }
 
@@ -289,6 +309,8 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
     d.l1 = reinterpret_cast<Cand *>(ws + J.off_l1);
     d.l2 = reinterpret_cast<Rescored *>(ws + J.off_l2);
     d.l2_cap = J.l2_cap;
+    d.path = J.path;
+    d.pairs = J.path == fiuncho::kPathPairs ? reinterpret_cast<uint32_t *>(ws + J.off_pairs) : nullptr;
     d.state = reinterpret_cast<JobState *>(ws + J.off_state);
     d.out = host_inputs ? reinterpret_cast<fiuncho_hit *>(ws + J.off_out) : jobs[i].out;
     d.n_out = host_inputs ? reinterpret_cast<uint32_t *>(ws + J.off_nout) : jobs[i].n_out;
@@ -411,6 +433,7 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   if ((st = prof_record(0, s))) return st;
   fiuncho::launch_init(g, s);
   fiuncho::launch_pack(g, L.max_n_pad, s);
+  if (L.max_pairs_n) fiuncho::launch_pairs(g, L.max_pairs_n, s);
   if ((st = prof_record(1, s))) return st;
   int grid = fiuncho::scan_grid_size(L.ksel);
   if ((u64)grid > g.total_tiles) grid = (int)std::max<u64>(g.total_tiles, 1);

@@ -19,6 +19,12 @@ constexpr int kHistBins = 1 << (31 - kHistShift);
 constexpr uint32_t kSortMax = 4096;           // candidates ordered in one LDS sort
 constexpr int kScanWaves = 4;                 // waves per workgroup in the scan
 constexpr int kOrder2Prefixes = 8;            // first variants per wave at order 2
+constexpr int kOrder3Prefixes = 2;            // prefixes per wave, order-3 pair path
+
+// scan paths of a job
+constexpr uint32_t kPathGeneric = 0;          // rows g = 0, 1 of the last variant
+constexpr uint32_t kPathPairs = 1;            // order 3, {0,1}^3 cells + pair tables
+constexpr int kSelPairs = 31;                 // scan_kernel selector: order-3 pair path only
 
 // state the device writes during one run of a job (cleared at the start)
 struct JobState {
@@ -81,8 +87,9 @@ struct JobDesc {
   Cand *l1;
   Rescored *l2;
   uint32_t l2_cap;
-  uint32_t pad0;
+  uint32_t path;              // kPathGeneric or kPathPairs
   JobState *state;
+  uint32_t *pairs;            // kPathPairs: [n][n_pad][g_a 0..1][g_j 0..1][class] counts
   // outputs
   fiuncho_hit *out;
   uint32_t *n_out;
@@ -102,6 +109,7 @@ struct Globals {
 // launchers (kernels.hip)
 void launch_init(const Globals &g, hipStream_t s);
 void launch_pack(const Globals &g, uint32_t max_n_pad, hipStream_t s);
+void launch_pairs(const Globals &g, uint32_t max_n, hipStream_t s);
 void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s);
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
 void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s);

@@ -38,6 +38,8 @@ struct JV {
   uint32_t *hist;
   Cand *cand;
   JobState *st;
+  const uint32_t *pairs;
+  uint32_t path;
 };
 
 template <typename T>
@@ -63,6 +65,8 @@ __device__ __forceinline__ JV load_view(const JobDesc *jd) {
   v.hist = uni_ptr(J->hist);
   v.cand = uni_ptr(J->cand);
   v.st = uni_ptr(J->state);
+  v.pairs = uni_ptr(J->pairs);
+  v.path = uni(J->path);
   return v;
 }
 
@@ -168,6 +172,59 @@ __device__ __forceinline__ void emit(const JV &v, bool active, float mi32, u64 r
   if ((old + cnt) / qs != old / qs) refresh_tau(v.hist, v.st, v.top_n, lane);
 }
 
+// Constants of the single-precision score of a job: m * MI starts at
+// f(m) - f(m0) - f(m1).
+struct MiConst {
+  float s0, e0;     // compensated start
+  float c_hi;       // plain start
+  float inv_m;
+};
+
+__device__ __forceinline__ MiConst mi_const(const JV &v) {
+  MiConst c;
+  mi_start(v, c.s0, c.e0);
+  const FI_CONST u64 *F = as_const(reinterpret_cast<const u64 *>(v.F32));
+  c.c_hi = (__uint_as_float((uint32_t)F[v.m]) - __uint_as_float((uint32_t)F[v.m0])) -
+           __uint_as_float((uint32_t)F[v.m1]);
+  c.inv_m = 1.0f / (float)v.m;
+  return c;
+}
+
+// Scores a complete table of NC cells x 2 classes and appends it if it may be
+// among the best.  A plain single-precision estimate comes first: with
+// u = 2^-24, every table value is within u f(m) of f, every cell sum within
+// 2 u f(m), and every partial sum of m * MI stays below 2m, so its error is
+// below 3u (NC + 1)(f(m) + m); an estimate more than 8u (NC + 1)(f(m) + m) / m
+// below the threshold proves the compensated score is below it too.  Only
+// the remaining lanes evaluate the compensated sum.
+template <int NC>
+__device__ __forceinline__ void score_table(const JV &v, const FI_GLOBAL u64 *F,
+                                            const uint32_t (&t)[NC][2], bool active, float thr,
+                                            const MiConst &mc, u64 rank, uint32_t lane) {
+  const float fmm = __uint_as_float((uint32_t)as_const(reinterpret_cast<const u64 *>(v.F32))[v.m]);
+  const float bound = 4.76837158203125e-07f * (float)(NC + 1) * (fmm + (float)v.m) * mc.inv_m;
+  bool maybe = false;
+  if (active) {
+    float fs = mc.c_hi;
+#pragma unroll
+    for (int x = 0; x < NC; ++x) {
+      const float a = __uint_as_float((uint32_t)F[t[x][0]]);
+      const float b = __uint_as_float((uint32_t)F[t[x][1]]);
+      const float c = __uint_as_float((uint32_t)F[t[x][0] + t[x][1]]);
+      fs += (a + b) - c;
+    }
+    maybe = fs * mc.inv_m + bound >= thr;
+  }
+  float mi32 = 0.f;
+  if (maybe) {
+    float s = mc.s0, e = mc.e0;
+#pragma unroll
+    for (int x = 0; x < NC; ++x) mi_cell(F, t[x][0], t[x][1], s, e);
+    mi32 = (s + e) * mc.inv_m;
+  }
+  emit(v, maybe, mi32, rank, thr, lane);
+}
+
 // ---------------------------------------------------------------------------
 // order 1: the contingency table of one variant is its class counts
 // ---------------------------------------------------------------------------
@@ -237,10 +294,8 @@ __device__ __forceinline__ void tile_order2(const Globals &g, const JV &v, uint3
   for (int gg = 0; gg < 2; ++gg)
 #pragma unroll
     for (int c = 0; c < 2; ++c) Mj[gg][c] = mj[2 * gg + c];
-  float s0, e0;
-  mi_start(v, s0, e0);
+  const MiConst mc = mi_const(v);
   const u64 cn2 = binom(g, n, 2);
-  const float inv_m = 1.0f / (float)v.m;
   const FI_GLOBAL u64 *F = as_global(reinterpret_cast<const u64 *>(v.F32));
   cu32p marg = as_const(v.marg);
 #pragma unroll
@@ -249,32 +304,24 @@ __device__ __forceinline__ void tile_order2(const Globals &g, const JV &v, uint3
     const bool pvalid = ap <= n - 2;
     const bool active = pvalid && j < n && j > ap;
     const uint32_t apc = pvalid ? ap : n - 2;
-    uint32_t t[3][3][2];
+    uint32_t t[9][2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const uint32_t Ma0 = marg[(size_t)apc * 6 + 0 + c];
       const uint32_t Ma1 = marg[(size_t)apc * 6 + 2 + c];
       const uint32_t Ma2 = marg[(size_t)apc * 6 + 4 + c];
-      t[0][0][c] = acc[p][c][0][0];
-      t[0][1][c] = acc[p][c][0][1];
-      t[1][0][c] = acc[p][c][1][0];
-      t[1][1][c] = acc[p][c][1][1];
-      t[0][2][c] = Ma0 - t[0][0][c] - t[0][1][c];
-      t[1][2][c] = Ma1 - t[1][0][c] - t[1][1][c];
-      t[2][0][c] = Mj[0][c] - t[0][0][c] - t[1][0][c];
-      t[2][1][c] = Mj[1][c] - t[0][1][c] - t[1][1][c];
-      t[2][2][c] = Ma2 - t[2][0][c] - t[2][1][c];
+      t[0][c] = acc[p][c][0][0];
+      t[1][c] = acc[p][c][0][1];
+      t[3][c] = acc[p][c][1][0];
+      t[4][c] = acc[p][c][1][1];
+      t[2][c] = Ma0 - t[0][c] - t[1][c];
+      t[5][c] = Ma1 - t[3][c] - t[4][c];
+      t[6][c] = Mj[0][c] - t[0][c] - t[3][c];
+      t[7][c] = Mj[1][c] - t[1][c] - t[4][c];
+      t[8][c] = Ma2 - t[6][c] - t[7][c];
     }
-    float s = s0, e = e0;
-    if (active) {
-#pragma unroll
-      for (int x = 0; x < 3; ++x)
-#pragma unroll
-        for (int y = 0; y < 3; ++y) mi_cell(F, t[x][y][0], t[x][y][1], s, e);
-    }
-    const float mi32 = (s + e) * inv_m;
     const u64 rank = cn2 - binom(g, n - apc, 2) + (u64)(j - apc - 1);
-    emit(v, active, mi32, rank, thr, lane);
+    score_table<9>(v, F, t, active, thr, mc, rank, lane);
   }
 }
 
@@ -387,6 +434,207 @@ __device__ __forceinline__ void tile_orderk(const Globals &g, const JV &v,
 }
 
 // ---------------------------------------------------------------------------
+// order 3 by inclusion-exclusion.  Every sample has exactly one genotype per
+// variant, so a count with "any genotype" at one position is the sum of the
+// counts with 0, 1 and 2 there; hence every cell with a genotype 2 follows
+// from the {0,1} cells of the combination and of its sub-combinations.  The
+// wave counts only the 8 cells of {0,1}^3 per class (4 prefix rows against
+// rows g = 0, 1 of the last variant, i.e. 8 AND+popcounts per word instead of
+// 18); the {0,1}^2 cells of every pair come from a table built beforehand by
+// the order-2 counting loop, and the {0,1} cells of every variant from the
+// per-variant class counts.
+// ---------------------------------------------------------------------------
+
+// Pair tables: PT[(a * n_pad + j) * 8 + ga * 4 + gj * 2 + c], a < j.
+// Grid: x = rows of kScanWaves * 8 first variants, y = 64-wide blocks of j,
+// z = job.  Jobs without a pair table return at once.
+__global__ __launch_bounds__(kScanWaves * 64) void pairs_kernel(Globals g) {
+  const JobDesc *jd = g.jobs + blockIdx.z;
+  JV v = load_view(jd);
+  uint32_t *PT = uni_ptr(as_const(jd)->pairs);
+  if (PT == nullptr) return;
+  const JobState *st = v.st;
+  if (uni((uint32_t)st->status) != 0) return;
+  v.W0 = uni(st->W0);
+  v.W1 = uni(st->W1);
+  const uint32_t n = v.n;
+  const uint32_t wave = uni(threadIdx.x >> 6), lane = lane_id();
+  const uint32_t row_first = blockIdx.x * (kScanWaves * 8);
+  const uint32_t a_first = row_first + wave * 8;
+  const uint32_t j0 = row_first + 1 + blockIdx.y * 64;
+  if (row_first + 1 >= n || j0 >= n) return;
+  if (a_first > n - 2 || a_first + 1 >= j0 + 64) return;
+  const uint32_t j = j0 + lane;
+  const FI_GLOBAL Ulong2 *col = as_global(reinterpret_cast<const Ulong2 *>(v.Bv)) + j;
+  uint32_t acc[8][2][2][2];
+#pragma unroll
+  for (int p = 0; p < 8; ++p)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int x = 0; x < 2; ++x) acc[p][c][x][0] = acc[p][c][x][1] = 0;
+  cu64p Bvc = as_const(v.Bv);
+  count_order2<8, 0>(Bvc, col, v.n_pad, a_first, 0, v.W0, acc);
+  count_order2<8, 1>(Bvc, col, v.n_pad, a_first, v.W0, v.W0 + v.W1, acc);
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const uint32_t ap = a_first + p;
+    if (ap <= n - 2 && j < n && j > ap) {
+      uint4 *dst = reinterpret_cast<uint4 *>(PT + ((size_t)ap * v.n_pad + j) * 8);
+      dst[0] = make_uint4(acc[p][0][0][0], acc[p][1][0][0], acc[p][0][0][1], acc[p][1][0][1]);
+      dst[1] = make_uint4(acc[p][0][1][0], acc[p][1][1][0], acc[p][0][1][1], acc[p][1][1][1]);
+    }
+  }
+}
+
+template <int P, int CLS>
+__device__ __forceinline__ void count3p_word(cu64p rb, const cu64p (&ra)[P], uint32_t w,
+                                             const FI_GLOBAL Ulong2 *col, uint32_t n_pad,
+                                             uint32_t (&acc)[P][2][2][2][2]) {
+  const u64 B0 = rb[(size_t)w * 4 + 0], B1 = rb[(size_t)w * 4 + 1];
+  Ulong2 L;
+  L.x = col[(size_t)w * n_pad].x;
+  L.y = col[(size_t)w * n_pad].y;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const u64 A0 = ra[p][(size_t)w * 4 + 0], A1 = ra[p][(size_t)w * 4 + 1];
+    const u64 R[2][2] = {{A0 & B0, A0 & B1}, {A1 & B0, A1 & B1}};
+#pragma unroll
+    for (int ga = 0; ga < 2; ++ga)
+#pragma unroll
+      for (int gb = 0; gb < 2; ++gb) {
+        acc[p][CLS][ga][gb][0] = add_popc64(acc[p][CLS][ga][gb][0], R[ga][gb] & L.x);
+        acc[p][CLS][ga][gb][1] = add_popc64(acc[p][CLS][ga][gb][1], R[ga][gb] & L.y);
+      }
+  }
+}
+
+template <int P, int CLS>
+__device__ __forceinline__ void count3p(cu64p rb, const cu64p (&ra)[P], uint32_t wbeg,
+                                        uint32_t wend, const FI_GLOBAL Ulong2 *col,
+                                        uint32_t n_pad, uint32_t (&acc)[P][2][2][2][2]) {
+  uint32_t w = wbeg;
+  for (; w + 1 < wend; w += 2) {
+    count3p_word<P, CLS>(rb, ra, w, col, n_pad, acc);
+    count3p_word<P, CLS>(rb, ra, w + 1, col, n_pad, acc);
+  }
+  if (w < wend) count3p_word<P, CLS>(rb, ra, w, col, n_pad, acc);
+}
+
+// 8 u32 of a pair table entry: [ga][gj][c]
+__device__ __forceinline__ void load_pair(const FI_GLOBAL uint32_t *p, uint32_t (&q)[8]) {
+  const FI_GLOBAL u64 *p64 = reinterpret_cast<const FI_GLOBAL u64 *>(p);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const u64 x = p64[i];
+    q[2 * i] = (uint32_t)x;
+    q[2 * i + 1] = (uint32_t)(x >> 32);
+  }
+}
+
+// A wave holds P prefixes (a_first + p, b) with a common last prefix variant
+// b; lanes own the last variants j.
+template <int P>
+__device__ __forceinline__ void tile_order3p(const Globals &g, const JV &v, uint32_t b,
+                                             uint32_t a_first, uint32_t j0, uint32_t lane) {
+  const uint32_t n = v.n;
+  if (a_first >= b) return;
+  const uint32_t j = j0 + lane;
+  const bool jvalid = j < n;
+  const FI_GLOBAL Ulong2 *col = as_global(reinterpret_cast<const Ulong2 *>(v.Bv)) + j;
+  cu64p Bsc = as_const(v.Bs);
+  cu64p rb = Bsc + (size_t)b * 4 * v.wcap;
+  cu64p ra[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) ra[p] = Bsc + (size_t)min(a_first + p, b - 1) * 4 * v.wcap;
+  uint32_t acc[P][2][2][2][2];
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[p][c][x][y][0] = acc[p][c][x][y][1] = 0;
+  count3p<P, 0>(rb, ra, 0, v.W0, col, v.n_pad, acc);
+  count3p<P, 1>(rb, ra, v.W0, v.W0 + v.W1, col, v.n_pad, acc);
+
+  const float thr = current_threshold(v.st);
+  const MiConst mc = mi_const(v);
+  const FI_GLOBAL u64 *F = as_global(reinterpret_cast<const u64 *>(v.F32));
+  cu32p marg = as_const(v.marg);
+  const uint32_t jj = jvalid ? j : n - 1;
+  const FI_GLOBAL uint32_t *PTg = as_global(v.pairs);
+  const FI_CONST uint32_t *PTc = as_const(v.pairs);
+  uint32_t bj[8];  // (b, j): [gb][gj][c]
+  load_pair(PTg + ((size_t)b * v.n_pad + jj) * 8, bj);
+  const FI_GLOBAL uint32_t *mj = as_global(v.marg) + (size_t)jj * 6;
+  uint32_t Mj[2][2], Mb[2][2];
+#pragma unroll
+  for (int gg = 0; gg < 2; ++gg)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      Mj[gg][c] = mj[2 * gg + c];
+      Mb[gg][c] = marg[(size_t)b * 6 + 2 * gg + c];
+    }
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const uint32_t a = min(a_first + p, b - 1);
+    const bool active = jvalid && a_first + p < b;
+    uint32_t aj[8], ab[8];
+    load_pair(PTg + ((size_t)a * v.n_pad + jj) * 8, aj);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ab[q] = PTc[((size_t)a * v.n_pad + b) * 8 + q];
+    uint32_t t[27][2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const uint32_t mc_ = c ? v.m1 : v.m0;
+      // N[x][y][z] over {0, 1, any}; index 2 = "any" before the conversion
+      uint32_t N[3][3][3];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+#pragma unroll
+          for (int z = 0; z < 2; ++z) N[x][y][z] = acc[p][c][x][y][z];
+          N[x][y][2] = ab[x * 4 + y * 2 + c];
+          N[x][2][y] = aj[x * 4 + y * 2 + c];
+          N[2][x][y] = bj[x * 4 + y * 2 + c];
+        }
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        N[x][2][2] = marg[(size_t)a * 6 + 2 * x + c];
+        N[2][x][2] = Mb[x][c];
+        N[2][2][x] = Mj[x][c];
+      }
+      N[2][2][2] = mc_;
+      // "any" -> genotype 2, one axis at a time
+#pragma unroll
+      for (int y = 0; y < 3; ++y)
+#pragma unroll
+        for (int z = 0; z < 3; ++z) N[2][y][z] -= N[0][y][z] + N[1][y][z];
+#pragma unroll
+      for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int z = 0; z < 3; ++z) N[x][2][z] -= N[x][0][z] + N[x][1][z];
+#pragma unroll
+      for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) N[x][y][2] -= N[x][y][0] + N[x][y][1];
+#pragma unroll
+      for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y)
+#pragma unroll
+          for (int z = 0; z < 3; ++z) t[(x * 3 + y) * 3 + z][c] = N[x][y][z];
+    }
+    const uint32_t pre[2] = {a, b};
+    const u64 rank = lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1);
+    score_table<27>(v, F, t, active, thr, mc, rank, lane);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // persistent driver
 // ---------------------------------------------------------------------------
 template <int K>
@@ -418,8 +666,11 @@ __device__ __forceinline__ void run_orderk(const Globals &g, const JV &v, uint32
   tile_orderk<K>(g, v, pre, b + 1 + jb * 64, lane);
 }
 
+// waves per SIMD each variant is compiled for (register budget 512 / waves)
+constexpr int scan_min_waves(int ksel) { return (ksel >= 3 && ksel <= 5) || ksel == 1 ? 4 : 2; }
+
 template <int KSEL>
-__global__ __launch_bounds__(kScanWaves * 64) void scan_kernel(Globals g) {
+__global__ __launch_bounds__(kScanWaves * 64, scan_min_waves(KSEL)) void scan_kernel(Globals g) {
   __shared__ u64 s_tile;
   const uint32_t lane = lane_id();
   const uint32_t wave = uni(threadIdx.x >> 6);
@@ -449,7 +700,7 @@ __global__ __launch_bounds__(kScanWaves * 64) void scan_kernel(Globals g) {
     }
     const FI_CONST JobDesc *jd = as_const(g.jobs) + lo;
     const u64 lt = t - uni64(jd->tile_begin);
-    const int k = KSEL ? KSEL : (int)v.k;
+    const int k = KSEL == kSelPairs ? 3 : KSEL ? KSEL : (int)v.k;
     if (k == 1) {
       if (KSEL == 0 || KSEL == 1) tile_order1(v, lt, wave, lane);
       continue;
@@ -468,6 +719,17 @@ __global__ __launch_bounds__(kScanWaves * 64) void scan_kernel(Globals g) {
         const uint32_t a_first = rl * (kScanWaves * kOrder2Prefixes);
         const uint32_t j0 = a_first + 1 + (uint32_t)local * 64;
         tile_order2<kOrder2Prefixes>(g, v, a_first + wave * kOrder2Prefixes, j0, lane);
+      }
+      continue;
+    }
+    if (k == 3 && (KSEL == kSelPairs || (KSEL == 0 && v.path == kPathPairs))) {
+      if (KSEL == 0 || KSEL == kSelPairs) {
+        const uint32_t b = rl + 1;
+        const uint32_t nj = (v.n - 1 - b + 63) / 64;
+        const u64 grp = local / nj;
+        const uint32_t jb = (uint32_t)(local - grp * nj);
+        const uint32_t a_first = (uint32_t)grp * (kScanWaves * kOrder3Prefixes) + wave * kOrder3Prefixes;
+        tile_order3p<kOrder3Prefixes>(g, v, b, a_first, b + 1 + jb * 64, lane);
       }
       continue;
     }
@@ -502,8 +764,16 @@ int scan_grid_size(int ksel) {
     case 3: return occupancy_grid<3>();
     case 4: return occupancy_grid<4>();
     case 5: return occupancy_grid<5>();
+    case kSelPairs: return occupancy_grid<kSelPairs>();
     default: return occupancy_grid<0>();
   }
+}
+
+void launch_pairs(const Globals &g, uint32_t max_n, hipStream_t s) {
+  const uint32_t rows = (max_n + kScanWaves * 8 - 2) / (kScanWaves * 8);
+  const uint32_t jbs = (max_n + 62) / 64;
+  hipLaunchKernelGGL(pairs_kernel, dim3(rows ? rows : 1, jbs ? jbs : 1, g.n_jobs),
+                     dim3(kScanWaves * 64), 0, s, g);
 }
 
 void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s) {
@@ -514,6 +784,7 @@ void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s) {
     case 3: hipLaunchKernelGGL(scan_kernel<3>, gd, bd, 0, s, g); break;
     case 4: hipLaunchKernelGGL(scan_kernel<4>, gd, bd, 0, s, g); break;
     case 5: hipLaunchKernelGGL(scan_kernel<5>, gd, bd, 0, s, g); break;
+    case kSelPairs: hipLaunchKernelGGL(scan_kernel<kSelPairs>, gd, bd, 0, s, g); break;
     default: hipLaunchKernelGGL(scan_kernel<0>, gd, bd, 0, s, g); break;
   }
 }

@@ -231,16 +231,22 @@ class DeviceBatch:
         _check(lib().fiuncho_scan_batch(self.jobs, len(self.shapes), DEVICE_PTRS, self.ws_ptr,
                                         self.ws_bytes, s.cuda_stream))
 
-    def capture(self):
+    def capture(self, profile: bool = False):
         """Capture one ``run`` into a HIP graph (torch.cuda.CUDAGraph).  The
         first eager ``run`` uploads the plan; the captured call then queues
-        kernels only (no allocation, no memset, no host synchronisation)."""
+        kernels only (no allocation, no memset, no host synchronisation).
+        With ``profile`` the phase events are captured too, so that
+        ``get_profile`` after replays reports the last replay."""
         torch = self.torch
         self.run()
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
+        if profile:
+            set_profiling(True)
         with torch.cuda.graph(self.graph):
             self.run(torch.cuda.current_stream())
+        if profile:
+            set_profiling(False)
         torch.cuda.synchronize()
         return self.graph
 

@@ -263,3 +263,15 @@ def test_batch_graph_replay():
         # unrelated eager work between replays
         x = torch.randn(1 << 20, device="cuda")
         (x * 2).sum().item()
+
+
+@pytest.mark.parametrize("pairs", ["0", "1"])
+def test_order3_both_paths(pairs, monkeypatch):
+    """Order 3 through the generic kernel (FIUNCHO_ORDER3_PAIRS=0) and through
+    the inclusion-exclusion kernel with pair tables (default)."""
+    monkeypatch.setenv("FIUNCHO_ORDER3_PAIRS", pairs)
+    for seed, n, m, frac in ((40, 67, 321, 0.45), (41, 130, 128, 0.5), (42, 9, 700, 0.2)):
+        say(f"case: order3 pairs={pairs} seed={seed} n={n} m={m}")
+        G, y = random_dataset(seed, n, m, frac, 1, 2)
+        hits = fiuncho.scan(G, y, 3, 37)
+        check_hits_against_oracle(G, y, 3, 37, hits)
