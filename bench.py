@@ -49,15 +49,19 @@ def workloads():
 
 
 def word_ops_per_combination(k: int, m0: int, m1: int) -> int:
-    """64-bit AND+popcount operations the counting kernel must execute per
-    combination: 4 per word at order 2 (rows g=0,1 of both variants), 2*3^(k-1)
-    per word at order >= 3 (rows g=0,1 of the last variant against every row of
-    the prefix), over ceil(m0/64) + ceil(m1/64) words."""
+    """64-bit AND+popcount operations the counting kernel executes per
+    combination, over W = ceil(m0/64) + ceil(m1/64) words: 4 per word at
+    order 2 and 8 at order 3 (only the {0,1}^k cells are counted, the others
+    follow from lower-order tables); 2*3^(k-1) at order >= 4 (rows g=0,1 of
+    the last variant against every row of the prefix).  The order-3 figure is
+    2*3^(k-1) = 18 when FIUNCHO_ORDER3_PAIRS=0 selects the generic kernel."""
     W = (m0 + 63) // 64 + (m1 + 63) // 64
     if k == 1:
         return 0
     if k == 2:
         return 4 * W
+    if k == 3 and os.environ.get("FIUNCHO_ORDER3_PAIRS", "1") != "0":
+        return 8 * W
     return 2 * 3 ** (k - 1) * W
 
 
@@ -115,7 +119,7 @@ def main():
     stream = torch.cuda.current_stream()
     graph = args.workload == "batch64"
     if graph:
-        batches[0].capture(profile=True)
+        batches[0].capture()
 
     def step():
         if graph:
@@ -136,8 +140,15 @@ def main():
     end.record(stream)
     torch.cuda.synchronize()
     fiuncho.set_profiling(False)
-    prof = fiuncho.get_profile()
     ms = start.elapsed_time(end) / args.steps
+    if graph:
+        # events recorded by graph replays cannot be timed: the phase times of
+        # a graph step come from one eager call right after the timed replays
+        fiuncho.set_profiling(True)
+        batches[0].run(stream)
+        torch.cuda.synchronize()
+        fiuncho.set_profiling(False)
+    prof = fiuncho.get_profile()
 
     # results of the last step: status and the top hit
     res = [r for b in batches for r in b.results()]

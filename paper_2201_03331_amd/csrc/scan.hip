@@ -208,6 +208,8 @@ __device__ __forceinline__ void score_table(const JV &v, const FI_GLOBAL u64 *F,
     float fs = mc.c_hi;
 #pragma unroll
     for (int x = 0; x < NC; ++x) {
+      // at most 9 cells of table loads in flight (bounds register use)
+      if (x % 9 == 0 && x) __builtin_amdgcn_sched_barrier(0);
       const float a = __uint_as_float((uint32_t)F[t[x][0]]);
       const float b = __uint_as_float((uint32_t)F[t[x][1]]);
       const float c = __uint_as_float((uint32_t)F[t[x][0] + t[x][1]]);
@@ -219,7 +221,10 @@ __device__ __forceinline__ void score_table(const JV &v, const FI_GLOBAL u64 *F,
   if (maybe) {
     float s = mc.s0, e = mc.e0;
 #pragma unroll
-    for (int x = 0; x < NC; ++x) mi_cell(F, t[x][0], t[x][1], s, e);
+    for (int x = 0; x < NC; ++x) {
+      if (x % 9 == 0 && x) __builtin_amdgcn_sched_barrier(0);
+      mi_cell(F, t[x][0], t[x][1], s, e);
+    }
     mi32 = (s + e) * mc.inv_m;
   }
   emit(v, maybe, mi32, rank, thr, lane);
@@ -532,6 +537,125 @@ __device__ __forceinline__ void load_pair(const FI_GLOBAL uint32_t *p, uint32_t 
   }
 }
 
+// The 27 cells of an order-3 table from its {0,1}^3 counts D, the {0,1}^2
+// counts of its three pairs, the {0,1} counts of its variants and the class
+// sizes.  With "any" marginalising a position, T[x][y][2] = N[x][y][any] -
+// T[x][y][0] - T[x][y][1] and likewise along the other positions; the cells
+// are produced in an order where each needs only cells already produced.
+struct Order3Parts {
+  const uint32_t (&D)[2][2][2][2];   // [c][ga][gb][gj]
+  const uint32_t (&ab)[8];           // (a, b): [ga][gb][c]
+  const uint32_t (&aj)[8];           // (a, j): [ga][gj][c]
+  const uint32_t (&bj)[8];           // (b, j): [gb][gj][c]
+  const uint32_t (&Ma)[2][2];        // [g][c]
+  const uint32_t (&Mb)[2][2];
+  const uint32_t (&Mj)[2][2];
+  const uint32_t (&m)[2];            // class sizes
+};
+
+template <typename Visit>
+__device__ __forceinline__ void walk_order3(const Order3Parts &q, Visit &&visit) {
+  uint32_t sum[2] = {0, 0};
+  uint32_t x2z[2][2][2], t2yz[2][2][2];  // [c][x or y][z]
+  auto cell = [&](uint32_t n0, uint32_t n1) {
+    sum[0] += n0;
+    sum[1] += n1;
+    visit(n0, n1);
+  };
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int z = 0; z < 2; ++z) cell(q.D[0][x][y][z], q.D[1][x][y][z]);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      uint32_t t[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) t[c] = q.ab[x * 4 + y * 2 + c] - q.D[c][x][y][0] - q.D[c][x][y][1];
+      cell(t[0], t[1]);  // (x, y, 2)
+    }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        x2z[c][x][z] = q.aj[x * 4 + z * 2 + c] - q.D[c][x][0][z] - q.D[c][x][1][z];
+      cell(x2z[0][x][z], x2z[1][x][z]);  // (x, 2, z)
+    }
+#pragma unroll
+  for (int y = 0; y < 2; ++y)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        t2yz[c][y][z] = q.bj[y * 4 + z * 2 + c] - q.D[c][0][y][z] - q.D[c][1][y][z];
+      cell(t2yz[0][y][z], t2yz[1][y][z]);  // (2, y, z)
+    }
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+    uint32_t t[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      t[c] = q.Ma[x][c] - q.ab[x * 4 + c] - q.ab[x * 4 + 2 + c] - x2z[c][x][0] - x2z[c][x][1];
+    cell(t[0], t[1]);  // (x, 2, 2)
+  }
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    uint32_t t[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      t[c] = q.Mb[y][c] - q.ab[y * 2 + c] - q.ab[4 + y * 2 + c] - t2yz[c][y][0] - t2yz[c][y][1];
+    cell(t[0], t[1]);  // (2, y, 2)
+  }
+#pragma unroll
+  for (int z = 0; z < 2; ++z) {
+    uint32_t t[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      t[c] = q.Mj[z][c] - q.aj[z * 2 + c] - q.aj[4 + z * 2 + c] - t2yz[c][0][z] - t2yz[c][1][z];
+    cell(t[0], t[1]);  // (2, 2, z)
+  }
+  visit(q.m[0] - sum[0], q.m[1] - sum[1]);  // (2, 2, 2)
+}
+
+// score_table for tables produced cell by cell by walk_order3
+template <int NC>
+__device__ __forceinline__ void score_streamed(const JV &v, const FI_GLOBAL u64 *F,
+                                               const Order3Parts &q, bool active, float thr,
+                                               const MiConst &mc, u64 rank, uint32_t lane) {
+  const float fmm = __uint_as_float((uint32_t)as_const(reinterpret_cast<const u64 *>(v.F32))[v.m]);
+  const float bound = 4.76837158203125e-07f * (float)(NC + 1) * (fmm + (float)v.m) * mc.inv_m;
+  bool maybe = false;
+  if (active) {
+    float fs = mc.c_hi;
+    int ci = 0;
+    walk_order3(q, [&](uint32_t n0, uint32_t n1) {
+      // at most 9 cells of table loads in flight (bounds register use)
+      if (++ci % 9 == 0) __builtin_amdgcn_sched_barrier(0);
+      const float fa = __uint_as_float((uint32_t)F[n0]);
+      const float fb = __uint_as_float((uint32_t)F[n1]);
+      const float fc = __uint_as_float((uint32_t)F[n0 + n1]);
+      fs += (fa + fb) - fc;
+    });
+    maybe = fs * mc.inv_m + bound >= thr;
+  }
+  float mi32 = 0.f;
+  if (maybe) {
+    float s = mc.s0, e = mc.e0;
+    int ci = 0;
+    walk_order3(q, [&](uint32_t n0, uint32_t n1) {
+      if (++ci % 9 == 0) __builtin_amdgcn_sched_barrier(0);
+      mi_cell(F, n0, n1, s, e);
+    });
+    mi32 = (s + e) * mc.inv_m;
+  }
+  emit(v, maybe, mi32, rank, thr, lane);
+}
+
 // A wave holds P prefixes (a_first + p, b) with a common last prefix variant
 // b; lanes own the last variants j.
 template <int P>
@@ -579,58 +703,23 @@ __device__ __forceinline__ void tile_order3p(const Globals &g, const JV &v, uint
     }
 #pragma unroll
   for (int p = 0; p < P; ++p) {
+    // one prefix's table and score at a time (bounds register use)
+    __builtin_amdgcn_sched_barrier(0);
     const uint32_t a = min(a_first + p, b - 1);
     const bool active = jvalid && a_first + p < b;
-    uint32_t aj[8], ab[8];
+    uint32_t aj[8], ab[8], Ma[2][2];
     load_pair(PTg + ((size_t)a * v.n_pad + jj) * 8, aj);
 #pragma unroll
     for (int q = 0; q < 8; ++q) ab[q] = PTc[((size_t)a * v.n_pad + b) * 8 + q];
-    uint32_t t[27][2];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const uint32_t mc_ = c ? v.m1 : v.m0;
-      // N[x][y][z] over {0, 1, any}; index 2 = "any" before the conversion
-      uint32_t N[3][3][3];
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-#pragma unroll
-          for (int z = 0; z < 2; ++z) N[x][y][z] = acc[p][c][x][y][z];
-          N[x][y][2] = ab[x * 4 + y * 2 + c];
-          N[x][2][y] = aj[x * 4 + y * 2 + c];
-          N[2][x][y] = bj[x * 4 + y * 2 + c];
-        }
-#pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        N[x][2][2] = marg[(size_t)a * 6 + 2 * x + c];
-        N[2][x][2] = Mb[x][c];
-        N[2][2][x] = Mj[x][c];
-      }
-      N[2][2][2] = mc_;
-      // "any" -> genotype 2, one axis at a time
-#pragma unroll
-      for (int y = 0; y < 3; ++y)
-#pragma unroll
-        for (int z = 0; z < 3; ++z) N[2][y][z] -= N[0][y][z] + N[1][y][z];
-#pragma unroll
-      for (int x = 0; x < 3; ++x)
-#pragma unroll
-        for (int z = 0; z < 3; ++z) N[x][2][z] -= N[x][0][z] + N[x][1][z];
-#pragma unroll
-      for (int x = 0; x < 3; ++x)
-#pragma unroll
-        for (int y = 0; y < 3; ++y) N[x][y][2] -= N[x][y][0] + N[x][y][1];
-#pragma unroll
-      for (int x = 0; x < 3; ++x)
-#pragma unroll
-        for (int y = 0; y < 3; ++y)
-#pragma unroll
-          for (int z = 0; z < 3; ++z) t[(x * 3 + y) * 3 + z][c] = N[x][y][z];
-    }
+      for (int c = 0; c < 2; ++c) Ma[x][c] = marg[(size_t)a * 6 + 2 * x + c];
     const uint32_t pre[2] = {a, b};
     const u64 rank = lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1);
-    score_table<27>(v, F, t, active, thr, mc, rank, lane);
+    const uint32_t mcls[2] = {v.m0, v.m1};
+    const Order3Parts parts = {acc[p], ab, aj, bj, Ma, Mb, Mj, mcls};
+    score_streamed<27>(v, F, parts, active, thr, mc, rank, lane);
   }
 }
 
