@@ -129,7 +129,7 @@ struct JobLayout {
   size_t off_G, off_y, off_idx, off_Bv, off_Bs, off_marg, off_hist, off_cand, off_l1, off_l2,
       off_state, off_out, off_nout, off_status, off_pairs;
   // plan (uploaded)
-  size_t off_rows, off_F32, off_P64;
+  size_t off_rows, off_F32, off_Fh, off_P64;
   std::vector<u64> row_start;
   u64 tiles;
   double cost;  // per-tile cost estimate, for ordering
@@ -227,6 +227,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     JobLayout &J = L.jobs[i];
     J.off_rows = take(sizeof(u64) * J.row_start.size());
     J.off_F32 = take(sizeof(float2) * ((size_t)J.m + 1));
+    J.off_Fh = take(sizeof(float) * ((size_t)J.m + 1));
     J.off_P64 = take(sizeof(double) * ((size_t)J.m + 1));
   }
   L.plan_end = off;
@@ -244,6 +245,21 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
   for (auto &J : L.jobs)
     if (sel(J) != L.ksel) L.ksel = 0;
   return FIUNCHO_OK;
+}
+
+// Bound of |plain single-precision MI - MI| for tables of 3^k cells and m
+// samples.  With u = 2^-24 and f(t) = t ln t: each table value is within
+// u f(m) of f; a cell adds (f(n0) + f(n1)) - f(n0 + n1), whose first sum is at
+// most f(m) and whose result, like every partial sum of m * MI, is at most m
+// in magnitude; so every cell, and the start f(m) - f(m0) - f(m1), costs at
+// most u (4 f(m) + 2 m).  Over 3^k + 2 such terms and after division by m the
+// error is below 4u (3^k + 2)(ln m + 1/2); twice that is used.
+float fbound(uint32_t k, uint32_t m) {
+  double cells = 1;
+  for (uint32_t i = 0; i < k; ++i) cells *= 3;
+  const double u = std::ldexp(1.0, -24);
+  const double b = 8.0 * u * (cells + 2.0) * (std::log((double)m) + 1.0);
+  return (float)(b * 1.0001);
 }
 
 // ---------------------------------------------------------------------------
@@ -300,6 +316,8 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
     d.Bs = reinterpret_cast<u64 *>(ws + J.off_Bs);
     d.marg = reinterpret_cast<uint32_t *>(ws + J.off_marg);
     d.F32 = reinterpret_cast<const float2 *>(ws + J.off_F32);
+    d.Fh = reinterpret_cast<const float *>(ws + J.off_Fh);
+    d.fbound = fbound(J.k, J.m);
     d.P64 = reinterpret_cast<const double *>(ws + J.off_P64);
     d.row_start = reinterpret_cast<const u64 *>(ws + J.off_rows);
     d.hist = reinterpret_cast<uint32_t *>(ws + J.off_hist);
@@ -320,14 +338,17 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
     std::memcpy(at(J.off_rows), J.row_start.data(), sizeof(u64) * J.row_start.size());
     // f(t) = t ln t as a float pair, and (t/m) ln(t/m) in double
     float2 *F = reinterpret_cast<float2 *>(at(J.off_F32));
+    float *Fh = reinterpret_cast<float *>(at(J.off_Fh));
     double *P = reinterpret_cast<double *>(at(J.off_P64));
     F[0] = make_float2(0.f, 0.f);
+    Fh[0] = 0.f;
     P[0] = 0.0;
     for (uint32_t t = 1; t <= J.m; ++t) {
       const double f = (double)t * std::log((double)t);
       const float hi = (float)f;
       const float lo = (float)(f - (double)hi);
       F[t] = make_float2(hi, lo);
+      Fh[t] = hi;
       const double p = (double)t / (double)J.m;
       P[t] = p * std::log(p);
     }

@@ -18,7 +18,7 @@ constexpr int kHistShift = 20;                // survivor histogram bin = key >>
 constexpr int kHistBins = 1 << (31 - kHistShift);
 constexpr uint32_t kSortMax = 4096;           // candidates ordered in one LDS sort
 constexpr int kScanWaves = 4;                 // waves per workgroup in the scan
-constexpr int kOrder2Prefixes = 8;            // first variants per wave at order 2
+constexpr int kOrder2Prefixes = 4;            // first variants per wave at order 2
 constexpr int kOrder3Prefixes = 2;            // prefixes per wave, order-3 pair path
 
 // scan paths of a job
@@ -47,15 +47,15 @@ constexpr uint32_t kFlagBound = 4u;           // |mi32 - mi| exceeded the stated
 
 struct Cand {                 // one appended candidate
   unsigned long long rank;
-  uint32_t key;               // float bits of max(mi32, 0)
-  float mi32;
+  uint32_t key;               // float bits of max(est, 0)
+  float est;                  // plain single-precision MI (within fbound of MI)
 };
 
-struct Rescored {             // candidate after FP64 rescoring
+struct Rescored {             // candidate after rescoring
   unsigned long long rank;
-  double mi;
-  float mi32;
-  float rel_err;
+  double mi;                  // IEEE double, Eq. 1-3 term by term
+  float mi32;                 // compensated single precision
+  float est;                  // the scan's plain single-precision estimate
   uint32_t snp[kMaxOrder];
 };
 
@@ -78,6 +78,8 @@ struct JobDesc {
   unsigned long long *Bs;     // [n][wcap][4] planes g=0,1,2 and a zero word
   uint32_t *marg;             // [n][3][2] per-variant class marginals
   const float2 *F32;          // (hi, lo) of t ln t for t in [0, m]
+  const float *Fh;            // t ln t rounded to float, t in [0, m]
+  float fbound;               // bound of |plain single-precision MI - MI|
   const double *P64;          // (t/m) ln(t/m) for t in [0, m]
   const unsigned long long *row_start;  // [nrows + 1] tile offsets
   uint32_t *hist;             // [kHistBins]

@@ -1,8 +1,9 @@
 // scan.hip -- the exhaustive search: for every k-combination, its contingency
 // table (section 3.2) by AND + population count of genotype-table rows
-// (section 3.1), its mutual information (section 3.3, Eq. 1-3) in compensated
-// single precision, and a filter that keeps every combination that can still
-// be among the best top_n (Algorithm 1's sorted list).
+// (section 3.1), its mutual information (section 3.3, Eq. 1-3) in plain single
+// precision with a bound of its rounding error, and a filter that keeps every
+// combination that can still be among the best top_n (Algorithm 1's sorted
+// list).
 //
 // Work decomposition (section 4.1 reuses the genotype table of a (k-1)-prefix
 // for every last variant j after it; here a wave does exactly that):
@@ -34,12 +35,13 @@ struct JV {
   const u64 *Bv;
   const u64 *Bs;
   const uint32_t *marg;
-  const float2 *F32;
   uint32_t *hist;
   Cand *cand;
   JobState *st;
   const uint32_t *pairs;
   uint32_t path;
+  const float *Fh;
+  float fbound;
 };
 
 template <typename T>
@@ -61,46 +63,23 @@ __device__ __forceinline__ JV load_view(const JobDesc *jd) {
   v.Bv = uni_ptr(J->Bv);
   v.Bs = uni_ptr(J->Bs);
   v.marg = uni_ptr(J->marg);
-  v.F32 = uni_ptr(J->F32);
   v.hist = uni_ptr(J->hist);
   v.cand = uni_ptr(J->cand);
   v.st = uni_ptr(J->state);
   v.pairs = uni_ptr(J->pairs);
   v.path = uni(J->path);
+  v.Fh = uni_ptr(J->Fh);
+  v.fbound = __uint_as_float(uni(__float_as_uint(J->fbound)));
   return v;
 }
 
 // m * MI = [f(m) - f(m0) - f(m1)] + sum_x [f(n_x0) + f(n_x1) - f(n_x0 + n_x1)]
 // with f(t) = t ln t: Eq. 1-3 with plug-in probabilities, multiplied out.
-// F holds f(t) as an unevaluated sum hi + lo of two floats.
-// one table entry: (hi, lo) floats packed in 8 bytes
-__device__ __forceinline__ void f_entry(const FI_GLOBAL u64 *F, uint32_t t, float &hi, float &lo) {
-  const u64 x = F[t];
-  hi = __uint_as_float((uint32_t)x);
-  lo = __uint_as_float((uint32_t)(x >> 32));
-}
-
-__device__ __forceinline__ void mi_cell(const FI_GLOBAL u64 *F, uint32_t n0, uint32_t n1,
-                                        float &s, float &e) {
-  float ah, al, bh, bl, ch, cl;
-  f_entry(F, n0, ah, al);
-  f_entry(F, n1, bh, bl);
-  f_entry(F, n0 + n1, ch, cl);
-  two_sum_add(s, e, ah);
-  two_sum_add(s, e, bh);
-  two_sum_add(s, e, -ch);
-  e += (al + bl) - cl;
-}
-
-__device__ __forceinline__ void mi_start(const JV &v, float &s, float &e) {
-  const FI_CONST u64 *F = as_const(reinterpret_cast<const u64 *>(v.F32));
-  const u64 fm = F[v.m], f0 = F[v.m0], f1 = F[v.m1];
-  s = __uint_as_float((uint32_t)fm);
-  e = 0.f;
-  two_sum_add(s, e, -__uint_as_float((uint32_t)f0));
-  two_sum_add(s, e, -__uint_as_float((uint32_t)f1));
-  e += (__uint_as_float((uint32_t)(fm >> 32)) - __uint_as_float((uint32_t)(f0 >> 32))) -
-       __uint_as_float((uint32_t)(f1 >> 32));
+// The scan evaluates it in plain single precision from a float table of f;
+// the job's fbound bounds the rounding error of the resulting MI, and every
+// filter below widens its threshold by twice that bound.
+__device__ __forceinline__ float mi_term(const FI_GLOBAL float *F, uint32_t n0, uint32_t n1) {
+  return (F[n0] + F[n1]) - F[n0 + n1];
 }
 
 // Lower bound of the top_n-th best score from the survivor histogram: the bin
@@ -135,15 +114,18 @@ __device__ __noinline__ void refresh_tau(uint32_t *hist, JobState *st, uint32_t 
   }
 }
 
-__device__ __forceinline__ float current_threshold(const JobState *st) {
-  const float tau = __uint_as_float(uni(load_relaxed(&st->tau_key)));
-  return tau * (1.0f - 2e-5f) - 2e-10f;
+// A combination is kept iff its estimate is at least tau - 2 fbound: with
+// |estimate - MI| <= fbound everywhere, tau <= the top_n-th best estimate
+// <= the top_n-th best MI + fbound, so anything lower cannot be in the top_n.
+__device__ __forceinline__ float current_threshold(const JV &v) {
+  const float tau = __uint_as_float(uni(load_relaxed(&v.st->tau_key)));
+  return tau - 2.0f * v.fbound;
 }
 
 // Appends every active lane whose score clears the threshold.
-__device__ __forceinline__ void emit(const JV &v, bool active, float mi32, u64 rank, float thr,
+__device__ __forceinline__ void emit(const JV &v, bool active, float est, u64 rank, float thr,
                                      uint32_t lane) {
-  const bool keep = active && mi32 >= thr;
+  const bool keep = active && est >= thr;
   const u64 mask = ballot(keep);
   if (mask == 0) return;
   const uint32_t cnt = popc64(mask);
@@ -158,12 +140,12 @@ __device__ __forceinline__ void emit(const JV &v, bool active, float mi32, u64 r
   if (keep) {
     const u64 lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     const u64 idx = base + popc64(mask & lt);
-    const uint32_t key = mi32 > 0.f ? __float_as_uint(mi32) : 0u;
+    const uint32_t key = est > 0.f ? __float_as_uint(est) : 0u;
     if (idx < v.cand_cap) {
       Cand c;
       c.rank = rank;
       c.key = key;
-      c.mi32 = mi32;
+      c.est = est;
       v.cand[idx] = c;
     }
     atomicAdd(&v.hist[key >> kHistShift], 1u);
@@ -172,62 +154,75 @@ __device__ __forceinline__ void emit(const JV &v, bool active, float mi32, u64 r
   if ((old + cnt) / qs != old / qs) refresh_tau(v.hist, v.st, v.top_n, lane);
 }
 
-// Constants of the single-precision score of a job: m * MI starts at
-// f(m) - f(m0) - f(m1).
+// Constants of the score of a job: m * MI starts at f(m) - f(m0) - f(m1).
 struct MiConst {
-  float s0, e0;     // compensated start
-  float c_hi;       // plain start
+  float c;
   float inv_m;
 };
 
 __device__ __forceinline__ MiConst mi_const(const JV &v) {
+  const FI_CONST float *F = as_const(v.Fh);
   MiConst c;
-  mi_start(v, c.s0, c.e0);
-  const FI_CONST u64 *F = as_const(reinterpret_cast<const u64 *>(v.F32));
-  c.c_hi = (__uint_as_float((uint32_t)F[v.m]) - __uint_as_float((uint32_t)F[v.m0])) -
-           __uint_as_float((uint32_t)F[v.m1]);
+  c.c = (F[v.m] - F[v.m0]) - F[v.m1];
   c.inv_m = 1.0f / (float)v.m;
   return c;
 }
 
 // Scores a complete table of NC cells x 2 classes and appends it if it may be
-// among the best.  A plain single-precision estimate comes first: with
-// u = 2^-24, every table value is within u f(m) of f, every cell sum within
-// 2 u f(m), and every partial sum of m * MI stays below 2m, so its error is
-// below 3u (NC + 1)(f(m) + m); an estimate more than 8u (NC + 1)(f(m) + m) / m
-// below the threshold proves the compensated score is below it too.  Only
-// the remaining lanes evaluate the compensated sum.
+// among the best.
 template <int NC>
-__device__ __forceinline__ void score_table(const JV &v, const FI_GLOBAL u64 *F,
+__device__ __forceinline__ void score_table(const JV &v, const FI_GLOBAL float *F,
                                             const uint32_t (&t)[NC][2], bool active, float thr,
                                             const MiConst &mc, u64 rank, uint32_t lane) {
-  const float fmm = __uint_as_float((uint32_t)as_const(reinterpret_cast<const u64 *>(v.F32))[v.m]);
-  const float bound = 4.76837158203125e-07f * (float)(NC + 1) * (fmm + (float)v.m) * mc.inv_m;
-  bool maybe = false;
+  float fs = mc.c;
   if (active) {
-    float fs = mc.c_hi;
 #pragma unroll
-    for (int x = 0; x < NC; ++x) {
-      // at most 9 cells of table loads in flight (bounds register use)
-      if (x % 9 == 0 && x) __builtin_amdgcn_sched_barrier(0);
-      const float a = __uint_as_float((uint32_t)F[t[x][0]]);
-      const float b = __uint_as_float((uint32_t)F[t[x][1]]);
-      const float c = __uint_as_float((uint32_t)F[t[x][0] + t[x][1]]);
-      fs += (a + b) - c;
-    }
-    maybe = fs * mc.inv_m + bound >= thr;
+    for (int x = 0; x < NC; ++x) fs += mi_term(F, t[x][0], t[x][1]);
   }
-  float mi32 = 0.f;
-  if (maybe) {
-    float s = mc.s0, e = mc.e0;
+  emit(v, active, fs * mc.inv_m, rank, thr, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Software-pipelined word loop shared by the counting kernels.  The lane's
+// rows of the next kAhead words are in flight in a register ring; each step
+// forms the current word's prefix rows from scalar registers, issues the
+// scalar loads of the next word, then does the vector work, so both kinds of
+// load latency overlap with VALU work.  step(wn, L) must hold word w's scalar
+// operands on entry and leave word wn's loads issued.
+// ---------------------------------------------------------------------------
+constexpr int kAhead = 4;
+
+template <typename Step>
+__device__ __forceinline__ void word_pipeline(uint32_t wbeg, uint32_t wend,
+                                              const FI_GLOBAL Ulong2 *col, uint32_t n_pad,
+                                              Step &&step) {
+  if (wbeg >= wend) return;
+  const uint32_t wlast = wend - 1;
+  Ulong2 L[kAhead];
 #pragma unroll
-    for (int x = 0; x < NC; ++x) {
-      if (x % 9 == 0 && x) __builtin_amdgcn_sched_barrier(0);
-      mi_cell(F, t[x][0], t[x][1], s, e);
-    }
-    mi32 = (s + e) * mc.inv_m;
+  for (int u = 0; u < kAhead; ++u) {
+    const uint32_t wl = min(wbeg + u, wlast);
+    L[u].x = col[(size_t)wl * n_pad].x;
+    L[u].y = col[(size_t)wl * n_pad].y;
   }
-  emit(v, maybe, mi32, rank, thr, lane);
+  uint32_t w = wbeg;
+  // full groups: no branches inside, so loads stay in flight across words
+  for (; w + kAhead <= wend; w += kAhead) {
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) {
+      step(min(w + u + 1, wlast), L[u]);
+      // refill the ring slot after its last use, so that the load can target
+      // the same registers and stay in flight across the loop back-edge
+      const uint32_t wf = min(w + u + kAhead, wlast);
+      L[u].x = col[(size_t)wf * n_pad].x;
+      L[u].y = col[(size_t)wf * n_pad].y;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // the last (wend - w) < kAhead words are already in the ring
+#pragma unroll
+  for (int u = 0; u < kAhead - 1; ++u)
+    if (w + u < wend) step(min(w + u + 1, wlast), L[u]);
 }
 
 // ---------------------------------------------------------------------------
@@ -238,13 +233,14 @@ __device__ __forceinline__ void tile_order1(const JV &v, u64 lt, uint32_t wave, 
   const bool active = j < v.n;
   const uint32_t jj = active ? j : 0;
   const FI_GLOBAL uint32_t *mg = as_global(v.marg) + (size_t)jj * 6;
-  float s, e;
-  mi_start(v, s, e);
-  const FI_GLOBAL u64 *F = as_global(reinterpret_cast<const u64 *>(v.F32));
+  const MiConst mc = mi_const(v);
+  const FI_GLOBAL float *F = as_global(v.Fh);
+  float fs = mc.c;
+  if (active) {
 #pragma unroll
-  for (int gg = 0; gg < 3; ++gg) mi_cell(F, mg[2 * gg], mg[2 * gg + 1], s, e);
-  const float mi32 = (s + e) / (float)v.m;
-  emit(v, active, mi32, (u64)j, current_threshold(v.st), lane);
+    for (int gg = 0; gg < 3; ++gg) fs += mi_term(F, mg[2 * gg], mg[2 * gg + 1]);
+  }
+  emit(v, active, fs * mc.inv_m, (u64)j, current_threshold(v), lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -255,21 +251,34 @@ template <int P, int CLS>
 __device__ __forceinline__ void count_order2(cu64p Bv, const FI_GLOBAL Ulong2 *col,
                                              uint32_t n_pad, uint32_t a_first, uint32_t wbeg,
                                              uint32_t wend, uint32_t (&acc)[P][2][2][2]) {
-  for (uint32_t w = wbeg; w < wend; ++w) {
-    Ulong2 L;
-    L.x = col[(size_t)w * n_pad].x;
-    L.y = col[(size_t)w * n_pad].y;
-    // rows g = 0, 1 of the P consecutive first variants: 16 P contiguous bytes
+  if (wbeg >= wend) return;
+  // rows g = 0, 1 of the P consecutive first variants: 16 P contiguous bytes
+  u64 A[P][2];
+  auto load = [&](uint32_t w) {
     cu64p rows = Bv + ((size_t)w * n_pad + a_first) * 2;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      const u64 A0 = rows[2 * p], A1 = rows[2 * p + 1];
-      acc[p][CLS][0][0] = add_popc64(acc[p][CLS][0][0], A0 & L.x);
-      acc[p][CLS][0][1] = add_popc64(acc[p][CLS][0][1], A0 & L.y);
-      acc[p][CLS][1][0] = add_popc64(acc[p][CLS][1][0], A1 & L.x);
-      acc[p][CLS][1][1] = add_popc64(acc[p][CLS][1][1], A1 & L.y);
+      A[p][0] = rows[2 * p];
+      A[p][1] = rows[2 * p + 1];
     }
-  }
+  };
+  load(wbeg);
+  word_pipeline(wbeg, wend, col, n_pad, [&](uint32_t wn, const Ulong2 &L) {
+    u64 R[P][2];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      R[p][0] = A[p][0];
+      R[p][1] = A[p][1];
+    }
+    load(wn);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      acc[p][CLS][0][0] = add_popc64(acc[p][CLS][0][0], R[p][0] & L.x);
+      acc[p][CLS][0][1] = add_popc64(acc[p][CLS][0][1], R[p][0] & L.y);
+      acc[p][CLS][1][0] = add_popc64(acc[p][CLS][1][0], R[p][1] & L.x);
+      acc[p][CLS][1][1] = add_popc64(acc[p][CLS][1][1], R[p][1] & L.y);
+    }
+  });
 }
 
 template <int P>
@@ -291,7 +300,7 @@ __device__ __forceinline__ void tile_order2(const Globals &g, const JV &v, uint3
   count_order2<P, 0>(Bvc, col, v.n_pad, a_first, 0, v.W0, acc);
   count_order2<P, 1>(Bvc, col, v.n_pad, a_first, v.W0, v.W0 + v.W1, acc);
 
-  const float thr = current_threshold(v.st);
+  const float thr = current_threshold(v);
   const uint32_t jj = j < n ? j : n - 1;
   const FI_GLOBAL uint32_t *mj = as_global(v.marg) + (size_t)jj * 6;
   uint32_t Mj[2][2];
@@ -301,7 +310,7 @@ __device__ __forceinline__ void tile_order2(const Globals &g, const JV &v, uint3
     for (int c = 0; c < 2; ++c) Mj[gg][c] = mj[2 * gg + c];
   const MiConst mc = mi_const(v);
   const u64 cn2 = binom(g, n, 2);
-  const FI_GLOBAL u64 *F = as_global(reinterpret_cast<const u64 *>(v.F32));
+  const FI_GLOBAL float *F = as_global(v.Fh);
   cu32p marg = as_const(v.marg);
 #pragma unroll
   for (int p = 0; p < P; ++p) {
@@ -340,51 +349,46 @@ __device__ __forceinline__ void tile_order2(const Globals &g, const JV &v, uint3
 // Bs holds, per variant and word, the rows g = 0, 1, 2 and a zero pad word
 // (32 bytes), so one scalar load brings a variant's three rows of a word.
 template <int K, int CLS>
-__device__ __forceinline__ void count_word(cu64p ra, cu64p rb, const cu64p (&rl)[K - 2],
-                                           const uint32_t (&lg)[K - 2], uint32_t w,
-                                           const FI_GLOBAL Ulong2 *col, uint32_t n_pad,
-                                           uint32_t (&acc)[2][9][2], uint32_t (&pc)[2][9]) {
-  u64 lead = ~0ull;
-#pragma unroll
-  for (int i = 0; i < K - 3; ++i) lead &= rl[i][(size_t)w * 4 + lg[i]];
-  u64 A[3], B[3];
-#pragma unroll
-  for (int gg = 0; gg < 3; ++gg) {
-    A[gg] = lead & ra[(size_t)w * 4 + gg];
-    B[gg] = rb[(size_t)w * 4 + gg];
-  }
-  Ulong2 L;
-  L.x = col[(size_t)w * n_pad].x;
-  L.y = col[(size_t)w * n_pad].y;
-#pragma unroll
-  for (int ga = 0; ga < 3; ++ga)
-#pragma unroll
-    for (int gb = 0; gb < 3; ++gb) {
-      const u64 R = A[ga] & B[gb];
-      pc[CLS][ga * 3 + gb] += popc64(R);
-      acc[CLS][ga * 3 + gb][0] = add_popc64(acc[CLS][ga * 3 + gb][0], R & L.x);
-      acc[CLS][ga * 3 + gb][1] = add_popc64(acc[CLS][ga * 3 + gb][1], R & L.y);
-    }
-}
-
-template <int K, int CLS>
 __device__ __forceinline__ void count_orderk(cu64p Bs, const FI_GLOBAL Ulong2 *col,
                                              uint32_t n_pad, uint32_t wcap,
                                              const uint32_t (&pre)[K - 1],
                                              const uint32_t (&lg)[K - 2], uint32_t wbeg,
                                              uint32_t wend, uint32_t (&acc)[2][9][2],
                                              uint32_t (&pc)[2][9]) {
+  if (wbeg >= wend) return;
   cu64p ra = Bs + (size_t)pre[K - 3] * 4 * wcap;
   cu64p rb = Bs + (size_t)pre[K - 2] * 4 * wcap;
   cu64p rl[K - 2];
 #pragma unroll
   for (int i = 0; i < K - 2; ++i) rl[i] = Bs + (size_t)pre[i < K - 3 ? i : 0] * 4 * wcap;
-  uint32_t w = wbeg;
-  for (; w + 1 < wend; w += 2) {
-    count_word<K, CLS>(ra, rb, rl, lg, w, col, n_pad, acc, pc);
-    count_word<K, CLS>(ra, rb, rl, lg, w + 1, col, n_pad, acc, pc);
-  }
-  if (w < wend) count_word<K, CLS>(ra, rb, rl, lg, w, col, n_pad, acc, pc);
+  u64 lead[K - 2], A[3], B[3];
+  auto load = [&](uint32_t w) {
+#pragma unroll
+    for (int i = 0; i < K - 3; ++i) lead[i] = rl[i][(size_t)w * 4 + lg[i]];
+#pragma unroll
+    for (int gg = 0; gg < 3; ++gg) {
+      A[gg] = ra[(size_t)w * 4 + gg];
+      B[gg] = rb[(size_t)w * 4 + gg];
+    }
+  };
+  load(wbeg);
+  word_pipeline(wbeg, wend, col, n_pad, [&](uint32_t wn, const Ulong2 &L) {
+    u64 ld = ~0ull;
+#pragma unroll
+    for (int i = 0; i < K - 3; ++i) ld &= lead[i];
+    u64 R[9];
+#pragma unroll
+    for (int ga = 0; ga < 3; ++ga)
+#pragma unroll
+      for (int gb = 0; gb < 3; ++gb) R[ga * 3 + gb] = ld & A[ga] & B[gb];
+    load(wn);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      pc[CLS][r] += popc64(R[r]);
+      acc[CLS][r][0] = add_popc64(acc[CLS][r][0], R[r] & L.x);
+      acc[CLS][r][1] = add_popc64(acc[CLS][r][1], R[r] & L.y);
+    }
+  });
 }
 
 template <int K>
@@ -401,9 +405,9 @@ __device__ __forceinline__ void tile_orderk(const Globals &g, const JV &v,
   const bool active = j < n;
   const FI_GLOBAL Ulong2 *col = as_global(reinterpret_cast<const Ulong2 *>(v.Bv)) + j;
   cu64p Bsc = as_const(v.Bs);
-  const FI_GLOBAL u64 *F = as_global(reinterpret_cast<const u64 *>(v.F32));
-  float s, e;
-  mi_start(v, s, e);
+  const FI_GLOBAL float *F = as_global(v.Fh);
+  const MiConst mc = mi_const(v);
+  float fs = mc.c;
   for (int pass = 0; pass < npass; ++pass) {
     uint32_t lg[K - 2];
     {
@@ -427,15 +431,14 @@ __device__ __forceinline__ void tile_orderk(const Globals &g, const JV &v,
       for (int r = 0; r < 9; ++r) {
         const uint32_t a0 = acc[0][r][0], a1 = acc[0][r][1];
         const uint32_t c0 = acc[1][r][0], c1 = acc[1][r][1];
-        mi_cell(F, a0, c0, s, e);
-        mi_cell(F, a1, c1, s, e);
-        mi_cell(F, pc[0][r] - a0 - a1, pc[1][r] - c0 - c1, s, e);
+        fs += mi_term(F, a0, c0);
+        fs += mi_term(F, a1, c1);
+        fs += mi_term(F, pc[0][r] - a0 - a1, pc[1][r] - c0 - c1);
       }
     }
   }
-  const float mi32 = (s + e) / (float)v.m;
   const u64 rank = lex_rank_prefix(g, n, K, pre) + (u64)(j - b - 1);
-  emit(v, active, mi32, rank, current_threshold(v.st), lane);
+  emit(v, active, fs * mc.inv_m, rank, current_threshold(v), lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -493,37 +496,41 @@ __global__ __launch_bounds__(kScanWaves * 64) void pairs_kernel(Globals g) {
 }
 
 template <int P, int CLS>
-__device__ __forceinline__ void count3p_word(cu64p rb, const cu64p (&ra)[P], uint32_t w,
-                                             const FI_GLOBAL Ulong2 *col, uint32_t n_pad,
-                                             uint32_t (&acc)[P][2][2][2][2]) {
-  const u64 B0 = rb[(size_t)w * 4 + 0], B1 = rb[(size_t)w * 4 + 1];
-  Ulong2 L;
-  L.x = col[(size_t)w * n_pad].x;
-  L.y = col[(size_t)w * n_pad].y;
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    const u64 A0 = ra[p][(size_t)w * 4 + 0], A1 = ra[p][(size_t)w * 4 + 1];
-    const u64 R[2][2] = {{A0 & B0, A0 & B1}, {A1 & B0, A1 & B1}};
-#pragma unroll
-    for (int ga = 0; ga < 2; ++ga)
-#pragma unroll
-      for (int gb = 0; gb < 2; ++gb) {
-        acc[p][CLS][ga][gb][0] = add_popc64(acc[p][CLS][ga][gb][0], R[ga][gb] & L.x);
-        acc[p][CLS][ga][gb][1] = add_popc64(acc[p][CLS][ga][gb][1], R[ga][gb] & L.y);
-      }
-  }
-}
-
-template <int P, int CLS>
 __device__ __forceinline__ void count3p(cu64p rb, const cu64p (&ra)[P], uint32_t wbeg,
                                         uint32_t wend, const FI_GLOBAL Ulong2 *col,
                                         uint32_t n_pad, uint32_t (&acc)[P][2][2][2][2]) {
-  uint32_t w = wbeg;
-  for (; w + 1 < wend; w += 2) {
-    count3p_word<P, CLS>(rb, ra, w, col, n_pad, acc);
-    count3p_word<P, CLS>(rb, ra, w + 1, col, n_pad, acc);
-  }
-  if (w < wend) count3p_word<P, CLS>(rb, ra, w, col, n_pad, acc);
+  if (wbeg >= wend) return;
+  u64 B0, B1, A0[P], A1[P];
+  auto load = [&](uint32_t w) {
+    B0 = rb[(size_t)w * 4 + 0];
+    B1 = rb[(size_t)w * 4 + 1];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      A0[p] = ra[p][(size_t)w * 4 + 0];
+      A1[p] = ra[p][(size_t)w * 4 + 1];
+    }
+  };
+  load(wbeg);
+  word_pipeline(wbeg, wend, col, n_pad, [&](uint32_t wn, const Ulong2 &L) {
+    u64 R[P][2][2];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      R[p][0][0] = A0[p] & B0;
+      R[p][0][1] = A0[p] & B1;
+      R[p][1][0] = A1[p] & B0;
+      R[p][1][1] = A1[p] & B1;
+    }
+    load(wn);
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int ga = 0; ga < 2; ++ga)
+#pragma unroll
+        for (int gb = 0; gb < 2; ++gb) {
+          acc[p][CLS][ga][gb][0] = add_popc64(acc[p][CLS][ga][gb][0], R[p][ga][gb] & L.x);
+          acc[p][CLS][ga][gb][1] = add_popc64(acc[p][CLS][ga][gb][1], R[p][ga][gb] & L.y);
+        }
+  });
 }
 
 // 8 u32 of a pair table entry: [ga][gj][c]
@@ -623,37 +630,12 @@ __device__ __forceinline__ void walk_order3(const Order3Parts &q, Visit &&visit)
 }
 
 // score_table for tables produced cell by cell by walk_order3
-template <int NC>
-__device__ __forceinline__ void score_streamed(const JV &v, const FI_GLOBAL u64 *F,
+__device__ __forceinline__ void score_streamed(const JV &v, const FI_GLOBAL float *F,
                                                const Order3Parts &q, bool active, float thr,
                                                const MiConst &mc, u64 rank, uint32_t lane) {
-  const float fmm = __uint_as_float((uint32_t)as_const(reinterpret_cast<const u64 *>(v.F32))[v.m]);
-  const float bound = 4.76837158203125e-07f * (float)(NC + 1) * (fmm + (float)v.m) * mc.inv_m;
-  bool maybe = false;
-  if (active) {
-    float fs = mc.c_hi;
-    int ci = 0;
-    walk_order3(q, [&](uint32_t n0, uint32_t n1) {
-      // at most 9 cells of table loads in flight (bounds register use)
-      if (++ci % 9 == 0) __builtin_amdgcn_sched_barrier(0);
-      const float fa = __uint_as_float((uint32_t)F[n0]);
-      const float fb = __uint_as_float((uint32_t)F[n1]);
-      const float fc = __uint_as_float((uint32_t)F[n0 + n1]);
-      fs += (fa + fb) - fc;
-    });
-    maybe = fs * mc.inv_m + bound >= thr;
-  }
-  float mi32 = 0.f;
-  if (maybe) {
-    float s = mc.s0, e = mc.e0;
-    int ci = 0;
-    walk_order3(q, [&](uint32_t n0, uint32_t n1) {
-      if (++ci % 9 == 0) __builtin_amdgcn_sched_barrier(0);
-      mi_cell(F, n0, n1, s, e);
-    });
-    mi32 = (s + e) * mc.inv_m;
-  }
-  emit(v, maybe, mi32, rank, thr, lane);
+  float fs = mc.c;
+  if (active) walk_order3(q, [&](uint32_t n0, uint32_t n1) { fs += mi_term(F, n0, n1); });
+  emit(v, active, fs * mc.inv_m, rank, thr, lane);
 }
 
 // A wave holds P prefixes (a_first + p, b) with a common last prefix variant
@@ -683,9 +665,9 @@ __device__ __forceinline__ void tile_order3p(const Globals &g, const JV &v, uint
   count3p<P, 0>(rb, ra, 0, v.W0, col, v.n_pad, acc);
   count3p<P, 1>(rb, ra, v.W0, v.W0 + v.W1, col, v.n_pad, acc);
 
-  const float thr = current_threshold(v.st);
+  const float thr = current_threshold(v);
   const MiConst mc = mi_const(v);
-  const FI_GLOBAL u64 *F = as_global(reinterpret_cast<const u64 *>(v.F32));
+  const FI_GLOBAL float *F = as_global(v.Fh);
   cu32p marg = as_const(v.marg);
   const uint32_t jj = jvalid ? j : n - 1;
   const FI_GLOBAL uint32_t *PTg = as_global(v.pairs);
@@ -719,7 +701,7 @@ __device__ __forceinline__ void tile_order3p(const Globals &g, const JV &v, uint
     const u64 rank = lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1);
     const uint32_t mcls[2] = {v.m0, v.m1};
     const Order3Parts parts = {acc[p], ab, aj, bj, Ma, Mb, Mj, mcls};
-    score_streamed<27>(v, F, parts, active, thr, mc, rank, lane);
+    score_streamed(v, F, parts, active, thr, mc, rank, lane);
   }
 }
 
@@ -756,7 +738,7 @@ __device__ __forceinline__ void run_orderk(const Globals &g, const JV &v, uint32
 }
 
 // waves per SIMD each variant is compiled for (register budget 512 / waves)
-constexpr int scan_min_waves(int ksel) { return (ksel >= 3 && ksel <= 5) || ksel == 1 ? 4 : 2; }
+constexpr int scan_min_waves(int ksel) { return ksel != 0 ? 4 : 2; }
 
 template <int KSEL>
 __global__ __launch_bounds__(kScanWaves * 64, scan_min_waves(KSEL)) void scan_kernel(Globals g) {

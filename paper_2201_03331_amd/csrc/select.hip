@@ -10,17 +10,19 @@
 //   3. rescore:  recount each kept combination's table and evaluate Eq. 1-3 in
 //                IEEE double, term by term in a fixed order;
 //   4. finish:   order by (MI descending, rank ascending), write top_n hits.
-// A combination is dropped only when its FP32 score is more than twice the
-// tolerance below a score that top_n other combinations reach, so with
-// |mi32 - mi| <= tolerance it cannot belong to the exact result.
+// The scan's plain single-precision estimate is within fbound of the MI (a
+// bound of its rounding error), so a combination is dropped only when its
+// estimate is more than 2 fbound below one that top_n others reach: it cannot
+// belong to the exact result.  The reported single-precision score is a
+// compensated evaluation made here, beside the double-precision one.
 #include <algorithm>
 
 #include "device_common.hpp"
 
 namespace fiuncho {
 
-__device__ __forceinline__ float tol_threshold(float tau) {
-  return tau * (1.0f - 2e-5f) - 2e-10f;
+__device__ __forceinline__ float tol_threshold(const JobDesc &J, float tau) {
+  return tau - 2.0f * J.fbound;
 }
 
 // 1. all workgroups, grid-stride over one job's candidates (blockIdx.y = job)
@@ -33,7 +35,7 @@ __global__ __launch_bounds__(256) void compact_kernel(Globals g) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&st->flags, kFlagCandOverflow);
     return;
   }
-  const float thr = tol_threshold(__uint_as_float(st->tau_key));
+  const float thr = tol_threshold(J, __uint_as_float(st->tau_key));
   const uint32_t lane = lane_id();
   for (u64 i0 = (u64)blockIdx.x * blockDim.x; i0 < count; i0 += (u64)gridDim.x * blockDim.x) {
     const u64 i = i0 + threadIdx.x;
@@ -41,7 +43,7 @@ __global__ __launch_bounds__(256) void compact_kernel(Globals g) {
     Cand c;
     if (i < count) {
       c = J.cand[i];
-      keep = c.mi32 >= thr;
+      keep = c.est >= thr;
     }
     const u64 mask = ballot(keep);
     if (mask == 0) continue;
@@ -106,20 +108,20 @@ __global__ __launch_bounds__(1024) void select_kernel(Globals g) {
     }
     const uint32_t kth = s_prefix;
     if (tid == 0) st->kth_key = kth;
-    thr2 = tol_threshold(__uint_as_float(kth));
+    thr2 = tol_threshold(J, __uint_as_float(kth));
   }
   if (tid == 0) s_count = 0;
   __syncthreads();
   for (uint32_t i = tid; i < M; i += blockDim.x) {
     const Cand c = J.l1[i];
-    if (c.mi32 >= thr2) {
+    if (c.est >= thr2) {
       const uint32_t at = atomicAdd(&s_count, 1u);
       if (at < J.l2_cap) {
         Rescored r;
         r.rank = c.rank;
-        r.mi32 = c.mi32;
+        r.est = c.est;
+        r.mi32 = 0.f;
         r.mi = 0.0;
-        r.rel_err = 0.f;
         J.l2[at] = r;
       }
     }
@@ -186,6 +188,26 @@ __device__ double mi64_of_table(const double *__restrict__ P64, const uint32_t *
   return (hx + hy) - hxy;
 }
 
+// m * MI = [f(m) - f(m0) - f(m1)] + sum_x [f(n_x0) + f(n_x1) - f(n_x0 + n_x1)]
+// (Eq. 1-3 multiplied out, f(t) = t ln t) in single precision: f as an
+// unevaluated pair hi + lo of floats, accumulated with TwoSum so that the
+// cancellation of the m ln m sized terms loses nothing.
+__device__ float mi32_compensated(const float2 *__restrict__ F, const uint32_t *t,
+                                  uint32_t cells, uint32_t m, uint32_t m0, uint32_t m1) {
+  float s = F[m].x, e = 0.f;
+  two_sum_add(s, e, -F[m0].x);
+  two_sum_add(s, e, -F[m1].x);
+  e += (F[m].y - F[m0].y) - F[m1].y;
+  for (uint32_t x = 0; x < cells; ++x) {
+    const float2 a = F[t[2 * x]], b = F[t[2 * x + 1]], c = F[t[2 * x] + t[2 * x + 1]];
+    two_sum_add(s, e, a.x);
+    two_sum_add(s, e, b.x);
+    two_sum_add(s, e, -c.x);
+    e += (a.y + b.y) - c.y;
+  }
+  return (s + e) / (float)m;
+}
+
 constexpr int kMaxCells = 6561;  // 3^8
 
 __global__ __launch_bounds__(64) void rescore_kernel(Globals g) {
@@ -207,10 +229,9 @@ __global__ __launch_bounds__(64) void rescore_kernel(Globals g) {
     if (lane == 0) {
       const double mi = mi64_of_table(J.P64, lds_t, cells, st->m0, st->m1);
       r.mi = mi;
-      const double d = fabs((double)r.mi32 - mi);
-      r.rel_err = mi != 0.0 ? (float)(d / fabs(mi)) : (float)d;
-      // the filters assumed |mi32 - mi| <= 1e-5 mi + 1e-10
-      if (d > 1e-5 * fabs(mi) + 1e-10) atomicOr(&st->flags, kFlagBound);
+      r.mi32 = mi32_compensated(J.F32, lds_t, cells, J.m, st->m0, st->m1);
+      // the filters assumed |estimate - mi| <= fbound
+      if (fabs((double)r.est - mi) > (double)J.fbound) atomicOr(&st->flags, kFlagBound);
       for (uint32_t q = 0; q < kMaxOrder; ++q) r.snp[q] = q < J.k ? c[q] : 0xffffffffu;
       J.l2[i] = r;
     }
@@ -306,7 +327,8 @@ __global__ __launch_bounds__(1024) void finish_kernel(Globals g) {
     h.rank = r.rank;
     h.mi = r.mi;
     h.mi32 = r.mi32;
-    h.rel_err = r.rel_err;
+    const double d = fabs((double)r.mi32 - r.mi);
+    h.rel_err = r.mi != 0.0 ? (float)(d / fabs(r.mi)) : (float)d;
     J.out[i] = h;
   }
   if (tid == 0) {
