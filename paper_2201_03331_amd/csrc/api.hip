@@ -248,17 +248,22 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
 }
 
 // Bound of |plain single-precision MI - MI| for tables of 3^k cells and m
-// samples.  With u = 2^-24 and f(t) = t ln t: each table value is within
-// u f(m) of f; a cell adds (f(n0) + f(n1)) - f(n0 + n1), whose first sum is at
-// most f(m) and whose result, like every partial sum of m * MI, is at most m
-// in magnitude; so every cell, and the start f(m) - f(m0) - f(m1), costs at
-// most u (4 f(m) + 2 m).  Over 3^k + 2 such terms and after division by m the
-// error is below 4u (3^k + 2)(ln m + 1/2); twice that is used.
+// samples.  Let u = 2^-24, f(t) = t ln t, n_x = n_x0 + n_x1.  The scan
+// computes c = (F[m] - F[m0]) - F[m1], then s += (F[n_x0] + F[n_x1]) -
+// F[n_x] over the cells, then s * (1/m), where each table value F[t] is
+// within u f(t) of f(t).  Because f is superadditive (f(a) + f(b) <= f(a+b)),
+// sum_x f(n_x) <= f(m); the exact start lies in [0, m ln 2], every exact cell
+// term in [-n_x ln 2, 0] and every partial sum in [-m ln 2, m ln 2].  Hence:
+//   start:        u (3 f(m) + m ln 2)
+//   cells:        sum_x u (3 f(n_x) + n_x ln 2) <= u (3 f(m) + m ln 2)
+//   accumulation: 3^k additions of at most u m ln 2 each
+//   final scaling: 2u ln 2 on MI
+// so |estimate - MI| <= u (6 ln m + (3^k + 4) ln 2); twice that is used.
 float fbound(uint32_t k, uint32_t m) {
   double cells = 1;
   for (uint32_t i = 0; i < k; ++i) cells *= 3;
   const double u = std::ldexp(1.0, -24);
-  const double b = 8.0 * u * (cells + 2.0) * (std::log((double)m) + 1.0);
+  const double b = 2.0 * u * (6.0 * std::log((double)m) + (cells + 4.0) * std::log(2.0));
   return (float)(b * 1.0001);
 }
 

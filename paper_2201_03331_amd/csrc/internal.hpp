@@ -16,7 +16,7 @@ constexpr int kWave = 64;                     // gfx950 wavefront
 constexpr int kJBlock = 64;                   // last variants per tile (one per lane)
 constexpr int kHistShift = 20;                // survivor histogram bin = key >> 20
 constexpr int kHistBins = 1 << (31 - kHistShift);
-constexpr uint32_t kSortMax = 4096;           // candidates ordered in one LDS sort
+constexpr uint32_t kSortMax = 8192;           // candidates ordered in one LDS sort
 constexpr int kScanWaves = 4;                 // waves per workgroup in the scan
 constexpr int kOrder2Prefixes = 4;            // first variants per wave at order 2
 constexpr int kOrder3Prefixes = 2;            // prefixes per wave, order-3 pair path
