@@ -242,8 +242,12 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     return J.path == fiuncho::kPathPairs ? fiuncho::kSelPairs : (J.k <= 5 ? (int)J.k : 0);
   };
   L.ksel = sel(L.jobs[0]);
-  for (auto &J : L.jobs)
+  bool only23 = true;
+  for (auto &J : L.jobs) {
     if (sel(J) != L.ksel) L.ksel = 0;
+    only23 = only23 && (J.k == 2 || J.path == fiuncho::kPathPairs);
+  }
+  if (L.ksel == 0 && only23) L.ksel = fiuncho::kSel23;
   return FIUNCHO_OK;
 }
 

@@ -25,6 +25,7 @@ constexpr int kOrder3Prefixes = 2;            // prefixes per wave, order-3 pair
 constexpr uint32_t kPathGeneric = 0;          // rows g = 0, 1 of the last variant
 constexpr uint32_t kPathPairs = 1;            // order 3, {0,1}^3 cells + pair tables
 constexpr int kSelPairs = 31;                 // scan_kernel selector: order-3 pair path only
+constexpr int kSel23 = 23;                    // scan_kernel selector: orders 2 and 3 (pair path)
 
 // state the device writes during one run of a job (cleared at the start)
 struct JobState {

@@ -771,7 +771,7 @@ __global__ __launch_bounds__(kScanWaves * 64, scan_min_waves(KSEL)) void scan_ke
     }
     const FI_CONST JobDesc *jd = as_const(g.jobs) + lo;
     const u64 lt = t - uni64(jd->tile_begin);
-    const int k = KSEL == kSelPairs ? 3 : KSEL ? KSEL : (int)v.k;
+    const int k = KSEL == kSelPairs ? 3 : (KSEL && KSEL != kSel23) ? KSEL : (int)v.k;
     if (k == 1) {
       if (KSEL == 0 || KSEL == 1) tile_order1(v, lt, wave, lane);
       continue;
@@ -786,15 +786,15 @@ __global__ __launch_bounds__(kScanWaves * 64, scan_min_waves(KSEL)) void scan_ke
     rl = uni(rl);
     const u64 local = uni64(lt - rows[rl]);
     if (k == 2) {
-      if (KSEL == 0 || KSEL == 2) {
+      if (KSEL == 0 || KSEL == 2 || KSEL == kSel23) {
         const uint32_t a_first = rl * (kScanWaves * kOrder2Prefixes);
         const uint32_t j0 = a_first + 1 + (uint32_t)local * 64;
         tile_order2<kOrder2Prefixes>(g, v, a_first + wave * kOrder2Prefixes, j0, lane);
       }
       continue;
     }
-    if (k == 3 && (KSEL == kSelPairs || (KSEL == 0 && v.path == kPathPairs))) {
-      if (KSEL == 0 || KSEL == kSelPairs) {
+    if (k == 3 && (KSEL == kSelPairs || KSEL == kSel23 || (KSEL == 0 && v.path == kPathPairs))) {
+      if (KSEL == 0 || KSEL == kSelPairs || KSEL == kSel23) {
         const uint32_t b = rl + 1;
         const uint32_t nj = (v.n - 1 - b + 63) / 64;
         const u64 grp = local / nj;
@@ -836,6 +836,7 @@ int scan_grid_size(int ksel) {
     case 4: return occupancy_grid<4>();
     case 5: return occupancy_grid<5>();
     case kSelPairs: return occupancy_grid<kSelPairs>();
+    case kSel23: return occupancy_grid<kSel23>();
     default: return occupancy_grid<0>();
   }
 }
@@ -856,6 +857,7 @@ void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s) {
     case 4: hipLaunchKernelGGL(scan_kernel<4>, gd, bd, 0, s, g); break;
     case 5: hipLaunchKernelGGL(scan_kernel<5>, gd, bd, 0, s, g); break;
     case kSelPairs: hipLaunchKernelGGL(scan_kernel<kSelPairs>, gd, bd, 0, s, g); break;
+    case kSel23: hipLaunchKernelGGL(scan_kernel<kSel23>, gd, bd, 0, s, g); break;
     default: hipLaunchKernelGGL(scan_kernel<0>, gd, bd, 0, s, g); break;
   }
 }
