@@ -145,6 +145,23 @@ int fiuncho_contingency(const uint8_t *genotypes, const uint8_t *phenotype,
                         uint32_t snps, uint32_t samples, int order,
                         const uint64_t *ranks, uint64_t n_ranks, uint32_t *tables);
 
+/*
+ * fiuncho_score -- mutual information (section 3.3, Eq. 1-3) of explicit
+ * combinations, from the same device tables as the search.
+ *   ranks  host array of n_ranks lexicographic ranks, each < C(snps, order)
+ *   est    host float[n_ranks] or NULL: the plain single-precision evaluation
+ *          the search filters with; |est - mi| is below a bound that
+ *          depends only on order and samples
+ *   mi32   host float[n_ranks] or NULL: compensated single precision, the
+ *          value reported as fiuncho_hit.mi32
+ *   mi     host double[n_ranks] or NULL: IEEE double, the value reported as
+ *          fiuncho_hit.mi
+ * Synchronous; validation and errors as in fiuncho_contingency.
+ */
+int fiuncho_score(const uint8_t *genotypes, const uint8_t *phenotype, uint32_t snps,
+                  uint32_t samples, int order, const uint64_t *ranks, uint64_t n_ranks,
+                  float *est, float *mi32, double *mi);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *fiuncho_last_error(void);
 

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -687,64 +688,108 @@ int fiuncho_scan(const uint8_t *genotypes, const uint8_t *phenotype, uint32_t sn
   }
 }
 
+}  // extern "C"
+
+namespace {
+
+// tables and/or scores of explicit combinations (fiuncho_contingency,
+// fiuncho_score)
+int explicit_impl(const uint8_t *genotypes, const uint8_t *phenotype, uint32_t snps,
+                  uint32_t samples, int order, const uint64_t *ranks, uint64_t n_ranks,
+                  uint32_t *tables, float *est, float *mi32, double *mi) {
+  fiuncho_job job;
+  std::memset(&job, 0, sizeof(job));
+  job.genotypes = genotypes;
+  job.phenotype = phenotype;
+  job.snps = snps;
+  job.samples = samples;
+  job.order = order;
+  job.top_n = 1;
+  if (!genotypes || !phenotype || (n_ranks && !ranks))
+    return fail(FIUNCHO_E_NULL, "a required pointer is NULL");
+  int st = check_shape(job, false);
+  if (st) return st;
+  st = check_values(genotypes, phenotype, snps, samples);
+  if (st) return st;
+  const u64 total = binom_host(snps, (u64)order);
+  for (uint64_t i = 0; i < n_ranks; ++i)
+    if (ranks[i] >= total)
+      return fail(FIUNCHO_E_SHAPE, "rank " + std::to_string(ranks[i]) + " is not below C(snps, order)");
+  if (n_ranks == 0) return FIUNCHO_OK;
+  st = check_device();
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  Layout L;
+  st = make_layout(&job, 1, true, 1, L);
+  if (st) return st;
+  uint64_t cells = 1;
+  for (int q = 0; q < order; ++q) cells *= 3;
+  const size_t rank_off = align256(L.total);
+  const size_t tab_off = align256(rank_off + sizeof(u64) * n_ranks);
+  const size_t est_off = align256(tab_off + (tables ? sizeof(uint32_t) * 2 * cells * n_ranks : 0));
+  const size_t m32_off = align256(est_off + (est ? sizeof(float) * n_ranks : 0));
+  const size_t m64_off = align256(m32_off + (mi32 ? sizeof(float) * n_ranks : 0));
+  const size_t need = m64_off + (mi ? sizeof(double) * n_ranks : 0);
+  void *wsv = nullptr;
+  st = owned_workspace(need, &wsv);
+  if (st) return st;
+  uint8_t *ws = static_cast<uint8_t *>(wsv);
+  hipStream_t s = nullptr;
+  st = upload_plan(L, &job, ws, true, s);
+  if (st) return st;
+  const JobLayout &J = L.jobs[0];
+  HIP_TRY(hipMemcpyAsync(ws + J.off_G, genotypes, (size_t)snps * samples, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(ws + J.off_y, phenotype, samples, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(ws + rank_off, ranks, sizeof(u64) * n_ranks, hipMemcpyHostToDevice, s));
+  const Globals g = make_globals(L, ws);
+  fiuncho::launch_init(g, s);
+  fiuncho::launch_pack(g, L.max_n_pad, s);
+  fiuncho::launch_tables(g, reinterpret_cast<const u64 *>(ws + rank_off), n_ranks,
+                         tables ? reinterpret_cast<uint32_t *>(ws + tab_off) : nullptr,
+                         est ? reinterpret_cast<float *>(ws + est_off) : nullptr,
+                         mi32 ? reinterpret_cast<float *>(ws + m32_off) : nullptr,
+                         mi ? reinterpret_cast<double *>(ws + m64_off) : nullptr, (uint32_t)order, s);
+  HIP_TRY(hipGetLastError());
+  int32_t status = 0;
+  HIP_TRY(hipMemcpyAsync(&status, ws + J.off_state + offsetof(JobState, status), sizeof(int32_t),
+                         hipMemcpyDeviceToHost, s));
+  if (tables)
+    HIP_TRY(hipMemcpyAsync(tables, ws + tab_off, sizeof(uint32_t) * 2 * cells * n_ranks,
+                           hipMemcpyDeviceToHost, s));
+  if (est) HIP_TRY(hipMemcpyAsync(est, ws + est_off, sizeof(float) * n_ranks, hipMemcpyDeviceToHost, s));
+  if (mi32) HIP_TRY(hipMemcpyAsync(mi32, ws + m32_off, sizeof(float) * n_ranks, hipMemcpyDeviceToHost, s));
+  if (mi) HIP_TRY(hipMemcpyAsync(mi, ws + m64_off, sizeof(double) * n_ranks, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (status != 0) return fail(status, "the device rejected the input");
+  return FIUNCHO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int fiuncho_contingency(const uint8_t *genotypes, const uint8_t *phenotype, uint32_t snps,
                         uint32_t samples, int order, const uint64_t *ranks, uint64_t n_ranks,
                         uint32_t *tables) {
   t_err.clear();
   try {
-    fiuncho_job job;
-    std::memset(&job, 0, sizeof(job));
-    job.genotypes = genotypes;
-    job.phenotype = phenotype;
-    job.snps = snps;
-    job.samples = samples;
-    job.order = order;
-    job.top_n = 1;
-    if (!genotypes || !phenotype || (n_ranks && (!ranks || !tables)))
-      return fail(FIUNCHO_E_NULL, "a required pointer is NULL");
-    int st = check_shape(job, false);
-    if (st) return st;
-    st = check_values(genotypes, phenotype, snps, samples);
-    if (st) return st;
-    const u64 total = binom_host(snps, (u64)order);
-    for (uint64_t i = 0; i < n_ranks; ++i)
-      if (ranks[i] >= total)
-        return fail(FIUNCHO_E_SHAPE, "rank " + std::to_string(ranks[i]) + " is not below C(snps, order)");
-    if (n_ranks == 0) return FIUNCHO_OK;
-    st = check_device();
-    if (st) return st;
-    std::lock_guard<std::mutex> lk(g_ws_mu);
-    Layout L;
-    st = make_layout(&job, 1, true, 1, L);
-    if (st) return st;
-    uint64_t cells = 1;
-    for (int q = 0; q < order; ++q) cells *= 3;
-    const size_t rank_off = align256(L.total);
-    const size_t tab_off = align256(rank_off + sizeof(u64) * n_ranks);
-    const size_t need = tab_off + sizeof(uint32_t) * 2 * cells * n_ranks;
-    void *wsv = nullptr;
-    st = owned_workspace(need, &wsv);
-    if (st) return st;
-    uint8_t *ws = static_cast<uint8_t *>(wsv);
-    hipStream_t s = nullptr;
-    // outputs of the scan part are unused; point them into the workspace
-    fiuncho_job j2 = job;
-    st = upload_plan(L, &j2, ws, true, s);
-    if (st) return st;
-    const JobLayout &J = L.jobs[0];
-    HIP_TRY(hipMemcpyAsync(ws + J.off_G, genotypes, (size_t)snps * samples, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(ws + J.off_y, phenotype, samples, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(ws + rank_off, ranks, sizeof(u64) * n_ranks, hipMemcpyHostToDevice, s));
-    const Globals g = make_globals(L, ws);
-    fiuncho::launch_init(g, s);
-    fiuncho::launch_pack(g, L.max_n_pad, s);
-    fiuncho::launch_tables(g, reinterpret_cast<const u64 *>(ws + rank_off), n_ranks,
-                           reinterpret_cast<uint32_t *>(ws + tab_off), s);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(tables, ws + tab_off, sizeof(uint32_t) * 2 * cells * n_ranks,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    return FIUNCHO_OK;
+    if (n_ranks && !tables) return fail(FIUNCHO_E_NULL, "tables is NULL");
+    return explicit_impl(genotypes, phenotype, snps, samples, order, ranks, n_ranks, tables,
+                         nullptr, nullptr, nullptr);
+  } catch (const std::exception &e) {
+    return fail(FIUNCHO_E_DEVICE, std::string("internal error: ") + e.what());
+  } catch (...) {
+    return fail(FIUNCHO_E_DEVICE, "internal error");
+  }
+}
+
+int fiuncho_score(const uint8_t *genotypes, const uint8_t *phenotype, uint32_t snps,
+                  uint32_t samples, int order, const uint64_t *ranks, uint64_t n_ranks,
+                  float *est, float *mi32, double *mi) {
+  t_err.clear();
+  try {
+    return explicit_impl(genotypes, phenotype, snps, samples, order, ranks, n_ranks, nullptr, est,
+                         mi32, mi);
   } catch (const std::exception &e) {
     return fail(FIUNCHO_E_DEVICE, std::string("internal error: ") + e.what());
   } catch (...) {

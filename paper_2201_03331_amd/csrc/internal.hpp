@@ -118,7 +118,8 @@ void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
 void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s);
 void launch_finish(const Globals &g, hipStream_t s);
 void launch_tables(const Globals &g, const unsigned long long *ranks, uint64_t n_ranks,
-                   uint32_t *tables, hipStream_t s);
+                   uint32_t *tables, float *est, float *mi32, double *mi, uint32_t k,
+                   hipStream_t s);
 int scan_grid_size(int ksel);
 
 }  // namespace fiuncho

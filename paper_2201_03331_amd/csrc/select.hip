@@ -337,19 +337,41 @@ __global__ __launch_bounds__(1024) void finish_kernel(Globals g) {
   }
 }
 
-// explicit tables of given ranks (single job 0)
+// Tables and scores of explicit combinations (job 0): one wave per rank.
+// Any output may be null.  est is the plain single-precision evaluation the
+// scan filters with (cells in ascending order), mi32 the compensated one, mi
+// the double-precision one.
 __global__ __launch_bounds__(64) void tables_kernel(Globals g, const u64 *ranks, u64 n_ranks,
-                                                    uint32_t *tables) {
+                                                    uint32_t *tables, float *est, float *mi32,
+                                                    double *mi) {
   const JobDesc &J = g.jobs[0];
   const JobState *st = J.state;
   if (st->status != 0) return;
-  const u64 i = blockIdx.x + (u64)blockIdx.y * gridDim.x;
-  if (i >= n_ranks) return;
+  extern __shared__ uint32_t lds_t[];
   uint32_t cells = 1;
   for (uint32_t q = 0; q < J.k; ++q) cells *= 3;
-  uint32_t c[kMaxOrder];
-  lex_unrank(g, J.n, J.k, ranks[i], c);
-  count_cells<true>(J, st, c, J.k, lane_id(), nullptr, tables + i * 2 * cells);
+  const u64 stride = (u64)gridDim.x * gridDim.y;
+  for (u64 i = blockIdx.x + (u64)blockIdx.y * gridDim.x; i < n_ranks; i += stride) {
+    uint32_t c[kMaxOrder];
+    lex_unrank(g, J.n, J.k, ranks[i], c);
+    if (tables) count_cells<true>(J, st, c, J.k, lane_id(), lds_t, tables + i * 2 * cells);
+    else count_cells<false>(J, st, c, J.k, lane_id(), lds_t, nullptr);
+    __syncthreads();
+    if (lane_id() == 0) {
+      if (est) {
+        const float *F = J.Fh;
+        float fs = (F[J.m] - F[st->m0]) - F[st->m1];
+        for (uint32_t x = 0; x < cells; ++x) {
+          const uint32_t a = lds_t[2 * x], b = lds_t[2 * x + 1];
+          fs += (F[a] + F[b]) - F[a + b];
+        }
+        est[i] = fs * (1.0f / (float)J.m);
+      }
+      if (mi32) mi32[i] = mi32_compensated(J.F32, lds_t, cells, J.m, st->m0, st->m1);
+      if (mi) mi[i] = mi64_of_table(J.P64, lds_t, cells, st->m0, st->m1);
+    }
+    __syncthreads();
+  }
 }
 
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s) {
@@ -372,11 +394,14 @@ void launch_finish(const Globals &g, hipStream_t s) {
 }
 
 void launch_tables(const Globals &g, const unsigned long long *ranks, uint64_t n_ranks,
-                   uint32_t *tables, hipStream_t s) {
+                   uint32_t *tables, float *est, float *mi32, double *mi, uint32_t k,
+                   hipStream_t s) {
+  uint32_t cells = 1;
+  for (uint32_t q = 0; q < k; ++q) cells *= 3;
   const uint64_t gx = n_ranks < 65535 ? (n_ranks ? n_ranks : 1) : 65535;
-  const uint64_t gy = (n_ranks + gx - 1) / gx;
-  hipLaunchKernelGGL(tables_kernel, dim3((uint32_t)gx, (uint32_t)(gy ? gy : 1)), dim3(64), 0, s,
-                     g, ranks, (u64)n_ranks, tables);
+  const uint64_t gy = std::min<uint64_t>((n_ranks + gx - 1) / gx, 64);
+  hipLaunchKernelGGL(tables_kernel, dim3((uint32_t)gx, (uint32_t)(gy ? gy : 1)), dim3(64),
+                     sizeof(uint32_t) * 2 * cells, s, g, ranks, (u64)n_ranks, tables, est, mi32, mi);
 }
 
 }  // namespace fiuncho

@@ -35,6 +35,7 @@ EXPORTS = (
     "fiuncho_workspace_bytes",
     "fiuncho_scan_batch",
     "fiuncho_contingency",
+    "fiuncho_score",
     "fiuncho_last_error",
     "fiuncho_set_profiling",
     "fiuncho_get_profile",
@@ -111,6 +112,10 @@ def lib() -> ctypes.CDLL:
         L.fiuncho_contingency.restype = ctypes.c_int
         L.fiuncho_contingency.argtypes = [u8p, u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
                                           ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+        L.fiuncho_score.restype = ctypes.c_int
+        L.fiuncho_score.argtypes = [u8p, u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                    ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p]
         L.fiuncho_last_error.restype = ctypes.c_char_p
         L.fiuncho_last_error.argtypes = []
         L.fiuncho_set_profiling.restype = None
@@ -171,6 +176,19 @@ def contingency(G, y, order: int, ranks) -> np.ndarray:
     _check(lib().fiuncho_contingency(G.ctypes.data, y.ctypes.data, G.shape[0], G.shape[1], order,
                                      r.ctypes.data, len(r), tabs.ctypes.data))
     return tabs
+
+
+def score(G, y, order: int, ranks):
+    """(est, mi32, mi) of explicit combinations (fiuncho_score)."""
+    G, y = _host_arrays(G, y)
+    r = np.ascontiguousarray(ranks, dtype=np.uint64)
+    est = np.zeros(len(r), dtype=np.float32)
+    m32 = np.zeros(len(r), dtype=np.float32)
+    m64 = np.zeros(len(r), dtype=np.float64)
+    _check(lib().fiuncho_score(G.ctypes.data, y.ctypes.data, G.shape[0], G.shape[1], order,
+                               r.ctypes.data, len(r), est.ctypes.data, m32.ctypes.data,
+                               m64.ctypes.data))
+    return est, m32, m64
 
 
 def set_profiling(enable: bool):

@@ -275,3 +275,43 @@ def test_order3_both_paths(pairs, monkeypatch):
         G, y = random_dataset(seed, n, m, frac, 1, 2)
         hits = fiuncho.scan(G, y, 3, 37)
         check_hits_against_oracle(G, y, 3, 37, hits)
+
+
+# ---------------------------------------------------------------------------
+# precision of the single-precision scores
+# ---------------------------------------------------------------------------
+
+def fp32_bound(k, m):
+    u = 2.0 ** -24
+    return 2 * u * (6 * math.log(m) + (3 ** k + 4) * math.log(2))
+
+
+def test_scores_of_every_order2_pair():
+    d = synth.order2_small()
+    ranks = np.arange(math.comb(d.n, 2), dtype=np.uint64)
+    est, m32, m64 = fiuncho.score(d.genotypes, d.phenotype, 2, ranks)
+    ref = oracle.score_ranks(d.genotypes, d.phenotype, 2, ranks)
+    np.testing.assert_array_equal(m64, ref)
+    assert np.all(np.abs(m32 - ref) <= TOL_REL * np.abs(ref) + TOL_ABS)
+    assert np.all(np.abs(est - ref) <= fp32_bound(2, d.m))
+
+
+@pytest.mark.parametrize("order,count", [(4, 1_000_000), (5, 200_000)])
+def test_precision_sample_high_order(order, count):
+    """FP32-vs-FP64 error on a seeded sample of combinations of the
+    200-variant x 4,000-sample high-order workload."""
+    d = synth.high_order(order)
+    total = math.comb(d.n, order)
+    rng = np.random.default_rng(55)
+    ranks = np.unique(rng.integers(0, total, size=count, dtype=np.uint64))
+    say(f"case: precision order {order}, {len(ranks)} combinations")
+    est, m32, m64 = fiuncho.score(d.genotypes, d.phenotype, order, ranks)
+    sub = ranks[:20000]
+    np.testing.assert_array_equal(m64[:20000], oracle.score_ranks(d.genotypes, d.phenotype, order, sub))
+    rel = np.abs(m32.astype(np.float64) - m64) / np.maximum(np.abs(m64), 1e-300)
+    absd = np.abs(m32.astype(np.float64) - m64)
+    say(f"order {order}: mi32 rel err max {rel.max():.3e} median {np.median(rel):.3e}, "
+        f"abs max {absd.max():.3e}; est abs err max {np.abs(est - m64).max():.3e} "
+        f"(bound {fp32_bound(order, d.m):.3e})")
+    assert np.all(absd <= TOL_REL * np.abs(m64) + TOL_ABS)
+    assert np.all(np.abs(est - m64) <= fp32_bound(order, d.m))
