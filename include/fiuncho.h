@@ -99,6 +99,17 @@ typedef struct {
   uint32_t *n_out;    /* device pointer with FIUNCHO_DEVICE_PTRS */
   int32_t *status;    /* optional (may be NULL): per-job FIUNCHO_* code; device
                          pointer with FIUNCHO_DEVICE_PTRS */
+  uint32_t shard_index; /* with shard_count > 1: search only this shard's work   */
+  uint32_t shard_count; /* tiles (one GPU's share of a search split across
+                           shard_count GPUs): the job's tiles are dealt in blocks of
+                           shard_count consecutive tiles, and in block q shard s takes
+                           the tile at offset (s + q) mod shard_count.  The result is
+                           the best top_n of that share, and merging the lists of
+                           all shards under the total order gives the full result.
+                           With an empty class every MI is 0 and the share is the
+                           ranks congruent to shard_index modulo shard_count.
+                           shard_count 0 or 1: the whole search.
+                           shard_index >= shard_count: FIUNCHO_E_SHAPE */
 } fiuncho_job;
 
 /* Flags of fiuncho_scan_batch. */
@@ -161,6 +172,23 @@ int fiuncho_contingency(const uint8_t *genotypes, const uint8_t *phenotype,
 int fiuncho_score(const uint8_t *genotypes, const uint8_t *phenotype, uint32_t snps,
                   uint32_t samples, int order, const uint64_t *ranks, uint64_t n_ranks,
                   float *est, float *mi32, double *mi);
+
+/*
+ * fiuncho_shard_counts -- combinations each of `units` processing units gets
+ * (host-only; no device work).
+ *   scheme 0: the paper's static distribution (section 4.1, Fig. 4): the
+ *             (order-1)-prefixes in ascending lexicographic order are dealt
+ *             round-robin to the units, and a unit tests every combination
+ *             that extends its prefixes;
+ *   scheme 1: this library's shards (fiuncho_job.shard_index/shard_count):
+ *             the work tiles of the search dealt in rotated blocks.
+ *   Errors: FIUNCHO_E_NULL (counts NULL), FIUNCHO_E_SHAPE (units 0, snps 0
+ *   or an unknown scheme), FIUNCHO_E_ORDER, FIUNCHO_E_OVERFLOW as for a job.
+ *   counts    host array of `units` entries
+ * The relative imbalance of Eq. 4 (section 5.1) is
+ * 100 * (max counts - C(snps,order)/units) / (C(snps,order)/units).
+ */
+int fiuncho_shard_counts(uint32_t snps, int order, uint32_t units, int scheme, uint64_t *counts);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *fiuncho_last_error(void);

@@ -120,11 +120,69 @@ void build_rows(uint32_t n, uint32_t k, uint32_t path, std::vector<u64> &row_sta
   }
 }
 
+// Every local tile of a job in tile order with the number of combinations it
+// tests, as the scan kernel decodes tiles: fn(tile, combinations).
+template <class Fn>
+void for_each_tile(uint32_t n, uint32_t k, uint32_t path, Fn fn) {
+  const u64 N = n;
+  if (k == 1) {
+    const u64 S = (u64)fiuncho::kScanWaves * 64;
+    for (u64 lt = 0; lt * S < N; ++lt) fn(lt, std::min<u64>(S, N - lt * S));
+    return;
+  }
+  u64 lt = 0;
+  if (k == 2) {
+    const u64 S = (u64)fiuncho::kScanWaves * fiuncho::kOrder2Prefixes;
+    for (u64 a_first = 0; a_first + 1 < N; a_first += S) {
+      const u64 a_end = std::min<u64>(a_first + S, N - 1);
+      for (u64 j0 = a_first + 1; j0 < N; j0 += 64) {
+        const u64 j_end = std::min<u64>(j0 + 64, N);
+        u64 c = 0;
+        for (u64 a = a_first; a < a_end; ++a) {
+          const u64 lo = std::max<u64>(j0, a + 1);
+          if (lo < j_end) c += j_end - lo;
+        }
+        fn(lt++, c);
+      }
+    }
+    return;
+  }
+  // rows b (second-to-last variant): groups of prefixes x blocks of 64 last variants
+  const u64 G = path == fiuncho::kPathPairs ? (u64)fiuncho::kScanWaves * fiuncho::kOrder3Prefixes
+                                            : (u64)fiuncho::kScanWaves;
+  for (u64 b = (path == fiuncho::kPathPairs ? 1 : k - 2); b + 2 <= N; ++b) {
+    const u64 prefixes = path == fiuncho::kPathPairs ? b : binom_host(b, k - 2);
+    for (u64 p0 = 0; p0 < prefixes; p0 += G) {
+      const u64 pc = std::min<u64>(G, prefixes - p0);
+      for (u64 j0 = b + 1; j0 < N; j0 += 64) fn(lt++, pc * std::min<u64>(64, N - j0));
+    }
+  }
+}
+
+// Shards deal the tiles of a job in blocks of shard_count consecutive tiles;
+// in block q, shard s takes the tile at offset (s + q) mod shard_count.  The
+// rotation keeps the shards from always drawing the same position of a
+// periodic tile pattern (such as the partial last block of 64 variants of
+// every row).
+u64 tile_shard(u64 lt, u64 count) { return (lt % count + count - (lt / count) % count) % count; }
+
+// tiles of shard s among `tiles`
+u64 shard_tiles(u64 tiles, u64 count, u64 s) {
+  const u64 q = tiles / count, r = tiles % count;
+  return q + ((s + q) % count < r ? 1 : 0);
+}
+
+uint32_t job_path(uint32_t n, uint32_t k) {
+  const char *env_pairs = std::getenv("FIUNCHO_ORDER3_PAIRS");
+  const bool use_pairs = !(env_pairs && env_pairs[0] == '0');
+  return (k == 3 && n >= 3 && use_pairs) ? fiuncho::kPathPairs : fiuncho::kPathGeneric;
+}
+
 // ---------------------------------------------------------------------------
 // workspace layout
 // ---------------------------------------------------------------------------
 struct JobLayout {
-  uint32_t n, m, k, top_n, n_pad, wcap, nrows, path;
+  uint32_t n, m, k, top_n, n_pad, wcap, nrows, path, shard_index, shard_count;
   u64 total;
   uint32_t cand_cap, l1_cap, l2_cap;
   size_t off_G, off_y, off_idx, off_Bv, off_Bs, off_marg, off_hist, off_cand, off_l1, off_l2,
@@ -156,8 +214,6 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
   L.max_cand_cap = 0;
   L.max_l2_cap = 0;
   L.max_pairs_n = 0;
-  const char *env_pairs = std::getenv("FIUNCHO_ORDER3_PAIRS");
-  const bool use_pairs = !(env_pairs && env_pairs[0] == '0');
   size_t off = 0;
   // per-job data
   for (uint32_t i = 0; i < n_jobs; ++i) {
@@ -177,10 +233,14 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     J.cand_cap = (uint32_t)std::max<u64>(cap, 1);
     J.l1_cap = J.cand_cap;
     J.l2_cap = fiuncho::kSortMax;
-    J.path = (J.k == 3 && J.n >= 3 && use_pairs) ? fiuncho::kPathPairs : fiuncho::kPathGeneric;
+    J.path = job_path(J.n, J.k);
     build_rows(J.n, J.k, J.path, J.row_start);
     J.nrows = (uint32_t)(J.row_start.size() - 1);
-    J.tiles = J.row_start.back();
+    J.shard_count = jobs[i].shard_count > 1 ? jobs[i].shard_count : 1;
+    J.shard_index = J.shard_count > 1 ? jobs[i].shard_index : 0;
+    if (J.shard_index >= J.shard_count)
+      return fail(FIUNCHO_E_SHAPE, "shard_index must be below shard_count");
+    J.tiles = shard_tiles(J.row_start.back(), J.shard_count, J.shard_index);
     const double words = (double)J.wcap;
     J.cost = J.k == 1 ? 1.0
              : J.k == 2 ? words * 4 * fiuncho::kOrder2Prefixes
@@ -338,6 +398,8 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
     d.l2 = reinterpret_cast<Rescored *>(ws + J.off_l2);
     d.l2_cap = J.l2_cap;
     d.path = J.path;
+    d.shard_index = J.shard_index;
+    d.shard_count = J.shard_count;
     d.pairs = J.path == fiuncho::kPathPairs ? reinterpret_cast<uint32_t *>(ws + J.off_pairs) : nullptr;
     d.state = reinterpret_cast<JobState *>(ws + J.off_state);
     d.out = host_inputs ? reinterpret_cast<fiuncho_hit *>(ws + J.off_out) : jobs[i].out;
@@ -459,7 +521,17 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   const Globals g = make_globals(L, ws);
   int st;
   u64 combos = 0;
-  for (auto &J : L.jobs) combos += J.total;
+  if (t_profiling) {
+    for (auto &J : L.jobs) {
+      if (J.shard_count <= 1) {
+        combos += J.total;
+        continue;
+      }
+      for_each_tile(J.n, J.k, J.path, [&](u64 lt, u64 c) {
+        if (tile_shard(lt, J.shard_count) == J.shard_index) combos += c;
+      });
+    }
+  }
   if ((st = prof_begin(combos, reinterpret_cast<JobState *>(ws + L.jobs[0].off_state)))) return st;
   if ((st = prof_record(0, s))) return st;
   fiuncho::launch_init(g, s);
@@ -653,6 +725,7 @@ int fiuncho_scan(const uint8_t *genotypes, const uint8_t *phenotype, uint32_t sn
   if (n_out) *n_out = 0;
   try {
     fiuncho_job job;
+    std::memset(&job, 0, sizeof(job));
     job.genotypes = genotypes;
     job.phenotype = phenotype;
     job.snps = snps;
@@ -781,6 +854,45 @@ int fiuncho_contingency(const uint8_t *genotypes, const uint8_t *phenotype, uint
   } catch (...) {
     return fail(FIUNCHO_E_DEVICE, "internal error");
   }
+}
+
+int fiuncho_shard_counts(uint32_t snps, int order, uint32_t units, int scheme, uint64_t *counts) {
+  t_err.clear();
+  if (!counts) return fail(FIUNCHO_E_NULL, "counts is NULL");
+  if (units == 0) return fail(FIUNCHO_E_SHAPE, "units must be positive");
+  if (scheme != 0 && scheme != 1) return fail(FIUNCHO_E_SHAPE, "scheme must be 0 or 1");
+  if (snps == 0) return fail(FIUNCHO_E_SHAPE, "snps must be positive");
+  if (order < 1 || order > FIUNCHO_MAX_ORDER || (uint32_t)order > snps)
+    return fail(FIUNCHO_E_ORDER, "order must be in [1, min(snps, 8)]");
+  if (binom_host(snps, (u64)order) >= (1ull << 63))
+    return fail(FIUNCHO_E_OVERFLOW, "C(snps, order) must be below 2^63");
+  for (uint32_t u = 0; u < units; ++u) counts[u] = 0;
+  const uint32_t k = (uint32_t)order;
+  if (scheme == 1) {
+    for_each_tile(snps, k, job_path(snps, k), [&](u64 lt, u64 c) { counts[tile_shard(lt, units)] += c; });
+    return FIUNCHO_OK;
+  }
+  if (k == 1) {  // a single, empty prefix
+    counts[0] = snps;
+    return FIUNCHO_OK;
+  }
+  // (k-1)-prefixes with a possible extension are the (k-1)-subsets of
+  // [0, snps-2]; in ascending lexicographic order, prefix i goes to unit
+  // i mod units and brings the snps - 1 - (its last variant) extensions
+  const uint32_t r = k - 1, top = snps - 2;
+  std::vector<uint32_t> c(r);
+  for (uint32_t q = 0; q < r; ++q) c[q] = q;
+  uint32_t unit = 0;
+  for (;;) {
+    counts[unit] += snps - 1 - c[r - 1];
+    unit = unit + 1 == units ? 0 : unit + 1;
+    int q = (int)r - 1;
+    while (q >= 0 && c[q] == top - (r - 1 - (uint32_t)q)) --q;
+    if (q < 0) break;
+    ++c[q];
+    for (uint32_t z = (uint32_t)q + 1; z < r; ++z) c[z] = c[z - 1] + 1;
+  }
+  return FIUNCHO_OK;
 }
 
 int fiuncho_score(const uint8_t *genotypes, const uint8_t *phenotype, uint32_t snps,

@@ -93,6 +93,8 @@ struct JobDesc {
   uint32_t path;              // kPathGeneric or kPathPairs
   JobState *state;
   uint32_t *pairs;            // kPathPairs: [n][n_pad][g_a 0..1][g_j 0..1][class] counts
+  uint32_t shard_index;       // local tile = launch tile * shard_count + shard_index
+  uint32_t shard_count;       // 1 = every tile
   // outputs
   fiuncho_hit *out;
   uint32_t *n_out;

@@ -770,7 +770,14 @@ __global__ __launch_bounds__(kScanWaves * 64, scan_min_waves(KSEL)) void scan_ke
       if (v.m0 == 0 || v.m1 == 0) continue;
     }
     const FI_CONST JobDesc *jd = as_const(g.jobs) + lo;
-    const u64 lt = t - uni64(jd->tile_begin);
+    // local tile: the job's li-th tile, or with shards the shard's li-th
+    // tile, dealt from block li of shard_count consecutive tiles at offset
+    // (shard_index + li) mod shard_count
+    u64 lt = t - uni64(jd->tile_begin);
+    {
+      const uint32_t sc = uni(jd->shard_count);
+      if (sc > 1) lt = uni64(lt * sc + (uni(jd->shard_index) + lt % sc) % sc);
+    }
     const int k = KSEL == kSelPairs ? 3 : (KSEL && KSEL != kSel23) ? KSEL : (int)v.k;
     if (k == 1) {
       if (KSEL == 0 || KSEL == 1) tile_order1(v, lt, wave, lane);

@@ -262,20 +262,25 @@ __global__ __launch_bounds__(1024) void finish_kernel(Globals g) {
   }
   if (st->m0 == 0 || st->m1 == 0) {
     // an empty class: every table is independent of the class, MI = 0, and the
-    // total order makes the result the first top_n ranks
-    for (uint32_t i = tid; i < want; i += blockDim.x) {
+    // total order makes the result the first top_n ranks (of a shard: the
+    // first top_n ranks congruent to shard_index modulo shard_count)
+    const u64 sc = J.shard_count, si = J.shard_index;
+    const u64 share = J.total > si ? (J.total - si + sc - 1) / sc : 0;
+    const uint32_t want_e = (uint32_t)(share < (u64)J.top_n ? share : (u64)J.top_n);
+    for (uint32_t i = tid; i < want_e; i += blockDim.x) {
       fiuncho_hit h;
       uint32_t c[kMaxOrder];
-      lex_unrank(g, J.n, J.k, (u64)i, c);
+      const u64 r = si + (u64)i * sc;
+      lex_unrank(g, J.n, J.k, r, c);
       for (uint32_t q = 0; q < kMaxOrder; ++q) h.snp[q] = q < J.k ? c[q] : 0xffffffffu;
-      h.rank = i;
+      h.rank = r;
       h.mi = 0.0;
       h.mi32 = 0.f;
       h.rel_err = 0.f;
       J.out[i] = h;
     }
     if (tid == 0) {
-      *J.n_out = want;
+      *J.n_out = want_e;
       if (J.status_out) *J.status_out = 0;
     }
     return;

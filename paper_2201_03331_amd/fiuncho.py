@@ -36,6 +36,7 @@ EXPORTS = (
     "fiuncho_scan_batch",
     "fiuncho_contingency",
     "fiuncho_score",
+    "fiuncho_shard_counts",
     "fiuncho_last_error",
     "fiuncho_set_profiling",
     "fiuncho_get_profile",
@@ -57,6 +58,8 @@ class Job(ctypes.Structure):
         ("out", ctypes.c_void_p),
         ("n_out", ctypes.c_void_p),
         ("status", ctypes.c_void_p),
+        ("shard_index", ctypes.c_uint32),
+        ("shard_count", ctypes.c_uint32),
     ]
 
 
@@ -116,6 +119,9 @@ def lib() -> ctypes.CDLL:
         L.fiuncho_score.argtypes = [u8p, u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
                                     ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p]
+        L.fiuncho_shard_counts.restype = ctypes.c_int
+        L.fiuncho_shard_counts.argtypes = [ctypes.c_uint32, ctypes.c_int, ctypes.c_uint32,
+                                           ctypes.c_int, ctypes.c_void_p]
         L.fiuncho_last_error.restype = ctypes.c_char_p
         L.fiuncho_last_error.argtypes = []
         L.fiuncho_set_profiling.restype = None
@@ -191,6 +197,18 @@ def score(G, y, order: int, ranks):
     return est, m32, m64
 
 
+PREFIX_ROUND_ROBIN = 0
+TILE_ROUND_ROBIN = 1
+
+
+def shard_counts(snps: int, order: int, units: int, scheme: int = PREFIX_ROUND_ROBIN) -> np.ndarray:
+    """Combinations per processing unit under a static distribution
+    (fiuncho_shard_counts; host-only)."""
+    counts = np.zeros(units, dtype=np.uint64)
+    _check(lib().fiuncho_shard_counts(snps, order, units, scheme, counts.ctypes.data))
+    return counts
+
+
 def set_profiling(enable: bool):
     lib().fiuncho_set_profiling(1 if enable else 0)
 
@@ -218,7 +236,8 @@ class DeviceBatch:
     """Inputs, outputs and workspace of a batched search held in device memory
     (torch tensors); ``run`` queues fiuncho_scan_batch on a stream."""
 
-    def __init__(self, datasets, device="cuda"):
+    def __init__(self, datasets, device="cuda", shards=None):
+        """``shards``: optional (shard_index, shard_count) per dataset."""
         import torch
 
         self.torch = torch
@@ -238,6 +257,8 @@ class DeviceBatch:
             J.out = self.out[i].data_ptr()
             J.n_out = self.n_out.data_ptr() + 4 * i
             J.status = self.status.data_ptr() + 4 * i
+            if shards is not None:
+                J.shard_index, J.shard_count = shards[i]
         self.ws_bytes = int(lib().fiuncho_workspace_bytes(self.jobs, len(datasets)))
         if self.ws_bytes == 0:
             raise FiunchoError(E_SHAPE, last_error())

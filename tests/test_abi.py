@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 def test_hit_layout_matches_header():
     # snp[8] (32 B) + rank (8 B) + mi (8 B) + mi32 + rel_err (8 B)
     assert fiuncho.HIT_DTYPE.itemsize == 56
-    assert ctypes.sizeof(fiuncho.Job) == 56
+    assert ctypes.sizeof(fiuncho.Job) == 64
 
 
 def _data(n=6, m=40, seed=0):

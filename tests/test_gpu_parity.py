@@ -315,3 +315,70 @@ def test_precision_sample_high_order(order, count):
         f"(bound {fp32_bound(order, d.m):.3e})")
     assert np.all(absd <= TOL_REL * np.abs(m64) + TOL_ABS)
     assert np.all(np.abs(est - m64) <= fp32_bound(order, d.m))
+
+
+# ---------------------------------------------------------------------------
+# shards: one GPU's share of a search split across several
+# ---------------------------------------------------------------------------
+
+def _merge(hit_lists, top_n):
+    allh = np.concatenate(hit_lists)
+    order = np.lexsort((allh["rank"], -allh["mi"]))
+    return allh[order][:top_n]
+
+
+def _run_shards(G, y, k, top_n, P):
+    d = synth.Dataset(G, y, k, top_n)
+    b = fiuncho.DeviceBatch([d] * P, shards=[(s, P) for s in range(P)])
+    b.run()
+    res = b.results()
+    for status, _ in res:
+        assert status == 0
+    return [h for _, h in res]
+
+
+@pytest.mark.parametrize("case", [(700, 300, 1, 20, 3), (300, 500, 2, 50, 7), (150, 400, 3, 40, 5),
+                                  (60, 300, 4, 30, 4), (30, 200, 5, 10, 3)])
+def test_shards_merge_to_full_result(case):
+    """The top-N lists of all shards, merged under the total order, equal the
+    full search (the oracle's)."""
+    n, m, k, top_n, P = case
+    say("case: shards", case)
+    G, y = random_dataset(100 + k, n, m, 0.5)
+    lists = _run_shards(G, y, k, top_n, P)
+    ranks = np.concatenate([h["rank"] for h in lists])
+    assert len(np.unique(ranks)) == len(ranks)
+    check_hits_against_oracle(G, y, k, top_n, _merge(lists, top_n))
+
+
+@pytest.mark.parametrize("n,k,P", [(1500, 1, 3), (60, 2, 7), (5, 2, 3), (20, 3, 4), (14, 4, 5),
+                                   (11, 5, 3)])
+def test_shards_cover_every_combination_once(n, k, P):
+    """With top_n at least C(n, k) each shard returns its whole share: its
+    size is the host's tile count for that shard, the shares are disjoint and
+    cover every rank, and every score is the oracle's."""
+    say("case: shard cover", n, k, P)
+    G, y = random_dataset(7, n, 150, 0.4)
+    total = math.comb(n, k)
+    assert total <= fiuncho.MAX_TOPN
+    lists = _run_shards(G, y, k, fiuncho.MAX_TOPN, P)
+    sizes = fiuncho.shard_counts(n, k, P, fiuncho.TILE_ROUND_ROBIN)
+    assert [len(h) for h in lists] == sizes.tolist()
+    ranks = np.sort(np.concatenate([h["rank"] for h in lists]))
+    np.testing.assert_array_equal(ranks, np.arange(total, dtype=np.uint64))
+    for h in lists:
+        if len(h):
+            np.testing.assert_array_equal(h["mi"], oracle.score_ranks(G, y, k, h["rank"]))
+
+
+def test_shards_with_an_empty_class():
+    n, k, top_n, P = 40, 3, 50, 4
+    G, y = random_dataset(9, n, 100, 0.0)
+    assert y.sum() == 0
+    lists = _run_shards(G, y, k, top_n, P)
+    total = math.comb(n, k)
+    for s, h in enumerate(lists):
+        want = min(top_n, (total - s + P - 1) // P)
+        np.testing.assert_array_equal(h["rank"], s + P * np.arange(want, dtype=np.uint64))
+        assert np.all(h["mi"] == 0.0)
+    np.testing.assert_array_equal(_merge(lists, top_n)["rank"], np.arange(top_n, dtype=np.uint64))
