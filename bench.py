@@ -7,6 +7,10 @@ selection, FP64 rescoring, final ordering) through fiuncho_scan_batch on a
 stream.  Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+                  [--shard I/P]
+
+--shard I/P times one GPU's share of a search split across P GPUs (shard I
+of the job's work tiles); the rate is that share's combinations per second.
 
 Workloads (seeded synthetic data, see paper_2201_03331_amd/synth.py):
   order3-1000x6400 (default), order2-100x1600, order2-4000x16000,
@@ -91,6 +95,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="order3-1000x6400", choices=sorted(workloads().keys()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--shard", default=None, metavar="I/P",
+                    help="search only shard I of P of every dataset's work tiles")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of this many MiB (for counter scaling)")
     args = ap.parse_args()
@@ -115,7 +121,15 @@ def main():
 
     datasets = workloads()[args.workload]()
     plain = args.workload.endswith("-plain")
-    batches = [fiuncho.DeviceBatch([d]) for d in datasets] if plain else [fiuncho.DeviceBatch(datasets)]
+    shard = None
+    if args.shard:
+        si, sp = (int(v) for v in args.shard.split("/"))
+        if not 0 <= si < sp:
+            ap.error("--shard I/P needs 0 <= I < P")
+        shard = (si, sp)
+    sh = None if shard is None else [shard] * len(datasets)
+    batches = ([fiuncho.DeviceBatch([d], shards=None if sh is None else [shard]) for d in datasets]
+               if plain else [fiuncho.DeviceBatch(datasets, shards=sh)])
     stream = torch.cuda.current_stream()
     graph = args.workload == "batch64"
     if graph:
@@ -153,8 +167,13 @@ def main():
     # results of the last step: status and the top hit
     res = [r for b in batches for r in b.results()]
     ok = all(s == 0 for s, _ in res)
-    combos = sum(math.comb(d.n, d.order) for d in datasets)
-    combos_m = sum(math.comb(d.n, d.order) * d.m for d in datasets)
+    def share(d):
+        if shard is None:
+            return math.comb(d.n, d.order)
+        return int(fiuncho.shard_counts(d.n, d.order, shard[1], fiuncho.TILE_ROUND_ROBIN)[shard[0]])
+
+    combos = sum(share(d) for d in datasets)
+    combos_m = sum(share(d) * d.m for d in datasets)
     value = combos / (ms / 1e3)
 
     # roofline of the counting kernel (the dominant one): algorithmic 32-bit
@@ -162,14 +181,14 @@ def main():
     lane_ops = 0
     for d in datasets:
         m1 = int(d.phenotype.sum())
-        lane_ops += 4 * word_ops_per_combination(d.order, d.m - m1, m1) * math.comb(d.n, d.order)
+        lane_ops += 4 * word_ops_per_combination(d.order, d.m - m1, m1) * share(d)
     scan_ms = prof["scan_ms"] if not plain else prof["scan_ms"] * len(batches)
     achieved = lane_ops / (scan_ms / 1e3) / 1e12
     peak = VALU_PEAK_LANE_OPS / 1e12
 
     d0 = datasets[0]
     planted_first = None
-    if len(datasets) == 1 and res[0][1].size:
+    if len(datasets) == 1 and shard is None and res[0][1].size:
         planted = [p for p in d0.planted if len(p) == d0.order]
         if planted:
             planted_first = tuple(int(v) for v in res[0][1][0]["snp"][: d0.order]) == planted[0]
@@ -196,9 +215,11 @@ def main():
             "top_n": d0.top_n,
             "combinations": combos,
             "calls_per_step": len(batches),
+            "shard": None if shard is None else f"{shard[0]}/{shard[1]}",
         },
         "combinations_x_samples_per_s": combos_m / (ms / 1e3),
-        "arithmetic": "u64 bitsets, u32 popcount counts, f32 compensated MI, f64 rescoring of the kept",
+        "arithmetic": "u64 bitsets, u32 popcount counts, plain f32 MI estimate with a rigorous "
+                      "rounding bound for filtering, compensated f32 and f64 MI of the kept",
         "phases_ms": {k: round(prof[k], 4) for k in ("pack_ms", "scan_ms", "select_ms", "total_ms")},
         "candidates": prof["candidates"],
         "rescored": prof["kept"],
@@ -208,7 +229,7 @@ def main():
                      "achieved": achieved, "peak": peak, "unit": "T int32 lane-op/s",
                      "frac": achieved / peak, "traffic": None},
     }
-    if not args.no_cpu_baseline and len(datasets) == 1:
+    if not args.no_cpu_baseline and len(datasets) == 1 and shard is None:
         out["cpu_baseline"] = cpu_baseline(d0)
     print(json.dumps(out), flush=True)
 

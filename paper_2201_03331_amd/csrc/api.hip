@@ -191,6 +191,7 @@ struct JobLayout {
   size_t off_rows, off_F32, off_Fh, off_P64;
   std::vector<u64> row_start;
   u64 tiles;
+  uint32_t pilot_tiles;
   double cost;  // per-tile cost estimate, for ordering
 };
 
@@ -199,7 +200,7 @@ struct Layout {
   std::vector<uint32_t> order;  // tile-space order of the jobs (costliest first)
   uint32_t nmax, kmax, max_n_pad, max_cand_cap, max_l2_cap, max_pairs_n;
   size_t plan_begin, plan_end;  // uploaded region
-  size_t off_desc, off_jts, off_binom, off_counter;
+  size_t off_desc, off_jts, off_jps, off_binom, off_counter, off_pcounter;
   size_t total;
   int ksel;
 };
@@ -241,6 +242,14 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     if (J.shard_index >= J.shard_count)
       return fail(FIUNCHO_E_SHAPE, "shard_index must be below shard_count");
     J.tiles = shard_tiles(J.row_start.back(), J.shard_count, J.shard_index);
+    // pilot sample: 1/32 of the tiles, at most kPilotTiles, for jobs large
+    // enough that the search would otherwise start with a flood of
+    // candidates; its scores live in the candidate buffer until the scan
+    {
+      const u64 s = std::min<u64>(fiuncho::kPilotTiles, J.tiles / 32);
+      const u64 slots = s * fiuncho::kScanWaves * fiuncho::kPilotEmits * 64;
+      J.pilot_tiles = (s >= 16 && slots * sizeof(uint32_t) <= (u64)J.cand_cap * sizeof(Cand)) ? (uint32_t)s : 0;
+    }
     const double words = (double)J.wcap;
     J.cost = J.k == 1 ? 1.0
              : J.k == 2 ? words * 4 * fiuncho::kOrder2Prefixes
@@ -283,6 +292,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
   };
   L.off_desc = take(sizeof(JobDesc) * n_jobs);
   L.off_jts = take(sizeof(u64) * (n_jobs + 1));
+  L.off_jps = take(sizeof(u64) * (n_jobs + 1));
   L.off_binom = take(sizeof(u64) * ((size_t)L.nmax + 1) * fiuncho::kBinomStride);
   for (uint32_t i = 0; i < n_jobs; ++i) {
     JobLayout &J = L.jobs[i];
@@ -293,6 +303,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
   }
   L.plan_end = off;
   L.off_counter = take(sizeof(u64));
+  L.off_pcounter = take(sizeof(u64));
   L.total = off;
   // tile-space order: costliest tiles first, so that cheap ones fill the tail
   L.order.resize(n_jobs);
@@ -362,6 +373,13 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
     acc += L.jobs[i].tiles;
   }
   jts[n_jobs] = acc;
+  u64 *jps = reinterpret_cast<u64 *>(at(L.off_jps));
+  acc = 0;
+  for (uint32_t p = 0; p < n_jobs; ++p) {
+    jps[p] = acc;
+    acc += L.jobs[L.order[p]].pilot_tiles;
+  }
+  jps[n_jobs] = acc;
   JobDesc *desc = reinterpret_cast<JobDesc *>(at(L.off_desc));
   for (uint32_t p = 0; p < n_jobs; ++p) {
     const uint32_t i = L.order[p];
@@ -379,6 +397,7 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
     d.total = J.total;
     d.tile_begin = begin[i];
     d.tile_count = J.tiles;
+    d.pilot_tiles = J.pilot_tiles;
     d.G = host_inputs ? ws + J.off_G : jobs[i].genotypes;
     d.y = host_inputs ? ws + J.off_y : jobs[i].phenotype;
     d.idx = reinterpret_cast<uint32_t *>(ws + J.off_idx);
@@ -437,6 +456,11 @@ Globals make_globals(const Layout &L, uint8_t *ws) {
   g.total_tiles = 0;
   for (auto &J : L.jobs) g.total_tiles += J.tiles;
   g.tile_counter = reinterpret_cast<u64 *>(ws + L.off_counter);
+  g.job_pilot_start = reinterpret_cast<const u64 *>(ws + L.off_jps);
+  g.total_pilot_tiles = 0;
+  for (auto &J : L.jobs) g.total_pilot_tiles += J.pilot_tiles;
+  g.pilot_counter = reinterpret_cast<u64 *>(ws + L.off_pcounter);
+  g.pilot = 0;
   return g;
 }
 
@@ -538,7 +562,17 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   fiuncho::launch_pack(g, L.max_n_pad, s);
   if (L.max_pairs_n) fiuncho::launch_pairs(g, L.max_pairs_n, s);
   if ((st = prof_record(1, s))) return st;
-  int grid = fiuncho::scan_grid_size(L.ksel);
+  const int grid_max = fiuncho::scan_grid_size(L.ksel);
+  if (g.total_pilot_tiles) {
+    Globals gp = g;
+    gp.job_tile_start = g.job_pilot_start;
+    gp.total_tiles = g.total_pilot_tiles;
+    gp.tile_counter = g.pilot_counter;
+    gp.pilot = 1;
+    fiuncho::launch_scan(gp, L.ksel, (int)std::min<u64>((u64)grid_max, gp.total_tiles), s);
+    fiuncho::launch_pilot_select(g, s);
+  }
+  int grid = grid_max;
   if ((u64)grid > g.total_tiles) grid = (int)std::max<u64>(g.total_tiles, 1);
   fiuncho::launch_scan(g, L.ksel, grid, s);
   if ((st = prof_record(2, s))) return st;

@@ -20,6 +20,9 @@ constexpr uint32_t kSortMax = 8192;           // candidates ordered in one LDS s
 constexpr int kScanWaves = 4;                 // waves per workgroup in the scan
 constexpr int kOrder2Prefixes = 4;            // first variants per wave at order 2
 constexpr int kOrder3Prefixes = 2;            // prefixes per wave, order-3 pair path
+constexpr int kPilotEmits = 4;                // score batches a wave emits per tile, at most
+constexpr uint32_t kPilotTiles = 256;         // tiles of a job scored by the pilot pass
+static_assert(kOrder2Prefixes <= kPilotEmits && kOrder3Prefixes <= kPilotEmits, "pilot slots");
 
 // scan paths of a job
 constexpr uint32_t kPathGeneric = 0;          // rows g = 0, 1 of the last variant
@@ -95,6 +98,7 @@ struct JobDesc {
   uint32_t *pairs;            // kPathPairs: [n][n_pad][g_a 0..1][g_j 0..1][class] counts
   uint32_t shard_index;       // local tile = launch tile * shard_count + shard_index
   uint32_t shard_count;       // 1 = every tile
+  uint32_t pilot_tiles;       // tiles sampled by the pilot pass (0: none)
   // outputs
   fiuncho_hit *out;
   uint32_t *n_out;
@@ -109,6 +113,13 @@ struct Globals {
   const unsigned long long *job_tile_start;  // [n_jobs + 1]
   unsigned long long total_tiles;
   unsigned long long *tile_counter;
+  // pilot pass: an evenly spaced sample of every job's tiles is scored first
+  // and only its scores are kept (in the candidate buffer, as float bits), to
+  // start the search with a lower bound of the top_n-th best score
+  const unsigned long long *job_pilot_start;  // [n_jobs + 1]
+  unsigned long long total_pilot_tiles;
+  unsigned long long *pilot_counter;
+  uint32_t pilot;             // 1 in the pilot launch of scan_kernel
 };
 
 // launchers (kernels.hip)
@@ -117,6 +128,7 @@ void launch_pack(const Globals &g, uint32_t max_n_pad, hipStream_t s);
 void launch_pairs(const Globals &g, uint32_t max_n, hipStream_t s);
 void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s);
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
+void launch_pilot_select(const Globals &g, hipStream_t s);
 void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s);
 void launch_finish(const Globals &g, hipStream_t s);
 void launch_tables(const Globals &g, const unsigned long long *ranks, uint64_t n_ranks,

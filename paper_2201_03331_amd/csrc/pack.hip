@@ -9,12 +9,18 @@
 
 namespace fiuncho {
 
-// Clears every job's run state and survivor histogram, and the tile counter.
+// Clears every job's run state, survivor histogram and pilot score slots, and
+// the tile counters.
 // (A fill kernel rather than hipMemsetAsync, so that the sequence can be
 // captured into a graph and replayed.)
 __global__ void init_kernel(Globals g) {
   const JobDesc &J = g.jobs[blockIdx.x];
   for (uint32_t i = threadIdx.x; i < (uint32_t)kHistBins; i += blockDim.x) J.hist[i] = 0;
+  {
+    uint4 *pk = reinterpret_cast<uint4 *>(J.cand);
+    const uint32_t n4 = J.pilot_tiles * (kScanWaves * kPilotEmits * 64 / 4);
+    for (uint32_t i = threadIdx.x; i < n4; i += blockDim.x) pk[i] = make_uint4(0, 0, 0, 0);
+  }
   if (threadIdx.x == 0) {
     JobState *st = J.state;
     st->m0 = st->m1 = st->W0 = st->W1 = 0;
@@ -26,7 +32,10 @@ __global__ void init_kernel(Globals g) {
     st->l2_count = 0;
     st->kth_key = 0;
     st->flags = 0;
-    if (blockIdx.x == 0) *g.tile_counter = 0;
+    if (blockIdx.x == 0) {
+      *g.tile_counter = 0;
+      *g.pilot_counter = 0;
+    }
   }
 }
 

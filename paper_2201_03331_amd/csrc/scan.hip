@@ -42,6 +42,7 @@ struct JV {
   uint32_t path;
   const float *Fh;
   float fbound;
+  mutable uint32_t *pk;       // pilot launch: this wave's next 64 score slots
 };
 
 template <typename T>
@@ -70,6 +71,7 @@ __device__ __forceinline__ JV load_view(const JobDesc *jd) {
   v.path = uni(J->path);
   v.Fh = uni_ptr(J->Fh);
   v.fbound = __uint_as_float(uni(__float_as_uint(J->fbound)));
+  v.pk = nullptr;
   return v;
 }
 
@@ -125,6 +127,11 @@ __device__ __forceinline__ float current_threshold(const JV &v) {
 // Appends every active lane whose score clears the threshold.
 __device__ __forceinline__ void emit(const JV &v, bool active, float est, u64 rank, float thr,
                                      uint32_t lane) {
+  if (v.pk) {  // pilot: record the score only
+    v.pk[lane] = (active && est > 0.f) ? __float_as_uint(est) : 0u;
+    v.pk += 64;
+    return;
+  }
   const bool keep = active && est >= thr;
   const u64 mask = ballot(keep);
   if (mask == 0) return;
@@ -770,10 +777,15 @@ __global__ __launch_bounds__(kScanWaves * 64, scan_min_waves(KSEL)) void scan_ke
       if (v.m0 == 0 || v.m1 == 0) continue;
     }
     const FI_CONST JobDesc *jd = as_const(g.jobs) + lo;
-    // local tile: the job's li-th tile, or with shards the shard's li-th
-    // tile, dealt from block li of shard_count consecutive tiles at offset
-    // (shard_index + li) mod shard_count
-    u64 lt = t - uni64(jd->tile_begin);
+    u64 lt = uni64(t - jts[lo]);
+    if (g.pilot) {
+      // pilot tile i of S stands for tile floor(i T / S) of the job's T
+      v.pk = reinterpret_cast<uint32_t *>(v.cand) + (lt * kScanWaves + wave) * (kPilotEmits * 64);
+      lt = uni64(lt * uni64(jd->tile_count) / uni(jd->pilot_tiles));
+    }
+    // local tile: the job's lt-th tile, or with shards the shard's lt-th
+    // tile, dealt from block lt of shard_count consecutive tiles at offset
+    // (shard_index + lt) mod shard_count
     {
       const uint32_t sc = uni(jd->shard_count);
       if (sc > 1) lt = uni64(lt * sc + (uni(jd->shard_index) + lt % sc) % sc);

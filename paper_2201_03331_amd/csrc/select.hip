@@ -59,16 +59,73 @@ __global__ __launch_bounds__(256) void compact_kernel(Globals g) {
   }
 }
 
+// Radix selection (12 + 12 + 7 bits of a non-negative float's bits) of the
+// N-th largest of M > N keys, key(i) for i in [0, M), by one workgroup.
+struct RadixLds {
+  uint32_t hist[4096];
+  uint32_t prefix, need;
+};
+
+template <typename KeyAt>
+__device__ uint32_t radix_kth_largest(KeyAt key_at, uint32_t M, uint32_t N, RadixLds &s) {
+  const uint32_t tid = threadIdx.x;
+  if (tid == 0) {
+    s.prefix = 0;
+    s.need = N;  // rank (1-based, from the top) still to locate
+  }
+  const int shifts[3] = {19, 7, 0};
+  const int widths[3] = {12, 12, 7};
+  uint32_t known_mask = 0;
+  for (int pass = 0; pass < 3; ++pass) {
+    for (uint32_t i = tid; i < 4096; i += blockDim.x) s.hist[i] = 0;
+    __syncthreads();
+    const uint32_t prefix = s.prefix;
+    const uint32_t bins = 1u << widths[pass];
+    for (uint32_t i = tid; i < M; i += blockDim.x) {
+      const uint32_t key = key_at(i);
+      if ((key & known_mask) == prefix) atomicAdd(&s.hist[(key >> shifts[pass]) & (bins - 1)], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t need = s.need, run = 0;
+      int bin = (int)bins - 1;
+      for (; bin > 0; --bin) {
+        if (run + s.hist[bin] >= need) break;
+        run += s.hist[bin];
+      }
+      s.need = need - run;
+      s.prefix = prefix | ((uint32_t)bin << shifts[pass]);
+    }
+    known_mask |= (bins - 1) << shifts[pass];
+    __syncthreads();
+  }
+  return s.prefix;
+}
+
+// 0. pilot: one workgroup per job; the top_n-th largest score of the pilot
+// sample is at most the top_n-th largest score of the whole job, so it is a
+// valid starting bound for the scan's filter.
+__global__ __launch_bounds__(1024) void pilot_select_kernel(Globals g) {
+  const JobDesc &J = g.jobs[blockIdx.x];
+  JobState *st = J.state;
+  if (J.pilot_tiles == 0 || st->status != 0 || st->m0 == 0 || st->m1 == 0) return;
+  __shared__ RadixLds s;
+  const uint32_t *keys = reinterpret_cast<const uint32_t *>(J.cand);
+  const uint32_t M = J.pilot_tiles * (kScanWaves * kPilotEmits * 64);
+  if (M <= J.top_n) return;
+  const uint32_t kth = radix_kth_largest([&](uint32_t i) { return keys[i]; }, M, J.top_n, s);
+  if (threadIdx.x == 0 && kth != 0) atomicMax(&st->tau_key, kth);
+}
+
 // 2. one workgroup per job: radix selection of the top_n-th largest key over
-// the compacted candidates (12 + 12 + 7 bits of a non-negative float), then
-// the final candidate set.
+// the compacted candidates, then the final candidate set.
 __global__ __launch_bounds__(1024) void select_kernel(Globals g) {
   const JobDesc &J = g.jobs[blockIdx.x];
   JobState *st = J.state;
   if (st->status != 0 || st->m0 == 0 || st->m1 == 0) return;
   if (st->flags & kFlagCandOverflow) return;
-  __shared__ uint32_t hist[4096];
-  __shared__ uint32_t s_prefix, s_need, s_count;
+  __shared__ RadixLds s;
+  __shared__ uint32_t s_count;
   const uint32_t tid = threadIdx.x;
   const uint32_t M = min(st->l1_count, J.l1_cap);
   const uint32_t N = J.top_n;
@@ -76,37 +133,7 @@ __global__ __launch_bounds__(1024) void select_kernel(Globals g) {
   if (M <= N) {
     thr2 = -INFINITY;  // every candidate is kept
   } else {
-    if (tid == 0) {
-      s_prefix = 0;
-      s_need = N;  // rank (1-based, from the top) still to locate
-    }
-    const int shifts[3] = {19, 7, 0};
-    const int widths[3] = {12, 12, 7};
-    uint32_t known_mask = 0;
-    for (int pass = 0; pass < 3; ++pass) {
-      for (uint32_t i = tid; i < 4096; i += blockDim.x) hist[i] = 0;
-      __syncthreads();
-      const uint32_t prefix = s_prefix;
-      const uint32_t bins = 1u << widths[pass];
-      for (uint32_t i = tid; i < M; i += blockDim.x) {
-        const uint32_t key = J.l1[i].key;
-        if ((key & known_mask) == prefix) atomicAdd(&hist[(key >> shifts[pass]) & (bins - 1)], 1u);
-      }
-      __syncthreads();
-      if (tid == 0) {
-        uint32_t need = s_need, run = 0;
-        int bin = (int)bins - 1;
-        for (; bin > 0; --bin) {
-          if (run + hist[bin] >= need) break;
-          run += hist[bin];
-        }
-        s_need = need - run;
-        s_prefix = prefix | ((uint32_t)bin << shifts[pass]);
-      }
-      known_mask |= (bins - 1) << shifts[pass];
-      __syncthreads();
-    }
-    const uint32_t kth = s_prefix;
+    const uint32_t kth = radix_kth_largest([&](uint32_t i) { return J.l1[i].key; }, M, N, s);
     if (tid == 0) st->kth_key = kth;
     thr2 = tol_threshold(J, __uint_as_float(kth));
   }
@@ -385,6 +412,10 @@ void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s) {
   if (blocks == 0) blocks = 1;
   hipLaunchKernelGGL(compact_kernel, dim3(blocks, g.n_jobs), dim3(256), 0, s, g);
   hipLaunchKernelGGL(select_kernel, dim3(g.n_jobs), dim3(1024), 0, s, g);
+}
+
+void launch_pilot_select(const Globals &g, hipStream_t s) {
+  hipLaunchKernelGGL(pilot_select_kernel, dim3(g.n_jobs), dim3(1024), 0, s, g);
 }
 
 void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s) {
