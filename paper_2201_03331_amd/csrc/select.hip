@@ -60,15 +60,20 @@ __global__ __launch_bounds__(256) void compact_kernel(Globals g) {
 }
 
 // Radix selection (12 + 12 + 7 bits of a non-negative float's bits) of the
-// N-th largest of M > N keys, key(i) for i in [0, M), by one workgroup.
+// N-th largest of M > N keys, key(i) for i in [0, M), by one workgroup of
+// 1024 threads.  Each pass histograms the keys that match the digits found so
+// far, then locates the bin holding the N-th largest with a parallel scan of
+// the bin counts from the top.
+constexpr uint32_t kRadixThreads = 1024;
 struct RadixLds {
   uint32_t hist[4096];
+  uint32_t wsum[kRadixThreads / 64];
   uint32_t prefix, need;
 };
 
 template <typename KeyAt>
 __device__ uint32_t radix_kth_largest(KeyAt key_at, uint32_t M, uint32_t N, RadixLds &s) {
-  const uint32_t tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (tid == 0) {
     s.prefix = 0;
     s.need = N;  // rank (1-based, from the top) still to locate
@@ -77,24 +82,45 @@ __device__ uint32_t radix_kth_largest(KeyAt key_at, uint32_t M, uint32_t N, Radi
   const int widths[3] = {12, 12, 7};
   uint32_t known_mask = 0;
   for (int pass = 0; pass < 3; ++pass) {
-    for (uint32_t i = tid; i < 4096; i += blockDim.x) s.hist[i] = 0;
+    for (uint32_t i = tid; i < 4096; i += kRadixThreads) s.hist[i] = 0;
     __syncthreads();
-    const uint32_t prefix = s.prefix;
+    const uint32_t prefix = s.prefix, need = s.need;
     const uint32_t bins = 1u << widths[pass];
-    for (uint32_t i = tid; i < M; i += blockDim.x) {
+    for (uint32_t i = tid; i < M; i += kRadixThreads) {
       const uint32_t key = key_at(i);
       if ((key & known_mask) == prefix) atomicAdd(&s.hist[(key >> shifts[pass]) & (bins - 1)], 1u);
     }
     __syncthreads();
-    if (tid == 0) {
-      uint32_t need = s.need, run = 0;
-      int bin = (int)bins - 1;
-      for (; bin > 0; --bin) {
-        if (run + s.hist[bin] >= need) break;
+    // thread t owns `per` consecutive bins counted from the top
+    const uint32_t per = (bins + kRadixThreads - 1) / kRadixThreads;
+    const uint32_t top = bins - 1 - tid * per;  // highest bin of this thread
+    uint32_t mine = 0;
+    for (uint32_t q = 0; q < per; ++q)
+      if (tid * per + q < bins) mine += s.hist[top - q];
+    // inclusive scan over threads (from the top)
+    uint32_t inc = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t o = __shfl_up(inc, off);
+      if (lane >= (uint32_t)off) inc += o;
+    }
+    if (lane == 63) s.wsum[wv] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t q = 0; q < wv; ++q) before += s.wsum[q];
+    const uint32_t excl = before + inc - mine;
+    // the thread whose range of the running count crosses `need`; bin 0 takes
+    // whatever is left (it is the lowest possible digit)
+    if (tid * per < bins && excl < need && (excl + mine >= need || tid * per + per >= bins)) {
+      uint32_t run = excl;
+      uint32_t bin = top;
+      for (uint32_t q = 0; q < per && tid * per + q < bins; ++q) {
+        bin = top - q;
+        if (run + s.hist[bin] >= need || bin == 0) break;
         run += s.hist[bin];
       }
       s.need = need - run;
-      s.prefix = prefix | ((uint32_t)bin << shifts[pass]);
+      s.prefix = prefix | (bin << shifts[pass]);
     }
     known_mask |= (bins - 1) << shifts[pass];
     __syncthreads();
@@ -170,23 +196,23 @@ __device__ void count_cells(const JobDesc &J, const JobState *st, const uint32_t
   uint32_t cells = 1;
   for (uint32_t i = 0; i < k; ++i) cells *= 3;
   const uint32_t W0 = st->W0, W = st->W0 + st->W1, wcap = J.wcap;
-  for (uint32_t x0 = 0; x0 < cells; x0 += 64) {
-    const uint32_t x = x0 + lane;
-    const bool on = x < cells;
-    const u64 *rows[kMaxOrder];
-    uint32_t rem = on ? x : 0;
-    for (int i = (int)k - 1; i >= 0; --i) {
-      rows[i] = J.Bs + (size_t)c[i] * 4 * wcap + rem % 3;
-      rem /= 3;
-    }
+  // cell x = sum_i g_i 3^(k-1-i): lanes split the words, a wave sum per class
+  uint32_t g[kMaxOrder];
+  for (uint32_t i = 0; i < k; ++i) g[i] = 0;
+  for (uint32_t x = 0; x < cells; ++x) {
     uint32_t n0 = 0, n1 = 0;
-    for (uint32_t w = 0; w < W; ++w) {
+    for (uint32_t w = lane; w < W; w += 64) {
       u64 r = ~0ull;
-      for (uint32_t i = 0; i < k; ++i) r &= rows[i][(size_t)w * 4];
+      for (uint32_t i = 0; i < k; ++i) r &= J.Bs[((size_t)c[i] * wcap + w) * 4 + g[i]];
       if (w < W0) n0 += popc64(r);
       else n1 += popc64(r);
     }
-    if (on) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      n0 += __shfl_xor(n0, off);
+      n1 += __shfl_xor(n1, off);
+    }
+    if (lane == 0) {
       if (lds_t) {
         lds_t[2 * x] = n0;
         lds_t[2 * x + 1] = n1;
@@ -195,6 +221,11 @@ __device__ void count_cells(const JobDesc &J, const JobState *st, const uint32_t
         table_out[2 * x] = n0;
         table_out[2 * x + 1] = n1;
       }
+    }
+    // next cell: increment the base-3 digits, last variant fastest
+    for (int i = (int)k - 1; i >= 0; --i) {
+      if (++g[i] < 3) break;
+      g[i] = 0;
     }
   }
 }
