@@ -104,6 +104,15 @@ void build_rows(uint32_t n, uint32_t k, uint32_t path, std::vector<u64> &row_sta
     }
     return;
   }
+  if (path == fiuncho::kPathMfma2) {
+    // rows A of the upper triangle of 64-variant blocks: tiles (A, B >= A)
+    const u64 nb = ceil_div(n, 64);
+    for (u64 A = 0; A < nb; ++A) {
+      acc += nb - A;
+      row_start.push_back(acc);
+    }
+    return;
+  }
   if (path == fiuncho::kPathPairs) {
     // rows b = 1 .. n-2; groups of kScanWaves * kOrder3Prefixes first variants
     for (u64 b = 1; b + 2 <= n; ++b) {
@@ -131,6 +140,19 @@ void for_each_tile(uint32_t n, uint32_t k, uint32_t path, Fn fn) {
     return;
   }
   u64 lt = 0;
+  if (k == 2 && path == fiuncho::kPathMfma2) {
+    for (u64 A = 0; A * 64 < N; ++A)
+      for (u64 B = A; B * 64 < N; ++B) {
+        u64 c = 0;
+        const u64 j_end = std::min<u64>(64 * B + 64, N);
+        for (u64 a = 64 * A; a < std::min<u64>(64 * A + 64, N); ++a) {
+          const u64 lo = std::max<u64>(64 * B, a + 1);
+          if (lo < j_end) c += j_end - lo;
+        }
+        fn(lt++, c);
+      }
+    return;
+  }
   if (k == 2) {
     const u64 S = (u64)fiuncho::kScanWaves * fiuncho::kOrder2Prefixes;
     for (u64 a_first = 0; a_first + 1 < N; a_first += S) {
@@ -175,7 +197,10 @@ u64 shard_tiles(u64 tiles, u64 count, u64 s) {
 uint32_t job_path(uint32_t n, uint32_t k) {
   const char *env_pairs = std::getenv("FIUNCHO_ORDER3_PAIRS");
   const bool use_pairs = !(env_pairs && env_pairs[0] == '0');
-  return (k == 3 && n >= 3 && use_pairs) ? fiuncho::kPathPairs : fiuncho::kPathGeneric;
+  if (k == 3 && n >= 3 && use_pairs) return fiuncho::kPathPairs;
+  const char *env_mfma = std::getenv("FIUNCHO_ORDER2_MFMA");
+  if (k == 2 && env_mfma && env_mfma[0] == '1') return fiuncho::kPathMfma2;
+  return fiuncho::kPathGeneric;
 }
 
 // ---------------------------------------------------------------------------
@@ -191,7 +216,7 @@ struct JobLayout {
   size_t off_rows, off_F32, off_Fh, off_P64;
   std::vector<u64> row_start;
   u64 tiles;
-  uint32_t pilot_tiles;
+  uint32_t pilot_tiles, pilot_slots;
   double cost;  // per-tile cost estimate, for ordering
 };
 
@@ -200,7 +225,8 @@ struct Layout {
   std::vector<uint32_t> order;  // tile-space order of the jobs (costliest first)
   uint32_t nmax, kmax, max_n_pad, max_cand_cap, max_l2_cap, max_pairs_n;
   size_t plan_begin, plan_end;  // uploaded region
-  size_t off_desc, off_jts, off_jps, off_binom, off_counter, off_pcounter;
+  size_t off_desc, off_jts, off_jps, off_binom, off_counter;
+  uint32_t n_scan;  // jobs [0, n_scan) of the tile-space order run in scan_kernel, the rest in mfma2_kernel
   size_t total;
   int ksel;
 };
@@ -247,11 +273,15 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     // candidates; its scores live in the candidate buffer until the scan
     {
       const u64 s = std::min<u64>(fiuncho::kPilotTiles, J.tiles / 32);
-      const u64 slots = s * fiuncho::kScanWaves * fiuncho::kPilotEmits * 64;
-      J.pilot_tiles = (s >= 16 && slots * sizeof(uint32_t) <= (u64)J.cand_cap * sizeof(Cand)) ? (uint32_t)s : 0;
+      const u64 per = J.path == fiuncho::kPathMfma2 ? fiuncho::kMfmaPilotEmits : fiuncho::kPilotEmits;
+      const u64 slots = s * fiuncho::kScanWaves * per * 64;
+      const bool fits = slots * sizeof(uint32_t) <= (u64)J.cand_cap * sizeof(Cand);
+      J.pilot_tiles = (s >= 16 && fits) ? (uint32_t)s : 0;
+      J.pilot_slots = J.pilot_tiles ? (uint32_t)slots : 0;
     }
     const double words = (double)J.wcap;
     J.cost = J.k == 1 ? 1.0
+             : J.path == fiuncho::kPathMfma2 ? words * 4 * 64
              : J.k == 2 ? words * 4 * fiuncho::kOrder2Prefixes
              : J.path == fiuncho::kPathPairs ? words * 8 * fiuncho::kOrder3Prefixes
                                              : words * 18 * std::pow(3.0, (double)J.k - 3);
@@ -302,23 +332,30 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     J.off_P64 = take(sizeof(double) * ((size_t)J.m + 1));
   }
   L.plan_end = off;
-  L.off_counter = take(sizeof(u64));
-  L.off_pcounter = take(sizeof(u64));
+  L.off_counter = take(sizeof(u64) * fiuncho::kTileCounters);
   L.total = off;
   // tile-space order: costliest tiles first, so that cheap ones fill the tail
   L.order.resize(n_jobs);
   for (uint32_t i = 0; i < n_jobs; ++i) L.order[i] = i;
   std::stable_sort(L.order.begin(), L.order.end(),
                    [&](uint32_t a, uint32_t b) { return L.jobs[a].cost > L.jobs[b].cost; });
+  // jobs on the matrix-core path go last: they run in their own launch
+  std::stable_partition(L.order.begin(), L.order.end(),
+                        [&](uint32_t a) { return L.jobs[a].path != fiuncho::kPathMfma2; });
+  L.n_scan = 0;
+  for (auto &J : L.jobs) L.n_scan += J.path != fiuncho::kPathMfma2;
   auto sel = [](const JobLayout &J) {
     return J.path == fiuncho::kPathPairs ? fiuncho::kSelPairs : (J.k <= 5 ? (int)J.k : 0);
   };
-  L.ksel = sel(L.jobs[0]);
+  L.ksel = -1;
   bool only23 = true;
   for (auto &J : L.jobs) {
-    if (sel(J) != L.ksel) L.ksel = 0;
+    if (J.path == fiuncho::kPathMfma2) continue;
+    if (L.ksel < 0) L.ksel = sel(J);
+    else if (sel(J) != L.ksel) L.ksel = 0;
     only23 = only23 && (J.k == 2 || J.path == fiuncho::kPathPairs);
   }
+  if (L.ksel < 0) L.ksel = 0;
   if (L.ksel == 0 && only23) L.ksel = fiuncho::kSel23;
   return FIUNCHO_OK;
 }
@@ -398,6 +435,7 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
     d.tile_begin = begin[i];
     d.tile_count = J.tiles;
     d.pilot_tiles = J.pilot_tiles;
+    d.pilot_slots = J.pilot_slots;
     d.G = host_inputs ? ws + J.off_G : jobs[i].genotypes;
     d.y = host_inputs ? ws + J.off_y : jobs[i].phenotype;
     d.idx = reinterpret_cast<uint32_t *>(ws + J.off_idx);
@@ -455,13 +493,29 @@ Globals make_globals(const Layout &L, uint8_t *ws) {
   g.job_tile_start = reinterpret_cast<const u64 *>(ws + L.off_jts);
   g.total_tiles = 0;
   for (auto &J : L.jobs) g.total_tiles += J.tiles;
-  g.tile_counter = reinterpret_cast<u64 *>(ws + L.off_counter);
+  g.tile_base = 0;
+  g.tile_counter = reinterpret_cast<u64 *>(ws + L.off_counter);  // kTileCounters of them
   g.job_pilot_start = reinterpret_cast<const u64 *>(ws + L.off_jps);
   g.total_pilot_tiles = 0;
   for (auto &J : L.jobs) g.total_pilot_tiles += J.pilot_tiles;
-  g.pilot_counter = reinterpret_cast<u64 *>(ws + L.off_pcounter);
   g.pilot = 0;
   return g;
+}
+
+// The globals of one counting launch over jobs [first, first + count) of the
+// tile-space order; `pilot` selects the pilot tiles.  tiles[] = the host's
+// copy of the job tile (or pilot) starts.
+Globals launch_globals(const Globals &g, const std::vector<u64> &starts, uint32_t first,
+                       uint32_t count, bool pilot, int counter) {
+  Globals r = g;
+  r.jobs = g.jobs + first;
+  r.n_jobs = count;
+  r.job_tile_start = (pilot ? g.job_pilot_start : g.job_tile_start) + first;
+  r.tile_base = starts[first];
+  r.total_tiles = starts[first + count];
+  r.tile_counter = g.tile_counter + counter;
+  r.pilot = pilot ? 1u : 0u;
+  return r;
 }
 
 int upload_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host_inputs,
@@ -562,19 +616,29 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   fiuncho::launch_pack(g, L.max_n_pad, s);
   if (L.max_pairs_n) fiuncho::launch_pairs(g, L.max_pairs_n, s);
   if ((st = prof_record(1, s))) return st;
-  const int grid_max = fiuncho::scan_grid_size(L.ksel);
+  // job tile and pilot starts in tile-space order (as uploaded)
+  const uint32_t nj = (uint32_t)L.jobs.size();
+  std::vector<u64> ts(nj + 1, 0), ps(nj + 1, 0);
+  for (uint32_t p = 0; p < nj; ++p) {
+    ts[p + 1] = ts[p] + L.jobs[L.order[p]].tiles;
+    ps[p + 1] = ps[p] + L.jobs[L.order[p]].pilot_tiles;
+  }
+  const uint32_t ns = L.n_scan, nm = nj - L.n_scan;
+  auto counting = [&](const Globals &c, bool mfma) {
+    if (c.total_tiles <= c.tile_base) return;
+    const u64 tiles = c.total_tiles - c.tile_base;
+    const int gmax = mfma ? fiuncho::mfma2_grid_size() : fiuncho::scan_grid_size(L.ksel);
+    const int grid = (int)std::min<u64>((u64)gmax, tiles);
+    if (mfma) fiuncho::launch_mfma2(c, grid, s);
+    else fiuncho::launch_scan(c, L.ksel, grid, s);
+  };
   if (g.total_pilot_tiles) {
-    Globals gp = g;
-    gp.job_tile_start = g.job_pilot_start;
-    gp.total_tiles = g.total_pilot_tiles;
-    gp.tile_counter = g.pilot_counter;
-    gp.pilot = 1;
-    fiuncho::launch_scan(gp, L.ksel, (int)std::min<u64>((u64)grid_max, gp.total_tiles), s);
+    if (ns) counting(launch_globals(g, ps, 0, ns, true, 1), false);
+    if (nm) counting(launch_globals(g, ps, ns, nm, true, 3), true);
     fiuncho::launch_pilot_select(g, s);
   }
-  int grid = grid_max;
-  if ((u64)grid > g.total_tiles) grid = (int)std::max<u64>(g.total_tiles, 1);
-  fiuncho::launch_scan(g, L.ksel, grid, s);
+  if (ns) counting(launch_globals(g, ts, 0, ns, false, 0), false);
+  if (nm) counting(launch_globals(g, ts, ns, nm, false, 2), true);
   if ((st = prof_record(2, s))) return st;
   fiuncho::launch_select(g, L.max_cand_cap, s);
   fiuncho::launch_rescore(g, L.max_l2_cap, L.kmax, s);

@@ -21,6 +21,7 @@ constexpr int kScanWaves = 4;                 // waves per workgroup in the scan
 constexpr int kOrder2Prefixes = 4;            // first variants per wave at order 2
 constexpr int kOrder3Prefixes = 2;            // prefixes per wave, order-3 pair path
 constexpr int kPilotEmits = 4;                // score batches a wave emits per tile, at most
+constexpr int kMfmaPilotEmits = 16;           // the same for the order-2 matrix-core kernel
 constexpr uint32_t kPilotTiles = 256;         // tiles of a job scored by the pilot pass
 static_assert(kOrder2Prefixes <= kPilotEmits && kOrder3Prefixes <= kPilotEmits, "pilot slots");
 
@@ -29,6 +30,8 @@ constexpr uint32_t kPathGeneric = 0;          // rows g = 0, 1 of the last varia
 constexpr uint32_t kPathPairs = 1;            // order 3, {0,1}^3 cells + pair tables
 constexpr int kSelPairs = 31;                 // scan_kernel selector: order-3 pair path only
 constexpr int kSel23 = 23;                    // scan_kernel selector: orders 2 and 3 (pair path)
+constexpr int kTileCounters = 4;              // scan, scan pilot, mfma2, mfma2 pilot
+constexpr uint32_t kPathMfma2 = 2;            // order 2 on the matrix cores (mfma2_kernel)
 
 // state the device writes during one run of a job (cleared at the start)
 struct JobState {
@@ -99,6 +102,7 @@ struct JobDesc {
   uint32_t shard_index;       // local tile = launch tile * shard_count + shard_index
   uint32_t shard_count;       // 1 = every tile
   uint32_t pilot_tiles;       // tiles sampled by the pilot pass (0: none)
+  uint32_t pilot_slots;       // score slots of the pilot pass (at the start of cand)
   // outputs
   fiuncho_hit *out;
   uint32_t *n_out;
@@ -111,14 +115,14 @@ struct Globals {
   uint32_t n_jobs;
   const JobDesc *jobs;
   const unsigned long long *job_tile_start;  // [n_jobs + 1]
-  unsigned long long total_tiles;
+  unsigned long long tile_base;    // first global tile of this launch
+  unsigned long long total_tiles;  // end of this launch's global tiles
   unsigned long long *tile_counter;
   // pilot pass: an evenly spaced sample of every job's tiles is scored first
   // and only its scores are kept (in the candidate buffer, as float bits), to
   // start the search with a lower bound of the top_n-th best score
   const unsigned long long *job_pilot_start;  // [n_jobs + 1]
   unsigned long long total_pilot_tiles;
-  unsigned long long *pilot_counter;
   uint32_t pilot;             // 1 in the pilot launch of scan_kernel
 };
 
@@ -127,6 +131,8 @@ void launch_init(const Globals &g, hipStream_t s);
 void launch_pack(const Globals &g, uint32_t max_n_pad, hipStream_t s);
 void launch_pairs(const Globals &g, uint32_t max_n, hipStream_t s);
 void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s);
+void launch_mfma2(const Globals &g, int grid, hipStream_t s);
+int mfma2_grid_size();
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
 void launch_pilot_select(const Globals &g, hipStream_t s);
 void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s);

@@ -1,0 +1,207 @@
+// mfma2.hip -- order 2 on the matrix cores.
+//
+// For a pair (a, j) the scan needs the four cells g_a, g_j in {0, 1} per class
+// (the cells with a 2 follow from the class counts, section 3.2).  Written
+// with one-hot rows X[(v, g)][s] = 1 iff sample s of the class has genotype g
+// at variant v, those cells are the entries of the Gram matrix X X^T: an
+// exact 0/1 contraction over the samples of the class, with int32
+// accumulation (counts stay below 2^24).  Here it runs on the int8 matrix
+// instruction v_mfma_i32_32x32x32_i8: rows 2v + g of a fragment are the two
+// genotype rows of 16 consecutive variants, so one 32 x 32 block holds every
+// {0,1} x {0,1} cell of 16 x 16 pairs.
+//
+// A workgroup owns 64 first variants x 64 last variants (tile of the upper
+// triangle of 64-variant blocks); each of its 4 waves owns 32 x 32 of them
+// (2 x 2 blocks) and accumulates both classes (class 0 words, then class 1
+// words).  Operands are not stored as bytes: each lane reads the 64-bit word
+// of its row from the packed bitsets and expands the 16 samples it feeds to
+// 16 bytes in registers, so the cache traffic is that of the bitsets.
+#include "filter.hpp"
+
+namespace fiuncho {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kMfmaWaves = 4;
+static_assert(kMfmaWaves == kScanWaves, "pilot slots and tile decoding assume equal waves per tile");
+
+// 16 sample bits -> 16 bytes 0/1, byte i = bit i: a nibble times
+// 1 + 2^7 + 2^14 + 2^21 puts bit b at bit 8b (no carries), then a mask.
+__device__ __forceinline__ v4i expand16(uint32_t b) {
+  v4i r;
+  r[0] = (int)(((b & 0xFu) * 0x00204081u) & 0x01010101u);
+  r[1] = (int)((((b >> 4) & 0xFu) * 0x00204081u) & 0x01010101u);
+  r[2] = (int)((((b >> 8) & 0xFu) * 0x00204081u) & 0x01010101u);
+  r[3] = (int)((((b >> 12) & 0xFu) * 0x00204081u) & 0x01010101u);
+  return r;
+}
+
+// Counts of one class: words [wbeg, wend) of the bitsets.  Lane l feeds row
+// r = l mod 32 of every fragment (variant base + r / 2, genotype r mod 2) and
+// the 16 samples [16 (l / 32), 16 (l / 32) + 16) of each 32-sample step; the
+// matrix instruction pairs the same lane half and byte of both operands, so
+// any fixed sample order inside a lane is exact.
+__device__ __forceinline__ void mfma_class(const FI_GLOBAL u64 *pa, const FI_GLOBAL u64 *pj,
+                                           size_t word_stride, uint32_t wbeg, uint32_t wend,
+                                           uint32_t h, v16i (&acc)[2][2]) {
+  if (wbeg >= wend) return;
+  u64 xa0 = pa[wbeg * word_stride], xa1 = pa[wbeg * word_stride + 32];
+  u64 xj0 = pj[wbeg * word_stride], xj1 = pj[wbeg * word_stride + 32];
+  for (uint32_t w = wbeg; w < wend; ++w) {
+    const u64 ca0 = xa0, ca1 = xa1, cj0 = xj0, cj1 = xj1;
+    const uint32_t wn = w + 1 < wend ? w + 1 : w;
+    xa0 = pa[wn * word_stride];
+    xa1 = pa[wn * word_stride + 32];
+    xj0 = pj[wn * word_stride];
+    xj1 = pj[wn * word_stride + 32];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const uint32_t sh = 32 * s + 16 * h;
+      const v4i A0 = expand16((uint32_t)(ca0 >> sh) & 0xFFFFu);
+      const v4i A1 = expand16((uint32_t)(ca1 >> sh) & 0xFFFFu);
+      const v4i J0 = expand16((uint32_t)(cj0 >> sh) & 0xFFFFu);
+      const v4i J1 = expand16((uint32_t)(cj1 >> sh) & 0xFFFFu);
+      acc[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, J0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, J1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, J0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, J1, acc[1][1], 0, 0, 0);
+    }
+  }
+}
+
+// One wave: pairs (a0 + [0, 32)) x (j0 + [0, 32)).
+__device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0, uint32_t lane) {
+  const uint32_t n = v.n;
+  const uint32_t r = lane & 31, h = lane >> 5;
+  const size_t word_stride = (size_t)v.n_pad * 2;
+  const FI_GLOBAL u64 *Bv = as_global(v.Bv);
+  const FI_GLOBAL u64 *pa = Bv + (size_t)a0 * 2 + r;
+  const FI_GLOBAL u64 *pj = Bv + (size_t)j0 * 2 + r;
+  v16i acc0[2][2], acc1[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc0[x][y][e] = acc1[x][y][e] = 0;
+  mfma_class(pa, pj, word_stride, 0, v.W0, h, acc0);
+  mfma_class(pa, pj, word_stride, v.W0, v.W0 + v.W1, h, acc1);
+
+  // Output block layout: lane l holds column l mod 32 (variant j0' + (l mod
+  // 32) / 2, genotype l mod 2); register e holds row 8 (e / 4) + 4 h + e mod 4
+  // (variant a0' + 4 (e / 4) + 2 h + (e mod 4) / 2, genotype e mod 2).  Lanes
+  // l and l ^ 1 hold the two genotypes of the same j; each scores the pairs
+  // whose a-offset (e mod 4) / 2 equals its own genotype bit, after taking the
+  // partner's counts for the other genotype of j.
+  const uint32_t gl = lane & 1;
+  const float thr = current_threshold(v);
+  const MiConst mc = mi_const(v);
+  const FI_GLOBAL float *F = as_global(v.Fh);
+  const FI_GLOBAL uint32_t *marg = as_global(v.marg);
+  const uint32_t mcls[2] = {v.m0, v.m1};
+#pragma unroll
+  for (int fb = 0; fb < 2; ++fb) {
+    const uint32_t j = j0 + 16 * fb + (r >> 1);
+    const uint32_t jj = j < n ? j : n - 1;
+    uint32_t Mj[2][2];
+#pragma unroll
+    for (int gg = 0; gg < 2; ++gg)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) Mj[gg][c] = marg[(size_t)jj * 6 + 2 * gg + c];
+#pragma unroll
+    for (int fa = 0; fa < 2; ++fa) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t a = a0 + 16 * fa + 4 * q + 2 * h + gl;
+        uint32_t cnt[2][2][2];  // [g_a][g_j][class]
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const v16i &A = c == 0 ? acc0[fa][fb] : acc1[fa][fb];
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            const uint32_t lo = (uint32_t)A[4 * q + t], hi = (uint32_t)A[4 * q + 2 + t];
+            const uint32_t own = gl ? hi : lo;
+            const uint32_t send = gl ? lo : hi;
+            const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
+            cnt[t][gl][c] = own;
+            cnt[t][gl ^ 1][c] = recv;
+          }
+        }
+        const bool active = a < j && j < n;
+        const uint32_t aa = a < n ? a : n - 1;
+        uint32_t t9[9][2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const uint32_t Ma0 = marg[(size_t)aa * 6 + c], Ma1 = marg[(size_t)aa * 6 + 2 + c];
+          t9[0][c] = cnt[0][0][c];
+          t9[1][c] = cnt[0][1][c];
+          t9[2][c] = Ma0 - cnt[0][0][c] - cnt[0][1][c];
+          t9[3][c] = cnt[1][0][c];
+          t9[4][c] = cnt[1][1][c];
+          t9[5][c] = Ma1 - cnt[1][0][c] - cnt[1][1][c];
+          t9[6][c] = Mj[0][c] - cnt[0][0][c] - cnt[1][0][c];
+          t9[7][c] = Mj[1][c] - cnt[0][1][c] - cnt[1][1][c];
+          t9[8][c] = mcls[c] - Ma0 - Ma1 - Mj[0][c] - Mj[1][c] + cnt[0][0][c] + cnt[0][1][c] +
+                     cnt[1][0][c] + cnt[1][1][c];
+          // every count is at most the class size; the clamp keeps the table
+          // lookups inside [0, m] whatever the counts hold
+#pragma unroll
+          for (int x = 0; x < 9; ++x) t9[x][c] = active ? min(t9[x][c], mcls[c]) : 0u;
+        }
+        // lexicographic rank of (a, j): sum over a' < a of (n - 1 - a'), plus j - a - 1
+        const u64 rank = active ? (u64)a * (n - 1) - (u64)a * (a - 1) / 2 + (j - a - 1) : 0;
+        score_table<9>(v, F, t9, active, thr, mc, rank, lane);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma2_kernel(Globals g) {
+  __shared__ u64 s_tile;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = uni(threadIdx.x >> 6);
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = g.tile_base + atomicAdd(g.tile_counter, 1ull);
+    __syncthreads();
+    const u64 t = uni64(s_tile);
+    __syncthreads();
+    if (t >= g.total_tiles) break;
+    JV v;
+    const FI_CONST JobDesc *jd;
+    u64 lt;
+    if (!locate_tile(g, t, wave, kMfmaPilotEmits, v, jd, lt)) continue;
+    // tile (A, B) of the upper triangle of 64-variant blocks, row A first
+    cu64p rows = as_const(uni_ptr(jd->row_start));
+    uint32_t rl = 0, rh = uni(jd->nrows) - 1;
+    while (rl < rh) {
+      const uint32_t mid = (rl + rh + 1) >> 1;
+      if (rows[mid] <= lt) rl = mid;
+      else rh = mid - 1;
+    }
+    rl = uni(rl);
+    const uint32_t B = rl + (uint32_t)uni64(lt - rows[rl]);
+    const uint32_t a0 = 64 * rl + 32 * (wave >> 1);
+    const uint32_t j0 = 64 * B + 32 * (wave & 1);
+    // a wave with no pair a < j < n has nothing to count; its pilot slots
+    // stay zero
+    if (a0 + 1 >= v.n || j0 >= v.n || j0 + 31 <= a0) continue;
+    wave_pairs(v, a0, j0, lane);
+  }
+}
+
+int mfma2_grid_size() {
+  int dev = 0, cus = 0, per = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma2_kernel, kMfmaWaves * 64, 0);
+  if (cus <= 0) cus = 256;
+  if (per <= 0) per = 1;
+  return cus * per;
+}
+
+void launch_mfma2(const Globals &g, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(mfma2_kernel, dim3(grid), dim3(kMfmaWaves * 64), 0, s, g);
+}
+
+}  // namespace fiuncho

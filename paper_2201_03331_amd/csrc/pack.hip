@@ -18,7 +18,7 @@ __global__ void init_kernel(Globals g) {
   for (uint32_t i = threadIdx.x; i < (uint32_t)kHistBins; i += blockDim.x) J.hist[i] = 0;
   {
     uint4 *pk = reinterpret_cast<uint4 *>(J.cand);
-    const uint32_t n4 = J.pilot_tiles * (kScanWaves * kPilotEmits * 64 / 4);
+    const uint32_t n4 = J.pilot_slots / 4;
     for (uint32_t i = threadIdx.x; i < n4; i += blockDim.x) pk[i] = make_uint4(0, 0, 0, 0);
   }
   if (threadIdx.x == 0) {
@@ -32,10 +32,8 @@ __global__ void init_kernel(Globals g) {
     st->l2_count = 0;
     st->kth_key = 0;
     st->flags = 0;
-    if (blockIdx.x == 0) {
-      *g.tile_counter = 0;
-      *g.pilot_counter = 0;
-    }
+    if (blockIdx.x == 0)
+      for (int i = 0; i < kTileCounters; ++i) g.tile_counter[i] = 0;
   }
 }
 

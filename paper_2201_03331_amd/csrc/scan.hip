@@ -19,175 +19,13 @@
 //     per-variant class counts, so 4 of the 9 cells are counted directly.
 // Tiles (workgroups of kScanWaves waves sharing the same 64 last variants)
 // are pulled from a device-wide counter by a persistent grid.
-#include "device_common.hpp"
+#include "filter.hpp"
 
 namespace fiuncho {
 
 struct Ulong2 {
   u64 x, y;
 };
-
-// Wave-uniform copy of what a tile needs from its job (every field is read
-// into scalar registers once per tile).
-struct JV {
-  uint32_t n, m, k, top_n, n_pad, wcap, cand_cap, m0, m1, W0, W1;
-  u64 total;
-  const u64 *Bv;
-  const u64 *Bs;
-  const uint32_t *marg;
-  uint32_t *hist;
-  Cand *cand;
-  JobState *st;
-  const uint32_t *pairs;
-  uint32_t path;
-  const float *Fh;
-  float fbound;
-  mutable uint32_t *pk;       // pilot launch: this wave's next 64 score slots
-};
-
-template <typename T>
-__device__ __forceinline__ T *uni_ptr(T *p) {
-  return reinterpret_cast<T *>(uni64(reinterpret_cast<u64>(p)));
-}
-
-__device__ __forceinline__ JV load_view(const JobDesc *jd) {
-  const FI_CONST JobDesc *J = as_const(jd);
-  JV v;
-  v.n = uni(J->n);
-  v.m = uni(J->m);
-  v.k = uni(J->k);
-  v.top_n = uni(J->top_n);
-  v.n_pad = uni(J->n_pad);
-  v.wcap = uni(J->wcap);
-  v.cand_cap = uni(J->cand_cap);
-  v.total = uni64(J->total);
-  v.Bv = uni_ptr(J->Bv);
-  v.Bs = uni_ptr(J->Bs);
-  v.marg = uni_ptr(J->marg);
-  v.hist = uni_ptr(J->hist);
-  v.cand = uni_ptr(J->cand);
-  v.st = uni_ptr(J->state);
-  v.pairs = uni_ptr(J->pairs);
-  v.path = uni(J->path);
-  v.Fh = uni_ptr(J->Fh);
-  v.fbound = __uint_as_float(uni(__float_as_uint(J->fbound)));
-  v.pk = nullptr;
-  return v;
-}
-
-// m * MI = [f(m) - f(m0) - f(m1)] + sum_x [f(n_x0) + f(n_x1) - f(n_x0 + n_x1)]
-// with f(t) = t ln t: Eq. 1-3 with plug-in probabilities, multiplied out.
-// The scan evaluates it in plain single precision from a float table of f;
-// the job's fbound bounds the rounding error of the resulting MI, and every
-// filter below widens its threshold by twice that bound.
-__device__ __forceinline__ float mi_term(const FI_GLOBAL float *F, uint32_t n0, uint32_t n1) {
-  return (F[n0] + F[n1]) - F[n0 + n1];
-}
-
-// Lower bound of the top_n-th best score from the survivor histogram: the bin
-// where the count from the top reaches top_n holds the top_n-th largest
-// appended score, so its lower edge is a valid bound.  One wave.
-__device__ __noinline__ void refresh_tau(uint32_t *hist, JobState *st, uint32_t top_n,
-                                         uint32_t lane) {
-  constexpr int PER = kHistBins / 64;
-  const uint32_t *bins = hist + lane * PER;
-  uint32_t tot = 0;
-  for (int i = 0; i < PER; ++i) tot += load_relaxed(&bins[i]);
-  uint32_t suf = tot;  // sum over lanes >= this lane
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    uint32_t o = __shfl_down(suf, off);
-    if (lane + off < 64) suf += o;
-  }
-  const u64 ok = ballot(suf >= top_n);
-  if (ok == 0) return;
-  const uint32_t L = 63 - __clzll((long long)ok);
-  if (lane == L) {
-    uint32_t run = suf - tot;
-    uint32_t bin = L * PER;
-    for (int i = PER - 1; i >= 0; --i) {
-      run += load_relaxed(&bins[i]);
-      if (run >= top_n) {
-        bin = L * PER + i;
-        break;
-      }
-    }
-    atomicMax(&st->tau_key, bin << kHistShift);
-  }
-}
-
-// A combination is kept iff its estimate is at least tau - 2 fbound: with
-// |estimate - MI| <= fbound everywhere, tau <= the top_n-th best estimate
-// <= the top_n-th best MI + fbound, so anything lower cannot be in the top_n.
-__device__ __forceinline__ float current_threshold(const JV &v) {
-  const float tau = __uint_as_float(uni(load_relaxed(&v.st->tau_key)));
-  return tau - 2.0f * v.fbound;
-}
-
-// Appends every active lane whose score clears the threshold.
-__device__ __forceinline__ void emit(const JV &v, bool active, float est, u64 rank, float thr,
-                                     uint32_t lane) {
-  if (v.pk) {  // pilot: record the score only
-    v.pk[lane] = (active && est > 0.f) ? __float_as_uint(est) : 0u;
-    v.pk += 64;
-    return;
-  }
-  const bool keep = active && est >= thr;
-  const u64 mask = ballot(keep);
-  if (mask == 0) return;
-  const uint32_t cnt = popc64(mask);
-  const uint32_t leader = __ffsll((long long)mask) - 1;
-  u64 base = 0, old = 0;
-  if (lane == leader) {
-    base = atomicAdd(&v.st->cand_count, (u64)cnt);
-    old = atomicAdd(&v.st->nsurv, (u64)cnt);
-  }
-  base = __shfl(base, leader);
-  old = __shfl(old, leader);
-  if (keep) {
-    const u64 lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const u64 idx = base + popc64(mask & lt);
-    const uint32_t key = est > 0.f ? __float_as_uint(est) : 0u;
-    if (idx < v.cand_cap) {
-      Cand c;
-      c.rank = rank;
-      c.key = key;
-      c.est = est;
-      v.cand[idx] = c;
-    }
-    atomicAdd(&v.hist[key >> kHistShift], 1u);
-  }
-  const u64 qs = v.top_n > 64 ? v.top_n : 64;
-  if ((old + cnt) / qs != old / qs) refresh_tau(v.hist, v.st, v.top_n, lane);
-}
-
-// Constants of the score of a job: m * MI starts at f(m) - f(m0) - f(m1).
-struct MiConst {
-  float c;
-  float inv_m;
-};
-
-__device__ __forceinline__ MiConst mi_const(const JV &v) {
-  const FI_CONST float *F = as_const(v.Fh);
-  MiConst c;
-  c.c = (F[v.m] - F[v.m0]) - F[v.m1];
-  c.inv_m = 1.0f / (float)v.m;
-  return c;
-}
-
-// Scores a complete table of NC cells x 2 classes and appends it if it may be
-// among the best.
-template <int NC>
-__device__ __forceinline__ void score_table(const JV &v, const FI_GLOBAL float *F,
-                                            const uint32_t (&t)[NC][2], bool active, float thr,
-                                            const MiConst &mc, u64 rank, uint32_t lane) {
-  float fs = mc.c;
-  if (active) {
-#pragma unroll
-    for (int x = 0; x < NC; ++x) fs += mi_term(F, t[x][0], t[x][1]);
-  }
-  emit(v, active, fs * mc.inv_m, rank, thr, lane);
-}
 
 // ---------------------------------------------------------------------------
 // Software-pipelined word loop shared by the counting kernels.  The lane's
@@ -753,43 +591,15 @@ __global__ __launch_bounds__(kScanWaves * 64, scan_min_waves(KSEL)) void scan_ke
   const uint32_t lane = lane_id();
   const uint32_t wave = uni(threadIdx.x >> 6);
   for (;;) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(g.tile_counter, 1ull);
+    if (threadIdx.x == 0) s_tile = g.tile_base + atomicAdd(g.tile_counter, 1ull);
     __syncthreads();
     const u64 t = uni64(s_tile);
     __syncthreads();
     if (t >= g.total_tiles) break;
-    cu64p jts = as_const(g.job_tile_start);
-    uint32_t lo = 0, hi = g.n_jobs - 1;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (jts[mid] <= t) lo = mid;
-      else hi = mid - 1;
-    }
-    lo = uni(lo);
-    JV v = load_view(g.jobs + lo);
-    {
-      const JobState *st = v.st;
-      if (uni((uint32_t)st->status) != 0) continue;
-      v.m0 = uni(st->m0);
-      v.m1 = uni(st->m1);
-      v.W0 = uni(st->W0);
-      v.W1 = uni(st->W1);
-      if (v.m0 == 0 || v.m1 == 0) continue;
-    }
-    const FI_CONST JobDesc *jd = as_const(g.jobs) + lo;
-    u64 lt = uni64(t - jts[lo]);
-    if (g.pilot) {
-      // pilot tile i of S stands for tile floor(i T / S) of the job's T
-      v.pk = reinterpret_cast<uint32_t *>(v.cand) + (lt * kScanWaves + wave) * (kPilotEmits * 64);
-      lt = uni64(lt * uni64(jd->tile_count) / uni(jd->pilot_tiles));
-    }
-    // local tile: the job's lt-th tile, or with shards the shard's lt-th
-    // tile, dealt from block lt of shard_count consecutive tiles at offset
-    // (shard_index + lt) mod shard_count
-    {
-      const uint32_t sc = uni(jd->shard_count);
-      if (sc > 1) lt = uni64(lt * sc + (uni(jd->shard_index) + lt % sc) % sc);
-    }
+    JV v;
+    const FI_CONST JobDesc *jd;
+    u64 lt;
+    if (!locate_tile(g, t, wave, kPilotEmits, v, jd, lt)) continue;
     const int k = KSEL == kSelPairs ? 3 : (KSEL && KSEL != kSel23) ? KSEL : (int)v.k;
     if (k == 1) {
       if (KSEL == 0 || KSEL == 1) tile_order1(v, lt, wave, lane);

@@ -137,7 +137,7 @@ __global__ __launch_bounds__(1024) void pilot_select_kernel(Globals g) {
   if (J.pilot_tiles == 0 || st->status != 0 || st->m0 == 0 || st->m1 == 0) return;
   __shared__ RadixLds s;
   const uint32_t *keys = reinterpret_cast<const uint32_t *>(J.cand);
-  const uint32_t M = J.pilot_tiles * (kScanWaves * kPilotEmits * 64);
+  const uint32_t M = J.pilot_slots;
   if (M <= J.top_n) return;
   const uint32_t kth = radix_kth_largest([&](uint32_t i) { return keys[i]; }, M, J.top_n, s);
   if (threadIdx.x == 0 && kth != 0) atomicMax(&st->tau_key, kth);

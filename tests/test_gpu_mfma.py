@@ -1,0 +1,74 @@
+"""GPU parity of the order-2 matrix-core path (FIUNCHO_ORDER2_MFMA=1): the
+one-hot int8 contraction must give the same tables, top-N set and FP64
+scores as the oracle, like the popcount path."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_03331_amd import fiuncho, synth
+from test_gpu_parity import check_hits_against_oracle, full_size_check, random_dataset, say, _merge, _run_shards
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def mfma(monkeypatch):
+    monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", "1")
+
+
+# n around the 16/32/64-variant block edges, m around the 32/64-sample steps
+CASES = [(2, 50, 0.5), (3, 64, 0.5), (17, 31, 0.4), (33, 100, 0.3), (64, 640, 0.5),
+         (65, 129, 0.7), (96, 65, 0.5), (130, 1000, 0.5), (257, 77, 0.45)]
+
+
+@pytest.mark.parametrize("n,m,frac", CASES)
+def test_order2_mfma_small(n, m, frac, mfma):
+    say(f"case: mfma order 2 n={n} m={m}")
+    G, y = random_dataset(31 + n, n, m, frac, 1 if n > 4 else 0, 1 if n > 4 else 0)
+    top = min(40, math.comb(n, 2))
+    hits = fiuncho.scan(G, y, 2, top)
+    check_hits_against_oracle(G, y, 2, top, hits)
+
+
+def test_order2_mfma_every_pair(mfma):
+    """top_n >= C(n, 2): every pair is returned, with the oracle's score."""
+    n = 60
+    G, y = random_dataset(77, n, 300, 0.5)
+    hits = fiuncho.scan(G, y, 2, fiuncho.MAX_TOPN)
+    assert len(hits) == math.comb(n, 2)
+    np.testing.assert_array_equal(np.sort(hits["rank"]), np.arange(math.comb(n, 2), dtype=np.uint64))
+    np.testing.assert_array_equal(hits["mi"], oracle.score_ranks(G, y, 2, hits["rank"]))
+    check_hits_against_oracle(G, y, 2, len(hits), hits)
+
+
+def test_order2_mfma_workloads(mfma):
+    d = synth.order2_small()
+    check_hits_against_oracle(d.genotypes, d.phenotype, 2, d.top_n,
+                              fiuncho.scan(d.genotypes, d.phenotype, 2, d.top_n))
+    full_size_check(synth.order2_dense(), 20000, 52)
+
+
+def test_order2_mfma_in_a_mixed_batch(mfma):
+    """Order-2 jobs on the matrix cores and order-3 jobs on the popcount
+    kernel in one batched call."""
+    jobs = synth.batch_jobs(10, scale=0.04)
+    say("case: mixed batch", [(j.n, j.m, j.order) for j in jobs])
+    b = fiuncho.DeviceBatch(jobs)
+    b.run()
+    for d, (status, hits) in zip(jobs, b.results()):
+        assert status == 0
+        check_hits_against_oracle(d.genotypes, d.phenotype, d.order, d.top_n, hits)
+
+
+@pytest.mark.parametrize("n,P", [(300, 7), (60, 3), (5, 3)])
+def test_order2_mfma_shards(n, P, mfma):
+    G, y = random_dataset(88 + n, n, 200, 0.5)
+    top = min(50, math.comb(n, 2))
+    lists = _run_shards(G, y, 2, top, P)
+    check_hits_against_oracle(G, y, 2, top, _merge(lists, top))
+    if math.comb(n, 2) <= fiuncho.MAX_TOPN:
+        full = _run_shards(G, y, 2, fiuncho.MAX_TOPN, P)
+        sizes = fiuncho.shard_counts(n, 2, P, fiuncho.TILE_ROUND_ROBIN)
+        assert [len(h) for h in full] == sizes.tolist()

@@ -57,6 +57,14 @@ def test_counts_partition_the_search(scheme, n, k):
     assert fiuncho.shard_counts(n, k, 1, scheme).tolist() == [total]
 
 
+@pytest.mark.parametrize("n", [2, 63, 64, 65, 129, 300])
+def test_matrix_core_tiles_partition_order2(n, monkeypatch):
+    monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", "1")
+    for p in (1, 3, 8):
+        c = fiuncho.shard_counts(n, 2, p, fiuncho.TILE_ROUND_ROBIN)
+        assert int(c.sum()) == math.comb(n, 2)
+
+
 def test_balance_of_section_5_1():
     """Eq. 4 over the configurations of section 5.1 (units in multiples of 18
     from 18 to 522).  Recomputed, the paper's scheme peaks at 3.08 percent
