@@ -94,21 +94,21 @@ void build_rows(uint32_t n, uint32_t k, uint32_t path, std::vector<u64> &row_sta
     row_start.push_back(acc);
     return;
   }
+  if (path == fiuncho::kPathMfma2) {
+    // rows A of the upper triangle of 64-variant blocks: tiles (A, B >= A)
+    const u64 nb = ceil_div(n, 64);
+    for (u64 A = 0; A < nb; ++A) {
+      acc += nb - A;
+      row_start.push_back(acc);
+    }
+    return;
+  }
   if (k == 2) {
     const u64 S = (u64)fiuncho::kScanWaves * fiuncho::kOrder2Prefixes;
     const u64 rows = ceil_div(n - 1, S);
     for (u64 r = 0; r < rows; ++r) {
       const u64 a_first = r * S;
       acc += ceil_div(n - 1 - a_first, 64);
-      row_start.push_back(acc);
-    }
-    return;
-  }
-  if (path == fiuncho::kPathMfma2) {
-    // rows A of the upper triangle of 64-variant blocks: tiles (A, B >= A)
-    const u64 nb = ceil_div(n, 64);
-    for (u64 A = 0; A < nb; ++A) {
-      acc += nb - A;
       row_start.push_back(acc);
     }
     return;
@@ -210,7 +210,7 @@ struct JobLayout {
   uint32_t n, m, k, top_n, n_pad, wcap, nrows, path, shard_index, shard_count;
   u64 total;
   uint32_t cand_cap, l1_cap, l2_cap;
-  size_t off_G, off_y, off_idx, off_Bv, off_Bs, off_marg, off_hist, off_cand, off_l1, off_l2,
+  size_t off_G, off_y, off_idx, off_Bv, off_Bs, off_marg, off_hist, off_phist, off_cand, off_l1, off_l2,
       off_state, off_out, off_nout, off_status, off_pairs;
   // plan (uploaded)
   size_t off_rows, off_F32, off_Fh, off_P64;
@@ -304,6 +304,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     J.off_Bs = take(sizeof(u64) * (size_t)J.n * 4 * J.wcap);
     J.off_marg = take(sizeof(uint32_t) * (size_t)J.n * 6);
     J.off_hist = take(sizeof(uint32_t) * fiuncho::kHistBins);
+    J.off_phist = J.pilot_tiles ? take(sizeof(uint32_t) * fiuncho::kHistBins) : 0;
     J.off_cand = take(sizeof(Cand) * (size_t)J.cand_cap);
     J.off_l1 = take(sizeof(Cand) * (size_t)J.l1_cap);
     J.off_l2 = take(sizeof(Rescored) * (size_t)J.l2_cap);
@@ -448,6 +449,7 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
     d.P64 = reinterpret_cast<const double *>(ws + J.off_P64);
     d.row_start = reinterpret_cast<const u64 *>(ws + J.off_rows);
     d.hist = reinterpret_cast<uint32_t *>(ws + J.off_hist);
+    d.phist = J.pilot_tiles ? reinterpret_cast<uint32_t *>(ws + J.off_phist) : nullptr;
     d.cand = reinterpret_cast<Cand *>(ws + J.off_cand);
     d.cand_cap = J.cand_cap;
     d.l1_cap = J.l1_cap;
@@ -635,7 +637,9 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   if (g.total_pilot_tiles) {
     if (ns) counting(launch_globals(g, ps, 0, ns, true, 1), false);
     if (nm) counting(launch_globals(g, ps, ns, nm, true, 3), true);
-    fiuncho::launch_pilot_select(g, s);
+    uint32_t max_slots = 0;
+    for (auto &J : L.jobs) max_slots = std::max(max_slots, J.pilot_slots);
+    fiuncho::launch_pilot_select(g, max_slots, s);
   }
   if (ns) counting(launch_globals(g, ts, 0, ns, false, 0), false);
   if (nm) counting(launch_globals(g, ts, ns, nm, false, 2), true);

@@ -90,6 +90,7 @@ struct JobDesc {
   const double *P64;          // (t/m) ln(t/m) for t in [0, m]
   const unsigned long long *row_start;  // [nrows + 1] tile offsets
   uint32_t *hist;             // [kHistBins]
+  uint32_t *phist;            // [kHistBins] pilot scores (a job with a pilot sample)
   Cand *cand;
   uint32_t cand_cap;
   uint32_t l1_cap;
@@ -134,7 +135,7 @@ void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s);
 void launch_mfma2(const Globals &g, int grid, hipStream_t s);
 int mfma2_grid_size();
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
-void launch_pilot_select(const Globals &g, hipStream_t s);
+void launch_pilot_select(const Globals &g, uint32_t max_pilot_slots, hipStream_t s);
 void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s);
 void launch_finish(const Globals &g, hipStream_t s);
 void launch_tables(const Globals &g, const unsigned long long *ranks, uint64_t n_ranks,

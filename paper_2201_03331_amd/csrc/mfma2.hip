@@ -26,14 +26,27 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 constexpr int kMfmaWaves = 4;
 static_assert(kMfmaWaves == kScanWaves, "pilot slots and tile decoding assume equal waves per tile");
 
-// 16 sample bits -> 16 bytes 0/1, byte i = bit i: a nibble times
-// 1 + 2^7 + 2^14 + 2^21 puts bit b at bit 8b (no carries), then a mask.
-__device__ __forceinline__ v4i expand16(uint32_t b) {
+// 8 sample bits -> 8 bytes 0/1 (byte i = bit i) by table lookup in LDS.
+// A nibble times 1 + 2^7 + 2^14 + 2^21 puts bit b at bit 8b (no carries);
+// the table holds that for every byte value, in kLutCopies interleaved copies
+// so that the 16 lanes an LDS cycle serves always hit distinct banks.
+constexpr int kLutCopies = 16;
+
+__device__ __forceinline__ u64 spread8(uint32_t e) {
+  const uint32_t lo = ((e & 0xFu) * 0x00204081u) & 0x01010101u;
+  const uint32_t hi = (((e >> 4) & 0xFu) * 0x00204081u) & 0x01010101u;
+  return (u64)lo | ((u64)hi << 32);
+}
+
+// 16 sample bits -> the 16 int8 operand bytes of one lane
+__device__ __forceinline__ v4i expand16(const u64 *lut, uint32_t b) {
+  const u64 lo = lut[__builtin_amdgcn_ubfe(b, 0, 8) * kLutCopies];
+  const u64 hi = lut[__builtin_amdgcn_ubfe(b, 8, 8) * kLutCopies];
   v4i r;
-  r[0] = (int)(((b & 0xFu) * 0x00204081u) & 0x01010101u);
-  r[1] = (int)((((b >> 4) & 0xFu) * 0x00204081u) & 0x01010101u);
-  r[2] = (int)((((b >> 8) & 0xFu) * 0x00204081u) & 0x01010101u);
-  r[3] = (int)((((b >> 12) & 0xFu) * 0x00204081u) & 0x01010101u);
+  r[0] = (int)(uint32_t)lo;
+  r[1] = (int)(uint32_t)(lo >> 32);
+  r[2] = (int)(uint32_t)hi;
+  r[3] = (int)(uint32_t)(hi >> 32);
   return r;
 }
 
@@ -44,34 +57,54 @@ __device__ __forceinline__ v4i expand16(uint32_t b) {
 // any fixed sample order inside a lane is exact.
 __device__ __forceinline__ void mfma_class(const FI_GLOBAL u64 *pa, const FI_GLOBAL u64 *pj,
                                            size_t word_stride, uint32_t wbeg, uint32_t wend,
-                                           uint32_t h, v16i (&acc)[2][2]) {
+                                           uint32_t h, const u64 *lut, v16i (&acc)[2][2]) {
   if (wbeg >= wend) return;
-  u64 xa0 = pa[wbeg * word_stride], xa1 = pa[wbeg * word_stride + 32];
-  u64 xj0 = pj[wbeg * word_stride], xj1 = pj[wbeg * word_stride + 32];
-  for (uint32_t w = wbeg; w < wend; ++w) {
-    const u64 ca0 = xa0, ca1 = xa1, cj0 = xj0, cj1 = xj1;
-    const uint32_t wn = w + 1 < wend ? w + 1 : w;
-    xa0 = pa[wn * word_stride];
-    xa1 = pa[wn * word_stride + 32];
-    xj0 = pj[wn * word_stride];
-    xj1 = pj[wn * word_stride + 32];
+  // the rows of the next kDepth words are in flight in a register ring
+  constexpr int kDepth = 3;
+  const uint32_t wlast = wend - 1;
+  u64 X[kDepth][4];
+  auto load = [&](int slot, uint32_t w) {
+    const size_t o = (size_t)w * word_stride;
+    X[slot][0] = pa[o];
+    X[slot][1] = pa[o + 32];
+    X[slot][2] = pj[o];
+    X[slot][3] = pj[o + 32];
+  };
+#pragma unroll
+  for (int u = 0; u < kDepth; ++u) load(u, min(wbeg + u, wlast));
+  auto step = [&](int slot) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      const uint32_t sh = 32 * s + 16 * h;
-      const v4i A0 = expand16((uint32_t)(ca0 >> sh) & 0xFFFFu);
-      const v4i A1 = expand16((uint32_t)(ca1 >> sh) & 0xFFFFu);
-      const v4i J0 = expand16((uint32_t)(cj0 >> sh) & 0xFFFFu);
-      const v4i J1 = expand16((uint32_t)(cj1 >> sh) & 0xFFFFu);
-      acc[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, J0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, J1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, J0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, J1, acc[1][1], 0, 0, 0);
+      // 16 samples of this lane half: bits [16 h, 16 h + 16) of the 32-bit half s
+      v4i E[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const uint32_t half = s ? (uint32_t)(X[slot][f] >> 32) : (uint32_t)X[slot][f];
+        E[f] = expand16(lut, __builtin_amdgcn_ubfe(half, 16 * h, 16));
+      }
+      acc[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(E[0], E[2], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(E[0], E[3], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(E[1], E[2], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(E[1], E[3], acc[1][1], 0, 0, 0);
+    }
+  };
+  uint32_t w = wbeg;
+  for (; w + kDepth <= wend; w += kDepth) {
+#pragma unroll
+    for (int u = 0; u < kDepth; ++u) {
+      step(u);
+      load(u, min(w + u + kDepth, wlast));
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
+#pragma unroll
+  for (int u = 0; u < kDepth - 1; ++u)
+    if (w + u < wend) step(u);
 }
 
 // One wave: pairs (a0 + [0, 32)) x (j0 + [0, 32)).
-__device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0, uint32_t lane) {
+__device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0, uint32_t lane,
+                                           const u64 *lut) {
   const uint32_t n = v.n;
   const uint32_t r = lane & 31, h = lane >> 5;
   const size_t word_stride = (size_t)v.n_pad * 2;
@@ -85,8 +118,8 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc0[x][y][e] = acc1[x][y][e] = 0;
-  mfma_class(pa, pj, word_stride, 0, v.W0, h, acc0);
-  mfma_class(pa, pj, word_stride, v.W0, v.W0 + v.W1, h, acc1);
+  mfma_class(pa, pj, word_stride, 0, v.W0, h, lut, acc0);
+  mfma_class(pa, pj, word_stride, v.W0, v.W0 + v.W1, h, lut, acc1);
 
   // Output block layout: lane l holds column l mod 32 (variant j0' + (l mod
   // 32) / 2, genotype l mod 2); register e holds row 8 (e / 4) + 4 h + e mod 4
@@ -159,8 +192,11 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
 
 __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma2_kernel(Globals g) {
   __shared__ u64 s_tile;
+  __shared__ u64 s_lut[256 * kLutCopies];
   const uint32_t lane = lane_id();
   const uint32_t wave = uni(threadIdx.x >> 6);
+  for (uint32_t i = threadIdx.x; i < 256 * kLutCopies; i += blockDim.x) s_lut[i] = spread8(i / kLutCopies);
+  const u64 *lut = s_lut + (lane % kLutCopies);
   for (;;) {
     if (threadIdx.x == 0) s_tile = g.tile_base + atomicAdd(g.tile_counter, 1ull);
     __syncthreads();
@@ -186,7 +222,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma2_kernel(Globals g) {
     // a wave with no pair a < j < n has nothing to count; its pilot slots
     // stay zero
     if (a0 + 1 >= v.n || j0 >= v.n || j0 + 31 <= a0) continue;
-    wave_pairs(v, a0, j0, lane);
+    wave_pairs(v, a0, j0, lane, lut);
   }
 }
 

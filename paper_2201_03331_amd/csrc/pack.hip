@@ -15,7 +15,10 @@ namespace fiuncho {
 // captured into a graph and replayed.)
 __global__ void init_kernel(Globals g) {
   const JobDesc &J = g.jobs[blockIdx.x];
-  for (uint32_t i = threadIdx.x; i < (uint32_t)kHistBins; i += blockDim.x) J.hist[i] = 0;
+  for (uint32_t i = threadIdx.x; i < (uint32_t)kHistBins; i += blockDim.x) {
+    J.hist[i] = 0;
+    if (J.phist) J.phist[i] = 0;
+  }
   {
     uint4 *pk = reinterpret_cast<uint4 *>(J.cand);
     const uint32_t n4 = J.pilot_slots / 4;

@@ -17,7 +17,7 @@
 // compensated evaluation made here, beside the double-precision one.
 #include <algorithm>
 
-#include "device_common.hpp"
+#include "filter.hpp"
 
 namespace fiuncho {
 
@@ -128,19 +128,33 @@ __device__ uint32_t radix_kth_largest(KeyAt key_at, uint32_t M, uint32_t N, Radi
   return s.prefix;
 }
 
-// 0. pilot: one workgroup per job; the top_n-th largest score of the pilot
-// sample is at most the top_n-th largest score of the whole job, so it is a
+// 0. pilot: histogram of the pilot sample's scores (2048 bins of the float
+// bits' top, as the scan's survivor histogram), then the lower edge of the
+// bin holding the top_n-th largest.  The top_n-th largest score of a sample
+// is at most the top_n-th largest score of the whole job, so that edge is a
 // valid starting bound for the scan's filter.
-__global__ __launch_bounds__(1024) void pilot_select_kernel(Globals g) {
+__global__ __launch_bounds__(256) void pilot_hist_kernel(Globals g) {
+  const JobDesc &J = g.jobs[blockIdx.y];
+  JobState *st = J.state;
+  if (J.pilot_tiles == 0 || st->status != 0 || st->m0 == 0 || st->m1 == 0) return;
+  __shared__ uint32_t h[kHistBins];
+  for (uint32_t i = threadIdx.x; i < (uint32_t)kHistBins; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const uint32_t *keys = reinterpret_cast<const uint32_t *>(J.cand);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < J.pilot_slots; i += gridDim.x * blockDim.x) {
+    const uint32_t key = keys[i];
+    if (key != 0) atomicAdd(&h[key >> kHistShift], 1u);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < (uint32_t)kHistBins; i += blockDim.x)
+    if (h[i]) atomicAdd(&J.phist[i], h[i]);
+}
+
+__global__ __launch_bounds__(64) void pilot_tau_kernel(Globals g) {
   const JobDesc &J = g.jobs[blockIdx.x];
   JobState *st = J.state;
   if (J.pilot_tiles == 0 || st->status != 0 || st->m0 == 0 || st->m1 == 0) return;
-  __shared__ RadixLds s;
-  const uint32_t *keys = reinterpret_cast<const uint32_t *>(J.cand);
-  const uint32_t M = J.pilot_slots;
-  if (M <= J.top_n) return;
-  const uint32_t kth = radix_kth_largest([&](uint32_t i) { return keys[i]; }, M, J.top_n, s);
-  if (threadIdx.x == 0 && kth != 0) atomicMax(&st->tau_key, kth);
+  refresh_tau(J.phist, st, J.top_n, lane_id());
 }
 
 // 2. one workgroup per job: radix selection of the top_n-th largest key over
@@ -445,8 +459,11 @@ void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s) {
   hipLaunchKernelGGL(select_kernel, dim3(g.n_jobs), dim3(1024), 0, s, g);
 }
 
-void launch_pilot_select(const Globals &g, hipStream_t s) {
-  hipLaunchKernelGGL(pilot_select_kernel, dim3(g.n_jobs), dim3(1024), 0, s, g);
+void launch_pilot_select(const Globals &g, uint32_t max_pilot_slots, hipStream_t s) {
+  uint32_t blocks = (max_pilot_slots + 4095) / 4096;
+  blocks = blocks < 1 ? 1 : (blocks > 256 ? 256 : blocks);
+  hipLaunchKernelGGL(pilot_hist_kernel, dim3(blocks, g.n_jobs), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(pilot_tau_kernel, dim3(g.n_jobs), dim3(64), 0, s, g);
 }
 
 void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s) {
