@@ -52,21 +52,26 @@ def workloads():
     }
 
 
-def word_ops_per_combination(k: int, m0: int, m1: int) -> int:
-    """64-bit AND+popcount operations the counting kernel executes per
+def word_ops_per_combination(k: int, m0: int, m1: int, kernel: int) -> int:
+    """64-bit AND+popcount operations a popcount kernel executes per
     combination, over W = ceil(m0/64) + ceil(m1/64) words: 4 per word at
-    order 2 and 8 at order 3 (only the {0,1}^k cells are counted, the others
-    follow from lower-order tables); 2*3^(k-1) at order >= 4 (rows g=0,1 of
-    the last variant against every row of the prefix).  The order-3 figure is
-    2*3^(k-1) = 18 when FIUNCHO_ORDER3_PAIRS=0 selects the generic kernel."""
+    order 2 (rows g=0,1 of both variants); 8 at order 3 on the pair-table
+    kernel (only the {0,1}^3 cells are counted, the others follow from
+    lower-order tables); 2*3^(k-1) otherwise (rows g=0,1 of the last variant
+    against every row of the prefix)."""
+    from paper_2201_03331_amd import fiuncho
     W = (m0 + 63) // 64 + (m1 + 63) // 64
     if k == 1:
         return 0
     if k == 2:
         return 4 * W
-    if k == 3 and os.environ.get("FIUNCHO_ORDER3_PAIRS", "1") != "0":
+    if k == 3 and kernel == fiuncho.KERNEL_PAIRS:
         return 8 * W
     return 2 * 3 ** (k - 1) * W
+
+
+# gfx950 dense int8 matrix-core peak (ops/s; one multiply-add = 2 ops)
+MFMA_I8_PEAK_OPS = 5.0e15
 
 
 def cpu_baseline(d, budget_s: float = 20.0):
@@ -95,6 +100,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="order3-1000x6400", choices=sorted(workloads().keys()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the kernels for every dataset shape first (fiuncho_autotune)")
     ap.add_argument("--shard", default=None, metavar="I/P",
                     help="search only shard I of P of every dataset's work tiles")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -121,6 +128,12 @@ def main():
 
     datasets = workloads()[args.workload]()
     plain = args.workload.endswith("-plain")
+    tuned = {}
+    if args.autotune:
+        for d in datasets:
+            key = (d.n.bit_length(), ((d.m + 63) // 64).bit_length(), d.order)
+            if key not in tuned:
+                tuned[key] = fiuncho.autotune(d.n, d.m, d.order)
     shard = None
     if args.shard:
         si, sp = (int(v) for v in args.shard.split("/"))
@@ -170,21 +183,43 @@ def main():
     def share(d):
         if shard is None:
             return math.comb(d.n, d.order)
-        return int(fiuncho.shard_counts(d.n, d.order, shard[1], fiuncho.TILE_ROUND_ROBIN)[shard[0]])
+        return int(fiuncho.shard_counts(d.n, d.m, d.order, shard[1], fiuncho.TILE_ROUND_ROBIN)[shard[0]])
 
     combos = sum(share(d) for d in datasets)
     combos_m = sum(share(d) * d.m for d in datasets)
     value = combos / (ms / 1e3)
 
-    # roofline of the counting kernel (the dominant one): algorithmic 32-bit
-    # lane-ops (4 per 64-bit AND+popcount) per launch over its measured time
+    # roofline of the dominant counting kernel: algorithmic work per launch
+    # over that kernel's measured time.  Popcount kernels: 32-bit VALU
+    # lane-ops (4 per 64-bit AND+popcount).  Matrix-core order 2: int8 ops of
+    # the one-hot contraction, 2 x 4 cells x m samples per pair.
     lane_ops = 0
+    mfma_ops = 0
+    kernels = set()
     for d in datasets:
         m1 = int(d.phenotype.sum())
-        lane_ops += 4 * word_ops_per_combination(d.order, d.m - m1, m1) * share(d)
-    scan_ms = prof["scan_ms"] if not plain else prof["scan_ms"] * len(batches)
-    achieved = lane_ops / (scan_ms / 1e3) / 1e12
-    peak = VALU_PEAK_LANE_OPS / 1e12
+        kern = fiuncho.get_kernel(d.n, d.m, d.order)
+        kernels.add(kern)
+        if kern == fiuncho.KERNEL_MFMA:
+            mfma_ops += 2 * 4 * d.m * share(d)
+        else:
+            lane_ops += 4 * word_ops_per_combination(d.order, d.m - m1, m1, kern) * share(d)
+    calls = len(batches) if plain else 1
+    scan_ms = prof["scan_ms"] * calls
+    mfma_ms = prof["mfma_ms"] * calls
+    if mfma_ms > scan_ms:
+        achieved = mfma_ops / (mfma_ms / 1e3) / 1e12
+        peak = MFMA_I8_PEAK_OPS / 1e12
+        roofline = {"bound": "mfma", "kernel": "mfma2_kernel (one-hot int8 contraction + FP32 MI + filter)",
+                    "achieved": achieved, "peak": peak, "unit": "T int8 op/s", "frac": achieved / peak,
+                    "traffic": None}
+    else:
+        achieved = lane_ops / (scan_ms / 1e3) / 1e12
+        peak = VALU_PEAK_LANE_OPS / 1e12
+        roofline = {"bound": "alu", "kernel": "scan_kernel (AND+popcount counting + FP32 MI + filter)",
+                    "achieved": achieved, "peak": peak, "unit": "T int32 lane-op/s", "frac": achieved / peak,
+                    "traffic": None}
+    names = {fiuncho.KERNEL_POPCOUNT: "popcount", fiuncho.KERNEL_PAIRS: "pairs", fiuncho.KERNEL_MFMA: "mfma"}
 
     d0 = datasets[0]
     planted_first = None
@@ -220,14 +255,15 @@ def main():
         "combinations_x_samples_per_s": combos_m / (ms / 1e3),
         "arithmetic": "u64 bitsets, u32 popcount counts, plain f32 MI estimate with a rigorous "
                       "rounding bound for filtering, compensated f32 and f64 MI of the kept",
-        "phases_ms": {k: round(prof[k], 4) for k in ("pack_ms", "scan_ms", "select_ms", "total_ms")},
+        "phases_ms": {k: round(prof[k], 4) for k in ("pack_ms", "pilot_ms", "scan_ms", "mfma_ms",
+                                                     "select_ms", "total_ms")},
+        "kernels": sorted(names[k] for k in kernels),
+        "autotuned": bool(args.autotune),
         "candidates": prof["candidates"],
         "rescored": prof["kept"],
         "status_ok": ok,
         "planted_first": planted_first,
-        "roofline": {"bound": "alu", "kernel": "scan_kernel (counting + FP32 MI + filter)",
-                     "achieved": achieved, "peak": peak, "unit": "T int32 lane-op/s",
-                     "frac": achieved / peak, "traffic": None},
+        "roofline": roofline,
     }
     if not args.no_cpu_baseline and len(datasets) == 1 and shard is None:
         out["cpu_baseline"] = cpu_baseline(d0)

@@ -115,12 +115,15 @@ typedef struct {
 /* Flags of fiuncho_scan_batch. */
 #define FIUNCHO_DEVICE_PTRS 1u /* all job pointers are device pointers and the
                                   call returns as soon as the work is queued */
+#define FIUNCHO_UPLOAD_PLAN 2u /* upload the plan even if this workspace already
+                                  holds it (see fiuncho_scan_batch) */
 
 /*
  * fiuncho_workspace_bytes -- device workspace needed by fiuncho_scan_batch for
- * these jobs (bitsets, tables, candidate buffers, plan).  Depends only on the
- * shapes (snps, samples, order, top_n) of the jobs.  Returns 0 for invalid
- * shapes.
+ * these jobs (bitsets, tables, candidate buffers, plan).  Depends on the
+ * shapes (snps, samples, order, top_n) of the jobs and on the kernel each
+ * shape is given (fiuncho_get_kernel): ask again after fiuncho_set_kernel or
+ * fiuncho_autotune.  Returns 0 for invalid shapes.
  */
 size_t fiuncho_workspace_bytes(const fiuncho_job *jobs, uint32_t n_jobs);
 
@@ -139,6 +142,10 @@ size_t fiuncho_workspace_bytes(const fiuncho_job *jobs, uint32_t n_jobs);
  * first call with a given workspace and job set uploads a plan (lookup tables,
  * tile tables) synchronously; later calls with the same workspace and job set
  * queue kernels only, so they can be captured into a HIP graph and replayed.
+ * The plan lives in the workspace: if anything else writes that memory, or it
+ * is freed and allocated again, between two calls, pass FIUNCHO_UPLOAD_PLAN
+ * on the next call.  Returns FIUNCHO_E_WORKSPACE if a plan upload is needed
+ * while the stream is being captured.
  */
 int fiuncho_scan_batch(const fiuncho_job *jobs, uint32_t n_jobs, uint32_t flags,
                        void *workspace, size_t ws_bytes, void *hip_stream);
@@ -181,14 +188,48 @@ int fiuncho_score(const uint8_t *genotypes, const uint8_t *phenotype, uint32_t s
  *             round-robin to the units, and a unit tests every combination
  *             that extends its prefixes;
  *   scheme 1: this library's shards (fiuncho_job.shard_index/shard_count):
- *             the work tiles of the search dealt in rotated blocks.
+ *             the work tiles of the search dealt in rotated blocks (the tiles
+ *             depend on the kernel chosen for snps, samples and order).
  *   Errors: FIUNCHO_E_NULL (counts NULL), FIUNCHO_E_SHAPE (units 0, snps 0
  *   or an unknown scheme), FIUNCHO_E_ORDER, FIUNCHO_E_OVERFLOW as for a job.
  *   counts    host array of `units` entries
  * The relative imbalance of Eq. 4 (section 5.1) is
  * 100 * (max counts - C(snps,order)/units) / (C(snps,order)/units).
  */
-int fiuncho_shard_counts(uint32_t snps, int order, uint32_t units, int scheme, uint64_t *counts);
+int fiuncho_shard_counts(uint32_t snps, uint32_t samples, int order, uint32_t units, int scheme,
+                         uint64_t *counts);
+
+/*
+ * Kernel choice.  Every job shape is searched by one of these counting
+ * kernels; the choice is made per (order, bit length of snps, bit length of
+ * ceil(samples / 64)) bucket: from a process-wide table filled by
+ * fiuncho_set_kernel or fiuncho_autotune, else from a built-in rule measured
+ * on MI355X.
+ */
+#define FIUNCHO_KERNEL_AUTO 0     /* no explicit choice (table entry cleared) */
+#define FIUNCHO_KERNEL_POPCOUNT 1 /* AND + popcount of the prefix rows against rows
+                                     g = 0, 1 of the last variant (any order) */
+#define FIUNCHO_KERNEL_PAIRS 2    /* order 3: only the {0,1}^3 cells counted, the
+                                     rest from stored pair tables */
+#define FIUNCHO_KERNEL_MFMA 3     /* order 2: one-hot int8 contraction on the
+                                     matrix cores */
+
+/* The kernel a job of this shape would use now (a FIUNCHO_KERNEL_* value),
+ * or FIUNCHO_E_ORDER. */
+int fiuncho_get_kernel(uint32_t snps, uint32_t samples, int order);
+
+/* Sets (or, with FIUNCHO_KERNEL_AUTO, clears) the table entry of the shape's
+ * bucket.  FIUNCHO_E_SHAPE if the kernel does not handle the order. */
+int fiuncho_set_kernel(uint32_t snps, uint32_t samples, int order, int kernel);
+
+/*
+ * fiuncho_autotune -- times every kernel that handles this shape on a seeded
+ * synthetic dataset of exactly this shape (balanced classes, top_n 16) on the
+ * current device, `reps` timed runs each after one warm-up, records the
+ * fastest in the table for the shape's bucket and returns it in *kernel.
+ * Synchronous; allocates and frees its own device memory.
+ */
+int fiuncho_autotune(uint32_t snps, uint32_t samples, int order, uint32_t reps, int *kernel);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *fiuncho_last_error(void);
@@ -197,16 +238,20 @@ const char *fiuncho_last_error(void);
  * calls made on this thread with profiling enabled since the last
  * fiuncho_get_profile; see fiuncho_set_profiling. */
 typedef struct {
-  float pack_ms;      /* class partition + bit packing */
-  float scan_ms;      /* counting + FP32 scoring + candidate filter (one kernel) */
+  float pack_ms;      /* class partition, bit packing (and order-3 pair tables) */
+  float pilot_ms;     /* pilot sample: scores of a sample of tiles, starting bound */
+  float scan_ms;      /* popcount counting kernel + FP32 estimate + candidate filter */
+  float mfma_ms;      /* matrix-core order-2 kernel + FP32 estimate + candidate filter */
   float select_ms;    /* candidate selection, FP64 rescoring, final order */
   float total_ms;     /* all of the above, first kernel start to last kernel end */
   uint32_t calls;        /* profiled calls averaged */
-  uint32_t flags;        /* 4 = some |mi32 - mi| exceeded 1e-5 mi + 1e-10 (last call, first job) */
+  uint32_t flags;        /* 4 = a rescored candidate's single-precision estimate was
+                            farther from its FP64 MI than the stated bound (last
+                            call, first job; never expected) */
   uint64_t combinations; /* sum of C(snps, order) over the jobs of the last call */
   uint64_t candidates;   /* candidates the scan appended (last call, first job) */
   uint32_t kept;         /* candidates rescored in double precision (last call, first job) */
-  uint32_t reserved;
+  uint32_t kernels;      /* bit (1 << FIUNCHO_KERNEL_*) for each kernel the last call used */
 } fiuncho_profile;
 
 /* Enable (1) or disable (0) HIP-event timing of the phases of later

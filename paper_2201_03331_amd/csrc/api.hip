@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.hpp"
@@ -194,13 +195,66 @@ u64 shard_tiles(u64 tiles, u64 count, u64 s) {
   return q + ((s + q) % count < r ? 1 : 0);
 }
 
-uint32_t job_path(uint32_t n, uint32_t k) {
-  const char *env_pairs = std::getenv("FIUNCHO_ORDER3_PAIRS");
-  const bool use_pairs = !(env_pairs && env_pairs[0] == '0');
-  if (k == 3 && n >= 3 && use_pairs) return fiuncho::kPathPairs;
-  const char *env_mfma = std::getenv("FIUNCHO_ORDER2_MFMA");
-  if (k == 2 && env_mfma && env_mfma[0] == '1') return fiuncho::kPathMfma2;
-  return fiuncho::kPathGeneric;
+// ---------------------------------------------------------------------------
+// kernel choice per job shape: environment override, else this thread's
+// forced choice (autotuning runs), else the tuned table, else the rule
+// ---------------------------------------------------------------------------
+typedef std::tuple<uint32_t, uint32_t, uint32_t> ShapeKey;  // order, bit length of snps, of words
+std::mutex g_tune_mu;
+std::map<ShapeKey, int> g_tuned;
+thread_local int t_force_kernel = FIUNCHO_KERNEL_AUTO;
+
+uint32_t bit_length(u64 x) {
+  uint32_t b = 0;
+  for (; x; x >>= 1) ++b;
+  return b;
+}
+
+ShapeKey shape_key(uint32_t n, uint32_t m, uint32_t k) {
+  return ShapeKey(k, bit_length(n), bit_length(ceil_div(m, 64)));
+}
+
+bool kernel_valid(int kernel, uint32_t n, uint32_t k) {
+  switch (kernel) {
+    case FIUNCHO_KERNEL_POPCOUNT: return true;
+    case FIUNCHO_KERNEL_PAIRS: return k == 3 && n >= 3;
+    case FIUNCHO_KERNEL_MFMA: return k == 2;
+    default: return false;
+  }
+}
+
+// measured on MI355X: the matrix-core order-2 kernel wins from about a
+// thousand variants (4,000 x 16,000: 0.91 vs 1.40 ms), the popcount kernel
+// below (100 x 1,600: 0.053 vs 0.097 ms); the pair-table kernel wins at every
+// order-3 size tried
+int rule_kernel(uint32_t n, uint32_t k) {
+  if (k == 3 && n >= 3) return FIUNCHO_KERNEL_PAIRS;
+  if (k == 2 && n >= 1024) return FIUNCHO_KERNEL_MFMA;
+  return FIUNCHO_KERNEL_POPCOUNT;
+}
+
+int choose_kernel(uint32_t n, uint32_t m, uint32_t k) {
+  const char *e3 = std::getenv("FIUNCHO_ORDER3_PAIRS");
+  if (k == 3 && e3 && e3[0] == '0') return FIUNCHO_KERNEL_POPCOUNT;
+  if (k == 3 && e3 && e3[0] == '1' && n >= 3) return FIUNCHO_KERNEL_PAIRS;
+  const char *e2 = std::getenv("FIUNCHO_ORDER2_MFMA");
+  if (k == 2 && e2 && e2[0] == '0') return FIUNCHO_KERNEL_POPCOUNT;
+  if (k == 2 && e2 && e2[0] == '1') return FIUNCHO_KERNEL_MFMA;
+  if (t_force_kernel != FIUNCHO_KERNEL_AUTO && kernel_valid(t_force_kernel, n, k)) return t_force_kernel;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(shape_key(n, m, k));
+    if (it != g_tuned.end() && kernel_valid(it->second, n, k)) return it->second;
+  }
+  return rule_kernel(n, k);
+}
+
+uint32_t job_path(uint32_t n, uint32_t m, uint32_t k) {
+  switch (choose_kernel(n, m, k)) {
+    case FIUNCHO_KERNEL_PAIRS: return fiuncho::kPathPairs;
+    case FIUNCHO_KERNEL_MFMA: return fiuncho::kPathMfma2;
+    default: return fiuncho::kPathGeneric;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -260,7 +314,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     J.cand_cap = (uint32_t)std::max<u64>(cap, 1);
     J.l1_cap = J.cand_cap;
     J.l2_cap = fiuncho::kSortMax;
-    J.path = job_path(J.n, J.k);
+    J.path = job_path(J.n, J.m, J.k);
     build_rows(J.n, J.k, J.path, J.row_start);
     J.nrows = (uint32_t)(J.row_start.size() - 1);
     J.shard_count = jobs[i].shard_count > 1 ? jobs[i].shard_count : 1;
@@ -521,14 +575,14 @@ Globals launch_globals(const Globals &g, const std::vector<u64> &starts, uint32_
 }
 
 int upload_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host_inputs,
-                hipStream_t stream) {
+                hipStream_t stream, bool force = false) {
   std::vector<uint8_t> plan;
   build_plan(L, jobs, ws, host_inputs, plan);
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_plan_mu);
   PlanCache &pc = g_plans[std::make_pair(dev, (const void *)ws)];
-  if (pc.bytes == plan) return FIUNCHO_OK;
+  if (!force && pc.bytes == plan) return FIUNCHO_OK;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing(stream, &cs));
   if (cs != hipStreamCaptureStatusNone)
@@ -560,21 +614,25 @@ int check_device() {
 // profiling events
 // ---------------------------------------------------------------------------
 // one profiled call: events before pack, before scan, before select, at end
+constexpr int kProfEvents = 6;
 struct ProfCall {
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // before pack, after pack (and pair tables), after the pilot pass, after
+  // the popcount kernel, after the matrix-core kernel, at the end
+  hipEvent_t ev[kProfEvents] = {};
   u64 combos = 0;
+  uint32_t kernels = 0;
   JobState *state0 = nullptr;
 };
 thread_local std::vector<ProfCall> t_calls;   // recorded, not yet collected
 thread_local std::vector<hipEvent_t> t_free;  // event pool
 thread_local ProfCall *t_cur = nullptr;
 
-int prof_begin(u64 combos, JobState *state0) {
+int prof_begin(u64 combos, uint32_t kernels, JobState *state0) {
   t_cur = nullptr;
   if (!t_profiling) return FIUNCHO_OK;
   t_calls.emplace_back();
   ProfCall &c = t_calls.back();
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < kProfEvents; ++i) {
     if (!t_free.empty()) {
       c.ev[i] = t_free.back();
       t_free.pop_back();
@@ -583,6 +641,7 @@ int prof_begin(u64 combos, JobState *state0) {
     }
   }
   c.combos = combos;
+  c.kernels = kernels;
   c.state0 = state0;
   t_cur = &c;
   return FIUNCHO_OK;
@@ -612,7 +671,13 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
       });
     }
   }
-  if ((st = prof_begin(combos, reinterpret_cast<JobState *>(ws + L.jobs[0].off_state)))) return st;
+  uint32_t kernels = 0;
+  for (auto &J : L.jobs)
+    kernels |= 1u << (J.path == fiuncho::kPathPairs   ? FIUNCHO_KERNEL_PAIRS
+                      : J.path == fiuncho::kPathMfma2 ? FIUNCHO_KERNEL_MFMA
+                                                      : FIUNCHO_KERNEL_POPCOUNT);
+  if ((st = prof_begin(combos, kernels, reinterpret_cast<JobState *>(ws + L.jobs[0].off_state))))
+    return st;
   if ((st = prof_record(0, s))) return st;
   fiuncho::launch_init(g, s);
   fiuncho::launch_pack(g, L.max_n_pad, s);
@@ -641,13 +706,15 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
     for (auto &J : L.jobs) max_slots = std::max(max_slots, J.pilot_slots);
     fiuncho::launch_pilot_select(g, max_slots, s);
   }
-  if (ns) counting(launch_globals(g, ts, 0, ns, false, 0), false);
-  if (nm) counting(launch_globals(g, ts, ns, nm, false, 2), true);
   if ((st = prof_record(2, s))) return st;
+  if (ns) counting(launch_globals(g, ts, 0, ns, false, 0), false);
+  if ((st = prof_record(3, s))) return st;
+  if (nm) counting(launch_globals(g, ts, ns, nm, false, 2), true);
+  if ((st = prof_record(4, s))) return st;
   fiuncho::launch_select(g, L.max_cand_cap, s);
   fiuncho::launch_rescore(g, L.max_l2_cap, L.kmax, s);
   fiuncho::launch_finish(g, s);
-  if ((st = prof_record(3, s))) return st;
+  if ((st = prof_record(5, s))) return st;
   HIP_TRY(hipGetLastError());
   return FIUNCHO_OK;
 }
@@ -676,7 +743,7 @@ int batch_impl(const fiuncho_job *jobs, uint32_t n_jobs, uint32_t flags, void *w
     return fail(FIUNCHO_E_WORKSPACE, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
                                          std::to_string(L.total));
   uint8_t *ws = static_cast<uint8_t *>(workspace);
-  st = upload_plan(L, jobs, ws, host_inputs, stream);
+  st = upload_plan(L, jobs, ws, host_inputs, stream, (flags & FIUNCHO_UPLOAD_PLAN) != 0);
   if (st) return st;
   if (host_inputs) {
     for (uint32_t i = 0; i < n_jobs; ++i) {
@@ -736,6 +803,18 @@ struct OwnedWs {
 std::mutex g_ws_mu;
 std::map<int, OwnedWs> g_ws;
 
+// frees device memory that held a workspace, forgetting its plan
+int free_workspace(void *p) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    g_plans.erase(std::make_pair(dev, (const void *)p));
+  }
+  HIP_TRY(hipFree(p));
+  return FIUNCHO_OK;
+}
+
 int owned_workspace(size_t need, void **out) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -769,34 +848,37 @@ void fiuncho_set_profiling(int enable) { t_profiling = enable != 0; }
 int fiuncho_get_profile(fiuncho_profile *out) {
   if (!out) return fail(FIUNCHO_E_NULL, "out is NULL");
   if (t_calls.empty()) return fail(FIUNCHO_E_NULL, "no profiled call on this thread");
-  double a = 0, b = 0, c = 0, d = 0;
+  // phase i runs from event i to event i + 1; the total from the first to the last
+  double ph[kProfEvents] = {0};
   for (ProfCall &pc : t_calls) {
-    HIP_TRY(hipEventSynchronize(pc.ev[3]));
+    HIP_TRY(hipEventSynchronize(pc.ev[kProfEvents - 1]));
+    for (int i = 0; i + 1 < kProfEvents; ++i) {
+      float x = 0;
+      HIP_TRY(hipEventElapsedTime(&x, pc.ev[i], pc.ev[i + 1]));
+      ph[i] += x;
+    }
     float x = 0;
-    HIP_TRY(hipEventElapsedTime(&x, pc.ev[0], pc.ev[1]));
-    a += x;
-    HIP_TRY(hipEventElapsedTime(&x, pc.ev[1], pc.ev[2]));
-    b += x;
-    HIP_TRY(hipEventElapsedTime(&x, pc.ev[2], pc.ev[3]));
-    c += x;
-    HIP_TRY(hipEventElapsedTime(&x, pc.ev[0], pc.ev[3]));
-    d += x;
+    HIP_TRY(hipEventElapsedTime(&x, pc.ev[0], pc.ev[kProfEvents - 1]));
+    ph[kProfEvents - 1] += x;
   }
   const double n = (double)t_calls.size();
   const ProfCall &last = t_calls.back();
   JobState s0;
   HIP_TRY(hipMemcpy(&s0, last.state0, sizeof(JobState), hipMemcpyDeviceToHost));
-  out->pack_ms = (float)(a / n);
-  out->scan_ms = (float)(b / n);
-  out->select_ms = (float)(c / n);
-  out->total_ms = (float)(d / n);
+  out->pack_ms = (float)(ph[0] / n);
+  out->pilot_ms = (float)(ph[1] / n);
+  out->scan_ms = (float)(ph[2] / n);
+  out->mfma_ms = (float)(ph[3] / n);
+  out->select_ms = (float)(ph[4] / n);
+  out->total_ms = (float)(ph[5] / n);
   out->calls = (uint32_t)t_calls.size();
   out->combinations = last.combos;
   out->candidates = s0.cand_count;
   out->kept = s0.l2_count;
   out->flags = s0.flags;
+  out->kernels = last.kernels;
   for (ProfCall &pc : t_calls)
-    for (int i = 0; i < 4; ++i) t_free.push_back(pc.ev[i]);
+    for (int i = 0; i < kProfEvents; ++i) t_free.push_back(pc.ev[i]);
   t_calls.clear();
   t_cur = nullptr;
   return FIUNCHO_OK;
@@ -958,7 +1040,8 @@ int fiuncho_contingency(const uint8_t *genotypes, const uint8_t *phenotype, uint
   }
 }
 
-int fiuncho_shard_counts(uint32_t snps, int order, uint32_t units, int scheme, uint64_t *counts) {
+int fiuncho_shard_counts(uint32_t snps, uint32_t samples, int order, uint32_t units, int scheme,
+                         uint64_t *counts) {
   t_err.clear();
   if (!counts) return fail(FIUNCHO_E_NULL, "counts is NULL");
   if (units == 0) return fail(FIUNCHO_E_SHAPE, "units must be positive");
@@ -971,7 +1054,8 @@ int fiuncho_shard_counts(uint32_t snps, int order, uint32_t units, int scheme, u
   for (uint32_t u = 0; u < units; ++u) counts[u] = 0;
   const uint32_t k = (uint32_t)order;
   if (scheme == 1) {
-    for_each_tile(snps, k, job_path(snps, k), [&](u64 lt, u64 c) { counts[tile_shard(lt, units)] += c; });
+    for_each_tile(snps, k, job_path(snps, samples, k),
+                  [&](u64 lt, u64 c) { counts[tile_shard(lt, units)] += c; });
     return FIUNCHO_OK;
   }
   if (k == 1) {  // a single, empty prefix
@@ -995,6 +1079,133 @@ int fiuncho_shard_counts(uint32_t snps, int order, uint32_t units, int scheme, u
     for (uint32_t z = (uint32_t)q + 1; z < r; ++z) c[z] = c[z - 1] + 1;
   }
   return FIUNCHO_OK;
+}
+
+int fiuncho_get_kernel(uint32_t snps, uint32_t samples, int order) {
+  t_err.clear();
+  if (order < 1 || order > FIUNCHO_MAX_ORDER || (uint32_t)order > snps)
+    return fail(FIUNCHO_E_ORDER, "order must be in [1, min(snps, 8)]");
+  return choose_kernel(snps, samples, (uint32_t)order);
+}
+
+int fiuncho_set_kernel(uint32_t snps, uint32_t samples, int order, int kernel) {
+  t_err.clear();
+  if (order < 1 || order > FIUNCHO_MAX_ORDER || (uint32_t)order > snps)
+    return fail(FIUNCHO_E_ORDER, "order must be in [1, min(snps, 8)]");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const ShapeKey key = shape_key(snps, samples, (uint32_t)order);
+  if (kernel == FIUNCHO_KERNEL_AUTO) {
+    g_tuned.erase(key);
+    return FIUNCHO_OK;
+  }
+  if (!kernel_valid(kernel, snps, (uint32_t)order))
+    return fail(FIUNCHO_E_SHAPE, "kernel " + std::to_string(kernel) + " does not handle order " +
+                                     std::to_string(order));
+  g_tuned[key] = kernel;
+  return FIUNCHO_OK;
+}
+
+int fiuncho_autotune(uint32_t snps, uint32_t samples, int order, uint32_t reps, int *kernel) {
+  t_err.clear();
+  try {
+    if (!kernel) return fail(FIUNCHO_E_NULL, "kernel is NULL");
+    fiuncho_job job;
+    std::memset(&job, 0, sizeof(job));
+    job.snps = snps;
+    job.samples = samples;
+    job.order = order;
+    job.top_n = 16;
+    int st = check_shape(job, false);
+    if (st) return st;
+    st = check_device();
+    if (st) return st;
+    const uint32_t k = (uint32_t)order;
+    std::vector<int> cands;
+    for (int c : {FIUNCHO_KERNEL_POPCOUNT, FIUNCHO_KERNEL_PAIRS, FIUNCHO_KERNEL_MFMA})
+      if (kernel_valid(c, snps, k)) cands.push_back(c);
+    int best = cands[0];
+    if (cands.size() > 1) {
+      // seeded synthetic data of this shape: uniform genotypes, alternating classes
+      std::vector<uint8_t> G((size_t)snps * samples), y(samples);
+      u64 x = 0x9E3779B97F4A7C15ull ^ ((u64)snps << 32 | samples);
+      for (auto &g : G) {
+        x ^= x << 13;
+        x ^= x >> 7;
+        x ^= x << 17;
+        g = (uint8_t)((x >> 11) % 3);
+      }
+      for (uint32_t s2 = 0; s2 < samples; ++s2) y[s2] = (uint8_t)(s2 & 1);
+      struct Dev {
+        void *p = nullptr;
+        ~Dev() {
+          if (p) (void)hipFree(p);
+        }
+      } dG, dy, dout, dn, dst;
+      HIP_TRY(hipMalloc(&dG.p, G.size()));
+      HIP_TRY(hipMalloc(&dy.p, y.size()));
+      HIP_TRY(hipMalloc(&dout.p, sizeof(fiuncho_hit) * job.top_n));
+      HIP_TRY(hipMalloc(&dn.p, sizeof(uint32_t)));
+      HIP_TRY(hipMalloc(&dst.p, sizeof(int32_t)));
+      HIP_TRY(hipMemcpy(dG.p, G.data(), G.size(), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(dy.p, y.data(), y.size(), hipMemcpyHostToDevice));
+      job.genotypes = static_cast<const uint8_t *>(dG.p);
+      job.phenotype = static_cast<const uint8_t *>(dy.p);
+      job.out = static_cast<fiuncho_hit *>(dout.p);
+      job.n_out = static_cast<uint32_t *>(dn.p);
+      job.status = static_cast<int32_t *>(dst.p);
+      struct Force {
+        ~Force() { t_force_kernel = FIUNCHO_KERNEL_AUTO; }
+      } restore;
+      hipEvent_t e0, e1;
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      float best_ms = 0.f;
+      for (int c : cands) {
+        t_force_kernel = c;
+        Layout L;
+        st = make_layout(&job, 1, false, 1, L);
+        if (st) break;
+        void *ws = nullptr;
+        if (hipMalloc(&ws, L.total) != hipSuccess) {
+          st = fail(FIUNCHO_E_DEVICE, "autotune: no device memory for the workspace");
+          break;
+        }
+        st = batch_impl(&job, 1, FIUNCHO_DEVICE_PTRS, ws, L.total, nullptr, 1, nullptr);
+        if (st == FIUNCHO_OK && hipEventRecord(e0, nullptr) != hipSuccess) st = FIUNCHO_E_DEVICE;
+        for (uint32_t r = 0; st == FIUNCHO_OK && r < std::max<uint32_t>(reps, 1); ++r)
+          st = batch_impl(&job, 1, FIUNCHO_DEVICE_PTRS, ws, L.total, nullptr, 1, nullptr);
+        float ms = 0.f;
+        if (st == FIUNCHO_OK && (hipEventRecord(e1, nullptr) != hipSuccess ||
+                                 hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          st = fail(FIUNCHO_E_DEVICE, "autotune: event timing failed");
+        int32_t status = 0;
+        if (st == FIUNCHO_OK && hipMemcpy(&status, dst.p, sizeof(status), hipMemcpyDeviceToHost) != hipSuccess)
+          st = fail(FIUNCHO_E_DEVICE, "autotune: status copy failed");
+        const int fst = free_workspace(ws);
+        if (st == FIUNCHO_OK) st = fst;
+        if (st == FIUNCHO_OK && status != 0) st = fail(status, "autotune: the search failed");
+        if (st) break;
+        if (c == cands[0] || ms < best_ms) {
+          best_ms = ms;
+          best = c;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      if (st) return st;
+    }
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tuned[shape_key(snps, samples, k)] = best;
+    }
+    *kernel = best;
+    return FIUNCHO_OK;
+  } catch (const std::exception &e) {
+    return fail(FIUNCHO_E_DEVICE, std::string("internal error: ") + e.what());
+  } catch (...) {
+    return fail(FIUNCHO_E_DEVICE, "internal error");
+  }
 }
 
 int fiuncho_score(const uint8_t *genotypes, const uint8_t *phenotype, uint32_t snps,

@@ -28,6 +28,11 @@ E_DEVICE = -9
 MAX_ORDER = 8
 MAX_TOPN = 2048
 DEVICE_PTRS = 1
+UPLOAD_PLAN = 2
+KERNEL_AUTO = 0
+KERNEL_POPCOUNT = 1
+KERNEL_PAIRS = 2
+KERNEL_MFMA = 3
 
 # every entry point declared in include/fiuncho.h
 EXPORTS = (
@@ -37,6 +42,9 @@ EXPORTS = (
     "fiuncho_contingency",
     "fiuncho_score",
     "fiuncho_shard_counts",
+    "fiuncho_get_kernel",
+    "fiuncho_set_kernel",
+    "fiuncho_autotune",
     "fiuncho_last_error",
     "fiuncho_set_profiling",
     "fiuncho_get_profile",
@@ -66,7 +74,9 @@ class Job(ctypes.Structure):
 class Profile(ctypes.Structure):
     _fields_ = [
         ("pack_ms", ctypes.c_float),
+        ("pilot_ms", ctypes.c_float),
         ("scan_ms", ctypes.c_float),
+        ("mfma_ms", ctypes.c_float),
         ("select_ms", ctypes.c_float),
         ("total_ms", ctypes.c_float),
         ("calls", ctypes.c_uint32),
@@ -74,7 +84,7 @@ class Profile(ctypes.Structure):
         ("combinations", ctypes.c_uint64),
         ("candidates", ctypes.c_uint64),
         ("kept", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("kernels", ctypes.c_uint32),
     ]
 
 
@@ -120,8 +130,15 @@ def lib() -> ctypes.CDLL:
                                     ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p]
         L.fiuncho_shard_counts.restype = ctypes.c_int
-        L.fiuncho_shard_counts.argtypes = [ctypes.c_uint32, ctypes.c_int, ctypes.c_uint32,
-                                           ctypes.c_int, ctypes.c_void_p]
+        L.fiuncho_shard_counts.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                           ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p]
+        L.fiuncho_get_kernel.restype = ctypes.c_int
+        L.fiuncho_get_kernel.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]
+        L.fiuncho_set_kernel.restype = ctypes.c_int
+        L.fiuncho_set_kernel.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_int]
+        L.fiuncho_autotune.restype = ctypes.c_int
+        L.fiuncho_autotune.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_uint32,
+                                       ctypes.POINTER(ctypes.c_int)]
         L.fiuncho_last_error.restype = ctypes.c_char_p
         L.fiuncho_last_error.argtypes = []
         L.fiuncho_set_profiling.restype = None
@@ -201,12 +218,33 @@ PREFIX_ROUND_ROBIN = 0
 TILE_ROUND_ROBIN = 1
 
 
-def shard_counts(snps: int, order: int, units: int, scheme: int = PREFIX_ROUND_ROBIN) -> np.ndarray:
+def shard_counts(snps: int, samples: int, order: int, units: int,
+                 scheme: int = PREFIX_ROUND_ROBIN) -> np.ndarray:
     """Combinations per processing unit under a static distribution
     (fiuncho_shard_counts; host-only)."""
     counts = np.zeros(units, dtype=np.uint64)
-    _check(lib().fiuncho_shard_counts(snps, order, units, scheme, counts.ctypes.data))
+    _check(lib().fiuncho_shard_counts(snps, samples, order, units, scheme, counts.ctypes.data))
     return counts
+
+
+def get_kernel(snps: int, samples: int, order: int) -> int:
+    """KERNEL_* value a job of this shape would use (fiuncho_get_kernel)."""
+    k = lib().fiuncho_get_kernel(snps, samples, order)
+    if k < 0:
+        raise FiunchoError(k, last_error())
+    return k
+
+
+def set_kernel(snps: int, samples: int, order: int, kernel: int):
+    _check(lib().fiuncho_set_kernel(snps, samples, order, kernel))
+
+
+def autotune(snps: int, samples: int, order: int, reps: int = 3) -> int:
+    """Times the kernels for this shape on the device and records the fastest
+    (fiuncho_autotune); returns its KERNEL_* value."""
+    k = ctypes.c_int(0)
+    _check(lib().fiuncho_autotune(snps, samples, order, reps, ctypes.byref(k)))
+    return k.value
 
 
 def set_profiling(enable: bool):
@@ -265,9 +303,10 @@ class DeviceBatch:
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
         self.ws_ptr = (self.ws.data_ptr() + 255) & ~255
 
-    def run(self, stream=None):
+    def run(self, stream=None, upload_plan: bool = False):
         s = stream if stream is not None else self.torch.cuda.current_stream()
-        _check(lib().fiuncho_scan_batch(self.jobs, len(self.shapes), DEVICE_PTRS, self.ws_ptr,
+        flags = DEVICE_PTRS | (UPLOAD_PLAN if upload_plan else 0)
+        _check(lib().fiuncho_scan_batch(self.jobs, len(self.shapes), flags, self.ws_ptr,
                                         self.ws_bytes, s.cuda_stream))
 
     def capture(self, profile: bool = False):

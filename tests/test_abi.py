@@ -31,6 +31,7 @@ def test_hit_layout_matches_header():
     # snp[8] (32 B) + rank (8 B) + mi (8 B) + mi32 + rel_err (8 B)
     assert fiuncho.HIT_DTYPE.itemsize == 56
     assert ctypes.sizeof(fiuncho.Job) == 64
+    assert ctypes.sizeof(fiuncho.Profile) == 56
 
 
 def _data(n=6, m=40, seed=0):
@@ -95,3 +96,38 @@ def test_no_cpu_fallback_in_product():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "liboracle" not in text, f
+
+
+def test_kernel_choice_table(monkeypatch):
+    """The kernel each shape gets: built-in rule, table entries set and
+    cleared per (order, snps, words) bucket, environment overrides first;
+    the tile dealing follows the chosen kernel.  Host-only."""
+    monkeypatch.delenv("FIUNCHO_ORDER2_MFMA", raising=False)
+    monkeypatch.delenv("FIUNCHO_ORDER3_PAIRS", raising=False)
+    L = fiuncho.lib()
+    assert fiuncho.get_kernel(100, 1600, 2) == fiuncho.KERNEL_POPCOUNT
+    assert fiuncho.get_kernel(4000, 16000, 2) == fiuncho.KERNEL_MFMA
+    assert fiuncho.get_kernel(1000, 6400, 3) == fiuncho.KERNEL_PAIRS
+    assert fiuncho.get_kernel(200, 4000, 4) == fiuncho.KERNEL_POPCOUNT
+    assert L.fiuncho_get_kernel(5, 100, 6) == fiuncho.E_ORDER
+    before = fiuncho.shard_counts(300, 500, 2, 5, fiuncho.TILE_ROUND_ROBIN)
+    try:
+        fiuncho.set_kernel(300, 500, 2, fiuncho.KERNEL_MFMA)
+        assert fiuncho.get_kernel(300, 500, 2) == fiuncho.KERNEL_MFMA
+        # same bucket (bit lengths of snps and of words), other sizes
+        assert fiuncho.get_kernel(400, 450, 2) == fiuncho.KERNEL_MFMA
+        assert fiuncho.get_kernel(600, 500, 2) == fiuncho.KERNEL_POPCOUNT
+        after = fiuncho.shard_counts(300, 500, 2, 5, fiuncho.TILE_ROUND_ROBIN)
+        assert int(after.sum()) == int(before.sum()) and after.tolist() != before.tolist()
+        monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", "0")
+        assert fiuncho.get_kernel(300, 500, 2) == fiuncho.KERNEL_POPCOUNT
+        monkeypatch.delenv("FIUNCHO_ORDER2_MFMA")
+    finally:
+        fiuncho.set_kernel(300, 500, 2, fiuncho.KERNEL_AUTO)
+    assert fiuncho.get_kernel(300, 500, 2) == fiuncho.KERNEL_POPCOUNT
+    assert L.fiuncho_set_kernel(300, 500, 3, fiuncho.KERNEL_MFMA) == fiuncho.E_SHAPE
+    assert L.fiuncho_set_kernel(300, 500, 2, fiuncho.KERNEL_PAIRS) == fiuncho.E_SHAPE
+    assert L.fiuncho_set_kernel(300, 500, 2, 9) == fiuncho.E_SHAPE
+    k = ctypes.c_int(0)
+    assert L.fiuncho_autotune(300, 500, 2, 1, None) == fiuncho.E_NULL
+    assert L.fiuncho_autotune(3, 500, 4, 1, ctypes.byref(k)) == fiuncho.E_ORDER

@@ -70,5 +70,5 @@ def test_order2_mfma_shards(n, P, mfma):
     check_hits_against_oracle(G, y, 2, top, _merge(lists, top))
     if math.comb(n, 2) <= fiuncho.MAX_TOPN:
         full = _run_shards(G, y, 2, fiuncho.MAX_TOPN, P)
-        sizes = fiuncho.shard_counts(n, 2, P, fiuncho.TILE_ROUND_ROBIN)
+        sizes = fiuncho.shard_counts(n, 200, 2, P, fiuncho.TILE_ROUND_ROBIN)
         assert [len(h) for h in full] == sizes.tolist()

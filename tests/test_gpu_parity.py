@@ -194,6 +194,11 @@ def test_order2_dense_workload():
     full_size_check(synth.order2_dense(), 20000, 32)
 
 
+def test_order2_dense_workload_popcount_kernel(monkeypatch):
+    monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", "0")
+    full_size_check(synth.order2_dense(), 20000, 33)
+
+
 def test_order4_high_order_workload():
     full_size_check(synth.high_order(4), 20000, 34)
 
@@ -362,7 +367,7 @@ def test_shards_cover_every_combination_once(n, k, P):
     total = math.comb(n, k)
     assert total <= fiuncho.MAX_TOPN
     lists = _run_shards(G, y, k, fiuncho.MAX_TOPN, P)
-    sizes = fiuncho.shard_counts(n, k, P, fiuncho.TILE_ROUND_ROBIN)
+    sizes = fiuncho.shard_counts(n, 150, k, P, fiuncho.TILE_ROUND_ROBIN)
     assert [len(h) for h in lists] == sizes.tolist()
     ranks = np.sort(np.concatenate([h["rank"] for h in lists]))
     np.testing.assert_array_equal(ranks, np.arange(total, dtype=np.uint64))
@@ -382,3 +387,43 @@ def test_shards_with_an_empty_class():
         np.testing.assert_array_equal(h["rank"], s + P * np.arange(want, dtype=np.uint64))
         assert np.all(h["mi"] == 0.0)
     np.testing.assert_array_equal(_merge(lists, top_n)["rank"], np.arange(top_n, dtype=np.uint64))
+
+
+# ---------------------------------------------------------------------------
+# kernel choice: autotuning and the plan upload flag
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,m,k", [(300, 500, 2), (70, 300, 3)])
+def test_autotune_then_search(n, m, k):
+    say(f"case: autotune n={n} m={m} k={k}")
+    try:
+        kern = fiuncho.autotune(n, m, k, reps=2)
+        assert kern in ((fiuncho.KERNEL_POPCOUNT, fiuncho.KERNEL_MFMA) if k == 2 else
+                        (fiuncho.KERNEL_POPCOUNT, fiuncho.KERNEL_PAIRS))
+        assert fiuncho.get_kernel(n, m, k) == kern
+        G, y = random_dataset(60 + k, n, m, 0.5)
+        fiuncho.set_profiling(True)
+        b = fiuncho.DeviceBatch([synth.Dataset(G, y, k, 30)])
+        b.run()
+        (status, hits), = b.results()
+        prof = fiuncho.get_profile()
+        fiuncho.set_profiling(False)
+        assert status == 0
+        assert prof["kernels"] == 1 << kern
+        check_hits_against_oracle(G, y, k, 30, hits)
+    finally:
+        fiuncho.set_kernel(n, m, k, fiuncho.KERNEL_AUTO)
+
+
+def test_plan_upload_flag_after_workspace_reuse():
+    """A workspace overwritten between calls: with FIUNCHO_UPLOAD_PLAN the
+    next call uploads the plan again and the results are right."""
+    d = synth.generate(80, 400, seed=12, order=3, top_n=20)
+    b = fiuncho.DeviceBatch([d])
+    b.run()
+    first = b.results()
+    b.ws.fill_(0)
+    b.run(upload_plan=True)
+    again = b.results()
+    assert first[0][0] == 0 and first[0][1].tobytes() == again[0][1].tobytes()
+    check_hits_against_oracle(d.genotypes, d.phenotype, 3, 20, again[0][1])

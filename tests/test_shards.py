@@ -24,7 +24,7 @@ def imbalance(counts, n, k):
 
 def test_fig4_example():
     f = GOLD["fig4"]
-    got = fiuncho.shard_counts(f["variants"], f["order"], f["units"], fiuncho.PREFIX_ROUND_ROBIN)
+    got = fiuncho.shard_counts(f["variants"], 0, f["order"], f["units"], fiuncho.PREFIX_ROUND_ROBIN)
     assert got.tolist() == f["combinations_per_unit"]
 
 
@@ -42,7 +42,7 @@ def test_prefix_scheme_by_enumeration(n, k, p):
         want = np.zeros(p, np.uint64)
         for c in itertools.combinations(range(n), k):
             want[unit[c[:-1]]] += 1
-    got = fiuncho.shard_counts(n, k, p, fiuncho.PREFIX_ROUND_ROBIN)
+    got = fiuncho.shard_counts(n, 0, k, p, fiuncho.PREFIX_ROUND_ROBIN)
     np.testing.assert_array_equal(got, want)
 
 
@@ -52,16 +52,16 @@ def test_prefix_scheme_by_enumeration(n, k, p):
 def test_counts_partition_the_search(scheme, n, k):
     total = math.comb(n, k)
     for p in (1, 2, 3, 7, 64, 1000):
-        c = fiuncho.shard_counts(n, k, p, scheme)
+        c = fiuncho.shard_counts(n, 1000, k, p, scheme)
         assert len(c) == p and int(c.sum()) == total, p
-    assert fiuncho.shard_counts(n, k, 1, scheme).tolist() == [total]
+    assert fiuncho.shard_counts(n, 1000, k, 1, scheme).tolist() == [total]
 
 
 @pytest.mark.parametrize("n", [2, 63, 64, 65, 129, 300])
 def test_matrix_core_tiles_partition_order2(n, monkeypatch):
     monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", "1")
     for p in (1, 3, 8):
-        c = fiuncho.shard_counts(n, 2, p, fiuncho.TILE_ROUND_ROBIN)
+        c = fiuncho.shard_counts(n, 1000, 2, p, fiuncho.TILE_ROUND_ROBIN)
         assert int(c.sum()) == math.comb(n, 2)
 
 
@@ -75,8 +75,8 @@ def test_balance_of_section_5_1():
     for k_s, n in b["variants_by_order"].items():
         k = int(k_s)
         for p in range(b["units_min"], b["units_max"] + 1, 18):
-            e0 = imbalance(fiuncho.shard_counts(n, k, p, fiuncho.PREFIX_ROUND_ROBIN), n, k)
-            e1 = imbalance(fiuncho.shard_counts(n, k, p, fiuncho.TILE_ROUND_ROBIN), n, k)
+            e0 = imbalance(fiuncho.shard_counts(n, 2048, k, p, fiuncho.PREFIX_ROUND_ROBIN), n, k)
+            e1 = imbalance(fiuncho.shard_counts(n, 2048, k, p, fiuncho.TILE_ROUND_ROBIN), n, k)
             if (k, p) != (3, 522):
                 assert e0 < b["stated_max_percent"], (k, p, e0)
             worst_paper = max(worst_paper, e0)
@@ -88,13 +88,13 @@ def test_balance_of_section_5_1():
 def test_shard_counts_errors():
     L = fiuncho.lib()
     buf = np.zeros(4, np.uint64)
-    assert L.fiuncho_shard_counts(10, 2, 4, 0, None) == fiuncho.E_NULL
-    assert L.fiuncho_shard_counts(10, 2, 0, 0, buf.ctypes.data) == fiuncho.E_SHAPE
-    assert L.fiuncho_shard_counts(10, 2, 4, 2, buf.ctypes.data) == fiuncho.E_SHAPE
-    assert L.fiuncho_shard_counts(0, 1, 4, 0, buf.ctypes.data) == fiuncho.E_SHAPE
-    assert L.fiuncho_shard_counts(10, 9, 4, 0, buf.ctypes.data) == fiuncho.E_ORDER
-    assert L.fiuncho_shard_counts(3, 4, 4, 1, buf.ctypes.data) == fiuncho.E_ORDER
-    assert L.fiuncho_shard_counts(1 << 20, 8, 4, 0, buf.ctypes.data) == fiuncho.E_OVERFLOW
+    assert L.fiuncho_shard_counts(10, 64, 2, 4, 0, None) == fiuncho.E_NULL
+    assert L.fiuncho_shard_counts(10, 64, 2, 0, 0, buf.ctypes.data) == fiuncho.E_SHAPE
+    assert L.fiuncho_shard_counts(10, 64, 2, 4, 2, buf.ctypes.data) == fiuncho.E_SHAPE
+    assert L.fiuncho_shard_counts(0, 64, 1, 4, 0, buf.ctypes.data) == fiuncho.E_SHAPE
+    assert L.fiuncho_shard_counts(10, 64, 9, 4, 0, buf.ctypes.data) == fiuncho.E_ORDER
+    assert L.fiuncho_shard_counts(3, 64, 4, 4, 1, buf.ctypes.data) == fiuncho.E_ORDER
+    assert L.fiuncho_shard_counts(1 << 20, 64, 8, 4, 0, buf.ctypes.data) == fiuncho.E_OVERFLOW
 
 
 def test_job_shard_index_checked_on_host():
