@@ -277,7 +277,7 @@ struct JobLayout {
 struct Layout {
   std::vector<JobLayout> jobs;
   std::vector<uint32_t> order;  // tile-space order of the jobs (costliest first)
-  uint32_t nmax, kmax, max_n_pad, max_cand_cap, max_l2_cap, max_pairs_n;
+  uint32_t nmax, kmax, max_n_pad, max_wcap, max_cand_cap, max_l2_cap, max_pairs_n;
   size_t plan_begin, plan_end;  // uploaded region
   size_t off_desc, off_jts, off_jps, off_binom, off_counter;
   uint32_t n_scan;  // jobs [0, n_scan) of the tile-space order run in scan_kernel, the rest in mfma2_kernel
@@ -292,6 +292,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
   L.nmax = 0;
   L.kmax = 0;
   L.max_n_pad = 0;
+  L.max_wcap = 0;
   L.max_cand_cap = 0;
   L.max_l2_cap = 0;
   L.max_pairs_n = 0;
@@ -343,6 +344,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     L.nmax = std::max(L.nmax, J.n);
     L.kmax = std::max(L.kmax, J.k);
     L.max_n_pad = std::max(L.max_n_pad, J.n_pad);
+    L.max_wcap = std::max(L.max_wcap, J.wcap);
     L.max_cand_cap = std::max(L.max_cand_cap, J.cand_cap);
     L.max_l2_cap = std::max(L.max_l2_cap, J.l2_cap);
 
@@ -680,7 +682,7 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
     return st;
   if ((st = prof_record(0, s))) return st;
   fiuncho::launch_init(g, s);
-  fiuncho::launch_pack(g, L.max_n_pad, s);
+  fiuncho::launch_pack(g, L.max_n_pad, L.max_wcap, s);
   if (L.max_pairs_n) fiuncho::launch_pairs(g, L.max_pairs_n, s);
   if ((st = prof_record(1, s))) return st;
   // job tile and pilot starts in tile-space order (as uploaded)
@@ -1000,7 +1002,7 @@ int explicit_impl(const uint8_t *genotypes, const uint8_t *phenotype, uint32_t s
   HIP_TRY(hipMemcpyAsync(ws + rank_off, ranks, sizeof(u64) * n_ranks, hipMemcpyHostToDevice, s));
   const Globals g = make_globals(L, ws);
   fiuncho::launch_init(g, s);
-  fiuncho::launch_pack(g, L.max_n_pad, s);
+  fiuncho::launch_pack(g, L.max_n_pad, L.max_wcap, s);
   fiuncho::launch_tables(g, reinterpret_cast<const u64 *>(ws + rank_off), n_ranks,
                          tables ? reinterpret_cast<uint32_t *>(ws + tab_off) : nullptr,
                          est ? reinterpret_cast<float *>(ws + est_off) : nullptr,

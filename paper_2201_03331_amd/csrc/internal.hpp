@@ -129,7 +129,7 @@ struct Globals {
 
 // launchers (kernels.hip)
 void launch_init(const Globals &g, hipStream_t s);
-void launch_pack(const Globals &g, uint32_t max_n_pad, hipStream_t s);
+void launch_pack(const Globals &g, uint32_t max_n_pad, uint32_t max_wcap, hipStream_t s);
 void launch_pairs(const Globals &g, uint32_t max_n, hipStream_t s);
 void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s);
 void launch_mfma2(const Globals &g, int grid, hipStream_t s);

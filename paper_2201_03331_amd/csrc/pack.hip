@@ -9,8 +9,8 @@
 
 namespace fiuncho {
 
-// Clears every job's run state, survivor histogram and pilot score slots, and
-// the tile counters.
+// Clears every job's run state, survivor histograms, class counts and pilot
+// score slots, and the tile counters.
 // (A fill kernel rather than hipMemsetAsync, so that the sequence can be
 // captured into a graph and replayed.)
 __global__ void init_kernel(Globals g) {
@@ -19,6 +19,7 @@ __global__ void init_kernel(Globals g) {
     J.hist[i] = 0;
     if (J.phist) J.phist[i] = 0;
   }
+  for (uint32_t i = threadIdx.x; i < J.n * 6; i += blockDim.x) J.marg[i] = 0;
   {
     uint4 *pk = reinterpret_cast<uint4 *>(J.cand);
     const uint32_t n4 = J.pilot_slots / 4;
@@ -117,6 +118,8 @@ __global__ __launch_bounds__(1024) void partition_kernel(Globals g) {
 // Bs[j][w][g] (g = 0, 1, 2, then a zero word) serves wave-uniform (scalar)
 // reads of one variant.
 __global__ __launch_bounds__(256) void pack_kernel(Globals g) {
+  // one wave per (variant j, block of 64 words): blockIdx.x = group of 4
+  // variants, blockIdx.y = job, blockIdx.z = word block
   const JobDesc &J = g.jobs[blockIdx.y];
   const JobState *st = J.state;
   const uint32_t lane = threadIdx.x & 63;
@@ -125,10 +128,14 @@ __global__ __launch_bounds__(256) void pack_kernel(Globals g) {
   if (st->status != 0) return;
   const uint32_t m0 = st->m0, m1 = st->m1;
   const uint32_t W0 = st->W0, W1 = st->W1, W = W0 + W1;
+  const uint32_t wb = blockIdx.z * 64;
+  if (wb >= W) return;
+  const uint32_t we = min(wb + 64, W);
   const uint32_t n_pad = J.n_pad, wcap = J.wcap;
   if (j >= J.n) {
     // padding variants read by the last lanes of a tile: all-zero rows
-    for (uint32_t w = lane; w < W; w += 64) {
+    const uint32_t w = wb + lane;
+    if (w < we) {
       J.Bv[((size_t)w * n_pad + j) * 2 + 0] = 0;
       J.Bv[((size_t)w * n_pad + j) * 2 + 1] = 0;
     }
@@ -138,53 +145,56 @@ __global__ __launch_bounds__(256) void pack_kernel(Globals g) {
   uint32_t cnt[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   bool bad = false;
   u64 keep0 = 0, keep1 = 0, keep2 = 0;
-  // 8 words at a time so that 8 independent gathers per lane are in flight
-  for (uint32_t w0 = 0; w0 < W; w0 += 8) {
+  // 8 words at a time so that 8 independent gathers per lane are in flight;
+  // lane (w - wb) keeps word w and stores it at the end
+  for (uint32_t w0 = wb; w0 < we; w0 += 8) {
     uint32_t gv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const uint32_t w = w0 + u;
       const uint32_t cls = (w >= W0);
       const uint32_t p = (w - (cls ? W0 : 0)) * 64 + lane;
-      const bool valid = w < W && p < (cls ? m1 : m0);
+      const bool valid = w < we && p < (cls ? m1 : m0);
       gv[u] = valid ? (uint32_t)row[J.idx[(cls ? m0 : 0) + p]] : 0xffffffffu;
       bad |= valid && gv[u] > 2;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const uint32_t w = w0 + u;
-      if (w >= W) break;
+      if (w >= we) break;
       const uint32_t cls = (w >= W0);
       const u64 b0 = ballot(gv[u] == 0), b1 = ballot(gv[u] == 1), b2 = ballot(gv[u] == 2);
       cnt[0][cls] += popc64(b0);
       cnt[1][cls] += popc64(b1);
       cnt[2][cls] += popc64(b2);
-      // lane (w % 64) keeps word w; every 64 words (and at the end) all lanes store
-      if (lane == (w & 63)) {
+      if (lane == w - wb) {
         keep0 = b0;
         keep1 = b1;
         keep2 = b2;
       }
-      if ((w & 63) == 63 || w + 1 == W) {
-        const uint32_t wl = (w & ~63u) + lane;
-        if (wl <= w) {
-          J.Bv[((size_t)wl * n_pad + j) * 2 + 0] = keep0;
-          J.Bv[((size_t)wl * n_pad + j) * 2 + 1] = keep1;
-          u64 *bs = J.Bs + ((size_t)j * wcap + wl) * 4;
-          bs[0] = keep0;
-          bs[1] = keep1;
-          bs[2] = keep2;
-          bs[3] = 0;
-        }
-      }
+    }
+  }
+  {
+    const uint32_t wl = wb + lane;
+    if (wl < we) {
+      J.Bv[((size_t)wl * n_pad + j) * 2 + 0] = keep0;
+      J.Bv[((size_t)wl * n_pad + j) * 2 + 1] = keep1;
+      u64 *bs = J.Bs + ((size_t)j * wcap + wl) * 4;
+      bs[0] = keep0;
+      bs[1] = keep1;
+      bs[2] = keep2;
+      bs[3] = 0;
     }
   }
   if (ballot(bad)) {
     if (lane == 0) atomicMin(&J.state->status, (int32_t)FIUNCHO_E_GENOTYPE);
   }
-  if (lane == 0) {
-    for (int gg = 0; gg < 3; ++gg)
-      for (int c = 0; c < 2; ++c) J.marg[((size_t)j * 3 + gg) * 2 + c] = cnt[gg][c];
+  // class counts of this word block; init_kernel cleared them
+  if (lane < 6) {
+    const uint32_t gg = lane >> 1, c = lane & 1;
+    const uint32_t v = gg == 0 ? (c ? cnt[0][1] : cnt[0][0]) : gg == 1 ? (c ? cnt[1][1] : cnt[1][0])
+                                                                  : (c ? cnt[2][1] : cnt[2][0]);
+    if (v) atomicAdd(&J.marg[((size_t)j * 3 + gg) * 2 + c], v);
   }
 }
 
@@ -193,8 +203,9 @@ void launch_init(const Globals &g, hipStream_t s) {
   hipLaunchKernelGGL(partition_kernel, dim3(g.n_jobs), dim3(1024), 0, s, g);
 }
 
-void launch_pack(const Globals &g, uint32_t max_n_pad, hipStream_t s) {
-  hipLaunchKernelGGL(pack_kernel, dim3((max_n_pad + 3) / 4, g.n_jobs), dim3(256), 0, s, g);
+void launch_pack(const Globals &g, uint32_t max_n_pad, uint32_t max_wcap, hipStream_t s) {
+  hipLaunchKernelGGL(pack_kernel, dim3((max_n_pad + 3) / 4, g.n_jobs, (max_wcap + 63) / 64), dim3(256),
+                     0, s, g);
 }
 
 }  // namespace fiuncho
