@@ -323,15 +323,20 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     if (J.shard_index >= J.shard_count)
       return fail(FIUNCHO_E_SHAPE, "shard_index must be below shard_count");
     J.tiles = shard_tiles(J.row_start.back(), J.shard_count, J.shard_index);
-    // pilot sample: 1/32 of the tiles, at most kPilotTiles, for jobs large
-    // enough that the search would otherwise start with a flood of
-    // candidates; its scores live in the candidate buffer until the scan
+    // pilot sample: 1/32 of the tiles, between 16 and kPilotTiles, for jobs
+    // whose search would otherwise start with a flood of candidates (any job
+    // with more combinations than the candidate buffer holds, and every job
+    // of 512 tiles or more); its scores live in the candidate buffer until
+    // the scan
     {
-      const u64 s = std::min<u64>(fiuncho::kPilotTiles, J.tiles / 32);
+      const bool want = J.total > J.cand_cap || J.tiles >= 512;
+      const u64 s = want ? std::min<u64>({J.tiles, (u64)fiuncho::kPilotTiles,
+                                          std::max<u64>(16, J.tiles / 32)})
+                         : 0;
       const u64 per = J.path == fiuncho::kPathMfma2 ? fiuncho::kMfmaPilotEmits : fiuncho::kPilotEmits;
       const u64 slots = s * fiuncho::kScanWaves * per * 64;
       const bool fits = slots * sizeof(uint32_t) <= (u64)J.cand_cap * sizeof(Cand);
-      J.pilot_tiles = (s >= 16 && fits) ? (uint32_t)s : 0;
+      J.pilot_tiles = (s > 0 && fits) ? (uint32_t)s : 0;
       J.pilot_slots = J.pilot_tiles ? (uint32_t)slots : 0;
     }
     const double words = (double)J.wcap;

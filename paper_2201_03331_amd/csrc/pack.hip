@@ -117,84 +117,96 @@ __global__ __launch_bounds__(1024) void partition_kernel(Globals g) {
 // Bv[w][j][g] (g = 0, 1) serves lanes that each own a different variant j;
 // Bs[j][w][g] (g = 0, 1, 2, then a zero word) serves wave-uniform (scalar)
 // reads of one variant.
-__global__ __launch_bounds__(256) void pack_kernel(Globals g) {
-  // one wave per (variant j, block of 64 words): blockIdx.x = group of 4
-  // variants, blockIdx.y = job, blockIdx.z = word block
+constexpr int kPackWaves = 8;  // consecutive variants per workgroup
+
+__global__ __launch_bounds__(kPackWaves * 64) void pack_kernel(Globals g) {
+  // one wave per (variant j, block of 64 words): blockIdx.x = group of
+  // kPackWaves variants, blockIdx.y = job, blockIdx.z = word block.  The
+  // variant-fastest rows (Bv) of the group are staged in LDS and written as
+  // 128 contiguous bytes per word.
+  __shared__ u64 s_bv[64][kPackWaves][2];
   const JobDesc &J = g.jobs[blockIdx.y];
   const JobState *st = J.state;
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t j = uni(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (j >= J.n_pad) return;
-  if (st->status != 0) return;
+  const uint32_t wv = threadIdx.x >> 6;
+  const uint32_t j0 = blockIdx.x * kPackWaves;
+  const uint32_t j = uni(j0 + wv);
+  if (j0 >= J.n_pad) return;  // uniform over the workgroup
+  // the status can change while this kernel runs (other workgroups report
+  // bad genotypes): one read decides for the whole workgroup
+  __shared__ int32_t s_status;
+  if (threadIdx.x == 0) s_status = st->status;
+  __syncthreads();
+  if (s_status != 0) return;
   const uint32_t m0 = st->m0, m1 = st->m1;
   const uint32_t W0 = st->W0, W1 = st->W1, W = W0 + W1;
   const uint32_t wb = blockIdx.z * 64;
-  if (wb >= W) return;
+  if (wb >= W) return;  // uniform over the workgroup
   const uint32_t we = min(wb + 64, W);
   const uint32_t n_pad = J.n_pad, wcap = J.wcap;
-  if (j >= J.n) {
-    // padding variants read by the last lanes of a tile: all-zero rows
-    const uint32_t w = wb + lane;
-    if (w < we) {
-      J.Bv[((size_t)w * n_pad + j) * 2 + 0] = 0;
-      J.Bv[((size_t)w * n_pad + j) * 2 + 1] = 0;
-    }
-    return;
-  }
-  const uint8_t *row = J.G + (size_t)j * J.m;
-  uint32_t cnt[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-  bool bad = false;
   u64 keep0 = 0, keep1 = 0, keep2 = 0;
-  // 8 words at a time so that 8 independent gathers per lane are in flight;
-  // lane (w - wb) keeps word w and stores it at the end
-  for (uint32_t w0 = wb; w0 < we; w0 += 8) {
-    uint32_t gv[8];
+  if (j < J.n) {
+    // variants j >= n (padding read by the last lanes of a tile) keep zeros
+    const uint8_t *row = J.G + (size_t)j * J.m;
+    uint32_t cnt[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    bool bad = false;
+    // 8 words at a time so that 8 independent gathers per lane are in
+    // flight; lane (w - wb) keeps word w
+    for (uint32_t w0 = wb; w0 < we; w0 += 8) {
+      uint32_t gv[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const uint32_t w = w0 + u;
-      const uint32_t cls = (w >= W0);
-      const uint32_t p = (w - (cls ? W0 : 0)) * 64 + lane;
-      const bool valid = w < we && p < (cls ? m1 : m0);
-      gv[u] = valid ? (uint32_t)row[J.idx[(cls ? m0 : 0) + p]] : 0xffffffffu;
-      bad |= valid && gv[u] > 2;
-    }
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t w = w0 + u;
+        const uint32_t cls = (w >= W0);
+        const uint32_t p = (w - (cls ? W0 : 0)) * 64 + lane;
+        const bool valid = w < we && p < (cls ? m1 : m0);
+        gv[u] = valid ? (uint32_t)row[J.idx[(cls ? m0 : 0) + p]] : 0xffffffffu;
+        bad |= valid && gv[u] > 2;
+      }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const uint32_t w = w0 + u;
-      if (w >= we) break;
-      const uint32_t cls = (w >= W0);
-      const u64 b0 = ballot(gv[u] == 0), b1 = ballot(gv[u] == 1), b2 = ballot(gv[u] == 2);
-      cnt[0][cls] += popc64(b0);
-      cnt[1][cls] += popc64(b1);
-      cnt[2][cls] += popc64(b2);
-      if (lane == w - wb) {
-        keep0 = b0;
-        keep1 = b1;
-        keep2 = b2;
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t w = w0 + u;
+        if (w >= we) break;
+        const uint32_t cls = (w >= W0);
+        const u64 b0 = ballot(gv[u] == 0), b1 = ballot(gv[u] == 1), b2 = ballot(gv[u] == 2);
+        cnt[0][cls] += popc64(b0);
+        cnt[1][cls] += popc64(b1);
+        cnt[2][cls] += popc64(b2);
+        if (lane == w - wb) {
+          keep0 = b0;
+          keep1 = b1;
+          keep2 = b2;
+        }
       }
     }
-  }
-  {
     const uint32_t wl = wb + lane;
     if (wl < we) {
-      J.Bv[((size_t)wl * n_pad + j) * 2 + 0] = keep0;
-      J.Bv[((size_t)wl * n_pad + j) * 2 + 1] = keep1;
       u64 *bs = J.Bs + ((size_t)j * wcap + wl) * 4;
       bs[0] = keep0;
       bs[1] = keep1;
       bs[2] = keep2;
       bs[3] = 0;
     }
+    if (ballot(bad)) {
+      if (lane == 0) atomicMin(&J.state->status, (int32_t)FIUNCHO_E_GENOTYPE);
+    }
+    // class counts of this word block; init_kernel cleared them
+    if (lane < 6) {
+      const uint32_t gg = lane >> 1, c = lane & 1;
+      const uint32_t v = gg == 0 ? (c ? cnt[0][1] : cnt[0][0])
+                         : gg == 1 ? (c ? cnt[1][1] : cnt[1][0])
+                                   : (c ? cnt[2][1] : cnt[2][0]);
+      if (v) atomicAdd(&J.marg[((size_t)j * 3 + gg) * 2 + c], v);
+    }
   }
-  if (ballot(bad)) {
-    if (lane == 0) atomicMin(&J.state->status, (int32_t)FIUNCHO_E_GENOTYPE);
-  }
-  // class counts of this word block; init_kernel cleared them
-  if (lane < 6) {
-    const uint32_t gg = lane >> 1, c = lane & 1;
-    const uint32_t v = gg == 0 ? (c ? cnt[0][1] : cnt[0][0]) : gg == 1 ? (c ? cnt[1][1] : cnt[1][0])
-                                                                  : (c ? cnt[2][1] : cnt[2][0]);
-    if (v) atomicAdd(&J.marg[((size_t)j * 3 + gg) * 2 + c], v);
+  s_bv[lane][wv][0] = keep0;
+  s_bv[lane][wv][1] = keep1;
+  __syncthreads();
+  // thread t writes word wb + t / (2 kPackWaves), variant t / 2 mod kPackWaves, plane t mod 2
+  for (uint32_t t = threadIdx.x; t < 64 * kPackWaves * 2; t += blockDim.x) {
+    const uint32_t w = t / (2 * kPackWaves), v = (t / 2) % kPackWaves, gp = t & 1;
+    if (wb + w < we && j0 + v < n_pad)
+      J.Bv[((size_t)(wb + w) * n_pad + j0 + v) * 2 + gp] = s_bv[w][v][gp];
   }
 }
 
@@ -204,8 +216,8 @@ void launch_init(const Globals &g, hipStream_t s) {
 }
 
 void launch_pack(const Globals &g, uint32_t max_n_pad, uint32_t max_wcap, hipStream_t s) {
-  hipLaunchKernelGGL(pack_kernel, dim3((max_n_pad + 3) / 4, g.n_jobs, (max_wcap + 63) / 64), dim3(256),
-                     0, s, g);
+  hipLaunchKernelGGL(pack_kernel, dim3((max_n_pad + kPackWaves - 1) / kPackWaves, g.n_jobs, (max_wcap + 63) / 64),
+                     dim3(kPackWaves * 64), 0, s, g);
 }
 
 }  // namespace fiuncho
