@@ -7,7 +7,7 @@ selection, FP64 rescoring, final ordering) through fiuncho_scan_batch on a
 stream.  Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
-                  [--shard I/P]
+                  [--shard I/P] [--kernel auto|popcount|pairs|mfma] [--autotune]
 
 --shard I/P times one GPU's share of a search split across P GPUs (shard I
 of the job's work tiles); the rate is that share's combinations per second.
@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="order3-1000x6400", choices=sorted(workloads().keys()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel", default="auto", choices=("auto", "popcount", "pairs", "mfma"),
+                    help="force this counting kernel for every dataset shape it handles")
     ap.add_argument("--autotune", action="store_true",
                     help="time the kernels for every dataset shape first (fiuncho_autotune)")
     ap.add_argument("--shard", default=None, metavar="I/P",
@@ -128,6 +130,12 @@ def main():
 
     datasets = workloads()[args.workload]()
     plain = args.workload.endswith("-plain")
+    if args.kernel != "auto":
+        forced = {"popcount": fiuncho.KERNEL_POPCOUNT, "pairs": fiuncho.KERNEL_PAIRS,
+                  "mfma": fiuncho.KERNEL_MFMA}[args.kernel]
+        for d in datasets:
+            if fiuncho.lib().fiuncho_set_kernel(d.n, d.m, d.order, forced) != fiuncho.OK:
+                ap.error(f"kernel {args.kernel} does not handle order {d.order}")
     tuned = {}
     if args.autotune:
         for d in datasets:
