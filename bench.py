@@ -67,6 +67,8 @@ def word_ops_per_combination(k: int, m0: int, m1: int, kernel: int) -> int:
         return 4 * W
     if k == 3 and kernel == fiuncho.KERNEL_PAIRS:
         return 8 * W
+    if k == 4 and kernel == fiuncho.KERNEL_TRIPLES:
+        return 16 * W
     return 2 * 3 ** (k - 1) * W
 
 
@@ -100,7 +102,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="order3-1000x6400", choices=sorted(workloads().keys()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel", default="auto", choices=("auto", "popcount", "pairs", "mfma"),
+    ap.add_argument("--kernel", default="auto", choices=("auto", "popcount", "pairs", "mfma", "triples"),
                     help="force this counting kernel for every dataset shape it handles")
     ap.add_argument("--autotune", action="store_true",
                     help="time the kernels for every dataset shape first (fiuncho_autotune)")
@@ -132,7 +134,7 @@ def main():
     plain = args.workload.endswith("-plain")
     if args.kernel != "auto":
         forced = {"popcount": fiuncho.KERNEL_POPCOUNT, "pairs": fiuncho.KERNEL_PAIRS,
-                  "mfma": fiuncho.KERNEL_MFMA}[args.kernel]
+                  "mfma": fiuncho.KERNEL_MFMA, "triples": fiuncho.KERNEL_TRIPLES}[args.kernel]
         for d in datasets:
             if fiuncho.lib().fiuncho_set_kernel(d.n, d.m, d.order, forced) != fiuncho.OK:
                 ap.error(f"kernel {args.kernel} does not handle order {d.order}")
@@ -227,7 +229,8 @@ def main():
         roofline = {"bound": "alu", "kernel": "scan_kernel (AND+popcount counting + FP32 MI + filter)",
                     "achieved": achieved, "peak": peak, "unit": "T int32 lane-op/s", "frac": achieved / peak,
                     "traffic": None}
-    names = {fiuncho.KERNEL_POPCOUNT: "popcount", fiuncho.KERNEL_PAIRS: "pairs", fiuncho.KERNEL_MFMA: "mfma"}
+    names = {fiuncho.KERNEL_POPCOUNT: "popcount", fiuncho.KERNEL_PAIRS: "pairs", fiuncho.KERNEL_MFMA: "mfma",
+             fiuncho.KERNEL_TRIPLES: "triples"}
 
     d0 = datasets[0]
     planted_first = None

@@ -213,6 +213,10 @@ int fiuncho_shard_counts(uint32_t snps, uint32_t samples, int order, uint32_t un
                                      rest from stored pair tables */
 #define FIUNCHO_KERNEL_MFMA 3     /* order 2: one-hot int8 contraction on the
                                      matrix cores */
+#define FIUNCHO_KERNEL_TRIPLES 4  /* order 4: only the {0,1}^4 cells counted, the
+                                     rest from stored triple and pair tables
+                                     (64 bytes of device memory per pair and
+                                     variant; up to 16 GiB of tables) */
 
 /* The kernel a job of this shape would use now (a FIUNCHO_KERNEL_* value),
  * or FIUNCHO_E_ORDER. */

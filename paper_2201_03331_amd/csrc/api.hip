@@ -214,11 +214,20 @@ ShapeKey shape_key(uint32_t n, uint32_t m, uint32_t k) {
   return ShapeKey(k, bit_length(n), bit_length(ceil_div(m, 64)));
 }
 
+// bytes of the triple tables of an order-4 job (one 64-byte entry per pair
+// and last variant slot)
+u64 triple_table_bytes(uint32_t n) {
+  const u64 n_pad = (u64)(n + 63) / 64 * 64 + 64;
+  return binom_host(n, 2) * n_pad * 64;
+}
+constexpr u64 kMaxTripleTableBytes = 16ull << 30;
+
 bool kernel_valid(int kernel, uint32_t n, uint32_t k) {
   switch (kernel) {
     case FIUNCHO_KERNEL_POPCOUNT: return true;
     case FIUNCHO_KERNEL_PAIRS: return k == 3 && n >= 3;
     case FIUNCHO_KERNEL_MFMA: return k == 2;
+    case FIUNCHO_KERNEL_TRIPLES: return k == 4 && n >= 4 && triple_table_bytes(n) <= kMaxTripleTableBytes;
     default: return false;
   }
 }
@@ -229,6 +238,7 @@ bool kernel_valid(int kernel, uint32_t n, uint32_t k) {
 // order-3 size tried
 int rule_kernel(uint32_t n, uint32_t k) {
   if (k == 3 && n >= 3) return FIUNCHO_KERNEL_PAIRS;
+  if (k == 4 && kernel_valid(FIUNCHO_KERNEL_TRIPLES, n, k)) return FIUNCHO_KERNEL_TRIPLES;
   if (k == 2 && n >= 1024) return FIUNCHO_KERNEL_MFMA;
   return FIUNCHO_KERNEL_POPCOUNT;
 }
@@ -237,6 +247,10 @@ int choose_kernel(uint32_t n, uint32_t m, uint32_t k) {
   const char *e3 = std::getenv("FIUNCHO_ORDER3_PAIRS");
   if (k == 3 && e3 && e3[0] == '0') return FIUNCHO_KERNEL_POPCOUNT;
   if (k == 3 && e3 && e3[0] == '1' && n >= 3) return FIUNCHO_KERNEL_PAIRS;
+  const char *e4 = std::getenv("FIUNCHO_ORDER4_TRIPLES");
+  if (k == 4 && e4 && e4[0] == '0') return FIUNCHO_KERNEL_POPCOUNT;
+  if (k == 4 && e4 && e4[0] == '1' && kernel_valid(FIUNCHO_KERNEL_TRIPLES, n, k))
+    return FIUNCHO_KERNEL_TRIPLES;
   const char *e2 = std::getenv("FIUNCHO_ORDER2_MFMA");
   if (k == 2 && e2 && e2[0] == '0') return FIUNCHO_KERNEL_POPCOUNT;
   if (k == 2 && e2 && e2[0] == '1') return FIUNCHO_KERNEL_MFMA;
@@ -253,6 +267,7 @@ uint32_t job_path(uint32_t n, uint32_t m, uint32_t k) {
   switch (choose_kernel(n, m, k)) {
     case FIUNCHO_KERNEL_PAIRS: return fiuncho::kPathPairs;
     case FIUNCHO_KERNEL_MFMA: return fiuncho::kPathMfma2;
+    case FIUNCHO_KERNEL_TRIPLES: return fiuncho::kPathTriples;
     default: return fiuncho::kPathGeneric;
   }
 }
@@ -265,7 +280,7 @@ struct JobLayout {
   u64 total;
   uint32_t cand_cap, l1_cap, l2_cap;
   size_t off_G, off_y, off_idx, off_Bv, off_Bs, off_marg, off_hist, off_phist, off_cand, off_l1, off_l2,
-      off_state, off_out, off_nout, off_status, off_pairs;
+      off_state, off_out, off_nout, off_status, off_pairs, off_triples;
   // plan (uploaded)
   size_t off_rows, off_F32, off_Fh, off_P64;
   std::vector<u64> row_start;
@@ -277,7 +292,7 @@ struct JobLayout {
 struct Layout {
   std::vector<JobLayout> jobs;
   std::vector<uint32_t> order;  // tile-space order of the jobs (costliest first)
-  uint32_t nmax, kmax, max_n_pad, max_wcap, max_cand_cap, max_l2_cap, max_pairs_n;
+  uint32_t nmax, kmax, max_n_pad, max_wcap, max_cand_cap, max_l2_cap, max_pairs_n, max_triples_n;
   size_t plan_begin, plan_end;  // uploaded region
   size_t off_desc, off_jts, off_jps, off_binom, off_counter;
   uint32_t n_scan;  // jobs [0, n_scan) of the tile-space order run in scan_kernel, the rest in mfma2_kernel
@@ -296,6 +311,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
   L.max_cand_cap = 0;
   L.max_l2_cap = 0;
   L.max_pairs_n = 0;
+  L.max_triples_n = 0;
   size_t off = 0;
   // per-job data
   for (uint32_t i = 0; i < n_jobs; ++i) {
@@ -344,8 +360,11 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
              : J.path == fiuncho::kPathMfma2 ? words * 4 * 64
              : J.k == 2 ? words * 4 * fiuncho::kOrder2Prefixes
              : J.path == fiuncho::kPathPairs ? words * 8 * fiuncho::kOrder3Prefixes
+             : J.path == fiuncho::kPathTriples ? words * 20
                                              : words * 18 * std::pow(3.0, (double)J.k - 3);
-    if (J.path == fiuncho::kPathPairs) L.max_pairs_n = std::max(L.max_pairs_n, J.n);
+    const bool need_pairs = J.path == fiuncho::kPathPairs || J.path == fiuncho::kPathTriples;
+    if (need_pairs) L.max_pairs_n = std::max(L.max_pairs_n, J.n);
+    if (J.path == fiuncho::kPathTriples) L.max_triples_n = std::max(L.max_triples_n, J.n);
     L.nmax = std::max(L.nmax, J.n);
     L.kmax = std::max(L.kmax, J.k);
     L.max_n_pad = std::max(L.max_n_pad, J.n_pad);
@@ -373,7 +392,8 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     J.off_out = host_inputs ? take(sizeof(fiuncho_hit) * J.top_n) : 0;
     J.off_nout = host_inputs ? take(sizeof(uint32_t)) : 0;
     J.off_status = host_inputs ? take(sizeof(int32_t)) : 0;
-    J.off_pairs = J.path == fiuncho::kPathPairs ? take(sizeof(uint32_t) * 8 * (size_t)J.n * J.n_pad) : 0;
+    J.off_pairs = need_pairs ? take(sizeof(uint32_t) * 8 * (size_t)J.n * J.n_pad) : 0;
+    J.off_triples = J.path == fiuncho::kPathTriples ? take((size_t)triple_table_bytes(J.n)) : 0;
   }
   // plan region
   L.plan_begin = off;
@@ -407,7 +427,9 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
   L.n_scan = 0;
   for (auto &J : L.jobs) L.n_scan += J.path != fiuncho::kPathMfma2;
   auto sel = [](const JobLayout &J) {
-    return J.path == fiuncho::kPathPairs ? fiuncho::kSelPairs : (J.k <= 5 ? (int)J.k : 0);
+    return J.path == fiuncho::kPathPairs     ? fiuncho::kSelPairs
+           : J.path == fiuncho::kPathTriples ? fiuncho::kSelTriples
+                                             : (J.k <= 5 ? (int)J.k : 0);
   };
   L.ksel = -1;
   bool only23 = true;
@@ -520,7 +542,8 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
     d.path = J.path;
     d.shard_index = J.shard_index;
     d.shard_count = J.shard_count;
-    d.pairs = J.path == fiuncho::kPathPairs ? reinterpret_cast<uint32_t *>(ws + J.off_pairs) : nullptr;
+    d.pairs = J.off_pairs ? reinterpret_cast<uint32_t *>(ws + J.off_pairs) : nullptr;
+    d.triples = J.off_triples ? reinterpret_cast<uint32_t *>(ws + J.off_triples) : nullptr;
     d.state = reinterpret_cast<JobState *>(ws + J.off_state);
     d.out = host_inputs ? reinterpret_cast<fiuncho_hit *>(ws + J.off_out) : jobs[i].out;
     d.n_out = host_inputs ? reinterpret_cast<uint32_t *>(ws + J.off_nout) : jobs[i].n_out;
@@ -680,7 +703,8 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   }
   uint32_t kernels = 0;
   for (auto &J : L.jobs)
-    kernels |= 1u << (J.path == fiuncho::kPathPairs   ? FIUNCHO_KERNEL_PAIRS
+    kernels |= 1u << (J.path == fiuncho::kPathPairs     ? FIUNCHO_KERNEL_PAIRS
+                      : J.path == fiuncho::kPathTriples ? FIUNCHO_KERNEL_TRIPLES
                       : J.path == fiuncho::kPathMfma2 ? FIUNCHO_KERNEL_MFMA
                                                       : FIUNCHO_KERNEL_POPCOUNT);
   if ((st = prof_begin(combos, kernels, reinterpret_cast<JobState *>(ws + L.jobs[0].off_state))))
@@ -689,6 +713,7 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   fiuncho::launch_init(g, s);
   fiuncho::launch_pack(g, L.max_n_pad, L.max_wcap, s);
   if (L.max_pairs_n) fiuncho::launch_pairs(g, L.max_pairs_n, s);
+  if (L.max_triples_n) fiuncho::launch_triples(g, L.max_triples_n, s);
   if ((st = prof_record(1, s))) return st;
   // job tile and pilot starts in tile-space order (as uploaded)
   const uint32_t nj = (uint32_t)L.jobs.size();
@@ -1128,7 +1153,7 @@ int fiuncho_autotune(uint32_t snps, uint32_t samples, int order, uint32_t reps, 
     if (st) return st;
     const uint32_t k = (uint32_t)order;
     std::vector<int> cands;
-    for (int c : {FIUNCHO_KERNEL_POPCOUNT, FIUNCHO_KERNEL_PAIRS, FIUNCHO_KERNEL_MFMA})
+    for (int c : {FIUNCHO_KERNEL_POPCOUNT, FIUNCHO_KERNEL_PAIRS, FIUNCHO_KERNEL_MFMA, FIUNCHO_KERNEL_TRIPLES})
       if (kernel_valid(c, snps, k)) cands.push_back(c);
     int best = cands[0];
     if (cands.size() > 1) {

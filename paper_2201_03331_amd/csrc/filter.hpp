@@ -20,6 +20,7 @@ struct JV {
   Cand *cand;
   JobState *st;
   const uint32_t *pairs;
+  const uint32_t *triples;
   uint32_t path;
   const float *Fh;
   float fbound;
@@ -49,6 +50,7 @@ __device__ __forceinline__ JV load_view(const JobDesc *jd) {
   v.cand = uni_ptr(J->cand);
   v.st = uni_ptr(J->state);
   v.pairs = uni_ptr(J->pairs);
+  v.triples = uni_ptr(J->triples);
   v.path = uni(J->path);
   v.Fh = uni_ptr(J->Fh);
   v.fbound = __uint_as_float(uni(__float_as_uint(J->fbound)));

@@ -31,7 +31,9 @@ constexpr uint32_t kPathPairs = 1;            // order 3, {0,1}^3 cells + pair t
 constexpr int kSelPairs = 31;                 // scan_kernel selector: order-3 pair path only
 constexpr int kSel23 = 23;                    // scan_kernel selector: orders 2 and 3 (pair path)
 constexpr int kTileCounters = 4;              // scan, scan pilot, mfma2, mfma2 pilot
-constexpr uint32_t kPathMfma2 = 2;            // order 2 on the matrix cores (mfma2_kernel)
+constexpr uint32_t kPathMfma2 = 2;
+constexpr uint32_t kPathTriples = 3;          // order 4, {0,1}^4 cells + triple and pair tables
+constexpr int kSelTriples = 41;               // scan_kernel selector: order-4 triple-table path only            // order 2 on the matrix cores (mfma2_kernel)
 
 // state the device writes during one run of a job (cleared at the start)
 struct JobState {
@@ -99,7 +101,8 @@ struct JobDesc {
   uint32_t l2_cap;
   uint32_t path;              // kPathGeneric or kPathPairs
   JobState *state;
-  uint32_t *pairs;            // kPathPairs: [n][n_pad][g_a 0..1][g_j 0..1][class] counts
+  uint32_t *pairs;            // kPathPairs, kPathTriples: [n][n_pad][g_a 0..1][g_j 0..1][class] counts
+  uint32_t *triples;          // kPathTriples: [pair (a, b)][n_pad][g_a][g_b][g_j][class] counts
   uint32_t shard_index;       // local tile = launch tile * shard_count + shard_index
   uint32_t shard_count;       // 1 = every tile
   uint32_t pilot_tiles;       // tiles sampled by the pilot pass (0: none)
@@ -131,6 +134,7 @@ struct Globals {
 void launch_init(const Globals &g, hipStream_t s);
 void launch_pack(const Globals &g, uint32_t max_n_pad, uint32_t max_wcap, hipStream_t s);
 void launch_pairs(const Globals &g, uint32_t max_n, hipStream_t s);
+void launch_triples(const Globals &g, uint32_t max_n, hipStream_t s);
 void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s);
 void launch_mfma2(const Globals &g, int grid, hipStream_t s);
 int mfma2_grid_size();

@@ -551,9 +551,362 @@ __device__ __forceinline__ void tile_order3p(const Globals &g, const JV &v, uint
 }
 
 // ---------------------------------------------------------------------------
+// order 4 with stored triple tables: only the {0,1}^4 cells of (a, b, c, j)
+// are counted (16 word-ops per word instead of 54).  The other cells follow
+// by inclusion-exclusion: for g_j in {0, 1}, the cells (., ., ., g_j) form an
+// order-3 table over (a, b, c) whose "pairs" are the {0,1}^3 tables of
+// (a, b, j), (a, c, j), (b, c, j) at g_j, whose "variants" are the {0,1}^2
+// pair tables of (a, j), (b, j), (c, j) at g_j and whose size is the count of
+// g_j at j; the cells (., ., ., 2) are the prefix's own order-3 table minus
+// those two.
+// ---------------------------------------------------------------------------
+
+// lexicographic index of the pair (x, y), x < y, among the pairs of n
+__device__ __forceinline__ u64 pair_index(uint32_t n, uint32_t x, uint32_t y) {
+  return (u64)x * (n - 1) - (u64)x * (x - 1) / 2 + (y - x - 1);
+}
+
+// Pass over all (a, b, j), a < b < j: their {0,1}^3 counts per class into
+// the triple tables [pair_index(a, b)][j][g_a][g_b][g_j][class].  Grid: x =
+// group of kScanWaves * 2 first variants a, y = b - 1, z = job; each wave
+// owns 2 first variants and walks the blocks of 64 last variants.
+__global__ __launch_bounds__(kScanWaves * 64) void triples_kernel(Globals g) {
+  const JobDesc *jd = g.jobs + blockIdx.z;
+  JV v = load_view(jd);
+  uint32_t *TT = uni_ptr(as_const(jd)->triples);
+  if (TT == nullptr) return;
+  const JobState *st = v.st;
+  if (uni((uint32_t)st->status) != 0) return;
+  v.W0 = uni(st->W0);
+  v.W1 = uni(st->W1);
+  const uint32_t n = v.n;
+  const uint32_t wave = uni(threadIdx.x >> 6), lane = lane_id();
+  const uint32_t b = blockIdx.y + 1;
+  if (b + 1 >= n) return;
+  const uint32_t a_first = blockIdx.x * (kScanWaves * 2) + wave * 2;
+  if (a_first >= b) return;
+  cu64p Bsc = as_const(v.Bs);
+  cu64p rb = Bsc + (size_t)b * 4 * v.wcap;
+  cu64p ra[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) ra[p] = Bsc + (size_t)min(a_first + p, b - 1) * 4 * v.wcap;
+  for (uint32_t j0 = b + 1; j0 < n; j0 += 64) {
+    const uint32_t j = j0 + lane;
+    const FI_GLOBAL Ulong2 *col = as_global(reinterpret_cast<const Ulong2 *>(v.Bv)) + j;
+    uint32_t acc[2][2][2][2][2];  // [p][c][g_a][g_b][g_j]
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[p][c][x][y][0] = acc[p][c][x][y][1] = 0;
+    count3p<2, 0>(rb, ra, 0, v.W0, col, v.n_pad, acc);
+    count3p<2, 1>(rb, ra, v.W0, v.W0 + v.W1, col, v.n_pad, acc);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const uint32_t a = a_first + p;
+      if (a < b && j < n) {
+        uint4 *dst = reinterpret_cast<uint4 *>(TT + (pair_index(n, a, b) * v.n_pad + j) * 16);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            dst[x * 2 + y] = make_uint4(acc[p][0][x][y][0], acc[p][1][x][y][0], acc[p][0][x][y][1],
+                                        acc[p][1][x][y][1]);
+      }
+    }
+  }
+}
+
+// The inputs of an order-3 table walk, held by value.
+struct Tab3 {
+  uint32_t D[2][2][2][2];  // [c][x][y][z] over {0,1}^3
+  uint32_t xy[8];          // sum over z: [x][y][c]
+  uint32_t xz[8];          // sum over y: [x][z][c]
+  uint32_t yz[8];          // sum over x: [y][z][c]
+  uint32_t Mx[2][2];       // [x][c]
+  uint32_t My[2][2];
+  uint32_t Mz[2][2];
+  uint32_t m[2];
+};
+
+// walk_order3 over NT tables at once: visit(cells) sees cell p of every table
+// (cells[t][class]), p in the walk's order.
+template <int NT, typename Visit>
+__device__ __forceinline__ void walk3_zip(const Tab3 (&q)[NT], Visit &&visit) {
+  uint32_t sum[NT][2], x2z[NT][2][2][2], t2yz[NT][2][2][2], cell[NT][2];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) sum[t][0] = sum[t][1] = 0;
+  auto emit_cell = [&]() {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      sum[t][0] += cell[t][0];
+      sum[t][1] += cell[t][1];
+    }
+    visit(cell);
+  };
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int z = 0; z < 2; ++z) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) cell[t][c] = q[t].D[c][x][y][z];
+        emit_cell();
+      }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          cell[t][c] = q[t].xy[x * 4 + y * 2 + c] - q[t].D[c][x][y][0] - q[t].D[c][x][y][1];
+      emit_cell();  // (x, y, 2)
+    }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          cell[t][c] = x2z[t][c][x][z] =
+              q[t].xz[x * 4 + z * 2 + c] - q[t].D[c][x][0][z] - q[t].D[c][x][1][z];
+      emit_cell();  // (x, 2, z)
+    }
+#pragma unroll
+  for (int y = 0; y < 2; ++y)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          cell[t][c] = t2yz[t][c][y][z] =
+              q[t].yz[y * 4 + z * 2 + c] - q[t].D[c][0][y][z] - q[t].D[c][1][y][z];
+      emit_cell();  // (2, y, z)
+    }
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        cell[t][c] = q[t].Mx[x][c] - q[t].xy[x * 4 + c] - q[t].xy[x * 4 + 2 + c] - x2z[t][c][x][0] -
+                     x2z[t][c][x][1];
+    emit_cell();  // (x, 2, 2)
+  }
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        cell[t][c] = q[t].My[y][c] - q[t].xy[y * 2 + c] - q[t].xy[4 + y * 2 + c] - t2yz[t][c][y][0] -
+                     t2yz[t][c][y][1];
+    emit_cell();  // (2, y, 2)
+  }
+#pragma unroll
+  for (int z = 0; z < 2; ++z) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        cell[t][c] = q[t].Mz[z][c] - q[t].xz[z * 2 + c] - q[t].xz[4 + z * 2 + c] - t2yz[t][c][0][z] -
+                     t2yz[t][c][1][z];
+    emit_cell();  // (2, 2, z)
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) cell[t][c] = q[t].m[c] - sum[t][c];
+  visit(cell);  // (2, 2, 2)
+}
+
+// {0,1}^4 counts of (a, b, c, j) for one class: the 8 rows of (a, b, c) with
+// g in {0, 1} are formed in scalar registers per word
+template <int CLS>
+__device__ __forceinline__ void count4t(cu64p ra, cu64p rb, cu64p rc, uint32_t wbeg, uint32_t wend,
+                                        const FI_GLOBAL Ulong2 *col, uint32_t n_pad,
+                                        uint32_t (&acc)[2][2][2][2][2]) {
+  if (wbeg >= wend) return;
+  u64 A[2], B[2], C[2];
+  auto load = [&](uint32_t w) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      A[x] = ra[(size_t)w * 4 + x];
+      B[x] = rb[(size_t)w * 4 + x];
+      C[x] = rc[(size_t)w * 4 + x];
+    }
+  };
+  load(wbeg);
+  word_pipeline(wbeg, wend, col, n_pad, [&](uint32_t wn, const Ulong2 &L) {
+    u64 R[2][2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const u64 ab = A[x] & B[y];
+        R[x][y][0] = ab & C[0];
+        R[x][y][1] = ab & C[1];
+      }
+    load(wn);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int z = 0; z < 2; ++z) {
+          acc[CLS][x][y][z][0] = add_popc64(acc[CLS][x][y][z][0], R[x][y][z] & L.x);
+          acc[CLS][x][y][z][1] = add_popc64(acc[CLS][x][y][z][1], R[x][y][z] & L.y);
+        }
+  });
+}
+
+// 16 u32 of a triple table entry ([g_x][g_y][g_z][class]) and its slice at g_z
+__device__ __forceinline__ void load_triple(const FI_GLOBAL uint32_t *p, uint32_t (&q)[16]) {
+  const FI_GLOBAL u64 *p64 = reinterpret_cast<const FI_GLOBAL u64 *>(p);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const u64 x = p64[i];
+    q[2 * i] = (uint32_t)x;
+    q[2 * i + 1] = (uint32_t)(x >> 32);
+  }
+}
+
+__device__ __forceinline__ void tile_order4t(const Globals &g, const JV &v, const uint32_t (&pre)[3],
+                                             uint32_t j0, uint32_t lane) {
+  const uint32_t n = v.n, a = pre[0], b = pre[1], c = pre[2];
+  const uint32_t j = j0 + lane;
+  const bool active = j < n;
+  const uint32_t jj = active ? j : n - 1;
+  const FI_GLOBAL Ulong2 *col = as_global(reinterpret_cast<const Ulong2 *>(v.Bv)) + j;
+  cu64p Bsc = as_const(v.Bs);
+  cu64p ra = Bsc + (size_t)a * 4 * v.wcap, rb = Bsc + (size_t)b * 4 * v.wcap,
+        rc = Bsc + (size_t)c * 4 * v.wcap;
+  uint32_t acc[2][2][2][2][2];  // [class][g_a][g_b][g_c][g_j]
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int z = 0; z < 2; ++z) acc[q][x][y][z][0] = acc[q][x][y][z][1] = 0;
+  count4t<0>(ra, rb, rc, 0, v.W0, col, v.n_pad, acc);
+  count4t<1>(ra, rb, rc, v.W0, v.W0 + v.W1, col, v.n_pad, acc);
+
+  const float thr = current_threshold(v);
+  const MiConst mc = mi_const(v);
+  const FI_GLOBAL float *F = as_global(v.Fh);
+  const uint32_t np = v.n_pad;
+  const FI_GLOBAL uint32_t *TTg = as_global(v.triples);
+  const FI_CONST uint32_t *TTc = as_const(v.triples);
+  const FI_GLOBAL uint32_t *PTg = as_global(v.pairs);
+  const FI_CONST uint32_t *PTc = as_const(v.pairs);
+  cu32p marg = as_const(v.marg);
+  const FI_GLOBAL uint32_t *mgj = as_global(v.marg) + (size_t)jj * 6;
+
+  Tab3 q[3];  // [0]: (a, b, c) itself; [1], [2]: the cells with g_j = 0, 1
+  // the prefix's table (wave-uniform)
+  {
+    const FI_CONST uint32_t *e = TTc + (pair_index(n, a, b) * np + c) * 16;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int z = 0; z < 2; ++z)
+#pragma unroll
+          for (int cl = 0; cl < 2; ++cl) q[0].D[cl][x][y][z] = e[x * 8 + y * 4 + z * 2 + cl];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      q[0].xy[i] = PTc[((size_t)a * np + b) * 8 + i];
+      q[0].xz[i] = PTc[((size_t)a * np + c) * 8 + i];
+      q[0].yz[i] = PTc[((size_t)b * np + c) * 8 + i];
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int cl = 0; cl < 2; ++cl) {
+        q[0].Mx[x][cl] = marg[(size_t)a * 6 + 2 * x + cl];
+        q[0].My[x][cl] = marg[(size_t)b * 6 + 2 * x + cl];
+        q[0].Mz[x][cl] = marg[(size_t)c * 6 + 2 * x + cl];
+      }
+    q[0].m[0] = v.m0;
+    q[0].m[1] = v.m1;
+  }
+  // the g_j slices (per lane)
+  {
+    uint32_t tab[16], tac[16], tbc[16], paj[8], pbj[8], pcj[8];
+    load_triple(TTg + (pair_index(n, a, b) * np + jj) * 16, tab);
+    load_triple(TTg + (pair_index(n, a, c) * np + jj) * 16, tac);
+    load_triple(TTg + (pair_index(n, b, c) * np + jj) * 16, tbc);
+    load_pair(PTg + ((size_t)a * np + jj) * 8, paj);
+    load_pair(PTg + ((size_t)b * np + jj) * 8, pbj);
+    load_pair(PTg + ((size_t)c * np + jj) * 8, pcj);
+#pragma unroll
+    for (int gj = 0; gj < 2; ++gj) {
+      Tab3 &t = q[1 + gj];
+#pragma unroll
+      for (int cl = 0; cl < 2; ++cl)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int z = 0; z < 2; ++z) t.D[cl][x][y][z] = acc[cl][x][y][z][gj];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int cl = 0; cl < 2; ++cl) {
+            t.xy[x * 4 + y * 2 + cl] = tab[x * 8 + y * 4 + gj * 2 + cl];
+            t.xz[x * 4 + y * 2 + cl] = tac[x * 8 + y * 4 + gj * 2 + cl];
+            t.yz[x * 4 + y * 2 + cl] = tbc[x * 8 + y * 4 + gj * 2 + cl];
+          }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int cl = 0; cl < 2; ++cl) {
+          t.Mx[x][cl] = paj[x * 4 + gj * 2 + cl];
+          t.My[x][cl] = pbj[x * 4 + gj * 2 + cl];
+          t.Mz[x][cl] = pcj[x * 4 + gj * 2 + cl];
+        }
+#pragma unroll
+      for (int cl = 0; cl < 2; ++cl) t.m[cl] = mgj[2 * gj + cl];
+    }
+  }
+  float fs = mc.c;
+  if (active) {
+    // every count is at most its class size; the clamps keep the table
+    // lookups inside [0, m] whatever the inputs hold
+    const uint32_t m0 = v.m0, m1 = v.m1;
+    walk3_zip<3>(q, [&](const uint32_t (&cell)[3][2]) {
+      const uint32_t n20 = cell[0][0] - cell[1][0] - cell[2][0];
+      const uint32_t n21 = cell[0][1] - cell[1][1] - cell[2][1];
+      fs += mi_term(F, min(cell[1][0], m0), min(cell[1][1], m1));
+      fs += mi_term(F, min(cell[2][0], m0), min(cell[2][1], m1));
+      fs += mi_term(F, min(n20, m0), min(n21, m1));
+    });
+  }
+  const u64 rank = lex_rank_prefix(g, n, 4, pre) + (u64)(j - c - 1);
+  emit(v, active, fs * mc.inv_m, rank, thr, lane);
+}
+
+// ---------------------------------------------------------------------------
 // persistent driver
 // ---------------------------------------------------------------------------
-template <int K>
+template <int K, bool TRIPLES = false>
 __device__ __forceinline__ void run_orderk(const Globals &g, const JV &v, uint32_t rho, u64 local,
                                            uint32_t wave, uint32_t lane) {
   const uint32_t n = v.n;
@@ -579,11 +932,12 @@ __device__ __forceinline__ void run_orderk(const Globals &g, const JV &v, uint32
     pre[r - 1] = uni(lo);
     hi = lo;
   }
-  tile_orderk<K>(g, v, pre, b + 1 + jb * 64, lane);
+  if constexpr (TRIPLES && K == 4) tile_order4t(g, v, pre, b + 1 + jb * 64, lane);
+  else tile_orderk<K>(g, v, pre, b + 1 + jb * 64, lane);
 }
 
 // waves per SIMD each variant is compiled for (register budget 512 / waves)
-constexpr int scan_min_waves(int ksel) { return ksel != 0 ? 4 : 2; }
+constexpr int scan_min_waves(int ksel) { return (ksel != 0 && ksel != kSelTriples) ? 4 : 2; }
 
 template <int KSEL>
 __global__ __launch_bounds__(kScanWaves * 64, scan_min_waves(KSEL)) void scan_kernel(Globals g) {
@@ -600,7 +954,7 @@ __global__ __launch_bounds__(kScanWaves * 64, scan_min_waves(KSEL)) void scan_ke
     const FI_CONST JobDesc *jd;
     u64 lt;
     if (!locate_tile(g, t, wave, kPilotEmits, v, jd, lt)) continue;
-    const int k = KSEL == kSelPairs ? 3 : (KSEL && KSEL != kSel23) ? KSEL : (int)v.k;
+    const int k = KSEL == kSelPairs ? 3 : KSEL == kSelTriples ? 4 : (KSEL && KSEL != kSel23) ? KSEL : (int)v.k;
     if (k == 1) {
       if (KSEL == 0 || KSEL == 1) tile_order1(v, lt, wave, lane);
       continue;
@@ -635,7 +989,12 @@ __global__ __launch_bounds__(kScanWaves * 64, scan_min_waves(KSEL)) void scan_ke
     }
     switch (k) {
       case 3: if (KSEL == 0 || KSEL == 3) run_orderk<3>(g, v, rl, local, wave, lane); break;
-      case 4: if (KSEL == 0 || KSEL == 4) run_orderk<4>(g, v, rl, local, wave, lane); break;
+      case 4:
+        if (KSEL == kSelTriples || (KSEL == 0 && v.path == kPathTriples))
+          run_orderk<4, true>(g, v, rl, local, wave, lane);
+        else if (KSEL == 0 || KSEL == 4)
+          run_orderk<4>(g, v, rl, local, wave, lane);
+        break;
       case 5: if (KSEL == 0 || KSEL == 5) run_orderk<5>(g, v, rl, local, wave, lane); break;
       case 6: if (KSEL == 0 || KSEL == 6) run_orderk<6>(g, v, rl, local, wave, lane); break;
       case 7: if (KSEL == 0 || KSEL == 7) run_orderk<7>(g, v, rl, local, wave, lane); break;
@@ -666,8 +1025,16 @@ int scan_grid_size(int ksel) {
     case 5: return occupancy_grid<5>();
     case kSelPairs: return occupancy_grid<kSelPairs>();
     case kSel23: return occupancy_grid<kSel23>();
+    case kSelTriples: return occupancy_grid<kSelTriples>();
     default: return occupancy_grid<0>();
   }
+}
+
+void launch_triples(const Globals &g, uint32_t max_n, hipStream_t s) {
+  const uint32_t groups = (max_n + kScanWaves * 2 - 1) / (kScanWaves * 2);
+  const uint32_t rows = max_n > 2 ? max_n - 2 : 1;
+  hipLaunchKernelGGL(triples_kernel, dim3(groups ? groups : 1, rows, g.n_jobs), dim3(kScanWaves * 64), 0,
+                     s, g);
 }
 
 void launch_pairs(const Globals &g, uint32_t max_n, hipStream_t s) {
@@ -687,6 +1054,7 @@ void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s) {
     case 5: hipLaunchKernelGGL(scan_kernel<5>, gd, bd, 0, s, g); break;
     case kSelPairs: hipLaunchKernelGGL(scan_kernel<kSelPairs>, gd, bd, 0, s, g); break;
     case kSel23: hipLaunchKernelGGL(scan_kernel<kSel23>, gd, bd, 0, s, g); break;
+    case kSelTriples: hipLaunchKernelGGL(scan_kernel<kSelTriples>, gd, bd, 0, s, g); break;
     default: hipLaunchKernelGGL(scan_kernel<0>, gd, bd, 0, s, g); break;
   }
 }

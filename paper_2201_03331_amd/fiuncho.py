@@ -33,6 +33,7 @@ KERNEL_AUTO = 0
 KERNEL_POPCOUNT = 1
 KERNEL_PAIRS = 2
 KERNEL_MFMA = 3
+KERNEL_TRIPLES = 4
 
 # every entry point declared in include/fiuncho.h
 EXPORTS = (

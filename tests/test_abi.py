@@ -104,11 +104,14 @@ def test_kernel_choice_table(monkeypatch):
     the tile dealing follows the chosen kernel.  Host-only."""
     monkeypatch.delenv("FIUNCHO_ORDER2_MFMA", raising=False)
     monkeypatch.delenv("FIUNCHO_ORDER3_PAIRS", raising=False)
+    monkeypatch.delenv("FIUNCHO_ORDER4_TRIPLES", raising=False)
     L = fiuncho.lib()
     assert fiuncho.get_kernel(100, 1600, 2) == fiuncho.KERNEL_POPCOUNT
     assert fiuncho.get_kernel(4000, 16000, 2) == fiuncho.KERNEL_MFMA
     assert fiuncho.get_kernel(1000, 6400, 3) == fiuncho.KERNEL_PAIRS
-    assert fiuncho.get_kernel(200, 4000, 4) == fiuncho.KERNEL_POPCOUNT
+    assert fiuncho.get_kernel(200, 4000, 4) == fiuncho.KERNEL_TRIPLES
+    assert fiuncho.get_kernel(5000, 4000, 4) == fiuncho.KERNEL_POPCOUNT  # tables over 16 GiB
+    assert fiuncho.get_kernel(100, 4000, 5) == fiuncho.KERNEL_POPCOUNT
     assert L.fiuncho_get_kernel(5, 100, 6) == fiuncho.E_ORDER
     before = fiuncho.shard_counts(300, 500, 2, 5, fiuncho.TILE_ROUND_ROBIN)
     try:
@@ -128,6 +131,8 @@ def test_kernel_choice_table(monkeypatch):
     assert L.fiuncho_set_kernel(300, 500, 3, fiuncho.KERNEL_MFMA) == fiuncho.E_SHAPE
     assert L.fiuncho_set_kernel(300, 500, 2, fiuncho.KERNEL_PAIRS) == fiuncho.E_SHAPE
     assert L.fiuncho_set_kernel(300, 500, 2, 9) == fiuncho.E_SHAPE
+    assert L.fiuncho_set_kernel(300, 500, 3, fiuncho.KERNEL_TRIPLES) == fiuncho.E_SHAPE
+    assert L.fiuncho_set_kernel(5000, 500, 4, fiuncho.KERNEL_TRIPLES) == fiuncho.E_SHAPE
     k = ctypes.c_int(0)
     assert L.fiuncho_autotune(300, 500, 2, 1, None) == fiuncho.E_NULL
     assert L.fiuncho_autotune(3, 500, 4, 1, ctypes.byref(k)) == fiuncho.E_ORDER

@@ -203,6 +203,26 @@ def test_order4_high_order_workload():
     full_size_check(synth.high_order(4), 20000, 34)
 
 
+def test_order4_high_order_workload_popcount_kernel(monkeypatch):
+    monkeypatch.setenv("FIUNCHO_ORDER4_TRIPLES", "0")
+    full_size_check(synth.high_order(4), 20000, 35)
+
+
+@pytest.mark.parametrize("triples", ["0", "1"])
+def test_order4_both_kernels(triples, monkeypatch):
+    """Order 4 through the generic kernel and through the inclusion-exclusion
+    kernel with triple tables, on ragged sizes around the 64-variant and
+    64-sample block edges."""
+    monkeypatch.setenv("FIUNCHO_ORDER4_TRIPLES", triples)
+    for seed, n, m, frac in ((50, 4, 90, 0.5), (51, 9, 64, 0.3), (52, 33, 129, 0.5),
+                             (53, 66, 200, 0.45), (54, 70, 65, 0.6)):
+        say(f"case: order4 triples={triples} seed={seed} n={n} m={m}")
+        G, y = random_dataset(seed, n, m, frac, 1 if n > 5 else 0, 1 if n > 5 else 0)
+        top = min(37, math.comb(n, 4))
+        hits = fiuncho.scan(G, y, 4, top)
+        check_hits_against_oracle(G, y, 4, top, hits)
+
+
 # ---------------------------------------------------------------------------
 # batched form on device pointers
 # ---------------------------------------------------------------------------
