@@ -119,12 +119,45 @@ __global__ __launch_bounds__(1024) void partition_kernel(Globals g) {
 // reads of one variant.
 constexpr int kPackWaves = 8;  // consecutive variants per workgroup
 
+// Words [wb, we) of one class of variant `row`: lane l reads class position
+// 64 (w - c0) + l of word w (consecutive lanes read nearby bytes of the row);
+// the three genotype ballots of word w go into lane w - blk of b0, b1, b2.
+__device__ __forceinline__ void pack_class(const uint8_t *row, const uint32_t *ix, uint32_t c0,
+                                           uint32_t size, uint32_t blk, uint32_t wb, uint32_t we,
+                                           uint32_t lane,
+                                           u64 &b0, u64 &b1, u64 &b2, uint32_t (&cnt)[3],
+                                           bool &bad) {
+  for (uint32_t w0 = wb; w0 < we; w0 += 8) {
+    uint32_t gv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t p = (w0 + u - c0) * 64 + lane;
+      const bool valid = w0 + u < we && p < size;
+      gv[u] = valid ? (uint32_t)row[ix[p]] : 3u;
+      bad |= valid && gv[u] > 2;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (w0 + u >= we) break;
+      const u64 x0 = ballot(gv[u] == 0), x1 = ballot(gv[u] == 1), x2 = ballot(gv[u] == 2);
+      cnt[0] += popc64(x0);
+      cnt[1] += popc64(x1);
+      cnt[2] += popc64(x2);
+      if (lane == w0 + u - blk) {
+        b0 = x0;
+        b1 = x1;
+        b2 = x2;
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kPackWaves * 64) void pack_kernel(Globals g) {
   // one wave per (variant j, block of 64 words): blockIdx.x = group of
   // kPackWaves variants, blockIdx.y = job, blockIdx.z = word block.  The
   // variant-fastest rows (Bv) of the group are staged in LDS and written as
   // 128 contiguous bytes per word.
-  __shared__ u64 s_bv[64][kPackWaves][2];
+  __shared__ u64 s_bv[64][2 * kPackWaves + 1];  // padded against bank conflicts
   const JobDesc &J = g.jobs[blockIdx.y];
   const JobState *st = J.state;
   const uint32_t lane = threadIdx.x & 63;
@@ -144,69 +177,43 @@ __global__ __launch_bounds__(kPackWaves * 64) void pack_kernel(Globals g) {
   if (wb >= W) return;  // uniform over the workgroup
   const uint32_t we = min(wb + 64, W);
   const uint32_t n_pad = J.n_pad, wcap = J.wcap;
-  u64 keep0 = 0, keep1 = 0, keep2 = 0;
+  u64 b0 = 0, b1 = 0, b2 = 0;
   if (j < J.n) {
     // variants j >= n (padding read by the last lanes of a tile) keep zeros
     const uint8_t *row = J.G + (size_t)j * J.m;
-    uint32_t cnt[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    uint32_t cnt[2][3] = {{0, 0, 0}, {0, 0, 0}};
     bool bad = false;
-    // 8 words at a time so that 8 independent gathers per lane are in
-    // flight; lane (w - wb) keeps word w
-    for (uint32_t w0 = wb; w0 < we; w0 += 8) {
-      uint32_t gv[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const uint32_t w = w0 + u;
-        const uint32_t cls = (w >= W0);
-        const uint32_t p = (w - (cls ? W0 : 0)) * 64 + lane;
-        const bool valid = w < we && p < (cls ? m1 : m0);
-        gv[u] = valid ? (uint32_t)row[J.idx[(cls ? m0 : 0) + p]] : 0xffffffffu;
-        bad |= valid && gv[u] > 2;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const uint32_t w = w0 + u;
-        if (w >= we) break;
-        const uint32_t cls = (w >= W0);
-        const u64 b0 = ballot(gv[u] == 0), b1 = ballot(gv[u] == 1), b2 = ballot(gv[u] == 2);
-        cnt[0][cls] += popc64(b0);
-        cnt[1][cls] += popc64(b1);
-        cnt[2][cls] += popc64(b2);
-        if (lane == w - wb) {
-          keep0 = b0;
-          keep1 = b1;
-          keep2 = b2;
-        }
-      }
-    }
+    if (wb < W0) pack_class(row, J.idx, 0, m0, wb, wb, min(we, W0), lane, b0, b1, b2, cnt[0], bad);
+    if (we > W0)
+      pack_class(row, J.idx + m0, W0, m1, wb, max(wb, W0), we, lane, b0, b1, b2, cnt[1], bad);
     const uint32_t wl = wb + lane;
     if (wl < we) {
       u64 *bs = J.Bs + ((size_t)j * wcap + wl) * 4;
-      bs[0] = keep0;
-      bs[1] = keep1;
-      bs[2] = keep2;
+      bs[0] = b0;
+      bs[1] = b1;
+      bs[2] = b2;
       bs[3] = 0;
     }
     if (ballot(bad)) {
       if (lane == 0) atomicMin(&J.state->status, (int32_t)FIUNCHO_E_GENOTYPE);
     }
     // class counts of this word block; init_kernel cleared them
-    if (lane < 6) {
-      const uint32_t gg = lane >> 1, c = lane & 1;
-      const uint32_t v = gg == 0 ? (c ? cnt[0][1] : cnt[0][0])
-                         : gg == 1 ? (c ? cnt[1][1] : cnt[1][0])
-                                   : (c ? cnt[2][1] : cnt[2][0]);
-      if (v) atomicAdd(&J.marg[((size_t)j * 3 + gg) * 2 + c], v);
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int gg = 0; gg < 3; ++gg)
+          if (cnt[c][gg]) atomicAdd(&J.marg[((size_t)j * 3 + gg) * 2 + c], cnt[c][gg]);
     }
   }
-  s_bv[lane][wv][0] = keep0;
-  s_bv[lane][wv][1] = keep1;
+  s_bv[lane][2 * wv] = b0;
+  s_bv[lane][2 * wv + 1] = b1;
   __syncthreads();
   // thread t writes word wb + t / (2 kPackWaves), variant t / 2 mod kPackWaves, plane t mod 2
   for (uint32_t t = threadIdx.x; t < 64 * kPackWaves * 2; t += blockDim.x) {
-    const uint32_t w = t / (2 * kPackWaves), v = (t / 2) % kPackWaves, gp = t & 1;
-    if (wb + w < we && j0 + v < n_pad)
-      J.Bv[((size_t)(wb + w) * n_pad + j0 + v) * 2 + gp] = s_bv[w][v][gp];
+    const uint32_t ww = t / (2 * kPackWaves), vv = (t / 2) % kPackWaves, gp = t & 1;
+    if (wb + ww < we && j0 + vv < n_pad)
+      J.Bv[((size_t)(wb + ww) * n_pad + j0 + vv) * 2 + gp] = s_bv[ww][2 * vv + gp];
   }
 }
 

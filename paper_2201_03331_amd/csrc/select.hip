@@ -203,10 +203,59 @@ __global__ __launch_bounds__(1024) void select_kernel(Globals g) {
 // 3. one wave per kept candidate: recount the contingency table with one lane
 // per genotype cell (AND of the cell's rows, popcount per class), then MI in
 // double precision.  Also used for explicit tables (fiuncho_contingency).
+// Orders 2 and 3: one pass over the words, every cell of the table counted
+// per lane from the rows loaded once, then one wave sum per cell and class.
+template <int K, bool WRITE_TABLE>
+__device__ void count_cells_small(const JobDesc &J, const JobState *st, const uint32_t *c,
+                                  uint32_t lane, uint32_t *lds_t, uint32_t *table_out) {
+  constexpr int NC = K == 2 ? 9 : 27;
+  const uint32_t W0 = st->W0, W = st->W0 + st->W1, wcap = J.wcap;
+  uint32_t t[NC][2];
+#pragma unroll
+  for (int x = 0; x < NC; ++x) t[x][0] = t[x][1] = 0;
+#pragma unroll
+  for (int cls = 0; cls < 2; ++cls) {
+    const uint32_t wb = cls ? W0 : 0, we = cls ? W : W0;
+    for (uint32_t w = wb + lane; w < we; w += 64) {
+      u64 r[K][3];
+#pragma unroll
+      for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int gg = 0; gg < 3; ++gg) r[i][gg] = J.Bs[((size_t)c[i] * wcap + w) * 4 + gg];
+#pragma unroll
+      for (int x = 0; x < NC; ++x) {
+        // cell x = sum_i g_i 3^(K-1-i)
+        u64 a = ~0ull;
+        int rem = x;
+#pragma unroll
+        for (int i = K - 1; i >= 0; --i) {
+          a &= r[i][rem % 3];
+          rem /= 3;
+        }
+        t[x][cls] += popc64(a);
+      }
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < NC; ++x)
+#pragma unroll
+    for (int cls = 0; cls < 2; ++cls) {
+      uint32_t v = t[x][cls];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) {
+        if (lds_t) lds_t[2 * x + cls] = v;
+        if (WRITE_TABLE) table_out[2 * x + cls] = v;
+      }
+    }
+}
+
 template <bool WRITE_TABLE>
 __device__ void count_cells(const JobDesc &J, const JobState *st, const uint32_t *c,
                             uint32_t k, uint32_t lane, uint32_t *lds_t,
                             uint32_t *table_out) {
+  if (k == 2) return count_cells_small<2, WRITE_TABLE>(J, st, c, lane, lds_t, table_out);
+  if (k == 3) return count_cells_small<3, WRITE_TABLE>(J, st, c, lane, lds_t, table_out);
   uint32_t cells = 1;
   for (uint32_t i = 0; i < k; ++i) cells *= 3;
   const uint32_t W0 = st->W0, W = st->W0 + st->W1, wcap = J.wcap;
