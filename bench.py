@@ -76,6 +76,39 @@ def word_ops_per_combination(k: int, m0: int, m1: int, kernel: int) -> int:
 MFMA_I8_PEAK_OPS = 5.0e15
 
 
+def kernel_sources_sha256() -> str:
+    """Hash of every device source of the library (any change voids counters
+    taken on an earlier build)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2201_03331_amd", "csrc", "*.hip")) +
+                   glob.glob(os.path.join(ROOT, "paper_2201_03331_amd", "csrc", "*.hpp")) +
+                   [os.path.join(ROOT, "include", "fiuncho.h")])
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the counter table in
+    profiles/hbm_traffic.md (rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a
+    copy of known size), or None when no row was taken on these sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    sha = kernel_sources_sha256()
+    for line in open(path):
+        cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 8 and cells[0] == kernel and cells[1] == workload and cells[2] == sha:
+            try:
+                return float(cells[7])
+            except ValueError:
+                return None
+    return None
+
+
 def cpu_baseline(d, budget_s: float = 20.0):
     """The oracle (plain per-sample counting, FP64 MI) timed on the host cores
     over a contiguous sample of ranks of the same workload."""
@@ -222,13 +255,13 @@ def main():
         peak = MFMA_I8_PEAK_OPS / 1e12
         roofline = {"bound": "mfma", "kernel": "mfma2_kernel (one-hot int8 contraction + FP32 MI + filter)",
                     "achieved": achieved, "peak": peak, "unit": "T int8 op/s", "frac": achieved / peak,
-                    "traffic": None}
+                    "traffic": measured_traffic("mfma2_kernel", args.workload)}
     else:
         achieved = lane_ops / (scan_ms / 1e3) / 1e12
         peak = VALU_PEAK_LANE_OPS / 1e12
         roofline = {"bound": "alu", "kernel": "scan_kernel (AND+popcount counting + FP32 MI + filter)",
                     "achieved": achieved, "peak": peak, "unit": "T int32 lane-op/s", "frac": achieved / peak,
-                    "traffic": None}
+                    "traffic": measured_traffic("scan_kernel", args.workload)}
     names = {fiuncho.KERNEL_POPCOUNT: "popcount", fiuncho.KERNEL_PAIRS: "pairs", fiuncho.KERNEL_MFMA: "mfma",
              fiuncho.KERNEL_TRIPLES: "triples"}
 

@@ -447,3 +447,34 @@ def test_plan_upload_flag_after_workspace_reuse():
     again = b.results()
     assert first[0][0] == 0 and first[0][1].tobytes() == again[0][1].tobytes()
     check_hits_against_oracle(d.genotypes, d.phenotype, 3, 20, again[0][1])
+
+
+# ---------------------------------------------------------------------------
+# size extremes
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mfma", ["0", "1"])
+def test_maximum_samples(mfma, monkeypatch):
+    """samples = 2^24 - 1, the largest accepted: counts far above 2^16, the
+    widest single-precision bound, 262,146-word rows."""
+    monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", mfma)
+    n, m = 5, (1 << 24) - 1
+    rng = np.random.default_rng(70)
+    G = rng.integers(0, 3, (n, m), dtype=np.uint8)
+    y = (rng.random(m) < 0.45).astype(np.uint8)
+    for k in ((2,) if mfma == "1" else (1, 2, 3)):
+        say(f"case: maximum samples k={k} mfma={mfma}")
+        hits = fiuncho.scan(G, y, k, 5)
+        check_hits_against_oracle(G, y, k, 5, hits)
+
+
+def test_many_variants_order2():
+    """30,000 variants (4.5e8 pairs, matrix-core kernel by the rule)."""
+    full_size_check(synth.generate(30000, 128, seed=71, order=2, top_n=50, name="order2-30000x128"),
+                    20000, 72)
+
+
+def test_many_variants_order3():
+    """3,000 variants (4.5e9 triples, 295 MB of pair tables)."""
+    full_size_check(synth.generate(3000, 64, seed=73, order=3, top_n=50, name="order3-3000x64"),
+                    20000, 74)
