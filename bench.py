@@ -234,8 +234,8 @@ def main():
 
     # roofline of the dominant counting kernel: algorithmic work per launch
     # over that kernel's measured time.  Popcount kernels: 32-bit VALU
-    # lane-ops (4 per 64-bit AND+popcount).  Matrix-core order 2: int8 ops of
-    # the one-hot contraction, 2 x 4 cells x m samples per pair.
+    # lane-ops (4 per 64-bit AND+popcount).  Matrix-core kernels: int8 ops of
+    # the one-hot contraction, 2 x (4 or 8) cells x m samples per combination.
     lane_ops = 0
     mfma_ops = 0
     kernels = set()
@@ -244,7 +244,10 @@ def main():
         kern = fiuncho.get_kernel(d.n, d.m, d.order)
         kernels.add(kern)
         if kern == fiuncho.KERNEL_MFMA:
-            mfma_ops += 2 * 4 * d.m * share(d)
+            # the {0,1}^k cells of every combination over every sample: 4 at
+            # order 2, 8 at order 3 (the others come from class counts and
+            # pair tables)
+            mfma_ops += 2 * (4 if d.order == 2 else 8) * d.m * share(d)
         else:
             lane_ops += 4 * word_ops_per_combination(d.order, d.m - m1, m1, kern) * share(d)
     calls = len(batches) if plain else 1
@@ -253,9 +256,9 @@ def main():
     if mfma_ms > scan_ms:
         achieved = mfma_ops / (mfma_ms / 1e3) / 1e12
         peak = MFMA_I8_PEAK_OPS / 1e12
-        roofline = {"bound": "mfma", "kernel": "mfma2_kernel (one-hot int8 contraction + FP32 MI + filter)",
+        roofline = {"bound": "mfma", "kernel": "mfma_kernel (one-hot int8 contraction + FP32 MI + filter)",
                     "achieved": achieved, "peak": peak, "unit": "T int8 op/s", "frac": achieved / peak,
-                    "traffic": measured_traffic("mfma2_kernel", args.workload)}
+                    "traffic": measured_traffic("mfma_kernel", args.workload)}
     else:
         achieved = lane_ops / (scan_ms / 1e3) / 1e12
         peak = VALU_PEAK_LANE_OPS / 1e12

@@ -211,8 +211,10 @@ int fiuncho_shard_counts(uint32_t snps, uint32_t samples, int order, uint32_t un
                                      g = 0, 1 of the last variant (any order) */
 #define FIUNCHO_KERNEL_PAIRS 2    /* order 3: only the {0,1}^3 cells counted, the
                                      rest from stored pair tables */
-#define FIUNCHO_KERNEL_MFMA 3     /* order 2: one-hot int8 contraction on the
-                                     matrix cores */
+#define FIUNCHO_KERNEL_MFMA 3     /* orders 2 and 3: one-hot int8 contraction on
+                                     the matrix cores (order 2: variant x variant;
+                                     order 3: prefix pair x variant, the other
+                                     cells from pair tables) */
 #define FIUNCHO_KERNEL_TRIPLES 4  /* order 4: only the {0,1}^4 cells counted, the
                                      rest from stored triple and pair tables
                                      (64 bytes of device memory per pair and

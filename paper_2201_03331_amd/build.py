@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfiuncho.so")
-SOURCES = ["api.hip", "pack.hip", "scan.hip", "mfma2.hip", "select.hip"]
+SOURCES = ["api.hip", "pack.hip", "scan.hip", "mfma.hip", "select.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

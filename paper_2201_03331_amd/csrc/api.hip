@@ -114,10 +114,12 @@ void build_rows(uint32_t n, uint32_t k, uint32_t path, std::vector<u64> &row_sta
     }
     return;
   }
-  if (path == fiuncho::kPathPairs) {
-    // rows b = 1 .. n-2; groups of kScanWaves * kOrder3Prefixes first variants
+  if (path == fiuncho::kPathPairs || path == fiuncho::kPathMfma3) {
+    // rows b = 1 .. n-2; groups of first variants (kScanWaves * kOrder3Prefixes
+    // on the popcount kernel, 32 on the matrix cores) x blocks of 64 last variants
+    const u64 G = path == fiuncho::kPathPairs ? (u64)fiuncho::kScanWaves * fiuncho::kOrder3Prefixes : 32;
     for (u64 b = 1; b + 2 <= n; ++b) {
-      const u64 groups = ceil_div(b, (u64)fiuncho::kScanWaves * fiuncho::kOrder3Prefixes);
+      const u64 groups = ceil_div(b, G);
       acc += groups * ceil_div(n - 1 - b, 64);
       row_start.push_back(acc);
     }
@@ -171,10 +173,12 @@ void for_each_tile(uint32_t n, uint32_t k, uint32_t path, Fn fn) {
     return;
   }
   // rows b (second-to-last variant): groups of prefixes x blocks of 64 last variants
-  const u64 G = path == fiuncho::kPathPairs ? (u64)fiuncho::kScanWaves * fiuncho::kOrder3Prefixes
-                                            : (u64)fiuncho::kScanWaves;
-  for (u64 b = (path == fiuncho::kPathPairs ? 1 : k - 2); b + 2 <= N; ++b) {
-    const u64 prefixes = path == fiuncho::kPathPairs ? b : binom_host(b, k - 2);
+  const bool by_pairs = path == fiuncho::kPathPairs || path == fiuncho::kPathMfma3;
+  const u64 G = path == fiuncho::kPathPairs   ? (u64)fiuncho::kScanWaves * fiuncho::kOrder3Prefixes
+                : path == fiuncho::kPathMfma3 ? 32
+                                              : (u64)fiuncho::kScanWaves;
+  for (u64 b = (by_pairs ? 1 : k - 2); b + 2 <= N; ++b) {
+    const u64 prefixes = by_pairs ? b : binom_host(b, k - 2);
     for (u64 p0 = 0; p0 < prefixes; p0 += G) {
       const u64 pc = std::min<u64>(G, prefixes - p0);
       for (u64 j0 = b + 1; j0 < N; j0 += 64) fn(lt++, pc * std::min<u64>(64, N - j0));
@@ -226,7 +230,7 @@ bool kernel_valid(int kernel, uint32_t n, uint32_t k) {
   switch (kernel) {
     case FIUNCHO_KERNEL_POPCOUNT: return true;
     case FIUNCHO_KERNEL_PAIRS: return k == 3 && n >= 3;
-    case FIUNCHO_KERNEL_MFMA: return k == 2;
+    case FIUNCHO_KERNEL_MFMA: return k == 2 || (k == 3 && n >= 3);
     case FIUNCHO_KERNEL_TRIPLES: return k == 4 && n >= 4 && triple_table_bytes(n) <= kMaxTripleTableBytes;
     default: return false;
   }
@@ -251,6 +255,8 @@ int choose_kernel(uint32_t n, uint32_t m, uint32_t k) {
   if (k == 4 && e4 && e4[0] == '0') return FIUNCHO_KERNEL_POPCOUNT;
   if (k == 4 && e4 && e4[0] == '1' && kernel_valid(FIUNCHO_KERNEL_TRIPLES, n, k))
     return FIUNCHO_KERNEL_TRIPLES;
+  const char *e3m = std::getenv("FIUNCHO_ORDER3_MFMA");
+  if (k == 3 && e3m && e3m[0] == '1' && n >= 3) return FIUNCHO_KERNEL_MFMA;
   const char *e2 = std::getenv("FIUNCHO_ORDER2_MFMA");
   if (k == 2 && e2 && e2[0] == '0') return FIUNCHO_KERNEL_POPCOUNT;
   if (k == 2 && e2 && e2[0] == '1') return FIUNCHO_KERNEL_MFMA;
@@ -263,10 +269,14 @@ int choose_kernel(uint32_t n, uint32_t m, uint32_t k) {
   return rule_kernel(n, k);
 }
 
+bool on_matrix_cores(uint32_t path) {
+  return path == fiuncho::kPathMfma2 || path == fiuncho::kPathMfma3;
+}
+
 uint32_t job_path(uint32_t n, uint32_t m, uint32_t k) {
   switch (choose_kernel(n, m, k)) {
     case FIUNCHO_KERNEL_PAIRS: return fiuncho::kPathPairs;
-    case FIUNCHO_KERNEL_MFMA: return fiuncho::kPathMfma2;
+    case FIUNCHO_KERNEL_MFMA: return k == 2 ? fiuncho::kPathMfma2 : fiuncho::kPathMfma3;
     case FIUNCHO_KERNEL_TRIPLES: return fiuncho::kPathTriples;
     default: return fiuncho::kPathGeneric;
   }
@@ -295,7 +305,9 @@ struct Layout {
   uint32_t nmax, kmax, max_n_pad, max_wcap, max_cand_cap, max_l2_cap, max_pairs_n, max_triples_n;
   size_t plan_begin, plan_end;  // uploaded region
   size_t off_desc, off_jts, off_jps, off_binom, off_counter;
-  uint32_t n_scan;  // jobs [0, n_scan) of the tile-space order run in scan_kernel, the rest in mfma2_kernel
+  // tile-space order: [0, n_scan) popcount kernel, then n_mfma2 order-2 and
+  // the rest order-3 matrix-core jobs
+  uint32_t n_scan, n_mfma2;
   size_t total;
   int ksel;
 };
@@ -349,7 +361,8 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
       const u64 s = want ? std::min<u64>({J.tiles, (u64)fiuncho::kPilotTiles,
                                           std::max<u64>(16, J.tiles / 32)})
                          : 0;
-      const u64 per = J.path == fiuncho::kPathMfma2 ? fiuncho::kMfmaPilotEmits : fiuncho::kPilotEmits;
+      const bool mm = J.path == fiuncho::kPathMfma2 || J.path == fiuncho::kPathMfma3;
+      const u64 per = mm ? fiuncho::kMfmaPilotEmits : fiuncho::kPilotEmits;
       const u64 slots = s * fiuncho::kScanWaves * per * 64;
       const bool fits = slots * sizeof(uint32_t) <= (u64)J.cand_cap * sizeof(Cand);
       J.pilot_tiles = (s > 0 && fits) ? (uint32_t)s : 0;
@@ -358,11 +371,13 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     const double words = (double)J.wcap;
     J.cost = J.k == 1 ? 1.0
              : J.path == fiuncho::kPathMfma2 ? words * 4 * 64
+             : J.path == fiuncho::kPathMfma3 ? words * 8 * 64
              : J.k == 2 ? words * 4 * fiuncho::kOrder2Prefixes
              : J.path == fiuncho::kPathPairs ? words * 8 * fiuncho::kOrder3Prefixes
              : J.path == fiuncho::kPathTriples ? words * 20
                                              : words * 18 * std::pow(3.0, (double)J.k - 3);
-    const bool need_pairs = J.path == fiuncho::kPathPairs || J.path == fiuncho::kPathTriples;
+    const bool need_pairs = J.path == fiuncho::kPathPairs || J.path == fiuncho::kPathTriples ||
+                            J.path == fiuncho::kPathMfma3;
     if (need_pairs) L.max_pairs_n = std::max(L.max_pairs_n, J.n);
     if (J.path == fiuncho::kPathTriples) L.max_triples_n = std::max(L.max_triples_n, J.n);
     L.nmax = std::max(L.nmax, J.n);
@@ -421,11 +436,17 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
   for (uint32_t i = 0; i < n_jobs; ++i) L.order[i] = i;
   std::stable_sort(L.order.begin(), L.order.end(),
                    [&](uint32_t a, uint32_t b) { return L.jobs[a].cost > L.jobs[b].cost; });
-  // jobs on the matrix-core path go last: they run in their own launch
+  // jobs on the matrix cores go last, order 2 before order 3: each group runs
+  // in its own launch
   std::stable_partition(L.order.begin(), L.order.end(),
-                        [&](uint32_t a) { return L.jobs[a].path != fiuncho::kPathMfma2; });
-  L.n_scan = 0;
-  for (auto &J : L.jobs) L.n_scan += J.path != fiuncho::kPathMfma2;
+                        [&](uint32_t a) { return !on_matrix_cores(L.jobs[a].path); });
+  std::stable_partition(L.order.begin(), L.order.end(),
+                        [&](uint32_t a) { return L.jobs[a].path != fiuncho::kPathMfma3; });
+  L.n_scan = L.n_mfma2 = 0;
+  for (auto &J : L.jobs) {
+    L.n_scan += !on_matrix_cores(J.path);
+    L.n_mfma2 += J.path == fiuncho::kPathMfma2;
+  }
   auto sel = [](const JobLayout &J) {
     return J.path == fiuncho::kPathPairs     ? fiuncho::kSelPairs
            : J.path == fiuncho::kPathTriples ? fiuncho::kSelTriples
@@ -434,7 +455,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
   L.ksel = -1;
   bool only23 = true;
   for (auto &J : L.jobs) {
-    if (J.path == fiuncho::kPathMfma2) continue;
+    if (on_matrix_cores(J.path)) continue;
     if (L.ksel < 0) L.ksel = sel(J);
     else if (sel(J) != L.ksel) L.ksel = 0;
     only23 = only23 && (J.k == 2 || J.path == fiuncho::kPathPairs);
@@ -705,7 +726,7 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   for (auto &J : L.jobs)
     kernels |= 1u << (J.path == fiuncho::kPathPairs     ? FIUNCHO_KERNEL_PAIRS
                       : J.path == fiuncho::kPathTriples ? FIUNCHO_KERNEL_TRIPLES
-                      : J.path == fiuncho::kPathMfma2 ? FIUNCHO_KERNEL_MFMA
+                      : on_matrix_cores(J.path)         ? FIUNCHO_KERNEL_MFMA
                                                       : FIUNCHO_KERNEL_POPCOUNT);
   if ((st = prof_begin(combos, kernels, reinterpret_cast<JobState *>(ws + L.jobs[0].off_state))))
     return st;
@@ -722,26 +743,29 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
     ts[p + 1] = ts[p] + L.jobs[L.order[p]].tiles;
     ps[p + 1] = ps[p] + L.jobs[L.order[p]].pilot_tiles;
   }
-  const uint32_t ns = L.n_scan, nm = nj - L.n_scan;
-  auto counting = [&](const Globals &c, bool mfma) {
+  const uint32_t ns = L.n_scan, nm2 = L.n_mfma2, nm3 = nj - L.n_scan - L.n_mfma2;
+  // order 0: the popcount kernel; 2, 3: the matrix-core kernel of that order
+  auto counting = [&](const Globals &c, int order) {
     if (c.total_tiles <= c.tile_base) return;
     const u64 tiles = c.total_tiles - c.tile_base;
-    const int gmax = mfma ? fiuncho::mfma2_grid_size() : fiuncho::scan_grid_size(L.ksel);
+    const int gmax = order ? fiuncho::mfma_grid_size(order) : fiuncho::scan_grid_size(L.ksel);
     const int grid = (int)std::min<u64>((u64)gmax, tiles);
-    if (mfma) fiuncho::launch_mfma2(c, grid, s);
+    if (order) fiuncho::launch_mfma(c, order, grid, s);
     else fiuncho::launch_scan(c, L.ksel, grid, s);
   };
   if (g.total_pilot_tiles) {
-    if (ns) counting(launch_globals(g, ps, 0, ns, true, 1), false);
-    if (nm) counting(launch_globals(g, ps, ns, nm, true, 3), true);
+    if (ns) counting(launch_globals(g, ps, 0, ns, true, 1), 0);
+    if (nm2) counting(launch_globals(g, ps, ns, nm2, true, 3), 2);
+    if (nm3) counting(launch_globals(g, ps, ns + nm2, nm3, true, 5), 3);
     uint32_t max_slots = 0;
     for (auto &J : L.jobs) max_slots = std::max(max_slots, J.pilot_slots);
     fiuncho::launch_pilot_select(g, max_slots, s);
   }
   if ((st = prof_record(2, s))) return st;
-  if (ns) counting(launch_globals(g, ts, 0, ns, false, 0), false);
+  if (ns) counting(launch_globals(g, ts, 0, ns, false, 0), 0);
   if ((st = prof_record(3, s))) return st;
-  if (nm) counting(launch_globals(g, ts, ns, nm, false, 2), true);
+  if (nm2) counting(launch_globals(g, ts, ns, nm2, false, 2), 2);
+  if (nm3) counting(launch_globals(g, ts, ns + nm2, nm3, false, 4), 3);
   if ((st = prof_record(4, s))) return st;
   fiuncho::launch_select(g, L.max_cand_cap, s);
   fiuncho::launch_rescore(g, L.max_l2_cap, L.kmax, s);

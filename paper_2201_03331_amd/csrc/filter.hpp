@@ -172,6 +172,102 @@ __device__ __forceinline__ void score_table(const JV &v, const FI_GLOBAL float *
   emit(v, active, fs * mc.inv_m, rank, thr, lane);
 }
 
+// 8 u32 of a pair table entry: [ga][gj][c]
+__device__ __forceinline__ void load_pair(const FI_GLOBAL uint32_t *p, uint32_t (&q)[8]) {
+  const FI_GLOBAL u64 *p64 = reinterpret_cast<const FI_GLOBAL u64 *>(p);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const u64 x = p64[i];
+    q[2 * i] = (uint32_t)x;
+    q[2 * i + 1] = (uint32_t)(x >> 32);
+  }
+}
+
+// The 27 cells of an order-3 table from its {0,1}^3 counts D, the {0,1}^2
+// counts of its three pairs, the {0,1} counts of its variants and the class
+// sizes.  With "any" marginalising a position, T[x][y][2] = N[x][y][any] -
+// T[x][y][0] - T[x][y][1] and likewise along the other positions; the cells
+// are produced in an order where each needs only cells already produced.
+struct Order3Parts {
+  const uint32_t (&D)[2][2][2][2];   // [c][ga][gb][gj]
+  const uint32_t (&ab)[8];           // (a, b): [ga][gb][c]
+  const uint32_t (&aj)[8];           // (a, j): [ga][gj][c]
+  const uint32_t (&bj)[8];           // (b, j): [gb][gj][c]
+  const uint32_t (&Ma)[2][2];        // [g][c]
+  const uint32_t (&Mb)[2][2];
+  const uint32_t (&Mj)[2][2];
+  const uint32_t (&m)[2];            // class sizes
+};
+
+template <typename Visit>
+__device__ __forceinline__ void walk_order3(const Order3Parts &q, Visit &&visit) {
+  uint32_t sum[2] = {0, 0};
+  uint32_t x2z[2][2][2], t2yz[2][2][2];  // [c][x or y][z]
+  auto cell = [&](uint32_t n0, uint32_t n1) {
+    sum[0] += n0;
+    sum[1] += n1;
+    visit(n0, n1);
+  };
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int z = 0; z < 2; ++z) cell(q.D[0][x][y][z], q.D[1][x][y][z]);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      uint32_t t[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) t[c] = q.ab[x * 4 + y * 2 + c] - q.D[c][x][y][0] - q.D[c][x][y][1];
+      cell(t[0], t[1]);  // (x, y, 2)
+    }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        x2z[c][x][z] = q.aj[x * 4 + z * 2 + c] - q.D[c][x][0][z] - q.D[c][x][1][z];
+      cell(x2z[0][x][z], x2z[1][x][z]);  // (x, 2, z)
+    }
+#pragma unroll
+  for (int y = 0; y < 2; ++y)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        t2yz[c][y][z] = q.bj[y * 4 + z * 2 + c] - q.D[c][0][y][z] - q.D[c][1][y][z];
+      cell(t2yz[0][y][z], t2yz[1][y][z]);  // (2, y, z)
+    }
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+    uint32_t t[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      t[c] = q.Ma[x][c] - q.ab[x * 4 + c] - q.ab[x * 4 + 2 + c] - x2z[c][x][0] - x2z[c][x][1];
+    cell(t[0], t[1]);  // (x, 2, 2)
+  }
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    uint32_t t[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      t[c] = q.Mb[y][c] - q.ab[y * 2 + c] - q.ab[4 + y * 2 + c] - t2yz[c][y][0] - t2yz[c][y][1];
+    cell(t[0], t[1]);  // (2, y, 2)
+  }
+#pragma unroll
+  for (int z = 0; z < 2; ++z) {
+    uint32_t t[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      t[c] = q.Mj[z][c] - q.aj[z * 2 + c] - q.aj[4 + z * 2 + c] - t2yz[c][0][z] - t2yz[c][1][z];
+    cell(t[0], t[1]);  // (2, 2, z)
+  }
+  visit(q.m[0] - sum[0], q.m[1] - sum[1]);  // (2, 2, 2)
+}
+
 // Decodes global tile t of a launch: its job (binary search over the job
 // tile starts), the job's view with the run state read in, and the job-local
 // tile index.  In a pilot launch, pilot tile i of S stands for tile

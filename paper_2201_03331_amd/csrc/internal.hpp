@@ -30,9 +30,10 @@ constexpr uint32_t kPathGeneric = 0;          // rows g = 0, 1 of the last varia
 constexpr uint32_t kPathPairs = 1;            // order 3, {0,1}^3 cells + pair tables
 constexpr int kSelPairs = 31;                 // scan_kernel selector: order-3 pair path only
 constexpr int kSel23 = 23;                    // scan_kernel selector: orders 2 and 3 (pair path)
-constexpr int kTileCounters = 4;              // scan, scan pilot, mfma2, mfma2 pilot
+constexpr int kTileCounters = 6;              // scan, its pilot, order-2 mfma, its pilot, order-3 mfma, its pilot
 constexpr uint32_t kPathMfma2 = 2;
 constexpr uint32_t kPathTriples = 3;          // order 4, {0,1}^4 cells + triple and pair tables
+constexpr uint32_t kPathMfma3 = 4;            // order 3 on the matrix cores (prefix pairs x variants)
 constexpr int kSelTriples = 41;               // scan_kernel selector: order-4 triple-table path only            // order 2 on the matrix cores (mfma2_kernel)
 
 // state the device writes during one run of a job (cleared at the start)
@@ -136,8 +137,8 @@ void launch_pack(const Globals &g, uint32_t max_n_pad, uint32_t max_wcap, hipStr
 void launch_pairs(const Globals &g, uint32_t max_n, hipStream_t s);
 void launch_triples(const Globals &g, uint32_t max_n, hipStream_t s);
 void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s);
-void launch_mfma2(const Globals &g, int grid, hipStream_t s);
-int mfma2_grid_size();
+void launch_mfma(const Globals &g, int order, int grid, hipStream_t s);
+int mfma_grid_size(int order);
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
 void launch_pilot_select(const Globals &g, uint32_t max_pilot_slots, hipStream_t s);
 void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s);

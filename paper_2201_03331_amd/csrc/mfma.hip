@@ -1,4 +1,4 @@
-// mfma2.hip -- order 2 on the matrix cores.
+// mfma.hip -- orders 2 and 3 on the matrix cores.
 //
 // For a pair (a, j) the scan needs the four cells g_a, g_j in {0, 1} per class
 // (the cells with a 2 follow from the class counts, section 3.2).  Written
@@ -16,6 +16,12 @@
 // words).  Operands are not stored as bytes: each lane reads the 64-bit word
 // of its row from the packed bitsets and expands the 16 samples it feeds to
 // 16 bytes in registers, so the cache traffic is that of the bitsets.
+//
+// Order 3 uses the same contraction with prefix pairs as rows: row 4p + 2 g_a
+// + g_b of a fragment is the AND of the genotype rows g_a of a_p and g_b of b
+// (8 prefix pairs (a_p, b) per fragment, b fixed for the tile), so a block
+// holds the {0,1}^3 cells of 8 prefixes x 16 last variants; the other cells
+// come from the pair tables by inclusion-exclusion, as in the popcount kernel.
 #include "filter.hpp"
 
 namespace fiuncho {
@@ -55,23 +61,18 @@ __device__ __forceinline__ v4i expand16(const u64 *lut, uint32_t b) {
 // the 16 samples [16 (l / 32), 16 (l / 32) + 16) of each 32-sample step; the
 // matrix instruction pairs the same lane half and byte of both operands, so
 // any fixed sample order inside a lane is exact.
-__device__ __forceinline__ void mfma_class(const FI_GLOBAL u64 *pa, const FI_GLOBAL u64 *pj,
-                                           size_t word_stride, uint32_t wbeg, uint32_t wend,
+template <typename Load>
+__device__ __forceinline__ void mfma_class(Load &&load_words, uint32_t wbeg, uint32_t wend,
                                            uint32_t h, const u64 *lut, v16i (&acc)[2][2]) {
   if (wbeg >= wend) return;
-  // the rows of the next kDepth words are in flight in a register ring
+  // the rows of the next kDepth words are in flight in a register ring;
+  // load_words(w, x) fills x with the lane's words of both A fragments and
+  // both B fragments
   constexpr int kDepth = 3;
   const uint32_t wlast = wend - 1;
   u64 X[kDepth][4];
-  auto load = [&](int slot, uint32_t w) {
-    const size_t o = (size_t)w * word_stride;
-    X[slot][0] = pa[o];
-    X[slot][1] = pa[o + 32];
-    X[slot][2] = pj[o];
-    X[slot][3] = pj[o + 32];
-  };
 #pragma unroll
-  for (int u = 0; u < kDepth; ++u) load(u, min(wbeg + u, wlast));
+  for (int u = 0; u < kDepth; ++u) load_words(min(wbeg + u, wlast), X[u]);
   auto step = [&](int slot) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -93,7 +94,7 @@ __device__ __forceinline__ void mfma_class(const FI_GLOBAL u64 *pa, const FI_GLO
 #pragma unroll
     for (int u = 0; u < kDepth; ++u) {
       step(u);
-      load(u, min(w + u + kDepth, wlast));
+      load_words(min(w + u + kDepth, wlast), X[u]);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -111,6 +112,13 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
   const FI_GLOBAL u64 *Bv = as_global(v.Bv);
   const FI_GLOBAL u64 *pa = Bv + (size_t)a0 * 2 + r;
   const FI_GLOBAL u64 *pj = Bv + (size_t)j0 * 2 + r;
+  auto load_words = [&](uint32_t w, u64 (&x)[4]) {
+    const size_t o = (size_t)w * word_stride;
+    x[0] = pa[o];
+    x[1] = pa[o + 32];
+    x[2] = pj[o];
+    x[3] = pj[o + 32];
+  };
   v16i acc0[2][2], acc1[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -118,8 +126,8 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc0[x][y][e] = acc1[x][y][e] = 0;
-  mfma_class(pa, pj, word_stride, 0, v.W0, h, lut, acc0);
-  mfma_class(pa, pj, word_stride, v.W0, v.W0 + v.W1, h, lut, acc1);
+  mfma_class(load_words, 0, v.W0, h, lut, acc0);
+  mfma_class(load_words, v.W0, v.W0 + v.W1, h, lut, acc1);
 
   // Output block layout: lane l holds column l mod 32 (variant j0' + (l mod
   // 32) / 2, genotype l mod 2); register e holds row 8 (e / 4) + 4 h + e mod 4
@@ -190,7 +198,124 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
   }
 }
 
-__global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma2_kernel(Globals g) {
+// One wave: prefixes (a_first + [0, 16), b) x last variants (j0 + [0, 32)).
+__device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint32_t b,
+                                             uint32_t a_first, uint32_t j0, uint32_t lane,
+                                             const u64 *lut) {
+  const uint32_t n = v.n;
+  const uint32_t r = lane & 31, h = lane >> 5;
+  const size_t word_stride = (size_t)v.n_pad * 2;
+  const FI_GLOBAL u64 *Bv = as_global(v.Bv);
+  const FI_GLOBAL u64 *Bs = as_global(v.Bs);
+  // A rows: lane r of fragment f is prefix a_first + 8 f + r / 4 with genotype
+  // rows g_a = (r >> 1) & 1, g_b = r & 1; prefixes a >= b count nothing
+  const uint32_t ga = (r >> 1) & 1, gb = r & 1;
+  const FI_GLOBAL u64 *pb = Bs + (size_t)b * 4 * v.wcap + gb;
+  const FI_GLOBAL u64 *pa[2];
+  u64 amask[2];
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    const uint32_t a = a_first + 8 * f + (r >> 2);
+    pa[f] = Bs + (size_t)min(a, b - 1) * 4 * v.wcap + ga;
+    amask[f] = a < b ? ~0ull : 0ull;
+  }
+  const FI_GLOBAL u64 *pj = Bv + (size_t)j0 * 2 + r;
+  auto load_words = [&](uint32_t w, u64 (&x)[4]) {
+    const u64 wb = pb[(size_t)w * 4];
+    x[0] = pa[0][(size_t)w * 4] & wb & amask[0];
+    x[1] = pa[1][(size_t)w * 4] & wb & amask[1];
+    const size_t o = (size_t)w * word_stride;
+    x[2] = pj[o];
+    x[3] = pj[o + 32];
+  };
+  v16i acc0[2][2], acc1[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc0[x][y][e] = acc1[x][y][e] = 0;
+  mfma_class(load_words, 0, v.W0, h, lut, acc0);
+  mfma_class(load_words, v.W0, v.W0 + v.W1, h, lut, acc1);
+
+  // Output block (f, fb): lane l holds column l mod 32 (last variant j0 + 16 fb
+  // + (l mod 32) / 2, genotype l mod 2); register e holds row 8 (e / 4) + 4 h +
+  // e mod 4, i.e. prefix a_first + 8 f + 2 (e / 4) + h with (g_a, g_b) = e mod 4
+  // in binary.  Lanes l and l ^ 1 hold the two genotypes of the same j; the
+  // lane of genotype bit gl scores the prefixes with e / 4 in {2 gl, 2 gl + 1}
+  // after taking the partner's counts for the other genotype of j.
+  const uint32_t gl = lane & 1;
+  const float thr = current_threshold(v);
+  const MiConst mc = mi_const(v);
+  const FI_GLOBAL float *F = as_global(v.Fh);
+  const FI_GLOBAL uint32_t *marg = as_global(v.marg);
+  const FI_GLOBAL uint32_t *PT = as_global(v.pairs);
+  const uint32_t mcls[2] = {v.m0, v.m1};
+  uint32_t Mb[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) Mb[x][c] = marg[(size_t)b * 6 + 2 * x + c];
+#pragma unroll
+  for (int fb = 0; fb < 2; ++fb) {
+    const uint32_t j = j0 + 16 * fb + (r >> 1);
+    const uint32_t jj = j < n ? j : n - 1;
+    uint32_t Mj[2][2], bj[8];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) Mj[x][c] = marg[(size_t)jj * 6 + 2 * x + c];
+    load_pair(PT + ((size_t)b * v.n_pad + jj) * 8, bj);
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        // this lane's prefix: e / 4 = 2 gl + t
+        const uint32_t a = a_first + 8 * f + 2 * (2 * gl + t) + h;
+        uint32_t D[2][2][2][2];  // [class][g_a][g_b][g_j]
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const v16i &A = c == 0 ? acc0[f][fb] : acc1[f][fb];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint32_t lo = (uint32_t)A[4 * t + i], hi = (uint32_t)A[4 * (2 + t) + i];
+            const uint32_t own = gl ? hi : lo;
+            const uint32_t send = gl ? lo : hi;
+            const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
+            D[c][i >> 1][i & 1][gl] = own;
+            D[c][i >> 1][i & 1][gl ^ 1] = recv;
+          }
+        }
+        const bool active = a < b && j < n;
+        const uint32_t aa = a < b ? a : b - 1;
+        uint32_t ab[8], aj[8], Ma[2][2];
+        load_pair(PT + ((size_t)aa * v.n_pad + b) * 8, ab);
+        load_pair(PT + ((size_t)aa * v.n_pad + jj) * 8, aj);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) Ma[x][c] = marg[(size_t)aa * 6 + 2 * x + c];
+        const Order3Parts parts = {D, ab, aj, bj, Ma, Mb, Mj, mcls};
+        float fs = mc.c;
+        if (active) {
+          // every count is at most its class size; the clamps keep the table
+          // lookups inside [0, m] whatever the counts hold
+          walk_order3(parts, [&](uint32_t n0, uint32_t n1) {
+            fs += mi_term(F, min(n0, mcls[0]), min(n1, mcls[1]));
+          });
+        }
+        const uint32_t pre[2] = {aa, b};
+        const u64 rank = active ? lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1) : 0;
+        emit(v, active, fs * mc.inv_m, rank, thr, lane);
+      }
+    }
+  }
+}
+
+// ORDER 2 or 3: the kernel serves the jobs of that order (a batch with both
+// launches it twice, over the two orders' tiles)
+template <int ORDER>
+__global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
   __shared__ u64 s_tile;
   __shared__ u64 s_lut[256 * kLutCopies];
   const uint32_t lane = lane_id();
@@ -207,7 +332,6 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma2_kernel(Globals g) {
     const FI_CONST JobDesc *jd;
     u64 lt;
     if (!locate_tile(g, t, wave, kMfmaPilotEmits, v, jd, lt)) continue;
-    // tile (A, B) of the upper triangle of 64-variant blocks, row A first
     cu64p rows = as_const(uni_ptr(jd->row_start));
     uint32_t rl = 0, rh = uni(jd->nrows) - 1;
     while (rl < rh) {
@@ -216,7 +340,25 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma2_kernel(Globals g) {
       else rh = mid - 1;
     }
     rl = uni(rl);
-    const uint32_t B = rl + (uint32_t)uni64(lt - rows[rl]);
+    const u64 local = uni64(lt - rows[rl]);
+    if (ORDER == 3) {
+      if (v.path != kPathMfma3) continue;
+      // row b = rl + 1: groups of 32 first variants x blocks of 64 last variants
+      const uint32_t b = rl + 1;
+      const uint32_t nj = (v.n - 1 - b + 63) / 64;
+      const u64 grp = local / nj;
+      const uint32_t jb = (uint32_t)(local - grp * nj);
+      const uint32_t a_first = (uint32_t)grp * 32 + 16 * (wave >> 1);
+      const uint32_t j0 = b + 1 + 64 * jb + 32 * (wave & 1);
+      // a wave without a prefix a < b or a last variant j < n has nothing to
+      // count; its pilot slots stay zero
+      if (a_first >= b || j0 >= v.n) continue;
+      wave_prefix3(g, v, b, a_first, j0, lane, lut);
+      continue;
+    }
+    // order 2: tile (A, B) of the upper triangle of 64-variant blocks, row A first
+    if (v.path != kPathMfma2) continue;
+    const uint32_t B = rl + (uint32_t)local;
     const uint32_t a0 = 64 * rl + 32 * (wave >> 1);
     const uint32_t j0 = 64 * B + 32 * (wave & 1);
     // a wave with no pair a < j < n has nothing to count; its pilot slots
@@ -226,18 +368,22 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma2_kernel(Globals g) {
   }
 }
 
-int mfma2_grid_size() {
+int mfma_grid_size(int order) {
   int dev = 0, cus = 0, per = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma2_kernel, kMfmaWaves * 64, 0);
+  if (order == 3)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_kernel<3>, kMfmaWaves * 64, 0);
+  else
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_kernel<2>, kMfmaWaves * 64, 0);
   if (cus <= 0) cus = 256;
   if (per <= 0) per = 1;
   return cus * per;
 }
 
-void launch_mfma2(const Globals &g, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(mfma2_kernel, dim3(grid), dim3(kMfmaWaves * 64), 0, s, g);
+void launch_mfma(const Globals &g, int order, int grid, hipStream_t s) {
+  if (order == 3) hipLaunchKernelGGL(mfma_kernel<3>, dim3(grid), dim3(kMfmaWaves * 64), 0, s, g);
+  else hipLaunchKernelGGL(mfma_kernel<2>, dim3(grid), dim3(kMfmaWaves * 64), 0, s, g);
 }
 
 }  // namespace fiuncho

@@ -105,6 +105,7 @@ def test_kernel_choice_table(monkeypatch):
     monkeypatch.delenv("FIUNCHO_ORDER2_MFMA", raising=False)
     monkeypatch.delenv("FIUNCHO_ORDER3_PAIRS", raising=False)
     monkeypatch.delenv("FIUNCHO_ORDER4_TRIPLES", raising=False)
+    monkeypatch.delenv("FIUNCHO_ORDER3_MFMA", raising=False)
     L = fiuncho.lib()
     assert fiuncho.get_kernel(100, 1600, 2) == fiuncho.KERNEL_POPCOUNT
     assert fiuncho.get_kernel(4000, 16000, 2) == fiuncho.KERNEL_MFMA
@@ -128,7 +129,7 @@ def test_kernel_choice_table(monkeypatch):
     finally:
         fiuncho.set_kernel(300, 500, 2, fiuncho.KERNEL_AUTO)
     assert fiuncho.get_kernel(300, 500, 2) == fiuncho.KERNEL_POPCOUNT
-    assert L.fiuncho_set_kernel(300, 500, 3, fiuncho.KERNEL_MFMA) == fiuncho.E_SHAPE
+    assert L.fiuncho_set_kernel(300, 500, 4, fiuncho.KERNEL_MFMA) == fiuncho.E_SHAPE
     assert L.fiuncho_set_kernel(300, 500, 2, fiuncho.KERNEL_PAIRS) == fiuncho.E_SHAPE
     assert L.fiuncho_set_kernel(300, 500, 2, 9) == fiuncho.E_SHAPE
     assert L.fiuncho_set_kernel(300, 500, 3, fiuncho.KERNEL_TRIPLES) == fiuncho.E_SHAPE

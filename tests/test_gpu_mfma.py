@@ -1,6 +1,7 @@
-"""GPU parity of the order-2 matrix-core path (FIUNCHO_ORDER2_MFMA=1): the
-one-hot int8 contraction must give the same tables, top-N set and FP64
-scores as the oracle, like the popcount path."""
+"""GPU parity of the matrix-core paths (order 2: FIUNCHO_ORDER2_MFMA=1,
+order 3: FIUNCHO_ORDER3_MFMA=1): the one-hot int8 contraction must give the
+same tables, top-N set and FP64 scores as the oracle, like the popcount
+path."""
 import math
 
 import numpy as np
@@ -72,3 +73,52 @@ def test_order2_mfma_shards(n, P, mfma):
         full = _run_shards(G, y, 2, fiuncho.MAX_TOPN, P)
         sizes = fiuncho.shard_counts(n, 200, 2, P, fiuncho.TILE_ROUND_ROBIN)
         assert [len(h) for h in full] == sizes.tolist()
+
+
+# ---------------------------------------------------------------------------
+# order 3: prefix pairs x last variants on the matrix cores
+# ---------------------------------------------------------------------------
+
+@pytest.fixture
+def mfma3(monkeypatch):
+    monkeypatch.setenv("FIUNCHO_ORDER3_MFMA", "1")
+
+
+# n around the 8-prefix fragments, 32-prefix groups and 64-variant blocks
+CASES3 = [(3, 50, 0.5), (9, 64, 0.4), (17, 31, 0.5), (34, 129, 0.3), (66, 200, 0.5), (100, 65, 0.6)]
+
+
+@pytest.mark.parametrize("n,m,frac", CASES3)
+def test_order3_mfma_small(n, m, frac, mfma3):
+    say(f"case: mfma order 3 n={n} m={m}")
+    G, y = random_dataset(131 + n, n, m, frac, 1 if n > 5 else 0, 1 if n > 5 else 0)
+    top = min(40, math.comb(n, 3))
+    hits = fiuncho.scan(G, y, 3, top)
+    check_hits_against_oracle(G, y, 3, top, hits)
+
+
+def test_order3_mfma_every_triple(mfma3):
+    n = 23  # C(23, 3) = 1771 <= 2048: every combination is returned
+    G, y = random_dataset(177, n, 150, 0.5)
+    hits = fiuncho.scan(G, y, 3, fiuncho.MAX_TOPN)
+    assert len(hits) == math.comb(n, 3)
+    np.testing.assert_array_equal(np.sort(hits["rank"]), np.arange(math.comb(n, 3), dtype=np.uint64))
+    check_hits_against_oracle(G, y, 3, len(hits), hits)
+
+
+def test_order3_mfma_workload(mfma3):
+    full_size_check(synth.order3_main(), 20000, 53)
+
+
+def test_order3_mfma_shards_and_batch(mfma3, monkeypatch):
+    monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", "1")
+    G, y = random_dataset(93, 120, 180, 0.5)
+    lists = _run_shards(G, y, 3, 40, 5)
+    check_hits_against_oracle(G, y, 3, 40, _merge(lists, 40))
+    # both matrix-core orders and the popcount kernel in one batch
+    jobs = synth.batch_jobs(6, scale=0.04) + [synth.generate(30, 300, seed=9, order=4, top_n=5)]
+    b = fiuncho.DeviceBatch(jobs)
+    b.run()
+    for d, (status, hits) in zip(jobs, b.results()):
+        assert status == 0
+        check_hits_against_oracle(d.genotypes, d.phenotype, d.order, d.top_n, hits)
