@@ -174,7 +174,7 @@ def main():
     tuned = {}
     if args.autotune:
         for d in datasets:
-            key = (d.n.bit_length(), ((d.m + 63) // 64).bit_length(), d.order)
+            key = (d.order, d.n.bit_length(), ((d.m + 63) // 64).bit_length())
             if key not in tuned:
                 tuned[key] = fiuncho.autotune(d.n, d.m, d.order)
     shard = None
@@ -305,7 +305,8 @@ def main():
         "phases_ms": {k: round(prof[k], 4) for k in ("pack_ms", "pilot_ms", "scan_ms", "mfma_ms",
                                                      "select_ms", "total_ms")},
         "kernels": sorted(names[k] for k in kernels),
-        "autotuned": bool(args.autotune),
+        "autotuned": {f"order {k[0]}, snps < 2^{k[1]}, words < 2^{k[2]}": names[v]
+                      for k, v in sorted(tuned.items())} if args.autotune else None,
         "candidates": prof["candidates"],
         "rescored": prof["kept"],
         "status_ok": ok,
