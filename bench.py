@@ -77,14 +77,15 @@ MFMA_I8_PEAK_OPS = 5.0e15
 
 
 def kernel_sources_sha256() -> str:
-    """Hash of every device source of the library (any change voids counters
-    taken on an earlier build)."""
+    """Hash of every source that defines or launches a kernel (all of csrc
+    but the host-side API file, and the public header): any change voids
+    counters taken on an earlier build."""
     import glob
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2201_03331_amd", "csrc", "*.hip")) +
-                   glob.glob(os.path.join(ROOT, "paper_2201_03331_amd", "csrc", "*.hpp")) +
-                   [os.path.join(ROOT, "include", "fiuncho.h")])
+    csrc = os.path.join(ROOT, "paper_2201_03331_amd", "csrc")
+    files = sorted(f for f in glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))
+                   if os.path.basename(f) != "api.hip") + [os.path.join(ROOT, "include", "fiuncho.h")]
     for f in files:
         h.update(os.path.basename(f).encode())
         h.update(open(f, "rb").read())
