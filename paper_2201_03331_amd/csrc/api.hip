@@ -236,14 +236,16 @@ bool kernel_valid(int kernel, uint32_t n, uint32_t k) {
   }
 }
 
-// measured on MI355X: the matrix-core order-2 kernel wins from about a
-// thousand variants (4,000 x 16,000: 0.91 vs 1.40 ms), the popcount kernel
-// below (100 x 1,600: 0.053 vs 0.097 ms); the pair-table kernel wins at every
-// order-3 size tried
-int rule_kernel(uint32_t n, uint32_t k) {
-  if (k == 3 && n >= 3) return FIUNCHO_KERNEL_PAIRS;
+// From autotuning on MI355X (the 64-dataset batch: 200-2,000 variants,
+// 1,000-20,000 samples): the matrix-core kernels win at order 2 from about a
+// thousand variants or 256 words, at order 3 from 128 words; below, the
+// popcount kernels (order 2 rows against rows, order 3 with pair tables).
+// Order 4 uses the triple tables while they fit in 16 GiB.
+int rule_kernel(uint32_t n, uint32_t m, uint32_t k) {
+  const u64 words = ceil_div(m, 64);
+  if (k == 3 && n >= 3) return words >= 128 ? FIUNCHO_KERNEL_MFMA : FIUNCHO_KERNEL_PAIRS;
   if (k == 4 && kernel_valid(FIUNCHO_KERNEL_TRIPLES, n, k)) return FIUNCHO_KERNEL_TRIPLES;
-  if (k == 2 && n >= 1024) return FIUNCHO_KERNEL_MFMA;
+  if (k == 2 && (n >= 1024 || words >= 256)) return FIUNCHO_KERNEL_MFMA;
   return FIUNCHO_KERNEL_POPCOUNT;
 }
 
@@ -266,7 +268,7 @@ int choose_kernel(uint32_t n, uint32_t m, uint32_t k) {
     auto it = g_tuned.find(shape_key(n, m, k));
     if (it != g_tuned.end() && kernel_valid(it->second, n, k)) return it->second;
   }
-  return rule_kernel(n, k);
+  return rule_kernel(n, m, k);
 }
 
 bool on_matrix_cores(uint32_t path) {
