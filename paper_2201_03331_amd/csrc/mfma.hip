@@ -44,6 +44,17 @@ __device__ __forceinline__ u64 spread8(uint32_t e) {
   return (u64)lo | ((u64)hi << 32);
 }
 
+// 16 sample bits -> 16 bytes by arithmetic: each nibble times 1 + 2^7 + 2^14
+// + 2^21, masked (no table; VALU only)
+__device__ __forceinline__ v4i expand16_alu(uint32_t b) {
+  v4i r;
+  r[0] = (int)(((b & 0xFu) * 0x00204081u) & 0x01010101u);
+  r[1] = (int)((((b >> 4) & 0xFu) * 0x00204081u) & 0x01010101u);
+  r[2] = (int)((((b >> 8) & 0xFu) * 0x00204081u) & 0x01010101u);
+  r[3] = (int)((((b >> 12) & 0xFu) * 0x00204081u) & 0x01010101u);
+  return r;
+}
+
 // 16 sample bits -> the 16 int8 operand bytes of one lane
 __device__ __forceinline__ v4i expand16(const u64 *lut, uint32_t b) {
   const u64 lo = lut[__builtin_amdgcn_ubfe(b, 0, 8) * kLutCopies];
@@ -61,14 +72,14 @@ __device__ __forceinline__ v4i expand16(const u64 *lut, uint32_t b) {
 // the 16 samples [16 (l / 32), 16 (l / 32) + 16) of each 32-sample step; the
 // matrix instruction pairs the same lane half and byte of both operands, so
 // any fixed sample order inside a lane is exact.
-template <typename Load>
+template <int kDepth, typename Load>
 __device__ __forceinline__ void mfma_class(Load &&load_words, uint32_t wbeg, uint32_t wend,
                                            uint32_t h, const u64 *lut, v16i (&acc)[2][2]) {
   if (wbeg >= wend) return;
-  // the rows of the next kDepth words are in flight in a register ring;
+  // the rows of the next kDepth words are in flight in a register ring (the
+  // depth is what the kernel's register budget allows);
   // load_words(w, x) fills x with the lane's words of both A fragments and
   // both B fragments
-  constexpr int kDepth = 3;
   const uint32_t wlast = wend - 1;
   u64 X[kDepth][4];
 #pragma unroll
@@ -77,11 +88,15 @@ __device__ __forceinline__ void mfma_class(Load &&load_words, uint32_t wbeg, uin
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       // 16 samples of this lane half: bits [16 h, 16 h + 16) of the 32-bit half s
+      // the A fragments through the LDS table, the B fragments by arithmetic:
+      // the two expansions load different units (LDS, VALU), so neither
+      // alone has to keep up with the matrix instructions
       v4i E[4];
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         const uint32_t half = s ? (uint32_t)(X[slot][f] >> 32) : (uint32_t)X[slot][f];
-        E[f] = expand16(lut, __builtin_amdgcn_ubfe(half, 16 * h, 16));
+        const uint32_t bits = __builtin_amdgcn_ubfe(half, 16 * h, 16);
+        E[f] = f < 2 ? expand16(lut, bits) : expand16_alu(bits);
       }
       acc[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(E[0], E[2], acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(E[0], E[3], acc[0][1], 0, 0, 0);
@@ -126,8 +141,8 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc0[x][y][e] = acc1[x][y][e] = 0;
-  mfma_class(load_words, 0, v.W0, h, lut, acc0);
-  mfma_class(load_words, v.W0, v.W0 + v.W1, h, lut, acc1);
+  mfma_class<3>(load_words, 0, v.W0, h, lut, acc0);
+  mfma_class<3>(load_words, v.W0, v.W0 + v.W1, h, lut, acc1);
 
   // Output block layout: lane l holds column l mod 32 (variant j0' + (l mod
   // 32) / 2, genotype l mod 2); register e holds row 8 (e / 4) + 4 h + e mod 4
@@ -235,8 +250,8 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc0[x][y][e] = acc1[x][y][e] = 0;
-  mfma_class(load_words, 0, v.W0, h, lut, acc0);
-  mfma_class(load_words, v.W0, v.W0 + v.W1, h, lut, acc1);
+  mfma_class<3>(load_words, 0, v.W0, h, lut, acc0);
+  mfma_class<3>(load_words, v.W0, v.W0 + v.W1, h, lut, acc1);
 
   // Output block (f, fb): lane l holds column l mod 32 (last variant j0 + 16 fb
   // + (l mod 32) / 2, genotype l mod 2); register e holds row 8 (e / 4) + 4 h +
