@@ -30,11 +30,13 @@ constexpr uint32_t kPathGeneric = 0;          // rows g = 0, 1 of the last varia
 constexpr uint32_t kPathPairs = 1;            // order 3, {0,1}^3 cells + pair tables
 constexpr int kSelPairs = 31;                 // scan_kernel selector: order-3 pair path only
 constexpr int kSel23 = 23;                    // scan_kernel selector: orders 2 and 3 (pair path)
-constexpr int kTileCounters = 6;              // scan, its pilot, order-2 mfma, its pilot, order-3 mfma, its pilot
-constexpr uint32_t kPathMfma2 = 2;
+constexpr uint32_t kPathMfma2 = 2;            // order 2 on the matrix cores (mfma_kernel<2>)
 constexpr uint32_t kPathTriples = 3;          // order 4, {0,1}^4 cells + triple and pair tables
-constexpr uint32_t kPathMfma3 = 4;            // order 3 on the matrix cores (prefix pairs x variants)
-constexpr int kSelTriples = 41;               // scan_kernel selector: order-4 triple-table path only            // order 2 on the matrix cores (mfma2_kernel)
+constexpr uint32_t kPathMfma3 = 4;            // order 3 on the matrix cores (mfma_kernel<3>)
+constexpr int kSelTriples = 41;               // scan_kernel selector: order-4 triple-table path only
+// tile counters: popcount kernel, its pilot, order-2 matrix cores, its pilot,
+// order-3 matrix cores, its pilot
+constexpr int kTileCounters = 6;
 
 // state the device writes during one run of a job (cleared at the start)
 struct JobState {

@@ -15,7 +15,8 @@
 // (2 x 2 blocks) and accumulates both classes (class 0 words, then class 1
 // words).  Operands are not stored as bytes: each lane reads the 64-bit word
 // of its row from the packed bitsets and expands the 16 samples it feeds to
-// 16 bytes in registers, so the cache traffic is that of the bitsets.
+// 16 bytes in registers (A operands through an LDS table, B operands by
+// arithmetic), so the cache traffic is that of the bitsets.
 //
 // Order 3 uses the same contraction with prefix pairs as rows: row 4p + 2 g_a
 // + g_b of a fragment is the AND of the genotype rows g_a of a_p and g_b of b

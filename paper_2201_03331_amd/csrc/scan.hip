@@ -16,7 +16,10 @@
 //     prefix row is that row's own population count minus the other two
 //     (every sample has exactly one genotype);
 //   * at order 2 the first variant's g = 2 row is likewise derived from the
-//     per-variant class counts, so 4 of the 9 cells are counted directly.
+//     per-variant class counts, so 4 of the 9 cells are counted directly;
+//   * at order 3 (pair tables) and order 4 (triple tables) only the {0,1}^k
+//     cells are counted; the others follow by inclusion-exclusion from
+//     stored lower-order tables and class counts.
 // Tiles (workgroups of kScanWaves waves sharing the same 64 last variants)
 // are pulled from a device-wide counter by a persistent grid.
 #include "filter.hpp"
@@ -189,7 +192,7 @@ __device__ __forceinline__ void tile_order2(const Globals &g, const JV &v, uint3
 // 9 at a time (one "pass" per genotype assignment of the first k-3 prefix
 // variants); the 9 rows of a pass are lead & row_a[ga] & row_b[gb] for the
 // last two prefix variants a, b.  Scores are separable over cells, so each
-// pass adds its 27 cells to the compensated sum and drops its counters.
+// pass adds its 27 cells to the running estimate and drops its counters.
 // ---------------------------------------------------------------------------
 // Bs holds, per variant and word, the rows g = 0, 1, 2 and a zero pad word
 // (32 bytes), so one scalar load brings a variant's three rows of a word.
