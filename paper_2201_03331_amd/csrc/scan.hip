@@ -843,8 +843,11 @@ __device__ __forceinline__ void run_orderk(const Globals &g, const JV &v, uint32
   else tile_orderk<K>(g, v, pre, b + 1 + jb * 64, lane);
 }
 
-// waves per SIMD each variant is compiled for (register budget 512 / waves)
-constexpr int scan_min_waves(int ksel) { return (ksel != 0 && ksel != kSelTriples) ? 4 : 2; }
+// waves per SIMD each variant is compiled for (register budget 512 / waves);
+// measured: the order-4 triple-table kernel is fastest at 3 (165 registers,
+// no spills; 2 waves: 24.1 ms, 3: 19.6 ms, 4 with spills: 24.3 ms at 200 x
+// 4,000)
+constexpr int scan_min_waves(int ksel) { return ksel == kSelTriples ? 3 : ksel != 0 ? 4 : 2; }
 
 template <int KSEL>
 __global__ __launch_bounds__(kScanWaves * 64, scan_min_waves(KSEL)) void scan_kernel(Globals g) {
