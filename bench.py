@@ -7,7 +7,7 @@ selection, FP64 rescoring, final ordering) through fiuncho_scan_batch on a
 stream.  Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
-                  [--shard I/P] [--kernel auto|popcount|pairs|mfma] [--autotune]
+                  [--shard I/P] [--kernel auto|popcount|pairs|mfma|mfma-fp4|triples] [--autotune]
 
 --shard I/P times one GPU's share of a search split across P GPUs (shard I
 of the job's work tiles); the rate is that share's combinations per second.
@@ -74,6 +74,8 @@ def word_ops_per_combination(k: int, m0: int, m1: int, kernel: int) -> int:
 
 # gfx950 dense int8 matrix-core peak (ops/s; one multiply-add = 2 ops)
 MFMA_I8_PEAK_OPS = 5.0e15
+# dense FP4 (E2M1) matrix peak of MI355X, operations per second
+MFMA_FP4_PEAK_OPS = 10.1e15
 
 
 def kernel_sources_sha256() -> str:
@@ -136,7 +138,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="order3-1000x6400", choices=sorted(workloads().keys()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel", default="auto", choices=("auto", "popcount", "pairs", "mfma", "triples"),
+    ap.add_argument("--kernel", default="auto", choices=("auto", "popcount", "pairs", "mfma", "mfma-fp4", "triples"),
                     help="force this counting kernel for every dataset shape it handles")
     ap.add_argument("--autotune", action="store_true",
                     help="time the kernels for every dataset shape first (fiuncho_autotune)")
@@ -168,7 +170,8 @@ def main():
     plain = args.workload.endswith("-plain")
     if args.kernel != "auto":
         forced = {"popcount": fiuncho.KERNEL_POPCOUNT, "pairs": fiuncho.KERNEL_PAIRS,
-                  "mfma": fiuncho.KERNEL_MFMA, "triples": fiuncho.KERNEL_TRIPLES}[args.kernel]
+                  "mfma": fiuncho.KERNEL_MFMA, "mfma-fp4": fiuncho.KERNEL_MFMA_FP4,
+                  "triples": fiuncho.KERNEL_TRIPLES}[args.kernel]
         for d in datasets:
             if fiuncho.lib().fiuncho_set_kernel(d.n, d.m, d.order, forced) != fiuncho.OK:
                 ap.error(f"kernel {args.kernel} does not handle order {d.order}")
@@ -235,20 +238,25 @@ def main():
 
     # roofline of the dominant counting kernel: algorithmic work per launch
     # over that kernel's measured time.  Popcount kernels: 32-bit VALU
-    # lane-ops (4 per 64-bit AND+popcount).  Matrix-core kernels: int8 ops of
-    # the one-hot contraction, 2 x (4 or 8) cells x m samples per combination.
+    # lane-ops (4 per 64-bit AND+popcount).  Matrix-core kernels: operations
+    # of the one-hot contraction, 2 x (4 or 8) cells x m samples per
+    # combination, against the int8 or the FP4 peak (a batch with both: the
+    # time both parts would take at their peaks).
     lane_ops = 0
     mfma_ops = 0
+    mfma_peak_s = 0.0
     kernels = set()
     for d in datasets:
         m1 = int(d.phenotype.sum())
         kern = fiuncho.get_kernel(d.n, d.m, d.order)
         kernels.add(kern)
-        if kern == fiuncho.KERNEL_MFMA:
+        if kern in (fiuncho.KERNEL_MFMA, fiuncho.KERNEL_MFMA_FP4):
             # the {0,1}^k cells of every combination over every sample: 4 at
             # order 2, 8 at order 3 (the others come from class counts and
             # pair tables)
-            mfma_ops += 2 * (4 if d.order == 2 else 8) * d.m * share(d)
+            ops = 2 * (4 if d.order == 2 else 8) * d.m * share(d)
+            mfma_ops += ops
+            mfma_peak_s += ops / (MFMA_FP4_PEAK_OPS if kern == fiuncho.KERNEL_MFMA_FP4 else MFMA_I8_PEAK_OPS)
         else:
             lane_ops += 4 * word_ops_per_combination(d.order, d.m - m1, m1, kern) * share(d)
     calls = len(batches) if plain else 1
@@ -256,9 +264,12 @@ def main():
     mfma_ms = prof["mfma_ms"] * calls
     if mfma_ms > scan_ms:
         achieved = mfma_ops / (mfma_ms / 1e3) / 1e12
-        peak = MFMA_I8_PEAK_OPS / 1e12
-        roofline = {"bound": "mfma", "kernel": "mfma_kernel (one-hot int8 contraction + FP32 MI + filter)",
-                    "achieved": achieved, "peak": peak, "unit": "T int8 op/s", "frac": achieved / peak,
+        peak = mfma_ops / mfma_peak_s / 1e12
+        fp4 = fiuncho.KERNEL_MFMA_FP4 in kernels
+        i8 = fiuncho.KERNEL_MFMA in kernels
+        fmt = "int8 and FP4" if fp4 and i8 else "FP4" if fp4 else "int8"
+        roofline = {"bound": "mfma", "kernel": f"mfma_kernel (one-hot {fmt} contraction + FP32 MI + filter)",
+                    "achieved": achieved, "peak": peak, "unit": f"T {fmt} op/s", "frac": achieved / peak,
                     "traffic": measured_traffic("mfma_kernel", args.workload)}
     else:
         achieved = lane_ops / (scan_ms / 1e3) / 1e12
@@ -267,7 +278,7 @@ def main():
                     "achieved": achieved, "peak": peak, "unit": "T int32 lane-op/s", "frac": achieved / peak,
                     "traffic": measured_traffic("scan_kernel", args.workload)}
     names = {fiuncho.KERNEL_POPCOUNT: "popcount", fiuncho.KERNEL_PAIRS: "pairs", fiuncho.KERNEL_MFMA: "mfma",
-             fiuncho.KERNEL_TRIPLES: "triples"}
+             fiuncho.KERNEL_TRIPLES: "triples", fiuncho.KERNEL_MFMA_FP4: "mfma-fp4"}
 
     d0 = datasets[0]
     planted_first = None

@@ -219,6 +219,10 @@ int fiuncho_shard_counts(uint32_t snps, uint32_t samples, int order, uint32_t un
                                      rest from stored triple and pair tables
                                      (64 bytes of device memory per pair and
                                      variant; up to 16 GiB of tables) */
+#define FIUNCHO_KERNEL_MFMA_FP4 5 /* orders 2 and 3: the FIUNCHO_KERNEL_MFMA
+                                     contraction with FP4 (E2M1) 0/1 operands
+                                     and FP32 accumulation (exact: counts stay
+                                     below 2^24), 64 samples per instruction */
 
 /* The kernel a job of this shape would use now (a FIUNCHO_KERNEL_* value),
  * or FIUNCHO_E_ORDER. */

@@ -230,7 +230,8 @@ bool kernel_valid(int kernel, uint32_t n, uint32_t k) {
   switch (kernel) {
     case FIUNCHO_KERNEL_POPCOUNT: return true;
     case FIUNCHO_KERNEL_PAIRS: return k == 3 && n >= 3;
-    case FIUNCHO_KERNEL_MFMA: return k == 2 || (k == 3 && n >= 3);
+    case FIUNCHO_KERNEL_MFMA:
+    case FIUNCHO_KERNEL_MFMA_FP4: return k == 2 || (k == 3 && n >= 3);
     case FIUNCHO_KERNEL_TRIPLES: return k == 4 && n >= 4 && triple_table_bytes(n) <= kMaxTripleTableBytes;
     default: return false;
   }
@@ -257,11 +258,14 @@ int choose_kernel(uint32_t n, uint32_t m, uint32_t k) {
   if (k == 4 && e4 && e4[0] == '0') return FIUNCHO_KERNEL_POPCOUNT;
   if (k == 4 && e4 && e4[0] == '1' && kernel_valid(FIUNCHO_KERNEL_TRIPLES, n, k))
     return FIUNCHO_KERNEL_TRIPLES;
+  // matrix-core overrides: 1 = int8 operands, 4 = FP4 operands
   const char *e3m = std::getenv("FIUNCHO_ORDER3_MFMA");
   if (k == 3 && e3m && e3m[0] == '1' && n >= 3) return FIUNCHO_KERNEL_MFMA;
+  if (k == 3 && e3m && e3m[0] == '4' && n >= 3) return FIUNCHO_KERNEL_MFMA_FP4;
   const char *e2 = std::getenv("FIUNCHO_ORDER2_MFMA");
   if (k == 2 && e2 && e2[0] == '0') return FIUNCHO_KERNEL_POPCOUNT;
   if (k == 2 && e2 && e2[0] == '1') return FIUNCHO_KERNEL_MFMA;
+  if (k == 2 && e2 && e2[0] == '4') return FIUNCHO_KERNEL_MFMA_FP4;
   if (t_force_kernel != FIUNCHO_KERNEL_AUTO && kernel_valid(t_force_kernel, n, k)) return t_force_kernel;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -275,20 +279,23 @@ bool on_matrix_cores(uint32_t path) {
   return path == fiuncho::kPathMfma2 || path == fiuncho::kPathMfma3;
 }
 
-uint32_t job_path(uint32_t n, uint32_t m, uint32_t k) {
-  switch (choose_kernel(n, m, k)) {
+uint32_t kernel_path(int kernel, uint32_t k) {
+  switch (kernel) {
     case FIUNCHO_KERNEL_PAIRS: return fiuncho::kPathPairs;
-    case FIUNCHO_KERNEL_MFMA: return k == 2 ? fiuncho::kPathMfma2 : fiuncho::kPathMfma3;
+    case FIUNCHO_KERNEL_MFMA:
+    case FIUNCHO_KERNEL_MFMA_FP4: return k == 2 ? fiuncho::kPathMfma2 : fiuncho::kPathMfma3;
     case FIUNCHO_KERNEL_TRIPLES: return fiuncho::kPathTriples;
     default: return fiuncho::kPathGeneric;
   }
 }
 
+uint32_t job_path(uint32_t n, uint32_t m, uint32_t k) { return kernel_path(choose_kernel(n, m, k), k); }
+
 // ---------------------------------------------------------------------------
 // workspace layout
 // ---------------------------------------------------------------------------
 struct JobLayout {
-  uint32_t n, m, k, top_n, n_pad, wcap, nrows, path, shard_index, shard_count;
+  uint32_t n, m, k, top_n, n_pad, wcap, nrows, path, fp4, shard_index, shard_count;
   u64 total;
   uint32_t cand_cap, l1_cap, l2_cap;
   size_t off_G, off_y, off_idx, off_Bv, off_Bs, off_marg, off_hist, off_phist, off_cand, off_l1, off_l2,
@@ -301,15 +308,22 @@ struct JobLayout {
   double cost;  // per-tile cost estimate, for ordering
 };
 
+// matrix-core launch group of a job (order 2 int8, order 2 FP4, order 3
+// int8, order 3 FP4), -1 for the popcount kernel
+int mfma_group(const JobLayout &J) {
+  if (!on_matrix_cores(J.path)) return -1;
+  return 2 * (J.path == fiuncho::kPathMfma3 ? 1 : 0) + (J.fp4 ? 1 : 0);
+}
+
 struct Layout {
   std::vector<JobLayout> jobs;
   std::vector<uint32_t> order;  // tile-space order of the jobs (costliest first)
   uint32_t nmax, kmax, max_n_pad, max_wcap, max_cand_cap, max_l2_cap, max_pairs_n, max_triples_n;
   size_t plan_begin, plan_end;  // uploaded region
   size_t off_desc, off_jts, off_jps, off_binom, off_counter;
-  // tile-space order: [0, n_scan) popcount kernel, then n_mfma2 order-2 and
-  // the rest order-3 matrix-core jobs
-  uint32_t n_scan, n_mfma2;
+  // tile-space order: [0, n_scan) popcount kernel, then the jobs of each
+  // matrix-core group (mfma_group order), n_group[q] of group q
+  uint32_t n_scan, n_group[fiuncho::kMfmaGroups];
   size_t total;
   int ksel;
 };
@@ -345,7 +359,9 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     J.cand_cap = (uint32_t)std::max<u64>(cap, 1);
     J.l1_cap = J.cand_cap;
     J.l2_cap = fiuncho::kSortMax;
-    J.path = job_path(J.n, J.m, J.k);
+    const int kern = choose_kernel(J.n, J.m, J.k);
+    J.path = kernel_path(kern, J.k);
+    J.fp4 = kern == FIUNCHO_KERNEL_MFMA_FP4;
     build_rows(J.n, J.k, J.path, J.row_start);
     J.nrows = (uint32_t)(J.row_start.size() - 1);
     J.shard_count = jobs[i].shard_count > 1 ? jobs[i].shard_count : 1;
@@ -438,16 +454,16 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
   for (uint32_t i = 0; i < n_jobs; ++i) L.order[i] = i;
   std::stable_sort(L.order.begin(), L.order.end(),
                    [&](uint32_t a, uint32_t b) { return L.jobs[a].cost > L.jobs[b].cost; });
-  // jobs on the matrix cores go last, order 2 before order 3: each group runs
-  // in its own launch
-  std::stable_partition(L.order.begin(), L.order.end(),
-                        [&](uint32_t a) { return !on_matrix_cores(L.jobs[a].path); });
-  std::stable_partition(L.order.begin(), L.order.end(),
-                        [&](uint32_t a) { return L.jobs[a].path != fiuncho::kPathMfma3; });
-  L.n_scan = L.n_mfma2 = 0;
+  // jobs on the matrix cores go last, by group: each group runs in its own
+  // launch
+  std::stable_sort(L.order.begin(), L.order.end(),
+                   [&](uint32_t a, uint32_t b) { return mfma_group(L.jobs[a]) < mfma_group(L.jobs[b]); });
+  L.n_scan = 0;
+  for (auto &c : L.n_group) c = 0;
   for (auto &J : L.jobs) {
-    L.n_scan += !on_matrix_cores(J.path);
-    L.n_mfma2 += J.path == fiuncho::kPathMfma2;
+    const int q = mfma_group(J);
+    if (q < 0) ++L.n_scan;
+    else ++L.n_group[q];
   }
   auto sel = [](const JobLayout &J) {
     return J.path == fiuncho::kPathPairs     ? fiuncho::kSelPairs
@@ -563,6 +579,7 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
     d.l2 = reinterpret_cast<Rescored *>(ws + J.off_l2);
     d.l2_cap = J.l2_cap;
     d.path = J.path;
+    d.fp4 = J.fp4;
     d.shard_index = J.shard_index;
     d.shard_count = J.shard_count;
     d.pairs = J.off_pairs ? reinterpret_cast<uint32_t *>(ws + J.off_pairs) : nullptr;
@@ -728,7 +745,7 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   for (auto &J : L.jobs)
     kernels |= 1u << (J.path == fiuncho::kPathPairs     ? FIUNCHO_KERNEL_PAIRS
                       : J.path == fiuncho::kPathTriples ? FIUNCHO_KERNEL_TRIPLES
-                      : on_matrix_cores(J.path)         ? FIUNCHO_KERNEL_MFMA
+                      : on_matrix_cores(J.path)         ? (J.fp4 ? FIUNCHO_KERNEL_MFMA_FP4 : FIUNCHO_KERNEL_MFMA)
                                                       : FIUNCHO_KERNEL_POPCOUNT);
   if ((st = prof_begin(combos, kernels, reinterpret_cast<JobState *>(ws + L.jobs[0].off_state))))
     return st;
@@ -745,29 +762,38 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
     ts[p + 1] = ts[p] + L.jobs[L.order[p]].tiles;
     ps[p + 1] = ps[p] + L.jobs[L.order[p]].pilot_tiles;
   }
-  const uint32_t ns = L.n_scan, nm2 = L.n_mfma2, nm3 = nj - L.n_scan - L.n_mfma2;
-  // order 0: the popcount kernel; 2, 3: the matrix-core kernel of that order
-  auto counting = [&](const Globals &c, int order) {
+  const uint32_t ns = L.n_scan;
+  // group -1: the popcount kernel; q >= 0: the matrix-core kernel of group q
+  auto counting = [&](const Globals &c, int q) {
     if (c.total_tiles <= c.tile_base) return;
     const u64 tiles = c.total_tiles - c.tile_base;
-    const int gmax = order ? fiuncho::mfma_grid_size(order) : fiuncho::scan_grid_size(L.ksel);
+    const int order = 2 + q / 2;
+    const bool fp4 = q % 2 == 1;
+    const int gmax = q >= 0 ? fiuncho::mfma_grid_size(order, fp4) : fiuncho::scan_grid_size(L.ksel);
     const int grid = (int)std::min<u64>((u64)gmax, tiles);
-    if (order) fiuncho::launch_mfma(c, order, grid, s);
+    if (q >= 0) fiuncho::launch_mfma(c, order, fp4, grid, s);
     else fiuncho::launch_scan(c, L.ksel, grid, s);
   };
+  // the matrix-core groups' launches over their jobs; counters 2 + 2q (counting)
+  // and 3 + 2q (pilot)
+  auto mfma_groups = [&](const std::vector<u64> &starts, bool pilot) {
+    uint32_t first = ns;
+    for (int q = 0; q < fiuncho::kMfmaGroups; ++q) {
+      if (L.n_group[q]) counting(launch_globals(g, starts, first, L.n_group[q], pilot, 2 + 2 * q + pilot), q);
+      first += L.n_group[q];
+    }
+  };
   if (g.total_pilot_tiles) {
-    if (ns) counting(launch_globals(g, ps, 0, ns, true, 1), 0);
-    if (nm2) counting(launch_globals(g, ps, ns, nm2, true, 3), 2);
-    if (nm3) counting(launch_globals(g, ps, ns + nm2, nm3, true, 5), 3);
+    if (ns) counting(launch_globals(g, ps, 0, ns, true, 1), -1);
+    mfma_groups(ps, true);
     uint32_t max_slots = 0;
     for (auto &J : L.jobs) max_slots = std::max(max_slots, J.pilot_slots);
     fiuncho::launch_pilot_select(g, max_slots, s);
   }
   if ((st = prof_record(2, s))) return st;
-  if (ns) counting(launch_globals(g, ts, 0, ns, false, 0), 0);
+  if (ns) counting(launch_globals(g, ts, 0, ns, false, 0), -1);
   if ((st = prof_record(3, s))) return st;
-  if (nm2) counting(launch_globals(g, ts, ns, nm2, false, 2), 2);
-  if (nm3) counting(launch_globals(g, ts, ns + nm2, nm3, false, 4), 3);
+  mfma_groups(ts, false);
   if ((st = prof_record(4, s))) return st;
   fiuncho::launch_select(g, L.max_cand_cap, s);
   fiuncho::launch_rescore(g, L.max_l2_cap, L.kmax, s);
@@ -1179,7 +1205,8 @@ int fiuncho_autotune(uint32_t snps, uint32_t samples, int order, uint32_t reps, 
     if (st) return st;
     const uint32_t k = (uint32_t)order;
     std::vector<int> cands;
-    for (int c : {FIUNCHO_KERNEL_POPCOUNT, FIUNCHO_KERNEL_PAIRS, FIUNCHO_KERNEL_MFMA, FIUNCHO_KERNEL_TRIPLES})
+    for (int c : {FIUNCHO_KERNEL_POPCOUNT, FIUNCHO_KERNEL_PAIRS, FIUNCHO_KERNEL_MFMA, FIUNCHO_KERNEL_TRIPLES,
+                  FIUNCHO_KERNEL_MFMA_FP4})
       if (kernel_valid(c, snps, k)) cands.push_back(c);
     int best = cands[0];
     if (cands.size() > 1) {

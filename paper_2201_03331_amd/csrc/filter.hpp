@@ -22,6 +22,7 @@ struct JV {
   const uint32_t *pairs;
   const uint32_t *triples;
   uint32_t path;
+  uint32_t fp4;               // matrix-core paths: FP4 operands (else int8)
   const float *Fh;
   float fbound;
   mutable uint32_t *pk;       // pilot launch: this wave's next 64 score slots
@@ -52,6 +53,7 @@ __device__ __forceinline__ JV load_view(const JobDesc *jd) {
   v.pairs = uni_ptr(J->pairs);
   v.triples = uni_ptr(J->triples);
   v.path = uni(J->path);
+  v.fp4 = uni(J->fp4);
   v.Fh = uni_ptr(J->Fh);
   v.fbound = __uint_as_float(uni(__float_as_uint(J->fbound)));
   v.pk = nullptr;

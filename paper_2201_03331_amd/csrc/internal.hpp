@@ -34,9 +34,12 @@ constexpr uint32_t kPathMfma2 = 2;            // order 2 on the matrix cores (mf
 constexpr uint32_t kPathTriples = 3;          // order 4, {0,1}^4 cells + triple and pair tables
 constexpr uint32_t kPathMfma3 = 4;            // order 3 on the matrix cores (mfma_kernel<3>)
 constexpr int kSelTriples = 41;               // scan_kernel selector: order-4 triple-table path only
-// tile counters: popcount kernel, its pilot, order-2 matrix cores, its pilot,
-// order-3 matrix cores, its pilot
-constexpr int kTileCounters = 6;
+// matrix-core launch groups, in tile-space order: order 2 with int8 and with
+// FP4 operands, then order 3 with int8 and with FP4 operands
+constexpr int kMfmaGroups = 4;
+// tile counters: the popcount kernel and its pilot, then each matrix-core
+// group's counting launch and its pilot
+constexpr int kTileCounters = 2 + 2 * kMfmaGroups;
 
 // state the device writes during one run of a job (cleared at the start)
 struct JobState {
@@ -110,6 +113,7 @@ struct JobDesc {
   uint32_t shard_count;       // 1 = every tile
   uint32_t pilot_tiles;       // tiles sampled by the pilot pass (0: none)
   uint32_t pilot_slots;       // score slots of the pilot pass (at the start of cand)
+  uint32_t fp4;               // kPathMfma2, kPathMfma3: 1 = FP4 operands, 0 = int8
   // outputs
   fiuncho_hit *out;
   uint32_t *n_out;
@@ -139,8 +143,8 @@ void launch_pack(const Globals &g, uint32_t max_n_pad, uint32_t max_wcap, hipStr
 void launch_pairs(const Globals &g, uint32_t max_n, hipStream_t s);
 void launch_triples(const Globals &g, uint32_t max_n, hipStream_t s);
 void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s);
-void launch_mfma(const Globals &g, int order, int grid, hipStream_t s);
-int mfma_grid_size(int order);
+void launch_mfma(const Globals &g, int order, bool fp4, int grid, hipStream_t s);
+int mfma_grid_size(int order, bool fp4);
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
 void launch_pilot_select(const Globals &g, uint32_t max_pilot_slots, hipStream_t s);
 void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s);

@@ -18,6 +18,13 @@
 // 16 bytes in registers (A operands through an LDS table, B operands by
 // arithmetic), so the cache traffic is that of the bitsets.
 //
+// The same contraction also runs with FP4 (E2M1) operands on the scaled
+// matrix instruction v_mfma_scale_f32_32x32x64_f8f6f4 (scales 1): 0 and 1 are
+// exact E2M1 values, every product is 0 or 1 and the FP32 accumulators hold
+// integers below 2^24 exactly, so the counts are the same; one instruction
+// takes 64 samples per row instead of 32, and a lane's 32 operand values come
+// from its 32-bit half word by two bit operations per register.
+//
 // Order 3 uses the same contraction with prefix pairs as rows: row 4p + 2 g_a
 // + g_b of a fragment is the AND of the genotype rows g_a of a_p and g_b of b
 // (8 prefix pairs (a_p, b) per fragment, b fixed for the tile), so a block
@@ -28,7 +35,14 @@
 namespace fiuncho {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// operand format code of E2M1 in the scaled instruction's format fields, and
+// the E8M0 scale exponent of 1.0
+constexpr int kFmtFp4 = 4;
+constexpr int kScaleOne = 127;
 
 constexpr int kMfmaWaves = 4;
 static_assert(kMfmaWaves == kScanWaves, "pilot slots and tile decoding assume equal waves per tile");
@@ -119,7 +133,93 @@ __device__ __forceinline__ void mfma_class(Load &&load_words, uint32_t wbeg, uin
     if (w + u < wend) step(u);
 }
 
+// 32 sample bits -> the 32 FP4 operand values of one lane.  E2M1 1.0 is the
+// nibble 0b0010, so register d takes bit 4p + d of b to bit 1 of nibble p;
+// only the low four registers are read for FP4 operands.
+__device__ __forceinline__ v8i expand32_fp4(uint32_t b) {
+  v8i r;
+  r[0] = (int)((b << 1) & 0x22222222u);
+  r[1] = (int)(b & 0x22222222u);
+  r[2] = (int)((b >> 1) & 0x22222222u);
+  r[3] = (int)((b >> 2) & 0x22222222u);
+  r[4] = r[5] = r[6] = r[7] = 0;
+  return r;
+}
+
+// Counts of one class with FP4 operands: words [wbeg, wend).  Lane l feeds
+// row l mod 32 of every fragment and the 32 samples of 32-bit half l / 32 of
+// each word (load_words(w, x) fills x with the lane's half words of both A
+// and both B fragments); the instruction pairs the same lane half and nibble
+// of both operands.
+template <int kDepth, typename Load>
+__device__ __forceinline__ void mfma_class_fp4(Load &&load_words, uint32_t wbeg, uint32_t wend,
+                                               v16f (&acc)[2][2]) {
+  if (wbeg >= wend) return;
+  const uint32_t wlast = wend - 1;
+  uint32_t X[kDepth][4];
+#pragma unroll
+  for (int u = 0; u < kDepth; ++u) load_words(min(wbeg + u, wlast), X[u]);
+  auto step = [&](int slot) {
+    v8i E[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) E[f] = expand32_fp4(X[slot][f]);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+        acc[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+            E[x], E[2 + y], acc[x][y], kFmtFp4, kFmtFp4, 0, kScaleOne, 0, kScaleOne);
+  };
+  uint32_t w = wbeg;
+  for (; w + kDepth <= wend; w += kDepth) {
+#pragma unroll
+    for (int u = 0; u < kDepth; ++u) {
+      step(u);
+      load_words(min(w + u + kDepth, wlast), X[u]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kDepth - 1; ++u)
+    if (w + u < wend) step(u);
+}
+
+__device__ __forceinline__ void zero_acc(v16i (&acc0)[2][2], v16i (&acc1)[2][2]) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc0[x][y][e] = acc1[x][y][e] = 0;
+}
+
+// Both classes with FP4 operands (class 0: words [0, W0), class 1: the next
+// W1), counts returned as integers: the FP32 sums are integers below 2^24
+template <int kDepth, typename Load>
+__device__ __forceinline__ void contract_fp4(Load &&load_words, uint32_t W0, uint32_t W1,
+                                             v16i (&acc0)[2][2], v16i (&acc1)[2][2]) {
+  v16f f0[2][2], f1[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) f0[x][y][e] = f1[x][y][e] = 0.f;
+  mfma_class_fp4<kDepth>(load_words, 0, W0, f0);
+  mfma_class_fp4<kDepth>(load_words, W0, W0 + W1, f1);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        acc0[x][y][e] = (int)(uint32_t)f0[x][y][e];
+        acc1[x][y][e] = (int)(uint32_t)f1[x][y][e];
+      }
+}
+
 // One wave: pairs (a0 + [0, 32)) x (j0 + [0, 32)).
+template <bool F4>
 __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0, uint32_t lane,
                                            const u64 *lut) {
   const uint32_t n = v.n;
@@ -128,22 +228,31 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
   const FI_GLOBAL u64 *Bv = as_global(v.Bv);
   const FI_GLOBAL u64 *pa = Bv + (size_t)a0 * 2 + r;
   const FI_GLOBAL u64 *pj = Bv + (size_t)j0 * 2 + r;
-  auto load_words = [&](uint32_t w, u64 (&x)[4]) {
-    const size_t o = (size_t)w * word_stride;
-    x[0] = pa[o];
-    x[1] = pa[o + 32];
-    x[2] = pj[o];
-    x[3] = pj[o + 32];
-  };
   v16i acc0[2][2], acc1[2][2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc0[x][y][e] = acc1[x][y][e] = 0;
-  mfma_class<3>(load_words, 0, v.W0, h, lut, acc0);
-  mfma_class<3>(load_words, v.W0, v.W0 + v.W1, h, lut, acc1);
+  if constexpr (F4) {
+    // the lane's 32-bit half of each word
+    const FI_GLOBAL uint32_t *qa = reinterpret_cast<const FI_GLOBAL uint32_t *>(pa) + h;
+    const FI_GLOBAL uint32_t *qj = reinterpret_cast<const FI_GLOBAL uint32_t *>(pj) + h;
+    auto load_words = [&](uint32_t w, uint32_t (&x)[4]) {
+      const size_t o = (size_t)w * word_stride * 2;
+      x[0] = qa[o];
+      x[1] = qa[o + 64];
+      x[2] = qj[o];
+      x[3] = qj[o + 64];
+    };
+    contract_fp4<4>(load_words, v.W0, v.W1, acc0, acc1);
+  } else {
+    zero_acc(acc0, acc1);
+    auto load_words = [&](uint32_t w, u64 (&x)[4]) {
+      const size_t o = (size_t)w * word_stride;
+      x[0] = pa[o];
+      x[1] = pa[o + 32];
+      x[2] = pj[o];
+      x[3] = pj[o + 32];
+    };
+    mfma_class<3>(load_words, 0, v.W0, h, lut, acc0);
+    mfma_class<3>(load_words, v.W0, v.W0 + v.W1, h, lut, acc1);
+  }
 
   // Output block layout: lane l holds column l mod 32 (variant j0' + (l mod
   // 32) / 2, genotype l mod 2); register e holds row 8 (e / 4) + 4 h + e mod 4
@@ -215,6 +324,7 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
 }
 
 // One wave: prefixes (a_first + [0, 16), b) x last variants (j0 + [0, 32)).
+template <bool F4>
 __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint32_t b,
                                              uint32_t a_first, uint32_t j0, uint32_t lane,
                                              const u64 *lut) {
@@ -236,23 +346,36 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
     amask[f] = a < b ? ~0ull : 0ull;
   }
   const FI_GLOBAL u64 *pj = Bv + (size_t)j0 * 2 + r;
-  auto load_words = [&](uint32_t w, u64 (&x)[4]) {
-    const u64 wb = pb[(size_t)w * 4];
-    x[0] = pa[0][(size_t)w * 4] & wb & amask[0];
-    x[1] = pa[1][(size_t)w * 4] & wb & amask[1];
-    const size_t o = (size_t)w * word_stride;
-    x[2] = pj[o];
-    x[3] = pj[o + 32];
-  };
   v16i acc0[2][2], acc1[2][2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc0[x][y][e] = acc1[x][y][e] = 0;
-  mfma_class<3>(load_words, 0, v.W0, h, lut, acc0);
-  mfma_class<3>(load_words, v.W0, v.W0 + v.W1, h, lut, acc1);
+  if constexpr (F4) {
+    // the lane's 32-bit half of each word
+    typedef const FI_GLOBAL uint32_t *q32;
+    const q32 qb = reinterpret_cast<q32>(pb) + h;
+    const q32 qa0 = reinterpret_cast<q32>(pa[0]) + h, qa1 = reinterpret_cast<q32>(pa[1]) + h;
+    const uint32_t m0 = (uint32_t)amask[0], m1 = (uint32_t)amask[1];
+    const q32 qj = reinterpret_cast<q32>(pj) + h;
+    auto load_words = [&](uint32_t w, uint32_t (&x)[4]) {
+      const uint32_t wb = qb[(size_t)w * 8];
+      x[0] = qa0[(size_t)w * 8] & wb & m0;
+      x[1] = qa1[(size_t)w * 8] & wb & m1;
+      const size_t o = (size_t)w * word_stride * 2;
+      x[2] = qj[o];
+      x[3] = qj[o + 64];
+    };
+    contract_fp4<3>(load_words, v.W0, v.W1, acc0, acc1);
+  } else {
+    zero_acc(acc0, acc1);
+    auto load_words = [&](uint32_t w, u64 (&x)[4]) {
+      const u64 wb = pb[(size_t)w * 4];
+      x[0] = pa[0][(size_t)w * 4] & wb & amask[0];
+      x[1] = pa[1][(size_t)w * 4] & wb & amask[1];
+      const size_t o = (size_t)w * word_stride;
+      x[2] = pj[o];
+      x[3] = pj[o + 32];
+    };
+    mfma_class<3>(load_words, 0, v.W0, h, lut, acc0);
+    mfma_class<3>(load_words, v.W0, v.W0 + v.W1, h, lut, acc1);
+  }
 
   // Output block (f, fb): lane l holds column l mod 32 (last variant j0 + 16 fb
   // + (l mod 32) / 2, genotype l mod 2); register e holds row 8 (e / 4) + 4 h +
@@ -328,16 +451,18 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
   }
 }
 
-// ORDER 2 or 3: the kernel serves the jobs of that order (a batch with both
-// launches it twice, over the two orders' tiles)
-template <int ORDER>
+// ORDER 2 or 3, F4: FP4 (else int8) operands; the kernel serves the jobs of
+// that order and operand format (a batch with several launches it once per
+// group, each over the group's tiles)
+template <int ORDER, bool F4>
 __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
   __shared__ u64 s_tile;
-  __shared__ u64 s_lut[256 * kLutCopies];
+  __shared__ u64 s_lut[F4 ? 1 : 256 * kLutCopies];
   const uint32_t lane = lane_id();
   const uint32_t wave = uni(threadIdx.x >> 6);
-  for (uint32_t i = threadIdx.x; i < 256 * kLutCopies; i += blockDim.x) s_lut[i] = spread8(i / kLutCopies);
-  const u64 *lut = s_lut + (lane % kLutCopies);
+  if (!F4)
+    for (uint32_t i = threadIdx.x; i < 256 * kLutCopies; i += blockDim.x) s_lut[i] = spread8(i / kLutCopies);
+  const u64 *lut = s_lut + (F4 ? 0 : lane % kLutCopies);
   for (;;) {
     if (threadIdx.x == 0) s_tile = g.tile_base + atomicAdd(g.tile_counter, 1ull);
     __syncthreads();
@@ -348,6 +473,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
     const FI_CONST JobDesc *jd;
     u64 lt;
     if (!locate_tile(g, t, wave, kMfmaPilotEmits, v, jd, lt)) continue;
+    if (v.fp4 != (F4 ? 1u : 0u)) continue;
     cu64p rows = as_const(uni_ptr(jd->row_start));
     uint32_t rl = 0, rh = uni(jd->nrows) - 1;
     while (rl < rh) {
@@ -369,7 +495,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
       // a wave without a prefix a < b or a last variant j < n has nothing to
       // count; its pilot slots stay zero
       if (a_first >= b || j0 >= v.n) continue;
-      wave_prefix3(g, v, b, a_first, j0, lane, lut);
+      wave_prefix3<F4>(g, v, b, a_first, j0, lane, lut);
       continue;
     }
     // order 2: tile (A, B) of the upper triangle of 64-variant blocks, row A first
@@ -380,26 +506,35 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
     // a wave with no pair a < j < n has nothing to count; its pilot slots
     // stay zero
     if (a0 + 1 >= v.n || j0 >= v.n || j0 + 31 <= a0) continue;
-    wave_pairs(v, a0, j0, lane, lut);
+    wave_pairs<F4>(v, a0, j0, lane, lut);
   }
 }
 
-int mfma_grid_size(int order) {
+template <int ORDER, bool F4>
+int mfma_grid() {
   int dev = 0, cus = 0, per = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (order == 3)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_kernel<3>, kMfmaWaves * 64, 0);
-  else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_kernel<2>, kMfmaWaves * 64, 0);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_kernel<ORDER, F4>, kMfmaWaves * 64, 0);
   if (cus <= 0) cus = 256;
   if (per <= 0) per = 1;
   return cus * per;
 }
 
-void launch_mfma(const Globals &g, int order, int grid, hipStream_t s) {
-  if (order == 3) hipLaunchKernelGGL(mfma_kernel<3>, dim3(grid), dim3(kMfmaWaves * 64), 0, s, g);
-  else hipLaunchKernelGGL(mfma_kernel<2>, dim3(grid), dim3(kMfmaWaves * 64), 0, s, g);
+int mfma_grid_size(int order, bool fp4) {
+  if (order == 3) return fp4 ? mfma_grid<3, true>() : mfma_grid<3, false>();
+  return fp4 ? mfma_grid<2, true>() : mfma_grid<2, false>();
+}
+
+void launch_mfma(const Globals &g, int order, bool fp4, int grid, hipStream_t s) {
+  const dim3 gd(grid), bd(kMfmaWaves * 64);
+  if (order == 3) {
+    if (fp4) hipLaunchKernelGGL((mfma_kernel<3, true>), gd, bd, 0, s, g);
+    else hipLaunchKernelGGL((mfma_kernel<3, false>), gd, bd, 0, s, g);
+  } else {
+    if (fp4) hipLaunchKernelGGL((mfma_kernel<2, true>), gd, bd, 0, s, g);
+    else hipLaunchKernelGGL((mfma_kernel<2, false>), gd, bd, 0, s, g);
+  }
 }
 
 }  // namespace fiuncho

@@ -34,6 +34,7 @@ KERNEL_POPCOUNT = 1
 KERNEL_PAIRS = 2
 KERNEL_MFMA = 3
 KERNEL_TRIPLES = 4
+KERNEL_MFMA_FP4 = 5
 
 # every entry point declared in include/fiuncho.h
 EXPORTS = (

@@ -127,11 +127,22 @@ def test_kernel_choice_table(monkeypatch):
         assert int(after.sum()) == int(before.sum()) and after.tolist() != before.tolist()
         monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", "0")
         assert fiuncho.get_kernel(300, 500, 2) == fiuncho.KERNEL_POPCOUNT
+        monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", "4")
+        assert fiuncho.get_kernel(300, 500, 2) == fiuncho.KERNEL_MFMA_FP4
         monkeypatch.delenv("FIUNCHO_ORDER2_MFMA")
+        monkeypatch.setenv("FIUNCHO_ORDER3_MFMA", "4")
+        assert fiuncho.get_kernel(300, 500, 3) == fiuncho.KERNEL_MFMA_FP4
+        monkeypatch.delenv("FIUNCHO_ORDER3_MFMA")
+        # the operand format does not change the tile dealing
+        fiuncho.set_kernel(300, 500, 2, fiuncho.KERNEL_MFMA_FP4)
+        assert fiuncho.get_kernel(300, 500, 2) == fiuncho.KERNEL_MFMA_FP4
+        assert fiuncho.shard_counts(300, 500, 2, 5, fiuncho.TILE_ROUND_ROBIN).tolist() == after.tolist()
     finally:
         fiuncho.set_kernel(300, 500, 2, fiuncho.KERNEL_AUTO)
     assert fiuncho.get_kernel(300, 500, 2) == fiuncho.KERNEL_POPCOUNT
     assert L.fiuncho_set_kernel(300, 500, 4, fiuncho.KERNEL_MFMA) == fiuncho.E_SHAPE
+    assert L.fiuncho_set_kernel(300, 500, 4, fiuncho.KERNEL_MFMA_FP4) == fiuncho.E_SHAPE
+    assert L.fiuncho_set_kernel(2, 500, 3, fiuncho.KERNEL_MFMA_FP4) == fiuncho.E_ORDER
     assert L.fiuncho_set_kernel(300, 500, 2, fiuncho.KERNEL_PAIRS) == fiuncho.E_SHAPE
     assert L.fiuncho_set_kernel(300, 500, 2, 9) == fiuncho.E_SHAPE
     assert L.fiuncho_set_kernel(300, 500, 3, fiuncho.KERNEL_TRIPLES) == fiuncho.E_SHAPE

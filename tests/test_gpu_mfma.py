@@ -1,7 +1,7 @@
-"""GPU parity of the matrix-core paths (order 2: FIUNCHO_ORDER2_MFMA=1,
-order 3: FIUNCHO_ORDER3_MFMA=1): the one-hot int8 contraction must give the
-same tables, top-N set and FP64 scores as the oracle, like the popcount
-path."""
+"""GPU parity of the matrix-core paths (order 2: FIUNCHO_ORDER2_MFMA, order
+3: FIUNCHO_ORDER3_MFMA; 1 = int8 operands, 4 = FP4 operands): the one-hot
+contraction must give the same tables, top-N set and FP64 scores as the
+oracle, like the popcount path, in either operand format."""
 import math
 
 import numpy as np
@@ -14,9 +14,14 @@ from test_gpu_parity import check_hits_against_oracle, full_size_check, random_d
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture
-def mfma(monkeypatch):
-    monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", "1")
+# operand formats of the matrix-core kernels: environment value, test id
+FORMATS = dict(params=["1", "4"], ids=["int8", "fp4"])
+
+
+@pytest.fixture(**FORMATS)
+def mfma(monkeypatch, request):
+    monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", request.param)
+    return request.param
 
 
 # n around the 16/32/64-variant block edges, m around the 32/64-sample steps
@@ -79,9 +84,10 @@ def test_order2_mfma_shards(n, P, mfma):
 # order 3: prefix pairs x last variants on the matrix cores
 # ---------------------------------------------------------------------------
 
-@pytest.fixture
-def mfma3(monkeypatch):
-    monkeypatch.setenv("FIUNCHO_ORDER3_MFMA", "1")
+@pytest.fixture(**FORMATS)
+def mfma3(monkeypatch, request):
+    monkeypatch.setenv("FIUNCHO_ORDER3_MFMA", request.param)
+    return request.param
 
 
 # n around the 8-prefix fragments, 32-prefix groups and 64-variant blocks
@@ -111,7 +117,8 @@ def test_order3_mfma_workload(mfma3):
 
 
 def test_order3_mfma_shards_and_batch(mfma3, monkeypatch):
-    monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", "1")
+    # order 2 on the matrix cores in the other operand format
+    monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", "4" if mfma3 == "1" else "1")
     G, y = random_dataset(93, 120, 180, 0.5)
     lists = _run_shards(G, y, 3, 40, 5)
     check_hits_against_oracle(G, y, 3, 40, _merge(lists, 40))
@@ -148,3 +155,37 @@ def test_matrix_core_batch_graph_replay(mfma, mfma3):
             assert s1 == s2 and h1.tobytes() == h2.tobytes(), rep
         x = torch.randn(1 << 20, device="cuda")
         (x * 2).sum().item()
+
+
+def test_both_operand_formats_in_one_batch(monkeypatch):
+    """Order-2 and order-3 jobs on the matrix cores, int8 for some shapes and
+    FP4 for others, next to popcount jobs, in one batched call: each of the
+    four matrix-core groups runs its own launch over its own tiles."""
+    for v in ("FIUNCHO_ORDER2_MFMA", "FIUNCHO_ORDER3_MFMA", "FIUNCHO_ORDER3_PAIRS"):
+        monkeypatch.delenv(v, raising=False)
+    jobs = [synth.generate(150, 300, seed=21, order=2, top_n=20),
+            synth.generate(300, 700, seed=22, order=2, top_n=20),
+            synth.generate(60, 400, seed=23, order=3, top_n=20),
+            synth.generate(130, 200, seed=24, order=3, top_n=20),
+            synth.generate(40, 500, seed=25, order=3, top_n=10),
+            synth.generate(70, 900, seed=26, order=2, top_n=10)]
+    kinds = [fiuncho.KERNEL_MFMA, fiuncho.KERNEL_MFMA_FP4, fiuncho.KERNEL_MFMA_FP4, fiuncho.KERNEL_MFMA,
+             fiuncho.KERNEL_PAIRS, fiuncho.KERNEL_POPCOUNT]
+    try:
+        for d, kind in zip(jobs, kinds):
+            fiuncho.set_kernel(d.n, d.m, d.order, kind)
+        for d, kind in zip(jobs, kinds):
+            assert fiuncho.get_kernel(d.n, d.m, d.order) == kind
+        fiuncho.set_profiling(True)
+        b = fiuncho.DeviceBatch(jobs)
+        b.run()
+        res = b.results()
+        prof = fiuncho.get_profile()
+        fiuncho.set_profiling(False)
+        assert prof["kernels"] == sum(1 << k for k in set(kinds))
+        for d, (status, hits) in zip(jobs, res):
+            assert status == 0
+            check_hits_against_oracle(d.genotypes, d.phenotype, d.order, d.top_n, hits)
+    finally:
+        for d in jobs:
+            fiuncho.set_kernel(d.n, d.m, d.order, fiuncho.KERNEL_AUTO)

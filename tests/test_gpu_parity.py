@@ -418,8 +418,9 @@ def test_autotune_then_search(n, m, k):
     say(f"case: autotune n={n} m={m} k={k}")
     try:
         kern = fiuncho.autotune(n, m, k, reps=2)
-        assert kern in ((fiuncho.KERNEL_POPCOUNT, fiuncho.KERNEL_MFMA) if k == 2 else
-                        (fiuncho.KERNEL_POPCOUNT, fiuncho.KERNEL_PAIRS))
+        assert kern in ((fiuncho.KERNEL_POPCOUNT, fiuncho.KERNEL_MFMA, fiuncho.KERNEL_MFMA_FP4) if k == 2 else
+                        (fiuncho.KERNEL_POPCOUNT, fiuncho.KERNEL_PAIRS, fiuncho.KERNEL_MFMA,
+                         fiuncho.KERNEL_MFMA_FP4))
         assert fiuncho.get_kernel(n, m, k) == kern
         G, y = random_dataset(60 + k, n, m, 0.5)
         fiuncho.set_profiling(True)
@@ -453,7 +454,7 @@ def test_plan_upload_flag_after_workspace_reuse():
 # size extremes
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("mfma", ["0", "1"])
+@pytest.mark.parametrize("mfma", ["0", "1", "4"])
 def test_maximum_samples(mfma, monkeypatch):
     """samples = 2^24 - 1, the largest accepted: counts far above 2^16, the
     widest single-precision bound, 262,146-word rows."""
@@ -462,7 +463,7 @@ def test_maximum_samples(mfma, monkeypatch):
     rng = np.random.default_rng(70)
     G = rng.integers(0, 3, (n, m), dtype=np.uint8)
     y = (rng.random(m) < 0.45).astype(np.uint8)
-    for k in ((2,) if mfma == "1" else (1, 2, 3)):
+    for k in ((2,) if mfma != "0" else (1, 2, 3)):
         say(f"case: maximum samples k={k} mfma={mfma}")
         hits = fiuncho.scan(G, y, k, 5)
         check_hits_against_oracle(G, y, k, 5, hits)
