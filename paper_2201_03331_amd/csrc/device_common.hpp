@@ -13,6 +13,7 @@ typedef unsigned long long u64;
 // data is read through the global address space (no flat-address checks).
 #define FI_CONST __attribute__((address_space(4)))
 #define FI_GLOBAL __attribute__((address_space(1)))
+#define FI_LDS __attribute__((address_space(3)))
 typedef const FI_CONST u64 *cu64p;
 typedef const FI_CONST uint32_t *cu32p;
 typedef const FI_GLOBAL u64 *gu64p;

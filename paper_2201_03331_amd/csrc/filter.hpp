@@ -65,7 +65,9 @@ __device__ __forceinline__ JV load_view(const JobDesc *jd) {
 // The scan evaluates it in plain single precision from a float table of f;
 // the job's fbound bounds the rounding error of the resulting MI, and every
 // filter below widens its threshold by twice that bound.
-__device__ __forceinline__ float mi_term(const FI_GLOBAL float *F, uint32_t n0, uint32_t n1) {
+// F is the table in global memory or a copy of it in LDS.
+template <typename FP>
+__device__ __forceinline__ float mi_term(FP F, uint32_t n0, uint32_t n1) {
   return (F[n0] + F[n1]) - F[n0 + n1];
 }
 
@@ -162,8 +164,8 @@ __device__ __forceinline__ MiConst mi_const(const JV &v) {
 
 // Scores a complete table of NC cells x 2 classes and appends it if it may be
 // among the best.
-template <int NC>
-__device__ __forceinline__ void score_table(const JV &v, const FI_GLOBAL float *F,
+template <int NC, typename FP>
+__device__ __forceinline__ void score_table(const JV &v, FP F,
                                             const uint32_t (&t)[NC][2], bool active, float thr,
                                             const MiConst &mc, u64 rank, uint32_t lane) {
   float fs = mc.c;
@@ -278,9 +280,8 @@ __device__ __forceinline__ void walk_order3(const Order3Parts &q, Visit &&visit)
 // the tile at offset (shard_index + i) mod shard_count of block i of
 // shard_count consecutive tiles.  Returns false when the job is skipped
 // (invalid input or an empty class).
-__device__ __forceinline__ bool locate_tile(const Globals &g, u64 t, uint32_t wave,
-                                            uint32_t slots_per_wave, JV &v,
-                                            const FI_CONST JobDesc *&jd, u64 &lt) {
+// the job (index into g.jobs) that owns launch tile t
+__device__ __forceinline__ uint32_t job_of_tile(const Globals &g, u64 t) {
   cu64p jts = as_const(g.job_tile_start);
   uint32_t lo = 0, hi = g.n_jobs - 1;
   while (lo < hi) {
@@ -288,7 +289,14 @@ __device__ __forceinline__ bool locate_tile(const Globals &g, u64 t, uint32_t wa
     if (jts[mid] <= t) lo = mid;
     else hi = mid - 1;
   }
-  lo = uni(lo);
+  return uni(lo);
+}
+
+__device__ __forceinline__ bool locate_tile(const Globals &g, u64 t, uint32_t wave,
+                                            uint32_t slots_per_wave, JV &v,
+                                            const FI_CONST JobDesc *&jd, u64 &lt) {
+  cu64p jts = as_const(g.job_tile_start);
+  const uint32_t lo = job_of_tile(g, t);
   v = load_view(g.jobs + lo);
   {
     const JobState *st = v.st;

@@ -53,6 +53,12 @@ static_assert(kMfmaWaves == kScanWaves, "pilot slots and tile decoding assume eq
 // so that the 16 lanes an LDS cycle serves always hit distinct banks.
 constexpr int kLutCopies = 16;
 
+// Entries of the f table a matrix-core workgroup keeps in LDS (dynamic LDS;
+// jobs with more samples read the table from global memory).  Two
+// workgroups share a compute unit's 160 KB: 64 KB each with FP4 operands, 32
+// KB next to the 32 KB byte table with int8 operands.
+__host__ __device__ constexpr uint32_t mfma_f_entries(bool fp4) { return fp4 ? 16384u : 8192u; }
+
 __device__ __forceinline__ u64 spread8(uint32_t e) {
   const uint32_t lo = ((e & 0xFu) * 0x00204081u) & 0x01010101u;
   const uint32_t hi = (((e >> 4) & 0xFu) * 0x00204081u) & 0x01010101u;
@@ -221,7 +227,7 @@ __device__ __forceinline__ void contract_fp4(Load &&load_words, uint32_t W0, uin
 // One wave: pairs (a0 + [0, 32)) x (j0 + [0, 32)).
 template <bool F4>
 __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0, uint32_t lane,
-                                           const u64 *lut) {
+                                           const u64 *lut, const FI_LDS float *Fl, bool f_lds) {
   const uint32_t n = v.n;
   const uint32_t r = lane & 31, h = lane >> 5;
   const size_t word_stride = (size_t)v.n_pad * 2;
@@ -263,71 +269,75 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
   const uint32_t gl = lane & 1;
   const float thr = current_threshold(v);
   const MiConst mc = mi_const(v);
-  const FI_GLOBAL float *F = as_global(v.Fh);
   const FI_GLOBAL uint32_t *marg = as_global(v.marg);
   const uint32_t mcls[2] = {v.m0, v.m1};
-#pragma unroll
-  for (int fb = 0; fb < 2; ++fb) {
-    const uint32_t j = j0 + 16 * fb + (r >> 1);
-    const uint32_t jj = j < n ? j : n - 1;
-    uint32_t Mj[2][2];
-#pragma unroll
-    for (int gg = 0; gg < 2; ++gg)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) Mj[gg][c] = marg[(size_t)jj * 6 + 2 * gg + c];
-#pragma unroll
-    for (int fa = 0; fa < 2; ++fa) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t a = a0 + 16 * fa + 4 * q + 2 * h + gl;
-        uint32_t cnt[2][2][2];  // [g_a][g_j][class]
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const v16i &A = c == 0 ? acc0[fa][fb] : acc1[fa][fb];
-#pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            const uint32_t lo = (uint32_t)A[4 * q + t], hi = (uint32_t)A[4 * q + 2 + t];
-            const uint32_t own = gl ? hi : lo;
-            const uint32_t send = gl ? lo : hi;
-            const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
-            cnt[t][gl][c] = own;
-            cnt[t][gl ^ 1][c] = recv;
+  // the scoring reads the f table from the workgroup's LDS copy when it
+  // holds this job's table, else from global memory
+  auto score = [&](auto F) {
+  #pragma unroll
+    for (int fb = 0; fb < 2; ++fb) {
+      const uint32_t j = j0 + 16 * fb + (r >> 1);
+      const uint32_t jj = j < n ? j : n - 1;
+      uint32_t Mj[2][2];
+  #pragma unroll
+      for (int gg = 0; gg < 2; ++gg)
+  #pragma unroll
+        for (int c = 0; c < 2; ++c) Mj[gg][c] = marg[(size_t)jj * 6 + 2 * gg + c];
+  #pragma unroll
+      for (int fa = 0; fa < 2; ++fa) {
+  #pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t a = a0 + 16 * fa + 4 * q + 2 * h + gl;
+          uint32_t cnt[2][2][2];  // [g_a][g_j][class]
+  #pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const v16i &A = c == 0 ? acc0[fa][fb] : acc1[fa][fb];
+  #pragma unroll
+            for (int t = 0; t < 2; ++t) {
+              const uint32_t lo = (uint32_t)A[4 * q + t], hi = (uint32_t)A[4 * q + 2 + t];
+              const uint32_t own = gl ? hi : lo;
+              const uint32_t send = gl ? lo : hi;
+              const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
+              cnt[t][gl][c] = own;
+              cnt[t][gl ^ 1][c] = recv;
+            }
           }
+          const bool active = a < j && j < n;
+          const uint32_t aa = a < n ? a : n - 1;
+          uint32_t t9[9][2];
+  #pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const uint32_t Ma0 = marg[(size_t)aa * 6 + c], Ma1 = marg[(size_t)aa * 6 + 2 + c];
+            t9[0][c] = cnt[0][0][c];
+            t9[1][c] = cnt[0][1][c];
+            t9[2][c] = Ma0 - cnt[0][0][c] - cnt[0][1][c];
+            t9[3][c] = cnt[1][0][c];
+            t9[4][c] = cnt[1][1][c];
+            t9[5][c] = Ma1 - cnt[1][0][c] - cnt[1][1][c];
+            t9[6][c] = Mj[0][c] - cnt[0][0][c] - cnt[1][0][c];
+            t9[7][c] = Mj[1][c] - cnt[0][1][c] - cnt[1][1][c];
+            t9[8][c] = mcls[c] - Ma0 - Ma1 - Mj[0][c] - Mj[1][c] + cnt[0][0][c] + cnt[0][1][c] +
+                       cnt[1][0][c] + cnt[1][1][c];
+            // every count is at most the class size; the clamp keeps the table
+            // lookups inside [0, m] whatever the counts hold
+  #pragma unroll
+            for (int x = 0; x < 9; ++x) t9[x][c] = active ? min(t9[x][c], mcls[c]) : 0u;
+          }
+          // lexicographic rank of (a, j): sum over a' < a of (n - 1 - a'), plus j - a - 1
+          const u64 rank = active ? (u64)a * (n - 1) - (u64)a * (a - 1) / 2 + (j - a - 1) : 0;
+          score_table<9>(v, F, t9, active, thr, mc, rank, lane);
         }
-        const bool active = a < j && j < n;
-        const uint32_t aa = a < n ? a : n - 1;
-        uint32_t t9[9][2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const uint32_t Ma0 = marg[(size_t)aa * 6 + c], Ma1 = marg[(size_t)aa * 6 + 2 + c];
-          t9[0][c] = cnt[0][0][c];
-          t9[1][c] = cnt[0][1][c];
-          t9[2][c] = Ma0 - cnt[0][0][c] - cnt[0][1][c];
-          t9[3][c] = cnt[1][0][c];
-          t9[4][c] = cnt[1][1][c];
-          t9[5][c] = Ma1 - cnt[1][0][c] - cnt[1][1][c];
-          t9[6][c] = Mj[0][c] - cnt[0][0][c] - cnt[1][0][c];
-          t9[7][c] = Mj[1][c] - cnt[0][1][c] - cnt[1][1][c];
-          t9[8][c] = mcls[c] - Ma0 - Ma1 - Mj[0][c] - Mj[1][c] + cnt[0][0][c] + cnt[0][1][c] +
-                     cnt[1][0][c] + cnt[1][1][c];
-          // every count is at most the class size; the clamp keeps the table
-          // lookups inside [0, m] whatever the counts hold
-#pragma unroll
-          for (int x = 0; x < 9; ++x) t9[x][c] = active ? min(t9[x][c], mcls[c]) : 0u;
-        }
-        // lexicographic rank of (a, j): sum over a' < a of (n - 1 - a'), plus j - a - 1
-        const u64 rank = active ? (u64)a * (n - 1) - (u64)a * (a - 1) / 2 + (j - a - 1) : 0;
-        score_table<9>(v, F, t9, active, thr, mc, rank, lane);
       }
     }
-  }
+  };
+  score(f_lds ? (const float *)Fl : v.Fh);
 }
 
 // One wave: prefixes (a_first + [0, 16), b) x last variants (j0 + [0, 32)).
 template <bool F4>
 __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint32_t b,
                                              uint32_t a_first, uint32_t j0, uint32_t lane,
-                                             const u64 *lut) {
+                                             const u64 *lut, const FI_LDS float *Fl, bool f_lds) {
   const uint32_t n = v.n;
   const uint32_t r = lane & 31, h = lane >> 5;
   const size_t word_stride = (size_t)v.n_pad * 2;
@@ -386,7 +396,6 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
   const uint32_t gl = lane & 1;
   const float thr = current_threshold(v);
   const MiConst mc = mi_const(v);
-  const FI_GLOBAL float *F = as_global(v.Fh);
   const FI_GLOBAL uint32_t *marg = as_global(v.marg);
   const FI_GLOBAL uint32_t *PT = as_global(v.pairs);
   const uint32_t mcls[2] = {v.m0, v.m1};
@@ -395,60 +404,65 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int c = 0; c < 2; ++c) Mb[x][c] = marg[(size_t)b * 6 + 2 * x + c];
-#pragma unroll
-  for (int fb = 0; fb < 2; ++fb) {
-    const uint32_t j = j0 + 16 * fb + (r >> 1);
-    const uint32_t jj = j < n ? j : n - 1;
-    uint32_t Mj[2][2], bj[8];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) Mj[x][c] = marg[(size_t)jj * 6 + 2 * x + c];
-    load_pair(PT + ((size_t)b * v.n_pad + jj) * 8, bj);
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        // this lane's prefix: e / 4 = 2 gl + t
-        const uint32_t a = a_first + 8 * f + 2 * (2 * gl + t) + h;
-        uint32_t D[2][2][2][2];  // [class][g_a][g_b][g_j]
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const v16i &A = c == 0 ? acc0[f][fb] : acc1[f][fb];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const uint32_t lo = (uint32_t)A[4 * t + i], hi = (uint32_t)A[4 * (2 + t) + i];
-            const uint32_t own = gl ? hi : lo;
-            const uint32_t send = gl ? lo : hi;
-            const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
-            D[c][i >> 1][i & 1][gl] = own;
-            D[c][i >> 1][i & 1][gl ^ 1] = recv;
+  // the scoring reads the f table from the workgroup's LDS copy when it
+  // holds this job's table, else from global memory
+  auto score = [&](auto F) {
+  #pragma unroll
+    for (int fb = 0; fb < 2; ++fb) {
+      const uint32_t j = j0 + 16 * fb + (r >> 1);
+      const uint32_t jj = j < n ? j : n - 1;
+      uint32_t Mj[2][2], bj[8];
+  #pragma unroll
+      for (int x = 0; x < 2; ++x)
+  #pragma unroll
+        for (int c = 0; c < 2; ++c) Mj[x][c] = marg[(size_t)jj * 6 + 2 * x + c];
+      load_pair(PT + ((size_t)b * v.n_pad + jj) * 8, bj);
+  #pragma unroll
+      for (int f = 0; f < 2; ++f) {
+  #pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          // this lane's prefix: e / 4 = 2 gl + t
+          const uint32_t a = a_first + 8 * f + 2 * (2 * gl + t) + h;
+          uint32_t D[2][2][2][2];  // [class][g_a][g_b][g_j]
+  #pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const v16i &A = c == 0 ? acc0[f][fb] : acc1[f][fb];
+  #pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const uint32_t lo = (uint32_t)A[4 * t + i], hi = (uint32_t)A[4 * (2 + t) + i];
+              const uint32_t own = gl ? hi : lo;
+              const uint32_t send = gl ? lo : hi;
+              const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
+              D[c][i >> 1][i & 1][gl] = own;
+              D[c][i >> 1][i & 1][gl ^ 1] = recv;
+            }
           }
+          const bool active = a < b && j < n;
+          const uint32_t aa = a < b ? a : b - 1;
+          uint32_t ab[8], aj[8], Ma[2][2];
+          load_pair(PT + ((size_t)aa * v.n_pad + b) * 8, ab);
+          load_pair(PT + ((size_t)aa * v.n_pad + jj) * 8, aj);
+  #pragma unroll
+          for (int x = 0; x < 2; ++x)
+  #pragma unroll
+            for (int c = 0; c < 2; ++c) Ma[x][c] = marg[(size_t)aa * 6 + 2 * x + c];
+          const Order3Parts parts = {D, ab, aj, bj, Ma, Mb, Mj, mcls};
+          float fs = mc.c;
+          if (active) {
+            // every count is at most its class size; the clamps keep the table
+            // lookups inside [0, m] whatever the counts hold
+            walk_order3(parts, [&](uint32_t n0, uint32_t n1) {
+              fs += mi_term(F, min(n0, mcls[0]), min(n1, mcls[1]));
+            });
+          }
+          const uint32_t pre[2] = {aa, b};
+          const u64 rank = active ? lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1) : 0;
+          emit(v, active, fs * mc.inv_m, rank, thr, lane);
         }
-        const bool active = a < b && j < n;
-        const uint32_t aa = a < b ? a : b - 1;
-        uint32_t ab[8], aj[8], Ma[2][2];
-        load_pair(PT + ((size_t)aa * v.n_pad + b) * 8, ab);
-        load_pair(PT + ((size_t)aa * v.n_pad + jj) * 8, aj);
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int c = 0; c < 2; ++c) Ma[x][c] = marg[(size_t)aa * 6 + 2 * x + c];
-        const Order3Parts parts = {D, ab, aj, bj, Ma, Mb, Mj, mcls};
-        float fs = mc.c;
-        if (active) {
-          // every count is at most its class size; the clamps keep the table
-          // lookups inside [0, m] whatever the counts hold
-          walk_order3(parts, [&](uint32_t n0, uint32_t n1) {
-            fs += mi_term(F, min(n0, mcls[0]), min(n1, mcls[1]));
-          });
-        }
-        const uint32_t pre[2] = {aa, b};
-        const u64 rank = active ? lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1) : 0;
-        emit(v, active, fs * mc.inv_m, rank, thr, lane);
       }
     }
-  }
+  };
+  score(f_lds ? (const float *)Fl : v.Fh);
 }
 
 // ORDER 2 or 3, F4: FP4 (else int8) operands; the kernel serves the jobs of
@@ -458,17 +472,39 @@ template <int ORDER, bool F4>
 __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
   __shared__ u64 s_tile;
   __shared__ u64 s_lut[F4 ? 1 : 256 * kLutCopies];
+  // the f table of the current job, when it has at most mfma_f_entries(F4)
+  // entries (dynamic LDS of that size)
+  extern __shared__ float s_f[];
   const uint32_t lane = lane_id();
   const uint32_t wave = uni(threadIdx.x >> 6);
   if (!F4)
     for (uint32_t i = threadIdx.x; i < 256 * kLutCopies; i += blockDim.x) s_lut[i] = spread8(i / kLutCopies);
   const u64 *lut = s_lut + (F4 ? 0 : lane % kLutCopies);
+  const FI_LDS float *Fl = (const FI_LDS float *)s_f;
+  uint32_t f_job = ~0u;  // job whose table s_f holds (same in every thread)
+  bool f_lds = false;
   for (;;) {
     if (threadIdx.x == 0) s_tile = g.tile_base + atomicAdd(g.tile_counter, 1ull);
     __syncthreads();
     const u64 t = uni64(s_tile);
     __syncthreads();
     if (t >= g.total_tiles) break;
+    {
+      // every wave of the workgroup has finished the previous tile (the
+      // barriers above), so the table can be replaced
+      const uint32_t jx = job_of_tile(g, t);
+      if (jx != f_job) {
+        const FI_CONST JobDesc *J = as_const(g.jobs) + jx;
+        const uint32_t entries = uni(J->m) + 1;
+        f_lds = entries <= mfma_f_entries(F4);
+        if (f_lds) {
+          const FI_GLOBAL float *Fh = as_global(uni_ptr(J->Fh));
+          for (uint32_t i = threadIdx.x; i < entries; i += blockDim.x) s_f[i] = Fh[i];
+        }
+        f_job = jx;
+        __syncthreads();
+      }
+    }
     JV v;
     const FI_CONST JobDesc *jd;
     u64 lt;
@@ -495,7 +531,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
       // a wave without a prefix a < b or a last variant j < n has nothing to
       // count; its pilot slots stay zero
       if (a_first >= b || j0 >= v.n) continue;
-      wave_prefix3<F4>(g, v, b, a_first, j0, lane, lut);
+      wave_prefix3<F4>(g, v, b, a_first, j0, lane, lut, Fl, f_lds);
       continue;
     }
     // order 2: tile (A, B) of the upper triangle of 64-variant blocks, row A first
@@ -506,7 +542,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
     // a wave with no pair a < j < n has nothing to count; its pilot slots
     // stay zero
     if (a0 + 1 >= v.n || j0 >= v.n || j0 + 31 <= a0) continue;
-    wave_pairs<F4>(v, a0, j0, lane, lut);
+    wave_pairs<F4>(v, a0, j0, lane, lut, Fl, f_lds);
   }
 }
 
@@ -515,7 +551,8 @@ int mfma_grid() {
   int dev = 0, cus = 0, per = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_kernel<ORDER, F4>, kMfmaWaves * 64, 0);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_kernel<ORDER, F4>, kMfmaWaves * 64,
+                                                     mfma_f_entries(F4) * sizeof(float));
   if (cus <= 0) cus = 256;
   if (per <= 0) per = 1;
   return cus * per;
@@ -528,12 +565,13 @@ int mfma_grid_size(int order, bool fp4) {
 
 void launch_mfma(const Globals &g, int order, bool fp4, int grid, hipStream_t s) {
   const dim3 gd(grid), bd(kMfmaWaves * 64);
+  const size_t lds = mfma_f_entries(fp4) * sizeof(float);
   if (order == 3) {
-    if (fp4) hipLaunchKernelGGL((mfma_kernel<3, true>), gd, bd, 0, s, g);
-    else hipLaunchKernelGGL((mfma_kernel<3, false>), gd, bd, 0, s, g);
+    if (fp4) hipLaunchKernelGGL((mfma_kernel<3, true>), gd, bd, lds, s, g);
+    else hipLaunchKernelGGL((mfma_kernel<3, false>), gd, bd, lds, s, g);
   } else {
-    if (fp4) hipLaunchKernelGGL((mfma_kernel<2, true>), gd, bd, 0, s, g);
-    else hipLaunchKernelGGL((mfma_kernel<2, false>), gd, bd, 0, s, g);
+    if (fp4) hipLaunchKernelGGL((mfma_kernel<2, true>), gd, bd, lds, s, g);
+    else hipLaunchKernelGGL((mfma_kernel<2, false>), gd, bd, lds, s, g);
   }
 }
 
