@@ -225,9 +225,9 @@ __device__ __forceinline__ void contract_fp4(Load &&load_words, uint32_t W0, uin
 }
 
 // One wave: pairs (a0 + [0, 32)) x (j0 + [0, 32)).
-template <bool F4>
+template <bool F4, bool LDS_F>
 __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0, uint32_t lane,
-                                           const u64 *lut, const FI_LDS float *Fl, bool f_lds) {
+                                           const u64 *lut, const FI_LDS float *Fl) {
   const uint32_t n = v.n;
   const uint32_t r = lane & 31, h = lane >> 5;
   const size_t word_stride = (size_t)v.n_pad * 2;
@@ -271,41 +271,43 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
   const MiConst mc = mi_const(v);
   const FI_GLOBAL uint32_t *marg = as_global(v.marg);
   const uint32_t mcls[2] = {v.m0, v.m1};
-  // the scoring reads the f table from the workgroup's LDS copy when it
-  // holds this job's table, else from global memory
+  // the scoring reads the f table from the workgroup's LDS copy (LDS_F:
+  // it holds this job's table) or from global memory
   auto score = [&](auto F) {
-  #pragma unroll
+#pragma unroll
     for (int fb = 0; fb < 2; ++fb) {
       const uint32_t j = j0 + 16 * fb + (r >> 1);
       const uint32_t jj = j < n ? j : n - 1;
       uint32_t Mj[2][2];
-  #pragma unroll
+#pragma unroll
       for (int gg = 0; gg < 2; ++gg)
-  #pragma unroll
+#pragma unroll
         for (int c = 0; c < 2; ++c) Mj[gg][c] = marg[(size_t)jj * 6 + 2 * gg + c];
-  #pragma unroll
+#pragma unroll
       for (int fa = 0; fa < 2; ++fa) {
-  #pragma unroll
+#pragma unroll
         for (int q = 0; q < 4; ++q) {
           const uint32_t a = a0 + 16 * fa + 4 * q + 2 * h + gl;
           uint32_t cnt[2][2][2];  // [g_a][g_j][class]
-  #pragma unroll
+#pragma unroll
           for (int c = 0; c < 2; ++c) {
             const v16i &A = c == 0 ? acc0[fa][fb] : acc1[fa][fb];
-  #pragma unroll
+#pragma unroll
             for (int t = 0; t < 2; ++t) {
               const uint32_t lo = (uint32_t)A[4 * q + t], hi = (uint32_t)A[4 * q + 2 + t];
               const uint32_t own = gl ? hi : lo;
               const uint32_t send = gl ? lo : hi;
               const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
-              cnt[t][gl][c] = own;
-              cnt[t][gl ^ 1][c] = recv;
+              // static indices only: a lane-dependent index into a register
+              // array becomes a compare-and-select over every element
+              cnt[t][0][c] = gl ? recv : own;
+              cnt[t][1][c] = gl ? own : recv;
             }
           }
           const bool active = a < j && j < n;
           const uint32_t aa = a < n ? a : n - 1;
           uint32_t t9[9][2];
-  #pragma unroll
+#pragma unroll
           for (int c = 0; c < 2; ++c) {
             const uint32_t Ma0 = marg[(size_t)aa * 6 + c], Ma1 = marg[(size_t)aa * 6 + 2 + c];
             t9[0][c] = cnt[0][0][c];
@@ -320,7 +322,7 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
                        cnt[1][0][c] + cnt[1][1][c];
             // every count is at most the class size; the clamp keeps the table
             // lookups inside [0, m] whatever the counts hold
-  #pragma unroll
+#pragma unroll
             for (int x = 0; x < 9; ++x) t9[x][c] = active ? min(t9[x][c], mcls[c]) : 0u;
           }
           // lexicographic rank of (a, j): sum over a' < a of (n - 1 - a'), plus j - a - 1
@@ -330,14 +332,15 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
       }
     }
   };
-  score(f_lds ? (const float *)Fl : v.Fh);
+  if constexpr (LDS_F) score(Fl);
+  else score(as_global(v.Fh));
 }
 
 // One wave: prefixes (a_first + [0, 16), b) x last variants (j0 + [0, 32)).
-template <bool F4>
+template <bool F4, bool LDS_F>
 __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint32_t b,
                                              uint32_t a_first, uint32_t j0, uint32_t lane,
-                                             const u64 *lut, const FI_LDS float *Fl, bool f_lds) {
+                                             const u64 *lut, const FI_LDS float *Fl) {
   const uint32_t n = v.n;
   const uint32_t r = lane & 31, h = lane >> 5;
   const size_t word_stride = (size_t)v.n_pad * 2;
@@ -404,37 +407,37 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int c = 0; c < 2; ++c) Mb[x][c] = marg[(size_t)b * 6 + 2 * x + c];
-  // the scoring reads the f table from the workgroup's LDS copy when it
-  // holds this job's table, else from global memory
+  // the scoring reads the f table from the workgroup's LDS copy (LDS_F:
+  // it holds this job's table) or from global memory
   auto score = [&](auto F) {
-  #pragma unroll
+#pragma unroll
     for (int fb = 0; fb < 2; ++fb) {
       const uint32_t j = j0 + 16 * fb + (r >> 1);
       const uint32_t jj = j < n ? j : n - 1;
       uint32_t Mj[2][2], bj[8];
-  #pragma unroll
+#pragma unroll
       for (int x = 0; x < 2; ++x)
-  #pragma unroll
+#pragma unroll
         for (int c = 0; c < 2; ++c) Mj[x][c] = marg[(size_t)jj * 6 + 2 * x + c];
       load_pair(PT + ((size_t)b * v.n_pad + jj) * 8, bj);
-  #pragma unroll
+#pragma unroll
       for (int f = 0; f < 2; ++f) {
-  #pragma unroll
+#pragma unroll
         for (int t = 0; t < 2; ++t) {
           // this lane's prefix: e / 4 = 2 gl + t
           const uint32_t a = a_first + 8 * f + 2 * (2 * gl + t) + h;
           uint32_t D[2][2][2][2];  // [class][g_a][g_b][g_j]
-  #pragma unroll
+#pragma unroll
           for (int c = 0; c < 2; ++c) {
             const v16i &A = c == 0 ? acc0[f][fb] : acc1[f][fb];
-  #pragma unroll
+#pragma unroll
             for (int i = 0; i < 4; ++i) {
               const uint32_t lo = (uint32_t)A[4 * t + i], hi = (uint32_t)A[4 * (2 + t) + i];
               const uint32_t own = gl ? hi : lo;
               const uint32_t send = gl ? lo : hi;
               const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
-              D[c][i >> 1][i & 1][gl] = own;
-              D[c][i >> 1][i & 1][gl ^ 1] = recv;
+              D[c][i >> 1][i & 1][0] = gl ? recv : own;
+              D[c][i >> 1][i & 1][1] = gl ? own : recv;
             }
           }
           const bool active = a < b && j < n;
@@ -442,9 +445,9 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
           uint32_t ab[8], aj[8], Ma[2][2];
           load_pair(PT + ((size_t)aa * v.n_pad + b) * 8, ab);
           load_pair(PT + ((size_t)aa * v.n_pad + jj) * 8, aj);
-  #pragma unroll
+#pragma unroll
           for (int x = 0; x < 2; ++x)
-  #pragma unroll
+#pragma unroll
             for (int c = 0; c < 2; ++c) Ma[x][c] = marg[(size_t)aa * 6 + 2 * x + c];
           const Order3Parts parts = {D, ab, aj, bj, Ma, Mb, Mj, mcls};
           float fs = mc.c;
@@ -462,7 +465,8 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
       }
     }
   };
-  score(f_lds ? (const float *)Fl : v.Fh);
+  if constexpr (LDS_F) score(Fl);
+  else score(as_global(v.Fh));
 }
 
 // ORDER 2 or 3, F4: FP4 (else int8) operands; the kernel serves the jobs of
@@ -531,7 +535,8 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
       // a wave without a prefix a < b or a last variant j < n has nothing to
       // count; its pilot slots stay zero
       if (a_first >= b || j0 >= v.n) continue;
-      wave_prefix3<F4>(g, v, b, a_first, j0, lane, lut, Fl, f_lds);
+      if (f_lds) wave_prefix3<F4, true>(g, v, b, a_first, j0, lane, lut, Fl);
+      else wave_prefix3<F4, false>(g, v, b, a_first, j0, lane, lut, Fl);
       continue;
     }
     // order 2: tile (A, B) of the upper triangle of 64-variant blocks, row A first
@@ -542,7 +547,8 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
     // a wave with no pair a < j < n has nothing to count; its pilot slots
     // stay zero
     if (a0 + 1 >= v.n || j0 >= v.n || j0 + 31 <= a0) continue;
-    wave_pairs<F4>(v, a0, j0, lane, lut, Fl, f_lds);
+    if (f_lds) wave_pairs<F4, true>(v, a0, j0, lane, lut, Fl);
+    else wave_pairs<F4, false>(v, a0, j0, lane, lut, Fl);
   }
 }
 
