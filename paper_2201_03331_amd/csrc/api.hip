@@ -237,16 +237,17 @@ bool kernel_valid(int kernel, uint32_t n, uint32_t k) {
   }
 }
 
-// From autotuning on MI355X (the 64-dataset batch: 200-2,000 variants,
-// 1,000-20,000 samples): the matrix-core kernels win at order 2 from about a
-// thousand variants or 256 words, at order 3 from 128 words; below, the
-// popcount kernels (order 2 rows against rows, order 3 with pair tables).
-// Order 4 uses the triple tables while they fit in 16 GiB.
+// From timing every kernel on MI355X over 100-4,000 variants and
+// 1,000-20,000 samples: order 3 on the matrix cores with FP4 operands
+// everywhere (1.1-2.4 times the pair-table kernel); order 2 on the same
+// kernel except for 256-4,095 variants with fewer than 128 words, where the
+// popcount kernel is up to 25 % faster.  Order 4 uses the triple tables while
+// they fit in 16 GiB.
 int rule_kernel(uint32_t n, uint32_t m, uint32_t k) {
   const u64 words = ceil_div(m, 64);
-  if (k == 3 && n >= 3) return words >= 128 ? FIUNCHO_KERNEL_MFMA : FIUNCHO_KERNEL_PAIRS;
+  if (k == 3 && n >= 3) return FIUNCHO_KERNEL_MFMA_FP4;
   if (k == 4 && kernel_valid(FIUNCHO_KERNEL_TRIPLES, n, k)) return FIUNCHO_KERNEL_TRIPLES;
-  if (k == 2 && (n >= 1024 || words >= 256)) return FIUNCHO_KERNEL_MFMA;
+  if (k == 2 && !(n >= 256 && n < 4096 && words < 128)) return FIUNCHO_KERNEL_MFMA_FP4;
   return FIUNCHO_KERNEL_POPCOUNT;
 }
 
@@ -371,11 +372,13 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     J.tiles = shard_tiles(J.row_start.back(), J.shard_count, J.shard_index);
     // pilot sample: 1/32 of the tiles, between 16 and kPilotTiles, for jobs
     // whose search would otherwise start with a flood of candidates (any job
-    // with more combinations than the candidate buffer holds, and every job
-    // of 512 tiles or more); its scores live in the candidate buffer until
-    // the scan
+    // with more combinations than the candidate buffer holds, every job of
+    // 512 tiles or more, and jobs of 64 tiles or more with over 64 times
+    // top_n combinations); its scores live in the candidate buffer until the
+    // scan
     {
-      const bool want = J.total > J.cand_cap || J.tiles >= 512;
+      const bool want = J.total > J.cand_cap || J.tiles >= 512 ||
+                        (J.tiles >= 64 && J.total > 64ull * J.top_n);
       const u64 s = want ? std::min<u64>({J.tiles, (u64)fiuncho::kPilotTiles,
                                           std::max<u64>(16, J.tiles / 32)})
                          : 0;

@@ -111,17 +111,25 @@ __device__ __forceinline__ float current_threshold(const JV &v) {
   return tau - 2.0f * v.fbound;
 }
 
-// Appends every active lane whose score clears the threshold.
-__device__ __forceinline__ void emit(const JV &v, bool active, float est, u64 rank, float thr,
+// The same, read by every lane (no wave-uniform copy): the wave waits for the
+// load only where the value is next used, so a refresh between two scores
+// does not stall.
+__device__ __forceinline__ float current_threshold_lanes(const JV &v) {
+  return __uint_as_float(load_relaxed(&v.st->tau_key)) - 2.0f * v.fbound;
+}
+
+// Appends every active lane whose score clears the threshold; true (in every
+// lane) when the wave appended anything, after which the bound may have risen.
+__device__ __forceinline__ bool emit(const JV &v, bool active, float est, u64 rank, float thr,
                                      uint32_t lane) {
   if (v.pk) {  // pilot: record the score only
     v.pk[lane] = (active && est > 0.f) ? __float_as_uint(est) : 0u;
     v.pk += 64;
-    return;
+    return false;
   }
   const bool keep = active && est >= thr;
   const u64 mask = ballot(keep);
-  if (mask == 0) return;
+  if (mask == 0) return false;
   const uint32_t cnt = popc64(mask);
   const uint32_t leader = __ffsll((long long)mask) - 1;
   u64 base = 0, old = 0;
@@ -142,10 +150,19 @@ __device__ __forceinline__ void emit(const JV &v, bool active, float est, u64 ra
       c.est = est;
       v.cand[idx] = c;
     }
-    atomicAdd(&v.hist[key >> kHistShift], 1u);
+  }
+  // histogram counts: the kept lanes that share the first kept lane's bin
+  // (often most of them) add with one atomic, the others with one each
+  {
+    const uint32_t bin = __float_as_uint(est > 0.f ? est : 0.f) >> kHistShift;
+    const uint32_t b0 = __shfl(bin, leader);
+    const u64 same = mask & ballot(bin == b0);
+    if (lane == leader) atomicAdd(&v.hist[b0], (uint32_t)popc64(same));
+    if (keep && bin != b0) atomicAdd(&v.hist[bin], 1u);
   }
   const u64 qs = v.top_n > 64 ? v.top_n : 64;
   if ((old + cnt) / qs != old / qs) refresh_tau(v.hist, v.st, v.top_n, lane);
+  return true;
 }
 
 // Constants of the score of a job: m * MI starts at f(m) - f(m0) - f(m1).
@@ -165,7 +182,7 @@ __device__ __forceinline__ MiConst mi_const(const JV &v) {
 // Scores a complete table of NC cells x 2 classes and appends it if it may be
 // among the best.
 template <int NC, typename FP>
-__device__ __forceinline__ void score_table(const JV &v, FP F,
+__device__ __forceinline__ bool score_table(const JV &v, FP F,
                                             const uint32_t (&t)[NC][2], bool active, float thr,
                                             const MiConst &mc, u64 rank, uint32_t lane) {
   float fs = mc.c;
@@ -173,7 +190,7 @@ __device__ __forceinline__ void score_table(const JV &v, FP F,
 #pragma unroll
     for (int x = 0; x < NC; ++x) fs += mi_term(F, t[x][0], t[x][1]);
   }
-  emit(v, active, fs * mc.inv_m, rank, thr, lane);
+  return emit(v, active, fs * mc.inv_m, rank, thr, lane);
 }
 
 // 8 u32 of a pair table entry: [ga][gj][c]

@@ -55,9 +55,10 @@ constexpr int kLutCopies = 16;
 
 // Entries of the f table a matrix-core workgroup keeps in LDS (dynamic LDS;
 // jobs with more samples read the table from global memory).  Two
-// workgroups share a compute unit's 160 KB: 64 KB each with FP4 operands, 32
-// KB next to the 32 KB byte table with int8 operands.
-__host__ __device__ constexpr uint32_t mfma_f_entries(bool fp4) { return fp4 ? 16384u : 8192u; }
+// workgroups share a compute unit's 160 KB, 80 KB each with their static
+// LDS: the table holds up to 20,448 entries with FP4 operands and 12,280
+// next to the 32 KB byte table with int8 operands.
+__host__ __device__ constexpr uint32_t mfma_f_entries(bool fp4) { return fp4 ? 20448u : 12280u; }
 
 __device__ __forceinline__ u64 spread8(uint32_t e) {
   const uint32_t lo = ((e & 0xFu) * 0x00204081u) & 0x01010101u;
@@ -267,12 +268,12 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
   // whose a-offset (e mod 4) / 2 equals its own genotype bit, after taking the
   // partner's counts for the other genotype of j.
   const uint32_t gl = lane & 1;
-  const float thr = current_threshold(v);
   const MiConst mc = mi_const(v);
   const FI_GLOBAL uint32_t *marg = as_global(v.marg);
   const uint32_t mcls[2] = {v.m0, v.m1};
   // the scoring reads the f table from the workgroup's LDS copy (LDS_F:
   // it holds this job's table) or from global memory
+  float thr = current_threshold(v);
   auto score = [&](auto F) {
 #pragma unroll
     for (int fb = 0; fb < 2; ++fb) {
@@ -327,7 +328,8 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
           }
           // lexicographic rank of (a, j): sum over a' < a of (n - 1 - a'), plus j - a - 1
           const u64 rank = active ? (u64)a * (n - 1) - (u64)a * (a - 1) / 2 + (j - a - 1) : 0;
-          score_table<9>(v, F, t9, active, thr, mc, rank, lane);
+          // the bound is read again after every append: appends raise it
+          if (score_table<9>(v, F, t9, active, thr, mc, rank, lane)) thr = current_threshold_lanes(v);
         }
       }
     }
@@ -397,7 +399,6 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
   // lane of genotype bit gl scores the prefixes with e / 4 in {2 gl, 2 gl + 1}
   // after taking the partner's counts for the other genotype of j.
   const uint32_t gl = lane & 1;
-  const float thr = current_threshold(v);
   const MiConst mc = mi_const(v);
   const FI_GLOBAL uint32_t *marg = as_global(v.marg);
   const FI_GLOBAL uint32_t *PT = as_global(v.pairs);
@@ -409,6 +410,7 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
     for (int c = 0; c < 2; ++c) Mb[x][c] = marg[(size_t)b * 6 + 2 * x + c];
   // the scoring reads the f table from the workgroup's LDS copy (LDS_F:
   // it holds this job's table) or from global memory
+  float thr = current_threshold(v);
   auto score = [&](auto F) {
 #pragma unroll
     for (int fb = 0; fb < 2; ++fb) {
@@ -460,7 +462,8 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
           }
           const uint32_t pre[2] = {aa, b};
           const u64 rank = active ? lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1) : 0;
-          emit(v, active, fs * mc.inv_m, rank, thr, lane);
+          // the bound is read again after every append: appends raise it
+          if (emit(v, active, fs * mc.inv_m, rank, thr, lane)) thr = current_threshold_lanes(v);
         }
       }
     }

@@ -107,11 +107,14 @@ def test_kernel_choice_table(monkeypatch):
     monkeypatch.delenv("FIUNCHO_ORDER4_TRIPLES", raising=False)
     monkeypatch.delenv("FIUNCHO_ORDER3_MFMA", raising=False)
     L = fiuncho.lib()
-    assert fiuncho.get_kernel(100, 1600, 2) == fiuncho.KERNEL_POPCOUNT
-    assert fiuncho.get_kernel(4000, 16000, 2) == fiuncho.KERNEL_MFMA
-    assert fiuncho.get_kernel(1000, 6400, 3) == fiuncho.KERNEL_PAIRS
-    assert fiuncho.get_kernel(1000, 9000, 3) == fiuncho.KERNEL_MFMA  # 141 words
-    assert fiuncho.get_kernel(300, 17000, 2) == fiuncho.KERNEL_MFMA  # 266 words
+    assert fiuncho.get_kernel(100, 1600, 2) == fiuncho.KERNEL_MFMA_FP4
+    assert fiuncho.get_kernel(4000, 16000, 2) == fiuncho.KERNEL_MFMA_FP4
+    assert fiuncho.get_kernel(1000, 6400, 2) == fiuncho.KERNEL_POPCOUNT  # 100 words
+    assert fiuncho.get_kernel(1000, 9000, 2) == fiuncho.KERNEL_MFMA_FP4  # 141 words
+    assert fiuncho.get_kernel(5000, 1000, 2) == fiuncho.KERNEL_MFMA_FP4
+    assert fiuncho.get_kernel(1000, 6400, 3) == fiuncho.KERNEL_MFMA_FP4
+    assert fiuncho.get_kernel(3, 10, 3) == fiuncho.KERNEL_MFMA_FP4
+    assert fiuncho.get_kernel(300, 17000, 2) == fiuncho.KERNEL_MFMA_FP4  # 266 words
     assert fiuncho.get_kernel(200, 4000, 4) == fiuncho.KERNEL_TRIPLES
     assert fiuncho.get_kernel(5000, 4000, 4) == fiuncho.KERNEL_POPCOUNT  # tables over 16 GiB
     assert fiuncho.get_kernel(100, 4000, 5) == fiuncho.KERNEL_POPCOUNT

@@ -97,10 +97,22 @@ CASES = [
 ]
 
 
+# counting kernels of the small cases: the rule's choice, the popcount kernel
+# (orders 2 and 3 forced off the matrix cores and the pair tables), the
+# order-3 pair-table kernel
+KERNEL_ENV = {"auto": {}, "popcount": {"FIUNCHO_ORDER2_MFMA": "0", "FIUNCHO_ORDER3_PAIRS": "0"},
+              "pairs": {"FIUNCHO_ORDER3_PAIRS": "1"}}
+
+
+@pytest.mark.parametrize("kernel", list(KERNEL_ENV))
 @pytest.mark.parametrize("case", CASES, ids=[f"seed{c[0]}-n{c[1]}-m{c[2]}-k{c[4]}" for c in CASES])
-def test_small_cases(case):
+def test_small_cases(case, kernel, monkeypatch):
     seed, n, m, frac, k, top, mono, dup = case
-    say(f"case: {case}")
+    if kernel == "pairs" and k != 3:
+        pytest.skip("the pair-table kernel serves order 3 only")
+    for name, val in KERNEL_ENV[kernel].items():
+        monkeypatch.setenv(name, val)
+    say(f"case: {case} kernel={kernel}")
     G, y = random_dataset(seed, n, m, frac, mono, dup)
     hits = fiuncho.scan(G, y, k, top)
     check_hits_against_oracle(G, y, k, top, hits)
@@ -188,6 +200,11 @@ def full_size_check(d, n_sample, seed):
 
 def test_order3_main_workload():
     full_size_check(synth.order3_main(), 20000, 31)
+
+
+def test_order3_main_workload_pair_kernel(monkeypatch):
+    monkeypatch.setenv("FIUNCHO_ORDER3_PAIRS", "1")
+    full_size_check(synth.order3_main(), 20000, 34)
 
 
 def test_order2_dense_workload():
@@ -292,8 +309,8 @@ def test_batch_graph_replay():
 
 @pytest.mark.parametrize("pairs", ["0", "1"])
 def test_order3_both_paths(pairs, monkeypatch):
-    """Order 3 through the generic kernel (FIUNCHO_ORDER3_PAIRS=0) and through
-    the inclusion-exclusion kernel with pair tables (default)."""
+    """Order 3 through the generic popcount kernel (FIUNCHO_ORDER3_PAIRS=0)
+    and through the inclusion-exclusion kernel with pair tables (1)."""
     monkeypatch.setenv("FIUNCHO_ORDER3_PAIRS", pairs)
     for seed, n, m, frac in ((40, 67, 321, 0.45), (41, 130, 128, 0.5), (42, 9, 700, 0.2)):
         say(f"case: order3 pairs={pairs} seed={seed} n={n} m={m}")
