@@ -120,8 +120,11 @@ __device__ __forceinline__ float current_threshold_lanes(const JV &v) {
 
 // Appends every active lane whose score clears the threshold; true (in every
 // lane) when the wave appended anything, after which the bound may have risen.
-__device__ __forceinline__ bool emit(const JV &v, bool active, float est, u64 rank, float thr,
-                                     uint32_t lane) {
+// rank_of() gives the lane's combination rank; it is evaluated only by lanes
+// that append.
+template <typename RankOf>
+__device__ __forceinline__ bool emit_with(const JV &v, bool active, float est, RankOf &&rank_of,
+                                          float thr, uint32_t lane) {
   if (v.pk) {  // pilot: record the score only
     v.pk[lane] = (active && est > 0.f) ? __float_as_uint(est) : 0u;
     v.pk += 64;
@@ -145,7 +148,7 @@ __device__ __forceinline__ bool emit(const JV &v, bool active, float est, u64 ra
     const uint32_t key = est > 0.f ? __float_as_uint(est) : 0u;
     if (idx < v.cand_cap) {
       Cand c;
-      c.rank = rank;
+      c.rank = rank_of();
       c.key = key;
       c.est = est;
       v.cand[idx] = c;
@@ -163,6 +166,11 @@ __device__ __forceinline__ bool emit(const JV &v, bool active, float est, u64 ra
   const u64 qs = v.top_n > 64 ? v.top_n : 64;
   if ((old + cnt) / qs != old / qs) refresh_tau(v.hist, v.st, v.top_n, lane);
   return true;
+}
+
+__device__ __forceinline__ bool emit(const JV &v, bool active, float est, u64 rank, float thr,
+                                     uint32_t lane) {
+  return emit_with(v, active, est, [&] { return rank; }, thr, lane);
 }
 
 // Constants of the score of a job: m * MI starts at f(m) - f(m0) - f(m1).

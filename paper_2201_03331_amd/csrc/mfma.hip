@@ -377,7 +377,7 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
       x[2] = qj[o];
       x[3] = qj[o + 64];
     };
-    contract_fp4<3>(load_words, v.W0, v.W1, acc0, acc1);
+    contract_fp4<4>(load_words, v.W0, v.W1, acc0, acc1);
   } else {
     zero_acc(acc0, acc1);
     auto load_words = [&](uint32_t w, u64 (&x)[4]) {
@@ -454,16 +454,36 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
           const Order3Parts parts = {D, ab, aj, bj, Ma, Mb, Mj, mcls};
           float fs = mc.c;
           if (active) {
-            // every count is at most its class size; the clamps keep the table
-            // lookups inside [0, m] whatever the counts hold
+            // the cells in groups of 3, each group's 9 table reads issued
+            // together rather than one cell at a time
+            constexpr int kGroup = 3;
+            uint32_t c0[kGroup], c1[kGroup];
+            int nc = 0;
             walk_order3(parts, [&](uint32_t n0, uint32_t n1) {
-              fs += mi_term(F, min(n0, mcls[0]), min(n1, mcls[1]));
+              // every count is at most its class size; in global memory the
+              // clamps keep the reads inside [0, m] whatever the counts hold
+              // (LDS reads cannot fault)
+              c0[nc] = LDS_F ? n0 : min(n0, mcls[0]);
+              c1[nc] = LDS_F ? n1 : min(n1, mcls[1]);
+              if (++nc == kGroup) {
+                float f0[kGroup], f1[kGroup], f01[kGroup];
+#pragma unroll
+                for (int x = 0; x < kGroup; ++x) {
+                  f0[x] = F[c0[x]];
+                  f1[x] = F[c1[x]];
+                  f01[x] = F[c0[x] + c1[x]];
+                }
+#pragma unroll
+                for (int x = 0; x < kGroup; ++x) fs += (f0[x] + f1[x]) - f01[x];
+                nc = 0;
+              }
             });
           }
           const uint32_t pre[2] = {aa, b};
-          const u64 rank = active ? lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1) : 0;
           // the bound is read again after every append: appends raise it
-          if (emit(v, active, fs * mc.inv_m, rank, thr, lane)) thr = current_threshold_lanes(v);
+          if (emit_with(v, active, fs * mc.inv_m,
+                        [&] { return lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1); }, thr, lane))
+            thr = current_threshold_lanes(v);
         }
       }
     }
