@@ -275,20 +275,32 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
   // it holds this job's table) or from global memory
   float thr = current_threshold(v);
   auto score = [&](auto F) {
+    // the class counts of the lane's two last variants, then per first
+    // variant its class counts once for both
+    uint32_t jv[2], Mj[2][2][2];  // Mj[fb][g][class]
 #pragma unroll
     for (int fb = 0; fb < 2; ++fb) {
-      const uint32_t j = j0 + 16 * fb + (r >> 1);
-      const uint32_t jj = j < n ? j : n - 1;
-      uint32_t Mj[2][2];
+      jv[fb] = j0 + 16 * fb + (r >> 1);
+      const uint32_t jj = jv[fb] < n ? jv[fb] : n - 1;
 #pragma unroll
       for (int gg = 0; gg < 2; ++gg)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) Mj[gg][c] = marg[(size_t)jj * 6 + 2 * gg + c];
+        for (int c = 0; c < 2; ++c) Mj[fb][gg][c] = marg[(size_t)jj * 6 + 2 * gg + c];
+    }
 #pragma unroll
-      for (int fa = 0; fa < 2; ++fa) {
+    for (int fa = 0; fa < 2; ++fa) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint32_t a = a0 + 16 * fa + 4 * q + 2 * h + gl;
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t a = a0 + 16 * fa + 4 * q + 2 * h + gl;
+        const uint32_t aa = a < n ? a : n - 1;
+        uint32_t Ma[2][2];  // [g][class]
+#pragma unroll
+        for (int gg = 0; gg < 2; ++gg)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) Ma[gg][c] = marg[(size_t)aa * 6 + 2 * gg + c];
+#pragma unroll
+        for (int fb = 0; fb < 2; ++fb) {
+          const uint32_t j = jv[fb];
           uint32_t cnt[2][2][2];  // [g_a][g_j][class]
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
@@ -306,30 +318,47 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
             }
           }
           const bool active = a < j && j < n;
-          const uint32_t aa = a < n ? a : n - 1;
-          uint32_t t9[9][2];
+          float fs = mc.c;
+          if (active) {
+            uint32_t t9[9][2];
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const uint32_t Ma0 = marg[(size_t)aa * 6 + c], Ma1 = marg[(size_t)aa * 6 + 2 + c];
-            t9[0][c] = cnt[0][0][c];
-            t9[1][c] = cnt[0][1][c];
-            t9[2][c] = Ma0 - cnt[0][0][c] - cnt[0][1][c];
-            t9[3][c] = cnt[1][0][c];
-            t9[4][c] = cnt[1][1][c];
-            t9[5][c] = Ma1 - cnt[1][0][c] - cnt[1][1][c];
-            t9[6][c] = Mj[0][c] - cnt[0][0][c] - cnt[1][0][c];
-            t9[7][c] = Mj[1][c] - cnt[0][1][c] - cnt[1][1][c];
-            t9[8][c] = mcls[c] - Ma0 - Ma1 - Mj[0][c] - Mj[1][c] + cnt[0][0][c] + cnt[0][1][c] +
-                       cnt[1][0][c] + cnt[1][1][c];
-            // every count is at most the class size; the clamp keeps the table
-            // lookups inside [0, m] whatever the counts hold
+            for (int c = 0; c < 2; ++c) {
+              const uint32_t (&C)[2][2][2] = cnt;
+              t9[0][c] = C[0][0][c];
+              t9[1][c] = C[0][1][c];
+              t9[2][c] = Ma[0][c] - C[0][0][c] - C[0][1][c];
+              t9[3][c] = C[1][0][c];
+              t9[4][c] = C[1][1][c];
+              t9[5][c] = Ma[1][c] - C[1][0][c] - C[1][1][c];
+              t9[6][c] = Mj[fb][0][c] - C[0][0][c] - C[1][0][c];
+              t9[7][c] = Mj[fb][1][c] - C[0][1][c] - C[1][1][c];
+              t9[8][c] = mcls[c] - Ma[0][c] - Ma[1][c] - Mj[fb][0][c] - Mj[fb][1][c] + C[0][0][c] +
+                         C[0][1][c] + C[1][0][c] + C[1][1][c];
+              // every count is at most the class size; in global memory the
+              // clamp keeps the reads inside [0, m] whatever the counts hold
+              // (LDS reads cannot fault)
+              if (!LDS_F) {
 #pragma unroll
-            for (int x = 0; x < 9; ++x) t9[x][c] = active ? min(t9[x][c], mcls[c]) : 0u;
+                for (int x = 0; x < 9; ++x) t9[x][c] = min(t9[x][c], mcls[c]);
+              }
+            }
+            // the 27 table reads issued together
+            float f0[9], f1[9], f01[9];
+#pragma unroll
+            for (int x = 0; x < 9; ++x) {
+              f0[x] = F[t9[x][0]];
+              f1[x] = F[t9[x][1]];
+              f01[x] = F[t9[x][0] + t9[x][1]];
+            }
+#pragma unroll
+            for (int x = 0; x < 9; ++x) fs += (f0[x] + f1[x]) - f01[x];
           }
-          // lexicographic rank of (a, j): sum over a' < a of (n - 1 - a'), plus j - a - 1
-          const u64 rank = active ? (u64)a * (n - 1) - (u64)a * (a - 1) / 2 + (j - a - 1) : 0;
-          // the bound is read again after every append: appends raise it
-          if (score_table<9>(v, F, t9, active, thr, mc, rank, lane)) thr = current_threshold_lanes(v);
+          // the rank is computed by appending lanes only: lexicographic rank of
+          // (a, j) = sum over a' < a of (n - 1 - a'), plus j - a - 1; the
+          // bound is read again after every append (appends raise it)
+          if (emit_with(v, active, fs * mc.inv_m,
+                        [&] { return (u64)a * (n - 1) - (u64)a * (a - 1) / 2 + (j - a - 1); }, thr, lane))
+            thr = current_threshold_lanes(v);
         }
       }
     }
