@@ -118,21 +118,21 @@ __device__ __forceinline__ float current_threshold_lanes(const JV &v) {
   return __uint_as_float(load_relaxed(&v.st->tau_key)) - 2.0f * v.fbound;
 }
 
-// Appends every active lane whose score clears the threshold; true (in every
-// lane) when the wave appended anything, after which the bound may have risen.
-// rank_of() gives the lane's combination rank; it is evaluated only by lanes
-// that append.
+// Appends every active lane whose score clears the threshold and returns the
+// number of lanes that appended (the same in every lane); after appends the
+// bound may have risen.  rank_of() gives the lane's combination rank; it is
+// evaluated only by lanes that append.
 template <typename RankOf>
-__device__ __forceinline__ bool emit_with(const JV &v, bool active, float est, RankOf &&rank_of,
+__device__ __forceinline__ uint32_t emit_with(const JV &v, bool active, float est, RankOf &&rank_of,
                                           float thr, uint32_t lane) {
   if (v.pk) {  // pilot: record the score only
     v.pk[lane] = (active && est > 0.f) ? __float_as_uint(est) : 0u;
     v.pk += 64;
-    return false;
+    return 0;
   }
   const bool keep = active && est >= thr;
   const u64 mask = ballot(keep);
-  if (mask == 0) return false;
+  if (mask == 0) return 0;
   const uint32_t cnt = popc64(mask);
   const uint32_t leader = __ffsll((long long)mask) - 1;
   u64 base = 0, old = 0;
@@ -165,10 +165,10 @@ __device__ __forceinline__ bool emit_with(const JV &v, bool active, float est, R
   }
   const u64 qs = v.top_n > 64 ? v.top_n : 64;
   if ((old + cnt) / qs != old / qs) refresh_tau(v.hist, v.st, v.top_n, lane);
-  return true;
+  return cnt;
 }
 
-__device__ __forceinline__ bool emit(const JV &v, bool active, float est, u64 rank, float thr,
+__device__ __forceinline__ uint32_t emit(const JV &v, bool active, float est, u64 rank, float thr,
                                      uint32_t lane) {
   return emit_with(v, active, est, [&] { return rank; }, thr, lane);
 }
@@ -190,7 +190,7 @@ __device__ __forceinline__ MiConst mi_const(const JV &v) {
 // Scores a complete table of NC cells x 2 classes and appends it if it may be
 // among the best.
 template <int NC, typename FP>
-__device__ __forceinline__ bool score_table(const JV &v, FP F,
+__device__ __forceinline__ uint32_t score_table(const JV &v, FP F,
                                             const uint32_t (&t)[NC][2], bool active, float thr,
                                             const MiConst &mc, u64 rank, uint32_t lane) {
   float fs = mc.c;

@@ -53,6 +53,11 @@ static_assert(kMfmaWaves == kScanWaves, "pilot slots and tile decoding assume eq
 // so that the 16 lanes an LDS cycle serves always hit distinct banks.
 constexpr int kLutCopies = 16;
 
+// A wave reads the bound again within a tile after an emit in which this many
+// lanes appended (a flood: the bound it holds is far below the current one);
+// otherwise once per tile.
+constexpr uint32_t kRefreshAppends = 16;
+
 // Entries of the f table a matrix-core workgroup keeps in LDS (dynamic LDS;
 // jobs with more samples read the table from global memory).  Two
 // workgroups share a compute unit's 160 KB, 80 KB each with their static
@@ -354,10 +359,10 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
             for (int x = 0; x < 9; ++x) fs += (f0[x] + f1[x]) - f01[x];
           }
           // the rank is computed by appending lanes only: lexicographic rank of
-          // (a, j) = sum over a' < a of (n - 1 - a'), plus j - a - 1; the
-          // bound is read again after every append (appends raise it)
+          // (a, j) = sum over a' < a of (n - 1 - a'), plus j - a - 1
           if (emit_with(v, active, fs * mc.inv_m,
-                        [&] { return (u64)a * (n - 1) - (u64)a * (a - 1) / 2 + (j - a - 1); }, thr, lane))
+                        [&] { return (u64)a * (n - 1) - (u64)a * (a - 1) / 2 + (j - a - 1); }, thr,
+                        lane) >= kRefreshAppends)
             thr = current_threshold_lanes(v);
         }
       }
@@ -509,9 +514,9 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
             });
           }
           const uint32_t pre[2] = {aa, b};
-          // the bound is read again after every append: appends raise it
           if (emit_with(v, active, fs * mc.inv_m,
-                        [&] { return lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1); }, thr, lane))
+                        [&] { return lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1); }, thr,
+                        lane) >= kRefreshAppends)
             thr = current_threshold_lanes(v);
         }
       }
