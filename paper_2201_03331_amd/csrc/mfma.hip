@@ -99,19 +99,23 @@ __device__ __forceinline__ v4i expand16(const u64 *lut, uint32_t b) {
 // the 16 samples [16 (l / 32), 16 (l / 32) + 16) of each 32-sample step; the
 // matrix instruction pairs the same lane half and byte of both operands, so
 // any fixed sample order inside a lane is exact.
-template <int kDepth, typename Load>
-__device__ __forceinline__ void mfma_class(Load &&load_words, uint32_t wbeg, uint32_t wend,
-                                           uint32_t h, const u64 *lut, v16i (&acc)[2][2]) {
+template <int kDepth, int kRaw, typename Load, typename Prep>
+__device__ __forceinline__ void mfma_class(Load &&load_words, Prep &&prep, uint32_t wbeg,
+                                           uint32_t wend, uint32_t h, const u64 *lut,
+                                           v16i (&acc)[2][2]) {
   if (wbeg >= wend) return;
-  // the rows of the next kDepth words are in flight in a register ring (the
-  // depth is what the kernel's register budget allows);
-  // load_words(w, x) fills x with the lane's words of both A fragments and
-  // both B fragments
+  // the loads of the next kDepth words are in flight in a register ring (the
+  // depth is what the kernel's register budget allows): load_words(w, x)
+  // fills x with the kRaw words the lane loads for word w, and prep(x, o)
+  // makes the lane's words of both A and both B fragments from them when the
+  // word is used (so no load is waited for early)
   const uint32_t wlast = wend - 1;
-  u64 X[kDepth][4];
+  u64 X[kDepth][kRaw];
 #pragma unroll
   for (int u = 0; u < kDepth; ++u) load_words(min(wbeg + u, wlast), X[u]);
   auto step = [&](int slot) {
+    u64 O[4];
+    prep(X[slot], O);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       // 16 samples of this lane half: bits [16 h, 16 h + 16) of the 32-bit half s
@@ -121,7 +125,7 @@ __device__ __forceinline__ void mfma_class(Load &&load_words, uint32_t wbeg, uin
       v4i E[4];
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        const uint32_t half = s ? (uint32_t)(X[slot][f] >> 32) : (uint32_t)X[slot][f];
+        const uint32_t half = s ? (uint32_t)(O[f] >> 32) : (uint32_t)O[f];
         const uint32_t bits = __builtin_amdgcn_ubfe(half, 16 * h, 16);
         E[f] = f < 2 ? expand16(lut, bits) : expand16_alu(bits);
       }
@@ -160,21 +164,23 @@ __device__ __forceinline__ v8i expand32_fp4(uint32_t b) {
 
 // Counts of one class with FP4 operands: words [wbeg, wend).  Lane l feeds
 // row l mod 32 of every fragment and the 32 samples of 32-bit half l / 32 of
-// each word (load_words(w, x) fills x with the lane's half words of both A
-// and both B fragments); the instruction pairs the same lane half and nibble
-// of both operands.
-template <int kDepth, typename Load>
-__device__ __forceinline__ void mfma_class_fp4(Load &&load_words, uint32_t wbeg, uint32_t wend,
-                                               v16f (&acc)[2][2]) {
+// each word (load_words and prep as for int8 operands, on the lane's half
+// words); the instruction pairs the same lane half and nibble of both
+// operands.
+template <int kDepth, int kRaw, typename Load, typename Prep>
+__device__ __forceinline__ void mfma_class_fp4(Load &&load_words, Prep &&prep, uint32_t wbeg,
+                                               uint32_t wend, v16f (&acc)[2][2]) {
   if (wbeg >= wend) return;
   const uint32_t wlast = wend - 1;
-  uint32_t X[kDepth][4];
+  uint32_t X[kDepth][kRaw];
 #pragma unroll
   for (int u = 0; u < kDepth; ++u) load_words(min(wbeg + u, wlast), X[u]);
   auto step = [&](int slot) {
+    uint32_t O[4];
+    prep(X[slot], O);
     v8i E[4];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) E[f] = expand32_fp4(X[slot][f]);
+    for (int f = 0; f < 4; ++f) E[f] = expand32_fp4(O[f]);
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -207,8 +213,8 @@ __device__ __forceinline__ void zero_acc(v16i (&acc0)[2][2], v16i (&acc1)[2][2])
 
 // Both classes with FP4 operands (class 0: words [0, W0), class 1: the next
 // W1), counts returned as integers: the FP32 sums are integers below 2^24
-template <int kDepth, typename Load>
-__device__ __forceinline__ void contract_fp4(Load &&load_words, uint32_t W0, uint32_t W1,
+template <int kDepth, int kRaw, typename Load, typename Prep>
+__device__ __forceinline__ void contract_fp4(Load &&load_words, Prep &&prep, uint32_t W0, uint32_t W1,
                                              v16i (&acc0)[2][2], v16i (&acc1)[2][2]) {
   v16f f0[2][2], f1[2][2];
 #pragma unroll
@@ -217,8 +223,8 @@ __device__ __forceinline__ void contract_fp4(Load &&load_words, uint32_t W0, uin
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) f0[x][y][e] = f1[x][y][e] = 0.f;
-  mfma_class_fp4<kDepth>(load_words, 0, W0, f0);
-  mfma_class_fp4<kDepth>(load_words, W0, W0 + W1, f1);
+  mfma_class_fp4<kDepth, kRaw>(load_words, prep, 0, W0, f0);
+  mfma_class_fp4<kDepth, kRaw>(load_words, prep, W0, W0 + W1, f1);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -252,7 +258,11 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
       x[2] = qj[o];
       x[3] = qj[o + 64];
     };
-    contract_fp4<4>(load_words, v.W0, v.W1, acc0, acc1);
+    auto prep = [](const uint32_t (&x)[4], uint32_t (&o)[4]) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f) o[f] = x[f];
+    };
+    contract_fp4<4, 4>(load_words, prep, v.W0, v.W1, acc0, acc1);
   } else {
     zero_acc(acc0, acc1);
     auto load_words = [&](uint32_t w, u64 (&x)[4]) {
@@ -262,8 +272,12 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
       x[2] = pj[o];
       x[3] = pj[o + 32];
     };
-    mfma_class<3>(load_words, 0, v.W0, h, lut, acc0);
-    mfma_class<3>(load_words, v.W0, v.W0 + v.W1, h, lut, acc1);
+    auto prep = [](const u64 (&x)[4], u64 (&o)[4]) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f) o[f] = x[f];
+    };
+    mfma_class<3, 4>(load_words, prep, 0, v.W0, h, lut, acc0);
+    mfma_class<3, 4>(load_words, prep, v.W0, v.W0 + v.W1, h, lut, acc1);
   }
 
   // Output block layout: lane l holds column l mod 32 (variant j0' + (l mod
@@ -383,16 +397,15 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
   const FI_GLOBAL u64 *Bv = as_global(v.Bv);
   const FI_GLOBAL u64 *Bs = as_global(v.Bs);
   // A rows: lane r of fragment f is prefix a_first + 8 f + r / 4 with genotype
-  // rows g_a = (r >> 1) & 1, g_b = r & 1; prefixes a >= b count nothing
+  // rows g_a = (r >> 1) & 1, g_b = r & 1; prefixes a >= b count nothing: their
+  // lanes read the zero word that follows the three genotype words
   const uint32_t ga = (r >> 1) & 1, gb = r & 1;
   const FI_GLOBAL u64 *pb = Bs + (size_t)b * 4 * v.wcap + gb;
   const FI_GLOBAL u64 *pa[2];
-  u64 amask[2];
 #pragma unroll
   for (int f = 0; f < 2; ++f) {
     const uint32_t a = a_first + 8 * f + (r >> 2);
-    pa[f] = Bs + (size_t)min(a, b - 1) * 4 * v.wcap + ga;
-    amask[f] = a < b ? ~0ull : 0ull;
+    pa[f] = Bs + (size_t)min(a, b - 1) * 4 * v.wcap + (a < b ? ga : 3);
   }
   const FI_GLOBAL u64 *pj = Bv + (size_t)j0 * 2 + r;
   v16i acc0[2][2], acc1[2][2];
@@ -401,29 +414,41 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
     typedef const FI_GLOBAL uint32_t *q32;
     const q32 qb = reinterpret_cast<q32>(pb) + h;
     const q32 qa0 = reinterpret_cast<q32>(pa[0]) + h, qa1 = reinterpret_cast<q32>(pa[1]) + h;
-    const uint32_t m0 = (uint32_t)amask[0], m1 = (uint32_t)amask[1];
     const q32 qj = reinterpret_cast<q32>(pj) + h;
-    auto load_words = [&](uint32_t w, uint32_t (&x)[4]) {
-      const uint32_t wb = qb[(size_t)w * 8];
-      x[0] = qa0[(size_t)w * 8] & wb & m0;
-      x[1] = qa1[(size_t)w * 8] & wb & m1;
+    auto load_words = [&](uint32_t w, uint32_t (&x)[5]) {
+      x[0] = qa0[(size_t)w * 8];
+      x[1] = qa1[(size_t)w * 8];
       const size_t o = (size_t)w * word_stride * 2;
       x[2] = qj[o];
       x[3] = qj[o + 64];
+      x[4] = qb[(size_t)w * 8];
     };
-    contract_fp4<4>(load_words, v.W0, v.W1, acc0, acc1);
+    // A row = row of a AND row of b
+    auto prep = [](const uint32_t (&x)[5], uint32_t (&o)[4]) {
+      o[0] = x[0] & x[4];
+      o[1] = x[1] & x[4];
+      o[2] = x[2];
+      o[3] = x[3];
+    };
+    contract_fp4<4, 5>(load_words, prep, v.W0, v.W1, acc0, acc1);
   } else {
     zero_acc(acc0, acc1);
-    auto load_words = [&](uint32_t w, u64 (&x)[4]) {
-      const u64 wb = pb[(size_t)w * 4];
-      x[0] = pa[0][(size_t)w * 4] & wb & amask[0];
-      x[1] = pa[1][(size_t)w * 4] & wb & amask[1];
+    auto load_words = [&](uint32_t w, u64 (&x)[5]) {
+      x[0] = pa[0][(size_t)w * 4];
+      x[1] = pa[1][(size_t)w * 4];
       const size_t o = (size_t)w * word_stride;
       x[2] = pj[o];
       x[3] = pj[o + 32];
+      x[4] = pb[(size_t)w * 4];
     };
-    mfma_class<3>(load_words, 0, v.W0, h, lut, acc0);
-    mfma_class<3>(load_words, v.W0, v.W0 + v.W1, h, lut, acc1);
+    auto prep = [](const u64 (&x)[5], u64 (&o)[4]) {
+      o[0] = x[0] & x[4];
+      o[1] = x[1] & x[4];
+      o[2] = x[2];
+      o[3] = x[3];
+    };
+    mfma_class<3, 5>(load_words, prep, 0, v.W0, h, lut, acc0);
+    mfma_class<3, 5>(load_words, prep, v.W0, v.W0 + v.W1, h, lut, acc1);
   }
 
   // Output block (f, fb): lane l holds column l mod 32 (last variant j0 + 16 fb
