@@ -149,6 +149,17 @@ __device__ __forceinline__ void mfma_class(Load &&load_words, Prep &&prep, uint3
     if (w + u < wend) step(u);
 }
 
+// 32-bit load at a wave-uniform base plus a lane offset, as a raw buffer
+// load: the base becomes a buffer descriptor in scalar registers (built by
+// scalar arithmetic for every word) and the lane offset stays one 32-bit
+// vector register, so no per-lane 64-bit address arithmetic is needed
+constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit buffer of gfx9-class GPUs
+__device__ __forceinline__ uint32_t ld32(const FI_GLOBAL char *base, uint32_t off) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, 0x7fffffff, kBufferWord3);
+  return __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
+}
+
 // 32 sample bits -> the 32 FP4 operand values of one lane.  E2M1 1.0 is the
 // nibble 0b0010, so register d takes bit 4p + d of b to bit 1 of nibble p;
 // only the low four registers are read for FP4 operands.
@@ -248,15 +259,19 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
   const FI_GLOBAL u64 *pj = Bv + (size_t)j0 * 2 + r;
   v16i acc0[2][2], acc1[2][2];
   if constexpr (F4) {
-    // the lane's 32-bit half of each word
-    const FI_GLOBAL uint32_t *qa = reinterpret_cast<const FI_GLOBAL uint32_t *>(pa) + h;
-    const FI_GLOBAL uint32_t *qj = reinterpret_cast<const FI_GLOBAL uint32_t *>(pj) + h;
+    // the lane's 32-bit half of each word: wave-uniform bases of the
+    // fragments' words (advanced by scalar arithmetic) plus a 32-bit lane
+    // offset
+    const FI_GLOBAL char *Bvc = reinterpret_cast<const FI_GLOBAL char *>(Bv);
+    const size_t word_bytes = (size_t)v.n_pad * 16;  // one word of every variant
+    const uint32_t ol = r * 8 + 4 * h;
     auto load_words = [&](uint32_t w, uint32_t (&x)[4]) {
-      const size_t o = (size_t)w * word_stride * 2;
-      x[0] = qa[o];
-      x[1] = qa[o + 64];
-      x[2] = qj[o];
-      x[3] = qj[o + 64];
+      const FI_GLOBAL char *sa = Bvc + (size_t)w * word_bytes + (size_t)a0 * 16;
+      const FI_GLOBAL char *sj = Bvc + (size_t)w * word_bytes + (size_t)j0 * 16;
+      x[0] = ld32(sa, ol);
+      x[1] = ld32(sa, ol + 256);
+      x[2] = ld32(sj, ol);
+      x[3] = ld32(sj, ol + 256);
     };
     auto prep = [](const uint32_t (&x)[4], uint32_t (&o)[4]) {
 #pragma unroll
@@ -410,18 +425,28 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
   const FI_GLOBAL u64 *pj = Bv + (size_t)j0 * 2 + r;
   v16i acc0[2][2], acc1[2][2];
   if constexpr (F4) {
-    // the lane's 32-bit half of each word
-    typedef const FI_GLOBAL uint32_t *q32;
-    const q32 qb = reinterpret_cast<q32>(pb) + h;
-    const q32 qa0 = reinterpret_cast<q32>(pa[0]) + h, qa1 = reinterpret_cast<q32>(pa[1]) + h;
-    const q32 qj = reinterpret_cast<q32>(pj) + h;
+    // the lane's 32-bit half of each word: wave-uniform bases (the prefix
+    // block's first variant, b, the last variants' block) advanced by scalar
+    // arithmetic, plus 32-bit lane offsets (a prefix block spans at most 16
+    // variants of Bs)
+    const FI_GLOBAL char *Bsc = reinterpret_cast<const FI_GLOBAL char *>(Bs);
+    const FI_GLOBAL char *Bvc = reinterpret_cast<const FI_GLOBAL char *>(Bv);
+    const size_t vrow = (size_t)v.wcap * 32;         // Bs bytes of one variant
+    const size_t word_bytes = (size_t)v.n_pad * 16;  // Bv bytes of one word
+    uint32_t oa[2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+      oa[f] = (uint32_t)((const FI_GLOBAL char *)pa[f] - (Bsc + (size_t)a_first * vrow)) + 4 * h;
+    const uint32_t ob = gb * 8 + 4 * h, ol = r * 8 + 4 * h;
     auto load_words = [&](uint32_t w, uint32_t (&x)[5]) {
-      x[0] = qa0[(size_t)w * 8];
-      x[1] = qa1[(size_t)w * 8];
-      const size_t o = (size_t)w * word_stride * 2;
-      x[2] = qj[o];
-      x[3] = qj[o + 64];
-      x[4] = qb[(size_t)w * 8];
+      const FI_GLOBAL char *sa = Bsc + (size_t)a_first * vrow + (size_t)w * 32;
+      const FI_GLOBAL char *sb = Bsc + (size_t)b * vrow + (size_t)w * 32;
+      const FI_GLOBAL char *sj = Bvc + (size_t)w * word_bytes + (size_t)j0 * 16;
+      x[0] = ld32(sa, oa[0]);
+      x[1] = ld32(sa, oa[1]);
+      x[2] = ld32(sj, ol);
+      x[3] = ld32(sj, ol + 256);
+      x[4] = ld32(sb, ob);
     };
     // A row = row of a AND row of b
     auto prep = [](const uint32_t (&x)[5], uint32_t (&o)[4]) {
