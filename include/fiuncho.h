@@ -248,10 +248,11 @@ const char *fiuncho_last_error(void);
  * calls made on this thread with profiling enabled since the last
  * fiuncho_get_profile; see fiuncho_set_profiling. */
 typedef struct {
-  float pack_ms;      /* class partition, bit packing (and order-3 pair tables) */
+  float pack_ms;      /* class partition, bit packing (and pair / triple tables) */
   float pilot_ms;     /* pilot sample: scores of a sample of tiles, starting bound */
   float scan_ms;      /* popcount counting kernel + FP32 estimate + candidate filter */
-  float mfma_ms;      /* matrix-core order-2 kernel + FP32 estimate + candidate filter */
+  float mfma_ms;      /* matrix-core kernels (orders 2 and 3, int8 and FP4) + FP32
+                         estimate + candidate filter */
   float select_ms;    /* candidate selection, FP64 rescoring, final order */
   float total_ms;     /* all of the above, first kernel start to last kernel end */
   uint32_t calls;        /* profiled calls averaged */
