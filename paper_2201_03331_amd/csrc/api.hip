@@ -309,11 +309,13 @@ struct JobLayout {
   double cost;  // per-tile cost estimate, for ordering
 };
 
-// matrix-core launch group of a job (order 2 int8, order 2 FP4, order 3
-// int8, order 3 FP4), -1 for the popcount kernel
+// matrix-core launch group of a job: 3 (order - 2) + operand format (0
+// int8, 1 FP4, 2 FP4 with at most mfma_narrow_max_samples() samples, run by
+// the kernel variant that keeps counts in 16 bits); -1 for the popcount kernel
 int mfma_group(const JobLayout &J) {
   if (!on_matrix_cores(J.path)) return -1;
-  return 2 * (J.path == fiuncho::kPathMfma3 ? 1 : 0) + (J.fp4 ? 1 : 0);
+  const int fmt = !J.fp4 ? 0 : J.m <= fiuncho::mfma_narrow_max_samples() ? 2 : 1;
+  return 3 * (J.path == fiuncho::kPathMfma3 ? 1 : 0) + fmt;
 }
 
 struct Layout {
@@ -770,11 +772,11 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   auto counting = [&](const Globals &c, int q) {
     if (c.total_tiles <= c.tile_base) return;
     const u64 tiles = c.total_tiles - c.tile_base;
-    const int order = 2 + q / 2;
-    const bool fp4 = q % 2 == 1;
-    const int gmax = q >= 0 ? fiuncho::mfma_grid_size(order, fp4) : fiuncho::scan_grid_size(L.ksel);
+    const int order = 2 + q / 3;
+    const int fmt = q % 3;
+    const int gmax = q >= 0 ? fiuncho::mfma_grid_size(order, fmt) : fiuncho::scan_grid_size(L.ksel);
     const int grid = (int)std::min<u64>((u64)gmax, tiles);
-    if (q >= 0) fiuncho::launch_mfma(c, order, fp4, grid, s);
+    if (q >= 0) fiuncho::launch_mfma(c, order, fmt, grid, s);
     else fiuncho::launch_scan(c, L.ksel, grid, s);
   };
   // the matrix-core groups' launches over their jobs; counters 2 + 2q (counting)

@@ -34,9 +34,9 @@ constexpr uint32_t kPathMfma2 = 2;            // order 2 on the matrix cores (mf
 constexpr uint32_t kPathTriples = 3;          // order 4, {0,1}^4 cells + triple and pair tables
 constexpr uint32_t kPathMfma3 = 4;            // order 3 on the matrix cores (mfma_kernel<3>)
 constexpr int kSelTriples = 41;               // scan_kernel selector: order-4 triple-table path only
-// matrix-core launch groups, in tile-space order: order 2 with int8 and with
-// FP4 operands, then order 3 with int8 and with FP4 operands
-constexpr int kMfmaGroups = 4;
+// matrix-core launch groups, in tile-space order: order 2 with int8, FP4 and
+// narrow FP4 operands, then order 3 likewise (group = 3 (order - 2) + format)
+constexpr int kMfmaGroups = 6;
 // tile counters: the popcount kernel and its pilot, then each matrix-core
 // group's counting launch and its pilot
 constexpr int kTileCounters = 2 + 2 * kMfmaGroups;
@@ -143,8 +143,11 @@ void launch_pack(const Globals &g, uint32_t max_n_pad, uint32_t max_wcap, hipStr
 void launch_pairs(const Globals &g, uint32_t max_n, hipStream_t s);
 void launch_triples(const Globals &g, uint32_t max_n, hipStream_t s);
 void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s);
-void launch_mfma(const Globals &g, int order, bool fp4, int grid, hipStream_t s);
-int mfma_grid_size(int order, bool fp4);
+// fmt: 0 int8, 1 FP4, 2 narrow FP4 (jobs of at most mfma_narrow_max_samples()
+// samples: table in LDS, counts in 16 bits)
+void launch_mfma(const Globals &g, int order, int fmt, int grid, hipStream_t s);
+int mfma_grid_size(int order, int fmt);
+uint32_t mfma_narrow_max_samples();
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
 void launch_pilot_select(const Globals &g, uint32_t max_pilot_slots, hipStream_t s);
 void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s);

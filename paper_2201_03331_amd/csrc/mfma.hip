@@ -58,12 +58,20 @@ constexpr int kLutCopies = 16;
 // otherwise once per tile.
 constexpr uint32_t kRefreshAppends = 16;
 
+// Operand formats of the matrix-core kernels: int8; FP4; FP4 for jobs whose
+// f table fits in LDS ("narrow": their class counts fit 16 bits, so class-0
+// counts wait as 16-bit pairs while class 1 accumulates, and both classes of
+// a cell share one register afterwards: half the registers for finished
+// counts and one exchange between partner lanes instead of two).
+constexpr int kMfmaI8 = 0, kMfmaF4 = 1, kMfmaF4Narrow = 2;
+
 // Entries of the f table a matrix-core workgroup keeps in LDS (dynamic LDS;
 // jobs with more samples read the table from global memory).  Two
 // workgroups share a compute unit's 160 KB, 80 KB each with their static
-// LDS: the table holds up to 20,448 entries with FP4 operands and 12,280
-// next to the 32 KB byte table with int8 operands.
-__host__ __device__ constexpr uint32_t mfma_f_entries(bool fp4) { return fp4 ? 20448u : 12280u; }
+// LDS: up to 12,280 entries next to the 32 KB byte table with int8 operands,
+// 20,448 with FP4 operands (every job of a narrow launch has at most 20,447
+// samples).
+__host__ __device__ constexpr uint32_t mfma_f_entries(int fmt) { return fmt == kMfmaI8 ? 12280u : 20448u; }
 
 __device__ __forceinline__ u64 spread8(uint32_t e) {
   const uint32_t lo = ((e & 0xFu) * 0x00204081u) & 0x01010101u;
@@ -247,8 +255,78 @@ __device__ __forceinline__ void contract_fp4(Load &&load_words, Prep &&prep, uin
       }
 }
 
+// Both classes with FP4 operands for the narrow kernels: counts of at most 16
+// bits.  Class 0's counts wait as 16-bit pairs while class 1 accumulates;
+// the result Q holds class 0 in the low and class 1 in the high 16 bits of
+// each output element (register e of block (x, y)).
+template <int kDepth, int kRaw, typename Load, typename Prep>
+__device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Prep &&prep, uint32_t W0,
+                                                    uint32_t W1, uint32_t (&Q)[2][2][16]) {
+  v16f f[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) f[x][y][e] = 0.f;
+  mfma_class_fp4<kDepth, kRaw>(load_words, prep, 0, W0, f);
+  uint32_t P0[2][2][8];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        P0[x][y][i] = (uint32_t)f[x][y][2 * i] | ((uint32_t)f[x][y][2 * i + 1] << 16);
+        f[x][y][2 * i] = f[x][y][2 * i + 1] = 0.f;
+      }
+  mfma_class_fp4<kDepth, kRaw>(load_words, prep, W0, W0 + W1, f);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        Q[x][y][e] = ((P0[x][y][e >> 1] >> (16 * (e & 1))) & 0xFFFFu) | ((uint32_t)f[x][y][e] << 16);
+}
+
+// Counts of the lane's combination from output registers elo (the lane's own
+// genotype row gl of the last variant, if gl = 0) and ehi (if gl = 1) of
+// block (x, y): o[class][g_j] after taking the partner lane's (l ^ 1) counts
+// for the other genotype of j.  Static register indices only: a
+// lane-dependent index into a register array becomes a compare-and-select
+// over every element.
+template <int FMT>
+__device__ __forceinline__ void partner_counts(const v16i (&acc0)[2][2], const v16i (&acc1)[2][2],
+                                               const uint32_t (&Q)[2][2][16], int x, int y, int elo,
+                                               int ehi, uint32_t gl, uint32_t (&o)[2][2]) {
+  if constexpr (FMT == kMfmaF4Narrow) {
+    // both classes in one register: one exchange
+    const uint32_t lo = Q[x][y][elo], hi = Q[x][y][ehi];
+    const uint32_t own = gl ? hi : lo;
+    const uint32_t send = gl ? lo : hi;
+    const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
+    const uint32_t g0 = gl ? recv : own, g1 = gl ? own : recv;
+    o[0][0] = g0 & 0xFFFFu;
+    o[1][0] = g0 >> 16;
+    o[0][1] = g1 & 0xFFFFu;
+    o[1][1] = g1 >> 16;
+  } else {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const v16i &A = c == 0 ? acc0[x][y] : acc1[x][y];
+      const uint32_t lo = (uint32_t)A[elo], hi = (uint32_t)A[ehi];
+      const uint32_t own = gl ? hi : lo;
+      const uint32_t send = gl ? lo : hi;
+      const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
+      o[c][0] = gl ? recv : own;
+      o[c][1] = gl ? own : recv;
+    }
+  }
+}
+
 // One wave: pairs (a0 + [0, 32)) x (j0 + [0, 32)).
-template <bool F4, bool LDS_F>
+template <int FMT, bool LDS_F>
 __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0, uint32_t lane,
                                            const u64 *lut, const FI_LDS float *Fl) {
   const uint32_t n = v.n;
@@ -257,8 +335,9 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
   const FI_GLOBAL u64 *Bv = as_global(v.Bv);
   const FI_GLOBAL u64 *pa = Bv + (size_t)a0 * 2 + r;
   const FI_GLOBAL u64 *pj = Bv + (size_t)j0 * 2 + r;
-  v16i acc0[2][2], acc1[2][2];
-  if constexpr (F4) {
+  v16i acc0[2][2], acc1[2][2];  // int8, FP4: counts per class
+  uint32_t Q[2][2][16];         // narrow FP4: both classes per register
+  if constexpr (FMT != kMfmaI8) {
     // the lane's 32-bit half of each word: wave-uniform bases of the
     // fragments' words (advanced by scalar arithmetic) plus a 32-bit lane
     // offset
@@ -277,7 +356,8 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
 #pragma unroll
       for (int f = 0; f < 4; ++f) o[f] = x[f];
     };
-    contract_fp4<4, 4>(load_words, prep, v.W0, v.W1, acc0, acc1);
+    if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<4, 4>(load_words, prep, v.W0, v.W1, Q);
+    else contract_fp4<4, 4>(load_words, prep, v.W0, v.W1, acc0, acc1);
   } else {
     zero_acc(acc0, acc1);
     auto load_words = [&](uint32_t w, u64 (&x)[4]) {
@@ -337,18 +417,13 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
           const uint32_t j = jv[fb];
           uint32_t cnt[2][2][2];  // [g_a][g_j][class]
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const v16i &A = c == 0 ? acc0[fa][fb] : acc1[fa][fb];
+          for (int t = 0; t < 2; ++t) {
+            uint32_t o[2][2];
+            partner_counts<FMT>(acc0, acc1, Q, fa, fb, 4 * q + t, 4 * q + 2 + t, gl, o);
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-              const uint32_t lo = (uint32_t)A[4 * q + t], hi = (uint32_t)A[4 * q + 2 + t];
-              const uint32_t own = gl ? hi : lo;
-              const uint32_t send = gl ? lo : hi;
-              const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
-              // static indices only: a lane-dependent index into a register
-              // array becomes a compare-and-select over every element
-              cnt[t][0][c] = gl ? recv : own;
-              cnt[t][1][c] = gl ? own : recv;
+            for (int c = 0; c < 2; ++c) {
+              cnt[t][0][c] = o[c][0];
+              cnt[t][1][c] = o[c][1];
             }
           }
           const bool active = a < j && j < n;
@@ -402,7 +477,7 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
 }
 
 // One wave: prefixes (a_first + [0, 16), b) x last variants (j0 + [0, 32)).
-template <bool F4, bool LDS_F>
+template <int FMT, bool LDS_F>
 __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint32_t b,
                                              uint32_t a_first, uint32_t j0, uint32_t lane,
                                              const u64 *lut, const FI_LDS float *Fl) {
@@ -423,8 +498,9 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
     pa[f] = Bs + (size_t)min(a, b - 1) * 4 * v.wcap + (a < b ? ga : 3);
   }
   const FI_GLOBAL u64 *pj = Bv + (size_t)j0 * 2 + r;
-  v16i acc0[2][2], acc1[2][2];
-  if constexpr (F4) {
+  v16i acc0[2][2], acc1[2][2];  // int8, FP4: counts per class
+  uint32_t Q[2][2][16];         // narrow FP4: both classes per register
+  if constexpr (FMT != kMfmaI8) {
     // the lane's 32-bit half of each word: wave-uniform bases (the prefix
     // block's first variant, b, the last variants' block) advanced by scalar
     // arithmetic, plus 32-bit lane offsets (a prefix block spans at most 16
@@ -455,7 +531,8 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
       o[2] = x[2];
       o[3] = x[3];
     };
-    contract_fp4<4, 5>(load_words, prep, v.W0, v.W1, acc0, acc1);
+    if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<4, 5>(load_words, prep, v.W0, v.W1, Q);
+    else contract_fp4<4, 5>(load_words, prep, v.W0, v.W1, acc0, acc1);
   } else {
     zero_acc(acc0, acc1);
     auto load_words = [&](uint32_t w, u64 (&x)[5]) {
@@ -514,16 +591,13 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
           const uint32_t a = a_first + 8 * f + 2 * (2 * gl + t) + h;
           uint32_t D[2][2][2][2];  // [class][g_a][g_b][g_j]
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const v16i &A = c == 0 ? acc0[f][fb] : acc1[f][fb];
+          for (int i = 0; i < 4; ++i) {
+            uint32_t o[2][2];
+            partner_counts<FMT>(acc0, acc1, Q, f, fb, 4 * t + i, 4 * (2 + t) + i, gl, o);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const uint32_t lo = (uint32_t)A[4 * t + i], hi = (uint32_t)A[4 * (2 + t) + i];
-              const uint32_t own = gl ? hi : lo;
-              const uint32_t send = gl ? lo : hi;
-              const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
-              D[c][i >> 1][i & 1][0] = gl ? recv : own;
-              D[c][i >> 1][i & 1][1] = gl ? own : recv;
+            for (int c = 0; c < 2; ++c) {
+              D[c][i >> 1][i & 1][0] = o[c][0];
+              D[c][i >> 1][i & 1][1] = o[c][1];
             }
           }
           const bool active = a < b && j < n;
@@ -576,14 +650,15 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
   else score(as_global(v.Fh));
 }
 
-// ORDER 2 or 3, F4: FP4 (else int8) operands; the kernel serves the jobs of
-// that order and operand format (a batch with several launches it once per
-// group, each over the group's tiles)
-template <int ORDER, bool F4>
+// ORDER 2 or 3, FMT: operand format (kMfmaI8, kMfmaF4, kMfmaF4Narrow); the
+// kernel serves the jobs of that order and format (a batch with several
+// launches it once per group, each over the group's tiles)
+template <int ORDER, int FMT>
 __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
+  constexpr bool F4 = FMT != kMfmaI8;
   __shared__ u64 s_tile;
   __shared__ u64 s_lut[F4 ? 1 : 256 * kLutCopies];
-  // the f table of the current job, when it has at most mfma_f_entries(F4)
+  // the f table of the current job, when it has at most mfma_f_entries(FMT)
   // entries (dynamic LDS of that size)
   extern __shared__ float s_f[];
   const uint32_t lane = lane_id();
@@ -607,7 +682,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
       if (jx != f_job) {
         const FI_CONST JobDesc *J = as_const(g.jobs) + jx;
         const uint32_t entries = uni(J->m) + 1;
-        f_lds = entries <= mfma_f_entries(F4);
+        f_lds = entries <= mfma_f_entries(FMT);
         if (f_lds) {
           const FI_GLOBAL float *Fh = as_global(uni_ptr(J->Fh));
           for (uint32_t i = threadIdx.x; i < entries; i += blockDim.x) s_f[i] = Fh[i];
@@ -621,6 +696,9 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
     u64 lt;
     if (!locate_tile(g, t, wave, kMfmaPilotEmits, v, jd, lt)) continue;
     if (v.fp4 != (F4 ? 1u : 0u)) continue;
+    // the narrow kernel needs the table in LDS (and so counts below 2^16);
+    // the host gives it no other job
+    if (FMT == kMfmaF4Narrow && !f_lds) continue;
     cu64p rows = as_const(uni_ptr(jd->row_start));
     uint32_t rl = 0, rh = uni(jd->nrows) - 1;
     while (rl < rh) {
@@ -642,8 +720,8 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
       // a wave without a prefix a < b or a last variant j < n has nothing to
       // count; its pilot slots stay zero
       if (a_first >= b || j0 >= v.n) continue;
-      if (f_lds) wave_prefix3<F4, true>(g, v, b, a_first, j0, lane, lut, Fl);
-      else wave_prefix3<F4, false>(g, v, b, a_first, j0, lane, lut, Fl);
+      if (FMT == kMfmaF4Narrow || f_lds) wave_prefix3<FMT, true>(g, v, b, a_first, j0, lane, lut, Fl);
+      else wave_prefix3<FMT, false>(g, v, b, a_first, j0, lane, lut, Fl);
       continue;
     }
     // order 2: tile (A, B) of the upper triangle of 64-variant blocks, row A first
@@ -654,37 +732,44 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
     // a wave with no pair a < j < n has nothing to count; its pilot slots
     // stay zero
     if (a0 + 1 >= v.n || j0 >= v.n || j0 + 31 <= a0) continue;
-    if (f_lds) wave_pairs<F4, true>(v, a0, j0, lane, lut, Fl);
-    else wave_pairs<F4, false>(v, a0, j0, lane, lut, Fl);
+    if (FMT == kMfmaF4Narrow || f_lds) wave_pairs<FMT, true>(v, a0, j0, lane, lut, Fl);
+    else wave_pairs<FMT, false>(v, a0, j0, lane, lut, Fl);
   }
 }
 
-template <int ORDER, bool F4>
+template <int ORDER, int FMT>
 int mfma_grid() {
   int dev = 0, cus = 0, per = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_kernel<ORDER, F4>, kMfmaWaves * 64,
-                                                     mfma_f_entries(F4) * sizeof(float));
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_kernel<ORDER, FMT>, kMfmaWaves * 64,
+                                                     mfma_f_entries(FMT) * sizeof(float));
   if (cus <= 0) cus = 256;
   if (per <= 0) per = 1;
   return cus * per;
 }
 
-int mfma_grid_size(int order, bool fp4) {
-  if (order == 3) return fp4 ? mfma_grid<3, true>() : mfma_grid<3, false>();
-  return fp4 ? mfma_grid<2, true>() : mfma_grid<2, false>();
+int mfma_grid_size(int order, int fmt) {
+  if (order == 3)
+    return fmt == kMfmaI8 ? mfma_grid<3, kMfmaI8>() : fmt == kMfmaF4 ? mfma_grid<3, kMfmaF4>()
+                                                                   : mfma_grid<3, kMfmaF4Narrow>();
+  return fmt == kMfmaI8 ? mfma_grid<2, kMfmaI8>() : fmt == kMfmaF4 ? mfma_grid<2, kMfmaF4>()
+                                                                 : mfma_grid<2, kMfmaF4Narrow>();
 }
 
-void launch_mfma(const Globals &g, int order, bool fp4, int grid, hipStream_t s) {
+uint32_t mfma_narrow_max_samples() { return mfma_f_entries(kMfmaF4Narrow) - 1; }
+
+void launch_mfma(const Globals &g, int order, int fmt, int grid, hipStream_t s) {
   const dim3 gd(grid), bd(kMfmaWaves * 64);
-  const size_t lds = mfma_f_entries(fp4) * sizeof(float);
+  const size_t lds = mfma_f_entries(fmt) * sizeof(float);
   if (order == 3) {
-    if (fp4) hipLaunchKernelGGL((mfma_kernel<3, true>), gd, bd, lds, s, g);
-    else hipLaunchKernelGGL((mfma_kernel<3, false>), gd, bd, lds, s, g);
+    if (fmt == kMfmaI8) hipLaunchKernelGGL((mfma_kernel<3, kMfmaI8>), gd, bd, lds, s, g);
+    else if (fmt == kMfmaF4) hipLaunchKernelGGL((mfma_kernel<3, kMfmaF4>), gd, bd, lds, s, g);
+    else hipLaunchKernelGGL((mfma_kernel<3, kMfmaF4Narrow>), gd, bd, lds, s, g);
   } else {
-    if (fp4) hipLaunchKernelGGL((mfma_kernel<2, true>), gd, bd, lds, s, g);
-    else hipLaunchKernelGGL((mfma_kernel<2, false>), gd, bd, lds, s, g);
+    if (fmt == kMfmaI8) hipLaunchKernelGGL((mfma_kernel<2, kMfmaI8>), gd, bd, lds, s, g);
+    else if (fmt == kMfmaF4) hipLaunchKernelGGL((mfma_kernel<2, kMfmaF4>), gd, bd, lds, s, g);
+    else hipLaunchKernelGGL((mfma_kernel<2, kMfmaF4Narrow>), gd, bd, lds, s, g);
   }
 }
 

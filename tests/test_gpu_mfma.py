@@ -189,3 +189,21 @@ def test_both_operand_formats_in_one_batch(monkeypatch):
     finally:
         for d in jobs:
             fiuncho.set_kernel(d.n, d.m, d.order, fiuncho.KERNEL_AUTO)
+
+
+def test_fp4_narrow_and_wide_launches(monkeypatch):
+    """FP4 jobs with at most 20,447 samples run the kernel variant that keeps
+    counts in 16 bits (f table in LDS); larger ones the 32-bit variant (f
+    table in global memory).  Both orders, both variants, one batch."""
+    monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", "4")
+    monkeypatch.setenv("FIUNCHO_ORDER3_MFMA", "4")
+    jobs = [synth.generate(40, 25000, seed=81, order=3, top_n=15),
+            synth.generate(70, 3000, seed=82, order=3, top_n=15),
+            synth.generate(90, 20447, seed=83, order=2, top_n=15),
+            synth.generate(90, 20448, seed=84, order=2, top_n=15)]
+    say("case: narrow and wide FP4", [(j.n, j.m, j.order) for j in jobs])
+    b = fiuncho.DeviceBatch(jobs)
+    b.run()
+    for d, (status, hits) in zip(jobs, b.results()):
+        assert status == 0
+        check_hits_against_oracle(d.genotypes, d.phenotype, d.order, d.top_n, hits)
