@@ -250,11 +250,14 @@ def main():
         m1 = int(d.phenotype.sum())
         kern = fiuncho.get_kernel(d.n, d.m, d.order)
         kernels.add(kern)
-        if kern in (fiuncho.KERNEL_MFMA, fiuncho.KERNEL_MFMA_FP4):
-            # the {0,1}^k cells of every combination over every sample: 4 at
-            # order 2, 8 at order 3 (the others come from class counts and
-            # pair tables)
-            ops = 2 * (4 if d.order == 2 else 8) * d.m * share(d)
+        if kern in (fiuncho.KERNEL_MFMA, fiuncho.KERNEL_MFMA_FP4) and (d.order <= 3 or d.m <= 20447):
+            # cells counted on the matrix cores for every combination over
+            # every sample: the {0,1}^k cells at orders 2 and 3 (4 and 8; the
+            # others come from class counts and pair tables), at orders 4 and
+            # 5 every prefix row against rows 0, 1 of the last variant
+            # (2 * 3^(k-1))
+            cells = 4 if d.order == 2 else 8 if d.order == 3 else 2 * 3 ** (d.order - 1)
+            ops = 2 * cells * d.m * share(d)
             mfma_ops += ops
             mfma_peak_s += ops / (MFMA_FP4_PEAK_OPS if kern == fiuncho.KERNEL_MFMA_FP4 else MFMA_I8_PEAK_OPS)
         else:

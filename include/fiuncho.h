@@ -222,7 +222,12 @@ int fiuncho_shard_counts(uint32_t snps, uint32_t samples, int order, uint32_t un
 #define FIUNCHO_KERNEL_MFMA_FP4 5 /* orders 2 and 3: the FIUNCHO_KERNEL_MFMA
                                      contraction with FP4 (E2M1) 0/1 operands
                                      and FP32 accumulation (exact: counts stay
-                                     below 2^24), 64 samples per instruction */
+                                     below 2^24), 64 samples per instruction;
+                                     orders 4 and 5: every genotype row of the
+                                     prefix against rows 0, 1 of the last
+                                     variant on the matrix cores (jobs of at
+                                     most 20,447 samples; larger ones run on
+                                     the popcount kernel) */
 
 /* The kernel a job of this shape would use now (a FIUNCHO_KERNEL_* value),
  * or FIUNCHO_E_ORDER. */

@@ -230,8 +230,8 @@ bool kernel_valid(int kernel, uint32_t n, uint32_t k) {
   switch (kernel) {
     case FIUNCHO_KERNEL_POPCOUNT: return true;
     case FIUNCHO_KERNEL_PAIRS: return k == 3 && n >= 3;
-    case FIUNCHO_KERNEL_MFMA:
-    case FIUNCHO_KERNEL_MFMA_FP4: return k == 2 || (k == 3 && n >= 3);
+    case FIUNCHO_KERNEL_MFMA: return k == 2 || (k == 3 && n >= 3);
+    case FIUNCHO_KERNEL_MFMA_FP4: return k == 2 || ((k == 3 || k == 4 || k == 5) && n >= k);
     case FIUNCHO_KERNEL_TRIPLES: return k == 4 && n >= 4 && triple_table_bytes(n) <= kMaxTripleTableBytes;
     default: return false;
   }
@@ -242,11 +242,16 @@ bool kernel_valid(int kernel, uint32_t n, uint32_t k) {
 // everywhere (1.1-2.4 times the pair-table kernel); order 2 on the same
 // kernel except for 256-4,095 variants with fewer than 128 words, where the
 // popcount kernel is up to 25 % faster.  Order 4 uses the triple tables while
-// they fit in 16 GiB.
+// they fit in 16 GiB (200 x 4,000: 19.2 ms, every prefix row on the matrix
+// cores 26.6 ms, popcount 44.7 ms), else the matrix cores; order 5 the matrix
+// cores (1.9 times the popcount kernel at 200 x 4,000).  The matrix cores take
+// orders 4 and 5 up to 20,447 samples.
 int rule_kernel(uint32_t n, uint32_t m, uint32_t k) {
   const u64 words = ceil_div(m, 64);
+  const bool rows = m <= fiuncho::mfma_narrow_max_samples() && n >= k;
   if (k == 3 && n >= 3) return FIUNCHO_KERNEL_MFMA_FP4;
   if (k == 4 && kernel_valid(FIUNCHO_KERNEL_TRIPLES, n, k)) return FIUNCHO_KERNEL_TRIPLES;
+  if ((k == 4 || k == 5) && rows) return FIUNCHO_KERNEL_MFMA_FP4;
   if (k == 2 && !(n >= 256 && n < 4096 && words < 128)) return FIUNCHO_KERNEL_MFMA_FP4;
   return FIUNCHO_KERNEL_POPCOUNT;
 }
@@ -277,14 +282,15 @@ int choose_kernel(uint32_t n, uint32_t m, uint32_t k) {
 }
 
 bool on_matrix_cores(uint32_t path) {
-  return path == fiuncho::kPathMfma2 || path == fiuncho::kPathMfma3;
+  return path == fiuncho::kPathMfma2 || path == fiuncho::kPathMfma3 || path == fiuncho::kPathMfmaRows;
 }
 
 uint32_t kernel_path(int kernel, uint32_t k) {
   switch (kernel) {
     case FIUNCHO_KERNEL_PAIRS: return fiuncho::kPathPairs;
-    case FIUNCHO_KERNEL_MFMA:
-    case FIUNCHO_KERNEL_MFMA_FP4: return k == 2 ? fiuncho::kPathMfma2 : fiuncho::kPathMfma3;
+    case FIUNCHO_KERNEL_MFMA: return k == 2 ? fiuncho::kPathMfma2 : fiuncho::kPathMfma3;
+    case FIUNCHO_KERNEL_MFMA_FP4:
+      return k == 2 ? fiuncho::kPathMfma2 : k == 3 ? fiuncho::kPathMfma3 : fiuncho::kPathMfmaRows;
     case FIUNCHO_KERNEL_TRIPLES: return fiuncho::kPathTriples;
     default: return fiuncho::kPathGeneric;
   }
@@ -314,6 +320,7 @@ struct JobLayout {
 // the kernel variant that keeps counts in 16 bits); -1 for the popcount kernel
 int mfma_group(const JobLayout &J) {
   if (!on_matrix_cores(J.path)) return -1;
+  if (J.path == fiuncho::kPathMfmaRows) return 6 + (int)J.k - 4;  // orders 4, 5
   const int fmt = !J.fp4 ? 0 : J.m <= fiuncho::mfma_narrow_max_samples() ? 2 : 1;
   return 3 * (J.path == fiuncho::kPathMfma3 ? 1 : 0) + fmt;
 }
@@ -365,6 +372,12 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     const int kern = choose_kernel(J.n, J.m, J.k);
     J.path = kernel_path(kern, J.k);
     J.fp4 = kern == FIUNCHO_KERNEL_MFMA_FP4;
+    // orders 4 and 5 on the matrix cores keep counts in 16 bits and the f
+    // table in LDS: larger jobs run on the popcount kernel
+    if (J.path == fiuncho::kPathMfmaRows && J.m > fiuncho::mfma_narrow_max_samples()) {
+      J.path = fiuncho::kPathGeneric;
+      J.fp4 = 0;
+    }
     build_rows(J.n, J.k, J.path, J.row_start);
     J.nrows = (uint32_t)(J.row_start.size() - 1);
     J.shard_count = jobs[i].shard_count > 1 ? jobs[i].shard_count : 1;
@@ -384,7 +397,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
       const u64 s = want ? std::min<u64>({J.tiles, (u64)fiuncho::kPilotTiles,
                                           std::max<u64>(16, J.tiles / 32)})
                          : 0;
-      const bool mm = J.path == fiuncho::kPathMfma2 || J.path == fiuncho::kPathMfma3;
+      const bool mm = on_matrix_cores(J.path);
       const u64 per = mm ? fiuncho::kMfmaPilotEmits : fiuncho::kPilotEmits;
       const u64 slots = s * fiuncho::kScanWaves * per * 64;
       const bool fits = slots * sizeof(uint32_t) <= (u64)J.cand_cap * sizeof(Cand);
@@ -395,6 +408,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     J.cost = J.k == 1 ? 1.0
              : J.path == fiuncho::kPathMfma2 ? words * 4 * 64
              : J.path == fiuncho::kPathMfma3 ? words * 8 * 64
+             : J.path == fiuncho::kPathMfmaRows ? words * 64 * std::pow(3.0, (double)J.k - 3)
              : J.k == 2 ? words * 4 * fiuncho::kOrder2Prefixes
              : J.path == fiuncho::kPathPairs ? words * 8 * fiuncho::kOrder3Prefixes
              : J.path == fiuncho::kPathTriples ? words * 20
@@ -772,6 +786,12 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   auto counting = [&](const Globals &c, int q) {
     if (c.total_tiles <= c.tile_base) return;
     const u64 tiles = c.total_tiles - c.tile_base;
+    if (q >= 6) {  // orders 4, 5: every prefix row on the matrix cores
+      const int order = q - 2;
+      const int grid = (int)std::min<u64>((u64)fiuncho::mfma_rows_grid_size(order), tiles);
+      fiuncho::launch_mfma_rows(c, order, grid, s);
+      return;
+    }
     const int order = 2 + q / 3;
     const int fmt = q % 3;
     const int gmax = q >= 0 ? fiuncho::mfma_grid_size(order, fmt) : fiuncho::scan_grid_size(L.ksel);

@@ -33,10 +33,12 @@ constexpr int kSel23 = 23;                    // scan_kernel selector: orders 2 
 constexpr uint32_t kPathMfma2 = 2;            // order 2 on the matrix cores (mfma_kernel<2>)
 constexpr uint32_t kPathTriples = 3;          // order 4, {0,1}^4 cells + triple and pair tables
 constexpr uint32_t kPathMfma3 = 4;            // order 3 on the matrix cores (mfma_kernel<3>)
+constexpr uint32_t kPathMfmaRows = 5;         // orders 4, 5 on the matrix cores, every prefix row (mfma_rows_kernel)
 constexpr int kSelTriples = 41;               // scan_kernel selector: order-4 triple-table path only
 // matrix-core launch groups, in tile-space order: order 2 with int8, FP4 and
-// narrow FP4 operands, then order 3 likewise (group = 3 (order - 2) + format)
-constexpr int kMfmaGroups = 6;
+// narrow FP4 operands, then order 3 likewise (group = 3 (order - 2) +
+// format), then orders 4 and 5 with every prefix row (groups 6, 7)
+constexpr int kMfmaGroups = 8;
 // tile counters: the popcount kernel and its pilot, then each matrix-core
 // group's counting launch and its pilot
 constexpr int kTileCounters = 2 + 2 * kMfmaGroups;
@@ -148,6 +150,10 @@ void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s);
 void launch_mfma(const Globals &g, int order, int fmt, int grid, hipStream_t s);
 int mfma_grid_size(int order, int fmt);
 uint32_t mfma_narrow_max_samples();
+// orders 4 and 5, every prefix genotype row on the matrix cores (FP4
+// operands; jobs of at most mfma_narrow_max_samples() samples)
+void launch_mfma_rows(const Globals &g, int order, int grid, hipStream_t s);
+int mfma_rows_grid_size(int order);
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
 void launch_pilot_select(const Globals &g, uint32_t max_pilot_slots, hipStream_t s);
 void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s);

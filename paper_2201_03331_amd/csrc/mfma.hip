@@ -650,6 +650,302 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
   else score(as_global(v.Fh));
 }
 
+// ---------------------------------------------------------------------------
+// Orders 4 and 5: every genotype row of the prefix on the matrix cores
+// ---------------------------------------------------------------------------
+//
+// For a prefix P of k - 1 variants and a last variant j the table has 3^k
+// cells.  Rows 0 .. 3^(k-1) - 1 of the A operand are the prefix's genotype
+// rows (the AND of one row of each prefix variant, first variant most
+// significant), the B operand holds rows g = 0, 1 of the last variants, so
+// the matrix cores give every cell with g_j in {0, 1}; the cells with g_j = 2
+// are the prefix row's count (its popcount, taken while the A operand is
+// formed) minus those two.  No lower-order tables are needed.  A wave owns one
+// prefix and 64 last variants: at order 4 the 27 prefix rows fill one
+// fragment (1 x 4 blocks of 32 x 32 outputs), at order 5 the 81 rows fill
+// three (3 x 1 blocks, the 64 last variants in four passes of 16).  FP4
+// operands, counts kept in 16 bits (jobs of at most 20,447 samples), f table
+// in LDS.
+
+constexpr uint32_t pow3(int e) { return e == 0 ? 1u : 3u * pow3(e - 1); }
+
+template <int K>
+struct RowsShape {
+  static constexpr uint32_t R = pow3(K - 1);                // prefix rows
+  static constexpr int FA = (int)((R + 31) / 32);           // A fragments
+  static constexpr int JB = FA == 1 ? 4 : 1;                // B fragments per pass
+  static constexpr int NSB = 4 / JB;                        // passes over 64 last variants
+  static constexpr int kRaw = FA * (K - 1) + JB;            // words a lane loads per word index
+  static constexpr int kDepth = FA == 1 ? 4 : 3;            // register ring depth
+};
+
+// One class: words [wbeg, wend) into acc; np[fa] accumulates the popcount of
+// the lane's A word of fragment fa (its prefix row's count over the lane's
+// half of the samples)
+template <int kDepth, int kRaw, int FA, int JB, typename Load, typename Prep>
+__device__ __forceinline__ void mfma_rows_class(Load &&load_words, Prep &&prep, uint32_t wbeg,
+                                                uint32_t wend, v16f (&acc)[FA][JB],
+                                                uint32_t (&np)[FA]) {
+  if (wbeg >= wend) return;
+  const uint32_t wlast = wend - 1;
+  uint32_t X[kDepth][kRaw];
+#pragma unroll
+  for (int u = 0; u < kDepth; ++u) load_words(min(wbeg + u, wlast), X[u]);
+  auto step = [&](int slot) {
+    uint32_t O[FA + JB];
+    prep(X[slot], O);
+    v8i E[FA + JB];
+#pragma unroll
+    for (int f = 0; f < FA + JB; ++f) E[f] = expand32_fp4(O[f]);
+#pragma unroll
+    for (int fa = 0; fa < FA; ++fa) np[fa] += __builtin_popcount(O[fa]);
+#pragma unroll
+    for (int fa = 0; fa < FA; ++fa)
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+        acc[fa][jb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+            E[fa], E[FA + jb], acc[fa][jb], kFmtFp4, kFmtFp4, 0, kScaleOne, 0, kScaleOne);
+  };
+  uint32_t w = wbeg;
+  for (; w + kDepth <= wend; w += kDepth) {
+#pragma unroll
+    for (int u = 0; u < kDepth; ++u) {
+      step(u);
+      load_words(min(w + u + kDepth, wlast), X[u]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kDepth - 1; ++u)
+    if (w + u < wend) step(u);
+}
+
+// One wave: prefix pre[0 .. K-2] x last variants j0 + [0, 64)
+template <int K>
+__device__ __forceinline__ void wave_rows(const Globals &g, const JV &v, const uint32_t (&pre)[K - 1],
+                                          uint32_t j0, uint32_t lane, const FI_LDS float *F) {
+  typedef RowsShape<K> S;
+  constexpr int FA = S::FA, JB = S::JB;
+  const uint32_t n = v.n, b = pre[K - 2];
+  const uint32_t r = lane & 31, h = lane >> 5, gl = lane & 1;
+  const FI_GLOBAL char *Bsc = reinterpret_cast<const FI_GLOBAL char *>(as_global(v.Bs));
+  const FI_GLOBAL char *Bvc = reinterpret_cast<const FI_GLOBAL char *>(as_global(v.Bv));
+  const size_t vrow = (size_t)v.wcap * 32;         // Bs bytes of one variant
+  const size_t word_bytes = (size_t)v.n_pad * 16;  // Bv bytes of one word
+  // lane r of A fragment fa forms prefix row rho = 32 fa + r: genotype digit
+  // i (base 3, first variant most significant) selects row g_i of variant
+  // pre[i]; rows past 3^(K-1) read the zero word that follows the three
+  // genotype words
+  uint32_t oa[FA][K - 1];
+#pragma unroll
+  for (int fa = 0; fa < FA; ++fa) {
+    const uint32_t rho = 32 * fa + r;
+    uint32_t t = rho;
+#pragma unroll
+    for (int i = K - 2; i >= 0; --i) {
+      const uint32_t gi = rho < S::R ? t % 3 : 3;
+      t /= 3;
+      oa[fa][i] = gi * 8 + 4 * h;
+    }
+  }
+  const uint32_t ol = r * 8 + 4 * h;
+  const MiConst mc = mi_const(v);
+  float thr = current_threshold(v);
+#pragma unroll 1
+  for (int sb = 0; sb < S::NSB; ++sb) {
+    const uint32_t jbase = j0 + 16 * JB * sb;
+    if (jbase >= n) break;
+    auto load_words = [&](uint32_t w, uint32_t (&x)[S::kRaw]) {
+#pragma unroll
+      for (int i = 0; i < K - 1; ++i) {
+        const FI_GLOBAL char *base = Bsc + (size_t)pre[i] * vrow + (size_t)w * 32;
+#pragma unroll
+        for (int fa = 0; fa < FA; ++fa) x[fa * (K - 1) + i] = ld32(base, oa[fa][i]);
+      }
+      const FI_GLOBAL char *sj = Bvc + (size_t)w * word_bytes + (size_t)jbase * 16;
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) x[FA * (K - 1) + jb] = ld32(sj, ol + 256 * jb);
+    };
+    // A word = AND of the prefix variants' rows
+    auto prep = [](const uint32_t (&x)[S::kRaw], uint32_t (&o)[FA + JB]) {
+#pragma unroll
+      for (int fa = 0; fa < FA; ++fa) {
+        uint32_t a = x[fa * (K - 1)];
+#pragma unroll
+        for (int i = 1; i < K - 1; ++i) a &= x[fa * (K - 1) + i];
+        o[fa] = a;
+      }
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) o[FA + jb] = x[FA * (K - 1) + jb];
+    };
+    // class 0, then class 1; counts as 16-bit pairs (class 0 low)
+    v16f f[FA][JB];
+    uint32_t np0[FA], np1[FA];
+#pragma unroll
+    for (int fa = 0; fa < FA; ++fa) {
+      np0[fa] = np1[fa] = 0;
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) f[fa][jb][e] = 0.f;
+    }
+    mfma_rows_class<S::kDepth, S::kRaw, FA, JB>(load_words, prep, 0, v.W0, f, np0);
+    uint32_t P0[FA][JB][8];
+#pragma unroll
+    for (int fa = 0; fa < FA; ++fa)
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          P0[fa][jb][i] = (uint32_t)f[fa][jb][2 * i] | ((uint32_t)f[fa][jb][2 * i + 1] << 16);
+          f[fa][jb][2 * i] = f[fa][jb][2 * i + 1] = 0.f;
+        }
+    mfma_rows_class<S::kDepth, S::kRaw, FA, JB>(load_words, prep, v.W0, v.W0 + v.W1, f, np1);
+    // prefix row counts of both lane halves, both classes in one register
+    uint32_t Np[FA];
+#pragma unroll
+    for (int fa = 0; fa < FA; ++fa) {
+      const uint32_t c0 = np0[fa] + (uint32_t)__shfl_xor((int)np0[fa], 32);
+      const uint32_t c1 = np1[fa] + (uint32_t)__shfl_xor((int)np1[fa], 32);
+      Np[fa] = c0 | (c1 << 16);
+    }
+    // Output block (fa, jb): lane l holds column l mod 32 (last variant jbase
+    // + 16 jb + (l mod 32) / 2, genotype l mod 2); register e holds prefix row
+    // 32 fa + 8 (e / 4) + 4 h + e mod 4.  Each lane scores the cells of its
+    // rows at its own g_j, and half of the rows' g_j = 2 cells (count = row
+    // count - partner's - own, both classes at once: every part is a count);
+    // MI is a sum over cells, so the four lanes of a combination (g_j, h)
+    // add their parts and the lane with g_j = 0, h = 0 appends.
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb) {
+      float s = 0.f;
+#pragma unroll
+      for (int fa = 0; fa < FA; ++fa)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const uint32_t row = 8 * (e / 4) + 4 * h + (e % 4);
+          const uint32_t rho = 32 * fa + row;
+          const uint32_t own = ((P0[fa][jb][e >> 1] >> (16 * (e & 1))) & 0xFFFFu) |
+                               ((uint32_t)f[fa][jb][e] << 16);
+          const uint32_t partner = (uint32_t)__shfl_xor((int)own, 1);
+          const uint32_t nr = (uint32_t)__shfl((int)Np[fa], (int)row);
+          if (rho < S::R) {
+            const uint32_t a0 = own & 0xFFFFu, a1 = own >> 16;
+            s += (F[a0] + F[a1]) - F[a0 + a1];
+            if (gl == (uint32_t)(e & 1)) {
+              const uint32_t c2 = nr - own - partner;
+              const uint32_t b0 = c2 & 0xFFFFu, b1 = c2 >> 16;
+              s += (F[b0] + F[b1]) - F[b0 + b1];
+            }
+          }
+        }
+      const float s2 = s + __shfl_xor(s, 1);
+      const float s4 = s2 + __shfl_xor(s2, 32);
+      const uint32_t j = jbase + 16 * jb + (r >> 1);
+      const bool owner = gl == 0 && h == 0 && j < n;
+      if (emit_with(v, owner, (mc.c + s4) * mc.inv_m,
+                    [&] { return lex_rank_prefix(g, n, K, pre) + (u64)(j - b - 1); }, thr,
+                    lane) >= kRefreshAppends)
+        thr = current_threshold_lanes(v);
+    }
+  }
+}
+
+// Orders 4 and 5 on the matrix cores: the popcount kernel's tiles (a row per
+// last prefix variant b, 4 prefixes x 64 last variants per tile, one prefix
+// per wave)
+template <int K>
+__global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_rows_kernel(Globals g) {
+  __shared__ u64 s_tile;
+  extern __shared__ float s_f[];
+  const uint32_t lane = lane_id();
+  const uint32_t wave = uni(threadIdx.x >> 6);
+  const FI_LDS float *Fl = (const FI_LDS float *)s_f;
+  uint32_t f_job = ~0u;
+  bool f_lds = false;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = g.tile_base + atomicAdd(g.tile_counter, 1ull);
+    __syncthreads();
+    const u64 t = uni64(s_tile);
+    __syncthreads();
+    if (t >= g.total_tiles) break;
+    {
+      const uint32_t jx = job_of_tile(g, t);
+      if (jx != f_job) {
+        const FI_CONST JobDesc *J = as_const(g.jobs) + jx;
+        const uint32_t entries = uni(J->m) + 1;
+        f_lds = entries <= mfma_f_entries(kMfmaF4Narrow);
+        if (f_lds) {
+          const FI_GLOBAL float *Fh = as_global(uni_ptr(J->Fh));
+          for (uint32_t i = threadIdx.x; i < entries; i += blockDim.x) s_f[i] = Fh[i];
+        }
+        f_job = jx;
+        __syncthreads();
+      }
+    }
+    JV v;
+    const FI_CONST JobDesc *jd;
+    u64 lt;
+    if (!locate_tile(g, t, wave, kMfmaPilotEmits, v, jd, lt)) continue;
+    // the host gives this kernel only such jobs
+    if (v.path != kPathMfmaRows || v.k != (uint32_t)K || !f_lds) continue;
+    cu64p rows = as_const(uni_ptr(jd->row_start));
+    uint32_t rl = 0, rh = uni(jd->nrows) - 1;
+    while (rl < rh) {
+      const uint32_t mid = (rl + rh + 1) >> 1;
+      if (rows[mid] <= lt) rl = mid;
+      else rh = mid - 1;
+    }
+    rl = uni(rl);
+    const u64 local = uni64(lt - rows[rl]);
+    const uint32_t n = v.n;
+    const uint32_t b = rl + (K - 2);
+    const uint32_t nj = (n - 1 - b + 63) / 64;
+    const u64 grp = local / nj;
+    const uint32_t jb = (uint32_t)(local - grp * nj);
+    u64 q = grp * kMfmaWaves + wave;
+    if (q >= binom(g, b, K - 2)) continue;
+    uint32_t pre[K - 1];
+    pre[K - 2] = b;
+    // colex unrank of the (K-2)-subset of [0, b) with index q
+    uint32_t hi = b;
+#pragma unroll
+    for (int rr = K - 2; rr >= 1; --rr) {
+      uint32_t lo = (uint32_t)(rr - 1), top = hi - 1;
+      while (lo < top) {
+        const uint32_t mid = (lo + top + 1) >> 1;
+        if (binom(g, mid, rr) <= q) lo = mid;
+        else top = mid - 1;
+      }
+      q -= binom(g, lo, rr);
+      pre[rr - 1] = uni(lo);
+      hi = lo;
+    }
+    wave_rows<K>(g, v, pre, b + 1 + jb * 64, lane, Fl);
+  }
+}
+
+template <int K>
+int mfma_rows_grid() {
+  int dev = 0, cus = 0, per = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_rows_kernel<K>, kMfmaWaves * 64,
+                                                     mfma_f_entries(kMfmaF4Narrow) * sizeof(float));
+  if (cus <= 0) cus = 256;
+  if (per <= 0) per = 1;
+  return cus * per;
+}
+
+int mfma_rows_grid_size(int order) { return order == 5 ? mfma_rows_grid<5>() : mfma_rows_grid<4>(); }
+
+void launch_mfma_rows(const Globals &g, int order, int grid, hipStream_t s) {
+  const dim3 gd(grid), bd(kMfmaWaves * 64);
+  const size_t lds = mfma_f_entries(kMfmaF4Narrow) * sizeof(float);
+  if (order == 5) hipLaunchKernelGGL((mfma_rows_kernel<5>), gd, bd, lds, s, g);
+  else hipLaunchKernelGGL((mfma_rows_kernel<4>), gd, bd, lds, s, g);
+}
+
 // ORDER 2 or 3, FMT: operand format (kMfmaI8, kMfmaF4, kMfmaF4Narrow); the
 // kernel serves the jobs of that order and format (a batch with several
 // launches it once per group, each over the group's tiles)

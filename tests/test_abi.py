@@ -116,8 +116,11 @@ def test_kernel_choice_table(monkeypatch):
     assert fiuncho.get_kernel(3, 10, 3) == fiuncho.KERNEL_MFMA_FP4
     assert fiuncho.get_kernel(300, 17000, 2) == fiuncho.KERNEL_MFMA_FP4  # 266 words
     assert fiuncho.get_kernel(200, 4000, 4) == fiuncho.KERNEL_TRIPLES
-    assert fiuncho.get_kernel(5000, 4000, 4) == fiuncho.KERNEL_POPCOUNT  # tables over 16 GiB
-    assert fiuncho.get_kernel(100, 4000, 5) == fiuncho.KERNEL_POPCOUNT
+    assert fiuncho.get_kernel(5000, 4000, 4) == fiuncho.KERNEL_MFMA_FP4  # tables over 16 GiB
+    assert fiuncho.get_kernel(5000, 30000, 4) == fiuncho.KERNEL_POPCOUNT  # over 20,447 samples
+    assert fiuncho.get_kernel(100, 4000, 5) == fiuncho.KERNEL_MFMA_FP4
+    assert fiuncho.get_kernel(100, 20448, 5) == fiuncho.KERNEL_POPCOUNT
+    assert fiuncho.get_kernel(100, 4000, 6) == fiuncho.KERNEL_POPCOUNT
     assert L.fiuncho_get_kernel(5, 100, 6) == fiuncho.E_ORDER
     before = fiuncho.shard_counts(300, 500, 2, 5, fiuncho.TILE_ROUND_ROBIN)
     try:
@@ -144,7 +147,8 @@ def test_kernel_choice_table(monkeypatch):
         fiuncho.set_kernel(300, 500, 2, fiuncho.KERNEL_AUTO)
     assert fiuncho.get_kernel(300, 500, 2) == fiuncho.KERNEL_POPCOUNT
     assert L.fiuncho_set_kernel(300, 500, 4, fiuncho.KERNEL_MFMA) == fiuncho.E_SHAPE
-    assert L.fiuncho_set_kernel(300, 500, 4, fiuncho.KERNEL_MFMA_FP4) == fiuncho.E_SHAPE
+    assert L.fiuncho_set_kernel(300, 500, 6, fiuncho.KERNEL_MFMA_FP4) == fiuncho.E_SHAPE
+    assert L.fiuncho_set_kernel(4, 500, 5, fiuncho.KERNEL_MFMA_FP4) == fiuncho.E_ORDER
     assert L.fiuncho_set_kernel(2, 500, 3, fiuncho.KERNEL_MFMA_FP4) == fiuncho.E_ORDER
     assert L.fiuncho_set_kernel(300, 500, 2, fiuncho.KERNEL_PAIRS) == fiuncho.E_SHAPE
     assert L.fiuncho_set_kernel(300, 500, 2, 9) == fiuncho.E_SHAPE

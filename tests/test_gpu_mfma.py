@@ -207,3 +207,73 @@ def test_fp4_narrow_and_wide_launches(monkeypatch):
     for d, (status, hits) in zip(jobs, b.results()):
         assert status == 0
         check_hits_against_oracle(d.genotypes, d.phenotype, d.order, d.top_n, hits)
+
+
+# ---------------------------------------------------------------------------
+# orders 4 and 5: every prefix row on the matrix cores (FP4)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture
+def rows_kernel():
+    """Puts the FP4 matrix-core kernel in the table for the shapes a test
+    registers; clears them afterwards."""
+    shapes = []
+
+    def use(n, m, k):
+        fiuncho.set_kernel(n, m, k, fiuncho.KERNEL_MFMA_FP4)
+        shapes.append((n, m, k))
+        assert fiuncho.get_kernel(n, m, k) == fiuncho.KERNEL_MFMA_FP4
+
+    yield use
+    for n, m, k in shapes:
+        fiuncho.set_kernel(n, m, k, fiuncho.KERNEL_AUTO)
+
+
+# n around the 4-prefix groups and 64-variant blocks, m around word edges
+CASES45 = [(4, 7, 64, 0.5), (4, 20, 300, 0.4), (4, 35, 130, 0.5), (4, 70, 1000, 0.3),
+           (5, 9, 77, 0.5), (5, 14, 190, 0.45), (5, 22, 400, 0.6), (5, 68, 129, 0.5)]
+
+
+@pytest.mark.parametrize("k,n,m,frac", CASES45)
+def test_orders45_rows_small(k, n, m, frac, rows_kernel):
+    say(f"case: rows order {k} n={n} m={m}")
+    rows_kernel(n, m, k)
+    G, y = random_dataset(211 + n + k, n, m, frac, 1 if n > 8 else 0, 1 if n > 8 else 0)
+    top = min(30, math.comb(n, k))
+    fiuncho.set_profiling(True)
+    hits = fiuncho.scan(G, y, k, top)
+    prof = fiuncho.get_profile()
+    fiuncho.set_profiling(False)
+    assert prof["kernels"] == 1 << fiuncho.KERNEL_MFMA_FP4
+    check_hits_against_oracle(G, y, k, top, hits)
+
+
+@pytest.mark.parametrize("k,n", [(4, 15), (5, 13)])
+def test_orders45_rows_every_combination(k, n, rows_kernel):
+    m = 150
+    rows_kernel(n, m, k)
+    G, y = random_dataset(300 + k, n, m, 0.5)
+    hits = fiuncho.scan(G, y, k, fiuncho.MAX_TOPN)
+    assert len(hits) == math.comb(n, k)
+    np.testing.assert_array_equal(np.sort(hits["rank"]), np.arange(math.comb(n, k), dtype=np.uint64))
+    np.testing.assert_array_equal(hits["mi"], oracle.score_ranks(G, y, k, hits["rank"]))
+    check_hits_against_oracle(G, y, k, len(hits), hits)
+
+
+def test_order4_rows_workload(rows_kernel):
+    d = synth.high_order(4)
+    rows_kernel(d.n, d.m, 4)
+    full_size_check(d, 20000, 57)
+
+
+def test_orders45_rows_large_samples_fall_back(rows_kernel):
+    """More than 20,447 samples: the job runs on the popcount kernel."""
+    n, m = 8, 25000
+    rows_kernel(n, m, 4)
+    G, y = random_dataset(88, n, m, 0.5)
+    fiuncho.set_profiling(True)
+    hits = fiuncho.scan(G, y, 4, 20)
+    prof = fiuncho.get_profile()
+    fiuncho.set_profiling(False)
+    assert prof["kernels"] == 1 << fiuncho.KERNEL_POPCOUNT
+    check_hits_against_oracle(G, y, 4, 20, hits)
