@@ -663,7 +663,9 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
 // formed) minus those two.  No lower-order tables are needed.  A wave owns one
 // prefix and 64 last variants: at order 4 the 27 prefix rows fill one
 // fragment (1 x 4 blocks of 32 x 32 outputs), at order 5 the 81 rows fill
-// three (3 x 1 blocks, the 64 last variants in four passes of 16).  FP4
+// three (3 x 2 blocks, the 64 last variants in two passes of 32; measured:
+// 21 % faster than 3 x 1 blocks in four passes despite a few register
+// spills, with a 2-word ring).  FP4
 // operands, counts kept in 16 bits (jobs of at most 20,447 samples), f table
 // in LDS.
 
@@ -673,10 +675,10 @@ template <int K>
 struct RowsShape {
   static constexpr uint32_t R = pow3(K - 1);                // prefix rows
   static constexpr int FA = (int)((R + 31) / 32);           // A fragments
-  static constexpr int JB = FA == 1 ? 4 : 1;                // B fragments per pass
+  static constexpr int JB = FA == 1 ? 4 : 2;                // B fragments per pass
   static constexpr int NSB = 4 / JB;                        // passes over 64 last variants
   static constexpr int kRaw = FA * (K - 1) + JB;            // words a lane loads per word index
-  static constexpr int kDepth = FA == 1 ? 4 : 3;            // register ring depth
+  static constexpr int kDepth = FA == 1 ? 4 : 2;            // register ring depth
 };
 
 // One class: words [wbeg, wend) into acc; np[fa] accumulates the popcount of
