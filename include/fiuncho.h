@@ -264,7 +264,8 @@ typedef struct {
   uint32_t flags;        /* 4 = a rescored candidate's single-precision estimate was
                             farther from its FP64 MI than the stated bound (last
                             call, first job; never expected) */
-  uint64_t combinations; /* sum of C(snps, order) over the jobs of the last call */
+  uint64_t combinations; /* combinations the last call tested: C(snps, order) per job,
+                            a sharded job's share for a sharded job */
   uint64_t candidates;   /* candidates the scan appended (last call, first job) */
   uint32_t kept;         /* candidates rescored in double precision (last call, first job) */
   uint32_t kernels;      /* bit (1 << FIUNCHO_KERNEL_*) for each kernel the last call used */

@@ -745,21 +745,34 @@ int prof_record(int i, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // the pipeline on an uploaded plan
 // ---------------------------------------------------------------------------
+// Combinations of one shard of a job (a walk over the job's tiles, so the
+// counts are kept per shape and shard: repeated profiled calls do not repeat
+// the walk)
+u64 shard_combinations(const JobLayout &J) {
+  typedef std::tuple<uint32_t, uint32_t, uint32_t, uint32_t, uint32_t> Key;
+  static std::mutex mu;
+  static std::map<Key, u64> memo;
+  const Key key(J.n, J.k, J.path, J.shard_count, J.shard_index);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+  }
+  u64 combos = 0;
+  for_each_tile(J.n, J.k, J.path, [&](u64 lt, u64 c) {
+    if (tile_shard(lt, J.shard_count) == J.shard_index) combos += c;
+  });
+  std::lock_guard<std::mutex> lk(mu);
+  memo[key] = combos;
+  return combos;
+}
+
 int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   const Globals g = make_globals(L, ws);
   int st;
   u64 combos = 0;
-  if (t_profiling) {
-    for (auto &J : L.jobs) {
-      if (J.shard_count <= 1) {
-        combos += J.total;
-        continue;
-      }
-      for_each_tile(J.n, J.k, J.path, [&](u64 lt, u64 c) {
-        if (tile_shard(lt, J.shard_count) == J.shard_index) combos += c;
-      });
-    }
-  }
+  if (t_profiling)
+    for (auto &J : L.jobs) combos += J.shard_count <= 1 ? J.total : shard_combinations(J);
   uint32_t kernels = 0;
   for (auto &J : L.jobs)
     kernels |= 1u << (J.path == fiuncho::kPathPairs     ? FIUNCHO_KERNEL_PAIRS
