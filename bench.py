@@ -249,6 +249,8 @@ def main():
     lane_ops = 0
     mfma_ops = 0
     mfma_peak_s = 0.0
+    # the counter table's workload key (a shard launches fewer tiles)
+    traffic_key = args.workload + ("" if shard is None else f" shard {shard[0]}/{shard[1]}")
     kernels = set()
     for d in datasets:
         m1 = int(d.phenotype.sum())
@@ -277,13 +279,13 @@ def main():
         fmt = "int8 and FP4" if fp4 and i8 else "FP4" if fp4 else "int8"
         roofline = {"bound": "mfma", "kernel": f"mfma_kernel (one-hot {fmt} contraction + FP32 MI + filter)",
                     "achieved": achieved, "peak": peak, "unit": f"T {fmt} op/s", "frac": achieved / peak,
-                    "traffic": measured_traffic("mfma_kernel", args.workload)}
+                    "traffic": measured_traffic("mfma_kernel", traffic_key)}
     else:
         achieved = lane_ops / (scan_ms / 1e3) / 1e12
         peak = VALU_PEAK_LANE_OPS / 1e12
         roofline = {"bound": "alu", "kernel": "scan_kernel (AND+popcount counting + FP32 MI + filter)",
                     "achieved": achieved, "peak": peak, "unit": "T int32 lane-op/s", "frac": achieved / peak,
-                    "traffic": measured_traffic("scan_kernel", args.workload)}
+                    "traffic": measured_traffic("scan_kernel", traffic_key)}
     names = {fiuncho.KERNEL_POPCOUNT: "popcount", fiuncho.KERNEL_PAIRS: "pairs", fiuncho.KERNEL_MFMA: "mfma",
              fiuncho.KERNEL_TRIPLES: "triples", fiuncho.KERNEL_MFMA_FP4: "mfma-fp4"}
 
