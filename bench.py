@@ -279,13 +279,17 @@ def main():
         fmt = "int8 and FP4" if fp4 and i8 else "FP4" if fp4 else "int8"
         roofline = {"bound": "mfma", "kernel": f"mfma_kernel (one-hot {fmt} contraction + FP32 MI + filter)",
                     "achieved": achieved, "peak": peak, "unit": f"T {fmt} op/s", "frac": achieved / peak,
-                    "traffic": measured_traffic("mfma_kernel", traffic_key)}
+                    # the counter table holds the FP4 kernels' launches
+                    "traffic": measured_traffic("mfma_kernel", traffic_key) if fmt == "FP4" else None}
     else:
         achieved = lane_ops / (scan_ms / 1e3) / 1e12
         peak = VALU_PEAK_LANE_OPS / 1e12
         roofline = {"bound": "alu", "kernel": "scan_kernel (AND+popcount counting + FP32 MI + filter)",
                     "achieved": achieved, "peak": peak, "unit": "T int32 lane-op/s", "frac": achieved / peak,
-                    "traffic": measured_traffic("scan_kernel", traffic_key)}
+                    # the counter table holds the pair-table (order 3) and
+                    # triple-table (order 4) kernels' launches
+                    "traffic": measured_traffic("scan_kernel", traffic_key)
+                    if kernels <= {fiuncho.KERNEL_PAIRS, fiuncho.KERNEL_TRIPLES} else None}
     names = {fiuncho.KERNEL_POPCOUNT: "popcount", fiuncho.KERNEL_PAIRS: "pairs", fiuncho.KERNEL_MFMA: "mfma",
              fiuncho.KERNEL_TRIPLES: "triples", fiuncho.KERNEL_MFMA_FP4: "mfma-fp4"}
 
