@@ -277,3 +277,34 @@ def test_orders45_rows_large_samples_fall_back(rows_kernel):
     fiuncho.set_profiling(False)
     assert prof["kernels"] == 1 << fiuncho.KERNEL_POPCOUNT
     check_hits_against_oracle(G, y, 4, 20, hits)
+
+
+def test_every_launch_group_in_one_batch(rows_kernel, monkeypatch):
+    """One batch with a job in each matrix-core launch group (orders 2 and 3
+    with int8, FP4 and 16-bit-count FP4 operands; orders 4 and 5 with every
+    prefix row) and popcount jobs: each group runs over its own tiles."""
+    for v in ("FIUNCHO_ORDER2_MFMA", "FIUNCHO_ORDER3_MFMA", "FIUNCHO_ORDER3_PAIRS", "FIUNCHO_ORDER4_TRIPLES"):
+        monkeypatch.delenv(v, raising=False)
+    specs = [(70, 300, 2, fiuncho.KERNEL_MFMA), (80, 21000, 2, fiuncho.KERNEL_MFMA_FP4),
+             (90, 500, 2, fiuncho.KERNEL_MFMA_FP4), (40, 260, 3, fiuncho.KERNEL_MFMA),
+             (30, 20500, 3, fiuncho.KERNEL_MFMA_FP4), (50, 700, 3, fiuncho.KERNEL_MFMA_FP4),
+             (24, 300, 4, fiuncho.KERNEL_MFMA_FP4), (16, 200, 5, fiuncho.KERNEL_MFMA_FP4),
+             (45, 150, 3, fiuncho.KERNEL_PAIRS), (18, 120, 4, fiuncho.KERNEL_TRIPLES),
+             (12, 100, 6, fiuncho.KERNEL_POPCOUNT)]
+    jobs = []
+    try:
+        for i, (n, m, k, kind) in enumerate(specs):
+            if kind == fiuncho.KERNEL_MFMA_FP4 and k >= 4:
+                rows_kernel(n, m, k)
+            else:
+                fiuncho.set_kernel(n, m, k, kind)
+            jobs.append(synth.generate(n, m, seed=500 + i, order=k, top_n=12))
+        say("case: every launch group", [(j.n, j.m, j.order) for j in jobs])
+        b = fiuncho.DeviceBatch(jobs)
+        b.run()
+        for d, (status, hits) in zip(jobs, b.results()):
+            assert status == 0
+            check_hits_against_oracle(d.genotypes, d.phenotype, d.order, d.top_n, hits)
+    finally:
+        for n, m, k, kind in specs:
+            fiuncho.set_kernel(n, m, k, fiuncho.KERNEL_AUTO)
