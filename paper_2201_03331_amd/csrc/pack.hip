@@ -10,20 +10,24 @@
 namespace fiuncho {
 
 // Clears every job's run state, survivor histograms, class counts and pilot
-// score slots, and the tile counters.
+// score slots, and the tile counters: workgroups (job, y) share the large
+// clears, y = 0 does the rest.
 // (A fill kernel rather than hipMemsetAsync, so that the sequence can be
 // captured into a graph and replayed.)
+constexpr int kInitBlocks = 32;
 __global__ void init_kernel(Globals g) {
   const JobDesc &J = g.jobs[blockIdx.x];
-  for (uint32_t i = threadIdx.x; i < (uint32_t)kHistBins; i += blockDim.x) {
-    J.hist[i] = 0;
-    if (J.phist) J.phist[i] = 0;
-  }
-  for (uint32_t i = threadIdx.x; i < J.n * 6; i += blockDim.x) J.marg[i] = 0;
+  const uint32_t t = blockIdx.y * blockDim.x + threadIdx.x, nt = gridDim.y * blockDim.x;
+  for (uint32_t i = t; i < J.n * 6; i += nt) J.marg[i] = 0;
   {
     uint4 *pk = reinterpret_cast<uint4 *>(J.cand);
     const uint32_t n4 = J.pilot_slots / 4;
-    for (uint32_t i = threadIdx.x; i < n4; i += blockDim.x) pk[i] = make_uint4(0, 0, 0, 0);
+    for (uint32_t i = t; i < n4; i += nt) pk[i] = make_uint4(0, 0, 0, 0);
+  }
+  if (blockIdx.y != 0) return;
+  for (uint32_t i = threadIdx.x; i < (uint32_t)kHistBins; i += blockDim.x) {
+    J.hist[i] = 0;
+    if (J.phist) J.phist[i] = 0;
   }
   if (threadIdx.x == 0) {
     JobState *st = J.state;
@@ -48,7 +52,6 @@ __global__ __launch_bounds__(1024) void partition_kernel(Globals g) {
   JobState *st = J.state;
   const uint32_t m = J.m;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ uint32_t s_wave[16];
   __shared__ uint32_t s_base1;
   __shared__ uint32_t s_bad;
   if (tid == 0) {
@@ -73,34 +76,51 @@ __global__ __launch_bounds__(1024) void partition_kernel(Globals g) {
     return;
   }
   __syncthreads();
-  // pass 2: stable scatter, chunk by chunk
+  // pass 2: stable scatter, 4,096 samples per round: thread t takes samples
+  // 4t .. 4t + 3 of the round; (controls, cases) counts travel as one u32 of
+  // two 16-bit halves through a block-wide exclusive scan
+  constexpr uint32_t kPer = 4;
+  __shared__ uint32_t s_scan[16];
   uint32_t base0 = 0, base1 = 0;
-  for (uint32_t c0 = 0; c0 < m; c0 += blockDim.x) {
-    uint32_t s = c0 + tid;
-    bool valid = s < m;
-    bool isc = valid && J.y[s] == 1;
-    u64 bc = ballot(isc), bv = ballot(valid);
-    u64 lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t pre1 = popc64(bc & lt);
-    uint32_t pre0 = popc64(bv & ~bc & lt);
-    if (lane == 0) s_wave[wave] = popc64(bc) | (popc64(bv & ~bc) << 16);
-    __syncthreads();
-    uint32_t off1 = 0, off0 = 0, tot1 = 0, tot0 = 0;
-    for (uint32_t w = 0; w < blockDim.x / 64; ++w) {
-      uint32_t v = s_wave[w];
-      if (w < wave) {
-        off1 += v & 0xffff;
-        off0 += v >> 16;
+  for (uint32_t c0 = 0; c0 < m; c0 += kPer * blockDim.x) {
+    const uint32_t s0 = c0 + kPer * tid;
+    uint32_t cls = 0, cnt = 0;  // bit u of cls: sample s0 + u is a case
+#pragma unroll
+    for (uint32_t u = 0; u < kPer; ++u) {
+      const uint32_t s = s0 + u;
+      if (s < m) {
+        const bool isc = J.y[s] == 1;
+        cls |= (uint32_t)isc << u;
+        cnt += isc ? 0x10000u : 1u;
       }
-      tot1 += v & 0xffff;
-      tot0 += v >> 16;
     }
-    if (valid) {
-      if (isc) J.idx[m0 + base1 + off1 + pre1] = s;
-      else J.idx[base0 + off0 + pre0] = s;
+    // inclusive scan over the wave, then over the waves
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t v = (uint32_t)__shfl_up((int)inc, off);
+      if (lane >= (uint32_t)off) inc += v;
     }
-    base1 += tot1;
-    base0 += tot0;
+    if (lane == 63) s_scan[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (uint32_t w = 0; w < blockDim.x / 64; ++w) {
+      const uint32_t v = s_scan[w];
+      if (w < wave) before += v;
+      total += v;
+    }
+    const uint32_t ex = before + inc - cnt;  // this thread's exclusive prefix
+    uint32_t p0 = base0 + (ex & 0xFFFFu), p1 = base1 + (ex >> 16);
+#pragma unroll
+    for (uint32_t u = 0; u < kPer; ++u) {
+      const uint32_t s = s0 + u;
+      if (s < m) {
+        if ((cls >> u) & 1u) J.idx[m0 + p1++] = s;
+        else J.idx[p0++] = s;
+      }
+    }
+    base0 += total & 0xFFFFu;
+    base1 += total >> 16;
     __syncthreads();
   }
   if (tid == 0) {
@@ -218,7 +238,7 @@ __global__ __launch_bounds__(kPackWaves * 64) void pack_kernel(Globals g) {
 }
 
 void launch_init(const Globals &g, hipStream_t s) {
-  hipLaunchKernelGGL(init_kernel, dim3(g.n_jobs), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(init_kernel, dim3(g.n_jobs, kInitBlocks), dim3(256), 0, s, g);
   hipLaunchKernelGGL(partition_kernel, dim3(g.n_jobs), dim3(1024), 0, s, g);
 }
 
