@@ -168,15 +168,31 @@ __device__ __forceinline__ uint32_t ld32(const FI_GLOBAL char *base, uint32_t of
   return __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
 }
 
-// 32 sample bits -> the 32 FP4 operand values of one lane.  E2M1 1.0 is the
-// nibble 0b0010, so register d takes bit 4p + d of b to bit 1 of nibble p;
-// only the low four registers are read for FP4 operands.
-__device__ __forceinline__ v8i expand32_fp4(uint32_t b) {
+// 32 sample bits -> the 32 FP4 operand values of one lane.  Register d takes
+// bit 4p + d of b into nibble p, so both operands pair the same samples; the
+// nibble bit it lands on sets the E2M1 value (bit 0: 0.5, bit 1: 1.0, bit 2:
+// 2.0), and the two operands use reciprocal values per register, so every
+// product of two set bits is exactly 1:
+//   register      0     1     2     3
+//   A operand    0.5   1.0   2.0   1.0   (no shift for registers 0-2)
+//   B operand    2.0   1.0   0.5   1.0   (registers 2 and 3 share one shift)
+// Only the low four registers are read for FP4 operands.
+__device__ __forceinline__ v8i expand32_fp4_a(uint32_t b) {
   v8i r;
-  r[0] = (int)((b << 1) & 0x22222222u);
+  r[0] = (int)(b & 0x11111111u);
   r[1] = (int)(b & 0x22222222u);
-  r[2] = (int)((b >> 1) & 0x22222222u);
+  r[2] = (int)(b & 0x44444444u);
   r[3] = (int)((b >> 2) & 0x22222222u);
+  r[4] = r[5] = r[6] = r[7] = 0;
+  return r;
+}
+__device__ __forceinline__ v8i expand32_fp4_b(uint32_t b) {
+  const uint32_t t = b >> 2;
+  v8i r;
+  r[0] = (int)((b << 2) & 0x44444444u);
+  r[1] = (int)(b & 0x22222222u);
+  r[2] = (int)(t & 0x11111111u);
+  r[3] = (int)(t & 0x22222222u);
   r[4] = r[5] = r[6] = r[7] = 0;
   return r;
 }
@@ -199,7 +215,7 @@ __device__ __forceinline__ void mfma_class_fp4(Load &&load_words, Prep &&prep, u
     prep(X[slot], O);
     v8i E[4];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) E[f] = expand32_fp4(O[f]);
+    for (int f = 0; f < 4; ++f) E[f] = f < 2 ? expand32_fp4_a(O[f]) : expand32_fp4_b(O[f]);
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -698,7 +714,7 @@ __device__ __forceinline__ void mfma_rows_class(Load &&load_words, Prep &&prep, 
     prep(X[slot], O);
     v8i E[FA + JB];
 #pragma unroll
-    for (int f = 0; f < FA + JB; ++f) E[f] = expand32_fp4(O[f]);
+    for (int f = 0; f < FA + JB; ++f) E[f] = f < FA ? expand32_fp4_a(O[f]) : expand32_fp4_b(O[f]);
 #pragma unroll
     for (int fa = 0; fa < FA; ++fa) np[fa] += __builtin_popcount(O[fa]);
 #pragma unroll
