@@ -801,8 +801,8 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
     const u64 tiles = c.total_tiles - c.tile_base;
     if (q >= 6) {  // orders 4, 5: every prefix row on the matrix cores
       const int order = q - 2;
-      const int grid = (int)std::min<u64>((u64)fiuncho::mfma_rows_grid_size(order), tiles);
-      fiuncho::launch_mfma_rows(c, order, grid, s);
+      const int grid = (int)std::min<u64>((u64)fiuncho::mfma_rows_grid_size(order, false), tiles);
+      fiuncho::launch_mfma_rows(c, order, false, grid, s);
       return;
     }
     const int order = 2 + q / 3;
@@ -813,11 +813,31 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
     else fiuncho::launch_scan(c, L.ksel, grid, s);
   };
   // the matrix-core groups' launches over their jobs; counters 2 + 2q (counting)
-  // and 3 + 2q (pilot)
+  // and 3 + 2q (pilot).  The narrow FP4 groups (2, 5) and the groups of orders
+  // 4 and 5 (6, 7) run the dual kernel first over the same tiles, on counters
+  // kDualCounters + 2 slot (+ 1 for the pilot): it takes the jobs whose class
+  // sizes allow one accumulator for both classes, the group's kernel the rest
   auto mfma_groups = [&](const std::vector<u64> &starts, bool pilot) {
     uint32_t first = ns;
     for (int q = 0; q < fiuncho::kMfmaGroups; ++q) {
-      if (L.n_group[q]) counting(launch_globals(g, starts, first, L.n_group[q], pilot, 2 + 2 * q + pilot), q);
+      if (L.n_group[q]) {
+        const Globals c = launch_globals(g, starts, first, L.n_group[q], pilot, 2 + 2 * q + pilot);
+        const int slot = q == 2 ? 0 : q == 5 ? 1 : q >= 6 ? q - 4 : -1;
+        if (slot >= 0 && c.total_tiles > c.tile_base) {
+          Globals d = c;
+          d.tile_counter = g.tile_counter + fiuncho::kDualCounters + 2 * slot + pilot;
+          const u64 tiles = d.total_tiles - d.tile_base;
+          if (q >= 6) {
+            const int grid = (int)std::min<u64>((u64)fiuncho::mfma_rows_grid_size(q - 2, true), tiles);
+            fiuncho::launch_mfma_rows(d, q - 2, true, grid, s);
+          } else {
+            const int order = 2 + q / 3;
+            const int grid = (int)std::min<u64>((u64)fiuncho::mfma_grid_size(order, 3), tiles);
+            fiuncho::launch_mfma(d, order, 3, grid, s);
+          }
+        }
+        counting(c, q);
+      }
       first += L.n_group[q];
     }
   };

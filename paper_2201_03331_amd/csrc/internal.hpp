@@ -41,7 +41,11 @@ constexpr int kSelTriples = 41;               // scan_kernel selector: order-4 t
 constexpr int kMfmaGroups = 8;
 // tile counters: the popcount kernel and its pilot, then each matrix-core
 // group's counting launch and its pilot
-constexpr int kTileCounters = 2 + 2 * kMfmaGroups;
+// (the narrow FP4 groups of orders 2 and 3 and the groups of orders 4 and 5
+// run a second kernel, the dual one, over the same tiles: 2 more counters
+// each, after the groups')
+constexpr int kTileCounters = 2 + 2 * kMfmaGroups + 8;
+constexpr int kDualCounters = 2 + 2 * kMfmaGroups;
 
 // state the device writes during one run of a job (cleared at the start)
 struct JobState {
@@ -146,14 +150,17 @@ void launch_pairs(const Globals &g, uint32_t max_n, hipStream_t s);
 void launch_triples(const Globals &g, uint32_t max_n, hipStream_t s);
 void launch_scan(const Globals &g, int ksel, int grid, hipStream_t s);
 // fmt: 0 int8, 1 FP4, 2 narrow FP4 (jobs of at most mfma_narrow_max_samples()
-// samples: table in LDS, counts in 16 bits)
+// samples: table in LDS, counts in 16 bits), 3 dual FP4 (launched over the
+// narrow group's tiles; takes the jobs whose class sizes fit 24 bits together)
 void launch_mfma(const Globals &g, int order, int fmt, int grid, hipStream_t s);
 int mfma_grid_size(int order, int fmt);
 uint32_t mfma_narrow_max_samples();
 // orders 4 and 5, every prefix genotype row on the matrix cores (FP4
 // operands; jobs of at most mfma_narrow_max_samples() samples)
-void launch_mfma_rows(const Globals &g, int order, int grid, hipStream_t s);
-int mfma_rows_grid_size(int order);
+// dual: the kernel that takes the jobs whose class sizes fit 24 bits together
+// (both classes in one accumulator); it and the other run over the same tiles
+void launch_mfma_rows(const Globals &g, int order, bool dual, int grid, hipStream_t s);
+int mfma_rows_grid_size(int order, bool dual);
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
 void launch_pilot_select(const Globals &g, uint32_t max_pilot_slots, hipStream_t s);
 void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s);

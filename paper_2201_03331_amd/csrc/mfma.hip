@@ -23,7 +23,7 @@
 // exact E2M1 values, every product is 0 or 1 and the FP32 accumulators hold
 // integers below 2^24 exactly, so the counts are the same; one instruction
 // takes 64 samples per row instead of 32, and a lane's 32 operand values come
-// from its 32-bit half word by two bit operations per register.
+// from its 32-bit half word by one or two bit operations per register.
 //
 // Order 3 uses the same contraction with prefix pairs as rows: row 4p + 2 g_a
 // + g_b of a fragment is the AND of the genotype rows g_a of a_p and g_b of b
@@ -64,14 +64,23 @@ constexpr uint32_t kRefreshAppends = 16;
 // a cell share one register afterwards: half the registers for finished
 // counts and one exchange between partner lanes instead of two).
 constexpr int kMfmaI8 = 0, kMfmaF4 = 1, kMfmaF4Narrow = 2;
+// FP4 for jobs whose two class sizes fit 24 bits together (bit length of m0
+// plus bit length of m1 at most 24, e.g. both below 4,096): class-1 products
+// carry the scale 2^bitlength(m0), so one FP32 accumulator holds c0 + 2^s c1
+// exactly and the kernel runs 3 waves per SIMD ("dual").  The same launch
+// group also runs the narrow kernel, each kernel skipping the other's jobs.
+constexpr int kMfmaF4Dual = 3;
 
 // Entries of the f table a matrix-core workgroup keeps in LDS (dynamic LDS;
 // jobs with more samples read the table from global memory).  Two
 // workgroups share a compute unit's 160 KB, 80 KB each with their static
 // LDS: up to 12,280 entries next to the 32 KB byte table with int8 operands,
 // 20,448 with FP4 operands (every job of a narrow launch has at most 20,447
-// samples).
-__host__ __device__ constexpr uint32_t mfma_f_entries(int fmt) { return fmt == kMfmaI8 ? 12280u : 20448u; }
+// samples); the dual kernels run 3 workgroups per compute unit, 8,192
+// entries each (jobs of at most 8,191 samples).
+__host__ __device__ constexpr uint32_t mfma_f_entries(int fmt) {
+  return fmt == kMfmaI8 ? 12280u : fmt == kMfmaF4Dual ? 8192u : 20448u;
+}
 
 __device__ __forceinline__ u64 spread8(uint32_t e) {
   const uint32_t lo = ((e & 0xFu) * 0x00204081u) & 0x01010101u;
@@ -204,7 +213,8 @@ __device__ __forceinline__ v8i expand32_fp4_b(uint32_t b) {
 // operands.
 template <int kDepth, int kRaw, typename Load, typename Prep>
 __device__ __forceinline__ void mfma_class_fp4(Load &&load_words, Prep &&prep, uint32_t wbeg,
-                                               uint32_t wend, v16f (&acc)[2][2]) {
+                                               uint32_t wend, v16f (&acc)[2][2],
+                                               int scale_a = kScaleOne) {
   if (wbeg >= wend) return;
   const uint32_t wlast = wend - 1;
   uint32_t X[kDepth][kRaw];
@@ -221,7 +231,7 @@ __device__ __forceinline__ void mfma_class_fp4(Load &&load_words, Prep &&prep, u
 #pragma unroll
       for (int y = 0; y < 2; ++y)
         acc[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-            E[x], E[2 + y], acc[x][y], kFmtFp4, kFmtFp4, 0, kScaleOne, 0, kScaleOne);
+            E[x], E[2 + y], acc[x][y], kFmtFp4, kFmtFp4, 0, scale_a, 0, kScaleOne);
   };
   uint32_t w = wbeg;
   for (; w + kDepth <= wend; w += kDepth) {
@@ -306,6 +316,38 @@ __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Prep &&pr
         Q[x][y][e] = ((P0[x][y][e >> 1] >> (16 * (e & 1))) & 0xFFFFu) | ((uint32_t)f[x][y][e] << 16);
 }
 
+// Both classes with FP4 operands for the dual kernels: class-1 products are
+// scaled by 2^s (s = bit length of m0, given by the caller), so the single
+// FP32 accumulator holds c0 + 2^s c1 < 2^24, an exact integer; Q as for the
+// narrow kernels.
+template <int kDepth, int kRaw, typename Load, typename Prep>
+__device__ __forceinline__ void contract_fp4_dual(Load &&load_words, Prep &&prep, uint32_t W0,
+                                                  uint32_t W1, uint32_t s,
+                                                  uint32_t (&Q)[2][2][16]) {
+  v16f f[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) f[x][y][e] = 0.f;
+  mfma_class_fp4<kDepth, kRaw>(load_words, prep, 0, W0, f);
+  mfma_class_fp4<kDepth, kRaw>(load_words, prep, W0, W0 + W1, f, kScaleOne + (int)s);
+  const uint32_t low = (1u << s) - 1;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const uint32_t u = (uint32_t)f[x][y][e];
+        Q[x][y][e] = (u & low) | ((u >> s) << 16);
+      }
+}
+
+// bit length of x (0 for 0)
+__device__ __forceinline__ uint32_t bit_len(uint32_t x) { return x ? 32u - __clz(x) : 0u; }
+
 // Counts of the lane's combination from output registers elo (the lane's own
 // genotype row gl of the last variant, if gl = 0) and ehi (if gl = 1) of
 // block (x, y): o[class][g_j] after taking the partner lane's (l ^ 1) counts
@@ -316,7 +358,7 @@ template <int FMT>
 __device__ __forceinline__ void partner_counts(const v16i (&acc0)[2][2], const v16i (&acc1)[2][2],
                                                const uint32_t (&Q)[2][2][16], int x, int y, int elo,
                                                int ehi, uint32_t gl, uint32_t (&o)[2][2]) {
-  if constexpr (FMT == kMfmaF4Narrow) {
+  if constexpr (FMT == kMfmaF4Narrow || FMT == kMfmaF4Dual) {
     // both classes in one register: one exchange
     const uint32_t lo = Q[x][y][elo], hi = Q[x][y][ehi];
     const uint32_t own = gl ? hi : lo;
@@ -373,6 +415,8 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
       for (int f = 0; f < 4; ++f) o[f] = x[f];
     };
     if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<4, 4>(load_words, prep, v.W0, v.W1, Q);
+    else if constexpr (FMT == kMfmaF4Dual)
+      contract_fp4_dual<4, 4>(load_words, prep, v.W0, v.W1, bit_len(v.m0), Q);
     else contract_fp4<4, 4>(load_words, prep, v.W0, v.W1, acc0, acc1);
   } else {
     zero_acc(acc0, acc1);
@@ -517,28 +561,27 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
   v16i acc0[2][2], acc1[2][2];  // int8, FP4: counts per class
   uint32_t Q[2][2][16];         // narrow FP4: both classes per register
   if constexpr (FMT != kMfmaI8) {
-    // the lane's 32-bit half of each word: wave-uniform bases (the prefix
-    // block's first variant, b, the last variants' block) advanced by scalar
-    // arithmetic, plus 32-bit lane offsets (a prefix block spans at most 16
-    // variants of Bs)
-    const FI_GLOBAL char *Bsc = reinterpret_cast<const FI_GLOBAL char *>(Bs);
+    // the lane's 32-bit half of each word, every operand from the
+    // variant-fastest rows (Bv): a wave-uniform base per word (scalar
+    // arithmetic) plus 32-bit lane offsets.  A fragment's 8 prefixes are
+    // consecutive variants, so each load of the wave reads contiguous bytes;
+    // prefixes a >= b read variant n, a padding variant whose words are zero.
     const FI_GLOBAL char *Bvc = reinterpret_cast<const FI_GLOBAL char *>(Bv);
-    const size_t vrow = (size_t)v.wcap * 32;         // Bs bytes of one variant
     const size_t word_bytes = (size_t)v.n_pad * 16;  // Bv bytes of one word
     uint32_t oa[2];
 #pragma unroll
-    for (int f = 0; f < 2; ++f)
-      oa[f] = (uint32_t)((const FI_GLOBAL char *)pa[f] - (Bsc + (size_t)a_first * vrow)) + 4 * h;
-    const uint32_t ob = gb * 8 + 4 * h, ol = r * 8 + 4 * h;
+    for (int f = 0; f < 2; ++f) {
+      const uint32_t a = a_first + 8 * f + (r >> 2);
+      oa[f] = (a < b ? a : n) * 16 + ga * 8 + 4 * h;
+    }
+    const uint32_t ob = b * 16 + gb * 8 + 4 * h, ol = j0 * 16 + r * 8 + 4 * h;
     auto load_words = [&](uint32_t w, uint32_t (&x)[5]) {
-      const FI_GLOBAL char *sa = Bsc + (size_t)a_first * vrow + (size_t)w * 32;
-      const FI_GLOBAL char *sb = Bsc + (size_t)b * vrow + (size_t)w * 32;
-      const FI_GLOBAL char *sj = Bvc + (size_t)w * word_bytes + (size_t)j0 * 16;
-      x[0] = ld32(sa, oa[0]);
-      x[1] = ld32(sa, oa[1]);
-      x[2] = ld32(sj, ol);
-      x[3] = ld32(sj, ol + 256);
-      x[4] = ld32(sb, ob);
+      const FI_GLOBAL char *sw = Bvc + (size_t)w * word_bytes;
+      x[0] = ld32(sw, oa[0]);
+      x[1] = ld32(sw, oa[1]);
+      x[2] = ld32(sw, ol);
+      x[3] = ld32(sw, ol + 256);
+      x[4] = ld32(sw, ob);
     };
     // A row = row of a AND row of b
     auto prep = [](const uint32_t (&x)[5], uint32_t (&o)[4]) {
@@ -548,6 +591,8 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
       o[3] = x[3];
     };
     if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<4, 5>(load_words, prep, v.W0, v.W1, Q);
+    else if constexpr (FMT == kMfmaF4Dual)
+      contract_fp4_dual<4, 5>(load_words, prep, v.W0, v.W1, bit_len(v.m0), Q);
     else contract_fp4<4, 5>(load_words, prep, v.W0, v.W1, acc0, acc1);
   } else {
     zero_acc(acc0, acc1);
@@ -703,7 +748,7 @@ struct RowsShape {
 template <int kDepth, int kRaw, int FA, int JB, typename Load, typename Prep>
 __device__ __forceinline__ void mfma_rows_class(Load &&load_words, Prep &&prep, uint32_t wbeg,
                                                 uint32_t wend, v16f (&acc)[FA][JB],
-                                                uint32_t (&np)[FA]) {
+                                                uint32_t (&np)[FA], int scale_a = kScaleOne) {
   if (wbeg >= wend) return;
   const uint32_t wlast = wend - 1;
   uint32_t X[kDepth][kRaw];
@@ -722,7 +767,7 @@ __device__ __forceinline__ void mfma_rows_class(Load &&load_words, Prep &&prep, 
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb)
         acc[fa][jb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-            E[fa], E[FA + jb], acc[fa][jb], kFmtFp4, kFmtFp4, 0, kScaleOne, 0, kScaleOne);
+            E[fa], E[FA + jb], acc[fa][jb], kFmtFp4, kFmtFp4, 0, scale_a, 0, kScaleOne);
   };
   uint32_t w = wbeg;
   for (; w + kDepth <= wend; w += kDepth) {
@@ -738,8 +783,10 @@ __device__ __forceinline__ void mfma_rows_class(Load &&load_words, Prep &&prep, 
     if (w + u < wend) step(u);
 }
 
-// One wave: prefix pre[0 .. K-2] x last variants j0 + [0, 64)
-template <int K>
+// One wave: prefix pre[0 .. K-2] x last variants j0 + [0, 64).  DUAL: both
+// classes in one accumulator, class 1 scaled by 2^bitlen(m0) (exact while
+// bitlen(m0) + bitlen(m1) <= 24), as in the dual order-2/3 kernels
+template <int K, bool DUAL>
 __device__ __forceinline__ void wave_rows(const Globals &g, const JV &v, const uint32_t (&pre)[K - 1],
                                           uint32_t j0, uint32_t lane, const FI_LDS float *F) {
   typedef RowsShape<K> S;
@@ -809,16 +856,22 @@ __device__ __forceinline__ void wave_rows(const Globals &g, const JV &v, const u
     }
     mfma_rows_class<S::kDepth, S::kRaw, FA, JB>(load_words, prep, 0, v.W0, f, np0);
     uint32_t P0[FA][JB][8];
+    const uint32_t sh = bit_len(v.m0), low = (1u << sh) - 1u;
+    if constexpr (DUAL) {
+      mfma_rows_class<S::kDepth, S::kRaw, FA, JB>(load_words, prep, v.W0, v.W0 + v.W1, f, np1,
+                                                  kScaleOne + (int)sh);
+    } else {
 #pragma unroll
-    for (int fa = 0; fa < FA; ++fa)
+      for (int fa = 0; fa < FA; ++fa)
 #pragma unroll
-      for (int jb = 0; jb < JB; ++jb)
+        for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          P0[fa][jb][i] = (uint32_t)f[fa][jb][2 * i] | ((uint32_t)f[fa][jb][2 * i + 1] << 16);
-          f[fa][jb][2 * i] = f[fa][jb][2 * i + 1] = 0.f;
-        }
-    mfma_rows_class<S::kDepth, S::kRaw, FA, JB>(load_words, prep, v.W0, v.W0 + v.W1, f, np1);
+          for (int i = 0; i < 8; ++i) {
+            P0[fa][jb][i] = (uint32_t)f[fa][jb][2 * i] | ((uint32_t)f[fa][jb][2 * i + 1] << 16);
+            f[fa][jb][2 * i] = f[fa][jb][2 * i + 1] = 0.f;
+          }
+      mfma_rows_class<S::kDepth, S::kRaw, FA, JB>(load_words, prep, v.W0, v.W0 + v.W1, f, np1);
+    }
     // prefix row counts of both lane halves, both classes in one register
     uint32_t Np[FA];
 #pragma unroll
@@ -843,8 +896,13 @@ __device__ __forceinline__ void wave_rows(const Globals &g, const JV &v, const u
         for (int e = 0; e < 16; ++e) {
           const uint32_t row = 8 * (e / 4) + 4 * h + (e % 4);
           const uint32_t rho = 32 * fa + row;
-          const uint32_t own = ((P0[fa][jb][e >> 1] >> (16 * (e & 1))) & 0xFFFFu) |
-                               ((uint32_t)f[fa][jb][e] << 16);
+          uint32_t own;
+          if constexpr (DUAL) {
+            const uint32_t u = (uint32_t)f[fa][jb][e];
+            own = (u & low) | ((u >> sh) << 16);
+          } else {
+            own = ((P0[fa][jb][e >> 1] >> (16 * (e & 1))) & 0xFFFFu) | ((uint32_t)f[fa][jb][e] << 16);
+          }
           const uint32_t partner = (uint32_t)__shfl_xor((int)own, 1);
           const uint32_t nr = (uint32_t)__shfl((int)Np[fa], (int)row);
           if (rho < S::R) {
@@ -871,9 +929,15 @@ __device__ __forceinline__ void wave_rows(const Globals &g, const JV &v, const u
 
 // Orders 4 and 5 on the matrix cores: the popcount kernel's tiles (a row per
 // last prefix variant b, 4 prefixes x 64 last variants per tile, one prefix
-// per wave)
-template <int K>
-__global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_rows_kernel(Globals g) {
+// per wave).  The DUAL and the two-accumulator kernels run over the same
+// tiles, each skipping the other's jobs.
+template <int K, bool DUAL>
+constexpr int rows_waves() { return DUAL && K == 4 ? 3 : 2; }
+template <int K, bool DUAL>
+constexpr int rows_f_entries() { return rows_waves<K, DUAL>() == 3 ? mfma_f_entries(kMfmaF4Dual) : mfma_f_entries(kMfmaF4Narrow); }
+
+template <int K, bool DUAL>
+__global__ __launch_bounds__(kMfmaWaves * 64, (rows_waves<K, DUAL>())) void mfma_rows_kernel(Globals g) {
   __shared__ u64 s_tile;
   extern __shared__ float s_f[];
   const uint32_t lane = lane_id();
@@ -892,7 +956,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_rows_kernel(Globals g
       if (jx != f_job) {
         const FI_CONST JobDesc *J = as_const(g.jobs) + jx;
         const uint32_t entries = uni(J->m) + 1;
-        f_lds = entries <= mfma_f_entries(kMfmaF4Narrow);
+        f_lds = entries <= rows_f_entries<K, DUAL>();
         if (f_lds) {
           const FI_GLOBAL float *Fh = as_global(uni_ptr(J->Fh));
           for (uint32_t i = threadIdx.x; i < entries; i += blockDim.x) s_f[i] = Fh[i];
@@ -906,7 +970,18 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_rows_kernel(Globals g
     u64 lt;
     if (!locate_tile(g, t, wave, kMfmaPilotEmits, v, jd, lt)) continue;
     // the host gives this kernel only such jobs
-    if (v.path != kPathMfmaRows || v.k != (uint32_t)K || !f_lds) continue;
+    if (v.path != kPathMfmaRows || v.k != (uint32_t)K) continue;
+    {
+      const bool dual = bit_len(v.m0) + bit_len(v.m1) <= 24 && v.m + 1 <= rows_f_entries<K, true>();
+      if (dual != DUAL) {
+        if (threadIdx.x == 0) {
+          const u64 end = as_const(g.job_tile_start)[job_of_tile(g, t) + 1];
+          atomicMax(g.tile_counter, end - g.tile_base);
+        }
+        continue;
+      }
+    }
+    if (!f_lds) continue;
     cu64p rows = as_const(uni_ptr(jd->row_start));
     uint32_t rl = 0, rh = uni(jd->nrows) - 1;
     while (rl < rh) {
@@ -939,36 +1014,47 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_rows_kernel(Globals g
       pre[rr - 1] = uni(lo);
       hi = lo;
     }
-    wave_rows<K>(g, v, pre, b + 1 + jb * 64, lane, Fl);
+    wave_rows<K, DUAL>(g, v, pre, b + 1 + jb * 64, lane, Fl);
   }
 }
 
-template <int K>
+template <int K, bool DUAL>
 int mfma_rows_grid() {
   int dev = 0, cus = 0, per = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_rows_kernel<K>, kMfmaWaves * 64,
-                                                     mfma_f_entries(kMfmaF4Narrow) * sizeof(float));
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_rows_kernel<K, DUAL>, kMfmaWaves * 64,
+                                                     rows_f_entries<K, DUAL>() * sizeof(float));
   if (cus <= 0) cus = 256;
   if (per <= 0) per = 1;
   return cus * per;
 }
 
-int mfma_rows_grid_size(int order) { return order == 5 ? mfma_rows_grid<5>() : mfma_rows_grid<4>(); }
+int mfma_rows_grid_size(int order, bool dual) {
+  if (order == 5) return dual ? mfma_rows_grid<5, true>() : mfma_rows_grid<5, false>();
+  return dual ? mfma_rows_grid<4, true>() : mfma_rows_grid<4, false>();
+}
 
-void launch_mfma_rows(const Globals &g, int order, int grid, hipStream_t s) {
+void launch_mfma_rows(const Globals &g, int order, bool dual, int grid, hipStream_t s) {
   const dim3 gd(grid), bd(kMfmaWaves * 64);
-  const size_t lds = mfma_f_entries(kMfmaF4Narrow) * sizeof(float);
-  if (order == 5) hipLaunchKernelGGL((mfma_rows_kernel<5>), gd, bd, lds, s, g);
-  else hipLaunchKernelGGL((mfma_rows_kernel<4>), gd, bd, lds, s, g);
+  constexpr size_t l5d = rows_f_entries<5, true>() * sizeof(float);
+  constexpr size_t l5 = rows_f_entries<5, false>() * sizeof(float);
+  constexpr size_t l4d = rows_f_entries<4, true>() * sizeof(float);
+  constexpr size_t l4 = rows_f_entries<4, false>() * sizeof(float);
+  if (order == 5) {
+    if (dual) hipLaunchKernelGGL((mfma_rows_kernel<5, true>), gd, bd, l5d, s, g);
+    else hipLaunchKernelGGL((mfma_rows_kernel<5, false>), gd, bd, l5, s, g);
+  } else {
+    if (dual) hipLaunchKernelGGL((mfma_rows_kernel<4, true>), gd, bd, l4d, s, g);
+    else hipLaunchKernelGGL((mfma_rows_kernel<4, false>), gd, bd, l4, s, g);
+  }
 }
 
 // ORDER 2 or 3, FMT: operand format (kMfmaI8, kMfmaF4, kMfmaF4Narrow); the
 // kernel serves the jobs of that order and format (a batch with several
 // launches it once per group, each over the group's tiles)
 template <int ORDER, int FMT>
-__global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
+__global__ __launch_bounds__(kMfmaWaves * 64, FMT == kMfmaF4Dual ? 3 : 2) void mfma_kernel(Globals g) {
   constexpr bool F4 = FMT != kMfmaI8;
   __shared__ u64 s_tile;
   __shared__ u64 s_lut[F4 ? 1 : 256 * kLutCopies];
@@ -1013,6 +1099,19 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
     // the narrow kernel needs the table in LDS (and so counts below 2^16);
     // the host gives it no other job
     if (FMT == kMfmaF4Narrow && !f_lds) continue;
+    if (FMT == kMfmaF4Narrow || FMT == kMfmaF4Dual) {
+      // the narrow and dual kernels run over the same tiles: each skips the
+      // other's jobs, jumping its tile counter past the job's last tile (the
+      // counter only grows, so no tile of a later job is lost)
+      const bool dual = bit_len(v.m0) + bit_len(v.m1) <= 24 && v.m + 1 <= mfma_f_entries(kMfmaF4Dual);
+      if (dual != (FMT == kMfmaF4Dual)) {
+        if (threadIdx.x == 0) {
+          const u64 end = as_const(g.job_tile_start)[job_of_tile(g, t) + 1];
+          atomicMax(g.tile_counter, end - g.tile_base);
+        }
+        continue;
+      }
+    }
     cu64p rows = as_const(uni_ptr(jd->row_start));
     uint32_t rl = 0, rh = uni(jd->nrows) - 1;
     while (rl < rh) {
@@ -1034,7 +1133,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
       // a wave without a prefix a < b or a last variant j < n has nothing to
       // count; its pilot slots stay zero
       if (a_first >= b || j0 >= v.n) continue;
-      if (FMT == kMfmaF4Narrow || f_lds) wave_prefix3<FMT, true>(g, v, b, a_first, j0, lane, lut, Fl);
+      if (FMT >= kMfmaF4Narrow || f_lds) wave_prefix3<FMT, true>(g, v, b, a_first, j0, lane, lut, Fl);
       else wave_prefix3<FMT, false>(g, v, b, a_first, j0, lane, lut, Fl);
       continue;
     }
@@ -1046,7 +1145,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_kernel(Globals g) {
     // a wave with no pair a < j < n has nothing to count; its pilot slots
     // stay zero
     if (a0 + 1 >= v.n || j0 >= v.n || j0 + 31 <= a0) continue;
-    if (FMT == kMfmaF4Narrow || f_lds) wave_pairs<FMT, true>(v, a0, j0, lane, lut, Fl);
+    if (FMT >= kMfmaF4Narrow || f_lds) wave_pairs<FMT, true>(v, a0, j0, lane, lut, Fl);
     else wave_pairs<FMT, false>(v, a0, j0, lane, lut, Fl);
   }
 }
@@ -1066,9 +1165,9 @@ int mfma_grid() {
 int mfma_grid_size(int order, int fmt) {
   if (order == 3)
     return fmt == kMfmaI8 ? mfma_grid<3, kMfmaI8>() : fmt == kMfmaF4 ? mfma_grid<3, kMfmaF4>()
-                                                                   : mfma_grid<3, kMfmaF4Narrow>();
+           : fmt == kMfmaF4Narrow ? mfma_grid<3, kMfmaF4Narrow>() : mfma_grid<3, kMfmaF4Dual>();
   return fmt == kMfmaI8 ? mfma_grid<2, kMfmaI8>() : fmt == kMfmaF4 ? mfma_grid<2, kMfmaF4>()
-                                                                 : mfma_grid<2, kMfmaF4Narrow>();
+         : fmt == kMfmaF4Narrow ? mfma_grid<2, kMfmaF4Narrow>() : mfma_grid<2, kMfmaF4Dual>();
 }
 
 uint32_t mfma_narrow_max_samples() { return mfma_f_entries(kMfmaF4Narrow) - 1; }
@@ -1079,11 +1178,13 @@ void launch_mfma(const Globals &g, int order, int fmt, int grid, hipStream_t s) 
   if (order == 3) {
     if (fmt == kMfmaI8) hipLaunchKernelGGL((mfma_kernel<3, kMfmaI8>), gd, bd, lds, s, g);
     else if (fmt == kMfmaF4) hipLaunchKernelGGL((mfma_kernel<3, kMfmaF4>), gd, bd, lds, s, g);
-    else hipLaunchKernelGGL((mfma_kernel<3, kMfmaF4Narrow>), gd, bd, lds, s, g);
+    else if (fmt == kMfmaF4Narrow) hipLaunchKernelGGL((mfma_kernel<3, kMfmaF4Narrow>), gd, bd, lds, s, g);
+    else hipLaunchKernelGGL((mfma_kernel<3, kMfmaF4Dual>), gd, bd, lds, s, g);
   } else {
     if (fmt == kMfmaI8) hipLaunchKernelGGL((mfma_kernel<2, kMfmaI8>), gd, bd, lds, s, g);
     else if (fmt == kMfmaF4) hipLaunchKernelGGL((mfma_kernel<2, kMfmaF4>), gd, bd, lds, s, g);
-    else hipLaunchKernelGGL((mfma_kernel<2, kMfmaF4Narrow>), gd, bd, lds, s, g);
+    else if (fmt == kMfmaF4Narrow) hipLaunchKernelGGL((mfma_kernel<2, kMfmaF4Narrow>), gd, bd, lds, s, g);
+    else hipLaunchKernelGGL((mfma_kernel<2, kMfmaF4Dual>), gd, bd, lds, s, g);
   }
 }
 

@@ -209,6 +209,32 @@ def test_fp4_narrow_and_wide_launches(monkeypatch):
         check_hits_against_oracle(d.genotypes, d.phenotype, d.order, d.top_n, hits)
 
 
+def test_fp4_dual_and_narrow_launches(monkeypatch):
+    """Among FP4 jobs with counts in 16 bits, those with at most 8,191 samples
+    whose class sizes m0, m1 satisfy bitlen(m0) + bitlen(m1) <= 24 run the
+    kernel that accumulates both classes in one FP32 register (class 1 scaled
+    by 2^bitlen(m0)); the rest run the two-accumulator kernel over the same
+    tiles.  Jobs at both sides of both limits, both orders, one batch."""
+    monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", "4")
+    monkeypatch.setenv("FIUNCHO_ORDER3_MFMA", "4")
+    # (m, cases): 6143 + 2047 and 2047 + 6143 reach 24 bits exactly; 4096 +
+    # 4095 needs 25; 8192 samples exceed the dual kernel's table
+    shapes = [(8190, 2047), (8190, 6143), (8191, 4095), (8192, 100), (500, 250)]
+    jobs = []
+    for order, n in ((2, 70), (3, 30)):
+        for i, (m, cases) in enumerate(shapes):
+            d = synth.generate(n + i, m, seed=90 + 10 * order + i, order=order, top_n=12,
+                               case_fraction=cases / m)
+            assert d.m == m and int(d.phenotype.sum()) == cases
+            jobs.append(d)
+    say("case: dual and narrow FP4", [(j.n, j.m, j.order) for j in jobs])
+    b = fiuncho.DeviceBatch(jobs)
+    b.run()
+    for d, (status, hits) in zip(jobs, b.results()):
+        assert status == 0
+        check_hits_against_oracle(d.genotypes, d.phenotype, d.order, d.top_n, hits)
+
+
 # ---------------------------------------------------------------------------
 # orders 4 and 5: every prefix row on the matrix cores (FP4)
 # ---------------------------------------------------------------------------
