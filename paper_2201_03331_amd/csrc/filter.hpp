@@ -297,6 +297,64 @@ __device__ __forceinline__ void walk_order3(const Order3Parts &q, Visit &&visit)
   visit(q.m[0] - sum[0], q.m[1] - sum[1]);  // (2, 2, 2)
 }
 
+// The same walk on packed counts: both classes of every count in one
+// register, lo + 2^16 hi.  Sums and differences of packed values are exact
+// modulo 2^32, so a result whose two true halves each lie in [0, 2^16) comes
+// out as exactly those halves, whatever borrows cross between them on the
+// way; every cell is a count of at most the class size.  The halves may carry
+// a common scale (4 x count gives byte offsets into a table of floats: class
+// sizes below 16,384).  D[ga][gb][gj], ab[ga][gb], aj[ga][gj], bj[gb][gj],
+// Ma/Mb/Mj[g], m = both class sizes.
+template <typename Visit>
+__device__ __forceinline__ void walk_order3_packed(const uint32_t (&D)[2][2][2],
+                                                   const uint32_t (&ab)[2][2],
+                                                   const uint32_t (&aj)[2][2],
+                                                   const uint32_t (&bj)[2][2],
+                                                   const uint32_t (&Ma)[2], const uint32_t (&Mb)[2],
+                                                   const uint32_t (&Mj)[2], uint32_t m,
+                                                   Visit &&visit) {
+  uint32_t sum = 0;
+  auto cell = [&](uint32_t p) {
+    sum += p;
+    visit(p);
+  };
+  uint32_t x2z[2][2], t2yz[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int z = 0; z < 2; ++z) cell(D[x][y][z]);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) cell(ab[x][y] - D[x][y][0] - D[x][y][1]);  // (x, y, 2)
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+      x2z[x][z] = aj[x][z] - D[x][0][z] - D[x][1][z];
+      cell(x2z[x][z]);  // (x, 2, z)
+    }
+#pragma unroll
+  for (int y = 0; y < 2; ++y)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+      t2yz[y][z] = bj[y][z] - D[0][y][z] - D[1][y][z];
+      cell(t2yz[y][z]);  // (2, y, z)
+    }
+#pragma unroll
+  for (int x = 0; x < 2; ++x) cell(Ma[x] - ab[x][0] - ab[x][1] - x2z[x][0] - x2z[x][1]);  // (x, 2, 2)
+#pragma unroll
+  for (int y = 0; y < 2; ++y) cell(Mb[y] - ab[0][y] - ab[1][y] - t2yz[y][0] - t2yz[y][1]);  // (2, y, 2)
+#pragma unroll
+  for (int z = 0; z < 2; ++z) cell(Mj[z] - aj[0][z] - aj[1][z] - t2yz[0][z] - t2yz[1][z]);  // (2, 2, z)
+  visit(m - sum);  // (2, 2, 2)
+}
+
+// Class counts (c0, c1) as one packed register of byte offsets 4 c0 | 4 c1 << 16
+__device__ __forceinline__ uint32_t pack_x4(uint32_t c0, uint32_t c1) { return (c0 << 2) | (c1 << 18); }
+
 // Decodes global tile t of a launch: its job (binary search over the job
 // tile starts), the job's view with the run state read in, and the job-local
 // tile index.  In a pilot launch, pilot tile i of S stands for tile

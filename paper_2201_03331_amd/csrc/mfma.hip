@@ -353,7 +353,18 @@ __device__ __forceinline__ uint32_t bit_len(uint32_t x) { return x ? 32u - __clz
 // block (x, y): o[class][g_j] after taking the partner lane's (l ^ 1) counts
 // for the other genotype of j.  Static register indices only: a
 // lane-dependent index into a register array becomes a compare-and-select
-// over every element.
+// over every element.  partner_packed: the same from packed registers (both
+// classes in one, class 0 low), o[g_j] packed.
+__device__ __forceinline__ void partner_packed(const uint32_t (&Q)[2][2][16], int x, int y, int elo,
+                                               int ehi, uint32_t gl, uint32_t (&o)[2]) {
+  const uint32_t lo = Q[x][y][elo], hi = Q[x][y][ehi];
+  const uint32_t own = gl ? hi : lo;
+  const uint32_t send = gl ? lo : hi;
+  const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
+  o[0] = gl ? recv : own;
+  o[1] = gl ? own : recv;
+}
+
 template <int FMT>
 __device__ __forceinline__ void partner_counts(const v16i (&acc0)[2][2], const v16i (&acc1)[2][2],
                                                const uint32_t (&Q)[2][2][16], int x, int y, int elo,
@@ -445,6 +456,11 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
   const MiConst mc = mi_const(v);
   const FI_GLOBAL uint32_t *marg = as_global(v.marg);
   const uint32_t mcls[2] = {v.m0, v.m1};
+  // the scoring on packed byte offsets (both class sizes below 16,384; the
+  // dual kernel's always are), with the table in LDS
+  constexpr bool kPackable = (FMT == kMfmaF4Dual || FMT == kMfmaF4Narrow) && LDS_F;
+  const bool packed = FMT == kMfmaF4Dual || (v.m0 < 16384u && v.m1 < 16384u);
+  const uint32_t m4 = pack_x4(v.m0, v.m1);
   // the scoring reads the f table from the workgroup's LDS copy (LDS_F:
   // it holds this job's table) or from global memory
   float thr = current_threshold(v);
@@ -475,6 +491,49 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
 #pragma unroll
         for (int fb = 0; fb < 2; ++fb) {
           const uint32_t j = jv[fb];
+          if (kPackable && packed) {
+            // the 9 cells as packed byte offsets, 4 x count per class half,
+            // as in the order-3 walk
+            uint32_t C4[2][2];  // [g_a][g_j]
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+              uint32_t o[2];
+              partner_packed(Q, fa, fb, 4 * q + t, 4 * q + 2 + t, gl, o);
+              C4[t][0] = o[0] << 2;
+              C4[t][1] = o[1] << 2;
+            }
+            const bool active = a < j && j < n;
+            float fs = mc.c;
+            if (active) {
+              uint32_t Ma4[2], Mj4[2];
+#pragma unroll
+              for (int gg = 0; gg < 2; ++gg) {
+                Ma4[gg] = pack_x4(Ma[gg][0], Ma[gg][1]);
+                Mj4[gg] = pack_x4(Mj[fb][gg][0], Mj[fb][gg][1]);
+              }
+              const uint32_t t9[9] = {C4[0][0], C4[0][1], Ma4[0] - C4[0][0] - C4[0][1],
+                                      C4[1][0], C4[1][1], Ma4[1] - C4[1][0] - C4[1][1],
+                                      Mj4[0] - C4[0][0] - C4[1][0], Mj4[1] - C4[0][1] - C4[1][1],
+                                      m4 - Ma4[0] - Ma4[1] - Mj4[0] - Mj4[1] + C4[0][0] + C4[0][1] +
+                                          C4[1][0] + C4[1][1]};
+              const FI_LDS char *Fb = (const FI_LDS char *)Fl;
+              float f0[9], f1[9], f01[9];
+#pragma unroll
+              for (int x = 0; x < 9; ++x) {
+                const uint32_t o0 = t9[x] & 0xFFFFu, o1 = t9[x] >> 16;
+                f0[x] = *(const FI_LDS float *)(Fb + o0);
+                f1[x] = *(const FI_LDS float *)(Fb + o1);
+                f01[x] = *(const FI_LDS float *)(Fb + o0 + o1);
+              }
+#pragma unroll
+              for (int x = 0; x < 9; ++x) fs += (f0[x] + f1[x]) - f01[x];
+            }
+            if (emit_with(v, active, fs * mc.inv_m,
+                          [&] { return (u64)a * (n - 1) - (u64)a * (a - 1) / 2 + (j - a - 1); }, thr,
+                          lane) >= kRefreshAppends)
+              thr = current_threshold_lanes(v);
+            continue;
+          }
           uint32_t cnt[2][2][2];  // [g_a][g_j][class]
 #pragma unroll
           for (int t = 0; t < 2; ++t) {
@@ -633,6 +692,15 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
   // the scoring reads the f table from the workgroup's LDS copy (LDS_F:
   // it holds this job's table) or from global memory
   float thr = current_threshold(v);
+  // the walk on packed counts, 4 x count per class half (byte offsets into
+  // the LDS table: both class sizes below 16,384; the dual kernel's always
+  // are)
+  constexpr bool kPackable = (FMT == kMfmaF4Dual || FMT == kMfmaF4Narrow) && LDS_F;
+  const bool packed = FMT == kMfmaF4Dual || (v.m0 < 16384u && v.m1 < 16384u);
+  uint32_t Mb4[2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x) Mb4[x] = pack_x4(Mb[x][0], Mb[x][1]);
+  const uint32_t m4 = pack_x4(v.m0, v.m1);
   auto score = [&](auto F) {
 #pragma unroll
     for (int fb = 0; fb < 2; ++fb) {
@@ -644,12 +712,73 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
 #pragma unroll
         for (int c = 0; c < 2; ++c) Mj[x][c] = marg[(size_t)jj * 6 + 2 * x + c];
       load_pair(PT + ((size_t)b * v.n_pad + jj) * 8, bj);
+      uint32_t Mj4[2], bj4[2][2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        Mj4[x] = pack_x4(Mj[x][0], Mj[x][1]);
+#pragma unroll
+        for (int z = 0; z < 2; ++z) bj4[x][z] = pack_x4(bj[x * 4 + z * 2], bj[x * 4 + z * 2 + 1]);
+      }
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           // this lane's prefix: e / 4 = 2 gl + t
           const uint32_t a = a_first + 8 * f + 2 * (2 * gl + t) + h;
+          if (kPackable && packed) {
+            uint32_t D4[2][2][2];  // [g_a][g_b][g_j], packed x 4
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              uint32_t o[2];
+              partner_packed(Q, f, fb, 4 * t + i, 4 * (2 + t) + i, gl, o);
+              D4[i >> 1][i & 1][0] = o[0] << 2;
+              D4[i >> 1][i & 1][1] = o[1] << 2;
+            }
+            const bool active = a < b && j < n;
+            const uint32_t aa = a < b ? a : b - 1;
+            uint32_t ab[8], aj[8];
+            load_pair(PT + ((size_t)aa * v.n_pad + b) * 8, ab);
+            load_pair(PT + ((size_t)aa * v.n_pad + jj) * 8, aj);
+            uint32_t ab4[2][2], aj4[2][2], Ma4[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+              Ma4[x] = pack_x4(marg[(size_t)aa * 6 + 2 * x], marg[(size_t)aa * 6 + 2 * x + 1]);
+#pragma unroll
+              for (int y = 0; y < 2; ++y) {
+                ab4[x][y] = pack_x4(ab[x * 4 + y * 2], ab[x * 4 + y * 2 + 1]);
+                aj4[x][y] = pack_x4(aj[x * 4 + y * 2], aj[x * 4 + y * 2 + 1]);
+              }
+            }
+            float fs = mc.c;
+            if (active) {
+              constexpr int kGroup = 3;
+              uint32_t o0[kGroup], o1[kGroup];
+              int nc = 0;
+              walk_order3_packed(D4, ab4, aj4, bj4, Ma4, Mb4, Mj4, m4, [&](uint32_t p) {
+                o0[nc] = p & 0xFFFFu;
+                o1[nc] = p >> 16;
+                if (++nc == kGroup) {
+                  const FI_LDS char *Fb = (const FI_LDS char *)Fl;
+                  float f0[kGroup], f1[kGroup], f01[kGroup];
+#pragma unroll
+                  for (int x = 0; x < kGroup; ++x) {
+                    f0[x] = *(const FI_LDS float *)(Fb + o0[x]);
+                    f1[x] = *(const FI_LDS float *)(Fb + o1[x]);
+                    f01[x] = *(const FI_LDS float *)(Fb + o0[x] + o1[x]);
+                  }
+#pragma unroll
+                  for (int x = 0; x < kGroup; ++x) fs += (f0[x] + f1[x]) - f01[x];
+                  nc = 0;
+                }
+              });
+            }
+            const uint32_t pre[2] = {aa, b};
+            if (emit_with(v, active, fs * mc.inv_m,
+                          [&] { return lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1); }, thr,
+                          lane) >= kRefreshAppends)
+              thr = current_threshold_lanes(v);
+            continue;
+          }
           uint32_t D[2][2][2][2];  // [class][g_a][g_b][g_j]
 #pragma unroll
           for (int i = 0; i < 4; ++i) {

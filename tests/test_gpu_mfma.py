@@ -214,12 +214,17 @@ def test_fp4_dual_and_narrow_launches(monkeypatch):
     whose class sizes m0, m1 satisfy bitlen(m0) + bitlen(m1) <= 24 run the
     kernel that accumulates both classes in one FP32 register (class 1 scaled
     by 2^bitlen(m0)); the rest run the two-accumulator kernel over the same
-    tiles.  Jobs at both sides of both limits, both orders, one batch."""
+    tiles.  Both score from packed byte offsets (4 x count per class, 16-bit
+    halves) when both class sizes are below 16,384.  Jobs at both sides of
+    every limit, both orders, one batch."""
     monkeypatch.setenv("FIUNCHO_ORDER2_MFMA", "4")
     monkeypatch.setenv("FIUNCHO_ORDER3_MFMA", "4")
     # (m, cases): 6143 + 2047 and 2047 + 6143 reach 24 bits exactly; 4096 +
-    # 4095 needs 25; 8192 samples exceed the dual kernel's table
-    shapes = [(8190, 2047), (8190, 6143), (8191, 4095), (8192, 100), (500, 250)]
+    # 4095 needs 25; 8192 samples exceed the dual kernel's table; 16,383
+    # controls are the most the packed scoring takes, 16,384 the fewest it
+    # leaves to the per-class scoring
+    shapes = [(8190, 2047), (8190, 6143), (8191, 4095), (8192, 100), (500, 250),
+              (18383, 2000), (18384, 2000)]
     jobs = []
     for order, n in ((2, 70), (3, 30)):
         for i, (m, cases) in enumerate(shapes):
