@@ -57,6 +57,43 @@ __device__ __forceinline__ u64 binom(const Globals &g, uint32_t a, uint32_t r) {
   return g.binom[(size_t)a * kBinomStride + r];
 }
 
+// C(a, r) for the r <= 3 of the tile decoders (r a compile-time constant
+// there) from its closed form in registers, else from the table: the
+// decoders' binary searches then wait on no memory.  Each product is exact
+// in 64 bits for a < 2^21 and vanishes for a < r; larger a read the table.
+__device__ __forceinline__ u64 binom_small(const Globals &g, uint32_t a, uint32_t r) {
+  if (r == 0) return 1;
+  if (r == 1) return a;
+  if (r == 2) return (u64)a * (a - 1u) / 2;
+  if (r == 3 && a < (1u << 21)) return (u64)a * (a - 1u) * (a - 2u) / 6;
+  return binom(g, a, r);
+}
+
+// Colex unrank of the (R)-subset of [0, hi) with index q into pre[0 .. R-1]
+// (ascending): the largest element is the largest v with C(v, R) <= q, and
+// so on down; the last element is the remaining index itself.
+template <int R>
+__device__ __forceinline__ void colex_unrank(const Globals &g, uint32_t hi, u64 q, uint32_t *pre) {
+#pragma unroll
+  for (int r = R; r >= 1; --r) {
+    uint32_t lo;
+    if (r == 1) {
+      lo = (uint32_t)q;
+    } else {
+      lo = (uint32_t)(r - 1);
+      uint32_t top = hi - 1;
+      while (lo < top) {
+        const uint32_t mid = (lo + top + 1) >> 1;
+        if (binom_small(g, mid, r) <= q) lo = mid;
+        else top = mid - 1;
+      }
+      q -= binom_small(g, lo, r);
+    }
+    pre[r - 1] = uni(lo);
+    hi = lo;
+  }
+}
+
 // relaxed loads that read the device-coherent copy (other workgroups update it)
 __device__ __forceinline__ uint32_t load_relaxed(const uint32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

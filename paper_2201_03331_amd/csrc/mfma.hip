@@ -1126,23 +1126,11 @@ __global__ __launch_bounds__(kMfmaWaves * 64, (rows_waves<K, DUAL>())) void mfma
     const u64 grp = local / nj;
     const uint32_t jb = (uint32_t)(local - grp * nj);
     u64 q = grp * kMfmaWaves + wave;
-    if (q >= binom(g, b, K - 2)) continue;
+    if (q >= binom_small(g, b, K - 2)) continue;
     uint32_t pre[K - 1];
     pre[K - 2] = b;
     // colex unrank of the (K-2)-subset of [0, b) with index q
-    uint32_t hi = b;
-#pragma unroll
-    for (int rr = K - 2; rr >= 1; --rr) {
-      uint32_t lo = (uint32_t)(rr - 1), top = hi - 1;
-      while (lo < top) {
-        const uint32_t mid = (lo + top + 1) >> 1;
-        if (binom(g, mid, rr) <= q) lo = mid;
-        else top = mid - 1;
-      }
-      q -= binom(g, lo, rr);
-      pre[rr - 1] = uni(lo);
-      hi = lo;
-    }
+    colex_unrank<K - 2>(g, b, q, pre);
     wave_rows<K, DUAL>(g, v, pre, b + 1 + jb * 64, lane, Fl);
   }
 }

@@ -822,23 +822,11 @@ __device__ __forceinline__ void run_orderk(const Globals &g, const JV &v, uint32
   const u64 grp = local / nj;
   const uint32_t jb = (uint32_t)(local - grp * nj);
   u64 q = grp * kScanWaves + wave;
-  if (q >= binom(g, b, K - 2)) return;
+  if (q >= binom_small(g, b, K - 2)) return;
   uint32_t pre[K - 1];
   pre[K - 2] = b;
   // colex unrank of the (k-2)-subset of [0, b) with index q
-  uint32_t hi = b;
-#pragma unroll
-  for (int r = K - 2; r >= 1; --r) {
-    uint32_t lo = (uint32_t)(r - 1), top = hi - 1;
-    while (lo < top) {
-      const uint32_t mid = (lo + top + 1) >> 1;
-      if (binom(g, mid, r) <= q) lo = mid;
-      else top = mid - 1;
-    }
-    q -= binom(g, lo, r);
-    pre[r - 1] = uni(lo);
-    hi = lo;
-  }
+  colex_unrank<K - 2>(g, b, q, pre);
   if constexpr (TRIPLES && K == 4) tile_order4t(g, v, pre, b + 1 + jb * 64, lane);
   else tile_orderk<K>(g, v, pre, b + 1 + jb * 64, lane);
 }
