@@ -375,6 +375,37 @@ __device__ __forceinline__ uint32_t job_of_tile(const Globals &g, u64 t) {
   return uni(lo);
 }
 
+// Row of tile-local index lt in a job's row table rows[0 .. nrows] (rows[0] =
+// 0 <= lt < rows[nrows]).  hint: the row of an earlier tile of the same job,
+// or 0; the tiles a workgroup draws only increase, and so do their local
+// indices (pilot sampling and shard dealing are monotone), so rows[hint] <=
+// lt, and one load settles the common case of the same row again.
+__device__ __forceinline__ uint32_t find_row(cu64p rows, uint32_t nrows, u64 lt, uint32_t hint) {
+  if (rows[hint + 1] > lt) return hint;
+  uint32_t rl = hint + 1, rh = nrows - 1;
+  while (rl < rh) {
+    const uint32_t mid = (rl + rh + 1) >> 1;
+    if (rows[mid] <= lt) rl = mid;
+    else rh = mid - 1;
+  }
+  return uni(rl);
+}
+
+// The hint find_row may use for job descriptor jd: the last row found when
+// the workgroup's previous tile was of the same job, else 0
+struct RowHint {
+  const FI_CONST JobDesc *jd = nullptr;
+  uint32_t row = 0;
+  __device__ __forceinline__ uint32_t find(const FI_CONST JobDesc *j, u64 lt) {
+    if (j != jd) {
+      jd = j;
+      row = 0;
+    }
+    row = find_row(as_const(uni_ptr(j->row_start)), uni(j->nrows), lt, row);
+    return row;
+  }
+};
+
 __device__ __forceinline__ bool locate_tile(const Globals &g, u64 t, uint32_t wave,
                                             uint32_t slots_per_wave, JV &v,
                                             const FI_CONST JobDesc *&jd, u64 &lt) {

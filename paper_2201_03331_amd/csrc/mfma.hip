@@ -1074,6 +1074,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, (rows_waves<K, DUAL>())) void mfma
   const FI_LDS float *Fl = (const FI_LDS float *)s_f;
   uint32_t f_job = ~0u;
   bool f_lds = false;
+  RowHint hint;  // the row of the workgroup's last tile
   for (;;) {
     if (threadIdx.x == 0) s_tile = g.tile_base + atomicAdd(g.tile_counter, 1ull);
     __syncthreads();
@@ -1112,13 +1113,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, (rows_waves<K, DUAL>())) void mfma
     }
     if (!f_lds) continue;
     cu64p rows = as_const(uni_ptr(jd->row_start));
-    uint32_t rl = 0, rh = uni(jd->nrows) - 1;
-    while (rl < rh) {
-      const uint32_t mid = (rl + rh + 1) >> 1;
-      if (rows[mid] <= lt) rl = mid;
-      else rh = mid - 1;
-    }
-    rl = uni(rl);
+    const uint32_t rl = hint.find(jd, lt);
     const u64 local = uni64(lt - rows[rl]);
     const uint32_t n = v.n;
     const uint32_t b = rl + (K - 2);
@@ -1186,6 +1181,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, FMT == kMfmaF4Dual ? 3 : 2) void m
   const FI_LDS float *Fl = (const FI_LDS float *)s_f;
   uint32_t f_job = ~0u;  // job whose table s_f holds (same in every thread)
   bool f_lds = false;
+  RowHint hint;  // the row of the workgroup's last tile
   for (;;) {
     if (threadIdx.x == 0) s_tile = g.tile_base + atomicAdd(g.tile_counter, 1ull);
     __syncthreads();
@@ -1230,13 +1226,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, FMT == kMfmaF4Dual ? 3 : 2) void m
       }
     }
     cu64p rows = as_const(uni_ptr(jd->row_start));
-    uint32_t rl = 0, rh = uni(jd->nrows) - 1;
-    while (rl < rh) {
-      const uint32_t mid = (rl + rh + 1) >> 1;
-      if (rows[mid] <= lt) rl = mid;
-      else rh = mid - 1;
-    }
-    rl = uni(rl);
+    const uint32_t rl = hint.find(jd, lt);
     const u64 local = uni64(lt - rows[rl]);
     if (ORDER == 3) {
       if (v.path != kPathMfma3) continue;

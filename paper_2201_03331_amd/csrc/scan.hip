@@ -842,6 +842,7 @@ __global__ __launch_bounds__(kScanWaves * 64, scan_min_waves(KSEL)) void scan_ke
   __shared__ u64 s_tile;
   const uint32_t lane = lane_id();
   const uint32_t wave = uni(threadIdx.x >> 6);
+  RowHint hint;  // the row of the workgroup's last tile
   for (;;) {
     if (threadIdx.x == 0) s_tile = g.tile_base + atomicAdd(g.tile_counter, 1ull);
     __syncthreads();
@@ -858,13 +859,7 @@ __global__ __launch_bounds__(kScanWaves * 64, scan_min_waves(KSEL)) void scan_ke
       continue;
     }
     cu64p rows = as_const(uni_ptr(jd->row_start));
-    uint32_t rl = 0, rh = uni(jd->nrows) - 1;
-    while (rl < rh) {
-      const uint32_t mid = (rl + rh + 1) >> 1;
-      if (rows[mid] <= lt) rl = mid;
-      else rh = mid - 1;
-    }
-    rl = uni(rl);
+    const uint32_t rl = hint.find(jd, lt);
     const u64 local = uni64(lt - rows[rl]);
     if (k == 2) {
       if (KSEL == 0 || KSEL == 2 || KSEL == kSel23) {
