@@ -823,15 +823,18 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
       if (L.n_group[q]) {
         const Globals c = launch_globals(g, starts, first, L.n_group[q], pilot, 2 + 2 * q + pilot);
         const int slot = q == 2 ? 0 : q == 5 ? 1 : q >= 6 ? q - 4 : -1;
-        if (slot >= 0 && c.total_tiles > c.tile_base) {
+        // no dual launch when no job of the group has few enough samples
+        const int order = q >= 6 ? q - 2 : 2 + q / 3;
+        uint32_t min_m = ~0u;
+        for (uint32_t i = first; i < first + L.n_group[q]; ++i) min_m = std::min(min_m, L.jobs[L.order[i]].m);
+        if (slot >= 0 && c.total_tiles > c.tile_base && min_m <= fiuncho::mfma_dual_max_samples(order)) {
           Globals d = c;
           d.tile_counter = g.tile_counter + fiuncho::kDualCounters + 2 * slot + pilot;
           const u64 tiles = d.total_tiles - d.tile_base;
           if (q >= 6) {
-            const int grid = (int)std::min<u64>((u64)fiuncho::mfma_rows_grid_size(q - 2, true), tiles);
-            fiuncho::launch_mfma_rows(d, q - 2, true, grid, s);
+            const int grid = (int)std::min<u64>((u64)fiuncho::mfma_rows_grid_size(order, true), tiles);
+            fiuncho::launch_mfma_rows(d, order, true, grid, s);
           } else {
-            const int order = 2 + q / 3;
             const int grid = (int)std::min<u64>((u64)fiuncho::mfma_grid_size(order, 3), tiles);
             fiuncho::launch_mfma(d, order, 3, grid, s);
           }

@@ -160,6 +160,8 @@ uint32_t mfma_narrow_max_samples();
 // dual: the kernel that takes the jobs whose class sizes fit 24 bits together
 // (both classes in one accumulator); it and the other run over the same tiles
 void launch_mfma_rows(const Globals &g, int order, bool dual, int grid, hipStream_t s);
+// the most samples a job of this order may have for the dual kernel
+uint32_t mfma_dual_max_samples(int order);
 int mfma_rows_grid_size(int order, bool dual);
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
 void launch_pilot_select(const Globals &g, uint32_t max_pilot_slots, hipStream_t s);

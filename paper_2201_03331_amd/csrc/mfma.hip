@@ -1073,7 +1073,6 @@ __global__ __launch_bounds__(kMfmaWaves * 64, (rows_waves<K, DUAL>())) void mfma
   const uint32_t wave = uni(threadIdx.x >> 6);
   const FI_LDS float *Fl = (const FI_LDS float *)s_f;
   uint32_t f_job = ~0u;
-  bool f_lds = false;
   RowHint hint;  // the row of the workgroup's last tile
   for (;;) {
     if (threadIdx.x == 0) s_tile = g.tile_base + atomicAdd(g.tile_counter, 1ull);
@@ -1081,20 +1080,6 @@ __global__ __launch_bounds__(kMfmaWaves * 64, (rows_waves<K, DUAL>())) void mfma
     const u64 t = uni64(s_tile);
     __syncthreads();
     if (t >= g.total_tiles) break;
-    {
-      const uint32_t jx = job_of_tile(g, t);
-      if (jx != f_job) {
-        const FI_CONST JobDesc *J = as_const(g.jobs) + jx;
-        const uint32_t entries = uni(J->m) + 1;
-        f_lds = entries <= rows_f_entries<K, DUAL>();
-        if (f_lds) {
-          const FI_GLOBAL float *Fh = as_global(uni_ptr(J->Fh));
-          for (uint32_t i = threadIdx.x; i < entries; i += blockDim.x) s_f[i] = Fh[i];
-        }
-        f_job = jx;
-        __syncthreads();
-      }
-    }
     JV v;
     const FI_CONST JobDesc *jd;
     u64 lt;
@@ -1111,7 +1096,18 @@ __global__ __launch_bounds__(kMfmaWaves * 64, (rows_waves<K, DUAL>())) void mfma
         continue;
       }
     }
-    if (!f_lds) continue;
+    if (v.m + 1 > rows_f_entries<K, DUAL>()) continue;
+    {
+      // the job's table, once the tile is known to be this kernel's (every
+      // wave has finished the previous tile: the barriers above)
+      const uint32_t jx = (uint32_t)(jd - as_const(g.jobs));
+      if (jx != f_job) {
+        const FI_GLOBAL float *Fh = as_global(uni_ptr(jd->Fh));
+        for (uint32_t i = threadIdx.x; i <= v.m; i += blockDim.x) s_f[i] = Fh[i];
+        f_job = jx;
+        __syncthreads();
+      }
+    }
     cu64p rows = as_const(uni_ptr(jd->row_start));
     const uint32_t rl = hint.find(jd, lt);
     const u64 local = uni64(lt - rows[rl]);
@@ -1140,6 +1136,11 @@ int mfma_rows_grid() {
   if (cus <= 0) cus = 256;
   if (per <= 0) per = 1;
   return cus * per;
+}
+
+uint32_t mfma_dual_max_samples(int order) {
+  return order == 5 ? rows_f_entries<5, true>() - 1
+         : order == 4 ? rows_f_entries<4, true>() - 1 : mfma_f_entries(kMfmaF4Dual) - 1;
 }
 
 int mfma_rows_grid_size(int order, bool dual) {
@@ -1188,30 +1189,15 @@ __global__ __launch_bounds__(kMfmaWaves * 64, FMT == kMfmaF4Dual ? 3 : 2) void m
     const u64 t = uni64(s_tile);
     __syncthreads();
     if (t >= g.total_tiles) break;
-    {
-      // every wave of the workgroup has finished the previous tile (the
-      // barriers above), so the table can be replaced
-      const uint32_t jx = job_of_tile(g, t);
-      if (jx != f_job) {
-        const FI_CONST JobDesc *J = as_const(g.jobs) + jx;
-        const uint32_t entries = uni(J->m) + 1;
-        f_lds = entries <= mfma_f_entries(FMT);
-        if (f_lds) {
-          const FI_GLOBAL float *Fh = as_global(uni_ptr(J->Fh));
-          for (uint32_t i = threadIdx.x; i < entries; i += blockDim.x) s_f[i] = Fh[i];
-        }
-        f_job = jx;
-        __syncthreads();
-      }
-    }
     JV v;
     const FI_CONST JobDesc *jd;
     u64 lt;
     if (!locate_tile(g, t, wave, kMfmaPilotEmits, v, jd, lt)) continue;
     if (v.fp4 != (F4 ? 1u : 0u)) continue;
+    const bool fits = v.m + 1 <= mfma_f_entries(FMT);
     // the narrow kernel needs the table in LDS (and so counts below 2^16);
     // the host gives it no other job
-    if (FMT == kMfmaF4Narrow && !f_lds) continue;
+    if (FMT == kMfmaF4Narrow && !fits) continue;
     if (FMT == kMfmaF4Narrow || FMT == kMfmaF4Dual) {
       // the narrow and dual kernels run over the same tiles: each skips the
       // other's jobs, jumping its tile counter past the job's last tile (the
@@ -1223,6 +1209,21 @@ __global__ __launch_bounds__(kMfmaWaves * 64, FMT == kMfmaF4Dual ? 3 : 2) void m
           atomicMax(g.tile_counter, end - g.tile_base);
         }
         continue;
+      }
+    }
+    {
+      // the job's table, once the tile is known to be this kernel's: every
+      // wave of the workgroup has finished the previous tile (the barriers
+      // above), so the table can be replaced
+      const uint32_t jx = (uint32_t)(jd - as_const(g.jobs));
+      if (jx != f_job) {
+        f_lds = fits;
+        if (f_lds) {
+          const FI_GLOBAL float *Fh = as_global(uni_ptr(jd->Fh));
+          for (uint32_t i = threadIdx.x; i <= v.m; i += blockDim.x) s_f[i] = Fh[i];
+        }
+        f_job = jx;
+        __syncthreads();
       }
     }
     cu64p rows = as_const(uni_ptr(jd->row_start));
