@@ -310,6 +310,31 @@ def test_orders45_rows_large_samples_fall_back(rows_kernel):
     check_hits_against_oracle(G, y, 4, 20, hits)
 
 
+def test_orders45_dual_and_two_accumulator_launches(rows_kernel):
+    """Orders 4 and 5 on the matrix cores: jobs whose class sizes fit 24 bits
+    together, and whose f table fits the dual kernel's LDS (8,192 entries at
+    order 4, 20,448 at order 5), run with both classes in one accumulator;
+    the rest run the two-accumulator kernel over the same tiles.  Jobs at
+    both sides of every limit, both orders, one batch."""
+    # (m, cases): 6143 + 2047 reach 24 bits exactly; 4096 + 4095 need 25;
+    # 9,000 samples exceed the order-4 dual table; 11,500 + 500 fit 23 bits
+    # (dual at order 5 only); 19,447 + 1,000 need 25
+    shapes = [(8190, 2047), (8191, 4095), (9000, 4500), (12000, 500), (20447, 1000), (500, 250)]
+    jobs = []
+    for k, n in ((4, 10), (5, 9)):
+        for i, (m, cases) in enumerate(shapes):
+            rows_kernel(n + i, m, k)
+            d = synth.generate(n + i, m, seed=700 + 10 * k + i, order=k, top_n=12, case_fraction=cases / m)
+            assert d.m == m and int(d.phenotype.sum()) == cases
+            jobs.append(d)
+    say("case: orders 4/5 dual and two-accumulator", [(j.n, j.m, j.order) for j in jobs])
+    b = fiuncho.DeviceBatch(jobs)
+    b.run()
+    for d, (status, hits) in zip(jobs, b.results()):
+        assert status == 0
+        check_hits_against_oracle(d.genotypes, d.phenotype, d.order, d.top_n, hits)
+
+
 def test_every_launch_group_in_one_batch(rows_kernel, monkeypatch):
     """One batch with a job in each matrix-core launch group (orders 2 and 3
     with int8, FP4 and 16-bit-count FP4 operands; orders 4 and 5 with every
