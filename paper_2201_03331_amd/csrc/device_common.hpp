@@ -57,9 +57,9 @@ __device__ __forceinline__ u64 binom(const Globals &g, uint32_t a, uint32_t r) {
   return g.binom[(size_t)a * kBinomStride + r];
 }
 
-// C(a, r) for the r <= 3 of the tile decoders (r a compile-time constant
-// there) from its closed form in registers, else from the table: the
-// decoders' binary searches then wait on no memory.  Each product is exact
+// C(a, r) for r <= 3 from its closed form in registers, else from the table:
+// the binary searches of the tile decoders and of the rank conversions then
+// wait on no memory for subsets of up to 3 variants.  Each product is exact
 // in 64 bits for a < 2^21 and vanishes for a < r; larger a read the table.
 __device__ __forceinline__ u64 binom_small(const Globals &g, uint32_t a, uint32_t r) {
   if (r == 0) return 1;
@@ -108,15 +108,15 @@ __device__ inline void lex_unrank(const Globals &g, uint32_t n, uint32_t k, u64 
   int64_t prev = -1;
   for (uint32_t i = 0; i < k; ++i) {
     uint32_t r = k - 1 - i;
-    u64 top = binom(g, (uint32_t)(n - prev - 1), r + 1);
+    u64 top = binom_small(g, (uint32_t)(n - prev - 1), r + 1);
     // largest v in [prev+1, n-1-r] with top - C(n - v, r + 1) <= rank
     uint32_t lo = (uint32_t)(prev + 1), hi = n - 1 - r;
     while (lo < hi) {
       uint32_t mid = (lo + hi + 1) >> 1;
-      if (top - binom(g, n - mid, r + 1) <= rank) lo = mid;
+      if (top - binom_small(g, n - mid, r + 1) <= rank) lo = mid;
       else hi = mid - 1;
     }
-    rank -= top - binom(g, n - lo, r + 1);
+    rank -= top - binom_small(g, n - lo, r + 1);
     c[i] = lo;
     prev = lo;
   }
@@ -130,7 +130,7 @@ __device__ inline u64 lex_rank_prefix(const Globals &g, uint32_t n, uint32_t k,
   u64 r = 0;
   int64_t prev = -1;
   for (uint32_t i = 0; i + 1 < k; ++i) {
-    r += binom(g, (uint32_t)(n - prev - 1), k - i) - binom(g, n - p[i], k - i);
+    r += binom_small(g, (uint32_t)(n - prev - 1), k - i) - binom_small(g, n - p[i], k - i);
     prev = p[i];
   }
   return r;

@@ -519,7 +519,9 @@ void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipSt
   uint32_t cells = 1;
   for (uint32_t q = 0; q < max_k; ++q) cells *= 3;
   const size_t lds = sizeof(uint32_t) * 2 * cells;
-  hipLaunchKernelGGL(rescore_kernel, dim3(std::min<uint32_t>(max_l2_cap, 512), g.n_jobs), dim3(64), lds, s, g);
+  // one candidate per workgroup up to 2,048 kept candidates: each one's work
+  // is a chain of dependent steps (unrank, count, score)
+  hipLaunchKernelGGL(rescore_kernel, dim3(std::min<uint32_t>(max_l2_cap, 2048), g.n_jobs), dim3(64), lds, s, g);
 }
 
 void launch_finish(const Globals &g, hipStream_t s) {
