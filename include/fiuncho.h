@@ -54,22 +54,48 @@ enum {
   FIUNCHO_E_ORDER = -5,     /* order < 1, order > 8 or order > snps */
   FIUNCHO_E_TOPN = -6,      /* top_n == 0 or top_n > FIUNCHO_MAX_TOPN */
   FIUNCHO_E_OVERFLOW = -7,  /* C(snps, order) >= 2^63 */
-  FIUNCHO_E_WORKSPACE = -8, /* workspace too small, or more near-ties at the
-                               cut-off than the candidate buffers hold */
-  FIUNCHO_E_DEVICE = -9     /* a HIP runtime error or no usable gfx950 device */
+  FIUNCHO_E_WORKSPACE = -8, /* workspace too small, or (batched calls) more
+                               candidates than the candidate buffer holds;
+                               fiuncho_scan enlarges its buffer and retries */
+  FIUNCHO_E_DEVICE = -9,    /* a HIP runtime error or no usable gfx950 device */
+  FIUNCHO_E_INTERNAL = -10  /* a self-check failed: the counting kernel's
+                               single-precision estimate of a rescored
+                               combination was farther from its exact MI than
+                               twice fiuncho_estimate_bound (never expected;
+                               the result is withheld) */
 };
 
-/* Largest supported top_n. */
-#define FIUNCHO_MAX_TOPN 2048u
+/* Largest supported top_n.  The device workspace grows with it: the
+ * candidate buffers hold about 32 * min(C(snps, order), max(2^20, 256 top_n))
+ * bytes and the results 64 + 48 bytes per result. */
+#define FIUNCHO_MAX_TOPN (1u << 24)
 
-/* One reported combination. */
+/* One reported combination (64 bytes). */
 typedef struct {
   uint32_t snp[FIUNCHO_MAX_ORDER]; /* ascending variant indices; unused = UINT32_MAX */
   uint64_t rank;                   /* lexicographic rank in [0, C(snps, order)) */
   double mi;                       /* mutual information, IEEE double, nats */
-  float mi32;                      /* the single-precision score used for selection */
-  float rel_err;                   /* |mi32 - mi| / mi, 0 when mi == 0 */
+  float mi32;                      /* compensated single-precision MI of the exact table */
+  float rel_err;                   /* |mi32 - mi| / mi, |mi32 - mi| when mi == 0 */
+  float est;                       /* the plain single-precision MI the counting
+                                      kernel computed from its own counts, the
+                                      score the search filtered on; within
+                                      fiuncho_estimate_bound(order, samples) of mi
+                                      (0 for a dataset with an empty class) */
+  uint32_t reserved;               /* 0 */
 } fiuncho_hit;
+
+/*
+ * fiuncho_estimate_bound -- bound of |est - mi| for any combination of this
+ * order in a dataset of this many samples (section 3.3, Eq. 1-3 evaluated in
+ * single precision as m MI = [f(m) - f(m0) - f(m1)] + sum over cells of
+ * [f(n0) + f(n1) - f(n0 + n1)], f(t) = t ln t from a float table):
+ * u (6 ln m + (3^order + 4) ln 2), u = 2^-24.  The search keeps every
+ * combination whose estimate lies within 4 times this bound of the top_n-th
+ * best estimate, so none of the exact best top_n is lost.  Returns a negative
+ * value for an order outside [1, 8] or samples == 0.
+ */
+double fiuncho_estimate_bound(int order, uint32_t samples);
 
 /*
  * fiuncho_scan -- the whole exhaustive search on one dataset (Fig. 1,
@@ -77,7 +103,8 @@ typedef struct {
  *   genotypes  host pointer, [snps][samples] uint8 (see conventions)
  *   phenotype  host pointer, [samples] uint8
  *   order      interaction order k, 1..8
- *   top_n      how many combinations to report, 1..FIUNCHO_MAX_TOPN
+ *   top_n      how many combinations to report, 1..FIUNCHO_MAX_TOPN (any number
+ *              of exact ties at the cut-off is resolved by rank)
  *   out        host array of at least top_n hits, written best first
  *   n_out      receives min(top_n, C(snps, order))
  * All inputs are validated on the host before any device work.  A dataset with
@@ -156,8 +183,11 @@ int fiuncho_scan_batch(const fiuncho_job *jobs, uint32_t n_jobs, uint32_t flags,
  *   genotypes, phenotype  host arrays as in fiuncho_scan
  *   ranks      host array of n_ranks lexicographic ranks, each < C(snps, order)
  *   tables     host array of n_ranks * 3^order * 2 uint32, [rank][cell][class]
- * Synchronous.  Counts come from the same bit-packed genotype tables and
- * AND/popcount device code as the search.
+ * Synchronous.  The tables are counted from the same bit-packed genotype
+ * tables as the search, by the kernel that rescores the search's kept
+ * candidates (AND of the cell's rows, one population count per class and
+ * cell), not by the search's counting kernels; those are checked through the
+ * estimates they return with every hit (fiuncho_hit.est).
  */
 int fiuncho_contingency(const uint8_t *genotypes, const uint8_t *phenotype,
                         uint32_t snps, uint32_t samples, int order,

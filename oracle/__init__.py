@@ -140,26 +140,61 @@ def mi(T) -> float:
     return float(lib().oracle_mi(_p(T, ctypes.c_uint32), k))
 
 
-def score_ranks(G, y, k: int, ranks, want_tables: bool = False):
-    """MI (and optionally tables) of the combinations with the given ranks."""
+def host_threads() -> int:
+    """Host CPUs this process may run on."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def score_ranks(G, y, k: int, ranks, want_tables: bool = False, nthreads: int = 0):
+    """MI (and optionally tables) of the combinations with the given ranks.
+    Long lists are split into contiguous parts scored by concurrent calls
+    (``nthreads``; 0 = every host CPU); each rank is scored alone, so the
+    values do not depend on the split."""
     G, y = _arrays(G, y)
     r = np.ascontiguousarray(ranks, dtype=np.uint64)
     mi_out = np.zeros(len(r), dtype=np.float64)
     tabs = np.zeros((len(r), 3 ** k, 2), dtype=np.uint32) if want_tables else None
-    st = lib().oracle_score_ranks(
-        _p(G, ctypes.c_uint8), _p(y, ctypes.c_uint8), G.shape[0], G.shape[1], k,
-        _p(r, ctypes.c_uint64), len(r), _p(mi_out, ctypes.c_double),
-        _p(tabs, ctypes.c_uint32) if want_tables else None)
-    if st != OK:
-        raise ValueError(f"oracle_score_ranks failed: {st}")
+    L = lib()
+
+    def part(lo, hi):
+        return L.oracle_score_ranks(
+            _p(G, ctypes.c_uint8), _p(y, ctypes.c_uint8), G.shape[0], G.shape[1], k,
+            _p(r[lo:hi], ctypes.c_uint64), hi - lo, _p(mi_out[lo:hi], ctypes.c_double),
+            _p(tabs[lo:hi], ctypes.c_uint32) if want_tables else None)
+
+    nt = nthreads if nthreads > 0 else host_threads()
+    nt = max(1, min(nt, len(r) // 4096))
+    if nt == 1:
+        sts = [part(0, len(r))]
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        cuts = np.linspace(0, len(r), nt + 1).astype(np.int64)
+        with ThreadPoolExecutor(nt) as ex:
+            sts = list(ex.map(lambda i: part(int(cuts[i]), int(cuts[i + 1])), range(nt)))
+    for st in sts:
+        if st != OK:
+            raise ValueError(f"oracle_score_ranks failed: {st}")
     return (mi_out, tabs) if want_tables else mi_out
+
+
+def order_all(G, y, k: int, nthreads: int = 0):
+    """Every combination of order k: (ranks, mi) in the output order (MI
+    descending, rank ascending), each combination scored by the oracle."""
+    total = binom(np.asarray(G).shape[0], k)
+    ranks = np.arange(total, dtype=np.uint64)
+    mi_all = score_ranks(G, y, k, ranks, nthreads=nthreads)
+    order = np.lexsort((ranks, -mi_all))
+    return ranks[order], mi_all[order]
 
 
 def scan_range(G, y, k: int, top_n: int, first: int, count: int, nthreads: int = 0):
     """Best ``top_n`` of ranks [first, first+count): (ranks, mi) best first."""
     G, y = _arrays(G, y)
     if nthreads <= 0:
-        nthreads = os.cpu_count() or 1
+        nthreads = host_threads()
     cap = min(top_n, max(count, 1))
     out_r = np.zeros(cap, dtype=np.uint64)
     out_m = np.zeros(cap, dtype=np.float64)

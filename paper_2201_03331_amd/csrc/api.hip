@@ -18,7 +18,7 @@ using fiuncho::Cand;
 using fiuncho::Globals;
 using fiuncho::JobDesc;
 using fiuncho::JobState;
-using fiuncho::Rescored;
+using fiuncho::SortItem;
 
 namespace {
 
@@ -304,9 +304,9 @@ uint32_t job_path(uint32_t n, uint32_t m, uint32_t k) { return kernel_path(choos
 struct JobLayout {
   uint32_t n, m, k, top_n, n_pad, wcap, nrows, path, fp4, shard_index, shard_count;
   u64 total;
-  uint32_t cand_cap, l1_cap, l2_cap;
-  size_t off_G, off_y, off_idx, off_Bv, off_Bs, off_marg, off_hist, off_phist, off_cand, off_l1, off_l2,
-      off_state, off_out, off_nout, off_status, off_pairs, off_triples;
+  uint32_t cand_cap, l1_cap, sel_cap;
+  size_t off_G, off_y, off_idx, off_Bv, off_Bs, off_marg, off_hist, off_phist, off_cand, off_l1, off_sel,
+      off_sel2, off_state, off_out, off_nout, off_status, off_pairs, off_triples;
   // plan (uploaded)
   size_t off_rows, off_F32, off_Fh, off_P64;
   std::vector<u64> row_start;
@@ -328,7 +328,7 @@ int mfma_group(const JobLayout &J) {
 struct Layout {
   std::vector<JobLayout> jobs;
   std::vector<uint32_t> order;  // tile-space order of the jobs (costliest first)
-  uint32_t nmax, kmax, max_n_pad, max_wcap, max_cand_cap, max_l2_cap, max_pairs_n, max_triples_n;
+  uint32_t nmax, kmax, max_n_pad, max_wcap, max_cand_cap, max_sel, max_pairs_n, max_triples_n;
   size_t plan_begin, plan_end;  // uploaded region
   size_t off_desc, off_jts, off_jps, off_binom, off_counter;
   // tile-space order: [0, n_scan) popcount kernel, then the jobs of each
@@ -347,7 +347,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
   L.max_n_pad = 0;
   L.max_wcap = 0;
   L.max_cand_cap = 0;
-  L.max_l2_cap = 0;
+  L.max_sel = 0;
   L.max_pairs_n = 0;
   L.max_triples_n = 0;
   size_t off = 0;
@@ -368,7 +368,9 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     cap = std::min<u64>(cap, 1ull << 31);
     J.cand_cap = (uint32_t)std::max<u64>(cap, 1);
     J.l1_cap = J.cand_cap;
-    J.l2_cap = fiuncho::kSortMax;
+    // room for every result: the results are gathered here when more than
+    // kSortMax candidates are kept
+    J.sel_cap = (uint32_t)std::max<u64>(std::min<u64>(J.top_n, J.total), 1);
     const int kern = choose_kernel(J.n, J.m, J.k);
     J.path = kernel_path(kern, J.k);
     J.fp4 = kern == FIUNCHO_KERNEL_MFMA_FP4;
@@ -422,7 +424,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     L.max_n_pad = std::max(L.max_n_pad, J.n_pad);
     L.max_wcap = std::max(L.max_wcap, J.wcap);
     L.max_cand_cap = std::max(L.max_cand_cap, J.cand_cap);
-    L.max_l2_cap = std::max(L.max_l2_cap, J.l2_cap);
+    L.max_sel = std::max(L.max_sel, J.sel_cap);
 
     auto take = [&](size_t bytes) {
       size_t o = off;
@@ -439,7 +441,8 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     J.off_phist = J.pilot_tiles ? take(sizeof(uint32_t) * fiuncho::kHistBins) : 0;
     J.off_cand = take(sizeof(Cand) * (size_t)J.cand_cap);
     J.off_l1 = take(sizeof(Cand) * (size_t)J.l1_cap);
-    J.off_l2 = take(sizeof(Rescored) * (size_t)J.l2_cap);
+    J.off_sel = take(sizeof(SortItem) * (size_t)J.sel_cap);
+    J.off_sel2 = J.sel_cap > fiuncho::kSortMax ? take(sizeof(SortItem) * (size_t)J.sel_cap) : 0;
     J.off_state = take(sizeof(JobState));
     J.off_out = host_inputs ? take(sizeof(fiuncho_hit) * J.top_n) : 0;
     J.off_nout = host_inputs ? take(sizeof(uint32_t)) : 0;
@@ -513,14 +516,15 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
 //   cells:        sum_x u (3 f(n_x) + n_x ln 2) <= u (3 f(m) + m ln 2)
 //   accumulation: 3^k additions of at most u m ln 2 each
 //   final scaling: 2u ln 2 on MI
-// so |estimate - MI| <= u (6 ln m + (3^k + 4) ln 2); twice that is used.
-float fbound(uint32_t k, uint32_t m) {
+// so |estimate - MI| <= u (6 ln m + (3^k + 4) ln 2) (estimate_bound); the
+// filters use twice that (fbound).
+double estimate_bound(uint32_t k, uint32_t m) {
   double cells = 1;
   for (uint32_t i = 0; i < k; ++i) cells *= 3;
   const double u = std::ldexp(1.0, -24);
-  const double b = 2.0 * u * (6.0 * std::log((double)m) + (cells + 4.0) * std::log(2.0));
-  return (float)(b * 1.0001);
+  return u * (6.0 * std::log((double)m) + (cells + 4.0) * std::log(2.0));
 }
+float fbound(uint32_t k, uint32_t m) { return (float)(2.0 * estimate_bound(k, m) * 1.0001); }
 
 // ---------------------------------------------------------------------------
 // plan: descriptors and lookup tables, built on the host
@@ -595,8 +599,9 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
     d.cand_cap = J.cand_cap;
     d.l1_cap = J.l1_cap;
     d.l1 = reinterpret_cast<Cand *>(ws + J.off_l1);
-    d.l2 = reinterpret_cast<Rescored *>(ws + J.off_l2);
-    d.l2_cap = J.l2_cap;
+    d.sel = reinterpret_cast<SortItem *>(ws + J.off_sel);
+    d.sel2 = J.off_sel2 ? reinterpret_cast<SortItem *>(ws + J.off_sel2) : nullptr;
+    d.sel_cap = J.sel_cap;
     d.path = J.path;
     d.fp4 = J.fp4;
     d.shard_index = J.shard_index;
@@ -857,8 +862,9 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   mfma_groups(ts, false);
   if ((st = prof_record(4, s))) return st;
   fiuncho::launch_select(g, L.max_cand_cap, s);
-  fiuncho::launch_rescore(g, L.max_l2_cap, L.kmax, s);
+  fiuncho::launch_rescore(g, L.kmax, s);
   fiuncho::launch_finish(g, s);
+  fiuncho::launch_big_sort(g, L.max_sel, s);
   if ((st = prof_record(5, s))) return st;
   HIP_TRY(hipGetLastError());
   return FIUNCHO_OK;
@@ -924,9 +930,9 @@ int batch_impl(const fiuncho_job *jobs, uint32_t n_jobs, uint32_t flags, void *w
         first_err = status[i];
         if (states[i].flags & fiuncho::kFlagCandOverflow)
           fail(status[i], "candidate buffer overflow in job " + std::to_string(i));
-        else if (states[i].flags & fiuncho::kFlagTieOverflow)
-          fail(status[i], "more than " + std::to_string(fiuncho::kSortMax) +
-                              " candidates tie within tolerance at the cut-off in job " + std::to_string(i));
+        else if (states[i].flags & fiuncho::kFlagBound)
+          fail(status[i], "self-check failed in job " + std::to_string(i) +
+                              ": a counting kernel's estimate is farther from the exact MI than its bound");
         else
           fail(status[i], "job " + std::to_string(i) + " failed on the device");
       }
@@ -987,6 +993,11 @@ int owned_workspace(size_t need, void **out) {
 extern "C" {
 
 const char *fiuncho_last_error(void) { return t_err.c_str(); }
+
+double fiuncho_estimate_bound(int order, uint32_t samples) {
+  if (order < 1 || order > FIUNCHO_MAX_ORDER || samples == 0) return -1.0;
+  return estimate_bound((uint32_t)order, samples);
+}
 
 void fiuncho_set_profiling(int enable) { t_profiling = enable != 0; }
 

@@ -17,6 +17,7 @@ constexpr int kJBlock = 64;                   // last variants per tile (one per
 constexpr int kHistShift = 20;                // survivor histogram bin = key >> 20
 constexpr int kHistBins = 1 << (31 - kHistShift);
 constexpr uint32_t kSortMax = 8192;           // candidates ordered in one LDS sort
+constexpr uint32_t kChunkSort = 4096;         // items per LDS sort of the multi-block sort
 constexpr int kScanWaves = 4;                 // waves per workgroup in the scan
 constexpr int kOrder2Prefixes = 4;            // first variants per wave at order 2
 constexpr int kOrder3Prefixes = 2;            // prefixes per wave, order-3 pair path
@@ -59,12 +60,12 @@ struct JobState {
   uint32_t l2_count;          // candidates within the tolerance of the N-th best
   uint32_t kth_key;           // exact N-th largest FP32 key among candidates
   uint32_t flags;             // kFlag* bits
-  uint32_t pad[4];
+  uint32_t n_sel;             // results left to the multi-block sort (0: none)
+  uint32_t pad[3];
 };
 
 constexpr uint32_t kFlagCandOverflow = 1u;    // candidate buffer too small
-constexpr uint32_t kFlagTieOverflow = 2u;     // too many near-ties for the final sort
-constexpr uint32_t kFlagBound = 4u;           // |mi32 - mi| exceeded the stated bound
+constexpr uint32_t kFlagBound = 4u;           // |estimate - mi| exceeded the stated bound
 
 struct Cand {                 // one appended candidate
   unsigned long long rank;
@@ -72,12 +73,20 @@ struct Cand {                 // one appended candidate
   float est;                  // plain single-precision MI (within fbound of MI)
 };
 
-struct Rescored {             // candidate after rescoring
-  unsigned long long rank;
+// Exact scores of kept candidate i, written over entry i of the candidate
+// buffer (dead once the candidates are compacted into l1)
+struct Scored {
   double mi;                  // IEEE double, Eq. 1-3 term by term
   float mi32;                 // compensated single precision
-  float est;                  // the scan's plain single-precision estimate
-  uint32_t snp[kMaxOrder];
+  uint32_t pad;
+};
+static_assert(sizeof(Scored) <= sizeof(Cand), "scores overlay the candidate buffer");
+
+struct SortItem {             // a result being ordered by (mi desc, rank asc)
+  double mi;
+  unsigned long long rank;
+  uint32_t idx;               // index of the candidate in l1 (and its Scored)
+  uint32_t pad;
 };
 
 // everything the kernels need about one job; built by the host, uploaded once
@@ -108,9 +117,10 @@ struct JobDesc {
   Cand *cand;
   uint32_t cand_cap;
   uint32_t l1_cap;
-  Cand *l1;
-  Rescored *l2;
-  uint32_t l2_cap;
+  Cand *l1;                   // compacted candidates; its first l2_count are kept
+  SortItem *sel;              // [sel_cap] the selected results, when more than kSortMax
+  SortItem *sel2;             // [sel_cap] second buffer of the multi-block sort (top_n > kSortMax)
+  uint32_t sel_cap;
   uint32_t path;              // kPathGeneric or kPathPairs
   JobState *state;
   uint32_t *pairs;            // kPathPairs, kPathTriples: [n][n_pad][g_a 0..1][g_j 0..1][class] counts
@@ -165,8 +175,11 @@ uint32_t mfma_dual_max_samples(int order);
 int mfma_rows_grid_size(int order, bool dual);
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
 void launch_pilot_select(const Globals &g, uint32_t max_pilot_slots, hipStream_t s);
-void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s);
+void launch_rescore(const Globals &g, uint32_t max_k, hipStream_t s);
 void launch_finish(const Globals &g, hipStream_t s);
+// ordering of more than kSortMax results (jobs with top_n > kSortMax): chunk
+// sorts, merge passes up to max_sel items, then the hits
+void launch_big_sort(const Globals &g, uint32_t max_sel, hipStream_t s);
 void launch_tables(const Globals &g, const unsigned long long *ranks, uint64_t n_ranks,
                    uint32_t *tables, float *est, float *mi32, double *mi, uint32_t k,
                    hipStream_t s);

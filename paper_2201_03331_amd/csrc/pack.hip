@@ -40,6 +40,7 @@ __global__ void init_kernel(Globals g) {
     st->l2_count = 0;
     st->kth_key = 0;
     st->flags = 0;
+    st->n_sel = 0;
     if (blockIdx.x == 0)
       for (int i = 0; i < kTileCounters; ++i) g.tile_counter[i] = 0;
   }

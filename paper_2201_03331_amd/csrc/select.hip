@@ -158,46 +158,55 @@ __global__ __launch_bounds__(64) void pilot_tau_kernel(Globals g) {
 }
 
 // 2. one workgroup per job: radix selection of the top_n-th largest key over
-// the compacted candidates, then the final candidate set.
+// the compacted candidates, then the final candidate set, compacted in place
+// to the front of l1 (order kept): a chunk's entries are all read before any
+// of its kept entries is written, and a kept entry only moves down.
 __global__ __launch_bounds__(1024) void select_kernel(Globals g) {
   const JobDesc &J = g.jobs[blockIdx.x];
   JobState *st = J.state;
   if (st->status != 0 || st->m0 == 0 || st->m1 == 0) return;
   if (st->flags & kFlagCandOverflow) return;
   __shared__ RadixLds s;
-  __shared__ uint32_t s_count;
-  const uint32_t tid = threadIdx.x;
+  __shared__ uint32_t s_wcnt[kRadixThreads / 64];
+  __shared__ uint32_t s_base;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const uint32_t M = min(st->l1_count, J.l1_cap);
   const uint32_t N = J.top_n;
-  float thr2;
-  if (M <= N) {
-    thr2 = -INFINITY;  // every candidate is kept
-  } else {
-    const uint32_t kth = radix_kth_largest([&](uint32_t i) { return J.l1[i].key; }, M, N, s);
-    if (tid == 0) st->kth_key = kth;
-    thr2 = tol_threshold(J, __uint_as_float(kth));
+  if (M <= N) {  // every candidate is kept
+    if (tid == 0) st->l2_count = M;
+    return;
   }
-  if (tid == 0) s_count = 0;
-  __syncthreads();
-  for (uint32_t i = tid; i < M; i += blockDim.x) {
-    const Cand c = J.l1[i];
-    if (c.est >= thr2) {
-      const uint32_t at = atomicAdd(&s_count, 1u);
-      if (at < J.l2_cap) {
-        Rescored r;
-        r.rank = c.rank;
-        r.est = c.est;
-        r.mi32 = 0.f;
-        r.mi = 0.0;
-        J.l2[at] = r;
-      }
-    }
-  }
-  __syncthreads();
+  const uint32_t kth = radix_kth_largest([&](uint32_t i) { return J.l1[i].key; }, M, N, s);
   if (tid == 0) {
-    st->l2_count = s_count;
-    if (s_count > J.l2_cap) st->flags |= kFlagTieOverflow;
+    st->kth_key = kth;
+    s_base = 0;
   }
+  const float thr2 = tol_threshold(J, __uint_as_float(kth));
+  __syncthreads();
+  const u64 below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (uint32_t i0 = 0; i0 < M; i0 += blockDim.x) {
+    const uint32_t i = i0 + tid;
+    Cand c;
+    bool keep = false;
+    if (i < M) {
+      c = J.l1[i];
+      keep = c.est >= thr2;
+    }
+    const u64 mask = ballot(keep);
+    if (lane == 0) s_wcnt[wv] = popc64(mask);
+    __syncthreads();
+    uint32_t at = s_base;
+    for (uint32_t q = 0; q < wv; ++q) at += s_wcnt[q];
+    if (keep) J.l1[at + popc64(mask & below)] = c;
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t t = s_base;
+      for (uint32_t q = 0; q < kRadixThreads / 64; ++q) t += s_wcnt[q];
+      s_base = t;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) st->l2_count = s_base;
 }
 
 // 3. one wave per kept candidate: recount the contingency table with one lane
@@ -331,104 +340,151 @@ __device__ float mi32_compensated(const float2 *__restrict__ F, const uint32_t *
 
 constexpr int kMaxCells = 6561;  // 3^8
 
+// 3. one workgroup (one wave) per kept candidate l1[i], i < l2_count: its
+// exact table, MI in double precision and compensated single precision,
+// written to entry i of the candidate buffer (as Scored)
 __global__ __launch_bounds__(64) void rescore_kernel(Globals g) {
   const JobDesc &J = g.jobs[blockIdx.y];
   JobState *st = J.state;
   if (st->status != 0 || st->m0 == 0 || st->m1 == 0) return;
-  if (st->flags & (kFlagCandOverflow | kFlagTieOverflow)) return;
+  if (st->flags & kFlagCandOverflow) return;
   extern __shared__ uint32_t lds_t[];
   const uint32_t lane = lane_id();
-  const uint32_t count = min(st->l2_count, J.l2_cap);
+  const uint32_t count = st->l2_count;
+  Scored *sc = reinterpret_cast<Scored *>(J.cand);
   uint32_t cells = 1;
   for (uint32_t q = 0; q < J.k; ++q) cells *= 3;
   for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
-    Rescored r = J.l2[i];
+    const Cand cd = J.l1[i];
     uint32_t c[kMaxOrder];
-    lex_unrank(g, J.n, J.k, r.rank, c);
+    lex_unrank(g, J.n, J.k, cd.rank, c);
     count_cells<false>(J, st, c, J.k, lane, lds_t, nullptr);
     __syncthreads();
     if (lane == 0) {
-      const double mi = mi64_of_table(J.P64, lds_t, cells, st->m0, st->m1);
-      r.mi = mi;
+      Scored r;
+      r.mi = mi64_of_table(J.P64, lds_t, cells, st->m0, st->m1);
       r.mi32 = mi32_compensated(J.F32, lds_t, cells, J.m, st->m0, st->m1);
+      r.pad = 0;
       // the filters assumed |estimate - mi| <= fbound
-      if (fabs((double)r.est - mi) > (double)J.fbound) atomicOr(&st->flags, kFlagBound);
-      for (uint32_t q = 0; q < kMaxOrder; ++q) r.snp[q] = q < J.k ? c[q] : 0xffffffffu;
-      J.l2[i] = r;
+      if (fabs((double)cd.est - r.mi) > (double)J.fbound) atomicOr(&st->flags, kFlagBound);
+      sc[i] = r;
     }
     __syncthreads();
   }
 }
 
-// 4. one workgroup per job: bitonic sort of the rescored candidates in LDS by
-// (mi descending, rank ascending) and output of the first top_n.
-__global__ __launch_bounds__(1024) void finish_kernel(Globals g) {
-  const JobDesc &J = g.jobs[blockIdx.x];
-  JobState *st = J.state;
-  const uint32_t tid = threadIdx.x;
-  __shared__ double s_mi[kSortMax];
-  __shared__ u64 s_rank[kSortMax];
-  __shared__ uint16_t s_idx[kSortMax];
-  int32_t status = st->status;
-  if (status == 0 && (st->flags & kFlagCandOverflow)) status = FIUNCHO_E_WORKSPACE;
-  if (status == 0 && (st->flags & kFlagTieOverflow)) status = FIUNCHO_E_WORKSPACE;
-  const u64 want64 = J.total < (u64)J.top_n ? J.total : (u64)J.top_n;
-  const uint32_t want = (uint32_t)want64;
-  if (status != 0) {
-    if (tid == 0) {
-      *J.n_out = 0;
-      if (J.status_out) *J.status_out = status;
-    }
-    return;
+// A result as the caller sees it: the combination unranked from its rank
+__device__ fiuncho_hit make_hit(const Globals &g, const JobDesc &J, u64 rank, double mi, float mi32,
+                                float est) {
+  fiuncho_hit h;
+  uint32_t c[kMaxOrder];
+  lex_unrank(g, J.n, J.k, rank, c);
+  for (uint32_t q = 0; q < kMaxOrder; ++q) h.snp[q] = q < J.k ? c[q] : 0xffffffffu;
+  h.rank = rank;
+  h.mi = mi;
+  h.mi32 = mi32;
+  const double d = fabs((double)mi32 - mi);
+  h.rel_err = mi != 0.0 ? (float)(d / fabs(mi)) : (float)d;
+  h.est = est;
+  h.reserved = 0;
+  return h;
+}
+
+// An unsigned integer whose order is the order of the double d (finite d)
+__device__ __forceinline__ u64 order_key(double d) {
+  const u64 b = (u64)__double_as_longlong(d);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// (mi, rank) of a precedes (mi, rank) of b in the output order
+__device__ __forceinline__ bool precedes(double ma, u64 ra, double mb, u64 rb) {
+  return ma > mb || (ma == mb && ra < rb);
+}
+
+// Radix selection of the N-th largest of 64-bit keys among the elements i in
+// [0, M) that take part (key_at(i, key) returns whether element i does; at
+// least N do), by one workgroup of kRadixThreads threads: six passes of 11,
+// 11, 11, 11, 10 and 10 bits, each histogramming the keys that match the
+// digits found so far.  Returns the key; *ties_in receives how many of the
+// elements equal to it belong to the N largest.
+struct RadixLds64 {
+  uint32_t hist[2048];
+  uint32_t wsum[kRadixThreads / 64];
+  u64 prefix;
+  uint32_t need;
+};
+
+template <typename KeyAt>
+__device__ u64 radix_kth_largest64(KeyAt key_at, uint32_t M, uint32_t N, RadixLds64 &s,
+                                   uint32_t *ties_in) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) {
+    s.prefix = 0;
+    s.need = N;
   }
-  if (st->m0 == 0 || st->m1 == 0) {
-    // an empty class: every table is independent of the class, MI = 0, and the
-    // total order makes the result the first top_n ranks (of a shard: the
-    // first top_n ranks congruent to shard_index modulo shard_count)
-    const u64 sc = J.shard_count, si = J.shard_index;
-    const u64 share = J.total > si ? (J.total - si + sc - 1) / sc : 0;
-    const uint32_t want_e = (uint32_t)(share < (u64)J.top_n ? share : (u64)J.top_n);
-    for (uint32_t i = tid; i < want_e; i += blockDim.x) {
-      fiuncho_hit h;
-      uint32_t c[kMaxOrder];
-      const u64 r = si + (u64)i * sc;
-      lex_unrank(g, J.n, J.k, r, c);
-      for (uint32_t q = 0; q < kMaxOrder; ++q) h.snp[q] = q < J.k ? c[q] : 0xffffffffu;
-      h.rank = r;
-      h.mi = 0.0;
-      h.mi32 = 0.f;
-      h.rel_err = 0.f;
-      J.out[i] = h;
+  const int shifts[6] = {53, 42, 31, 20, 10, 0};
+  const int widths[6] = {11, 11, 11, 11, 10, 10};
+  u64 known = 0;
+  for (int pass = 0; pass < 6; ++pass) {
+    for (uint32_t i = tid; i < 2048; i += kRadixThreads) s.hist[i] = 0;
+    __syncthreads();
+    const u64 prefix = s.prefix;
+    const uint32_t need = s.need;
+    const uint32_t bins = 1u << widths[pass];
+    for (uint32_t i = tid; i < M; i += kRadixThreads) {
+      u64 key;
+      if (key_at(i, key) && (key & known) == prefix)
+        atomicAdd(&s.hist[(uint32_t)(key >> shifts[pass]) & (bins - 1)], 1u);
     }
-    if (tid == 0) {
-      *J.n_out = want_e;
-      if (J.status_out) *J.status_out = 0;
+    __syncthreads();
+    // thread t owns `per` consecutive bins counted from the top
+    const uint32_t per = (bins + kRadixThreads - 1) / kRadixThreads;
+    const uint32_t top = bins - 1 - tid * per;
+    uint32_t mine = 0;
+    for (uint32_t q = 0; q < per; ++q)
+      if (tid * per + q < bins) mine += s.hist[top - q];
+    uint32_t inc = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t o = __shfl_up(inc, off);
+      if (lane >= (uint32_t)off) inc += o;
     }
-    return;
+    if (lane == 63) s.wsum[wv] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t q = 0; q < wv; ++q) before += s.wsum[q];
+    const uint32_t excl = before + inc - mine;
+    if (tid * per < bins && excl < need && (excl + mine >= need || tid * per + per >= bins)) {
+      uint32_t run = excl;
+      uint32_t bin = top;
+      for (uint32_t q = 0; q < per && tid * per + q < bins; ++q) {
+        bin = top - q;
+        if (run + s.hist[bin] >= need || bin == 0) break;
+        run += s.hist[bin];
+      }
+      s.need = need - run;
+      s.prefix = prefix | ((u64)bin << shifts[pass]);
+    }
+    known |= (u64)(bins - 1) << shifts[pass];
+    __syncthreads();
   }
-  const uint32_t M = min(st->l2_count, J.l2_cap);
-  uint32_t P = 1;
-  while (P < M) P <<= 1;
-  for (uint32_t i = tid; i < P; i += blockDim.x) {
-    if (i < M) {
-      s_mi[i] = J.l2[i].mi;
-      s_rank[i] = J.l2[i].rank;
-    } else {
-      s_mi[i] = -INFINITY;
-      s_rank[i] = ~0ull;
-    }
-    s_idx[i] = (uint16_t)i;
-  }
+  const u64 kth = s.prefix;
+  if (ties_in) *ties_in = s.need;
   __syncthreads();
-  // ascending in "badness": element a precedes b when a.mi > b.mi, or equal
-  // mi and a.rank < b.rank
+  return kth;
+}
+
+// Bitonic sort in LDS of P (a power of two) items by (mi descending, rank
+// ascending), carrying a 16-bit index
+__device__ void lds_sort(double *s_mi, u64 *s_rank, uint16_t *s_idx, uint32_t P) {
+  const uint32_t tid = threadIdx.x;
   for (uint32_t size = 2; size <= P; size <<= 1) {
     for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
       for (uint32_t i = tid; i < P; i += blockDim.x) {
         const uint32_t jx = i ^ stride;
         if (jx > i) {
           const bool up = (i & size) == 0;
-          const bool i_first = s_mi[i] > s_mi[jx] || (s_mi[i] == s_mi[jx] && s_rank[i] < s_rank[jx]);
+          const bool i_first = precedes(s_mi[i], s_rank[i], s_mi[jx], s_rank[jx]);
           if (i_first != up) {
             const double tm = s_mi[i];
             s_mi[i] = s_mi[jx];
@@ -445,20 +501,238 @@ __global__ __launch_bounds__(1024) void finish_kernel(Globals g) {
       __syncthreads();
     }
   }
+}
+
+// 4. one workgroup per job: the first min(top_n, C(n, k)) results by (mi
+// descending, rank ascending).  Up to kSortMax kept candidates are sorted in
+// LDS.  More (near-ties at the cut-off, or a large top_n) are first reduced
+// to exactly the results by two radix selections (the N-th largest MI, then
+// among the candidates with that MI the ranks that complete the N) and
+// gathered into sel; those are sorted in LDS when they fit, else left to the
+// multi-block sort.
+__global__ __launch_bounds__(1024) void finish_kernel(Globals g) {
+  const JobDesc &J = g.jobs[blockIdx.x];
+  JobState *st = J.state;
+  const uint32_t tid = threadIdx.x;
+  __shared__ double s_mi[kSortMax];
+  __shared__ u64 s_rank[kSortMax];
+  __shared__ uint16_t s_idx[kSortMax];
+  __shared__ RadixLds64 rs;
+  __shared__ uint32_t s_count;
+  int32_t status = st->status;
+  if (status == 0 && (st->flags & kFlagCandOverflow)) status = FIUNCHO_E_WORKSPACE;
+  if (status == 0 && (st->flags & kFlagBound)) status = FIUNCHO_E_INTERNAL;
+  const u64 want64 = J.total < (u64)J.top_n ? J.total : (u64)J.top_n;
+  const uint32_t want = (uint32_t)want64;
+  if (status != 0) {
+    if (tid == 0) {
+      *J.n_out = 0;
+      if (J.status_out) *J.status_out = status;
+    }
+    return;
+  }
+  if (st->m0 == 0 || st->m1 == 0) {
+    // an empty class: every table is independent of the class, MI = 0, and the
+    // total order makes the result the first top_n ranks (of a shard: the
+    // first top_n ranks congruent to shard_index modulo shard_count)
+    const u64 sc = J.shard_count, si = J.shard_index;
+    const u64 share = J.total > si ? (J.total - si + sc - 1) / sc : 0;
+    const uint32_t want_e = (uint32_t)(share < (u64)J.top_n ? share : (u64)J.top_n);
+    for (uint32_t i = tid; i < want_e; i += blockDim.x) J.out[i] = make_hit(g, J, si + (u64)i * sc, 0.0, 0.f, 0.f);
+    if (tid == 0) {
+      *J.n_out = want_e;
+      if (J.status_out) *J.status_out = 0;
+    }
+    return;
+  }
+  const uint32_t M = st->l2_count;
+  const Scored *sc = reinterpret_cast<const Scored *>(J.cand);
   const uint32_t outn = min(want, M);
+  bool from_sel = false;
+  if (M > kSortMax) {
+    // reduce the M kept candidates to exactly the outn results, in sel
+    u64 kth = 0, rcut = ~0ull;
+    if (outn < M) {
+      uint32_t ties = 0;
+      kth = radix_kth_largest64(
+          [&](uint32_t i, u64 &key) {
+            key = order_key(sc[i].mi);
+            return true;
+          },
+          M, outn, rs, &ties);
+      // among the candidates whose MI has that key, the `ties` smallest ranks
+      rcut = ~radix_kth_largest64(
+          [&](uint32_t i, u64 &key) {
+            key = ~J.l1[i].rank;
+            return order_key(sc[i].mi) == kth;
+          },
+          M, ties, rs, nullptr);
+    }
+    if (tid == 0) s_count = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < M; i += blockDim.x) {
+      const double mi = sc[i].mi;
+      const u64 key = order_key(mi), rank = J.l1[i].rank;
+      if (outn == M || key > kth || (key == kth && rank <= rcut)) {
+        const uint32_t at = atomicAdd(&s_count, 1u);
+        if (at < J.sel_cap) {
+          SortItem it;
+          it.mi = mi;
+          it.rank = rank;
+          it.idx = i;
+          it.pad = 0;
+          J.sel[at] = it;
+        }
+      }
+    }
+    __syncthreads();
+    if (outn > kSortMax) {
+      // ordered by the multi-block sort, which also writes the hits
+      if (tid == 0) st->n_sel = outn;
+      return;
+    }
+    from_sel = true;
+  }
+  // LDS sort of min(M, kSortMax) items: the kept candidates, or the selected
+  // results in sel
+  const uint32_t L = from_sel ? outn : M;
+  uint32_t P = 1;
+  while (P < L) P <<= 1;
+  for (uint32_t i = tid; i < P; i += blockDim.x) {
+    if (i < L) {
+      if (from_sel) {
+        const SortItem it = J.sel[i];
+        s_mi[i] = it.mi;
+        s_rank[i] = it.rank;
+      } else {
+        s_mi[i] = sc[i].mi;
+        s_rank[i] = J.l1[i].rank;
+      }
+    } else {
+      s_mi[i] = -INFINITY;
+      s_rank[i] = ~0ull;
+    }
+    s_idx[i] = (uint16_t)i;
+  }
+  __syncthreads();
+  lds_sort(s_mi, s_rank, s_idx, P);
   for (uint32_t i = tid; i < outn; i += blockDim.x) {
-    const Rescored r = J.l2[s_idx[i]];
-    fiuncho_hit h;
-    for (uint32_t q = 0; q < kMaxOrder; ++q) h.snp[q] = r.snp[q];
-    h.rank = r.rank;
-    h.mi = r.mi;
-    h.mi32 = r.mi32;
-    const double d = fabs((double)r.mi32 - r.mi);
-    h.rel_err = r.mi != 0.0 ? (float)(d / fabs(r.mi)) : (float)d;
-    J.out[i] = h;
+    const uint32_t c = from_sel ? J.sel[s_idx[i]].idx : s_idx[i];
+    J.out[i] = make_hit(g, J, s_rank[i], s_mi[i], sc[c].mi32, J.l1[c].est);
   }
   if (tid == 0) {
     *J.n_out = outn;
+    if (J.status_out) *J.status_out = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Multi-block ordering of more than kSortMax results (jobs whose top_n
+// exceeds kSortMax; n_sel of them in sel): chunks of kChunkSort sorted in LDS,
+// then merge passes of doubling run length (each item finds its place by a
+// binary search in the partner run; ranks are unique, so places are too),
+// then the hits.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void sort_chunks_kernel(Globals g) {
+  const JobDesc &J = g.jobs[blockIdx.y];
+  const uint32_t n = J.state->n_sel;
+  const uint32_t base = blockIdx.x * kChunkSort;
+  if (n == 0 || base >= n) return;
+  __shared__ double s_mi[kChunkSort];
+  __shared__ u64 s_rank[kChunkSort];
+  __shared__ uint32_t s_idx[kChunkSort];
+  const uint32_t cnt = min(kChunkSort, n - base);
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < kChunkSort; i += blockDim.x) {
+    if (i < cnt) {
+      const SortItem it = J.sel[base + i];
+      s_mi[i] = it.mi;
+      s_rank[i] = it.rank;
+      s_idx[i] = it.idx;
+    } else {
+      s_mi[i] = -INFINITY;
+      s_rank[i] = ~0ull;
+      s_idx[i] = 0;
+    }
+  }
+  __syncthreads();
+  for (uint32_t size = 2; size <= kChunkSort; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = tid; i < kChunkSort; i += blockDim.x) {
+        const uint32_t jx = i ^ stride;
+        if (jx > i) {
+          const bool up = (i & size) == 0;
+          if (precedes(s_mi[i], s_rank[i], s_mi[jx], s_rank[jx]) != up) {
+            const double tm = s_mi[i];
+            s_mi[i] = s_mi[jx];
+            s_mi[jx] = tm;
+            const u64 tr = s_rank[i];
+            s_rank[i] = s_rank[jx];
+            s_rank[jx] = tr;
+            const uint32_t ti = s_idx[i];
+            s_idx[i] = s_idx[jx];
+            s_idx[jx] = ti;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t i = tid; i < cnt; i += blockDim.x) {
+    SortItem it;
+    it.mi = s_mi[i];
+    it.rank = s_rank[i];
+    it.idx = s_idx[i];
+    it.pad = 0;
+    J.sel[base + i] = it;
+  }
+}
+
+// one merge pass: sorted runs of `width` items, from sel to sel2 (to_sel2) or
+// back; an item without a partner run keeps its place
+__global__ __launch_bounds__(256) void merge_pass_kernel(Globals g, uint32_t width, int to_sel2) {
+  const JobDesc &J = g.jobs[blockIdx.y];
+  const uint32_t n = J.state->n_sel;
+  if (n == 0) return;
+  const SortItem *src = to_sel2 ? J.sel : J.sel2;
+  SortItem *dst = to_sel2 ? J.sel2 : J.sel;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const SortItem it = src[i];
+    const uint32_t r = i / width;
+    const uint32_t start = r * width;
+    const u64 pstart64 = (u64)(r ^ 1u) * width;
+    uint32_t pos = i;
+    if (pstart64 < n) {
+      const uint32_t pstart = (uint32_t)pstart64;
+      const uint32_t plen = min(width, n - pstart);
+      // partner items that precede this one
+      uint32_t lo = 0, hi = plen;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        const SortItem p = src[pstart + mid];
+        if (precedes(p.mi, p.rank, it.mi, it.rank)) lo = mid + 1;
+        else hi = mid;
+      }
+      pos = min(start, pstart) + (i - start) + lo;
+    }
+    dst[pos] = it;
+  }
+}
+
+// the hits of the ordered results (in sel or sel2)
+__global__ __launch_bounds__(256) void sorted_hits_kernel(Globals g, int in_sel2) {
+  const JobDesc &J = g.jobs[blockIdx.y];
+  JobState *st = J.state;
+  const uint32_t n = st->n_sel;
+  if (n == 0) return;
+  const SortItem *src = in_sel2 ? J.sel2 : J.sel;
+  const Scored *sc = reinterpret_cast<const Scored *>(J.cand);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const SortItem it = src[i];
+    J.out[i] = make_hit(g, J, it.rank, it.mi, sc[it.idx].mi32, J.l1[it.idx].est);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *J.n_out = n;
     if (J.status_out) *J.status_out = 0;
   }
 }
@@ -515,17 +789,31 @@ void launch_pilot_select(const Globals &g, uint32_t max_pilot_slots, hipStream_t
   hipLaunchKernelGGL(pilot_tau_kernel, dim3(g.n_jobs), dim3(64), 0, s, g);
 }
 
-void launch_rescore(const Globals &g, uint32_t max_l2_cap, uint32_t max_k, hipStream_t s) {
+void launch_rescore(const Globals &g, uint32_t max_k, hipStream_t s) {
   uint32_t cells = 1;
   for (uint32_t q = 0; q < max_k; ++q) cells *= 3;
   const size_t lds = sizeof(uint32_t) * 2 * cells;
   // one candidate per workgroup up to 2,048 kept candidates: each one's work
   // is a chain of dependent steps (unrank, count, score)
-  hipLaunchKernelGGL(rescore_kernel, dim3(std::min<uint32_t>(max_l2_cap, 2048), g.n_jobs), dim3(64), lds, s, g);
+  hipLaunchKernelGGL(rescore_kernel, dim3(2048, g.n_jobs), dim3(64), lds, s, g);
 }
 
 void launch_finish(const Globals &g, hipStream_t s) {
   hipLaunchKernelGGL(finish_kernel, dim3(g.n_jobs), dim3(1024), 0, s, g);
+}
+
+void launch_big_sort(const Globals &g, uint32_t max_sel, hipStream_t s) {
+  if (max_sel <= kSortMax) return;
+  const uint32_t chunks = (max_sel + kChunkSort - 1) / kChunkSort;
+  hipLaunchKernelGGL(sort_chunks_kernel, dim3(chunks, g.n_jobs), dim3(1024), 0, s, g);
+  const uint32_t blocks = std::min<uint32_t>((max_sel + 255) / 256, 4096);
+  int in_sel2 = 0;
+  for (uint64_t width = kChunkSort; width < max_sel; width <<= 1) {
+    hipLaunchKernelGGL(merge_pass_kernel, dim3(blocks, g.n_jobs), dim3(256), 0, s, g, (uint32_t)width,
+                       in_sel2 ? 0 : 1);
+    in_sel2 ^= 1;
+  }
+  hipLaunchKernelGGL(sorted_hits_kernel, dim3(blocks, g.n_jobs), dim3(256), 0, s, g, in_sel2);
 }
 
 void launch_tables(const Globals &g, const unsigned long long *ranks, uint64_t n_ranks,

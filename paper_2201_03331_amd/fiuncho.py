@@ -8,6 +8,7 @@ PyTorch is used only for device memory and streams (``DeviceBatch``).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -25,8 +26,9 @@ E_TOPN = -6
 E_OVERFLOW = -7
 E_WORKSPACE = -8
 E_DEVICE = -9
+E_INTERNAL = -10
 MAX_ORDER = 8
-MAX_TOPN = 2048
+MAX_TOPN = 1 << 24
 DEVICE_PTRS = 1
 UPLOAD_PLAN = 2
 KERNEL_AUTO = 0
@@ -48,13 +50,14 @@ EXPORTS = (
     "fiuncho_set_kernel",
     "fiuncho_autotune",
     "fiuncho_last_error",
+    "fiuncho_estimate_bound",
     "fiuncho_set_profiling",
     "fiuncho_get_profile",
 )
 
 HIT_DTYPE = np.dtype([("snp", "<u4", (MAX_ORDER,)), ("rank", "<u8"), ("mi", "<f8"),
-                      ("mi32", "<f4"), ("rel_err", "<f4")])
-assert HIT_DTYPE.itemsize == 56
+                      ("mi32", "<f4"), ("rel_err", "<f4"), ("est", "<f4"), ("reserved", "<u4")])
+assert HIT_DTYPE.itemsize == 64
 
 
 class Job(ctypes.Structure):
@@ -143,6 +146,8 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(ctypes.c_int)]
         L.fiuncho_last_error.restype = ctypes.c_char_p
         L.fiuncho_last_error.argtypes = []
+        L.fiuncho_estimate_bound.restype = ctypes.c_double
+        L.fiuncho_estimate_bound.argtypes = [ctypes.c_int, ctypes.c_uint32]
         L.fiuncho_set_profiling.restype = None
         L.fiuncho_set_profiling.argtypes = [ctypes.c_int]
         L.fiuncho_get_profile.restype = ctypes.c_int
@@ -153,6 +158,12 @@ def lib() -> ctypes.CDLL:
 
 def last_error() -> str:
     return lib().fiuncho_last_error().decode()
+
+
+def estimate_bound(order: int, samples: int) -> float:
+    """Bound of |est - mi| for this order and sample count
+    (fiuncho_estimate_bound)."""
+    return float(lib().fiuncho_estimate_bound(order, samples))
 
 
 def _check(code: int):
@@ -171,7 +182,9 @@ def _host_arrays(G, y):
 def scan(G, y, order: int, top_n: int) -> np.ndarray:
     """Exhaustive search on host arrays (fiuncho_scan); hits best first."""
     G, y = _host_arrays(G, y)
-    out = np.zeros(max(top_n, 1), dtype=HIT_DTYPE)
+    k = order
+    room = min(top_n, math.comb(G.shape[0], k)) if 1 <= k <= G.shape[0] else 1
+    out = np.zeros(max(room, 1), dtype=HIT_DTYPE)
     n_out = ctypes.c_uint32(0)
     _check(lib().fiuncho_scan(G.ctypes.data, y.ctypes.data, G.shape[0], G.shape[1], order, top_n,
                               out.ctypes.data, ctypes.byref(n_out)))
@@ -182,10 +195,12 @@ def scan_code(G, y, order: int, top_n: int) -> int:
     """Return code of fiuncho_scan (for error-path checks)."""
     G = np.ascontiguousarray(G, dtype=np.uint8)
     y = np.ascontiguousarray(y, dtype=np.uint8)
-    out = np.zeros(max(top_n, 1), dtype=HIT_DTYPE)
-    n_out = ctypes.c_uint32(7)
     n = G.shape[0] if G.ndim == 2 else 0
     m = G.shape[1] if G.ndim == 2 else 0
+    # room for what a successful call writes: min(top_n, C(n, order)) hits
+    room = min(top_n, math.comb(n, order)) if 1 <= order <= n else 1
+    out = np.zeros(max(room, 1), dtype=HIT_DTYPE)
+    n_out = ctypes.c_uint32(7)
     code = lib().fiuncho_scan(G.ctypes.data, y.ctypes.data, n, m, order, top_n, out.ctypes.data,
                               ctypes.byref(n_out))
     if code != OK:
@@ -304,12 +319,17 @@ class DeviceBatch:
             raise FiunchoError(E_SHAPE, last_error())
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
         self.ws_ptr = (self.ws.data_ptr() + 255) & ~255
+        # a new workspace may reuse the memory of one the library planned
+        # before (the caching allocator hands back freed blocks), which other
+        # tensors may have overwritten since: the first run uploads the plan
+        self._planned = False
 
     def run(self, stream=None, upload_plan: bool = False):
         s = stream if stream is not None else self.torch.cuda.current_stream()
-        flags = DEVICE_PTRS | (UPLOAD_PLAN if upload_plan else 0)
+        flags = DEVICE_PTRS | (UPLOAD_PLAN if upload_plan or not self._planned else 0)
         _check(lib().fiuncho_scan_batch(self.jobs, len(self.shapes), flags, self.ws_ptr,
                                         self.ws_bytes, s.cuda_stream))
+        self._planned = True
 
     def capture(self, profile: bool = False):
         """Capture one ``run`` into a HIP graph (torch.cuda.CUDAGraph).  The

@@ -28,10 +28,26 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_hit_layout_matches_header():
-    # snp[8] (32 B) + rank (8 B) + mi (8 B) + mi32 + rel_err (8 B)
-    assert fiuncho.HIT_DTYPE.itemsize == 56
+    # snp[8] (32 B) + rank (8 B) + mi (8 B) + mi32, rel_err, est, reserved (16 B)
+    assert fiuncho.HIT_DTYPE.itemsize == 64
+    assert [fiuncho.HIT_DTYPE.fields[f][1] for f in ("snp", "rank", "mi", "mi32", "rel_err", "est")] == \
+        [0, 32, 40, 48, 52, 56]
     assert ctypes.sizeof(fiuncho.Job) == 64
     assert ctypes.sizeof(fiuncho.Profile) == 56
+
+
+def test_estimate_bound():
+    """u (6 ln m + (3^k + 4) ln 2) with u = 2^-24 (the rounding bound of the
+    plain single-precision evaluation of Eq. 1-3); negative for invalid
+    arguments.  Host-only."""
+    import math
+    u = 2.0 ** -24
+    for k, m in ((1, 1), (2, 1600), (3, 6400), (5, 4000), (8, (1 << 24) - 1)):
+        want = u * (6 * math.log(m) + (3 ** k + 4) * math.log(2))
+        assert fiuncho.estimate_bound(k, m) == pytest.approx(want, rel=1e-12)
+    assert fiuncho.estimate_bound(0, 10) < 0
+    assert fiuncho.estimate_bound(9, 10) < 0
+    assert fiuncho.estimate_bound(2, 0) < 0
 
 
 def _data(n=6, m=40, seed=0):

@@ -42,7 +42,7 @@ def test_order2_mfma_every_pair(mfma):
     """top_n >= C(n, 2): every pair is returned, with the oracle's score."""
     n = 60
     G, y = random_dataset(77, n, 300, 0.5)
-    hits = fiuncho.scan(G, y, 2, fiuncho.MAX_TOPN)
+    hits = fiuncho.scan(G, y, 2, math.comb(n, 2) + 5)
     assert len(hits) == math.comb(n, 2)
     np.testing.assert_array_equal(np.sort(hits["rank"]), np.arange(math.comb(n, 2), dtype=np.uint64))
     np.testing.assert_array_equal(hits["mi"], oracle.score_ranks(G, y, 2, hits["rank"]))
@@ -53,7 +53,7 @@ def test_order2_mfma_workloads(mfma):
     d = synth.order2_small()
     check_hits_against_oracle(d.genotypes, d.phenotype, 2, d.top_n,
                               fiuncho.scan(d.genotypes, d.phenotype, 2, d.top_n))
-    full_size_check(synth.order2_dense(), 20000, 52)
+    full_size_check(synth.order2_dense(), 2000, 52)
 
 
 def test_order2_mfma_in_a_mixed_batch(mfma):
@@ -74,8 +74,8 @@ def test_order2_mfma_shards(n, P, mfma):
     top = min(50, math.comb(n, 2))
     lists = _run_shards(G, y, 2, top, P)
     check_hits_against_oracle(G, y, 2, top, _merge(lists, top))
-    if math.comb(n, 2) <= fiuncho.MAX_TOPN:
-        full = _run_shards(G, y, 2, fiuncho.MAX_TOPN, P)
+    if math.comb(n, 2) <= 50000:
+        full = _run_shards(G, y, 2, math.comb(n, 2), P)
         sizes = fiuncho.shard_counts(n, 200, 2, P, fiuncho.TILE_ROUND_ROBIN)
         assert [len(h) for h in full] == sizes.tolist()
 
@@ -104,16 +104,16 @@ def test_order3_mfma_small(n, m, frac, mfma3):
 
 
 def test_order3_mfma_every_triple(mfma3):
-    n = 23  # C(23, 3) = 1771 <= 2048: every combination is returned
+    n = 23  # every combination is returned
     G, y = random_dataset(177, n, 150, 0.5)
-    hits = fiuncho.scan(G, y, 3, fiuncho.MAX_TOPN)
+    hits = fiuncho.scan(G, y, 3, math.comb(n, 3))
     assert len(hits) == math.comb(n, 3)
     np.testing.assert_array_equal(np.sort(hits["rank"]), np.arange(math.comb(n, 3), dtype=np.uint64))
     check_hits_against_oracle(G, y, 3, len(hits), hits)
 
 
 def test_order3_mfma_workload(mfma3):
-    full_size_check(synth.order3_main(), 20000, 53)
+    full_size_check(synth.order3_main(), 2000, 53)
 
 
 def test_order3_mfma_shards_and_batch(mfma3, monkeypatch):
@@ -284,7 +284,7 @@ def test_orders45_rows_every_combination(k, n, rows_kernel):
     m = 150
     rows_kernel(n, m, k)
     G, y = random_dataset(300 + k, n, m, 0.5)
-    hits = fiuncho.scan(G, y, k, fiuncho.MAX_TOPN)
+    hits = fiuncho.scan(G, y, k, math.comb(n, k))
     assert len(hits) == math.comb(n, k)
     np.testing.assert_array_equal(np.sort(hits["rank"]), np.arange(math.comb(n, k), dtype=np.uint64))
     np.testing.assert_array_equal(hits["mi"], oracle.score_ranks(G, y, k, hits["rank"]))
@@ -294,7 +294,7 @@ def test_orders45_rows_every_combination(k, n, rows_kernel):
 def test_order4_rows_workload(rows_kernel):
     d = synth.high_order(4)
     rows_kernel(d.n, d.m, 4)
-    full_size_check(d, 20000, 57)
+    full_size_check(d, 2000, 57)
 
 
 def test_orders45_rows_large_samples_fall_back(rows_kernel):
