@@ -178,6 +178,26 @@ int fiuncho_scan_batch(const fiuncho_job *jobs, uint32_t n_jobs, uint32_t flags,
                        void *workspace, size_t ws_bytes, void *hip_stream);
 
 /*
+ * fiuncho_scan_batch_static -- fiuncho_scan_batch without a caller workspace
+ * and without any device allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The workspace is a static array of
+ * FIUNCHO_STATIC_SCRATCH_BYTES in the library's device code: each GPU the
+ * library runs on holds one until the process ends, and every call on that
+ * GPU shares it.  Calls that overlap in time on one GPU (on different
+ * streams or threads) race on it and must not be made.
+ *   jobs, n_jobs, flags, hip_stream  as for fiuncho_scan_batch (with
+ *               FIUNCHO_DEVICE_PTRS the call only queues work; the first call
+ *               for a job set uploads its plan synchronously)
+ * Returns FIUNCHO_E_WORKSPACE, before any device work, when
+ * fiuncho_workspace_bytes(jobs, n_jobs) (plus the host-input copies without
+ * FIUNCHO_DEVICE_PTRS) exceeds FIUNCHO_STATIC_SCRATCH_BYTES.
+ */
+#define FIUNCHO_STATIC_SCRATCH_BYTES (64u << 20)
+int fiuncho_scan_batch_static(const fiuncho_job *jobs, uint32_t n_jobs, uint32_t flags,
+                              void *hip_stream);
+
+/*
  * fiuncho_contingency -- contingency tables of explicit combinations
  * (section 3.2, Fig. 3).
  *   genotypes, phenotype  host arrays as in fiuncho_scan

@@ -990,6 +990,38 @@ int owned_workspace(size_t need, void **out) {
 
 }  // namespace
 
+// Device memory of fiuncho_scan_batch_static: one array per GPU, held until
+// the process ends.  In host code its name is only a stand-in for the
+// symbol: the array's address on a device comes from hipGetSymbolAddress
+// (scratch_on_device), and only that address is handed to kernels.
+constexpr size_t kScratchBytes = (size_t)FIUNCHO_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch;  // device -> address of its scratch array
+
+// The current device's scratch address, looked up once per device with that
+// device current.
+int scratch_on_device(void **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(dev);
+  if (it == g_scratch.end()) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(FIUNCHO_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    it = g_scratch.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return FIUNCHO_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *fiuncho_last_error(void) { return t_err.c_str(); }
@@ -1051,6 +1083,32 @@ int fiuncho_scan_batch(const fiuncho_job *jobs, uint32_t n_jobs, uint32_t flags,
   t_err.clear();
   try {
     return batch_impl(jobs, n_jobs, flags, workspace, ws_bytes, (hipStream_t)hip_stream, 1, nullptr);
+  } catch (const std::exception &e) {
+    return fail(FIUNCHO_E_DEVICE, std::string("internal error: ") + e.what());
+  } catch (...) {
+    return fail(FIUNCHO_E_DEVICE, "internal error");
+  }
+}
+
+int fiuncho_scan_batch_static(const fiuncho_job *jobs, uint32_t n_jobs, uint32_t flags,
+                              void *hip_stream) {
+  t_err.clear();
+  try {
+    // the size check comes first, before any device work
+    Layout L;
+    int st = make_layout(jobs, n_jobs, !(flags & FIUNCHO_DEVICE_PTRS), 1, L);
+    if (st) return st;
+    if (L.total > kScratchBytes)
+      return fail(FIUNCHO_E_WORKSPACE, "these jobs need " + std::to_string(L.total) +
+                                           " bytes of workspace; the static scratch holds " +
+                                           std::to_string(kScratchBytes) +
+                                           " (use fiuncho_scan_batch with a workspace)");
+    void *ws = nullptr;
+    st = check_device();
+    if (st) return st;
+    st = scratch_on_device(&ws);
+    if (st) return st;
+    return batch_impl(jobs, n_jobs, flags, ws, kScratchBytes, (hipStream_t)hip_stream, 1, nullptr);
   } catch (const std::exception &e) {
     return fail(FIUNCHO_E_DEVICE, std::string("internal error: ") + e.what());
   } catch (...) {

@@ -31,6 +31,7 @@ MAX_ORDER = 8
 MAX_TOPN = 1 << 24
 DEVICE_PTRS = 1
 UPLOAD_PLAN = 2
+STATIC_SCRATCH_BYTES = 64 << 20
 KERNEL_AUTO = 0
 KERNEL_POPCOUNT = 1
 KERNEL_PAIRS = 2
@@ -43,6 +44,7 @@ EXPORTS = (
     "fiuncho_scan",
     "fiuncho_workspace_bytes",
     "fiuncho_scan_batch",
+    "fiuncho_scan_batch_static",
     "fiuncho_contingency",
     "fiuncho_score",
     "fiuncho_shard_counts",
@@ -127,6 +129,9 @@ def lib() -> ctypes.CDLL:
         L.fiuncho_scan_batch.restype = ctypes.c_int
         L.fiuncho_scan_batch.argtypes = [ctypes.POINTER(Job), ctypes.c_uint32, ctypes.c_uint32,
                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.fiuncho_scan_batch_static.restype = ctypes.c_int
+        L.fiuncho_scan_batch_static.argtypes = [ctypes.POINTER(Job), ctypes.c_uint32, ctypes.c_uint32,
+                                                ctypes.c_void_p]
         L.fiuncho_contingency.restype = ctypes.c_int
         L.fiuncho_contingency.argtypes = [u8p, u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
                                           ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
@@ -330,6 +335,12 @@ class DeviceBatch:
         _check(lib().fiuncho_scan_batch(self.jobs, len(self.shapes), flags, self.ws_ptr,
                                         self.ws_bytes, s.cuda_stream))
         self._planned = True
+
+    def run_static(self, stream=None):
+        """Queues fiuncho_scan_batch_static (the library's static scratch
+        instead of this batch's workspace; no device allocation)."""
+        s = stream if stream is not None else self.torch.cuda.current_stream()
+        _check(lib().fiuncho_scan_batch_static(self.jobs, len(self.shapes), DEVICE_PTRS, s.cuda_stream))
 
     def capture(self, profile: bool = False):
         """Capture one ``run`` into a HIP graph (torch.cuda.CUDAGraph).  The

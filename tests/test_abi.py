@@ -96,6 +96,18 @@ def test_workspace_bytes_depends_on_shape_only():
     assert fiuncho.workspace_bytes([(100, 1600, 0, 10)]) == 0
 
 
+def test_static_scratch_rejects_large_jobs():
+    """fiuncho_scan_batch_static refuses, before any device work, jobs whose
+    workspace exceeds its static scratch.  Host-only."""
+    assert fiuncho.STATIC_SCRATCH_BYTES == 64 << 20
+    arr = fiuncho._job_shapes([(1000, 6400, 3, 100)])
+    assert fiuncho.lib().fiuncho_workspace_bytes(arr, 1) > fiuncho.STATIC_SCRATCH_BYTES
+    code = fiuncho.lib().fiuncho_scan_batch_static(arr, 1, fiuncho.DEVICE_PTRS, None)
+    assert code == fiuncho.E_WORKSPACE
+    assert "static scratch holds 67108864" in fiuncho.last_error()
+    assert fiuncho.lib().fiuncho_scan_batch_static(None, 0, fiuncho.DEVICE_PTRS, None) == fiuncho.E_NULL
+
+
 def test_contingency_rejects_bad_rank():
     G, y = _data()
     with pytest.raises(fiuncho.FiunchoError) as e:
