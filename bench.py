@@ -12,6 +12,12 @@ stream.  Prints ONE JSON line.
 --shard I/P times one GPU's share of a search split across P GPUs (shard I
 of the job's work tiles); the rate is that share's combinations per second.
 
+A default run (order3-1000x6400, automatic kernels, no shard) also measures
+the other workloads of the metric in the same process and adds them as
+"configs": each with its step time, rate, kernels, dominant kernel and its
+roofline fraction; batch64 (one graph replay) carries its speed-up over
+batch64-plain (64 calls).  --no-configs skips them.
+
 Workloads (seeded synthetic data, see paper_2201_03331_amd/synth.py):
   order3-1000x6400 (default), order2-100x1600, order2-4000x16000,
   order4-200x4000, order5-200x4000, batch64 (64 uneven datasets in one
@@ -112,11 +118,19 @@ def measured_traffic(kernel: str, workload: str):
     return None
 
 
-def cpu_baseline(d, budget_s: float = 20.0):
-    """The oracle (plain per-sample counting, FP64 MI) timed on the host cores
-    over a contiguous sample of ranks of the same workload."""
+def host_cpus() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(d, budget_s: float = 15.0):
+    """The oracle (plain per-sample counting, FP64 MI) timed on every host CPU
+    this process may use, over a contiguous sample of ranks of the same
+    workload."""
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    threads = host_cpus()
     total = math.comb(d.n, d.order)
     probe = min(total, 20000)
     t0 = time.perf_counter()
@@ -127,71 +141,41 @@ def cpu_baseline(d, budget_s: float = 20.0):
     oracle.scan_range(d.genotypes, d.phenotype, d.order, d.top_n, 0, count, nthreads=threads)
     dt = time.perf_counter() - t0
     return {"value": count / dt, "unit": "combinations/s", "cores": threads, "kind": "oracle",
-            "sample": f"lexicographic ranks [0, {count}) of the same dataset "
-                      f"({count / total:.3g} of C({d.n},{d.order})), {dt:.1f} s"}
+            "nproc": os.cpu_count(), "sample": f"lexicographic ranks [0, {count}) of the same dataset "
+                                              f"({count / total:.3g} of C({d.n},{d.order})), {dt:.1f} s "
+                                              f"on {threads} threads"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="order3-1000x6400", choices=sorted(workloads().keys()))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel", default="auto", choices=("auto", "popcount", "pairs", "mfma", "mfma-fp4", "triples"),
-                    help="force this counting kernel for every dataset shape it handles")
-    ap.add_argument("--autotune", action="store_true",
-                    help="time the kernels for every dataset shape first (fiuncho_autotune)")
-    ap.add_argument("--shard", default=None, metavar="I/P",
-                    help="search only shard I of P of every dataset's work tiles")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only run a device-to-device copy of this many MiB (for counter scaling)")
-    args = ap.parse_args()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the scan would shard by (k-1)-prefix; see DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
+KERNEL_NAMES = {1: "popcount", 2: "pairs", 3: "mfma", 4: "triples", 5: "mfma-fp4"}
 
+
+def arithmetic_of(kernels) -> str:
+    """What the launched counting kernels compute in."""
+    from paper_2201_03331_amd import fiuncho
+    parts = []
+    if fiuncho.KERNEL_MFMA_FP4 in kernels:
+        parts.append("{0,1}^k cells (orders 2-3; every prefix row at orders 4-5) as a one-hot FP4 (E2M1) "
+                     "contraction on the matrix cores with FP32 accumulation (exact integer counts below 2^24)")
+    if fiuncho.KERNEL_MFMA in kernels:
+        parts.append("{0,1}^k cells as a one-hot int8 contraction on the matrix cores with int32 accumulation")
+    if kernels & {fiuncho.KERNEL_POPCOUNT, fiuncho.KERNEL_PAIRS, fiuncho.KERNEL_TRIPLES}:
+        parts.append("u64 bitset AND + u32 popcount counts")
+    return ("; ".join(parts) + "; remaining cells by inclusion-exclusion from u32 class counts and lower-order "
+            "tables; plain f32 MI estimate with a proven rounding bound for filtering; compensated f32 and "
+            "f64 MI of the kept")
+
+
+def measure(datasets, steps, warmup, graph=False, plain=False, shard=None):
+    """Times `steps` steps (one search of every dataset each) after `warmup`
+    untimed ones; returns the step time, the phase profile, the results and
+    the roofline of the dominant counting kernel."""
     import torch
     from paper_2201_03331_amd import fiuncho
 
-    if args.copy_calibration:
-        n = args.copy_calibration << 20
-        a = torch.ones(n, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": n, "launches": 5}))
-        return
-
-    datasets = workloads()[args.workload]()
-    plain = args.workload.endswith("-plain")
-    if args.kernel != "auto":
-        forced = {"popcount": fiuncho.KERNEL_POPCOUNT, "pairs": fiuncho.KERNEL_PAIRS,
-                  "mfma": fiuncho.KERNEL_MFMA, "mfma-fp4": fiuncho.KERNEL_MFMA_FP4,
-                  "triples": fiuncho.KERNEL_TRIPLES}[args.kernel]
-        for d in datasets:
-            if fiuncho.lib().fiuncho_set_kernel(d.n, d.m, d.order, forced) != fiuncho.OK:
-                ap.error(f"kernel {args.kernel} does not handle order {d.order}")
-    tuned = {}
-    if args.autotune:
-        for d in datasets:
-            key = (d.order, d.n.bit_length(), ((d.m + 63) // 64).bit_length())
-            if key not in tuned:
-                tuned[key] = fiuncho.autotune(d.n, d.m, d.order)
-    shard = None
-    if args.shard:
-        si, sp = (int(v) for v in args.shard.split("/"))
-        if not 0 <= si < sp:
-            ap.error("--shard I/P needs 0 <= I < P")
-        shard = (si, sp)
     sh = None if shard is None else [shard] * len(datasets)
     batches = ([fiuncho.DeviceBatch([d], shards=None if sh is None else [shard]) for d in datasets]
                if plain else [fiuncho.DeviceBatch(datasets, shards=sh)])
     stream = torch.cuda.current_stream()
-    graph = args.workload == "batch64"
     if graph:
         batches[0].capture()
 
@@ -205,20 +189,20 @@ def main():
     # warm-up calls run profiled too: a profiled call's first use of a job
     # shape does host-side bookkeeping (a sharded job's combination count)
     fiuncho.set_profiling(not graph)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    if args.warmup and not graph:
+    if warmup and not graph:
         fiuncho.get_profile()  # averages restart after the warm-up calls
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     end.record(stream)
     torch.cuda.synchronize()
     fiuncho.set_profiling(False)
-    ms = start.elapsed_time(end) / args.steps
+    ms = start.elapsed_time(end) / steps
     if graph:
         # events recorded by graph replays cannot be timed: the phase times of
         # a graph step come from one eager call right after the timed replays
@@ -227,10 +211,9 @@ def main():
         torch.cuda.synchronize()
         fiuncho.set_profiling(False)
     prof = fiuncho.get_profile()
-
-    # results of the last step: status and the top hit
     res = [r for b in batches for r in b.results()]
     ok = all(s == 0 for s, _ in res)
+
     def share(d):
         if shard is None:
             return math.comb(d.n, d.order)
@@ -238,7 +221,6 @@ def main():
 
     combos = sum(share(d) for d in datasets)
     combos_m = sum(share(d) * d.m for d in datasets)
-    value = combos / (ms / 1e3)
 
     # roofline of the dominant counting kernel: algorithmic work per launch
     # over that kernel's measured time.  Popcount kernels: 32-bit VALU
@@ -249,14 +231,14 @@ def main():
     lane_ops = 0
     mfma_ops = 0
     mfma_peak_s = 0.0
-    # the counter table's workload key (a shard launches fewer tiles)
-    traffic_key = args.workload + ("" if shard is None else f" shard {shard[0]}/{shard[1]}")
     kernels = set()
     for d in datasets:
         m1 = int(d.phenotype.sum())
         kern = fiuncho.get_kernel(d.n, d.m, d.order)
+        if kern == fiuncho.KERNEL_MFMA_FP4 and d.order >= 4 and d.m > 20447:
+            kern = fiuncho.KERNEL_POPCOUNT  # the matrix cores take orders 4-5 up to 20,447 samples
         kernels.add(kern)
-        if kern in (fiuncho.KERNEL_MFMA, fiuncho.KERNEL_MFMA_FP4) and (d.order <= 3 or d.m <= 20447):
+        if kern in (fiuncho.KERNEL_MFMA, fiuncho.KERNEL_MFMA_FP4):
             # cells counted on the matrix cores for every combination over
             # every sample: the {0,1}^k cells at orders 2 and 3 (4 and 8; the
             # others come from class counts and pair tables), at orders 4 and
@@ -279,30 +261,122 @@ def main():
         fmt = "int8 and FP4" if fp4 and i8 else "FP4" if fp4 else "int8"
         roofline = {"bound": "mfma", "kernel": f"mfma_kernel (one-hot {fmt} contraction + FP32 MI + filter)",
                     "achieved": achieved, "peak": peak, "unit": f"T {fmt} op/s", "frac": achieved / peak,
-                    # the counter table holds the FP4 kernels' launches
-                    "traffic": measured_traffic("mfma_kernel", traffic_key) if fmt == "FP4" else None}
+                    "kernel_ms": mfma_ms, "fmt": fmt}
     else:
         achieved = lane_ops / (scan_ms / 1e3) / 1e12
         peak = VALU_PEAK_LANE_OPS / 1e12
         roofline = {"bound": "alu", "kernel": "scan_kernel (AND+popcount counting + FP32 MI + filter)",
                     "achieved": achieved, "peak": peak, "unit": "T int32 lane-op/s", "frac": achieved / peak,
-                    # the counter table holds the pair-table (order 3) and
-                    # triple-table (order 4) kernels' launches
-                    "traffic": measured_traffic("scan_kernel", traffic_key)
-                    if kernels <= {fiuncho.KERNEL_PAIRS, fiuncho.KERNEL_TRIPLES} else None}
-    names = {fiuncho.KERNEL_POPCOUNT: "popcount", fiuncho.KERNEL_PAIRS: "pairs", fiuncho.KERNEL_MFMA: "mfma",
-             fiuncho.KERNEL_TRIPLES: "triples", fiuncho.KERNEL_MFMA_FP4: "mfma-fp4"}
-
-    d0 = datasets[0]
+                    "kernel_ms": scan_ms, "fmt": None}
     planted_first = None
     if len(datasets) == 1 and shard is None and res[0][1].size:
+        d0 = datasets[0]
         planted = [p for p in d0.planted if len(p) == d0.order]
         if planted:
             planted_first = tuple(int(v) for v in res[0][1][0]["snp"][: d0.order]) == planted[0]
+    elif len(datasets) > 1 and shard is None:
+        planted_first = all(h.size and tuple(int(v) for v in h[0]["snp"][: d.order]) == d.planted[0]
+                            for d, (_, h) in zip(datasets, res))
+    del batches
+    torch.cuda.synchronize()
+    return {"ms": ms, "prof": prof, "ok": ok, "combos": combos, "combos_m": combos_m, "roofline": roofline,
+            "kernels": kernels, "planted_first": planted_first}
 
+
+# the per-workload block of a default run: (workload, steps, warm-up)
+CONFIG_BLOCK = [("order2-100x1600", 50, 5), ("order2-4000x16000", 20, 3), ("batch64", 3, 1),
+                ("batch64-plain", 3, 1), ("order4-200x4000", 10, 2), ("order5-200x4000", 2, 1)]
+
+
+def summary(name, r, steps, warmup):
+    rf = r["roofline"]
+    return {"ms_per_step": round(r["ms"], 4), "steps": steps, "warmup": warmup,
+            "combinations": r["combos"], "combinations_per_s": r["combos"] / (r["ms"] / 1e3),
+            "combinations_x_samples_per_s": r["combos_m"] / (r["ms"] / 1e3),
+            "kernels": sorted(KERNEL_NAMES[k] for k in r["kernels"]),
+            "dominant_kernel": rf["kernel"], "kernel_ms": round(rf["kernel_ms"], 4),
+            "roofline_bound": rf["bound"], "roofline_frac": round(rf["frac"], 4),
+            "status_ok": r["ok"], "planted_first": r["planted_first"],
+            "phases_ms": {k: round(r["prof"][k], 4) for k in ("pack_ms", "pilot_ms", "scan_ms", "mfma_ms",
+                                                               "select_ms", "total_ms")}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="order3-1000x6400", choices=sorted(workloads().keys()))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the per-workload block (the other workloads of the metric)")
+    ap.add_argument("--kernel", default="auto", choices=("auto", "popcount", "pairs", "mfma", "mfma-fp4", "triples"),
+                    help="force this counting kernel for every dataset shape it handles")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the kernels for every dataset shape first (fiuncho_autotune)")
+    ap.add_argument("--shard", default=None, metavar="I/P",
+                    help="search only shard I of P of every dataset's work tiles")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of this many MiB (for counter scaling)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: a search splits into per-GPU shares of its work "
+              "tiles (fiuncho_job.shard_index / shard_count, timed here with --shard I/P), but "
+              "no multi-GPU run is built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2201_03331_amd import fiuncho
+
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        a = torch.ones(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "launches": 5}))
+        return
+
+    datasets = workloads()[args.workload]()
+    if args.kernel != "auto":
+        forced = {"popcount": fiuncho.KERNEL_POPCOUNT, "pairs": fiuncho.KERNEL_PAIRS,
+                  "mfma": fiuncho.KERNEL_MFMA, "mfma-fp4": fiuncho.KERNEL_MFMA_FP4,
+                  "triples": fiuncho.KERNEL_TRIPLES}[args.kernel]
+        for d in datasets:
+            if fiuncho.lib().fiuncho_set_kernel(d.n, d.m, d.order, forced) != fiuncho.OK:
+                ap.error(f"kernel {args.kernel} does not handle order {d.order}")
+    tuned = {}
+    if args.autotune:
+        for d in datasets:
+            key = (d.order, d.n.bit_length(), ((d.m + 63) // 64).bit_length())
+            if key not in tuned:
+                tuned[key] = fiuncho.autotune(d.n, d.m, d.order)
+    shard = None
+    if args.shard:
+        si, sp = (int(v) for v in args.shard.split("/"))
+        if not 0 <= si < sp:
+            ap.error("--shard I/P needs 0 <= I < P")
+        shard = (si, sp)
+    r = measure(datasets, args.steps, args.warmup, graph=args.workload == "batch64",
+                plain=args.workload.endswith("-plain"), shard=shard)
+    ms, prof, kernels = r["ms"], r["prof"], r["kernels"]
+    rf = dict(r["roofline"])
+    # the counter table's workload key (a shard launches fewer tiles); it holds
+    # the FP4 matrix-core kernels' and the pair- and triple-table kernels' launches
+    traffic_key = args.workload + ("" if shard is None else f" shard {shard[0]}/{shard[1]}")
+    if rf["bound"] == "mfma":
+        rf["traffic"] = measured_traffic("mfma_kernel", traffic_key) if rf["fmt"] == "FP4" else None
+    else:
+        rf["traffic"] = (measured_traffic("scan_kernel", traffic_key)
+                         if kernels <= {fiuncho.KERNEL_PAIRS, fiuncho.KERNEL_TRIPLES} else None)
+    rf["kernel_ms"] = round(rf["kernel_ms"], 4)
+    del rf["fmt"]
+    d0 = datasets[0]
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": r["combos"] / (ms / 1e3),
         "unit": "combinations/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -320,25 +394,38 @@ def main():
             "samples": d0.m if len(datasets) == 1 else None,
             "order": d0.order if len(datasets) == 1 else "2+3",
             "top_n": d0.top_n,
-            "combinations": combos,
-            "calls_per_step": len(batches),
+            "combinations": r["combos"],
+            "calls_per_step": len(datasets) if args.workload.endswith("-plain") else 1,
             "shard": None if shard is None else f"{shard[0]}/{shard[1]}",
         },
-        "combinations_x_samples_per_s": combos_m / (ms / 1e3),
-        "arithmetic": "u64 bitsets, u32 popcount counts, plain f32 MI estimate with a rigorous "
-                      "rounding bound for filtering, compensated f32 and f64 MI of the kept",
+        "combinations_x_samples_per_s": r["combos_m"] / (ms / 1e3),
+        "arithmetic": arithmetic_of(kernels),
         "phases_ms": {k: round(prof[k], 4) for k in ("pack_ms", "pilot_ms", "scan_ms", "mfma_ms",
                                                      "select_ms", "total_ms")},
-        "kernels": sorted(names[k] for k in kernels),
-        "autotuned": {f"order {k[0]}, snps < 2^{k[1]}, words < 2^{k[2]}": names[v]
+        "kernels": sorted(KERNEL_NAMES[k] for k in kernels),
+        "autotuned": {f"order {k[0]}, snps < 2^{k[1]}, words < 2^{k[2]}": KERNEL_NAMES[v]
                       for k, v in sorted(tuned.items())} if args.autotune else None,
         "candidates": prof["candidates"],
         "rescored": prof["kept"],
-        "status_ok": ok,
-        "planted_first": planted_first,
-        "roofline": roofline,
+        "status_ok": r["ok"],
+        "planted_first": r["planted_first"],
+        "roofline": rf,
     }
-    if not args.no_cpu_baseline and len(datasets) == 1 and shard is None:
+    del datasets
+    if not args.no_configs and args.workload == "order3-1000x6400" and shard is None and args.kernel == "auto":
+        block = {}
+        for name, steps, warm in CONFIG_BLOCK:
+            ds = workloads()[name]()
+            rc = measure(ds, steps, warm, graph=name == "batch64", plain=name.endswith("-plain"))
+            block[name] = summary(name, rc, steps, warm)
+            del ds
+            torch.cuda.empty_cache()
+            print(f"bench: {name} {rc['ms']:.3f} ms/step", file=sys.stderr, flush=True)
+        block["batch64"]["speedup_vs_plain"] = round(block["batch64-plain"]["ms_per_step"] /
+                                                     block["batch64"]["ms_per_step"], 4)
+        out["configs"] = block
+    if not args.no_cpu_baseline and len(d0.genotypes) and args.workload != "batch64" and \
+            not args.workload.endswith("-plain") and shard is None:
         out["cpu_baseline"] = cpu_baseline(d0)
     print(json.dumps(out), flush=True)
 

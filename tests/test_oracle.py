@@ -272,7 +272,7 @@ def _full_sort(G, y, k):
     return ranks, mi
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
 def test_scan_equals_full_sort(k):
     rng = np.random.default_rng(16 + k)
     G, y = random_data(rng, 11, 150, 0.5)
