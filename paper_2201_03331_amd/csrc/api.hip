@@ -306,7 +306,7 @@ struct JobLayout {
   u64 total;
   uint32_t cand_cap, l1_cap, sel_cap;
   size_t off_G, off_y, off_idx, off_Bv, off_Bs, off_marg, off_hist, off_phist, off_cand, off_l1, off_sel,
-      off_sel2, off_state, off_out, off_nout, off_status, off_pairs, off_triples;
+      off_sel2, off_state, off_out, off_nout, off_status, off_pairs, off_pairs4, off_triples;
   // plan (uploaded)
   size_t off_rows, off_F32, off_Fh, off_P64;
   std::vector<u64> row_start;
@@ -447,7 +447,11 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     J.off_out = host_inputs ? take(sizeof(fiuncho_hit) * J.top_n) : 0;
     J.off_nout = host_inputs ? take(sizeof(uint32_t)) : 0;
     J.off_status = host_inputs ? take(sizeof(int32_t)) : 0;
-    J.off_pairs = need_pairs ? take(sizeof(uint32_t) * 8 * (size_t)J.n * J.n_pad) : 0;
+    // the order-3 FP4 matrix-core kernels score from packed pair tables when
+    // every count fits 14 bits (fewer than 16,384 samples)
+    const bool packed_pairs = J.path == fiuncho::kPathMfma3 && J.fp4 && J.m < 16384;
+    J.off_pairs = need_pairs && !packed_pairs ? take(sizeof(uint32_t) * 8 * (size_t)J.n * J.n_pad) : 0;
+    J.off_pairs4 = packed_pairs ? take(sizeof(uint32_t) * 4 * (size_t)J.n * J.n_pad) : 0;
     J.off_triples = J.path == fiuncho::kPathTriples ? take((size_t)triple_table_bytes(J.n)) : 0;
   }
   // plan region
@@ -607,6 +611,7 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
     d.shard_index = J.shard_index;
     d.shard_count = J.shard_count;
     d.pairs = J.off_pairs ? reinterpret_cast<uint32_t *>(ws + J.off_pairs) : nullptr;
+    d.pairs4 = J.off_pairs4 ? reinterpret_cast<uint4 *>(ws + J.off_pairs4) : nullptr;
     d.triples = J.off_triples ? reinterpret_cast<uint32_t *>(ws + J.off_triples) : nullptr;
     d.state = reinterpret_cast<JobState *>(ws + J.off_state);
     d.out = host_inputs ? reinterpret_cast<fiuncho_hit *>(ws + J.off_out) : jobs[i].out;

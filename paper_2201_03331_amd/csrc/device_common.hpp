@@ -39,6 +39,12 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ u64 ballot(bool p) { return __ballot(p); }
 
+// The value x holds in lane l ^ 1, by a DPP quad permutation [1, 0, 3, 2]:
+// one VALU move, no round trip through the LDS crossbar
+__device__ __forceinline__ uint32_t xor1(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);
+}
+
 __device__ __forceinline__ uint32_t popc64(u64 x) { return (uint32_t)__popcll(x); }
 
 // acc + popcount(x) as two v_bcnt_u32_b32, each taking the running count as
@@ -92,6 +98,21 @@ __device__ __forceinline__ void colex_unrank(const Globals &g, uint32_t hi, u64 
     pre[r - 1] = uni(lo);
     hi = lo;
   }
+}
+
+// The matrix-core kernels feed 32 samples of one class to a lane as 32 FP4
+// (E2M1) operand values in four registers: register d holds sample 4p + d of
+// the 32-bit half word in nibble p.  A set sample's nibble holds one of the
+// values 0.5, 1, 2 (nibble bits 0, 1, 2; bit 3 is the sign); the two operands
+// of the one-hot contraction use reciprocal values per register, so every
+// product of two set samples is exactly 1:
+//   register      0     1     2     3
+//   A operand    0.5   1.0   2.0   1.0
+//   B operand    2.0   1.0   0.5   1.0
+// fp4_b_operand is the B form of a half word.
+__device__ __forceinline__ uint4 fp4_b_operand(uint32_t b) {
+  const uint32_t t = b >> 2;
+  return make_uint4((b << 2) & 0x44444444u, b & 0x22222222u, t & 0x11111111u, t & 0x22222222u);
 }
 
 // relaxed loads that read the device-coherent copy (other workgroups update it)

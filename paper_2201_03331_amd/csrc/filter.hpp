@@ -20,6 +20,7 @@ struct JV {
   Cand *cand;
   JobState *st;
   const uint32_t *pairs;
+  const uint4 *pairs4;
   const uint32_t *triples;
   uint32_t path;
   uint32_t fp4;               // matrix-core paths: FP4 operands (else int8)
@@ -51,6 +52,7 @@ __device__ __forceinline__ JV load_view(const JobDesc *jd) {
   v.cand = uni_ptr(J->cand);
   v.st = uni_ptr(J->state);
   v.pairs = uni_ptr(J->pairs);
+  v.pairs4 = uni_ptr(J->pairs4);
   v.triples = uni_ptr(J->triples);
   v.path = uni(J->path);
   v.fp4 = uni(J->fp4);

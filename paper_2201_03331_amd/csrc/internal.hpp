@@ -124,6 +124,8 @@ struct JobDesc {
   uint32_t path;              // kPathGeneric or kPathPairs
   JobState *state;
   uint32_t *pairs;            // kPathPairs, kPathTriples: [n][n_pad][g_a 0..1][g_j 0..1][class] counts
+  uint4 *pairs4;              // order 3 on the matrix cores with FP4 operands and fewer than 16,384
+                              // samples, instead of pairs: [n][n_pad] of [g_a][g_j] -> 4 c0 | 4 c1 << 16
   uint32_t *triples;          // kPathTriples: [pair (a, b)][n_pad][g_a][g_b][g_j][class] counts
   uint32_t shard_index;       // local tile = launch tile * shard_count + shard_index
   uint32_t shard_count;       // 1 = every tile

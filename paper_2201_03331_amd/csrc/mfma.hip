@@ -38,6 +38,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 // operand format code of E2M1 in the scaled instruction's format fields, and
 // the E8M0 scale exponent of 1.0
@@ -177,6 +178,7 @@ __device__ __forceinline__ uint32_t ld32(const FI_GLOBAL char *base, uint32_t of
   return __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
 }
 
+
 // 32 sample bits -> the 32 FP4 operand values of one lane.  Register d takes
 // bit 4p + d of b into nibble p, so both operands pair the same samples; the
 // nibble bit it lands on sets the E2M1 value (bit 0: 0.5, bit 1: 1.0, bit 2:
@@ -195,24 +197,37 @@ __device__ __forceinline__ v8i expand32_fp4_a(uint32_t b) {
   r[4] = r[5] = r[6] = r[7] = 0;
   return r;
 }
-__device__ __forceinline__ v8i expand32_fp4_b(uint32_t b) {
-  const uint32_t t = b >> 2;
+__device__ __forceinline__ v8i fp4_operand(uint4 q) {
   v8i r;
-  r[0] = (int)((b << 2) & 0x44444444u);
-  r[1] = (int)(b & 0x22222222u);
-  r[2] = (int)(t & 0x11111111u);
-  r[3] = (int)(t & 0x22222222u);
+  r[0] = (int)q.x;
+  r[1] = (int)q.y;
+  r[2] = (int)q.z;
+  r[3] = (int)q.w;
   r[4] = r[5] = r[6] = r[7] = 0;
   return r;
+}
+__device__ __forceinline__ v8i expand32_fp4_b(uint32_t b) { return fp4_operand(fp4_b_operand(b)); }
+
+// The operands of a word from the lane's four 32-bit half words O[4] (A
+// fragments 0, 1, B fragments 0, 1), expanded in registers
+template <int kRaw, typename Prep>
+__device__ __forceinline__ auto expanded_ops(Prep prep) {
+  return [prep](const uint32_t (&x)[kRaw], v8i (&E)[4]) {
+    uint32_t O[4];
+    prep(x, O);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) E[f] = f < 2 ? expand32_fp4_a(O[f]) : expand32_fp4_b(O[f]);
+  };
 }
 
 // Counts of one class with FP4 operands: words [wbeg, wend).  Lane l feeds
 // row l mod 32 of every fragment and the 32 samples of 32-bit half l / 32 of
-// each word (load_words and prep as for int8 operands, on the lane's half
-// words); the instruction pairs the same lane half and nibble of both
-// operands.
-template <int kDepth, int kRaw, typename Load, typename Prep>
-__device__ __forceinline__ void mfma_class_fp4(Load &&load_words, Prep &&prep, uint32_t wbeg,
+// each word; the instruction pairs the same lane half and nibble of both
+// operands.  load_words(w, x) fills x with the kRaw registers the lane loads
+// for word w; ops(x, E) makes the four operands (A fragments 0, 1, B
+// fragments 0, 1) from them when the word is used.
+template <int kDepth, int kRaw, typename Load, typename Ops>
+__device__ __forceinline__ void mfma_class_fp4(Load &&load_words, Ops &&ops, uint32_t wbeg,
                                                uint32_t wend, v16f (&acc)[2][2],
                                                int scale_a = kScaleOne) {
   if (wbeg >= wend) return;
@@ -221,11 +236,8 @@ __device__ __forceinline__ void mfma_class_fp4(Load &&load_words, Prep &&prep, u
 #pragma unroll
   for (int u = 0; u < kDepth; ++u) load_words(min(wbeg + u, wlast), X[u]);
   auto step = [&](int slot) {
-    uint32_t O[4];
-    prep(X[slot], O);
     v8i E[4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) E[f] = f < 2 ? expand32_fp4_a(O[f]) : expand32_fp4_b(O[f]);
+    ops(X[slot], E);
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -258,8 +270,8 @@ __device__ __forceinline__ void zero_acc(v16i (&acc0)[2][2], v16i (&acc1)[2][2])
 
 // Both classes with FP4 operands (class 0: words [0, W0), class 1: the next
 // W1), counts returned as integers: the FP32 sums are integers below 2^24
-template <int kDepth, int kRaw, typename Load, typename Prep>
-__device__ __forceinline__ void contract_fp4(Load &&load_words, Prep &&prep, uint32_t W0, uint32_t W1,
+template <int kDepth, int kRaw, typename Load, typename Ops>
+__device__ __forceinline__ void contract_fp4(Load &&load_words, Ops &&ops, uint32_t W0, uint32_t W1,
                                              v16i (&acc0)[2][2], v16i (&acc1)[2][2]) {
   v16f f0[2][2], f1[2][2];
 #pragma unroll
@@ -268,8 +280,8 @@ __device__ __forceinline__ void contract_fp4(Load &&load_words, Prep &&prep, uin
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) f0[x][y][e] = f1[x][y][e] = 0.f;
-  mfma_class_fp4<kDepth, kRaw>(load_words, prep, 0, W0, f0);
-  mfma_class_fp4<kDepth, kRaw>(load_words, prep, W0, W0 + W1, f1);
+  mfma_class_fp4<kDepth, kRaw>(load_words, ops, 0, W0, f0);
+  mfma_class_fp4<kDepth, kRaw>(load_words, ops, W0, W0 + W1, f1);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -285,8 +297,8 @@ __device__ __forceinline__ void contract_fp4(Load &&load_words, Prep &&prep, uin
 // bits.  Class 0's counts wait as 16-bit pairs while class 1 accumulates;
 // the result Q holds class 0 in the low and class 1 in the high 16 bits of
 // each output element (register e of block (x, y)).
-template <int kDepth, int kRaw, typename Load, typename Prep>
-__device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Prep &&prep, uint32_t W0,
+template <int kDepth, int kRaw, typename Load, typename Ops>
+__device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Ops &&ops, uint32_t W0,
                                                     uint32_t W1, uint32_t (&Q)[2][2][16]) {
   v16f f[2][2];
 #pragma unroll
@@ -295,7 +307,7 @@ __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Prep &&pr
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) f[x][y][e] = 0.f;
-  mfma_class_fp4<kDepth, kRaw>(load_words, prep, 0, W0, f);
+  mfma_class_fp4<kDepth, kRaw>(load_words, ops, 0, W0, f);
   uint32_t P0[2][2][8];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -306,7 +318,7 @@ __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Prep &&pr
         P0[x][y][i] = (uint32_t)f[x][y][2 * i] | ((uint32_t)f[x][y][2 * i + 1] << 16);
         f[x][y][2 * i] = f[x][y][2 * i + 1] = 0.f;
       }
-  mfma_class_fp4<kDepth, kRaw>(load_words, prep, W0, W0 + W1, f);
+  mfma_class_fp4<kDepth, kRaw>(load_words, ops, W0, W0 + W1, f);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -320,8 +332,8 @@ __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Prep &&pr
 // scaled by 2^s (s = bit length of m0, given by the caller), so the single
 // FP32 accumulator holds c0 + 2^s c1 < 2^24, an exact integer; Q as for the
 // narrow kernels.
-template <int kDepth, int kRaw, typename Load, typename Prep>
-__device__ __forceinline__ void contract_fp4_dual(Load &&load_words, Prep &&prep, uint32_t W0,
+template <int kDepth, int kRaw, typename Load, typename Ops>
+__device__ __forceinline__ void contract_fp4_dual(Load &&load_words, Ops &&ops, uint32_t W0,
                                                   uint32_t W1, uint32_t s,
                                                   uint32_t (&Q)[2][2][16]) {
   v16f f[2][2];
@@ -331,8 +343,8 @@ __device__ __forceinline__ void contract_fp4_dual(Load &&load_words, Prep &&prep
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) f[x][y][e] = 0.f;
-  mfma_class_fp4<kDepth, kRaw>(load_words, prep, 0, W0, f);
-  mfma_class_fp4<kDepth, kRaw>(load_words, prep, W0, W0 + W1, f, kScaleOne + (int)s);
+  mfma_class_fp4<kDepth, kRaw>(load_words, ops, 0, W0, f);
+  mfma_class_fp4<kDepth, kRaw>(load_words, ops, W0, W0 + W1, f, kScaleOne + (int)s);
   const uint32_t low = (1u << s) - 1;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -360,7 +372,7 @@ __device__ __forceinline__ void partner_packed(const uint32_t (&Q)[2][2][16], in
   const uint32_t lo = Q[x][y][elo], hi = Q[x][y][ehi];
   const uint32_t own = gl ? hi : lo;
   const uint32_t send = gl ? lo : hi;
-  const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
+  const uint32_t recv = xor1(send);
   o[0] = gl ? recv : own;
   o[1] = gl ? own : recv;
 }
@@ -374,7 +386,7 @@ __device__ __forceinline__ void partner_counts(const v16i (&acc0)[2][2], const v
     const uint32_t lo = Q[x][y][elo], hi = Q[x][y][ehi];
     const uint32_t own = gl ? hi : lo;
     const uint32_t send = gl ? lo : hi;
-    const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
+    const uint32_t recv = xor1(send);
     const uint32_t g0 = gl ? recv : own, g1 = gl ? own : recv;
     o[0][0] = g0 & 0xFFFFu;
     o[1][0] = g0 >> 16;
@@ -387,7 +399,7 @@ __device__ __forceinline__ void partner_counts(const v16i (&acc0)[2][2], const v
       const uint32_t lo = (uint32_t)A[elo], hi = (uint32_t)A[ehi];
       const uint32_t own = gl ? hi : lo;
       const uint32_t send = gl ? lo : hi;
-      const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
+      const uint32_t recv = xor1(send);
       o[c][0] = gl ? recv : own;
       o[c][1] = gl ? own : recv;
     }
@@ -425,10 +437,11 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
 #pragma unroll
       for (int f = 0; f < 4; ++f) o[f] = x[f];
     };
-    if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<4, 4>(load_words, prep, v.W0, v.W1, Q);
+    const auto ops = expanded_ops<4>(prep);
+    if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<4, 4>(load_words, ops, v.W0, v.W1, Q);
     else if constexpr (FMT == kMfmaF4Dual)
-      contract_fp4_dual<4, 4>(load_words, prep, v.W0, v.W1, bit_len(v.m0), Q);
-    else contract_fp4<4, 4>(load_words, prep, v.W0, v.W1, acc0, acc1);
+      contract_fp4_dual<4, 4>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
+    else contract_fp4<4, 4>(load_words, ops, v.W0, v.W1, acc0, acc1);
   } else {
     zero_acc(acc0, acc1);
     auto load_words = [&](uint32_t w, u64 (&x)[4]) {
@@ -649,10 +662,11 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
       o[2] = x[2];
       o[3] = x[3];
     };
-    if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<4, 5>(load_words, prep, v.W0, v.W1, Q);
+    const auto ops = expanded_ops<5>(prep);
+    if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<4, 5>(load_words, ops, v.W0, v.W1, Q);
     else if constexpr (FMT == kMfmaF4Dual)
-      contract_fp4_dual<4, 5>(load_words, prep, v.W0, v.W1, bit_len(v.m0), Q);
-    else contract_fp4<4, 5>(load_words, prep, v.W0, v.W1, acc0, acc1);
+      contract_fp4_dual<4, 5>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
+    else contract_fp4<4, 5>(load_words, ops, v.W0, v.W1, acc0, acc1);
   } else {
     zero_acc(acc0, acc1);
     auto load_words = [&](uint32_t w, u64 (&x)[5]) {
@@ -696,89 +710,124 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
   // the LDS table: both class sizes below 16,384; the dual kernel's always
   // are)
   constexpr bool kPackable = (FMT == kMfmaF4Dual || FMT == kMfmaF4Narrow) && LDS_F;
-  const bool packed = FMT == kMfmaF4Dual || (v.m0 < 16384u && v.m1 < 16384u);
+  // packed pair tables exist for jobs of fewer than 16,384 samples (every job
+  // of the dual kernel)
+  const bool packed = FMT == kMfmaF4Dual || v.pairs4 != nullptr;
   uint32_t Mb4[2];
 #pragma unroll
   for (int x = 0; x < 2; ++x) Mb4[x] = pack_x4(Mb[x][0], Mb[x][1]);
   const uint32_t m4 = pack_x4(v.m0, v.m1);
+  // the lane's two last variants j (fb = 0, 1): their class counts and (b, j)
+  // pair tables are read once for the four prefixes the lane scores
+  uint32_t jv[2], jj[2];
+#pragma unroll
+  for (int fb = 0; fb < 2; ++fb) {
+    jv[fb] = j0 + 16 * fb + (r >> 1);
+    jj[fb] = jv[fb] < n ? jv[fb] : n - 1;
+  }
+  // Each lane scores 4 prefixes a (e / 4 = 2 gl + t of blocks f = 0, 1) with
+  // its 2 last variants; the prefix's (a, b) pair table and class counts are
+  // read once for both, the (a, j) pair table from the same table row.
+  auto prefix_of = [&](int f, int t) { return a_first + 8 * f + 2 * (2 * gl + t) + h; };
+  auto score_packed = [&]() {
+    const FI_GLOBAL v4u *PT4 = reinterpret_cast<const FI_GLOBAL v4u *>(as_global(v.pairs4));
+    uint32_t Mj4[2][2], bj4[2][2][2];
+#pragma unroll
+    for (int fb = 0; fb < 2; ++fb) {
+      const v4u q = PT4[(size_t)b * v.n_pad + jj[fb]];
+      bj4[fb][0][0] = q[0];
+      bj4[fb][0][1] = q[1];
+      bj4[fb][1][0] = q[2];
+      bj4[fb][1][1] = q[3];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+        Mj4[fb][x] = pack_x4(marg[(size_t)jj[fb] * 6 + 2 * x], marg[(size_t)jj[fb] * 6 + 2 * x + 1]);
+    }
+    const FI_LDS char *Fb = (const FI_LDS char *)Fl;
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const uint32_t a = prefix_of(f, t);
+        const uint32_t aa = a < b ? a : b - 1;
+        const FI_GLOBAL v4u *row = PT4 + (size_t)aa * v.n_pad;
+        uint32_t ab4[2][2], Ma4[2];
+        {
+          const v4u q = row[b];
+          ab4[0][0] = q[0];
+          ab4[0][1] = q[1];
+          ab4[1][0] = q[2];
+          ab4[1][1] = q[3];
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x) Ma4[x] = pack_x4(marg[(size_t)aa * 6 + 2 * x], marg[(size_t)aa * 6 + 2 * x + 1]);
+        const uint32_t pre[2] = {aa, b};
+#pragma unroll
+        for (int fb = 0; fb < 2; ++fb) {
+          uint32_t D4[2][2][2];  // [g_a][g_b][g_j], packed x 4
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            uint32_t o[2];
+            partner_packed(Q, f, fb, 4 * t + i, 4 * (2 + t) + i, gl, o);
+            D4[i >> 1][i & 1][0] = o[0] << 2;
+            D4[i >> 1][i & 1][1] = o[1] << 2;
+          }
+          uint32_t aj4[2][2];
+          {
+            const v4u q = row[jj[fb]];
+            aj4[0][0] = q[0];
+            aj4[0][1] = q[1];
+            aj4[1][0] = q[2];
+            aj4[1][1] = q[3];
+          }
+          const uint32_t j = jv[fb];
+          const bool active = a < b && j < n;
+          float fs = mc.c;
+          if (active) {
+            constexpr int kGroup = 3;
+            uint32_t o0[kGroup], o1[kGroup];
+            int nc = 0;
+            walk_order3_packed(D4, ab4, aj4, bj4[fb], Ma4, Mb4, Mj4[fb], m4, [&](uint32_t p) {
+              o0[nc] = p & 0xFFFFu;
+              o1[nc] = p >> 16;
+              if (++nc == kGroup) {
+                float f0[kGroup], f1[kGroup], f01[kGroup];
+#pragma unroll
+                for (int x = 0; x < kGroup; ++x) {
+                  f0[x] = *(const FI_LDS float *)(Fb + o0[x]);
+                  f1[x] = *(const FI_LDS float *)(Fb + o1[x]);
+                  f01[x] = *(const FI_LDS float *)(Fb + o0[x] + o1[x]);
+                }
+#pragma unroll
+                for (int x = 0; x < kGroup; ++x) fs += (f0[x] + f1[x]) - f01[x];
+                nc = 0;
+              }
+            });
+          }
+          if (emit_with(v, active, fs * mc.inv_m,
+                        [&] { return lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1); }, thr,
+                        lane) >= kRefreshAppends)
+            thr = current_threshold_lanes(v);
+        }
+      }
+    }
+  };
+  // the per-class walk (counts of 16 bits or more per class): last variants
+  // outermost, so that only one j's tables are live at a time
   auto score = [&](auto F) {
 #pragma unroll
     for (int fb = 0; fb < 2; ++fb) {
-      const uint32_t j = j0 + 16 * fb + (r >> 1);
-      const uint32_t jj = j < n ? j : n - 1;
       uint32_t Mj[2][2], bj[8];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) Mj[x][c] = marg[(size_t)jj * 6 + 2 * x + c];
-      load_pair(PT + ((size_t)b * v.n_pad + jj) * 8, bj);
-      uint32_t Mj4[2], bj4[2][2];
-#pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        Mj4[x] = pack_x4(Mj[x][0], Mj[x][1]);
-#pragma unroll
-        for (int z = 0; z < 2; ++z) bj4[x][z] = pack_x4(bj[x * 4 + z * 2], bj[x * 4 + z * 2 + 1]);
-      }
+        for (int c = 0; c < 2; ++c) Mj[x][c] = marg[(size_t)jj[fb] * 6 + 2 * x + c];
+      load_pair(PT + ((size_t)b * v.n_pad + jj[fb]) * 8, bj);
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          // this lane's prefix: e / 4 = 2 gl + t
-          const uint32_t a = a_first + 8 * f + 2 * (2 * gl + t) + h;
-          if (kPackable && packed) {
-            uint32_t D4[2][2][2];  // [g_a][g_b][g_j], packed x 4
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              uint32_t o[2];
-              partner_packed(Q, f, fb, 4 * t + i, 4 * (2 + t) + i, gl, o);
-              D4[i >> 1][i & 1][0] = o[0] << 2;
-              D4[i >> 1][i & 1][1] = o[1] << 2;
-            }
-            const bool active = a < b && j < n;
-            const uint32_t aa = a < b ? a : b - 1;
-            uint32_t ab[8], aj[8];
-            load_pair(PT + ((size_t)aa * v.n_pad + b) * 8, ab);
-            load_pair(PT + ((size_t)aa * v.n_pad + jj) * 8, aj);
-            uint32_t ab4[2][2], aj4[2][2], Ma4[2];
-#pragma unroll
-            for (int x = 0; x < 2; ++x) {
-              Ma4[x] = pack_x4(marg[(size_t)aa * 6 + 2 * x], marg[(size_t)aa * 6 + 2 * x + 1]);
-#pragma unroll
-              for (int y = 0; y < 2; ++y) {
-                ab4[x][y] = pack_x4(ab[x * 4 + y * 2], ab[x * 4 + y * 2 + 1]);
-                aj4[x][y] = pack_x4(aj[x * 4 + y * 2], aj[x * 4 + y * 2 + 1]);
-              }
-            }
-            float fs = mc.c;
-            if (active) {
-              constexpr int kGroup = 3;
-              uint32_t o0[kGroup], o1[kGroup];
-              int nc = 0;
-              walk_order3_packed(D4, ab4, aj4, bj4, Ma4, Mb4, Mj4, m4, [&](uint32_t p) {
-                o0[nc] = p & 0xFFFFu;
-                o1[nc] = p >> 16;
-                if (++nc == kGroup) {
-                  const FI_LDS char *Fb = (const FI_LDS char *)Fl;
-                  float f0[kGroup], f1[kGroup], f01[kGroup];
-#pragma unroll
-                  for (int x = 0; x < kGroup; ++x) {
-                    f0[x] = *(const FI_LDS float *)(Fb + o0[x]);
-                    f1[x] = *(const FI_LDS float *)(Fb + o1[x]);
-                    f01[x] = *(const FI_LDS float *)(Fb + o0[x] + o1[x]);
-                  }
-#pragma unroll
-                  for (int x = 0; x < kGroup; ++x) fs += (f0[x] + f1[x]) - f01[x];
-                  nc = 0;
-                }
-              });
-            }
-            const uint32_t pre[2] = {aa, b};
-            if (emit_with(v, active, fs * mc.inv_m,
-                          [&] { return lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1); }, thr,
-                          lane) >= kRefreshAppends)
-              thr = current_threshold_lanes(v);
-            continue;
-          }
+          const uint32_t a = prefix_of(f, t);
           uint32_t D[2][2][2][2];  // [class][g_a][g_b][g_j]
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
@@ -790,11 +839,12 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
               D[c][i >> 1][i & 1][1] = o[c][1];
             }
           }
+          const uint32_t j = jv[fb];
           const bool active = a < b && j < n;
           const uint32_t aa = a < b ? a : b - 1;
           uint32_t ab[8], aj[8], Ma[2][2];
           load_pair(PT + ((size_t)aa * v.n_pad + b) * 8, ab);
-          load_pair(PT + ((size_t)aa * v.n_pad + jj) * 8, aj);
+          load_pair(PT + ((size_t)aa * v.n_pad + jj[fb]) * 8, aj);
 #pragma unroll
           for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -836,6 +886,12 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
       }
     }
   };
+  if constexpr (kPackable) {
+    if (packed) {
+      score_packed();
+      return;
+    }
+  }
   if constexpr (LDS_F) score(Fl);
   else score(as_global(v.Fh));
 }
@@ -1032,7 +1088,7 @@ __device__ __forceinline__ void wave_rows(const Globals &g, const JV &v, const u
           } else {
             own = ((P0[fa][jb][e >> 1] >> (16 * (e & 1))) & 0xFFFFu) | ((uint32_t)f[fa][jb][e] << 16);
           }
-          const uint32_t partner = (uint32_t)__shfl_xor((int)own, 1);
+          const uint32_t partner = xor1(own);
           const uint32_t nr = (uint32_t)__shfl((int)Np[fa], (int)row);
           if (rho < S::R) {
             const uint32_t a0 = own & 0xFFFFu, a1 = own >> 16;
@@ -1044,7 +1100,7 @@ __device__ __forceinline__ void wave_rows(const Globals &g, const JV &v, const u
             }
           }
         }
-      const float s2 = s + __shfl_xor(s, 1);
+      const float s2 = s + __uint_as_float(xor1(__float_as_uint(s)));
       const float s4 = s2 + __shfl_xor(s2, 32);
       const uint32_t j = jbase + 16 * jb + (r >> 1);
       const bool owner = gl == 0 && h == 0 && j < n;

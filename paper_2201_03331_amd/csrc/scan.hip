@@ -301,14 +301,17 @@ __device__ __forceinline__ void tile_orderk(const Globals &g, const JV &v,
 // per-variant class counts.
 // ---------------------------------------------------------------------------
 
-// Pair tables: PT[(a * n_pad + j) * 8 + ga * 4 + gj * 2 + c], a < j.
+// Pair tables: PT[(a * n_pad + j) * 8 + ga * 4 + gj * 2 + c], a < j; or, for
+// jobs of fewer than 16,384 samples on the order-3 matrix-core path, the
+// packed form PT4[a * n_pad + j] = 4 x (ga, gj) of (4 c0 | 4 c1 << 16).
 // Grid: x = rows of kScanWaves * 8 first variants, y = 64-wide blocks of j,
 // z = job.  Jobs without a pair table return at once.
 __global__ __launch_bounds__(kScanWaves * 64) void pairs_kernel(Globals g) {
   const JobDesc *jd = g.jobs + blockIdx.z;
   JV v = load_view(jd);
   uint32_t *PT = uni_ptr(as_const(jd)->pairs);
-  if (PT == nullptr) return;
+  uint4 *PT4 = uni_ptr(as_const(jd)->pairs4);
+  if (PT == nullptr && PT4 == nullptr) return;
   const JobState *st = v.st;
   if (uni((uint32_t)st->status) != 0) return;
   v.W0 = uni(st->W0);
@@ -336,9 +339,15 @@ __global__ __launch_bounds__(kScanWaves * 64) void pairs_kernel(Globals g) {
   for (int p = 0; p < 8; ++p) {
     const uint32_t ap = a_first + p;
     if (ap <= n - 2 && j < n && j > ap) {
-      uint4 *dst = reinterpret_cast<uint4 *>(PT + ((size_t)ap * v.n_pad + j) * 8);
-      dst[0] = make_uint4(acc[p][0][0][0], acc[p][1][0][0], acc[p][0][0][1], acc[p][1][0][1]);
-      dst[1] = make_uint4(acc[p][0][1][0], acc[p][1][1][0], acc[p][0][1][1], acc[p][1][1][1]);
+      if (PT4) {
+        PT4[(size_t)ap * v.n_pad + j] =
+            make_uint4(pack_x4(acc[p][0][0][0], acc[p][1][0][0]), pack_x4(acc[p][0][0][1], acc[p][1][0][1]),
+                       pack_x4(acc[p][0][1][0], acc[p][1][1][0]), pack_x4(acc[p][0][1][1], acc[p][1][1][1]));
+      } else {
+        uint4 *dst = reinterpret_cast<uint4 *>(PT + ((size_t)ap * v.n_pad + j) * 8);
+        dst[0] = make_uint4(acc[p][0][0][0], acc[p][1][0][0], acc[p][0][0][1], acc[p][1][0][1]);
+        dst[1] = make_uint4(acc[p][0][1][0], acc[p][1][1][0], acc[p][0][1][1], acc[p][1][1][1]);
+      }
     }
   }
 }
