@@ -654,6 +654,7 @@ Globals make_globals(const Layout &L, uint8_t *ws) {
   g.total_pilot_tiles = 0;
   for (auto &J : L.jobs) g.total_pilot_tiles += J.pilot_tiles;
   g.pilot = 0;
+  g.lds_f_entries = 0;
   return g;
 }
 
@@ -805,14 +806,25 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
     ps[p + 1] = ps[p] + L.jobs[L.order[p]].pilot_tiles;
   }
   const uint32_t ns = L.n_scan;
+  // f-table entries an orders-4/5 matrix-core launch keeps in LDS: those of
+  // the largest job of its jobs [first, first + count) of the tile-space
+  // order, up to the kernel's maximum
+  auto rows_f_entries = [&](const Globals &c, int order, bool dual) {
+    const uint32_t first = (uint32_t)(c.jobs - g.jobs);
+    uint32_t m_max = 0;
+    for (uint32_t i = first; i < first + c.n_jobs; ++i) m_max = std::max(m_max, L.jobs[L.order[i]].m);
+    return std::min(m_max + 1, fiuncho::mfma_rows_max_entries(order, dual));
+  };
   // group -1: the popcount kernel; q >= 0: the matrix-core kernel of group q
   auto counting = [&](const Globals &c, int q) {
     if (c.total_tiles <= c.tile_base) return;
     const u64 tiles = c.total_tiles - c.tile_base;
     if (q >= 6) {  // orders 4, 5: every prefix row on the matrix cores
       const int order = q - 2;
-      const int grid = (int)std::min<u64>((u64)fiuncho::mfma_rows_grid_size(order, false), tiles);
-      fiuncho::launch_mfma_rows(c, order, false, grid, s);
+      Globals r = c;
+      r.lds_f_entries = rows_f_entries(c, order, false);
+      const int grid = (int)std::min<u64>((u64)fiuncho::mfma_rows_grid_size(order, false, r.lds_f_entries), tiles);
+      fiuncho::launch_mfma_rows(r, order, false, grid, s);
       return;
     }
     const int order = 2 + q / 3;
@@ -842,7 +854,9 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
           d.tile_counter = g.tile_counter + fiuncho::kDualCounters + 2 * slot + pilot;
           const u64 tiles = d.total_tiles - d.tile_base;
           if (q >= 6) {
-            const int grid = (int)std::min<u64>((u64)fiuncho::mfma_rows_grid_size(order, true), tiles);
+            d.lds_f_entries = rows_f_entries(d, order, true);
+            const int grid =
+                (int)std::min<u64>((u64)fiuncho::mfma_rows_grid_size(order, true, d.lds_f_entries), tiles);
             fiuncho::launch_mfma_rows(d, order, true, grid, s);
           } else {
             const int grid = (int)std::min<u64>((u64)fiuncho::mfma_grid_size(order, 3), tiles);

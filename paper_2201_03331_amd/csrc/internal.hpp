@@ -153,6 +153,8 @@ struct Globals {
   const unsigned long long *job_pilot_start;  // [n_jobs + 1]
   unsigned long long total_pilot_tiles;
   uint32_t pilot;             // 1 in the pilot launch of scan_kernel
+  uint32_t lds_f_entries;     // orders 4 and 5 on the matrix cores: f-table entries this launch's
+                              // LDS holds (at least m + 1 of every job it counts)
 };
 
 // launchers (kernels.hip)
@@ -171,10 +173,13 @@ uint32_t mfma_narrow_max_samples();
 // operands; jobs of at most mfma_narrow_max_samples() samples)
 // dual: the kernel that takes the jobs whose class sizes fit 24 bits together
 // (both classes in one accumulator); it and the other run over the same tiles
+// (g.lds_f_entries: f-table entries of the launch's LDS, at most
+// mfma_rows_max_entries(order, dual))
 void launch_mfma_rows(const Globals &g, int order, bool dual, int grid, hipStream_t s);
 // the most samples a job of this order may have for the dual kernel
 uint32_t mfma_dual_max_samples(int order);
-int mfma_rows_grid_size(int order, bool dual);
+uint32_t mfma_rows_max_entries(int order, bool dual);
+int mfma_rows_grid_size(int order, bool dual, uint32_t f_entries);
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
 void launch_pilot_select(const Globals &g, uint32_t max_pilot_slots, hipStream_t s);
 void launch_rescore(const Globals &g, uint32_t max_k, hipStream_t s);

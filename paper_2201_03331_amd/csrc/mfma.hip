@@ -968,12 +968,24 @@ __device__ __forceinline__ void mfma_rows_class(Load &&load_words, Prep &&prep, 
     if (w + u < wend) step(u);
 }
 
+// Words of the prefix variants' rows a wave stages in LDS at a time: the
+// rows of one class of a job of up to 2,048 samples, or a part of them
+constexpr uint32_t kRowsChunk = 32;
+template <int K>
+constexpr uint32_t rows_stage_bytes() { return (uint32_t)(K - 1) * kRowsChunk * 32; }  // per wave
+
 // One wave: prefix pre[0 .. K-2] x last variants j0 + [0, 64).  DUAL: both
 // classes in one accumulator, class 1 scaled by 2^bitlen(m0) (exact while
-// bitlen(m0) + bitlen(m1) <= 24), as in the dual order-2/3 kernels
+// bitlen(m0) + bitlen(m1) <= 24), as in the dual order-2/3 kernels.
+// The prefix variants' rows (wave-uniform: every lane needs one of the three
+// genotype rows, or the zero word, of each variant) are copied to the wave's
+// LDS region `stage` kRowsChunk words at a time by 16-byte loads, and the A
+// operands are read from there: a load per variant and word instead of one
+// per variant, word, fragment and pass.
 template <int K, bool DUAL>
 __device__ __forceinline__ void wave_rows(const Globals &g, const JV &v, const uint32_t (&pre)[K - 1],
-                                          uint32_t j0, uint32_t lane, const FI_LDS float *F) {
+                                          uint32_t j0, uint32_t lane, const FI_LDS float *F,
+                                          FI_LDS char *stage) {
   typedef RowsShape<K> S;
   constexpr int FA = S::FA, JB = S::JB;
   const uint32_t n = v.n, b = pre[K - 2];
@@ -986,6 +998,8 @@ __device__ __forceinline__ void wave_rows(const Globals &g, const JV &v, const u
   // i (base 3, first variant most significant) selects row g_i of variant
   // pre[i]; rows past 3^(K-1) read the zero word that follows the three
   // genotype words
+  // (byte offsets of the lane's dword in a staged variant-word of 32 bytes,
+  // variant i's rows at i * kRowsChunk * 32)
   uint32_t oa[FA][K - 1];
 #pragma unroll
   for (int fa = 0; fa < FA; ++fa) {
@@ -995,9 +1009,23 @@ __device__ __forceinline__ void wave_rows(const Globals &g, const JV &v, const u
     for (int i = K - 2; i >= 0; --i) {
       const uint32_t gi = rho < S::R ? t % 3 : 3;
       t /= 3;
-      oa[fa][i] = gi * 8 + 4 * h;
+      oa[fa][i] = (uint32_t)i * kRowsChunk * 32 + gi * 8 + 4 * h;
     }
   }
+  // words [c0, c1) of every prefix variant's rows into the stage (c1 - c0 <=
+  // kRowsChunk): 2 x 16 bytes per variant and word
+  uint32_t c_first = 0;  // first word of the staged chunk
+  auto stage_words = [&](uint32_t c0, uint32_t c1) {
+    const uint32_t pieces = 2 * (c1 - c0);
+#pragma unroll
+    for (int i = 0; i < K - 1; ++i) {
+      const FI_GLOBAL v4u *src =
+          reinterpret_cast<const FI_GLOBAL v4u *>(Bsc + (size_t)pre[i] * vrow + (size_t)c0 * 32);
+      FI_LDS v4u *dst = reinterpret_cast<FI_LDS v4u *>(stage + (uint32_t)i * kRowsChunk * 32);
+      if (lane < pieces) dst[lane] = src[lane];
+    }
+    c_first = c0;
+  };
   const uint32_t ol = r * 8 + 4 * h;
   const MiConst mc = mi_const(v);
   float thr = current_threshold(v);
@@ -1006,12 +1034,11 @@ __device__ __forceinline__ void wave_rows(const Globals &g, const JV &v, const u
     const uint32_t jbase = j0 + 16 * JB * sb;
     if (jbase >= n) break;
     auto load_words = [&](uint32_t w, uint32_t (&x)[S::kRaw]) {
+      const FI_LDS char *sw = stage + (w - c_first) * 32;
 #pragma unroll
-      for (int i = 0; i < K - 1; ++i) {
-        const FI_GLOBAL char *base = Bsc + (size_t)pre[i] * vrow + (size_t)w * 32;
+      for (int i = 0; i < K - 1; ++i)
 #pragma unroll
-        for (int fa = 0; fa < FA; ++fa) x[fa * (K - 1) + i] = ld32(base, oa[fa][i]);
-      }
+        for (int fa = 0; fa < FA; ++fa) x[fa * (K - 1) + i] = *(const FI_LDS uint32_t *)(sw + oa[fa][i]);
       const FI_GLOBAL char *sj = Bvc + (size_t)w * word_bytes + (size_t)jbase * 16;
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb) x[FA * (K - 1) + jb] = ld32(sj, ol + 256 * jb);
@@ -1039,12 +1066,19 @@ __device__ __forceinline__ void wave_rows(const Globals &g, const JV &v, const u
 #pragma unroll
         for (int e = 0; e < 16; ++e) f[fa][jb][e] = 0.f;
     }
-    mfma_rows_class<S::kDepth, S::kRaw, FA, JB>(load_words, prep, 0, v.W0, f, np0);
+    // words [wb, we) of one class, kRowsChunk at a time through the stage
+    auto class_words = [&](uint32_t wb, uint32_t we, uint32_t (&np)[FA], int scale_a) {
+      for (uint32_t c0 = wb; c0 < we; c0 += kRowsChunk) {
+        const uint32_t c1 = min(c0 + kRowsChunk, we);
+        stage_words(c0, c1);
+        mfma_rows_class<S::kDepth, S::kRaw, FA, JB>(load_words, prep, c0, c1, f, np, scale_a);
+      }
+    };
+    class_words(0, v.W0, np0, kScaleOne);
     uint32_t P0[FA][JB][8];
     const uint32_t sh = bit_len(v.m0), low = (1u << sh) - 1u;
     if constexpr (DUAL) {
-      mfma_rows_class<S::kDepth, S::kRaw, FA, JB>(load_words, prep, v.W0, v.W0 + v.W1, f, np1,
-                                                  kScaleOne + (int)sh);
+      class_words(v.W0, v.W0 + v.W1, np1, kScaleOne + (int)sh);
     } else {
 #pragma unroll
       for (int fa = 0; fa < FA; ++fa)
@@ -1055,7 +1089,7 @@ __device__ __forceinline__ void wave_rows(const Globals &g, const JV &v, const u
             P0[fa][jb][i] = (uint32_t)f[fa][jb][2 * i] | ((uint32_t)f[fa][jb][2 * i + 1] << 16);
             f[fa][jb][2 * i] = f[fa][jb][2 * i + 1] = 0.f;
           }
-      mfma_rows_class<S::kDepth, S::kRaw, FA, JB>(load_words, prep, v.W0, v.W0 + v.W1, f, np1);
+      class_words(v.W0, v.W0 + v.W1, np1, kScaleOne);
     }
     // prefix row counts of both lane halves, both classes in one register
     uint32_t Np[FA];
@@ -1118,8 +1152,16 @@ __device__ __forceinline__ void wave_rows(const Globals &g, const JV &v, const u
 // tiles, each skipping the other's jobs.
 template <int K, bool DUAL>
 constexpr int rows_waves() { return DUAL && K == 4 ? 3 : 2; }
+// the most f-table entries a launch of the kernel keeps in LDS (a launch
+// sizes its LDS to the largest job of its group, up to this)
 template <int K, bool DUAL>
 constexpr int rows_f_entries() { return rows_waves<K, DUAL>() == 3 ? mfma_f_entries(kMfmaF4Dual) : mfma_f_entries(kMfmaF4Narrow); }
+// dynamic LDS of a launch: the f table (rounded to 16 bytes), then each
+// wave's stage
+template <int K>
+__host__ __device__ constexpr uint32_t rows_lds_bytes(uint32_t f_entries) {
+  return (f_entries * 4 + 15) / 16 * 16 + kMfmaWaves * rows_stage_bytes<K>();
+}
 
 template <int K, bool DUAL>
 __global__ __launch_bounds__(kMfmaWaves * 64, (rows_waves<K, DUAL>())) void mfma_rows_kernel(Globals g) {
@@ -1152,7 +1194,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, (rows_waves<K, DUAL>())) void mfma
         continue;
       }
     }
-    if (v.m + 1 > rows_f_entries<K, DUAL>()) continue;
+    if (v.m + 1 > g.lds_f_entries) continue;
     {
       // the job's table, once the tile is known to be this kernel's (every
       // wave has finished the previous tile: the barriers above)
@@ -1178,17 +1220,18 @@ __global__ __launch_bounds__(kMfmaWaves * 64, (rows_waves<K, DUAL>())) void mfma
     pre[K - 2] = b;
     // colex unrank of the (K-2)-subset of [0, b) with index q
     colex_unrank<K - 2>(g, b, q, pre);
-    wave_rows<K, DUAL>(g, v, pre, b + 1 + jb * 64, lane, Fl);
+    FI_LDS char *stage = (FI_LDS char *)s_f + (g.lds_f_entries * 4 + 15) / 16 * 16 + wave * rows_stage_bytes<K>();
+    wave_rows<K, DUAL>(g, v, pre, b + 1 + jb * 64, lane, Fl, stage);
   }
 }
 
 template <int K, bool DUAL>
-int mfma_rows_grid() {
+int mfma_rows_grid(uint32_t f_entries) {
   int dev = 0, cus = 0, per = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_rows_kernel<K, DUAL>, kMfmaWaves * 64,
-                                                     rows_f_entries<K, DUAL>() * sizeof(float));
+                                                     rows_lds_bytes<K>(f_entries));
   if (cus <= 0) cus = 256;
   if (per <= 0) per = 1;
   return cus * per;
@@ -1199,23 +1242,25 @@ uint32_t mfma_dual_max_samples(int order) {
          : order == 4 ? rows_f_entries<4, true>() - 1 : mfma_f_entries(kMfmaF4Dual) - 1;
 }
 
-int mfma_rows_grid_size(int order, bool dual) {
-  if (order == 5) return dual ? mfma_rows_grid<5, true>() : mfma_rows_grid<5, false>();
-  return dual ? mfma_rows_grid<4, true>() : mfma_rows_grid<4, false>();
+uint32_t mfma_rows_max_entries(int order, bool dual) {
+  if (order == 5) return dual ? rows_f_entries<5, true>() : rows_f_entries<5, false>();
+  return dual ? rows_f_entries<4, true>() : rows_f_entries<4, false>();
+}
+
+int mfma_rows_grid_size(int order, bool dual, uint32_t f_entries) {
+  if (order == 5) return dual ? mfma_rows_grid<5, true>(f_entries) : mfma_rows_grid<5, false>(f_entries);
+  return dual ? mfma_rows_grid<4, true>(f_entries) : mfma_rows_grid<4, false>(f_entries);
 }
 
 void launch_mfma_rows(const Globals &g, int order, bool dual, int grid, hipStream_t s) {
   const dim3 gd(grid), bd(kMfmaWaves * 64);
-  constexpr size_t l5d = rows_f_entries<5, true>() * sizeof(float);
-  constexpr size_t l5 = rows_f_entries<5, false>() * sizeof(float);
-  constexpr size_t l4d = rows_f_entries<4, true>() * sizeof(float);
-  constexpr size_t l4 = rows_f_entries<4, false>() * sizeof(float);
+  const size_t lds = order == 5 ? rows_lds_bytes<5>(g.lds_f_entries) : rows_lds_bytes<4>(g.lds_f_entries);
   if (order == 5) {
-    if (dual) hipLaunchKernelGGL((mfma_rows_kernel<5, true>), gd, bd, l5d, s, g);
-    else hipLaunchKernelGGL((mfma_rows_kernel<5, false>), gd, bd, l5, s, g);
+    if (dual) hipLaunchKernelGGL((mfma_rows_kernel<5, true>), gd, bd, lds, s, g);
+    else hipLaunchKernelGGL((mfma_rows_kernel<5, false>), gd, bd, lds, s, g);
   } else {
-    if (dual) hipLaunchKernelGGL((mfma_rows_kernel<4, true>), gd, bd, l4d, s, g);
-    else hipLaunchKernelGGL((mfma_rows_kernel<4, false>), gd, bd, l4, s, g);
+    if (dual) hipLaunchKernelGGL((mfma_rows_kernel<4, true>), gd, bd, lds, s, g);
+    else hipLaunchKernelGGL((mfma_rows_kernel<4, false>), gd, bd, lds, s, g);
   }
 }
 
