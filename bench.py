@@ -288,6 +288,20 @@ CONFIG_BLOCK = [("order2-100x1600", 50, 5), ("order2-4000x16000", 20, 3), ("batc
                 ("batch64-plain", 3, 1), ("order4-200x4000", 10, 2), ("order5-200x4000", 2, 1)]
 
 
+def launch_config(datasets):
+    """The counting kernel and the waves per SIMD its launch asks for
+    ("max": as many as fit) of each dataset shape, as the library chose them
+    (its heuristic, or fiuncho_autotune / fiuncho_set_config)."""
+    from paper_2201_03331_amd import fiuncho
+    out = {}
+    for d in datasets:
+        key = f"order {d.order}, {d.n} x {d.m}"
+        if key not in out and len(out) < 4:
+            k, w = fiuncho.get_config(d.n, d.m, d.order)
+            out[key] = {"kernel": KERNEL_NAMES[k], "waves_per_simd": w or "max"}
+    return out
+
+
 def summary(name, r, steps, warmup):
     rf = r["roofline"]
     return {"ms_per_step": round(r["ms"], 4), "steps": steps, "warmup": warmup,
@@ -352,7 +366,8 @@ def main():
         for d in datasets:
             key = (d.order, d.n.bit_length(), ((d.m + 63) // 64).bit_length())
             if key not in tuned:
-                tuned[key] = fiuncho.autotune(d.n, d.m, d.order)
+                fiuncho.autotune(d.n, d.m, d.order)
+                tuned[key] = fiuncho.get_config(d.n, d.m, d.order)
     shard = None
     if args.shard:
         si, sp = (int(v) for v in args.shard.split("/"))
@@ -403,7 +418,9 @@ def main():
         "phases_ms": {k: round(prof[k], 4) for k in ("pack_ms", "pilot_ms", "scan_ms", "mfma_ms",
                                                      "select_ms", "total_ms")},
         "kernels": sorted(KERNEL_NAMES[k] for k in kernels),
-        "autotuned": {f"order {k[0]}, snps < 2^{k[1]}, words < 2^{k[2]}": KERNEL_NAMES[v]
+        "launch_config": launch_config(datasets),
+        "autotuned": {f"order {k[0]}, snps < 2^{k[1]}, words < 2^{k[2]}":
+                      {"kernel": KERNEL_NAMES[v[0]], "waves_per_simd": v[1] or "max"}
                       for k, v in sorted(tuned.items())} if args.autotune else None,
         "candidates": prof["candidates"],
         "rescored": prof["kept"],

@@ -284,15 +284,34 @@ int fiuncho_shard_counts(uint32_t snps, uint32_t samples, int order, uint32_t un
 int fiuncho_get_kernel(uint32_t snps, uint32_t samples, int order);
 
 /* Sets (or, with FIUNCHO_KERNEL_AUTO, clears) the table entry of the shape's
- * bucket.  FIUNCHO_E_SHAPE if the kernel does not handle the order. */
+ * bucket, with waves_per_simd 0.  FIUNCHO_E_SHAPE if the kernel does not
+ * handle the order. */
 int fiuncho_set_kernel(uint32_t snps, uint32_t samples, int order, int kernel);
 
 /*
- * fiuncho_autotune -- times every kernel that handles this shape on a seeded
- * synthetic dataset of exactly this shape (balanced classes, top_n 16) on the
- * current device, `reps` timed runs each after one warm-up, records the
- * fastest in the table for the shape's bucket and returns it in *kernel.
- * Synchronous; allocates and frees its own device memory.
+ * The launch configuration of a shape's bucket: its counting kernel and the
+ * most waves per SIMD (workgroups of 4 waves per compute unit) the kernel's
+ * persistent launch keeps (0: as many as fit in registers and LDS; fewer
+ * waves leave each more cache and LDS bandwidth).  A launch that counts jobs
+ * of several buckets uses the largest of their limits (none if one has 0).
+ *   fiuncho_get_config: the configuration a job of this shape would use now
+ *     (FIUNCHO_E_NULL, FIUNCHO_E_ORDER).
+ *   fiuncho_set_config: sets the bucket's table entry (kernel
+ *     FIUNCHO_KERNEL_AUTO clears it); waves_per_simd in [0, 8], else
+ *     FIUNCHO_E_SHAPE; FIUNCHO_E_SHAPE also if the kernel does not handle
+ *     the order.
+ */
+int fiuncho_get_config(uint32_t snps, uint32_t samples, int order, int *kernel, int *waves_per_simd);
+int fiuncho_set_config(uint32_t snps, uint32_t samples, int order, int kernel, int waves_per_simd);
+
+/*
+ * fiuncho_autotune -- times every kernel that handles this shape, each at full
+ * occupancy and at 2 and 1 waves per SIMD, on a seeded synthetic dataset of
+ * exactly this shape (balanced classes, top_n 16) on the current device,
+ * `reps` timed runs each after one warm-up, records the fastest configuration
+ * in the table for the shape's bucket (fiuncho_get_config reads it back) and
+ * returns its kernel in *kernel.  Synchronous; allocates and frees its own
+ * device memory.
  */
 int fiuncho_autotune(uint32_t snps, uint32_t samples, int order, uint32_t reps, int *kernel);
 

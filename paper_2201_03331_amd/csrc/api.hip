@@ -204,9 +204,17 @@ u64 shard_tiles(u64 tiles, u64 count, u64 s) {
 // forced choice (autotuning runs), else the tuned table, else the rule
 // ---------------------------------------------------------------------------
 typedef std::tuple<uint32_t, uint32_t, uint32_t> ShapeKey;  // order, bit length of snps, of words
+// a bucket's configuration: counting kernel, and the most workgroups of 4
+// waves (so waves per SIMD) each persistent launch keeps on a compute unit
+// (0: as many as fit)
+struct TuneEntry {
+  int kernel;
+  int wps;
+};
 std::mutex g_tune_mu;
-std::map<ShapeKey, int> g_tuned;
+std::map<ShapeKey, TuneEntry> g_tuned;
 thread_local int t_force_kernel = FIUNCHO_KERNEL_AUTO;
+thread_local int t_force_wps = -1;  // an autotuning trial's waves per SIMD (-1: none)
 
 uint32_t bit_length(u64 x) {
   uint32_t b = 0;
@@ -276,9 +284,18 @@ int choose_kernel(uint32_t n, uint32_t m, uint32_t k) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(shape_key(n, m, k));
-    if (it != g_tuned.end() && kernel_valid(it->second, n, k)) return it->second;
+    if (it != g_tuned.end() && kernel_valid(it->second.kernel, n, k)) return it->second.kernel;
   }
   return rule_kernel(n, m, k);
+}
+
+// waves per SIMD a job of this shape asks of its counting launch (0: as many
+// as fit)
+int choose_wps(uint32_t n, uint32_t m, uint32_t k) {
+  if (t_force_wps >= 0) return t_force_wps;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(shape_key(n, m, k));
+  return it != g_tuned.end() ? it->second.wps : 0;
 }
 
 bool on_matrix_cores(uint32_t path) {
@@ -303,6 +320,7 @@ uint32_t job_path(uint32_t n, uint32_t m, uint32_t k) { return kernel_path(choos
 // ---------------------------------------------------------------------------
 struct JobLayout {
   uint32_t n, m, k, top_n, n_pad, wcap, nrows, path, fp4, shard_index, shard_count;
+  uint32_t wps;  // waves per SIMD asked of the counting launch (0: as many as fit)
   u64 total;
   uint32_t cand_cap, l1_cap, sel_cap;
   size_t off_G, off_y, off_idx, off_Bv, off_Bs, off_marg, off_hist, off_phist, off_cand, off_l1, off_sel,
@@ -374,6 +392,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     const int kern = choose_kernel(J.n, J.m, J.k);
     J.path = kernel_path(kern, J.k);
     J.fp4 = kern == FIUNCHO_KERNEL_MFMA_FP4;
+    J.wps = (uint32_t)choose_wps(J.n, J.m, J.k);
     // orders 4 and 5 on the matrix cores keep counts in 16 bits and the f
     // table in LDS: larger jobs run on the popcount kernel
     if (J.path == fiuncho::kPathMfmaRows && J.m > fiuncho::mfma_narrow_max_samples()) {
@@ -806,6 +825,26 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
     ps[p + 1] = ps[p] + L.jobs[L.order[p]].pilot_tiles;
   }
   const uint32_t ns = L.n_scan;
+  // the grid of a counting launch over jobs [first, first + count) of the
+  // tile-space order: at most gmax workgroups (every compute unit at full
+  // occupancy), fewer when every one of its jobs asks for fewer waves per
+  // SIMD (a workgroup is 4 waves: workgroups per compute unit = waves per SIMD)
+  int cus = 0;
+  {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  auto capped = [&](const Globals &c, int gmax) {
+    const uint32_t first = (uint32_t)(c.jobs - g.jobs);
+    uint32_t cap = 0;
+    for (uint32_t i = first; i < first + c.n_jobs; ++i) {
+      const uint32_t w = L.jobs[L.order[i]].wps;
+      if (w == 0) return gmax;
+      cap = std::max(cap, w);
+    }
+    return std::min(gmax, (int)(cap * (uint32_t)cus));
+  };
   // f-table entries an orders-4/5 matrix-core launch keeps in LDS: those of
   // the largest job of its jobs [first, first + count) of the tile-space
   // order, up to the kernel's maximum
@@ -823,14 +862,15 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
       const int order = q - 2;
       Globals r = c;
       r.lds_f_entries = rows_f_entries(c, order, false);
-      const int grid = (int)std::min<u64>((u64)fiuncho::mfma_rows_grid_size(order, false, r.lds_f_entries), tiles);
+      const int grid =
+          (int)std::min<u64>((u64)capped(c, fiuncho::mfma_rows_grid_size(order, false, r.lds_f_entries)), tiles);
       fiuncho::launch_mfma_rows(r, order, false, grid, s);
       return;
     }
     const int order = 2 + q / 3;
     const int fmt = q % 3;
     const int gmax = q >= 0 ? fiuncho::mfma_grid_size(order, fmt) : fiuncho::scan_grid_size(L.ksel);
-    const int grid = (int)std::min<u64>((u64)gmax, tiles);
+    const int grid = (int)std::min<u64>((u64)capped(c, gmax), tiles);
     if (q >= 0) fiuncho::launch_mfma(c, order, fmt, grid, s);
     else fiuncho::launch_scan(c, L.ksel, grid, s);
   };
@@ -855,11 +895,11 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
           const u64 tiles = d.total_tiles - d.tile_base;
           if (q >= 6) {
             d.lds_f_entries = rows_f_entries(d, order, true);
-            const int grid =
-                (int)std::min<u64>((u64)fiuncho::mfma_rows_grid_size(order, true, d.lds_f_entries), tiles);
+            const int grid = (int)std::min<u64>(
+                (u64)capped(d, fiuncho::mfma_rows_grid_size(order, true, d.lds_f_entries)), tiles);
             fiuncho::launch_mfma_rows(d, order, true, grid, s);
           } else {
-            const int grid = (int)std::min<u64>((u64)fiuncho::mfma_grid_size(order, 3), tiles);
+            const int grid = (int)std::min<u64>((u64)capped(d, fiuncho::mfma_grid_size(order, 3)), tiles);
             fiuncho::launch_mfma(d, order, 3, grid, s);
           }
         }
@@ -1321,10 +1361,12 @@ int fiuncho_get_kernel(uint32_t snps, uint32_t samples, int order) {
   return choose_kernel(snps, samples, (uint32_t)order);
 }
 
-int fiuncho_set_kernel(uint32_t snps, uint32_t samples, int order, int kernel) {
+int fiuncho_set_config(uint32_t snps, uint32_t samples, int order, int kernel, int waves_per_simd) {
   t_err.clear();
   if (order < 1 || order > FIUNCHO_MAX_ORDER || (uint32_t)order > snps)
     return fail(FIUNCHO_E_ORDER, "order must be in [1, min(snps, 8)]");
+  if (waves_per_simd < 0 || waves_per_simd > 8)
+    return fail(FIUNCHO_E_SHAPE, "waves_per_simd must be in [0, 8]");
   std::lock_guard<std::mutex> lk(g_tune_mu);
   const ShapeKey key = shape_key(snps, samples, (uint32_t)order);
   if (kernel == FIUNCHO_KERNEL_AUTO) {
@@ -1334,7 +1376,21 @@ int fiuncho_set_kernel(uint32_t snps, uint32_t samples, int order, int kernel) {
   if (!kernel_valid(kernel, snps, (uint32_t)order))
     return fail(FIUNCHO_E_SHAPE, "kernel " + std::to_string(kernel) + " does not handle order " +
                                      std::to_string(order));
-  g_tuned[key] = kernel;
+  g_tuned[key] = TuneEntry{kernel, waves_per_simd};
+  return FIUNCHO_OK;
+}
+
+int fiuncho_set_kernel(uint32_t snps, uint32_t samples, int order, int kernel) {
+  return fiuncho_set_config(snps, samples, order, kernel, 0);
+}
+
+int fiuncho_get_config(uint32_t snps, uint32_t samples, int order, int *kernel, int *waves_per_simd) {
+  t_err.clear();
+  if (!kernel || !waves_per_simd) return fail(FIUNCHO_E_NULL, "kernel and waves_per_simd must not be NULL");
+  if (order < 1 || order > FIUNCHO_MAX_ORDER || (uint32_t)order > snps)
+    return fail(FIUNCHO_E_ORDER, "order must be in [1, min(snps, 8)]");
+  *kernel = choose_kernel(snps, samples, (uint32_t)order);
+  *waves_per_simd = choose_wps(snps, samples, (uint32_t)order);
   return FIUNCHO_OK;
 }
 
@@ -1357,8 +1413,8 @@ int fiuncho_autotune(uint32_t snps, uint32_t samples, int order, uint32_t reps, 
     for (int c : {FIUNCHO_KERNEL_POPCOUNT, FIUNCHO_KERNEL_PAIRS, FIUNCHO_KERNEL_MFMA, FIUNCHO_KERNEL_TRIPLES,
                   FIUNCHO_KERNEL_MFMA_FP4})
       if (kernel_valid(c, snps, k)) cands.push_back(c);
-    int best = cands[0];
-    if (cands.size() > 1) {
+    int best = cands[0], best_wps = 0;
+    {
       // seeded synthetic data of this shape: uniform genotypes, alternating classes
       std::vector<uint8_t> G((size_t)snps * samples), y(samples);
       u64 x = 0x9E3779B97F4A7C15ull ^ ((u64)snps << 32 | samples);
@@ -1388,42 +1444,54 @@ int fiuncho_autotune(uint32_t snps, uint32_t samples, int order, uint32_t reps, 
       job.n_out = static_cast<uint32_t *>(dn.p);
       job.status = static_cast<int32_t *>(dst.p);
       struct Force {
-        ~Force() { t_force_kernel = FIUNCHO_KERNEL_AUTO; }
+        ~Force() {
+          t_force_kernel = FIUNCHO_KERNEL_AUTO;
+          t_force_wps = -1;
+        }
       } restore;
       hipEvent_t e0, e1;
       HIP_TRY(hipEventCreate(&e0));
       HIP_TRY(hipEventCreate(&e1));
       float best_ms = 0.f;
+      bool timed = false;
+      // every kernel, at full occupancy and at 2 and 1 waves per SIMD
       for (int c : cands) {
-        t_force_kernel = c;
-        Layout L;
-        st = make_layout(&job, 1, false, 1, L);
-        if (st) break;
-        void *ws = nullptr;
-        if (hipMalloc(&ws, L.total) != hipSuccess) {
-          st = fail(FIUNCHO_E_DEVICE, "autotune: no device memory for the workspace");
-          break;
-        }
-        st = batch_impl(&job, 1, FIUNCHO_DEVICE_PTRS, ws, L.total, nullptr, 1, nullptr);
-        if (st == FIUNCHO_OK && hipEventRecord(e0, nullptr) != hipSuccess) st = FIUNCHO_E_DEVICE;
-        for (uint32_t r = 0; st == FIUNCHO_OK && r < std::max<uint32_t>(reps, 1); ++r)
+        for (int wps : {0, 2, 1}) {
+          t_force_kernel = c;
+          t_force_wps = wps;
+          Layout L;
+          st = make_layout(&job, 1, false, 1, L);
+          if (st) break;
+          void *ws = nullptr;
+          if (hipMalloc(&ws, L.total) != hipSuccess) {
+            st = fail(FIUNCHO_E_DEVICE, "autotune: no device memory for the workspace");
+            break;
+          }
           st = batch_impl(&job, 1, FIUNCHO_DEVICE_PTRS, ws, L.total, nullptr, 1, nullptr);
-        float ms = 0.f;
-        if (st == FIUNCHO_OK && (hipEventRecord(e1, nullptr) != hipSuccess ||
-                                 hipEventSynchronize(e1) != hipSuccess ||
-                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-          st = fail(FIUNCHO_E_DEVICE, "autotune: event timing failed");
-        int32_t status = 0;
-        if (st == FIUNCHO_OK && hipMemcpy(&status, dst.p, sizeof(status), hipMemcpyDeviceToHost) != hipSuccess)
-          st = fail(FIUNCHO_E_DEVICE, "autotune: status copy failed");
-        const int fst = free_workspace(ws);
-        if (st == FIUNCHO_OK) st = fst;
-        if (st == FIUNCHO_OK && status != 0) st = fail(status, "autotune: the search failed");
-        if (st) break;
-        if (c == cands[0] || ms < best_ms) {
-          best_ms = ms;
-          best = c;
+          if (st == FIUNCHO_OK && hipEventRecord(e0, nullptr) != hipSuccess) st = FIUNCHO_E_DEVICE;
+          for (uint32_t r = 0; st == FIUNCHO_OK && r < std::max<uint32_t>(reps, 1); ++r)
+            st = batch_impl(&job, 1, FIUNCHO_DEVICE_PTRS, ws, L.total, nullptr, 1, nullptr);
+          float ms = 0.f;
+          if (st == FIUNCHO_OK && (hipEventRecord(e1, nullptr) != hipSuccess ||
+                                   hipEventSynchronize(e1) != hipSuccess ||
+                                   hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = fail(FIUNCHO_E_DEVICE, "autotune: event timing failed");
+          int32_t status = 0;
+          if (st == FIUNCHO_OK &&
+              hipMemcpy(&status, dst.p, sizeof(status), hipMemcpyDeviceToHost) != hipSuccess)
+            st = fail(FIUNCHO_E_DEVICE, "autotune: status copy failed");
+          const int fst = free_workspace(ws);
+          if (st == FIUNCHO_OK) st = fst;
+          if (st == FIUNCHO_OK && status != 0) st = fail(status, "autotune: the search failed");
+          if (st) break;
+          if (!timed || ms < best_ms) {
+            best_ms = ms;
+            best = c;
+            best_wps = wps;
+            timed = true;
+          }
         }
+        if (st) break;
       }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
@@ -1431,7 +1499,7 @@ int fiuncho_autotune(uint32_t snps, uint32_t samples, int order, uint32_t reps, 
     }
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
-      g_tuned[shape_key(snps, samples, k)] = best;
+      g_tuned[shape_key(snps, samples, k)] = TuneEntry{best, best_wps};
     }
     *kernel = best;
     return FIUNCHO_OK;

@@ -50,6 +50,8 @@ EXPORTS = (
     "fiuncho_shard_counts",
     "fiuncho_get_kernel",
     "fiuncho_set_kernel",
+    "fiuncho_get_config",
+    "fiuncho_set_config",
     "fiuncho_autotune",
     "fiuncho_last_error",
     "fiuncho_estimate_bound",
@@ -146,6 +148,12 @@ def lib() -> ctypes.CDLL:
         L.fiuncho_get_kernel.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]
         L.fiuncho_set_kernel.restype = ctypes.c_int
         L.fiuncho_set_kernel.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_int]
+        L.fiuncho_get_config.restype = ctypes.c_int
+        L.fiuncho_get_config.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.fiuncho_set_config.restype = ctypes.c_int
+        L.fiuncho_set_config.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int]
         L.fiuncho_autotune.restype = ctypes.c_int
         L.fiuncho_autotune.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_uint32,
                                        ctypes.POINTER(ctypes.c_int)]
@@ -259,6 +267,18 @@ def get_kernel(snps: int, samples: int, order: int) -> int:
 
 def set_kernel(snps: int, samples: int, order: int, kernel: int):
     _check(lib().fiuncho_set_kernel(snps, samples, order, kernel))
+
+
+def get_config(snps: int, samples: int, order: int):
+    """(KERNEL_* value, waves per SIMD) a job of this shape would use
+    (fiuncho_get_config; waves per SIMD 0 = as many as fit)."""
+    k, w = ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib().fiuncho_get_config(snps, samples, order, ctypes.byref(k), ctypes.byref(w)))
+    return k.value, w.value
+
+
+def set_config(snps: int, samples: int, order: int, kernel: int, waves_per_simd: int = 0):
+    _check(lib().fiuncho_set_config(snps, samples, order, kernel, waves_per_simd))
 
 
 def autotune(snps: int, samples: int, order: int, reps: int = 3) -> int:

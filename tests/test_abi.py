@@ -100,7 +100,7 @@ def test_static_scratch_rejects_large_jobs():
     """fiuncho_scan_batch_static refuses, before any device work, jobs whose
     workspace exceeds its static scratch.  Host-only."""
     assert fiuncho.STATIC_SCRATCH_BYTES == 64 << 20
-    arr = fiuncho._job_shapes([(1000, 6400, 3, 100)])
+    arr = fiuncho._job_shapes([(2000, 6400, 3, 100)])
     assert fiuncho.lib().fiuncho_workspace_bytes(arr, 1) > fiuncho.STATIC_SCRATCH_BYTES
     code = fiuncho.lib().fiuncho_scan_batch_static(arr, 1, fiuncho.DEVICE_PTRS, None)
     assert code == fiuncho.E_WORKSPACE
@@ -184,4 +184,21 @@ def test_kernel_choice_table(monkeypatch):
     assert L.fiuncho_set_kernel(5000, 500, 4, fiuncho.KERNEL_TRIPLES) == fiuncho.E_SHAPE
     k = ctypes.c_int(0)
     assert L.fiuncho_autotune(300, 500, 2, 1, None) == fiuncho.E_NULL
+    # launch configurations: kernel and waves per SIMD per bucket
+    try:
+        assert fiuncho.get_config(300, 500, 2) == (fiuncho.KERNEL_POPCOUNT, 0)
+        fiuncho.set_config(300, 500, 2, fiuncho.KERNEL_MFMA_FP4, 2)
+        assert fiuncho.get_config(300, 500, 2) == (fiuncho.KERNEL_MFMA_FP4, 2)
+        assert fiuncho.get_config(400, 450, 2) == (fiuncho.KERNEL_MFMA_FP4, 2)  # same bucket
+        assert fiuncho.get_kernel(300, 500, 2) == fiuncho.KERNEL_MFMA_FP4
+        fiuncho.set_kernel(300, 500, 2, fiuncho.KERNEL_MFMA)   # set_kernel: waves per SIMD 0
+        assert fiuncho.get_config(300, 500, 2) == (fiuncho.KERNEL_MFMA, 0)
+        assert L.fiuncho_set_config(300, 500, 2, fiuncho.KERNEL_MFMA, 9) == fiuncho.E_SHAPE
+        assert L.fiuncho_set_config(300, 500, 2, fiuncho.KERNEL_MFMA, -1) == fiuncho.E_SHAPE
+        assert L.fiuncho_set_config(300, 500, 2, fiuncho.KERNEL_PAIRS, 1) == fiuncho.E_SHAPE
+        assert L.fiuncho_get_config(300, 500, 2, None, None) == fiuncho.E_NULL
+        assert L.fiuncho_get_config(3, 500, 4, ctypes.byref(k), ctypes.byref(k)) == fiuncho.E_ORDER
+    finally:
+        fiuncho.set_config(300, 500, 2, fiuncho.KERNEL_AUTO, 0)
+    assert fiuncho.get_config(300, 500, 2) == (fiuncho.KERNEL_POPCOUNT, 0)
     assert L.fiuncho_autotune(3, 500, 4, 1, ctypes.byref(k)) == fiuncho.E_ORDER

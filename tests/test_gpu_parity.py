@@ -494,6 +494,9 @@ def test_autotune_then_search(n, m, k):
                         (fiuncho.KERNEL_POPCOUNT, fiuncho.KERNEL_PAIRS, fiuncho.KERNEL_MFMA,
                          fiuncho.KERNEL_MFMA_FP4))
         assert fiuncho.get_kernel(n, m, k) == kern
+        kk, wps = fiuncho.get_config(n, m, k)
+        say(f"autotuned: kernel {kk}, waves per SIMD {wps}")
+        assert kk == kern and wps in (0, 1, 2)
         G, y = random_dataset(60 + k, n, m, 0.5)
         fiuncho.set_profiling(True)
         b = fiuncho.DeviceBatch([synth.Dataset(G, y, k, 30)])
@@ -674,3 +677,18 @@ def test_new_batch_in_reused_memory():
     assert status == 0
     assert hits.tobytes() == first[0][1].tobytes()
     check_hits_against_oracle(d.genotypes, d.phenotype, 3, 25, hits)
+
+
+@pytest.mark.parametrize("wps", [1, 2])
+def test_waves_per_simd_limit(wps):
+    """A configuration that limits the counting launch to 1 or 2 waves per
+    SIMD gives the same result as full occupancy (a persistent grid of fewer
+    workgroups draws every tile)."""
+    G, y = random_dataset(64 + wps, 150, 700, 0.45, 1, 1)
+    try:
+        fiuncho.set_config(150, 700, 3, fiuncho.KERNEL_MFMA_FP4, wps)
+        assert fiuncho.get_config(150, 700, 3) == (fiuncho.KERNEL_MFMA_FP4, wps)
+        hits = fiuncho.scan(G, y, 3, 40)
+    finally:
+        fiuncho.set_config(150, 700, 3, fiuncho.KERNEL_AUTO, 0)
+    check_hits_against_oracle(G, y, 3, 40, hits)
