@@ -22,6 +22,7 @@ struct JV {
   const uint32_t *pairs;
   const uint4 *pairs4;
   const uint32_t *triples;
+  const uint4 *triples4;
   uint32_t path;
   uint32_t fp4;               // matrix-core paths: FP4 operands (else int8)
   const float *Fh;
@@ -54,6 +55,7 @@ __device__ __forceinline__ JV load_view(const JobDesc *jd) {
   v.pairs = uni_ptr(J->pairs);
   v.pairs4 = uni_ptr(J->pairs4);
   v.triples = uni_ptr(J->triples);
+  v.triples4 = uni_ptr(J->triples4);
   v.path = uni(J->path);
   v.fp4 = uni(J->fp4);
   v.Fh = uni_ptr(J->Fh);
@@ -208,6 +210,133 @@ __device__ __forceinline__ void load_pair(const FI_GLOBAL uint32_t *p, uint32_t 
   const FI_GLOBAL u64 *p64 = reinterpret_cast<const FI_GLOBAL u64 *>(p);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
+    const u64 x = p64[i];
+    q[2 * i] = (uint32_t)x;
+    q[2 * i + 1] = (uint32_t)(x >> 32);
+  }
+}
+
+// lexicographic index of the pair (x, y), x < y, among the pairs of n
+__device__ __forceinline__ u64 pair_index(uint32_t n, uint32_t x, uint32_t y) {
+  return (u64)x * (n - 1) - (u64)x * (x - 1) / 2 + (y - x - 1);
+}
+
+// The inputs of an order-3 table walk, held by value.
+struct Tab3 {
+  uint32_t D[2][2][2][2];  // [c][x][y][z] over {0,1}^3
+  uint32_t xy[8];          // sum over z: [x][y][c]
+  uint32_t xz[8];          // sum over y: [x][z][c]
+  uint32_t yz[8];          // sum over x: [y][z][c]
+  uint32_t Mx[2][2];       // [x][c]
+  uint32_t My[2][2];
+  uint32_t Mz[2][2];
+  uint32_t m[2];
+};
+
+// walk_order3 over NT tables at once: visit(cells) sees cell p of every table
+// (cells[t][class]), p in the walk's order.
+template <int NT, typename Visit>
+__device__ __forceinline__ void walk3_zip(const Tab3 (&q)[NT], Visit &&visit) {
+  uint32_t sum[NT][2], x2z[NT][2][2][2], t2yz[NT][2][2][2], cell[NT][2];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) sum[t][0] = sum[t][1] = 0;
+  auto emit_cell = [&]() {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      sum[t][0] += cell[t][0];
+      sum[t][1] += cell[t][1];
+    }
+    visit(cell);
+  };
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int z = 0; z < 2; ++z) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) cell[t][c] = q[t].D[c][x][y][z];
+        emit_cell();
+      }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          cell[t][c] = q[t].xy[x * 4 + y * 2 + c] - q[t].D[c][x][y][0] - q[t].D[c][x][y][1];
+      emit_cell();  // (x, y, 2)
+    }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          cell[t][c] = x2z[t][c][x][z] =
+              q[t].xz[x * 4 + z * 2 + c] - q[t].D[c][x][0][z] - q[t].D[c][x][1][z];
+      emit_cell();  // (x, 2, z)
+    }
+#pragma unroll
+  for (int y = 0; y < 2; ++y)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          cell[t][c] = t2yz[t][c][y][z] =
+              q[t].yz[y * 4 + z * 2 + c] - q[t].D[c][0][y][z] - q[t].D[c][1][y][z];
+      emit_cell();  // (2, y, z)
+    }
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        cell[t][c] = q[t].Mx[x][c] - q[t].xy[x * 4 + c] - q[t].xy[x * 4 + 2 + c] - x2z[t][c][x][0] -
+                     x2z[t][c][x][1];
+    emit_cell();  // (x, 2, 2)
+  }
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        cell[t][c] = q[t].My[y][c] - q[t].xy[y * 2 + c] - q[t].xy[4 + y * 2 + c] - t2yz[t][c][y][0] -
+                     t2yz[t][c][y][1];
+    emit_cell();  // (2, y, 2)
+  }
+#pragma unroll
+  for (int z = 0; z < 2; ++z) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        cell[t][c] = q[t].Mz[z][c] - q[t].xz[z * 2 + c] - q[t].xz[4 + z * 2 + c] - t2yz[t][c][0][z] -
+                     t2yz[t][c][1][z];
+    emit_cell();  // (2, 2, z)
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) cell[t][c] = q[t].m[c] - sum[t][c];
+  visit(cell);  // (2, 2, 2)
+}
+
+// 16 u32 of a triple table entry ([g_x][g_y][g_z][class]) and its slice at g_z
+__device__ __forceinline__ void load_triple(const FI_GLOBAL uint32_t *p, uint32_t (&q)[16]) {
+  const FI_GLOBAL u64 *p64 = reinterpret_cast<const FI_GLOBAL u64 *>(p);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
     const u64 x = p64[i];
     q[2 * i] = (uint32_t)x;
     q[2 * i + 1] = (uint32_t)(x >> 32);
@@ -432,6 +561,129 @@ __device__ __forceinline__ bool locate_tile(const Globals &g, u64 t, uint32_t wa
   const uint32_t sc = uni(jd->shard_count);
   if (sc > 1) lt = uni64(lt * sc + (uni(jd->shard_index) + lt % sc) % sc);
   return true;
+}
+
+// ---------------------------------------------------------------------------
+// Order 4 from stored triple tables.  Only the {0,1}^4 cells of (x, y, z, j)
+// are counted; the others follow by inclusion-exclusion: for g_j in {0, 1},
+// the cells (., ., ., g_j) form an order-3 table over (x, y, z) whose "pairs"
+// are the {0,1}^3 tables of (x, y, j), (x, z, j), (y, z, j) at g_j, whose
+// "variants" are the {0,1}^2 pair tables of (x, j), (y, j), (z, j) at g_j and
+// whose size is the count of g_j at j; the cells (., ., ., 2) are the
+// prefix's own order-3 table (x, y, z) minus those two.
+// ---------------------------------------------------------------------------
+
+// Sum of the MI terms of (x, y, z, j) added to `start`, from its {0,1}^4
+// counts acc[class][g_x][g_y][g_z][g_j]; jj = j clamped below n.  UNIFORM:
+// the prefix is the same in every lane (its tables are read by scalar loads).
+// CLAMP: clamp every count to its class size before the table reads (a table
+// in global memory; LDS reads cannot fault).
+template <bool UNIFORM, bool CLAMP, typename FP>
+__device__ __forceinline__ float order4_tables_sum(const JV &v, FP F, const uint32_t (&acc)[2][2][2][2][2],
+                                                   uint32_t x, uint32_t y, uint32_t z, uint32_t jj,
+                                                   bool active, float start) {
+  const uint32_t n = v.n, np = v.n_pad;
+  const FI_GLOBAL uint32_t *TTg = as_global(v.triples);
+  const FI_GLOBAL uint32_t *PTg = as_global(v.pairs);
+  const FI_GLOBAL uint32_t *mgj = as_global(v.marg) + (size_t)jj * 6;
+  // prefix tables: scalar loads when wave-uniform
+  auto TTp = [&](size_t i) -> uint32_t {
+    if constexpr (UNIFORM) return as_const(v.triples)[i];
+    else return TTg[i];
+  };
+  auto PTp = [&](size_t i) -> uint32_t {
+    if constexpr (UNIFORM) return as_const(v.pairs)[i];
+    else return PTg[i];
+  };
+  auto Mp = [&](size_t i) -> uint32_t {
+    if constexpr (UNIFORM) return as_const(v.marg)[i];
+    else return as_global(v.marg)[i];
+  };
+
+  Tab3 q[3];  // [0]: (x, y, z) itself; [1], [2]: the cells with g_j = 0, 1
+  {
+    const size_t e = (pair_index(n, x, y) * np + z) * 16;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int cl = 0; cl < 2; ++cl) q[0].D[cl][a][b][c] = TTp(e + a * 8 + b * 4 + c * 2 + cl);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      q[0].xy[i] = PTp(((size_t)x * np + y) * 8 + i);
+      q[0].xz[i] = PTp(((size_t)x * np + z) * 8 + i);
+      q[0].yz[i] = PTp(((size_t)y * np + z) * 8 + i);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int cl = 0; cl < 2; ++cl) {
+        q[0].Mx[a][cl] = Mp((size_t)x * 6 + 2 * a + cl);
+        q[0].My[a][cl] = Mp((size_t)y * 6 + 2 * a + cl);
+        q[0].Mz[a][cl] = Mp((size_t)z * 6 + 2 * a + cl);
+      }
+    q[0].m[0] = v.m0;
+    q[0].m[1] = v.m1;
+  }
+  // the g_j slices (per lane)
+  {
+    uint32_t txy[16], txz[16], tyz[16], pxj[8], pyj[8], pzj[8];
+    load_triple(TTg + (pair_index(n, x, y) * np + jj) * 16, txy);
+    load_triple(TTg + (pair_index(n, x, z) * np + jj) * 16, txz);
+    load_triple(TTg + (pair_index(n, y, z) * np + jj) * 16, tyz);
+    load_pair(PTg + ((size_t)x * np + jj) * 8, pxj);
+    load_pair(PTg + ((size_t)y * np + jj) * 8, pyj);
+    load_pair(PTg + ((size_t)z * np + jj) * 8, pzj);
+#pragma unroll
+    for (int gj = 0; gj < 2; ++gj) {
+      Tab3 &t = q[1 + gj];
+#pragma unroll
+      for (int cl = 0; cl < 2; ++cl)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) t.D[cl][a][b][c] = acc[cl][a][b][c][gj];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int cl = 0; cl < 2; ++cl) {
+            t.xy[a * 4 + b * 2 + cl] = txy[a * 8 + b * 4 + gj * 2 + cl];
+            t.xz[a * 4 + b * 2 + cl] = txz[a * 8 + b * 4 + gj * 2 + cl];
+            t.yz[a * 4 + b * 2 + cl] = tyz[a * 8 + b * 4 + gj * 2 + cl];
+          }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int cl = 0; cl < 2; ++cl) {
+          t.Mx[a][cl] = pxj[a * 4 + gj * 2 + cl];
+          t.My[a][cl] = pyj[a * 4 + gj * 2 + cl];
+          t.Mz[a][cl] = pzj[a * 4 + gj * 2 + cl];
+        }
+#pragma unroll
+      for (int cl = 0; cl < 2; ++cl) t.m[cl] = mgj[2 * gj + cl];
+    }
+  }
+  float fs = start;
+  if (active) {
+    const uint32_t m0 = v.m0, m1 = v.m1;
+    auto cl0 = [&](uint32_t t) { return CLAMP ? min(t, m0) : t; };
+    auto cl1 = [&](uint32_t t) { return CLAMP ? min(t, m1) : t; };
+    walk3_zip<3>(q, [&](const uint32_t (&cell)[3][2]) {
+      const uint32_t n20 = cell[0][0] - cell[1][0] - cell[2][0];
+      const uint32_t n21 = cell[0][1] - cell[1][1] - cell[2][1];
+      fs += mi_term(F, cl0(cell[1][0]), cl1(cell[1][1]));
+      fs += mi_term(F, cl0(cell[2][0]), cl1(cell[2][1]));
+      fs += mi_term(F, cl0(n20), cl1(n21));
+    });
+  }
+  return fs;
 }
 
 }  // namespace fiuncho

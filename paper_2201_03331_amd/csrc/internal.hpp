@@ -36,16 +36,18 @@ constexpr uint32_t kPathTriples = 3;          // order 4, {0,1}^4 cells + triple
 constexpr uint32_t kPathMfma3 = 4;            // order 3 on the matrix cores (mfma_kernel<3>)
 constexpr uint32_t kPathMfmaRows = 5;         // orders 4, 5 on the matrix cores, every prefix row (mfma_rows_kernel)
 constexpr int kSelTriples = 41;               // scan_kernel selector: order-4 triple-table path only
+constexpr uint32_t kPathMfma4t = 6;           // order 4, {0,1}^4 cells on the matrix cores + triple and pair tables
 // matrix-core launch groups, in tile-space order: order 2 with int8, FP4 and
 // narrow FP4 operands, then order 3 likewise (group = 3 (order - 2) +
-// format), then orders 4 and 5 with every prefix row (groups 6, 7)
-constexpr int kMfmaGroups = 8;
+// format), then orders 4 and 5 with every prefix row (groups 6, 7), then
+// order 4 with triple tables (group 8)
+constexpr int kMfmaGroups = 9;
 // tile counters: the popcount kernel and its pilot, then each matrix-core
 // group's counting launch and its pilot
-// (the narrow FP4 groups of orders 2 and 3 and the groups of orders 4 and 5
-// run a second kernel, the dual one, over the same tiles: 2 more counters
-// each, after the groups')
-constexpr int kTileCounters = 2 + 2 * kMfmaGroups + 8;
+// (the narrow FP4 groups of orders 2 and 3, the groups of orders 4 and 5 and
+// the triple-table group run a second kernel, the dual one, over the same
+// tiles: 2 more counters each, after the groups')
+constexpr int kTileCounters = 2 + 2 * kMfmaGroups + 10;
 constexpr int kDualCounters = 2 + 2 * kMfmaGroups;
 
 // state the device writes during one run of a job (cleared at the start)
@@ -127,6 +129,8 @@ struct JobDesc {
   uint4 *pairs4;              // order 3 on the matrix cores with FP4 operands and fewer than 16,384
                               // samples, instead of pairs: [n][n_pad] of [g_a][g_j] -> 4 c0 | 4 c1 << 16
   uint32_t *triples;          // kPathTriples: [pair (a, b)][n_pad][g_a][g_b][g_j][class] counts
+  uint4 *triples4;            // kPathMfma4t instead of triples: [pair (a, b)][n_pad][g_a] of
+                              // [g_b][g_j] -> 4 c0 | 4 c1 << 16 (fewer than 16,384 samples)
   uint32_t shard_index;       // local tile = launch tile * shard_count + shard_index
   uint32_t shard_count;       // 1 = every tile
   uint32_t pilot_tiles;       // tiles sampled by the pilot pass (0: none)
@@ -180,6 +184,14 @@ void launch_mfma_rows(const Globals &g, int order, bool dual, int grid, hipStrea
 uint32_t mfma_dual_max_samples(int order);
 uint32_t mfma_rows_max_entries(int order, bool dual);
 int mfma_rows_grid_size(int order, bool dual, uint32_t f_entries);
+// order 4, {0,1}^4 cells on the matrix cores (FP4 operands) and the other
+// cells from the triple and pair tables (jobs of at most
+// mfma_narrow_max_samples() samples); dual as for the rows kernels (jobs of
+// at most mfma_t4_dual_max_samples() samples whose class sizes fit 24 bits
+// together)
+void launch_mfma_t4(const Globals &g, bool dual, int grid, hipStream_t s);
+int mfma_t4_grid_size(bool dual);
+uint32_t mfma_t4_dual_max_samples();
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
 void launch_pilot_select(const Globals &g, uint32_t max_pilot_slots, hipStream_t s);
 void launch_rescore(const Globals &g, uint32_t max_k, hipStream_t s);

@@ -1264,6 +1264,373 @@ void launch_mfma_rows(const Globals &g, int order, bool dual, int grid, hipStrea
   }
 }
 
+// ---------------------------------------------------------------------------
+// Order 4 on the matrix cores with stored triple tables
+// ---------------------------------------------------------------------------
+//
+// Only the {0,1}^4 cells of each combination (x, y, b, j) are counted here
+// (16 per combination instead of the 54 of every prefix row); the other 65
+// follow by inclusion-exclusion from the triple tables of (x, y, j),
+// (x, b, j), (y, b, j) and (x, y, b), the pair tables and the class counts.
+// The A rows are the {0,1}^3 genotype rows of prefixes (x, y, b): row r =
+// 8 k + 4 s + i of a fragment is prefix 2 s + k / 2 of the fragment's four,
+// with g_x = k mod 2, g_y = i / 2, g_b = i mod 2; the B rows are rows 0, 1 of
+// the last variants.  In the output (register e of lane l holds row
+// 8 (e / 4) + 4 (l / 32) + e mod 4) lane half s then holds every {0,1}^3 row
+// of prefixes 2 s and 2 s + 1 at its column's g_j: registers 0-7 the first,
+// 8-15 the second.  Lanes l and l ^ 1 hold the two g_j of the same j; the
+// lane of g_j = t scores prefix 2 s + t after taking its partner's 8 counts
+// of that prefix.
+//
+// Tiles: rows b = 2 .. n - 2; a tile is 16 prefixes (x, y) of [0, b),
+// consecutive in colex order, by 64 last variants; wave w takes prefixes
+// 8 (w / 2) + [0, 8) (4 per fragment) and last variants 32 (w mod 2) + [0, 32).
+constexpr uint32_t kT4Prefixes = 16;
+
+// The pair (x, y), x < y, of colex index q = C(y, 2) + x (per lane)
+__device__ __forceinline__ void colex_pair(u64 q, uint32_t &x, uint32_t &y) {
+  u64 t = (u64)((1.0 + __dsqrt_rn(1.0 + 8.0 * (double)q)) * 0.5);
+  while (t * (t - 1) / 2 > q) --t;
+  while ((t + 1) * t / 2 <= q) ++t;
+  y = (uint32_t)t;
+  x = (uint32_t)(q - t * (t - 1) / 2);
+}
+
+// An order-3 table's inputs, both classes in one register as 4 c0 | 4 c1 << 16
+// (byte offsets into a table of floats: counts below 16,384)
+struct Tab3P {
+  uint32_t D[2][2][2];  // [x][y][z] over {0,1}^3
+  uint32_t xy[2][2], xz[2][2], yz[2][2];
+  uint32_t Mx[2], My[2], Mz[2];
+  uint32_t m;
+};
+
+// The order-3 walk (walk_order3_packed's cell order) over NT packed tables at
+// once: visit(cells) sees the same cell of every table.  Every result is a
+// count, so the packed differences never borrow across the halves.
+template <int NT, typename Visit>
+__device__ __forceinline__ void walk3_zip_packed(const Tab3P (&q)[NT], Visit &&visit) {
+  uint32_t sum[NT], x2z[NT][2][2], t2yz[NT][2][2], cell[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) sum[t] = 0;
+  auto emit_cell = [&]() {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) sum[t] += cell[t];
+    visit(cell);
+  };
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int z = 0; z < 2; ++z) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) cell[t] = q[t].D[x][y][z];
+        emit_cell();
+      }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) cell[t] = q[t].xy[x][y] - q[t].D[x][y][0] - q[t].D[x][y][1];
+      emit_cell();  // (x, y, 2)
+    }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) cell[t] = x2z[t][x][z] = q[t].xz[x][z] - q[t].D[x][0][z] - q[t].D[x][1][z];
+      emit_cell();  // (x, 2, z)
+    }
+#pragma unroll
+  for (int y = 0; y < 2; ++y)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) cell[t] = t2yz[t][y][z] = q[t].yz[y][z] - q[t].D[0][y][z] - q[t].D[1][y][z];
+      emit_cell();  // (2, y, z)
+    }
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      cell[t] = q[t].Mx[x] - q[t].xy[x][0] - q[t].xy[x][1] - x2z[t][x][0] - x2z[t][x][1];
+    emit_cell();  // (x, 2, 2)
+  }
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      cell[t] = q[t].My[y] - q[t].xy[0][y] - q[t].xy[1][y] - t2yz[t][y][0] - t2yz[t][y][1];
+    emit_cell();  // (2, y, 2)
+  }
+#pragma unroll
+  for (int z = 0; z < 2; ++z) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      cell[t] = q[t].Mz[z] - q[t].xz[0][z] - q[t].xz[1][z] - t2yz[t][0][z] - t2yz[t][1][z];
+    emit_cell();  // (2, 2, z)
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) cell[t] = q[t].m - sum[t];
+  visit(cell);  // (2, 2, 2)
+}
+
+// One wave: prefixes q0 + [0, 8) (colex indices of pairs (x, y) below b) x last
+// variants j0 + [0, 32).  DUAL: both classes in one accumulator (class sizes
+// of at most 24 bits together); else class 0 first, kept as 16-bit pairs.
+template <bool DUAL>
+__device__ __forceinline__ void wave_t4(const Globals &g, const JV &v, uint32_t b, u64 q0, uint32_t j0,
+                                        uint32_t lane, const FI_LDS float *Fl) {
+  const uint32_t n = v.n, np = v.n_pad;
+  const uint32_t r = lane & 31, h = lane >> 5, gl = lane & 1;
+  const u64 nq = (u64)b * (b - 1) / 2;  // prefixes (x, y) below b
+  const FI_GLOBAL char *Bvc = reinterpret_cast<const FI_GLOBAL char *>(as_global(v.Bv));
+  const size_t word_bytes = (size_t)np * 16;  // Bv bytes of one word
+  uint32_t Q[2][2][16];                       // both classes per register
+  {
+    // the lane's A row of fragment f: prefix q0 + 4 f + 2 s + k / 2; prefixes
+    // past the last read variant n, a padding variant whose words are zero
+    const uint32_t k = r >> 3, s = (r >> 2) & 1, i = r & 3;
+    const uint32_t gx = k & 1, gy = i >> 1, gb = i & 1;
+    uint32_t ox[2], oy[2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      const u64 q = q0 + 4 * f + 2 * s + (k >> 1);
+      uint32_t x = n, y = n;
+      if (q < nq) colex_pair(q, x, y);
+      ox[f] = x * 16 + gx * 8 + 4 * h;
+      oy[f] = y * 16 + gy * 8 + 4 * h;
+    }
+    const uint32_t ob = b * 16 + gb * 8 + 4 * h, ol = j0 * 16 + r * 8 + 4 * h;
+    auto load_words = [&](uint32_t w, uint32_t (&xw)[7]) {
+      const FI_GLOBAL char *sw = Bvc + (size_t)w * word_bytes;
+      xw[0] = ld32(sw, ox[0]);
+      xw[1] = ld32(sw, oy[0]);
+      xw[2] = ld32(sw, ox[1]);
+      xw[3] = ld32(sw, oy[1]);
+      xw[4] = ld32(sw, ob);
+      xw[5] = ld32(sw, ol);
+      xw[6] = ld32(sw, ol + 256);
+    };
+    // A row = row of x AND row of y AND row of b
+    auto prep = [](const uint32_t (&xw)[7], uint32_t (&o)[4]) {
+      o[0] = xw[0] & xw[1] & xw[4];
+      o[1] = xw[2] & xw[3] & xw[4];
+      o[2] = xw[5];
+      o[3] = xw[6];
+    };
+    const auto ops = expanded_ops<7>(prep);
+    if constexpr (DUAL) contract_fp4_dual<4, 7>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
+    else contract_fp4_narrow<4, 7>(load_words, ops, v.W0, v.W1, Q);
+  }
+
+  // scoring from the packed tables (every count times 4, class 0 in the low
+  // half: byte offsets into the LDS f table)
+  const MiConst mc = mi_const(v);
+  float thr = current_threshold(v);
+  const FI_GLOBAL v4u *TT4 = reinterpret_cast<const FI_GLOBAL v4u *>(as_global(v.triples4));
+  const FI_GLOBAL v4u *PT4 = reinterpret_cast<const FI_GLOBAL v4u *>(as_global(v.pairs4));
+  const FI_GLOBAL uint32_t *marg = as_global(v.marg);
+  const FI_LDS char *Fb = (const FI_LDS char *)Fl;
+  auto term = [&](uint32_t p) {
+    const uint32_t o0 = p & 0xFFFFu, o1 = p >> 16;
+    const float f0 = *(const FI_LDS float *)(Fb + o0);
+    const float f1 = *(const FI_LDS float *)(Fb + o1);
+    const float f01 = *(const FI_LDS float *)(Fb + o0 + o1);
+    return (f0 + f1) - f01;
+  };
+  auto marg4 = [&](uint32_t var, int g4) { return pack_x4(marg[(size_t)var * 6 + 2 * g4], marg[(size_t)var * 6 + 2 * g4 + 1]); };
+  // the lane's two last variants j (fb = 0, 1) and their class counts
+  uint32_t jv[2], jj[2], Mj4[2][2];
+#pragma unroll
+  for (int fb = 0; fb < 2; ++fb) {
+    jv[fb] = j0 + 16 * fb + (r >> 1);
+    jj[fb] = jv[fb] < n ? jv[fb] : n - 1;
+#pragma unroll
+    for (int gj = 0; gj < 2; ++gj) Mj4[fb][gj] = marg4(jj[fb], gj);
+  }
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    // the prefix this lane scores in fragment f and its own order-3 table
+    const u64 q = q0 + 4 * f + 2 * h + gl;
+    const bool valid = q < nq;
+    uint32_t x = 0, y = 1;
+    if (valid) colex_pair(q, x, y);
+    const u64 pxy = pair_index(n, x, y);
+    Tab3P t3[3];  // [0]: (x, y, b); [1], [2]: the cells with g_j = 0, 1
+    {
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const v4u e = TT4[(pxy * np + b) * 2 + a];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) t3[0].D[a][c >> 1][c & 1] = e[c];
+      }
+      const v4u exy = PT4[(size_t)x * np + y], exb = PT4[(size_t)x * np + b], eyb = PT4[(size_t)y * np + b];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        t3[0].xy[c >> 1][c & 1] = exy[c];
+        t3[0].xz[c >> 1][c & 1] = exb[c];
+        t3[0].yz[c >> 1][c & 1] = eyb[c];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        t3[0].Mx[a] = marg4(x, a);
+        t3[0].My[a] = marg4(y, a);
+        t3[0].Mz[a] = marg4(b, a);
+      }
+      t3[0].m = pack_x4(v.m0, v.m1);
+    }
+    const u64 pxb = pair_index(n, x, b), pyb = pair_index(n, y, b);
+#pragma unroll
+    for (int fb = 0; fb < 2; ++fb) {
+      // the {0,1}^3 counts of the prefix at both g_j: own registers 8 gl +
+      // [0, 8) at g_j = gl, the partner's at 1 - gl
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const uint32_t lo = Q[f][fb][a], hi = Q[f][fb][8 + a];
+        const uint32_t own = gl ? hi : lo;
+        const uint32_t recv = xor1(gl ? lo : hi);
+        t3[1].D[a >> 2][(a >> 1) & 1][a & 1] = (gl ? recv : own) << 2;
+        t3[2].D[a >> 2][(a >> 1) & 1][a & 1] = (gl ? own : recv) << 2;
+      }
+      {
+        const uint32_t J = jj[fb];
+        v4u txy[2], txb[2], tyb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          txy[a] = TT4[(pxy * np + J) * 2 + a];
+          txb[a] = TT4[(pxb * np + J) * 2 + a];
+          tyb[a] = TT4[(pyb * np + J) * 2 + a];
+        }
+        const v4u pxj = PT4[(size_t)x * np + J], pyj = PT4[(size_t)y * np + J], pbj = PT4[(size_t)b * np + J];
+#pragma unroll
+        for (int gj = 0; gj < 2; ++gj) {
+          Tab3P &t = t3[1 + gj];
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              t.xy[a][c] = txy[a][c * 2 + gj];
+              t.xz[a][c] = txb[a][c * 2 + gj];
+              t.yz[a][c] = tyb[a][c * 2 + gj];
+            }
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            t.Mx[a] = pxj[a * 2 + gj];
+            t.My[a] = pyj[a * 2 + gj];
+            t.Mz[a] = pbj[a * 2 + gj];
+          }
+          t.m = Mj4[fb][gj];
+        }
+      }
+      const uint32_t j = jv[fb];
+      const bool active = valid && j < n;
+      float fs = mc.c;
+      if (active)
+        walk3_zip_packed<3>(t3, [&](const uint32_t (&cell)[3]) {
+          fs += term(cell[1]);
+          fs += term(cell[2]);
+          fs += term(cell[0] - cell[1] - cell[2]);
+        });
+      const uint32_t pre[3] = {x, y, b};
+      if (emit_with(v, active, fs * mc.inv_m,
+                    [&] { return lex_rank_prefix(g, n, 4, pre) + (u64)(j - b - 1); }, thr,
+                    lane) >= kRefreshAppends)
+        thr = current_threshold_lanes(v);
+    }
+  }
+}
+
+// The f table entries the kernel keeps in LDS: 8,192 (dual) or 16,384 (two
+// accumulators; the packed tables hold counts below 16,384); the host gives
+// it only jobs whose table fits
+template <bool DUAL>
+constexpr uint32_t t4_f_entries() { return DUAL ? mfma_f_entries(kMfmaF4Dual) : 16384u; }
+
+template <bool DUAL>
+__global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_t4_kernel(Globals g) {
+  __shared__ u64 s_tile;
+  extern __shared__ float s_f[];
+  const uint32_t lane = lane_id();
+  const uint32_t wave = uni(threadIdx.x >> 6);
+  const FI_LDS float *Fl = (const FI_LDS float *)s_f;
+  uint32_t f_job = ~0u;
+  RowHint hint;  // the row of the workgroup's last tile
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = g.tile_base + atomicAdd(g.tile_counter, 1ull);
+    __syncthreads();
+    const u64 t = uni64(s_tile);
+    __syncthreads();
+    if (t >= g.total_tiles) break;
+    JV v;
+    const FI_CONST JobDesc *jd;
+    u64 lt;
+    if (!locate_tile(g, t, wave, kMfmaPilotEmits, v, jd, lt)) continue;
+    // the host gives this kernel only such jobs
+    if (v.path != kPathMfma4t || v.m + 1 > t4_f_entries<false>()) continue;
+    {
+      // the dual and the two-accumulator kernels run over the same tiles,
+      // each skipping the other's jobs
+      const bool dual = bit_len(v.m0) + bit_len(v.m1) <= 24 && v.m + 1 <= t4_f_entries<true>();
+      if (dual != DUAL) {
+        if (threadIdx.x == 0) {
+          const u64 end = as_const(g.job_tile_start)[job_of_tile(g, t) + 1];
+          atomicMax(g.tile_counter, end - g.tile_base);
+        }
+        continue;
+      }
+    }
+    {
+      // the job's table, once the tile is known to be this kernel's (every
+      // wave has finished the previous tile: the barriers above)
+      const uint32_t jx = (uint32_t)(jd - as_const(g.jobs));
+      if (jx != f_job) {
+        const FI_GLOBAL float *Fh = as_global(uni_ptr(jd->Fh));
+        for (uint32_t i = threadIdx.x; i <= v.m; i += blockDim.x) s_f[i] = Fh[i];
+        f_job = jx;
+        __syncthreads();
+      }
+    }
+    cu64p rows = as_const(uni_ptr(jd->row_start));
+    const uint32_t rl = hint.find(jd, lt);
+    const u64 local = uni64(lt - rows[rl]);
+    const uint32_t b = rl + 2;
+    const uint32_t nj = (v.n - 1 - b + 63) / 64;
+    const u64 grp = local / nj;
+    const uint32_t jb = (uint32_t)(local - grp * nj);
+    const u64 q0 = grp * kT4Prefixes + 8 * (wave >> 1);
+    const uint32_t j0 = b + 1 + 64 * jb + 32 * (wave & 1);
+    // a wave without a prefix or a last variant has nothing to count; its
+    // pilot slots stay zero
+    if (q0 >= (u64)b * (b - 1) / 2 || j0 >= v.n) continue;
+    wave_t4<DUAL>(g, v, b, q0, j0, lane, Fl);
+  }
+}
+
+template <bool DUAL>
+int mfma_t4_grid() {
+  int dev = 0, cus = 0, per = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_t4_kernel<DUAL>, kMfmaWaves * 64,
+                                                     t4_f_entries<DUAL>() * sizeof(float));
+  if (cus <= 0) cus = 256;
+  if (per <= 0) per = 1;
+  return cus * per;
+}
+
+int mfma_t4_grid_size(bool dual) { return dual ? mfma_t4_grid<true>() : mfma_t4_grid<false>(); }
+uint32_t mfma_t4_dual_max_samples() { return t4_f_entries<true>() - 1; }
+
+void launch_mfma_t4(const Globals &g, bool dual, int grid, hipStream_t s) {
+  const dim3 gd(grid), bd(kMfmaWaves * 64);
+  if (dual) hipLaunchKernelGGL(mfma_t4_kernel<true>, gd, bd, t4_f_entries<true>() * sizeof(float), s, g);
+  else hipLaunchKernelGGL(mfma_t4_kernel<false>, gd, bd, t4_f_entries<false>() * sizeof(float), s, g);
+}
+
 // ORDER 2 or 3, FMT: operand format (kMfmaI8, kMfmaF4, kMfmaF4Narrow); the
 // kernel serves the jobs of that order and format (a batch with several
 // launches it once per group, each over the group's tiles)

@@ -477,20 +477,17 @@ __device__ __forceinline__ void tile_order3p(const Globals &g, const JV &v, uint
 // those two.
 // ---------------------------------------------------------------------------
 
-// lexicographic index of the pair (x, y), x < y, among the pairs of n
-__device__ __forceinline__ u64 pair_index(uint32_t n, uint32_t x, uint32_t y) {
-  return (u64)x * (n - 1) - (u64)x * (x - 1) / 2 + (y - x - 1);
-}
-
 // Pass over all (a, b, j), a < b < j: their {0,1}^3 counts per class into
-// the triple tables [pair_index(a, b)][j][g_a][g_b][g_j][class].  Grid: x =
+// the triple tables [pair_index(a, b)][j][g_a][g_b][g_j][class] (or, packed,
+// [pair_index(a, b)][j][g_a] of [g_b][g_j] -> 4 c0 | 4 c1 << 16).  Grid: x =
 // group of kScanWaves * 2 first variants a, y = b - 1, z = job; each wave
 // owns 2 first variants and walks the blocks of 64 last variants.
 __global__ __launch_bounds__(kScanWaves * 64) void triples_kernel(Globals g) {
   const JobDesc *jd = g.jobs + blockIdx.z;
   JV v = load_view(jd);
   uint32_t *TT = uni_ptr(as_const(jd)->triples);
-  if (TT == nullptr) return;
+  uint4 *TT4 = uni_ptr(as_const(jd)->triples4);
+  if (TT == nullptr && TT4 == nullptr) return;
   const JobState *st = v.st;
   if (uni((uint32_t)st->status) != 0) return;
   v.W0 = uni(st->W0);
@@ -523,7 +520,7 @@ __global__ __launch_bounds__(kScanWaves * 64) void triples_kernel(Globals g) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       const uint32_t a = a_first + p;
-      if (a < b && j < n) {
+      if (a < b && j < n && TT) {
         uint4 *dst = reinterpret_cast<uint4 *>(TT + (pair_index(n, a, b) * v.n_pad + j) * 16);
 #pragma unroll
         for (int x = 0; x < 2; ++x)
@@ -532,119 +529,14 @@ __global__ __launch_bounds__(kScanWaves * 64) void triples_kernel(Globals g) {
             dst[x * 2 + y] = make_uint4(acc[p][0][x][y][0], acc[p][1][x][y][0], acc[p][0][x][y][1],
                                         acc[p][1][x][y][1]);
       }
-    }
-  }
-}
-
-// The inputs of an order-3 table walk, held by value.
-struct Tab3 {
-  uint32_t D[2][2][2][2];  // [c][x][y][z] over {0,1}^3
-  uint32_t xy[8];          // sum over z: [x][y][c]
-  uint32_t xz[8];          // sum over y: [x][z][c]
-  uint32_t yz[8];          // sum over x: [y][z][c]
-  uint32_t Mx[2][2];       // [x][c]
-  uint32_t My[2][2];
-  uint32_t Mz[2][2];
-  uint32_t m[2];
-};
-
-// walk_order3 over NT tables at once: visit(cells) sees cell p of every table
-// (cells[t][class]), p in the walk's order.
-template <int NT, typename Visit>
-__device__ __forceinline__ void walk3_zip(const Tab3 (&q)[NT], Visit &&visit) {
-  uint32_t sum[NT][2], x2z[NT][2][2][2], t2yz[NT][2][2][2], cell[NT][2];
+      if (a < b && j < n && TT4) {
+        uint4 *dst = TT4 + (pair_index(n, a, b) * v.n_pad + j) * 2;
+        auto pk = [&](int x, int y, int z) { return (acc[p][0][x][y][z] << 2) | (acc[p][1][x][y][z] << 18); };
 #pragma unroll
-  for (int t = 0; t < NT; ++t) sum[t][0] = sum[t][1] = 0;
-  auto emit_cell = [&]() {
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      sum[t][0] += cell[t][0];
-      sum[t][1] += cell[t][1];
-    }
-    visit(cell);
-  };
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int z = 0; z < 2; ++z) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-          for (int c = 0; c < 2; ++c) cell[t][c] = q[t].D[c][x][y][z];
-        emit_cell();
+        for (int x = 0; x < 2; ++x) dst[x] = make_uint4(pk(x, 0, 0), pk(x, 0, 1), pk(x, 1, 0), pk(x, 1, 1));
       }
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-          cell[t][c] = q[t].xy[x * 4 + y * 2 + c] - q[t].D[c][x][y][0] - q[t].D[c][x][y][1];
-      emit_cell();  // (x, y, 2)
     }
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int z = 0; z < 2; ++z) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-          cell[t][c] = x2z[t][c][x][z] =
-              q[t].xz[x * 4 + z * 2 + c] - q[t].D[c][x][0][z] - q[t].D[c][x][1][z];
-      emit_cell();  // (x, 2, z)
-    }
-#pragma unroll
-  for (int y = 0; y < 2; ++y)
-#pragma unroll
-    for (int z = 0; z < 2; ++z) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-          cell[t][c] = t2yz[t][c][y][z] =
-              q[t].yz[y * 4 + z * 2 + c] - q[t].D[c][0][y][z] - q[t].D[c][1][y][z];
-      emit_cell();  // (2, y, z)
-    }
-#pragma unroll
-  for (int x = 0; x < 2; ++x) {
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-        cell[t][c] = q[t].Mx[x][c] - q[t].xy[x * 4 + c] - q[t].xy[x * 4 + 2 + c] - x2z[t][c][x][0] -
-                     x2z[t][c][x][1];
-    emit_cell();  // (x, 2, 2)
   }
-#pragma unroll
-  for (int y = 0; y < 2; ++y) {
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-        cell[t][c] = q[t].My[y][c] - q[t].xy[y * 2 + c] - q[t].xy[4 + y * 2 + c] - t2yz[t][c][y][0] -
-                     t2yz[t][c][y][1];
-    emit_cell();  // (2, y, 2)
-  }
-#pragma unroll
-  for (int z = 0; z < 2; ++z) {
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-        cell[t][c] = q[t].Mz[z][c] - q[t].xz[z * 2 + c] - q[t].xz[4 + z * 2 + c] - t2yz[t][c][0][z] -
-                     t2yz[t][c][1][z];
-    emit_cell();  // (2, 2, z)
-  }
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) cell[t][c] = q[t].m[c] - sum[t][c];
-  visit(cell);  // (2, 2, 2)
 }
 
 // {0,1}^4 counts of (a, b, c, j) for one class: the 8 rows of (a, b, c) with
@@ -687,17 +579,6 @@ __device__ __forceinline__ void count4t(cu64p ra, cu64p rb, cu64p rc, uint32_t w
   });
 }
 
-// 16 u32 of a triple table entry ([g_x][g_y][g_z][class]) and its slice at g_z
-__device__ __forceinline__ void load_triple(const FI_GLOBAL uint32_t *p, uint32_t (&q)[16]) {
-  const FI_GLOBAL u64 *p64 = reinterpret_cast<const FI_GLOBAL u64 *>(p);
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const u64 x = p64[i];
-    q[2 * i] = (uint32_t)x;
-    q[2 * i + 1] = (uint32_t)(x >> 32);
-  }
-}
-
 __device__ __forceinline__ void tile_order4t(const Globals &g, const JV &v, const uint32_t (&pre)[3],
                                              uint32_t j0, uint32_t lane) {
   const uint32_t n = v.n, a = pre[0], b = pre[1], c = pre[2];
@@ -722,99 +603,7 @@ __device__ __forceinline__ void tile_order4t(const Globals &g, const JV &v, cons
 
   const float thr = current_threshold(v);
   const MiConst mc = mi_const(v);
-  const FI_GLOBAL float *F = as_global(v.Fh);
-  const uint32_t np = v.n_pad;
-  const FI_GLOBAL uint32_t *TTg = as_global(v.triples);
-  const FI_CONST uint32_t *TTc = as_const(v.triples);
-  const FI_GLOBAL uint32_t *PTg = as_global(v.pairs);
-  const FI_CONST uint32_t *PTc = as_const(v.pairs);
-  cu32p marg = as_const(v.marg);
-  const FI_GLOBAL uint32_t *mgj = as_global(v.marg) + (size_t)jj * 6;
-
-  Tab3 q[3];  // [0]: (a, b, c) itself; [1], [2]: the cells with g_j = 0, 1
-  // the prefix's table (wave-uniform)
-  {
-    const FI_CONST uint32_t *e = TTc + (pair_index(n, a, b) * np + c) * 16;
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y)
-#pragma unroll
-        for (int z = 0; z < 2; ++z)
-#pragma unroll
-          for (int cl = 0; cl < 2; ++cl) q[0].D[cl][x][y][z] = e[x * 8 + y * 4 + z * 2 + cl];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      q[0].xy[i] = PTc[((size_t)a * np + b) * 8 + i];
-      q[0].xz[i] = PTc[((size_t)a * np + c) * 8 + i];
-      q[0].yz[i] = PTc[((size_t)b * np + c) * 8 + i];
-    }
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int cl = 0; cl < 2; ++cl) {
-        q[0].Mx[x][cl] = marg[(size_t)a * 6 + 2 * x + cl];
-        q[0].My[x][cl] = marg[(size_t)b * 6 + 2 * x + cl];
-        q[0].Mz[x][cl] = marg[(size_t)c * 6 + 2 * x + cl];
-      }
-    q[0].m[0] = v.m0;
-    q[0].m[1] = v.m1;
-  }
-  // the g_j slices (per lane)
-  {
-    uint32_t tab[16], tac[16], tbc[16], paj[8], pbj[8], pcj[8];
-    load_triple(TTg + (pair_index(n, a, b) * np + jj) * 16, tab);
-    load_triple(TTg + (pair_index(n, a, c) * np + jj) * 16, tac);
-    load_triple(TTg + (pair_index(n, b, c) * np + jj) * 16, tbc);
-    load_pair(PTg + ((size_t)a * np + jj) * 8, paj);
-    load_pair(PTg + ((size_t)b * np + jj) * 8, pbj);
-    load_pair(PTg + ((size_t)c * np + jj) * 8, pcj);
-#pragma unroll
-    for (int gj = 0; gj < 2; ++gj) {
-      Tab3 &t = q[1 + gj];
-#pragma unroll
-      for (int cl = 0; cl < 2; ++cl)
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int z = 0; z < 2; ++z) t.D[cl][x][y][z] = acc[cl][x][y][z][gj];
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-#pragma unroll
-          for (int cl = 0; cl < 2; ++cl) {
-            t.xy[x * 4 + y * 2 + cl] = tab[x * 8 + y * 4 + gj * 2 + cl];
-            t.xz[x * 4 + y * 2 + cl] = tac[x * 8 + y * 4 + gj * 2 + cl];
-            t.yz[x * 4 + y * 2 + cl] = tbc[x * 8 + y * 4 + gj * 2 + cl];
-          }
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int cl = 0; cl < 2; ++cl) {
-          t.Mx[x][cl] = paj[x * 4 + gj * 2 + cl];
-          t.My[x][cl] = pbj[x * 4 + gj * 2 + cl];
-          t.Mz[x][cl] = pcj[x * 4 + gj * 2 + cl];
-        }
-#pragma unroll
-      for (int cl = 0; cl < 2; ++cl) t.m[cl] = mgj[2 * gj + cl];
-    }
-  }
-  float fs = mc.c;
-  if (active) {
-    // every count is at most its class size; the clamps keep the table
-    // lookups inside [0, m] whatever the inputs hold
-    const uint32_t m0 = v.m0, m1 = v.m1;
-    walk3_zip<3>(q, [&](const uint32_t (&cell)[3][2]) {
-      const uint32_t n20 = cell[0][0] - cell[1][0] - cell[2][0];
-      const uint32_t n21 = cell[0][1] - cell[1][1] - cell[2][1];
-      fs += mi_term(F, min(cell[1][0], m0), min(cell[1][1], m1));
-      fs += mi_term(F, min(cell[2][0], m0), min(cell[2][1], m1));
-      fs += mi_term(F, min(n20, m0), min(n21, m1));
-    });
-  }
+  const float fs = order4_tables_sum<true, true>(v, as_global(v.Fh), acc, a, b, c, jj, active, mc.c);
   const u64 rank = lex_rank_prefix(g, n, 4, pre) + (u64)(j - c - 1);
   emit(v, active, fs * mc.inv_m, rank, thr, lane);
 }

@@ -57,6 +57,12 @@ CASES = [
     ("rows-two-acc", 4, 20, 9000, 0.5, K.KERNEL_MFMA_FP4),
     ("rows-dual", 5, 22, 300, 0.5, K.KERNEL_MFMA_FP4),
     ("rows-two-acc", 5, 16, 8200, 0.5, K.KERNEL_MFMA_FP4),
+    # order 4, {0,1}^4 cells on the matrix cores and packed triple tables:
+    # dual, two accumulators, and one prefix group short of 16 at every row
+    ("fp4-triples-dual", 4, 30, 400, 0.5, K.KERNEL_MFMA_FP4_TRIPLES),
+    ("fp4-triples-dual", 4, 37, 1001, 0.3, K.KERNEL_MFMA_FP4_TRIPLES),
+    ("fp4-triples-two-acc", 4, 21, 9000, 0.5, K.KERNEL_MFMA_FP4_TRIPLES),
+    ("fp4-triples-two-acc", 4, 18, 16383, 0.5, K.KERNEL_MFMA_FP4_TRIPLES),
 ]
 
 ENV = ("FIUNCHO_ORDER2_MFMA", "FIUNCHO_ORDER3_MFMA", "FIUNCHO_ORDER3_PAIRS", "FIUNCHO_ORDER4_TRIPLES")
@@ -87,3 +93,24 @@ def test_every_combination(case, monkeypatch):
     # another summation order, yet every one within the bound
     say(f"{name} k={k}: max |est - mi| = {np.abs(hits['est'] - hits['mi']).max():.3e} "
         f"(bound {fiuncho.estimate_bound(k, m):.3e})")
+
+
+def test_fp4_triples_large_jobs_use_unpacked_tables(monkeypatch):
+    """Order-4 jobs of 16,384 samples or more forced onto the matrix-core
+    triple-table kernel run on the popcount triple-table kernel instead (the
+    packed tables hold counts below 16,384), with the same results."""
+    for v in ENV:
+        monkeypatch.delenv(v, raising=False)
+    n, m, k = 14, 16384, 4
+    G, y = random_dataset(4242, n, m, 0.5, 1, 1)
+    try:
+        fiuncho.set_kernel(n, m, k, fiuncho.KERNEL_MFMA_FP4_TRIPLES)
+        fiuncho.set_profiling(True)
+        hits = fiuncho.scan(G, y, k, math.comb(n, k))
+        prof = fiuncho.get_profile()
+    finally:
+        fiuncho.set_profiling(False)
+        fiuncho.set_kernel(n, m, k, fiuncho.KERNEL_AUTO)
+    assert prof["kernels"] == 1 << fiuncho.KERNEL_TRIPLES
+    r_or, m_or = oracle.order_all(G, y, k)
+    compare_with_order(hits, r_or, m_or, k, n, m)
