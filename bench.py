@@ -7,7 +7,7 @@ selection, FP64 rescoring, final ordering) through fiuncho_scan_batch on a
 stream.  Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
-                  [--shard I/P] [--kernel auto|popcount|pairs|mfma|mfma-fp4|triples|mfma-fp4-triples] [--autotune]
+                  [--shard I/P] [--kernel auto|popcount|pairs|mfma|mfma-fp4|triples|mfma-fp4-tables] [--autotune]
 
 --shard I/P times one GPU's share of a search split across P GPUs (shard I
 of the job's work tiles); the rate is that share's combinations per second.
@@ -146,15 +146,15 @@ def cpu_baseline(d, budget_s: float = 15.0):
                                               f"on {threads} threads"}
 
 
-KERNEL_NAMES = {1: "popcount", 2: "pairs", 3: "mfma", 4: "triples", 5: "mfma-fp4", 6: "mfma-fp4-triples"}
+KERNEL_NAMES = {1: "popcount", 2: "pairs", 3: "mfma", 4: "triples", 5: "mfma-fp4", 6: "mfma-fp4-tables"}
 
 
 def arithmetic_of(kernels) -> str:
     """What the launched counting kernels compute in."""
     from paper_2201_03331_amd import fiuncho
     parts = []
-    if kernels & {fiuncho.KERNEL_MFMA_FP4, fiuncho.KERNEL_MFMA_FP4_TRIPLES}:
-        parts.append("{0,1}^k cells (orders 2-4; every prefix row at order 5) as a one-hot FP4 (E2M1) "
+    if kernels & {fiuncho.KERNEL_MFMA_FP4, fiuncho.KERNEL_MFMA_FP4_TABLES}:
+        parts.append("{0,1}^k cells (or every prefix row, orders 4-5) as a one-hot FP4 (E2M1) "
                      "contraction on the matrix cores with FP32 accumulation (exact integer counts below 2^24)")
     if fiuncho.KERNEL_MFMA in kernels:
         parts.append("{0,1}^k cells as a one-hot int8 contraction on the matrix cores with int32 accumulation")
@@ -237,16 +237,18 @@ def measure(datasets, steps, warmup, graph=False, plain=False, shard=None):
         kern = fiuncho.get_kernel(d.n, d.m, d.order)
         if kern == fiuncho.KERNEL_MFMA_FP4 and d.order >= 4 and d.m > 20447:
             kern = fiuncho.KERNEL_POPCOUNT  # the matrix cores take orders 4-5 up to 20,447 samples
-        if kern == fiuncho.KERNEL_MFMA_FP4_TRIPLES and d.m >= 16384:
-            kern = fiuncho.KERNEL_TRIPLES  # packed tables: the matrix cores take fewer than 16,384 samples
+        if kern == fiuncho.KERNEL_MFMA_FP4_TABLES and d.m >= 16384:
+            # packed tables: fewer than 16,384 samples
+            kern = (fiuncho.KERNEL_TRIPLES if d.order == 4 else
+                    fiuncho.KERNEL_MFMA_FP4 if d.m <= 20447 else fiuncho.KERNEL_POPCOUNT)
         kernels.add(kern)
-        if kern in (fiuncho.KERNEL_MFMA, fiuncho.KERNEL_MFMA_FP4, fiuncho.KERNEL_MFMA_FP4_TRIPLES):
+        if kern in (fiuncho.KERNEL_MFMA, fiuncho.KERNEL_MFMA_FP4, fiuncho.KERNEL_MFMA_FP4_TABLES):
             # cells counted on the matrix cores for every combination over
-            # every sample: the {0,1}^k cells at orders 2-4 (4, 8 and 16; the
-            # others come from class counts and lower-order tables), at orders
-            # 4 and 5 on the rows kernel every prefix row against rows 0, 1 of
-            # the last variant (2 * 3^(k-1))
-            cells = (4 if d.order == 2 else 8 if d.order == 3 else 16 if kern == fiuncho.KERNEL_MFMA_FP4_TRIPLES
+            # every sample: the {0,1}^k cells (2^k; the others come from class
+            # counts and lower-order tables), on the rows kernel of orders 4
+            # and 5 every prefix row against rows 0, 1 of the last variant
+            # (2 * 3^(k-1))
+            cells = (4 if d.order == 2 else 8 if d.order == 3 else 2 ** d.order if kern == fiuncho.KERNEL_MFMA_FP4_TABLES
                      else 2 * 3 ** (d.order - 1))
             ops = 2 * cells * d.m * share(d)
             mfma_ops += ops
@@ -259,7 +261,7 @@ def measure(datasets, steps, warmup, graph=False, plain=False, shard=None):
     if mfma_ms > scan_ms:
         achieved = mfma_ops / (mfma_ms / 1e3) / 1e12
         peak = mfma_ops / mfma_peak_s / 1e12
-        fp4 = bool(kernels & {fiuncho.KERNEL_MFMA_FP4, fiuncho.KERNEL_MFMA_FP4_TRIPLES})
+        fp4 = bool(kernels & {fiuncho.KERNEL_MFMA_FP4, fiuncho.KERNEL_MFMA_FP4_TABLES})
         i8 = fiuncho.KERNEL_MFMA in kernels
         fmt = "int8 and FP4" if fp4 and i8 else "FP4" if fp4 else "int8"
         roofline = {"bound": "mfma", "kernel": f"mfma_kernel (one-hot {fmt} contraction + FP32 MI + filter)",
@@ -328,7 +330,7 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the per-workload block (the other workloads of the metric)")
     ap.add_argument("--kernel", default="auto", choices=("auto", "popcount", "pairs", "mfma", "mfma-fp4", "triples",
-                                                         "mfma-fp4-triples"),
+                                                         "mfma-fp4-tables"),
                     help="force this counting kernel for every dataset shape it handles")
     ap.add_argument("--autotune", action="store_true",
                     help="time the kernels for every dataset shape first (fiuncho_autotune)")
@@ -362,7 +364,7 @@ def main():
         forced = {"popcount": fiuncho.KERNEL_POPCOUNT, "pairs": fiuncho.KERNEL_PAIRS,
                   "mfma": fiuncho.KERNEL_MFMA, "mfma-fp4": fiuncho.KERNEL_MFMA_FP4,
                   "triples": fiuncho.KERNEL_TRIPLES,
-                  "mfma-fp4-triples": fiuncho.KERNEL_MFMA_FP4_TRIPLES}[args.kernel]
+                  "mfma-fp4-tables": fiuncho.KERNEL_MFMA_FP4_TABLES}[args.kernel]
         for d in datasets:
             if fiuncho.lib().fiuncho_set_kernel(d.n, d.m, d.order, forced) != fiuncho.OK:
                 ap.error(f"kernel {args.kernel} does not handle order {d.order}")

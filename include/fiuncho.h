@@ -278,13 +278,19 @@ int fiuncho_shard_counts(uint32_t snps, uint32_t samples, int order, uint32_t un
                                      variant on the matrix cores (jobs of at
                                      most 20,447 samples; larger ones run on
                                      the popcount kernel) */
-#define FIUNCHO_KERNEL_MFMA_FP4_TRIPLES 6 /* order 4: the {0,1}^4 cells on the
-                                     matrix cores (FP4 operands, {0,1}^3 rows
-                                     of 4 prefixes per operand fragment), the
-                                     rest from packed triple and pair tables
-                                     (32 bytes per pair and variant; jobs of
-                                     fewer than 16,384 samples, larger ones
-                                     run on FIUNCHO_KERNEL_TRIPLES) */
+#define FIUNCHO_KERNEL_MFMA_FP4_TABLES 6 /* orders 4 and 5: the {0,1}^k cells
+                                     on the matrix cores (FP4 operands,
+                                     {0,1}^(k-1) rows of 4 or 2 prefixes per
+                                     operand fragment), the rest by
+                                     inclusion-exclusion from packed lower-
+                                     order tables: triple and pair tables
+                                     (32 bytes per pair and variant, up to
+                                     16 GiB) and at order 5 quad tables (64
+                                     bytes per triple and variant, up to
+                                     48 GiB), built on the device per call;
+                                     jobs of fewer than 16,384 samples (larger
+                                     ones: order 4 on FIUNCHO_KERNEL_TRIPLES,
+                                     order 5 on FIUNCHO_KERNEL_MFMA_FP4) */
 
 /* The kernel a job of this shape would use now (a FIUNCHO_KERNEL_* value),
  * or FIUNCHO_E_ORDER. */

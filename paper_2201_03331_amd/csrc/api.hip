@@ -128,7 +128,9 @@ void build_rows(uint32_t n, uint32_t k, uint32_t path, std::vector<u64> &row_sta
   // rows b (last prefix variant): groups of prefixes (one per wave on the
   // popcount kernel, 16 per tile on the order-4 triple-table matrix-core
   // kernel) x blocks of 64 last variants
-  const u64 G = path == fiuncho::kPathMfma4t ? 16 : (u64)fiuncho::kScanWaves;
+  const u64 G = path == fiuncho::kPathMfma4t   ? 16
+                : path == fiuncho::kPathMfma5q ? 8
+                                               : (u64)fiuncho::kScanWaves;
   for (u64 b = k - 2; b + 2 <= n; ++b) {
     const u64 groups = ceil_div(binom_host(b, k - 2), G);
     acc += groups * ceil_div(n - 1 - b, 64);
@@ -181,6 +183,7 @@ void for_each_tile(uint32_t n, uint32_t k, uint32_t path, Fn fn) {
   const u64 G = path == fiuncho::kPathPairs    ? (u64)fiuncho::kScanWaves * fiuncho::kOrder3Prefixes
                 : path == fiuncho::kPathMfma3  ? 32
                 : path == fiuncho::kPathMfma4t ? 16
+                : path == fiuncho::kPathMfma5q ? 8
                                                : (u64)fiuncho::kScanWaves;
   for (u64 b = (by_pairs ? 1 : k - 2); b + 2 <= N; ++b) {
     const u64 prefixes = by_pairs ? b : binom_host(b, k - 2);
@@ -238,6 +241,13 @@ u64 triple_table_bytes(uint32_t n, bool packed = false) {
   return binom_host(n, 2) * n_pad * (packed ? 32 : 64);
 }
 constexpr u64 kMaxTripleTableBytes = 16ull << 30;
+// packed quad tables (order 5 with lower-order tables): 64 bytes per triple
+// and variant
+u64 quad_table_bytes(uint32_t n) {
+  const u64 n_pad = (u64)(n + 63) / 64 * 64 + 64;
+  return binom_host(n, 3) * n_pad * 64;
+}
+constexpr u64 kMaxQuadTableBytes = 48ull << 30;
 
 bool kernel_valid(int kernel, uint32_t n, uint32_t k) {
   switch (kernel) {
@@ -246,8 +256,9 @@ bool kernel_valid(int kernel, uint32_t n, uint32_t k) {
     case FIUNCHO_KERNEL_MFMA: return k == 2 || (k == 3 && n >= 3);
     case FIUNCHO_KERNEL_MFMA_FP4: return k == 2 || ((k == 3 || k == 4 || k == 5) && n >= k);
     case FIUNCHO_KERNEL_TRIPLES: return k == 4 && n >= 4 && triple_table_bytes(n) <= kMaxTripleTableBytes;
-    case FIUNCHO_KERNEL_MFMA_FP4_TRIPLES:
-      return k == 4 && n >= 4 && triple_table_bytes(n, true) <= kMaxTripleTableBytes;
+    case FIUNCHO_KERNEL_MFMA_FP4_TABLES:
+      return (k == 4 || k == 5) && n >= k && triple_table_bytes(n, true) <= kMaxTripleTableBytes &&
+             (k == 4 || quad_table_bytes(n) <= kMaxQuadTableBytes);
     default: return false;
   }
 }
@@ -261,16 +272,20 @@ bool kernel_valid(int kernel, uint32_t n, uint32_t k) {
 // fit in 16 GiB and the job has fewer than 16,384 samples (200 x 4,000: 5.7 ms
 // a search, triple tables on the popcount kernel 18.8 ms, every prefix row on
 // the matrix cores 17.6 ms), else the popcount kernel's triple tables, else
-// every prefix row on the matrix cores; order 5 the matrix cores (1.9 times
-// the popcount kernel at 200 x 4,000).  The matrix cores take every prefix
-// row of orders 4 and 5 up to 20,447 samples.
+// every prefix row on the matrix cores.  Order 5 likewise with quad tables
+// while they fit in 48 GiB (200 x 4,000: 1.32 s, every prefix row on the
+// matrix cores 1.93 s, popcount 3.7 s), else every prefix row on the matrix
+// cores.  The matrix cores take every prefix row of orders 4 and 5 up to
+// 20,447 samples.
 int rule_kernel(uint32_t n, uint32_t m, uint32_t k) {
   const u64 words = ceil_div(m, 64);
   const bool rows = m <= fiuncho::mfma_narrow_max_samples() && n >= k;
   if (k == 3 && n >= 3) return FIUNCHO_KERNEL_MFMA_FP4;
-  if (k == 4 && m < 16384 && kernel_valid(FIUNCHO_KERNEL_MFMA_FP4_TRIPLES, n, k))
-    return FIUNCHO_KERNEL_MFMA_FP4_TRIPLES;
+  if (k == 4 && m < 16384 && kernel_valid(FIUNCHO_KERNEL_MFMA_FP4_TABLES, n, k))
+    return FIUNCHO_KERNEL_MFMA_FP4_TABLES;
   if (k == 4 && kernel_valid(FIUNCHO_KERNEL_TRIPLES, n, k)) return FIUNCHO_KERNEL_TRIPLES;
+  if (k == 5 && m < 16384 && kernel_valid(FIUNCHO_KERNEL_MFMA_FP4_TABLES, n, k))
+    return FIUNCHO_KERNEL_MFMA_FP4_TABLES;
   if ((k == 4 || k == 5) && rows) return FIUNCHO_KERNEL_MFMA_FP4;
   if (k == 2 && !(n >= 256 && n < 4096 && words < 128)) return FIUNCHO_KERNEL_MFMA_FP4;
   return FIUNCHO_KERNEL_POPCOUNT;
@@ -312,7 +327,7 @@ int choose_wps(uint32_t n, uint32_t m, uint32_t k) {
 
 bool on_matrix_cores(uint32_t path) {
   return path == fiuncho::kPathMfma2 || path == fiuncho::kPathMfma3 || path == fiuncho::kPathMfmaRows ||
-         path == fiuncho::kPathMfma4t;
+         path == fiuncho::kPathMfma4t || path == fiuncho::kPathMfma5q;
 }
 
 uint32_t kernel_path(int kernel, uint32_t k) {
@@ -322,7 +337,7 @@ uint32_t kernel_path(int kernel, uint32_t k) {
     case FIUNCHO_KERNEL_MFMA_FP4:
       return k == 2 ? fiuncho::kPathMfma2 : k == 3 ? fiuncho::kPathMfma3 : fiuncho::kPathMfmaRows;
     case FIUNCHO_KERNEL_TRIPLES: return fiuncho::kPathTriples;
-    case FIUNCHO_KERNEL_MFMA_FP4_TRIPLES: return fiuncho::kPathMfma4t;
+    case FIUNCHO_KERNEL_MFMA_FP4_TABLES: return k == 4 ? fiuncho::kPathMfma4t : fiuncho::kPathMfma5q;
     default: return fiuncho::kPathGeneric;
   }
 }
@@ -338,7 +353,7 @@ struct JobLayout {
   u64 total;
   uint32_t cand_cap, l1_cap, sel_cap;
   size_t off_G, off_y, off_idx, off_Bv, off_Bs, off_marg, off_hist, off_phist, off_cand, off_l1, off_sel,
-      off_sel2, off_state, off_out, off_nout, off_status, off_pairs, off_pairs4, off_triples, off_triples4;
+      off_sel2, off_state, off_out, off_nout, off_status, off_pairs, off_pairs4, off_triples, off_triples4, off_quads4;
   // plan (uploaded)
   size_t off_rows, off_F32, off_Fh, off_P64;
   std::vector<u64> row_start;
@@ -354,6 +369,7 @@ int mfma_group(const JobLayout &J) {
   if (!on_matrix_cores(J.path)) return -1;
   if (J.path == fiuncho::kPathMfmaRows) return 6 + (int)J.k - 4;  // orders 4, 5
   if (J.path == fiuncho::kPathMfma4t) return 8;
+  if (J.path == fiuncho::kPathMfma5q) return 9;
   const int fmt = !J.fp4 ? 0 : J.m <= fiuncho::mfma_narrow_max_samples() ? 2 : 1;
   return 3 * (J.path == fiuncho::kPathMfma3 ? 1 : 0) + fmt;
 }
@@ -361,7 +377,7 @@ int mfma_group(const JobLayout &J) {
 struct Layout {
   std::vector<JobLayout> jobs;
   std::vector<uint32_t> order;  // tile-space order of the jobs (costliest first)
-  uint32_t nmax, kmax, max_n_pad, max_wcap, max_cand_cap, max_sel, max_pairs_n, max_triples_n;
+  uint32_t nmax, kmax, max_n_pad, max_wcap, max_cand_cap, max_sel, max_pairs_n, max_triples_n, max_quads_n;
   size_t plan_begin, plan_end;  // uploaded region
   size_t off_desc, off_jts, off_jps, off_binom, off_counter;
   // tile-space order: [0, n_scan) popcount kernel, then the jobs of each
@@ -383,6 +399,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
   L.max_sel = 0;
   L.max_pairs_n = 0;
   L.max_triples_n = 0;
+  L.max_quads_n = 0;
   size_t off = 0;
   // per-job data
   for (uint32_t i = 0; i < n_jobs; ++i) {
@@ -406,7 +423,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     J.sel_cap = (uint32_t)std::max<u64>(std::min<u64>(J.top_n, J.total), 1);
     const int kern = choose_kernel(J.n, J.m, J.k);
     J.path = kernel_path(kern, J.k);
-    J.fp4 = kern == FIUNCHO_KERNEL_MFMA_FP4 || kern == FIUNCHO_KERNEL_MFMA_FP4_TRIPLES;
+    J.fp4 = kern == FIUNCHO_KERNEL_MFMA_FP4 || kern == FIUNCHO_KERNEL_MFMA_FP4_TABLES;
     J.wps = (uint32_t)choose_wps(J.n, J.m, J.k);
     // orders 4 and 5 on the matrix cores keep counts in 16 bits and the f
     // table in LDS: larger jobs run on the popcount kernel
@@ -414,11 +431,19 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
       J.path = fiuncho::kPathGeneric;
       J.fp4 = 0;
     }
-    // order 4 on the matrix cores with triple tables: packed tables, counts
-    // below 16,384; larger jobs use the unpacked tables on the popcount kernel
-    if (J.path == fiuncho::kPathMfma4t && J.m >= 16384) {
-      J.path = fiuncho::kPathTriples;
-      J.fp4 = 0;
+    // orders 4 and 5 on the matrix cores with lower-order tables: packed
+    // tables, counts below 16,384; larger order-4 jobs use the unpacked
+    // triple tables on the popcount kernel, larger order-5 jobs every prefix
+    // row on the matrix cores (up to 20,447 samples) or the popcount kernel
+    if ((J.path == fiuncho::kPathMfma4t || J.path == fiuncho::kPathMfma5q) && J.m >= 16384) {
+      if (J.k == 4) {
+        J.path = fiuncho::kPathTriples;
+        J.fp4 = 0;
+      } else {
+        const bool rows = J.m <= fiuncho::mfma_narrow_max_samples();
+        J.path = rows ? fiuncho::kPathMfmaRows : fiuncho::kPathGeneric;
+        J.fp4 = rows ? 1 : 0;
+      }
     }
     build_rows(J.n, J.k, J.path, J.row_start);
     J.nrows = (uint32_t)(J.row_start.size() - 1);
@@ -455,12 +480,15 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
              : J.path == fiuncho::kPathPairs ? words * 8 * fiuncho::kOrder3Prefixes
              : J.path == fiuncho::kPathTriples ? words * 20
              : J.path == fiuncho::kPathMfma4t ? words * 16 * 16
+             : J.path == fiuncho::kPathMfma5q ? words * 32 * 8
                                              : words * 18 * std::pow(3.0, (double)J.k - 3);
     const bool need_pairs = J.path == fiuncho::kPathPairs || J.path == fiuncho::kPathTriples ||
-                            J.path == fiuncho::kPathMfma3 || J.path == fiuncho::kPathMfma4t;
+                            J.path == fiuncho::kPathMfma3 || J.path == fiuncho::kPathMfma4t ||
+                            J.path == fiuncho::kPathMfma5q;
     if (need_pairs) L.max_pairs_n = std::max(L.max_pairs_n, J.n);
-    if (J.path == fiuncho::kPathTriples || J.path == fiuncho::kPathMfma4t)
+    if (J.path == fiuncho::kPathTriples || J.path == fiuncho::kPathMfma4t || J.path == fiuncho::kPathMfma5q)
       L.max_triples_n = std::max(L.max_triples_n, J.n);
+    if (J.path == fiuncho::kPathMfma5q) L.max_quads_n = std::max(L.max_quads_n, J.n);
     L.nmax = std::max(L.nmax, J.n);
     L.kmax = std::max(L.kmax, J.k);
     L.max_n_pad = std::max(L.max_n_pad, J.n_pad);
@@ -492,11 +520,14 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     // the order-3 FP4 matrix-core kernels score from packed pair tables when
     // every count fits 14 bits (fewer than 16,384 samples)
     const bool packed_pairs = (J.path == fiuncho::kPathMfma3 && J.fp4 && J.m < 16384) ||
-                              J.path == fiuncho::kPathMfma4t;
+                              J.path == fiuncho::kPathMfma4t || J.path == fiuncho::kPathMfma5q;
     J.off_pairs = need_pairs && !packed_pairs ? take(sizeof(uint32_t) * 8 * (size_t)J.n * J.n_pad) : 0;
     J.off_pairs4 = packed_pairs ? take(sizeof(uint32_t) * 4 * (size_t)J.n * J.n_pad) : 0;
     J.off_triples = J.path == fiuncho::kPathTriples ? take((size_t)triple_table_bytes(J.n)) : 0;
-    J.off_triples4 = J.path == fiuncho::kPathMfma4t ? take((size_t)triple_table_bytes(J.n, true)) : 0;
+    J.off_triples4 = J.path == fiuncho::kPathMfma4t || J.path == fiuncho::kPathMfma5q
+                         ? take((size_t)triple_table_bytes(J.n, true))
+                         : 0;
+    J.off_quads4 = J.path == fiuncho::kPathMfma5q ? take((size_t)quad_table_bytes(J.n)) : 0;
   }
   // plan region
   L.plan_begin = off;
@@ -658,6 +689,7 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
     d.pairs4 = J.off_pairs4 ? reinterpret_cast<uint4 *>(ws + J.off_pairs4) : nullptr;
     d.triples = J.off_triples ? reinterpret_cast<uint32_t *>(ws + J.off_triples) : nullptr;
     d.triples4 = J.off_triples4 ? reinterpret_cast<uint4 *>(ws + J.off_triples4) : nullptr;
+    d.quads4 = J.off_quads4 ? reinterpret_cast<uint4 *>(ws + J.off_quads4) : nullptr;
     d.state = reinterpret_cast<JobState *>(ws + J.off_state);
     d.out = host_inputs ? reinterpret_cast<fiuncho_hit *>(ws + J.off_out) : jobs[i].out;
     d.n_out = host_inputs ? reinterpret_cast<uint32_t *>(ws + J.off_nout) : jobs[i].n_out;
@@ -833,7 +865,8 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   for (auto &J : L.jobs)
     kernels |= 1u << (J.path == fiuncho::kPathPairs     ? FIUNCHO_KERNEL_PAIRS
                       : J.path == fiuncho::kPathTriples ? FIUNCHO_KERNEL_TRIPLES
-                      : J.path == fiuncho::kPathMfma4t  ? FIUNCHO_KERNEL_MFMA_FP4_TRIPLES
+                      : J.path == fiuncho::kPathMfma4t || J.path == fiuncho::kPathMfma5q
+                          ? FIUNCHO_KERNEL_MFMA_FP4_TABLES
                       : on_matrix_cores(J.path)         ? (J.fp4 ? FIUNCHO_KERNEL_MFMA_FP4 : FIUNCHO_KERNEL_MFMA)
                                                       : FIUNCHO_KERNEL_POPCOUNT);
   if ((st = prof_begin(combos, kernels, reinterpret_cast<JobState *>(ws + L.jobs[0].off_state))))
@@ -843,6 +876,7 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   fiuncho::launch_pack(g, L.max_n_pad, L.max_wcap, s);
   if (L.max_pairs_n) fiuncho::launch_pairs(g, L.max_pairs_n, s);
   if (L.max_triples_n) fiuncho::launch_triples(g, L.max_triples_n, s);
+  if (L.max_quads_n) fiuncho::launch_quads(g, L.max_quads_n, s);
   if ((st = prof_record(1, s))) return st;
   // job tile and pilot starts in tile-space order (as uploaded)
   const uint32_t nj = (uint32_t)L.jobs.size();
@@ -885,9 +919,10 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   auto counting = [&](const Globals &c, int q) {
     if (c.total_tiles <= c.tile_base) return;
     const u64 tiles = c.total_tiles - c.tile_base;
-    if (q == 8) {  // order 4 with triple tables
-      const int grid = (int)std::min<u64>((u64)capped(c, fiuncho::mfma_t4_grid_size(false)), tiles);
-      fiuncho::launch_mfma_t4(c, false, grid, s);
+    if (q >= 8) {  // orders 4, 5 with lower-order tables
+      const int order = q - 4;
+      const int grid = (int)std::min<u64>((u64)capped(c, fiuncho::mfma_sub_grid_size(order, false)), tiles);
+      fiuncho::launch_mfma_sub(c, order, false, grid, s);
       return;
     }
     if (q >= 6) {  // orders 4, 5: every prefix row on the matrix cores
@@ -917,19 +952,19 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
       if (L.n_group[q]) {
         const Globals c = launch_globals(g, starts, first, L.n_group[q], pilot, 2 + 2 * q + pilot);
         const int slot = q == 2 ? 0 : q == 5 ? 1 : q >= 6 ? q - 4 : -1;
-        const bool t4 = q == 8;  // order 4 with triple tables
+        const bool sub = q >= 8;  // orders 4, 5 with lower-order tables
         // no dual launch when no job of the group has few enough samples
-        const int order = t4 ? 4 : q >= 6 ? q - 2 : 2 + q / 3;
-        const uint32_t dual_max = t4 ? fiuncho::mfma_t4_dual_max_samples() : fiuncho::mfma_dual_max_samples(order);
+        const int order = sub ? q - 4 : q >= 6 ? q - 2 : 2 + q / 3;
+        const uint32_t dual_max = sub ? fiuncho::mfma_sub_dual_max_samples() : fiuncho::mfma_dual_max_samples(order);
         uint32_t min_m = ~0u;
         for (uint32_t i = first; i < first + L.n_group[q]; ++i) min_m = std::min(min_m, L.jobs[L.order[i]].m);
         if (slot >= 0 && c.total_tiles > c.tile_base && min_m <= dual_max) {
           Globals d = c;
           d.tile_counter = g.tile_counter + fiuncho::kDualCounters + 2 * slot + pilot;
           const u64 tiles = d.total_tiles - d.tile_base;
-          if (t4) {
-            const int grid = (int)std::min<u64>((u64)capped(d, fiuncho::mfma_t4_grid_size(true)), tiles);
-            fiuncho::launch_mfma_t4(d, true, grid, s);
+          if (sub) {
+            const int grid = (int)std::min<u64>((u64)capped(d, fiuncho::mfma_sub_grid_size(order, true)), tiles);
+            fiuncho::launch_mfma_sub(d, order, true, grid, s);
           } else if (q >= 6) {
             d.lds_f_entries = rows_f_entries(d, order, true);
             const int grid = (int)std::min<u64>(
@@ -1448,7 +1483,7 @@ int fiuncho_autotune(uint32_t snps, uint32_t samples, int order, uint32_t reps, 
     const uint32_t k = (uint32_t)order;
     std::vector<int> cands;
     for (int c : {FIUNCHO_KERNEL_POPCOUNT, FIUNCHO_KERNEL_PAIRS, FIUNCHO_KERNEL_MFMA, FIUNCHO_KERNEL_TRIPLES,
-                  FIUNCHO_KERNEL_MFMA_FP4, FIUNCHO_KERNEL_MFMA_FP4_TRIPLES})
+                  FIUNCHO_KERNEL_MFMA_FP4, FIUNCHO_KERNEL_MFMA_FP4_TABLES})
       if (kernel_valid(c, snps, k)) cands.push_back(c);
     int best = cands[0], best_wps = 0;
     {

@@ -23,6 +23,7 @@ struct JV {
   const uint4 *pairs4;
   const uint32_t *triples;
   const uint4 *triples4;
+  const uint4 *quads4;
   uint32_t path;
   uint32_t fp4;               // matrix-core paths: FP4 operands (else int8)
   const float *Fh;
@@ -56,6 +57,7 @@ __device__ __forceinline__ JV load_view(const JobDesc *jd) {
   v.pairs4 = uni_ptr(J->pairs4);
   v.triples = uni_ptr(J->triples);
   v.triples4 = uni_ptr(J->triples4);
+  v.quads4 = uni_ptr(J->quads4);
   v.path = uni(J->path);
   v.fp4 = uni(J->fp4);
   v.Fh = uni_ptr(J->Fh);

@@ -37,17 +37,18 @@ constexpr uint32_t kPathMfma3 = 4;            // order 3 on the matrix cores (mf
 constexpr uint32_t kPathMfmaRows = 5;         // orders 4, 5 on the matrix cores, every prefix row (mfma_rows_kernel)
 constexpr int kSelTriples = 41;               // scan_kernel selector: order-4 triple-table path only
 constexpr uint32_t kPathMfma4t = 6;           // order 4, {0,1}^4 cells on the matrix cores + triple and pair tables
+constexpr uint32_t kPathMfma5q = 7;           // order 5, {0,1}^5 cells on the matrix cores + quad, triple, pair tables
 // matrix-core launch groups, in tile-space order: order 2 with int8, FP4 and
 // narrow FP4 operands, then order 3 likewise (group = 3 (order - 2) +
 // format), then orders 4 and 5 with every prefix row (groups 6, 7), then
-// order 4 with triple tables (group 8)
-constexpr int kMfmaGroups = 9;
+// orders 4 and 5 with lower-order tables (groups 8, 9)
+constexpr int kMfmaGroups = 10;
 // tile counters: the popcount kernel and its pilot, then each matrix-core
 // group's counting launch and its pilot
 // (the narrow FP4 groups of orders 2 and 3, the groups of orders 4 and 5 and
-// the triple-table group run a second kernel, the dual one, over the same
-// tiles: 2 more counters each, after the groups')
-constexpr int kTileCounters = 2 + 2 * kMfmaGroups + 10;
+// the lower-order-table groups run a second kernel, the dual one, over the
+// same tiles: 2 more counters each, after the groups')
+constexpr int kTileCounters = 2 + 2 * kMfmaGroups + 12;
 constexpr int kDualCounters = 2 + 2 * kMfmaGroups;
 
 // state the device writes during one run of a job (cleared at the start)
@@ -129,8 +130,10 @@ struct JobDesc {
   uint4 *pairs4;              // order 3 on the matrix cores with FP4 operands and fewer than 16,384
                               // samples, instead of pairs: [n][n_pad] of [g_a][g_j] -> 4 c0 | 4 c1 << 16
   uint32_t *triples;          // kPathTriples: [pair (a, b)][n_pad][g_a][g_b][g_j][class] counts
-  uint4 *triples4;            // kPathMfma4t instead of triples: [pair (a, b)][n_pad][g_a] of
-                              // [g_b][g_j] -> 4 c0 | 4 c1 << 16 (fewer than 16,384 samples)
+  uint4 *triples4;            // kPathMfma4t, kPathMfma5q instead of triples: [pair (a, b)][n_pad][g_a]
+                              // of [g_b][g_j] -> 4 c0 | 4 c1 << 16 (fewer than 16,384 samples)
+  uint4 *quads4;              // kPathMfma5q: [colex index of (a, b, c)][n_pad][g_a][g_b] of
+                              // [g_c][g_j] -> 4 c0 | 4 c1 << 16
   uint32_t shard_index;       // local tile = launch tile * shard_count + shard_index
   uint32_t shard_count;       // 1 = every tile
   uint32_t pilot_tiles;       // tiles sampled by the pilot pass (0: none)
@@ -184,14 +187,16 @@ void launch_mfma_rows(const Globals &g, int order, bool dual, int grid, hipStrea
 uint32_t mfma_dual_max_samples(int order);
 uint32_t mfma_rows_max_entries(int order, bool dual);
 int mfma_rows_grid_size(int order, bool dual, uint32_t f_entries);
-// order 4, {0,1}^4 cells on the matrix cores (FP4 operands) and the other
-// cells from the triple and pair tables (jobs of at most
-// mfma_narrow_max_samples() samples); dual as for the rows kernels (jobs of
-// at most mfma_t4_dual_max_samples() samples whose class sizes fit 24 bits
+// orders 4 and 5, {0,1}^k cells on the matrix cores (FP4 operands) and the
+// other cells from the packed lower-order tables (jobs of fewer than 16,384
+// samples); dual as for the rows kernels (jobs of at most
+// mfma_sub_dual_max_samples() samples whose class sizes fit 24 bits
 // together)
-void launch_mfma_t4(const Globals &g, bool dual, int grid, hipStream_t s);
-int mfma_t4_grid_size(bool dual);
-uint32_t mfma_t4_dual_max_samples();
+void launch_mfma_sub(const Globals &g, int order, bool dual, int grid, hipStream_t s);
+int mfma_sub_grid_size(int order, bool dual);
+uint32_t mfma_sub_dual_max_samples();
+// the quad tables of the order-5 jobs with lower-order tables
+void launch_quads(const Globals &g, uint32_t max_n, hipStream_t s);
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
 void launch_pilot_select(const Globals &g, uint32_t max_pilot_slots, hipStream_t s);
 void launch_rescore(const Globals &g, uint32_t max_k, hipStream_t s);

@@ -210,13 +210,14 @@ __device__ __forceinline__ v8i expand32_fp4_b(uint32_t b) { return fp4_operand(f
 
 // The operands of a word from the lane's four 32-bit half words O[4] (A
 // fragments 0, 1, B fragments 0, 1), expanded in registers
-template <int kRaw, typename Prep>
+// (FA A fragments: O[FA + 2], the A fragments first)
+template <int kRaw, typename Prep, int FA = 2>
 __device__ __forceinline__ auto expanded_ops(Prep prep) {
-  return [prep](const uint32_t (&x)[kRaw], v8i (&E)[4]) {
-    uint32_t O[4];
+  return [prep](const uint32_t (&x)[kRaw], v8i (&E)[FA + 2]) {
+    uint32_t O[FA + 2];
     prep(x, O);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) E[f] = f < 2 ? expand32_fp4_a(O[f]) : expand32_fp4_b(O[f]);
+    for (int f = 0; f < FA + 2; ++f) E[f] = f < FA ? expand32_fp4_a(O[f]) : expand32_fp4_b(O[f]);
   };
 }
 
@@ -226,9 +227,9 @@ __device__ __forceinline__ auto expanded_ops(Prep prep) {
 // operands.  load_words(w, x) fills x with the kRaw registers the lane loads
 // for word w; ops(x, E) makes the four operands (A fragments 0, 1, B
 // fragments 0, 1) from them when the word is used.
-template <int kDepth, int kRaw, typename Load, typename Ops>
+template <int kDepth, int kRaw, typename Load, typename Ops, int FA = 2>
 __device__ __forceinline__ void mfma_class_fp4(Load &&load_words, Ops &&ops, uint32_t wbeg,
-                                               uint32_t wend, v16f (&acc)[2][2],
+                                               uint32_t wend, v16f (&acc)[FA][2],
                                                int scale_a = kScaleOne) {
   if (wbeg >= wend) return;
   const uint32_t wlast = wend - 1;
@@ -236,14 +237,14 @@ __device__ __forceinline__ void mfma_class_fp4(Load &&load_words, Ops &&ops, uin
 #pragma unroll
   for (int u = 0; u < kDepth; ++u) load_words(min(wbeg + u, wlast), X[u]);
   auto step = [&](int slot) {
-    v8i E[4];
+    v8i E[FA + 2];
     ops(X[slot], E);
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < FA; ++x)
 #pragma unroll
       for (int y = 0; y < 2; ++y)
         acc[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-            E[x], E[2 + y], acc[x][y], kFmtFp4, kFmtFp4, 0, scale_a, 0, kScaleOne);
+            E[x], E[FA + y], acc[x][y], kFmtFp4, kFmtFp4, 0, scale_a, 0, kScaleOne);
   };
   uint32_t w = wbeg;
   for (; w + kDepth <= wend; w += kDepth) {
@@ -297,20 +298,20 @@ __device__ __forceinline__ void contract_fp4(Load &&load_words, Ops &&ops, uint3
 // bits.  Class 0's counts wait as 16-bit pairs while class 1 accumulates;
 // the result Q holds class 0 in the low and class 1 in the high 16 bits of
 // each output element (register e of block (x, y)).
-template <int kDepth, int kRaw, typename Load, typename Ops>
+template <int kDepth, int kRaw, typename Load, typename Ops, int FA = 2>
 __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Ops &&ops, uint32_t W0,
-                                                    uint32_t W1, uint32_t (&Q)[2][2][16]) {
-  v16f f[2][2];
+                                                    uint32_t W1, uint32_t (&Q)[FA][2][16]) {
+  v16f f[FA][2];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < FA; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) f[x][y][e] = 0.f;
-  mfma_class_fp4<kDepth, kRaw>(load_words, ops, 0, W0, f);
-  uint32_t P0[2][2][8];
+  mfma_class_fp4<kDepth, kRaw, Load, Ops, FA>(load_words, ops, 0, W0, f);
+  uint32_t P0[FA][2][8];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < FA; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
@@ -318,9 +319,9 @@ __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Ops &&ops
         P0[x][y][i] = (uint32_t)f[x][y][2 * i] | ((uint32_t)f[x][y][2 * i + 1] << 16);
         f[x][y][2 * i] = f[x][y][2 * i + 1] = 0.f;
       }
-  mfma_class_fp4<kDepth, kRaw>(load_words, ops, W0, W0 + W1, f);
+  mfma_class_fp4<kDepth, kRaw, Load, Ops, FA>(load_words, ops, W0, W0 + W1, f);
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < FA; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
@@ -332,22 +333,22 @@ __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Ops &&ops
 // scaled by 2^s (s = bit length of m0, given by the caller), so the single
 // FP32 accumulator holds c0 + 2^s c1 < 2^24, an exact integer; Q as for the
 // narrow kernels.
-template <int kDepth, int kRaw, typename Load, typename Ops>
+template <int kDepth, int kRaw, typename Load, typename Ops, int FA = 2>
 __device__ __forceinline__ void contract_fp4_dual(Load &&load_words, Ops &&ops, uint32_t W0,
                                                   uint32_t W1, uint32_t s,
-                                                  uint32_t (&Q)[2][2][16]) {
-  v16f f[2][2];
+                                                  uint32_t (&Q)[FA][2][16]) {
+  v16f f[FA][2];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < FA; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) f[x][y][e] = 0.f;
-  mfma_class_fp4<kDepth, kRaw>(load_words, ops, 0, W0, f);
-  mfma_class_fp4<kDepth, kRaw>(load_words, ops, W0, W0 + W1, f, kScaleOne + (int)s);
+  mfma_class_fp4<kDepth, kRaw, Load, Ops, FA>(load_words, ops, 0, W0, f);
+  mfma_class_fp4<kDepth, kRaw, Load, Ops, FA>(load_words, ops, W0, W0 + W1, f, kScaleOne + (int)s);
   const uint32_t low = (1u << s) - 1;
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < FA; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
@@ -1285,8 +1286,6 @@ void launch_mfma_rows(const Globals &g, int order, bool dual, int grid, hipStrea
 // Tiles: rows b = 2 .. n - 2; a tile is 16 prefixes (x, y) of [0, b),
 // consecutive in colex order, by 64 last variants; wave w takes prefixes
 // 8 (w / 2) + [0, 8) (4 per fragment) and last variants 32 (w mod 2) + [0, 32).
-constexpr uint32_t kT4Prefixes = 16;
-
 // The pair (x, y), x < y, of colex index q = C(y, 2) + x (per lane)
 __device__ __forceinline__ void colex_pair(u64 q, uint32_t &x, uint32_t &y) {
   u64 t = (u64)((1.0 + __dsqrt_rn(1.0 + 8.0 * (double)q)) * 0.5);
@@ -1378,54 +1377,112 @@ __device__ __forceinline__ void walk3_zip_packed(const Tab3P (&q)[NT], Visit &&v
   visit(cell);  // (2, 2, 2)
 }
 
-// One wave: prefixes q0 + [0, 8) (colex indices of pairs (x, y) below b) x last
-// variants j0 + [0, 32).  DUAL: both classes in one accumulator (class sizes
-// of at most 24 bits together); else class 0 first, kept as 16-bit pairs.
+// C(t, 3) (0 for t < 3)
+__device__ __forceinline__ u64 binom3(u64 t) { return t < 3 ? 0 : t * (t - 1) * (t - 2) / 6; }
+
+// The triple (w, x, y), w < x < y, of colex index q = C(y, 3) + C(x, 2) + w
+// (per lane)
+__device__ __forceinline__ void colex_triple(u64 q, uint32_t &w, uint32_t &x, uint32_t &y) {
+  u64 t = (u64)cbrt(6.0 * (double)q);
+  while (t > 0 && binom3(t) > q) --t;
+  while (binom3(t + 1) <= q) ++t;
+  y = (uint32_t)t;
+  colex_pair(q - binom3(t), w, x);
+}
+
+// The {0,1}^(K-1) x {0,1} counts of one wave: prefixes of K - 1 variants
+// ending in b (K = 4: pairs (x, y) below b, colex indices q0 + [0, 8), four
+// per fragment; K = 5: triples (w, x, y) below b, q0 + [0, 4), two per
+// fragment; indices from nq on are past the last prefix) x last variants
+// j0 + [0, 32).  A row r = 8 k + 4 s + i of fragment f: K = 4: prefix
+// q0 + 4 f + 2 s + k / 2 with (g_x, g_y, g_b) = (k mod 2, i / 2, i mod 2);
+// K = 5: prefix q0 + 2 f + s with (g_w, g_x, g_y, g_b) = (k / 2, k mod 2,
+// i / 2, i mod 2).  So in the output (register e of lane l holds row
+// 8 (e / 4) + 4 (l / 32) + e mod 4) lane half s holds at its column's g_j:
+// K = 4: every {0,1}^3 row of prefixes 2 s (registers 0-7) and 2 s + 1
+// (8-15), register 8 t + 4 g_x + 2 g_y + g_b; K = 5: every {0,1}^4 row of
+// prefix s, register 8 g_w + 4 g_x + 2 g_y + g_b.  Both classes per
+// register, class 0 in the low 16 bits.  DUAL: one accumulator for both
+// classes (class sizes of at most 24 bits together); else class 0 first.
+template <int K, bool DUAL, int FA = 2>
+__device__ __forceinline__ void sub_contract(const JV &v, uint32_t b, u64 q0, u64 nq, uint32_t j0,
+                                             uint32_t lane, uint32_t (&Q)[FA][2][16], int f0 = 0) {
+  constexpr int NP = K - 2;           // prefix variants that vary by lane (b does not)
+  constexpr int kRaw = FA * NP + 3;   // words a lane loads per word index
+  const uint32_t n = v.n;
+  const uint32_t r = lane & 31, h = lane >> 5;
+  const FI_GLOBAL char *Bvc = reinterpret_cast<const FI_GLOBAL char *>(as_global(v.Bv));
+  const size_t word_bytes = (size_t)v.n_pad * 16;  // Bv bytes of one word
+  const uint32_t k = r >> 3, s = (r >> 2) & 1, i = r & 3;
+  uint32_t gv[NP];  // genotype row of each lane-varying prefix variant
+  if constexpr (K == 4) {
+    gv[0] = k & 1;
+    gv[1] = i >> 1;
+  } else {
+    gv[0] = k >> 1;
+    gv[1] = k & 1;
+    gv[2] = i >> 1;
+  }
+  // byte offsets of the lane's rows in a word (fragments f0 .. f0 + FA - 1);
+  // prefixes past the last read variant n, a padding variant whose words
+  // are zero
+  uint32_t oa[FA][NP];
+#pragma unroll
+  for (int fa = 0; fa < FA; ++fa) {
+    const int f = f0 + fa;
+    const u64 q = q0 + (K == 4 ? 4 * f + 2 * s + (k >> 1) : 2 * f + s);
+    uint32_t pv[NP];
+#pragma unroll
+    for (int t = 0; t < NP; ++t) pv[t] = n;
+    if (q < nq) {
+      if constexpr (K == 4) colex_pair(q, pv[0], pv[1]);
+      else colex_triple(q, pv[0], pv[1], pv[2]);
+    }
+#pragma unroll
+    for (int t = 0; t < NP; ++t) oa[fa][t] = pv[t] * 16 + gv[t] * 8 + 4 * h;
+  }
+  const uint32_t ob = b * 16 + (i & 1) * 8 + 4 * h, ol = j0 * 16 + r * 8 + 4 * h;
+  auto load_words = [&](uint32_t w, uint32_t (&xw)[kRaw]) {
+    const FI_GLOBAL char *sw = Bvc + (size_t)w * word_bytes;
+#pragma unroll
+    for (int fa = 0; fa < FA; ++fa)
+#pragma unroll
+      for (int t = 0; t < NP; ++t) xw[fa * NP + t] = ld32(sw, oa[fa][t]);
+    xw[FA * NP] = ld32(sw, ob);
+    xw[FA * NP + 1] = ld32(sw, ol);
+    xw[FA * NP + 2] = ld32(sw, ol + 256);
+  };
+  // A row = AND of the rows of the prefix variants
+  auto prep = [](const uint32_t (&xw)[kRaw], uint32_t (&o)[FA + 2]) {
+#pragma unroll
+    for (int fa = 0; fa < FA; ++fa) {
+      uint32_t a = xw[FA * NP];
+#pragma unroll
+      for (int t = 0; t < NP; ++t) a &= xw[fa * NP + t];
+      o[fa] = a;
+    }
+    o[FA] = xw[FA * NP + 1];
+    o[FA + 1] = xw[FA * NP + 2];
+  };
+  const auto ops = expanded_ops<kRaw, decltype(prep), FA>(prep);
+  if constexpr (DUAL)
+    contract_fp4_dual<4, kRaw, decltype(load_words) &, decltype(ops) &, FA>(load_words, ops, v.W0, v.W1,
+                                                                             bit_len(v.m0), Q);
+  else
+    contract_fp4_narrow<4, kRaw, decltype(load_words) &, decltype(ops) &, FA>(load_words, ops, v.W0, v.W1, Q);
+}
+
+// One wave of order 4: prefixes (x, y, b), (x, y) of colex indices q0 + [0, 8),
+// x last variants j0 + [0, 32).  The lane of g_j = t in lane half s scores
+// prefix 2 s + t of each fragment after taking its partner's 8 counts of it.
 template <bool DUAL>
 __device__ __forceinline__ void wave_t4(const Globals &g, const JV &v, uint32_t b, u64 q0, uint32_t j0,
                                         uint32_t lane, const FI_LDS float *Fl) {
   const uint32_t n = v.n, np = v.n_pad;
   const uint32_t r = lane & 31, h = lane >> 5, gl = lane & 1;
   const u64 nq = (u64)b * (b - 1) / 2;  // prefixes (x, y) below b
-  const FI_GLOBAL char *Bvc = reinterpret_cast<const FI_GLOBAL char *>(as_global(v.Bv));
-  const size_t word_bytes = (size_t)np * 16;  // Bv bytes of one word
-  uint32_t Q[2][2][16];                       // both classes per register
-  {
-    // the lane's A row of fragment f: prefix q0 + 4 f + 2 s + k / 2; prefixes
-    // past the last read variant n, a padding variant whose words are zero
-    const uint32_t k = r >> 3, s = (r >> 2) & 1, i = r & 3;
-    const uint32_t gx = k & 1, gy = i >> 1, gb = i & 1;
-    uint32_t ox[2], oy[2];
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      const u64 q = q0 + 4 * f + 2 * s + (k >> 1);
-      uint32_t x = n, y = n;
-      if (q < nq) colex_pair(q, x, y);
-      ox[f] = x * 16 + gx * 8 + 4 * h;
-      oy[f] = y * 16 + gy * 8 + 4 * h;
-    }
-    const uint32_t ob = b * 16 + gb * 8 + 4 * h, ol = j0 * 16 + r * 8 + 4 * h;
-    auto load_words = [&](uint32_t w, uint32_t (&xw)[7]) {
-      const FI_GLOBAL char *sw = Bvc + (size_t)w * word_bytes;
-      xw[0] = ld32(sw, ox[0]);
-      xw[1] = ld32(sw, oy[0]);
-      xw[2] = ld32(sw, ox[1]);
-      xw[3] = ld32(sw, oy[1]);
-      xw[4] = ld32(sw, ob);
-      xw[5] = ld32(sw, ol);
-      xw[6] = ld32(sw, ol + 256);
-    };
-    // A row = row of x AND row of y AND row of b
-    auto prep = [](const uint32_t (&xw)[7], uint32_t (&o)[4]) {
-      o[0] = xw[0] & xw[1] & xw[4];
-      o[1] = xw[2] & xw[3] & xw[4];
-      o[2] = xw[5];
-      o[3] = xw[6];
-    };
-    const auto ops = expanded_ops<7>(prep);
-    if constexpr (DUAL) contract_fp4_dual<4, 7>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
-    else contract_fp4_narrow<4, 7>(load_words, ops, v.W0, v.W1, Q);
-  }
+  uint32_t Q[2][2][16];
+  sub_contract<4, DUAL>(v, b, q0, nq, j0, lane, Q);
 
   // scoring from the packed tables (every count times 4, class 0 in the low
   // half: byte offsets into the LDS f table)
@@ -1544,14 +1601,273 @@ __device__ __forceinline__ void wave_t4(const Globals &g, const JV &v, uint32_t 
   }
 }
 
-// The f table entries the kernel keeps in LDS: 8,192 (dual) or 16,384 (two
-// accumulators; the packed tables hold counts below 16,384); the host gives
-// it only jobs whose table fits
+// One wave of order 5: prefixes (w, x, y, b), (w, x, y) of colex indices
+// q0 + [0, 4), x last variants j0 + [0, 32).  The two lanes of a combination
+// (lane half s: prefix s of each fragment; lanes l, l ^ 1: g_j = 0, 1) split
+// its 243 cells.  Fixing g_w and g_j leaves an order-3 table over (x, y, b)
+// whose inputs (walk_order3_packed) are {0,1}^5 counts and the quad, triple
+// and pair tables restricted to them; the walk is linear in its inputs, so
+// the table at a 2 of g_w or g_j is the walk of (inputs with that position
+// marginalised) - (inputs at 0) - (inputs at 1).  The lane of g_j = t takes
+// the 3 tables at g_w = t and every cell; both lanes walk the 3 tables at
+// g_w = 2, each scoring every other cell position.
+template <bool DUAL>
+__device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t b, u64 q0, uint32_t j0,
+                                        uint32_t lane, const FI_LDS float *Fl) {
+  const uint32_t n = v.n, np = v.n_pad;
+  const uint32_t r = lane & 31, h = lane >> 5, gl = lane & 1;
+  const u64 nq = binom3(b);  // prefixes (w, x, y) below b
+
+  const MiConst mc = mi_const(v);
+  float thr = current_threshold(v);
+  const FI_GLOBAL v4u *QT4 = reinterpret_cast<const FI_GLOBAL v4u *>(as_global(v.quads4));
+  const FI_GLOBAL v4u *TT4 = reinterpret_cast<const FI_GLOBAL v4u *>(as_global(v.triples4));
+  const FI_GLOBAL v4u *PT4 = reinterpret_cast<const FI_GLOBAL v4u *>(as_global(v.pairs4));
+  const FI_GLOBAL uint32_t *marg = as_global(v.marg);
+  const FI_LDS char *Fb = (const FI_LDS char *)Fl;
+  auto term = [&](uint32_t p) {
+    const uint32_t o0 = p & 0xFFFFu, o1 = p >> 16;
+    const float f0 = *(const FI_LDS float *)(Fb + o0);
+    const float f1 = *(const FI_LDS float *)(Fb + o1);
+    const float f01 = *(const FI_LDS float *)(Fb + o0 + o1);
+    return (f0 + f1) - f01;
+  };
+  auto marg4 = [&](uint32_t var, uint32_t g4) {
+    return pack_x4(marg[(size_t)var * 6 + 2 * g4], marg[(size_t)var * 6 + 2 * g4 + 1]);
+  };
+  // entries of the packed tables: quad (a, b, c, j) of colex index c3 of
+  // (a, b, c): 4 v4u [g_a][g_b] of [g_c][g_j]; triple (a, b, j): 2 v4u [g_a]
+  // of [g_b][g_j]; pair (a, j): v4u [g_a][g_j]
+  // (each load through a base the compiler cannot see through: a table entry
+  // is read again where it is used rather than kept in registers between
+  // its uses)
+  auto fresh = [](auto p) {
+    asm volatile("" : "+s"(p));
+    return p;
+  };
+  auto quad = [&](u64 c3, uint32_t j, uint32_t i) { return fresh(QT4)[(c3 * np + j) * 4 + i]; };
+  auto triple = [&](uint32_t a, uint32_t bb, uint32_t j, uint32_t i) {
+    return fresh(TT4)[(pair_index(n, a, bb) * np + j) * 2 + i];
+  };
+  auto pair = [&](uint32_t a, uint32_t j) { return fresh(PT4)[(size_t)a * np + j]; };
+  // every input register of a table, of two tables side by side
+  auto each2 = [](Tab3P &t, const Tab3P &u, auto &&fn) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) fn(t.D[a >> 2][(a >> 1) & 1][a & 1], u.D[a >> 2][(a >> 1) & 1][a & 1]);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      fn(t.xy[a >> 1][a & 1], u.xy[a >> 1][a & 1]);
+      fn(t.xz[a >> 1][a & 1], u.xz[a >> 1][a & 1]);
+      fn(t.yz[a >> 1][a & 1], u.yz[a >> 1][a & 1]);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      fn(t.Mx[a], u.Mx[a]);
+      fn(t.My[a], u.My[a]);
+      fn(t.Mz[a], u.Mz[a]);
+    }
+    fn(t.m, u.m);
+  };
+  auto walk = [&](const Tab3P &t, auto &&visit) {
+    walk_order3_packed(t.D, t.xy, t.xz, t.yz, t.Mx, t.My, t.Mz, t.m, visit);
+  };
+  const uint32_t hb = binom3(b);  // colex index of (a, c, b) = C(b, 3) + colex index of (a, c)
+  // one A fragment at a time: its counts, then its two output blocks
+#pragma unroll 1
+  for (int f = 0; f < 2; ++f) {
+    uint32_t Q[1][2][16];
+    sub_contract<5, DUAL, 1>(v, b, q0, nq, j0, lane, Q, f);
+#pragma unroll 1
+    for (int fb = 0; fb < 2; ++fb) {
+      // {0,1}^5 counts at g_w = gl for both g_j: own registers 8 gl + [0, 8)
+      // at g_j = gl, the partner's (its registers 8 gl + [0, 8)) at 1 - gl
+      uint32_t dj[2][8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const uint32_t lo = fb ? Q[0][1][a] : Q[0][0][a], hi = fb ? Q[0][1][8 + a] : Q[0][0][8 + a];
+        const uint32_t own = gl ? hi : lo;
+        const uint32_t recv = xor1(gl ? lo : hi);
+        dj[0][a] = (gl ? recv : own) << 2;
+        dj[1][a] = (gl ? own : recv) << 2;
+      }
+      // the prefix of this lane half in fragment f
+      const u64 q = q0 + 2 * f + h;
+      const bool valid = q < nq;
+      uint32_t w = 0, x = 1, y = 2;
+      if (valid) colex_triple(q, w, x, y);
+      const u64 cwxb = hb + (u64)x * (x - 1) / 2 + w, cwyb = hb + (u64)y * (y - 1) / 2 + w,
+                cxyb = hb + (u64)y * (y - 1) / 2 + x;
+      const uint32_t j = j0 + 16 * fb + (r >> 1);
+      const uint32_t J = j < n ? j : n - 1;
+      const bool active = valid && j < n;
+      float fs = gl ? 0.f : mc.c;
+      // the lane's own table (all its cells) and the g_w = 2 table (every
+      // other cell position: the lane of g_j = 0 the even ones, its partner
+      // the odd ones; one instruction stream, the cells chosen by lane)
+      auto score_all = [&](const Tab3P &t) {
+        if (active) walk(t, [&](uint32_t p) { fs += term(p); });
+      };
+      auto score_half = [&](const Tab3P &t) {
+        if (active) {
+          uint32_t held = 0;
+          int pos = 0;
+          walk(t, [&](uint32_t p) {
+            if (pos & 1) fs += term(gl ? p : held);
+            else held = p;
+            ++pos;
+          });
+          if (pos & 1) fs += term(gl ? 0u : held);
+        }
+      };
+      Tab3P A, B;  // sums over g_j = 0, 1 of the own and the g_w = 2 inputs
+#pragma unroll
+      for (int sg = 0; sg < 2; ++sg) {
+        Tab3P o, t2;
+        // own: g_w = gl, g_j = sg
+#pragma unroll
+        for (int a = 0; a < 8; ++a) o.D[a >> 2][(a >> 1) & 1][a & 1] = dj[sg][a];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const v4u exy = quad(q, J, gl * 2 + a), exb = quad(cwxb, J, gl * 2 + a), eyb = quad(cwyb, J, gl * 2 + a);
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            o.xy[a][c] = exy[c * 2 + sg];
+            o.xz[a][c] = exb[c * 2 + sg];
+            o.yz[a][c] = eyb[c * 2 + sg];
+          }
+        }
+        {
+          const v4u mx = triple(w, x, J, gl), my = triple(w, y, J, gl), mb = triple(w, b, J, gl);
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            o.Mx[a] = mx[a * 2 + sg];
+            o.My[a] = my[a * 2 + sg];
+            o.Mz[a] = mb[a * 2 + sg];
+          }
+          o.m = pair(w, J)[gl * 2 + sg];
+        }
+        score_all(o);
+        // g_w = 2, g_j = sg: the table without w less both lanes' own
+        {
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const v4u e = quad(cxyb, J, a);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) t2.D[a >> 1][a & 1][c] = e[c * 2 + sg];
+          }
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const v4u exy = triple(x, y, J, a), exb = triple(x, b, J, a), eyb = triple(y, b, J, a);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              t2.xy[a][c] = exy[c * 2 + sg];
+              t2.xz[a][c] = exb[c * 2 + sg];
+              t2.yz[a][c] = eyb[c * 2 + sg];
+            }
+          }
+          const v4u px = pair(x, J), py = pair(y, J), pb = pair(b, J);
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            t2.Mx[a] = px[a * 2 + sg];
+            t2.My[a] = py[a * 2 + sg];
+            t2.Mz[a] = pb[a * 2 + sg];
+          }
+          t2.m = marg4(J, sg);
+        }
+        each2(t2, o, [](uint32_t &u, uint32_t ov) { u -= ov + xor1(ov); });
+        score_half(t2);
+        if (sg == 0) {
+          A = o;
+          B = t2;
+        } else {
+          each2(A, o, [](uint32_t &u, uint32_t ov) { u += ov; });
+          each2(B, t2, [](uint32_t &u, uint32_t ov) { u += ov; });
+        }
+      }
+      // g_j = 2: own = prefix table at g_w = gl - A; g_w = 2 = prefix table
+      // without w - both lanes' own prefix tables - B
+      {
+        Tab3P o, t2;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const v4u e = quad(q, b, gl * 2 + a);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) o.D[a][c >> 1][c & 1] = e[c];
+        }
+        {
+          const v4u exy = triple(w, x, y, gl), exb = triple(w, x, b, gl), eyb = triple(w, y, b, gl);
+          const v4u px = pair(w, x), py = pair(w, y), pb = pair(w, b);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            o.xy[c >> 1][c & 1] = exy[c];
+            o.xz[c >> 1][c & 1] = exb[c];
+            o.yz[c >> 1][c & 1] = eyb[c];
+          }
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            o.Mx[a] = px[gl * 2 + a];
+            o.My[a] = py[gl * 2 + a];
+            o.Mz[a] = pb[gl * 2 + a];
+          }
+          o.m = marg4(w, gl);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const v4u e = triple(x, y, b, a);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) t2.D[a][c >> 1][c & 1] = e[c];
+        }
+        {
+          const v4u exy = pair(x, y), exb = pair(x, b), eyb = pair(y, b);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            t2.xy[c >> 1][c & 1] = exy[c];
+            t2.xz[c >> 1][c & 1] = exb[c];
+            t2.yz[c >> 1][c & 1] = eyb[c];
+          }
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            t2.Mx[a] = marg4(x, a);
+            t2.My[a] = marg4(y, a);
+            t2.Mz[a] = marg4(b, a);
+          }
+          t2.m = pack_x4(v.m0, v.m1);
+        }
+        each2(t2, o, [](uint32_t &u, uint32_t ov) { u -= ov + xor1(ov); });
+        each2(t2, B, [](uint32_t &u, uint32_t bv) { u -= bv; });
+        each2(o, A, [](uint32_t &u, uint32_t av) { u -= av; });
+        score_all(o);
+        score_half(t2);
+      }
+      // both lanes' parts; the lane of g_j = 0 appends
+      const float total = fs + __uint_as_float(xor1(__float_as_uint(fs)));
+      const uint32_t pre[4] = {w, x, y, b};
+      if (emit_with(v, active && gl == 0, total * mc.inv_m,
+                    [&] { return lex_rank_prefix(g, n, 5, pre) + (u64)(j - b - 1); }, thr,
+                    lane) >= kRefreshAppends)
+        thr = current_threshold_lanes(v);
+    }
+  }
+}
+
+// The f table entries the order-4/5 table kernels keep in LDS: 8,192 (dual)
+// or 16,384 (two accumulators; the packed tables hold counts below 16,384);
+// the host gives them only jobs whose table fits
 template <bool DUAL>
 constexpr uint32_t t4_f_entries() { return DUAL ? mfma_f_entries(kMfmaF4Dual) : 16384u; }
 
-template <bool DUAL>
-__global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_t4_kernel(Globals g) {
+// Orders 4 (K = 4, path kPathMfma4t) and 5 (K = 5, kPathMfma5q) with stored
+// lower-order tables.  Tiles: rows b = K - 2 .. n - 2 (the last prefix
+// variant); a tile is 16 (K = 4) or 8 (K = 5) prefixes of [0, b), consecutive
+// in colex order, by 64 last variants; wave w takes half the prefixes
+// (w / 2) and last variants 32 (w mod 2) + [0, 32).
+template <int K>
+constexpr uint32_t sub_tile_prefixes() { return K == 4 ? 16u : 8u; }
+
+// (2 waves per SIMD; at order 5 some registers spill, measured faster than
+// one wave per SIMD without spills: 1.32 s against 1.96 s at 200 x 4,000)
+template <int K, bool DUAL>
+__global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_sub_kernel(Globals g) {
   __shared__ u64 s_tile;
   extern __shared__ float s_f[];
   const uint32_t lane = lane_id();
@@ -1570,7 +1886,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_t4_kernel(Globals g) 
     u64 lt;
     if (!locate_tile(g, t, wave, kMfmaPilotEmits, v, jd, lt)) continue;
     // the host gives this kernel only such jobs
-    if (v.path != kPathMfma4t || v.m + 1 > t4_f_entries<false>()) continue;
+    if (v.path != (K == 4 ? kPathMfma4t : kPathMfma5q) || v.m + 1 > t4_f_entries<false>()) continue;
     {
       // the dual and the two-accumulator kernels run over the same tiles,
       // each skipping the other's jobs
@@ -1597,38 +1913,119 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_t4_kernel(Globals g) 
     cu64p rows = as_const(uni_ptr(jd->row_start));
     const uint32_t rl = hint.find(jd, lt);
     const u64 local = uni64(lt - rows[rl]);
-    const uint32_t b = rl + 2;
+    const uint32_t b = rl + (K - 2);
     const uint32_t nj = (v.n - 1 - b + 63) / 64;
     const u64 grp = local / nj;
     const uint32_t jb = (uint32_t)(local - grp * nj);
-    const u64 q0 = grp * kT4Prefixes + 8 * (wave >> 1);
+    const u64 q0 = grp * sub_tile_prefixes<K>() + (sub_tile_prefixes<K>() / 2) * (wave >> 1);
     const uint32_t j0 = b + 1 + 64 * jb + 32 * (wave & 1);
+    const u64 nq = K == 4 ? (u64)b * (b - 1) / 2 : binom3(b);
     // a wave without a prefix or a last variant has nothing to count; its
     // pilot slots stay zero
-    if (q0 >= (u64)b * (b - 1) / 2 || j0 >= v.n) continue;
-    wave_t4<DUAL>(g, v, b, q0, j0, lane, Fl);
+    if (q0 >= nq || j0 >= v.n) continue;
+    if constexpr (K == 4) wave_t4<DUAL>(g, v, b, q0, j0, lane, Fl);
+    else wave_t5<DUAL>(g, v, b, q0, j0, lane, Fl);
   }
 }
 
-template <bool DUAL>
-int mfma_t4_grid() {
+// The quad tables of the order-5 jobs: for every 4-set a < b < c < j its
+// {0,1}^4 counts, packed, at [colex index of (a, b, c)][j] (4 v4u:
+// [g_a][g_b] of [g_c][g_j]).  Grid: x = group of 16 pairs (a, b) below c in
+// colex order, y = c - 2, z = job; the workgroup walks the blocks of 64 last
+// variants (the order-4 kernel's tiles, counts stored instead of scored).
+__global__ __launch_bounds__(kMfmaWaves * 64) void quads_kernel(Globals g) {
+  const JobDesc *jd = g.jobs + blockIdx.z;
+  JV v = load_view(jd);
+  v4u *QT = reinterpret_cast<v4u *>(uni_ptr(as_const(jd)->quads4));
+  if (QT == nullptr) return;
+  const JobState *st = v.st;
+  if (uni((uint32_t)st->status) != 0) return;
+  v.W0 = uni(st->W0);
+  v.W1 = uni(st->W1);
+  v.m0 = uni(st->m0);
+  v.m1 = uni(st->m1);
+  const uint32_t n = v.n, np = v.n_pad;
+  const uint32_t c = blockIdx.y + 2;
+  if (c + 1 >= n) return;
+  const u64 nq = (u64)c * (c - 1) / 2;
+  const uint32_t wave = uni(threadIdx.x >> 6), lane = lane_id();
+  const uint32_t r = lane & 31, h = lane >> 5, gl = lane & 1;
+  const u64 q0 = (u64)blockIdx.x * 16 + 8 * (wave >> 1);
+  if (q0 >= nq) return;
+  const bool dual = bit_len(v.m0) + bit_len(v.m1) <= 24;
+  const u64 hc = binom3(c);
+  for (uint32_t j0 = c + 1 + 32 * (wave & 1); j0 < n; j0 += 64) {
+    uint32_t Q[2][2][16];
+    if (dual) sub_contract<4, true>(v, c, q0, nq, j0, lane, Q);
+    else sub_contract<4, false>(v, c, q0, nq, j0, lane, Q);
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      // the lane of g_j = t in lane half s stores prefix 2 s + t
+      const u64 q = q0 + 4 * f + 2 * h + gl;
+#pragma unroll
+      for (int fb = 0; fb < 2; ++fb) {
+        const uint32_t j = j0 + 16 * fb + (r >> 1);
+        uint32_t cell[8][2];  // [4 g_a + 2 g_b + g_c][g_j], packed x 4
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const uint32_t lo = Q[f][fb][a], hi = Q[f][fb][8 + a];
+          const uint32_t own = gl ? hi : lo;
+          const uint32_t recv = xor1(gl ? lo : hi);
+          cell[a][0] = (gl ? recv : own) << 2;
+          cell[a][1] = (gl ? own : recv) << 2;
+        }
+        if (q < nq && j < n) {
+          v4u *dst = QT + ((hc + q) * np + j) * 4;
+#pragma unroll
+          for (int ab = 0; ab < 4; ++ab) {
+            v4u o;
+            o[0] = cell[2 * ab][0];
+            o[1] = cell[2 * ab][1];
+            o[2] = cell[2 * ab + 1][0];
+            o[3] = cell[2 * ab + 1][1];
+            dst[ab] = o;
+          }
+        }
+      }
+    }
+  }
+}
+
+void launch_quads(const Globals &g, uint32_t max_n, hipStream_t s) {
+  if (max_n < 5) return;
+  const u64 groups = ((u64)(max_n - 2) * (max_n - 3) / 2 + 15) / 16;
+  hipLaunchKernelGGL(quads_kernel, dim3((uint32_t)groups, max_n - 3, g.n_jobs), dim3(kMfmaWaves * 64), 0, s,
+                     g);
+}
+
+template <int K, bool DUAL>
+int mfma_sub_grid() {
   int dev = 0, cus = 0, per = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_t4_kernel<DUAL>, kMfmaWaves * 64,
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_sub_kernel<K, DUAL>, kMfmaWaves * 64,
                                                      t4_f_entries<DUAL>() * sizeof(float));
   if (cus <= 0) cus = 256;
   if (per <= 0) per = 1;
   return cus * per;
 }
 
-int mfma_t4_grid_size(bool dual) { return dual ? mfma_t4_grid<true>() : mfma_t4_grid<false>(); }
-uint32_t mfma_t4_dual_max_samples() { return t4_f_entries<true>() - 1; }
+int mfma_sub_grid_size(int order, bool dual) {
+  if (order == 5) return dual ? mfma_sub_grid<5, true>() : mfma_sub_grid<5, false>();
+  return dual ? mfma_sub_grid<4, true>() : mfma_sub_grid<4, false>();
+}
+uint32_t mfma_sub_dual_max_samples() { return t4_f_entries<true>() - 1; }
 
-void launch_mfma_t4(const Globals &g, bool dual, int grid, hipStream_t s) {
+void launch_mfma_sub(const Globals &g, int order, bool dual, int grid, hipStream_t s) {
   const dim3 gd(grid), bd(kMfmaWaves * 64);
-  if (dual) hipLaunchKernelGGL(mfma_t4_kernel<true>, gd, bd, t4_f_entries<true>() * sizeof(float), s, g);
-  else hipLaunchKernelGGL(mfma_t4_kernel<false>, gd, bd, t4_f_entries<false>() * sizeof(float), s, g);
+  const size_t lds = (dual ? t4_f_entries<true>() : t4_f_entries<false>()) * sizeof(float);
+  if (order == 5) {
+    if (dual) hipLaunchKernelGGL((mfma_sub_kernel<5, true>), gd, bd, lds, s, g);
+    else hipLaunchKernelGGL((mfma_sub_kernel<5, false>), gd, bd, lds, s, g);
+  } else {
+    if (dual) hipLaunchKernelGGL((mfma_sub_kernel<4, true>), gd, bd, lds, s, g);
+    else hipLaunchKernelGGL((mfma_sub_kernel<4, false>), gd, bd, lds, s, g);
+  }
 }
 
 // ORDER 2 or 3, FMT: operand format (kMfmaI8, kMfmaF4, kMfmaF4Narrow); the

@@ -38,7 +38,7 @@ KERNEL_PAIRS = 2
 KERNEL_MFMA = 3
 KERNEL_TRIPLES = 4
 KERNEL_MFMA_FP4 = 5
-KERNEL_MFMA_FP4_TRIPLES = 6
+KERNEL_MFMA_FP4_TABLES = 6
 
 # every entry point declared in include/fiuncho.h
 EXPORTS = (

@@ -143,13 +143,15 @@ def test_kernel_choice_table(monkeypatch):
     assert fiuncho.get_kernel(1000, 6400, 3) == fiuncho.KERNEL_MFMA_FP4
     assert fiuncho.get_kernel(3, 10, 3) == fiuncho.KERNEL_MFMA_FP4
     assert fiuncho.get_kernel(300, 17000, 2) == fiuncho.KERNEL_MFMA_FP4  # 266 words
-    assert fiuncho.get_kernel(200, 4000, 4) == fiuncho.KERNEL_MFMA_FP4_TRIPLES
+    assert fiuncho.get_kernel(200, 4000, 4) == fiuncho.KERNEL_MFMA_FP4_TABLES
     assert fiuncho.get_kernel(200, 16384, 4) == fiuncho.KERNEL_TRIPLES  # packed tables: below 16,384
-    assert fiuncho.get_kernel(800, 4000, 4) == fiuncho.KERNEL_MFMA_FP4_TRIPLES  # 9.2 GB packed tables
+    assert fiuncho.get_kernel(800, 4000, 4) == fiuncho.KERNEL_MFMA_FP4_TABLES  # 9.2 GB packed tables
     assert fiuncho.get_kernel(800, 17000, 4) == fiuncho.KERNEL_MFMA_FP4  # unpacked tables over 16 GiB
     assert fiuncho.get_kernel(5000, 4000, 4) == fiuncho.KERNEL_MFMA_FP4  # tables over 16 GiB
     assert fiuncho.get_kernel(5000, 30000, 4) == fiuncho.KERNEL_POPCOUNT  # over 20,447 samples
-    assert fiuncho.get_kernel(100, 4000, 5) == fiuncho.KERNEL_MFMA_FP4
+    assert fiuncho.get_kernel(100, 4000, 5) == fiuncho.KERNEL_MFMA_FP4_TABLES
+    assert fiuncho.get_kernel(100, 16384, 5) == fiuncho.KERNEL_MFMA_FP4  # packed tables: below 16,384
+    assert fiuncho.get_kernel(700, 4000, 5) == fiuncho.KERNEL_MFMA_FP4  # quad tables over 48 GiB
     assert fiuncho.get_kernel(100, 20448, 5) == fiuncho.KERNEL_POPCOUNT
     assert fiuncho.get_kernel(100, 4000, 6) == fiuncho.KERNEL_POPCOUNT
     assert L.fiuncho_get_kernel(5, 100, 6) == fiuncho.E_ORDER

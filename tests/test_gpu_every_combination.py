@@ -59,10 +59,16 @@ CASES = [
     ("rows-two-acc", 5, 16, 8200, 0.5, K.KERNEL_MFMA_FP4),
     # order 4, {0,1}^4 cells on the matrix cores and packed triple tables:
     # dual, two accumulators, and one prefix group short of 16 at every row
-    ("fp4-triples-dual", 4, 30, 400, 0.5, K.KERNEL_MFMA_FP4_TRIPLES),
-    ("fp4-triples-dual", 4, 37, 1001, 0.3, K.KERNEL_MFMA_FP4_TRIPLES),
-    ("fp4-triples-two-acc", 4, 21, 9000, 0.5, K.KERNEL_MFMA_FP4_TRIPLES),
-    ("fp4-triples-two-acc", 4, 18, 16383, 0.5, K.KERNEL_MFMA_FP4_TRIPLES),
+    ("fp4-triples-dual", 4, 30, 400, 0.5, K.KERNEL_MFMA_FP4_TABLES),
+    ("fp4-triples-dual", 4, 37, 1001, 0.3, K.KERNEL_MFMA_FP4_TABLES),
+    ("fp4-triples-two-acc", 4, 21, 9000, 0.5, K.KERNEL_MFMA_FP4_TABLES),
+    ("fp4-triples-two-acc", 4, 18, 16383, 0.5, K.KERNEL_MFMA_FP4_TABLES),
+    # order 5, {0,1}^5 cells on the matrix cores and packed quad, triple and
+    # pair tables: dual and two accumulators, prefix groups short of 8
+    ("fp4-quads-dual", 5, 22, 300, 0.5, K.KERNEL_MFMA_FP4_TABLES),
+    ("fp4-quads-dual", 5, 19, 777, 0.35, K.KERNEL_MFMA_FP4_TABLES),
+    ("fp4-quads-two-acc", 5, 16, 8200, 0.5, K.KERNEL_MFMA_FP4_TABLES),
+    ("fp4-quads-two-acc", 5, 13, 16383, 0.45, K.KERNEL_MFMA_FP4_TABLES),
 ]
 
 ENV = ("FIUNCHO_ORDER2_MFMA", "FIUNCHO_ORDER3_MFMA", "FIUNCHO_ORDER3_PAIRS", "FIUNCHO_ORDER4_TRIPLES")
@@ -104,7 +110,7 @@ def test_fp4_triples_large_jobs_use_unpacked_tables(monkeypatch):
     n, m, k = 14, 16384, 4
     G, y = random_dataset(4242, n, m, 0.5, 1, 1)
     try:
-        fiuncho.set_kernel(n, m, k, fiuncho.KERNEL_MFMA_FP4_TRIPLES)
+        fiuncho.set_kernel(n, m, k, fiuncho.KERNEL_MFMA_FP4_TABLES)
         fiuncho.set_profiling(True)
         hits = fiuncho.scan(G, y, k, math.comb(n, k))
         prof = fiuncho.get_profile()
