@@ -1719,82 +1719,82 @@ __device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t 
           if (pos & 1) fs += term(gl ? 0u : held);
         }
       };
-      Tab3P A, B;  // sums over g_j = 0, 1 of the own and the g_w = 2 inputs
+      // the lane's own inputs at g_w = gl and the inputs without w, at g_j =
+      // sg, or summed over g_j = 0, 1 (sg = 2: what the g_j = 2 tables
+      // subtract from the prefix tables)
+      auto own_at = [&](int sg, Tab3P &o) {
+        auto pick = [&](const v4u &e, int c) { return sg < 2 ? e[c * 2 + sg] : e[c * 2] + e[c * 2 + 1]; };
 #pragma unroll
-      for (int sg = 0; sg < 2; ++sg) {
-        Tab3P o, t2;
-        // own: g_w = gl, g_j = sg
-#pragma unroll
-        for (int a = 0; a < 8; ++a) o.D[a >> 2][(a >> 1) & 1][a & 1] = dj[sg][a];
+        for (int a = 0; a < 8; ++a)
+          o.D[a >> 2][(a >> 1) & 1][a & 1] = sg < 2 ? dj[sg][a] : dj[0][a] + dj[1][a];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
           const v4u exy = quad(q, J, gl * 2 + a), exb = quad(cwxb, J, gl * 2 + a), eyb = quad(cwyb, J, gl * 2 + a);
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
-            o.xy[a][c] = exy[c * 2 + sg];
-            o.xz[a][c] = exb[c * 2 + sg];
-            o.yz[a][c] = eyb[c * 2 + sg];
+            o.xy[a][c] = pick(exy, c);
+            o.xz[a][c] = pick(exb, c);
+            o.yz[a][c] = pick(eyb, c);
           }
         }
-        {
-          const v4u mx = triple(w, x, J, gl), my = triple(w, y, J, gl), mb = triple(w, b, J, gl);
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            o.Mx[a] = mx[a * 2 + sg];
-            o.My[a] = my[a * 2 + sg];
-            o.Mz[a] = mb[a * 2 + sg];
-          }
-          o.m = pair(w, J)[gl * 2 + sg];
-        }
-        score_all(o);
-        // g_w = 2, g_j = sg: the table without w less both lanes' own
-        {
-#pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            const v4u e = quad(cxyb, J, a);
-#pragma unroll
-            for (int c = 0; c < 2; ++c) t2.D[a >> 1][a & 1][c] = e[c * 2 + sg];
-          }
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            const v4u exy = triple(x, y, J, a), exb = triple(x, b, J, a), eyb = triple(y, b, J, a);
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              t2.xy[a][c] = exy[c * 2 + sg];
-              t2.xz[a][c] = exb[c * 2 + sg];
-              t2.yz[a][c] = eyb[c * 2 + sg];
-            }
-          }
-          const v4u px = pair(x, J), py = pair(y, J), pb = pair(b, J);
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            t2.Mx[a] = px[a * 2 + sg];
-            t2.My[a] = py[a * 2 + sg];
-            t2.Mz[a] = pb[a * 2 + sg];
-          }
-          t2.m = marg4(J, sg);
-        }
-        each2(t2, o, [](uint32_t &u, uint32_t ov) { u -= ov + xor1(ov); });
-        score_half(t2);
-        if (sg == 0) {
-          A = o;
-          B = t2;
-        } else {
-          each2(A, o, [](uint32_t &u, uint32_t ov) { u += ov; });
-          each2(B, t2, [](uint32_t &u, uint32_t ov) { u += ov; });
-        }
-      }
-      // g_j = 2: own = prefix table at g_w = gl - A; g_w = 2 = prefix table
-      // without w - both lanes' own prefix tables - B
-      {
-        Tab3P o, t2;
+        const v4u mx = triple(w, x, J, gl), my = triple(w, y, J, gl), mb = triple(w, b, J, gl);
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-          const v4u e = quad(q, b, gl * 2 + a);
-#pragma unroll
-          for (int c = 0; c < 4; ++c) o.D[a][c >> 1][c & 1] = e[c];
+          o.Mx[a] = pick(mx, a);
+          o.My[a] = pick(my, a);
+          o.Mz[a] = pick(mb, a);
         }
+        const v4u pj = pair(w, J);
+        o.m = sg < 2 ? pj[gl * 2 + sg] : pj[gl * 2] + pj[gl * 2 + 1];
+      };
+      auto star_at = [&](int sg, Tab3P &t) {
+        auto pick = [&](const v4u &e, int c) { return sg < 2 ? e[c * 2 + sg] : e[c * 2] + e[c * 2 + 1]; };
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const v4u e = quad(cxyb, J, a);
+#pragma unroll
+          for (int c = 0; c < 2; ++c) t.D[a >> 1][a & 1][c] = pick(e, c);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const v4u exy = triple(x, y, J, a), exb = triple(x, b, J, a), eyb = triple(y, b, J, a);
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            t.xy[a][c] = pick(exy, c);
+            t.xz[a][c] = pick(exb, c);
+            t.yz[a][c] = pick(eyb, c);
+          }
+        }
+        const v4u px = pair(x, J), py = pair(y, J), pb = pair(b, J);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          t.Mx[a] = pick(px, a);
+          t.My[a] = pick(py, a);
+          t.Mz[a] = pick(pb, a);
+        }
+        t.m = sg < 2 ? marg4(J, sg) : marg4(J, 0) + marg4(J, 1);
+      };
+#pragma unroll
+      for (int sg = 0; sg < 2; ++sg) {
+        Tab3P o, t2;
+        own_at(sg, o);  // g_w = gl, g_j = sg
+        score_all(o);
+        star_at(sg, t2);  // g_w = 2: the table without w less both lanes' own
+        each2(t2, o, [](uint32_t &u, uint32_t ov) { u -= ov + xor1(ov); });
+        score_half(t2);
+      }
+      // g_j = 2: the prefix tables less the tables at g_j = 0, 1
+      {
+        Tab3P o, t2;
         {
+          Tab3P d;
+          own_at(2, d);
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const v4u e = quad(q, b, gl * 2 + a);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) o.D[a][c >> 1][c & 1] = e[c];
+          }
           const v4u exy = triple(w, x, y, gl), exb = triple(w, x, b, gl), eyb = triple(w, y, b, gl);
           const v4u px = pair(w, x), py = pair(w, y), pb = pair(w, b);
 #pragma unroll
@@ -1810,14 +1810,17 @@ __device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t 
             o.Mz[a] = pb[gl * 2 + a];
           }
           o.m = marg4(w, gl);
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const v4u e = triple(x, y, b, a);
-#pragma unroll
-          for (int c = 0; c < 4; ++c) t2.D[a][c >> 1][c & 1] = e[c];
+          each2(o, d, [](uint32_t &u, uint32_t dv) { u -= dv; });
         }
         {
+          Tab3P d;
+          star_at(2, d);
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const v4u e = triple(x, y, b, a);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) t2.D[a][c >> 1][c & 1] = e[c];
+          }
           const v4u exy = pair(x, y), exb = pair(x, b), eyb = pair(y, b);
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
@@ -1832,10 +1835,9 @@ __device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t 
             t2.Mz[a] = marg4(b, a);
           }
           t2.m = pack_x4(v.m0, v.m1);
+          each2(t2, d, [](uint32_t &u, uint32_t dv) { u -= dv; });
         }
         each2(t2, o, [](uint32_t &u, uint32_t ov) { u -= ov + xor1(ov); });
-        each2(t2, B, [](uint32_t &u, uint32_t bv) { u -= bv; });
-        each2(o, A, [](uint32_t &u, uint32_t av) { u -= av; });
         score_all(o);
         score_half(t2);
       }
@@ -1864,8 +1866,8 @@ constexpr uint32_t t4_f_entries() { return DUAL ? mfma_f_entries(kMfmaF4Dual) : 
 template <int K>
 constexpr uint32_t sub_tile_prefixes() { return K == 4 ? 16u : 8u; }
 
-// (2 waves per SIMD; at order 5 some registers spill, measured faster than
-// one wave per SIMD without spills: 1.32 s against 1.96 s at 200 x 4,000)
+// (2 waves per SIMD; at order 5 a few registers spill, measured faster than
+// one wave per SIMD without spills)
 template <int K, bool DUAL>
 __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_sub_kernel(Globals g) {
   __shared__ u64 s_tile;
