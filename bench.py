@@ -264,7 +264,10 @@ def measure(datasets, steps, warmup, graph=False, plain=False, shard=None):
         fp4 = bool(kernels & {fiuncho.KERNEL_MFMA_FP4, fiuncho.KERNEL_MFMA_FP4_TABLES})
         i8 = fiuncho.KERNEL_MFMA in kernels
         fmt = "int8 and FP4" if fp4 and i8 else "FP4" if fp4 else "int8"
-        roofline = {"bound": "mfma", "kernel": f"mfma_kernel (one-hot {fmt} contraction + FP32 MI + filter)",
+        name = ("mfma_sub_kernel (one-hot FP4 contraction of the {0,1}^k cells + lower-order tables + FP32 MI "
+                "+ filter)" if kernels == {fiuncho.KERNEL_MFMA_FP4_TABLES}
+                else f"mfma_kernel (one-hot {fmt} contraction + FP32 MI + filter)")
+        roofline = {"bound": "mfma", "kernel": name,
                     "achieved": achieved, "peak": peak, "unit": f"T {fmt} op/s", "frac": achieved / peak,
                     "kernel_ms": mfma_ms, "fmt": fmt}
     else:
@@ -389,7 +392,7 @@ def main():
     # the FP4 matrix-core kernels' and the pair- and triple-table kernels' launches
     traffic_key = args.workload + ("" if shard is None else f" shard {shard[0]}/{shard[1]}")
     if rf["bound"] == "mfma":
-        rf["traffic"] = measured_traffic("mfma_kernel", traffic_key) if rf["fmt"] == "FP4" else None
+        rf["traffic"] = (measured_traffic(rf["kernel"].split()[0], traffic_key) if rf["fmt"] == "FP4" else None)
     else:
         rf["traffic"] = (measured_traffic("scan_kernel", traffic_key)
                          if kernels <= {fiuncho.KERNEL_PAIRS, fiuncho.KERNEL_TRIPLES} else None)
