@@ -286,8 +286,8 @@ int fiuncho_shard_counts(uint32_t snps, uint32_t samples, int order, uint32_t un
                                      order tables: triple and pair tables
                                      (32 bytes per pair and variant, up to
                                      16 GiB) and at order 5 quad tables (64
-                                     bytes per triple and variant, up to
-                                     48 GiB), built on the device per call;
+                                     bytes per 4-set, up to 48 GiB), built on
+                                     the device per call;
                                      jobs of fewer than 16,384 samples (larger
                                      ones: order 4 on FIUNCHO_KERNEL_TRIPLES,
                                      order 5 on FIUNCHO_KERNEL_MFMA_FP4) */

@@ -241,12 +241,8 @@ u64 triple_table_bytes(uint32_t n, bool packed = false) {
   return binom_host(n, 2) * n_pad * (packed ? 32 : 64);
 }
 constexpr u64 kMaxTripleTableBytes = 16ull << 30;
-// packed quad tables (order 5 with lower-order tables): 64 bytes per triple
-// and variant
-u64 quad_table_bytes(uint32_t n) {
-  const u64 n_pad = (u64)(n + 63) / 64 * 64 + 64;
-  return binom_host(n, 3) * n_pad * 64;
-}
+// packed quad tables (order 5 with lower-order tables): 64 bytes per 4-set
+u64 quad_table_bytes(uint32_t n) { return binom_host(n, 4) * 64; }
 constexpr u64 kMaxQuadTableBytes = 48ull << 30;
 
 bool kernel_valid(int kernel, uint32_t n, uint32_t k) {
@@ -273,7 +269,7 @@ bool kernel_valid(int kernel, uint32_t n, uint32_t k) {
 // a search, triple tables on the popcount kernel 18.8 ms, every prefix row on
 // the matrix cores 17.6 ms), else the popcount kernel's triple tables, else
 // every prefix row on the matrix cores.  Order 5 likewise with quad tables
-// while they fit in 48 GiB (200 x 4,000: 1.21 s, every prefix row on the
+// while they fit in 48 GiB (200 x 4,000: 1.26 s, every prefix row on the
 // matrix cores 1.93 s, popcount 3.7 s), else every prefix row on the matrix
 // cores.  The matrix cores take every prefix row of orders 4 and 5 up to
 // 20,447 samples.

@@ -132,8 +132,8 @@ struct JobDesc {
   uint32_t *triples;          // kPathTriples: [pair (a, b)][n_pad][g_a][g_b][g_j][class] counts
   uint4 *triples4;            // kPathMfma4t, kPathMfma5q instead of triples: [pair (a, b)][n_pad][g_a]
                               // of [g_b][g_j] -> 4 c0 | 4 c1 << 16 (fewer than 16,384 samples)
-  uint4 *quads4;              // kPathMfma5q: [colex index of (a, b, c)][n_pad][g_a][g_b] of
-                              // [g_c][g_j] -> 4 c0 | 4 c1 << 16
+  uint4 *quads4;              // kPathMfma5q: per 4-set a < b < c < j (triples in colex order, each
+                              // with j = c + 1 .. n - 1): [g_a][g_b] of [g_c][g_j] -> 4 c0 | 4 c1 << 16
   uint32_t shard_index;       // local tile = launch tile * shard_count + shard_index
   uint32_t shard_count;       // 1 = every tile
   uint32_t pilot_tiles;       // tiles sampled by the pilot pass (0: none)

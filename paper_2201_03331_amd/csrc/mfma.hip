@@ -1380,6 +1380,16 @@ __device__ __forceinline__ void walk3_zip_packed(const Tab3P (&q)[NT], Visit &&v
 // C(t, 3) (0 for t < 3)
 __device__ __forceinline__ u64 binom3(u64 t) { return t < 3 ? 0 : t * (t - 1) * (t - 2) / 6; }
 
+// Entry of the 4-set (a, b, c, j), a < b < c < j, in the packed quad tables:
+// the triples in colex order (index c3 = C(c, 3) + C(b, 2) + a), each with
+// its entries for j = c + 1 .. n - 1.  The triples whose largest variant is
+// below c hold sum over c' < c of C(c', 2) (n - 1 - c') = (n - 3) C(c, 3) -
+// 3 C(c, 4) entries.
+__device__ __forceinline__ u64 quad_entry(uint32_t n, u64 c3, uint32_t c, uint32_t j) {
+  const u64 C3 = binom3(c), C4 = c < 4 ? 0 : C3 * (c - 3) / 4;
+  return ((u64)n - 3) * C3 - 3 * C4 + (c3 - C3) * (n - 1 - c) + (j - c - 1);
+}
+
 // The triple (w, x, y), w < x < y, of colex index q = C(y, 3) + C(x, 2) + w
 // (per lane)
 __device__ __forceinline__ void colex_triple(u64 q, uint32_t &w, uint32_t &x, uint32_t &y) {
@@ -1635,8 +1645,8 @@ __device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t 
   auto marg4 = [&](uint32_t var, uint32_t g4) {
     return pack_x4(marg[(size_t)var * 6 + 2 * g4], marg[(size_t)var * 6 + 2 * g4 + 1]);
   };
-  // entries of the packed tables: quad (a, b, c, j) of colex index c3 of
-  // (a, b, c): 4 v4u [g_a][g_b] of [g_c][g_j]; triple (a, b, j): 2 v4u [g_a]
+  // entries of the packed tables: quad (a, b, c, j) (colex index c3 of
+  // (a, b, c)): 4 v4u [g_a][g_b] of [g_c][g_j] at quad_entry; triple (a, b, j): 2 v4u [g_a]
   // of [g_b][g_j]; pair (a, j): v4u [g_a][g_j]
   // (each load through a base the compiler cannot see through: a table entry
   // is read again where it is used rather than kept in registers between
@@ -1645,7 +1655,7 @@ __device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t 
     asm volatile("" : "+s"(p));
     return p;
   };
-  auto quad = [&](u64 c3, uint32_t j, uint32_t i) { return fresh(QT4)[(c3 * np + j) * 4 + i]; };
+  auto quad = [&](u64 c3, uint32_t c, uint32_t j, uint32_t i) { return fresh(QT4)[quad_entry(n, c3, c, j) * 4 + i]; };
   auto triple = [&](uint32_t a, uint32_t bb, uint32_t j, uint32_t i) {
     return fresh(TT4)[(pair_index(n, a, bb) * np + j) * 2 + i];
   };
@@ -1691,8 +1701,11 @@ __device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t 
         dj[1][a] = (gl ? own : recv) << 2;
       }
       // the prefix of this lane half in fragment f
-      const u64 q = q0 + 2 * f + h;
-      const bool valid = q < nq;
+      // (a lane past the last prefix scores nothing; it reads the tables of
+      // (0, 1, 2, b), colex index 0, so that every read stays in the tables)
+      const u64 qp = q0 + 2 * f + h;
+      const bool valid = qp < nq;
+      const u64 q = valid ? qp : 0;
       uint32_t w = 0, x = 1, y = 2;
       if (valid) colex_triple(q, w, x, y);
       const u64 cwxb = hb + (u64)x * (x - 1) / 2 + w, cwyb = hb + (u64)y * (y - 1) / 2 + w,
@@ -1729,7 +1742,7 @@ __device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t 
           o.D[a >> 2][(a >> 1) & 1][a & 1] = sg < 2 ? dj[sg][a] : dj[0][a] + dj[1][a];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-          const v4u exy = quad(q, J, gl * 2 + a), exb = quad(cwxb, J, gl * 2 + a), eyb = quad(cwyb, J, gl * 2 + a);
+          const v4u exy = quad(q, y, J, gl * 2 + a), exb = quad(cwxb, b, J, gl * 2 + a), eyb = quad(cwyb, b, J, gl * 2 + a);
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
             o.xy[a][c] = pick(exy, c);
@@ -1751,7 +1764,7 @@ __device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t 
         auto pick = [&](const v4u &e, int c) { return sg < 2 ? e[c * 2 + sg] : e[c * 2] + e[c * 2 + 1]; };
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          const v4u e = quad(cxyb, J, a);
+          const v4u e = quad(cxyb, b, J, a);
 #pragma unroll
           for (int c = 0; c < 2; ++c) t.D[a >> 1][a & 1][c] = pick(e, c);
         }
@@ -1791,7 +1804,7 @@ __device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t 
           own_at(2, d);
 #pragma unroll
           for (int a = 0; a < 2; ++a) {
-            const v4u e = quad(q, b, gl * 2 + a);
+            const v4u e = quad(q, y, b, gl * 2 + a);
 #pragma unroll
             for (int c = 0; c < 4; ++c) o.D[a][c >> 1][c & 1] = e[c];
           }
@@ -1931,8 +1944,8 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_sub_kernel(Globals g)
 }
 
 // The quad tables of the order-5 jobs: for every 4-set a < b < c < j its
-// {0,1}^4 counts, packed, at [colex index of (a, b, c)][j] (4 v4u:
-// [g_a][g_b] of [g_c][g_j]).  Grid: x = group of 16 pairs (a, b) below c in
+// {0,1}^4 counts, packed, at entry quad_entry (4 v4u: [g_a][g_b] of
+// [g_c][g_j]).  Grid: x = group of 16 pairs (a, b) below c in
 // colex order, y = c - 2, z = job; the workgroup walks the blocks of 64 last
 // variants (the order-4 kernel's tiles, counts stored instead of scored).
 __global__ __launch_bounds__(kMfmaWaves * 64) void quads_kernel(Globals g) {
@@ -1977,7 +1990,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64) void quads_kernel(Globals g) {
           cell[a][1] = (gl ? own : recv) << 2;
         }
         if (q < nq && j < n) {
-          v4u *dst = QT + ((hc + q) * np + j) * 4;
+          v4u *dst = QT + quad_entry(n, hc + q, c, j) * 4;
 #pragma unroll
           for (int ab = 0; ab < 4; ++ab) {
             v4u o;
