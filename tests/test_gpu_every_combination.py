@@ -69,6 +69,11 @@ CASES = [
     ("fp4-quads-dual", 5, 19, 777, 0.35, K.KERNEL_MFMA_FP4_TABLES),
     ("fp4-quads-two-acc", 5, 16, 8200, 0.5, K.KERNEL_MFMA_FP4_TABLES),
     ("fp4-quads-two-acc", 5, 13, 16383, 0.45, K.KERNEL_MFMA_FP4_TABLES),
+    # the fewest variants: a single combination, and one more variant
+    ("fp4-tables-min", 4, 4, 100, 0.5, K.KERNEL_MFMA_FP4_TABLES),
+    ("fp4-tables-min", 4, 5, 333, 0.4, K.KERNEL_MFMA_FP4_TABLES),
+    ("fp4-tables-min", 5, 5, 90, 0.5, K.KERNEL_MFMA_FP4_TABLES),
+    ("fp4-tables-min", 5, 6, 257, 0.6, K.KERNEL_MFMA_FP4_TABLES),
 ]
 
 ENV = ("FIUNCHO_ORDER2_MFMA", "FIUNCHO_ORDER3_MFMA", "FIUNCHO_ORDER3_PAIRS", "FIUNCHO_ORDER4_TRIPLES")

@@ -123,6 +123,7 @@ CASES = [
     (15, 24, 150, 0.45, 7, 20, 0, 1),
     (16, 22, 97, 0.5, 8, 15, 1, 0),
     (17, 13, 88, 0.5, 7, 1716, 0, 0),      # every combination of order 7
+    (18, 48, 200, 0.5, 6, 30, 1, 1),       # order 6 at 48 variants (1.2e7 combinations)
 ]
 
 
