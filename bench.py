@@ -16,7 +16,9 @@ A default run (order3-1000x6400, automatic kernels, no shard) also measures
 the other workloads of the metric in the same process and adds them as
 "configs": each with its step time, rate, kernels, dominant kernel and its
 roofline fraction; batch64 (one graph replay) carries its speed-up over
-batch64-plain (64 calls).  --no-configs skips them.
+batch64-plain (64 calls).  --no-configs skips them.  Besides combinations/s
+the line gives combinations x samples/s and table cells x samples/s
+(combinations x 3^k x samples), the unit of the paper's own figures.
 
 Workloads (seeded synthetic data, see paper_2201_03331_amd/synth.py):
   order3-1000x6400 (default), order2-100x1600, order2-4000x16000,
@@ -221,6 +223,8 @@ def measure(datasets, steps, warmup, graph=False, plain=False, shard=None):
 
     combos = sum(share(d) for d in datasets)
     combos_m = sum(share(d) * d.m for d in datasets)
+    # table cells times samples: the unit of the paper's own throughput figures
+    cells_m = sum(share(d) * 3 ** d.order * d.m for d in datasets)
 
     # roofline of the dominant counting kernel: algorithmic work per launch
     # over that kernel's measured time.  Popcount kernels: 32-bit VALU
@@ -287,7 +291,8 @@ def measure(datasets, steps, warmup, graph=False, plain=False, shard=None):
                             for d, (_, h) in zip(datasets, res))
     del batches
     torch.cuda.synchronize()
-    return {"ms": ms, "prof": prof, "ok": ok, "combos": combos, "combos_m": combos_m, "roofline": roofline,
+    return {"ms": ms, "prof": prof, "ok": ok, "combos": combos, "combos_m": combos_m, "cells_m": cells_m,
+            "roofline": roofline,
             "kernels": kernels, "planted_first": planted_first}
 
 
@@ -315,6 +320,7 @@ def summary(name, r, steps, warmup):
     return {"ms_per_step": round(r["ms"], 4), "steps": steps, "warmup": warmup,
             "combinations": r["combos"], "combinations_per_s": r["combos"] / (r["ms"] / 1e3),
             "combinations_x_samples_per_s": r["combos_m"] / (r["ms"] / 1e3),
+            "cells_x_samples_per_s": r["cells_m"] / (r["ms"] / 1e3),
             "kernels": sorted(KERNEL_NAMES[k] for k in r["kernels"]),
             "dominant_kernel": rf["kernel"], "kernel_ms": round(rf["kernel_ms"], 4),
             "roofline_bound": rf["bound"], "roofline_frac": round(rf["frac"], 4),
@@ -424,6 +430,7 @@ def main():
             "shard": None if shard is None else f"{shard[0]}/{shard[1]}",
         },
         "combinations_x_samples_per_s": r["combos_m"] / (ms / 1e3),
+        "cells_x_samples_per_s": r["cells_m"] / (ms / 1e3),
         "arithmetic": arithmetic_of(kernels),
         "phases_ms": {k: round(prof[k], 4) for k in ("pack_ms", "pilot_ms", "scan_ms", "mfma_ms",
                                                      "select_ms", "total_ms")},
