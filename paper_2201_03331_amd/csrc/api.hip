@@ -269,7 +269,7 @@ bool kernel_valid(int kernel, uint32_t n, uint32_t k) {
 // a search, triple tables on the popcount kernel 18.8 ms, every prefix row on
 // the matrix cores 17.6 ms), else the popcount kernel's triple tables, else
 // every prefix row on the matrix cores.  Order 5 likewise with quad tables
-// while they fit in 48 GiB (200 x 4,000: 1.26 s, every prefix row on the
+// while they fit in 48 GiB (200 x 4,000: 1.21 s, every prefix row on the
 // matrix cores 1.93 s, popcount 3.7 s), else every prefix row on the matrix
 // cores.  The matrix cores take every prefix row of orders 4 and 5 up to
 // 20,447 samples.

@@ -1612,15 +1612,14 @@ __device__ __forceinline__ void wave_t4(const Globals &g, const JV &v, uint32_t 
 }
 
 // One wave of order 5: prefixes (w, x, y, b), (w, x, y) of colex indices
-// q0 + [0, 4), x last variants j0 + [0, 32).  The two lanes of a combination
-// (lane half s: prefix s of each fragment; lanes l, l ^ 1: g_j = 0, 1) split
-// its 243 cells.  Fixing g_w and g_j leaves an order-3 table over (x, y, b)
-// whose inputs (walk_order3_packed) are {0,1}^5 counts and the quad, triple
-// and pair tables restricted to them; the walk is linear in its inputs, so
-// the table at a 2 of g_w or g_j is the walk of (inputs with that position
-// marginalised) - (inputs at 0) - (inputs at 1).  The lane of g_j = t takes
-// the 3 tables at g_w = t and every cell; both lanes walk the 3 tables at
-// g_w = 2, each scoring every other cell position.
+// q0 + [0, 4), x last variants j0 + [0, 32).  Fixing g_w and g_j leaves an
+// order-3 table over (x, y, b) whose inputs (walk_order3_packed) are {0,1}^5
+// counts and the quad, triple and pair tables restricted to them; the walk
+// is linear in its inputs, so the table at a 2 of g_w or g_j is the walk of
+// (inputs with that variant marginalised) - (inputs at 0) - (inputs at 1).
+// Each lane scores one combination, all 9 tables (243 cells): both output
+// blocks of a fragment are taken at once, the lane of g_j = t taking block t
+// with its partner's counts of the other g_j.
 template <bool DUAL>
 __device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t b, u64 q0, uint32_t j0,
                                         uint32_t lane, const FI_LDS float *Fl) {
@@ -1682,186 +1681,179 @@ __device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t 
     walk_order3_packed(t.D, t.xy, t.xz, t.yz, t.Mx, t.My, t.Mz, t.m, visit);
   };
   const uint32_t hb = binom3(b);  // colex index of (a, c, b) = C(b, 3) + colex index of (a, c)
-  // one A fragment at a time: its counts, then its two output blocks
+  // one A fragment at a time: its counts, then both its output blocks at
+  // once, one combination per lane: the lane of g_j = t in lane half s takes
+  // prefix s and the last variant of block fb = t, with its partner's counts
+  // of that block at the other g_j
 #pragma unroll 1
   for (int f = 0; f < 2; ++f) {
-    uint32_t Q[1][2][16];
-    sub_contract<5, DUAL, 1>(v, b, q0, nq, j0, lane, Q, f);
-#pragma unroll 1
-    for (int fb = 0; fb < 2; ++fb) {
-      // {0,1}^5 counts at g_w = gl for both g_j: own registers 8 gl + [0, 8)
-      // at g_j = gl, the partner's (its registers 8 gl + [0, 8)) at 1 - gl
-      uint32_t dj[2][8];
+    uint32_t cells[2][2][8];  // [g_w][g_j][4 g_x + 2 g_y + g_b], packed x 4
+    {
+      uint32_t Q[1][2][16];
+      sub_contract<5, DUAL, 1>(v, b, q0, nq, j0, lane, Q, f);
 #pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        const uint32_t lo = fb ? Q[0][1][a] : Q[0][0][a], hi = fb ? Q[0][1][8 + a] : Q[0][0][8 + a];
-        const uint32_t own = gl ? hi : lo;
-        const uint32_t recv = xor1(gl ? lo : hi);
-        dj[0][a] = (gl ? recv : own) << 2;
-        dj[1][a] = (gl ? own : recv) << 2;
+      for (int e = 0; e < 16; ++e) {
+        const uint32_t own = gl ? Q[0][1][e] : Q[0][0][e];
+        const uint32_t recv = xor1(gl ? Q[0][0][e] : Q[0][1][e]);
+        cells[e >> 3][0][e & 7] = (gl ? recv : own) << 2;
+        cells[e >> 3][1][e & 7] = (gl ? own : recv) << 2;
       }
-      // the prefix of this lane half in fragment f
-      // (a lane past the last prefix scores nothing; it reads the tables of
-      // (0, 1, 2, b), colex index 0, so that every read stays in the tables)
-      const u64 qp = q0 + 2 * f + h;
-      const bool valid = qp < nq;
-      const u64 q = valid ? qp : 0;
-      uint32_t w = 0, x = 1, y = 2;
-      if (valid) colex_triple(q, w, x, y);
-      const u64 cwxb = hb + (u64)x * (x - 1) / 2 + w, cwyb = hb + (u64)y * (y - 1) / 2 + w,
-                cxyb = hb + (u64)y * (y - 1) / 2 + x;
-      const uint32_t j = j0 + 16 * fb + (r >> 1);
-      const uint32_t J = j < n ? j : n - 1;
-      const bool active = valid && j < n;
-      float fs = gl ? 0.f : mc.c;
-      // the lane's own table (all its cells) and the g_w = 2 table (every
-      // other cell position: the lane of g_j = 0 the even ones, its partner
-      // the odd ones; one instruction stream, the cells chosen by lane)
-      auto score_all = [&](const Tab3P &t) {
-        if (active) walk(t, [&](uint32_t p) { fs += term(p); });
-      };
-      auto score_half = [&](const Tab3P &t) {
-        if (active) {
-          uint32_t held = 0;
-          int pos = 0;
-          walk(t, [&](uint32_t p) {
-            if (pos & 1) fs += term(gl ? p : held);
-            else held = p;
-            ++pos;
-          });
-          if (pos & 1) fs += term(gl ? 0u : held);
-        }
-      };
-      // the lane's own inputs at g_w = gl and the inputs without w, at g_j =
-      // sg, or summed over g_j = 0, 1 (sg = 2: what the g_j = 2 tables
-      // subtract from the prefix tables)
-      auto own_at = [&](int sg, Tab3P &o) {
-        auto pick = [&](const v4u &e, int c) { return sg < 2 ? e[c * 2 + sg] : e[c * 2] + e[c * 2 + 1]; };
+    }
+    // (a lane past the last prefix scores nothing; it reads the tables of
+    // (0, 1, 2, b), colex index 0, so that every read stays in the tables)
+    const u64 qp = q0 + 2 * f + h;
+    const bool valid = qp < nq;
+    const u64 q = valid ? qp : 0;
+    uint32_t w = 0, x = 1, y = 2;
+    if (valid) colex_triple(q, w, x, y);
+    const u64 cwxb = hb + (u64)x * (x - 1) / 2 + w, cwyb = hb + (u64)y * (y - 1) / 2 + w,
+              cxyb = hb + (u64)y * (y - 1) / 2 + x;
+    const uint32_t j = j0 + 16 * gl + (r >> 1);
+    const uint32_t J = j < n ? j : n - 1;
+    const bool active = valid && j < n;
+    float fs = mc.c;
+    auto score = [&](const Tab3P &t) {
+      if (active) walk(t, [&](uint32_t p) { fs += term(p); });
+    };
+    // X(gw, sj): the inputs of the order-3 table over (x, y, b) with w at
+    // genotype gw and j at sj, 2 meaning the variant marginalised (left out);
+    // sj = 3: the sum of sj = 0 and 1.  t = X (sign +1) or t -= X (-1).
+    auto X = [&](int gw, int sj, Tab3P &t, int sign) {
+      auto put = [&](uint32_t &u, uint32_t val) { u = sign > 0 ? val : u - val; };
+      auto pick = [&](const v4u &e, int c) { return sj < 2 ? e[c * 2 + sj] : e[c * 2] + e[c * 2 + 1]; };
+      if (gw < 2 && sj != 2) {
 #pragma unroll
         for (int a = 0; a < 8; ++a)
-          o.D[a >> 2][(a >> 1) & 1][a & 1] = sg < 2 ? dj[sg][a] : dj[0][a] + dj[1][a];
+          put(t.D[a >> 2][(a >> 1) & 1][a & 1], sj < 2 ? cells[gw][sj][a] : cells[gw][0][a] + cells[gw][1][a]);
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-          const v4u exy = quad(q, y, J, gl * 2 + a), exb = quad(cwxb, b, J, gl * 2 + a), eyb = quad(cwyb, b, J, gl * 2 + a);
+          const v4u exy = quad(q, y, J, gw * 2 + a), exb = quad(cwxb, b, J, gw * 2 + a),
+                    eyb = quad(cwyb, b, J, gw * 2 + a);
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
-            o.xy[a][c] = pick(exy, c);
-            o.xz[a][c] = pick(exb, c);
-            o.yz[a][c] = pick(eyb, c);
+            put(t.xy[a][c], pick(exy, c));
+            put(t.xz[a][c], pick(exb, c));
+            put(t.yz[a][c], pick(eyb, c));
           }
         }
-        const v4u mx = triple(w, x, J, gl), my = triple(w, y, J, gl), mb = triple(w, b, J, gl);
+        const v4u mx = triple(w, x, J, gw), my = triple(w, y, J, gw), mb = triple(w, b, J, gw);
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-          o.Mx[a] = pick(mx, a);
-          o.My[a] = pick(my, a);
-          o.Mz[a] = pick(mb, a);
+          put(t.Mx[a], pick(mx, a));
+          put(t.My[a], pick(my, a));
+          put(t.Mz[a], pick(mb, a));
         }
         const v4u pj = pair(w, J);
-        o.m = sg < 2 ? pj[gl * 2 + sg] : pj[gl * 2] + pj[gl * 2 + 1];
-      };
-      auto star_at = [&](int sg, Tab3P &t) {
-        auto pick = [&](const v4u &e, int c) { return sg < 2 ? e[c * 2 + sg] : e[c * 2] + e[c * 2 + 1]; };
+        put(t.m, sj < 2 ? pj[gw * 2 + sj] : pj[gw * 2] + pj[gw * 2 + 1]);
+      } else if (gw < 2) {  // j marginalised: the prefix's tables at g_w
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const v4u e = quad(q, y, b, gw * 2 + a);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) put(t.D[a][c >> 1][c & 1], e[c]);
+        }
+        const v4u exy = triple(w, x, y, gw), exb = triple(w, x, b, gw), eyb = triple(w, y, b, gw);
+        const v4u px = pair(w, x), py = pair(w, y), pb = pair(w, b);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          put(t.xy[c >> 1][c & 1], exy[c]);
+          put(t.xz[c >> 1][c & 1], exb[c]);
+          put(t.yz[c >> 1][c & 1], eyb[c]);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          put(t.Mx[a], px[gw * 2 + a]);
+          put(t.My[a], py[gw * 2 + a]);
+          put(t.Mz[a], pb[gw * 2 + a]);
+        }
+        put(t.m, marg4(w, gw));
+      } else if (sj != 2) {  // w marginalised: the tables of (x, y, b, j)
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
           const v4u e = quad(cxyb, b, J, a);
 #pragma unroll
-          for (int c = 0; c < 2; ++c) t.D[a >> 1][a & 1][c] = pick(e, c);
+          for (int c = 0; c < 2; ++c) put(t.D[a >> 1][a & 1][c], pick(e, c));
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
           const v4u exy = triple(x, y, J, a), exb = triple(x, b, J, a), eyb = triple(y, b, J, a);
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
-            t.xy[a][c] = pick(exy, c);
-            t.xz[a][c] = pick(exb, c);
-            t.yz[a][c] = pick(eyb, c);
+            put(t.xy[a][c], pick(exy, c));
+            put(t.xz[a][c], pick(exb, c));
+            put(t.yz[a][c], pick(eyb, c));
           }
         }
         const v4u px = pair(x, J), py = pair(y, J), pb = pair(b, J);
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-          t.Mx[a] = pick(px, a);
-          t.My[a] = pick(py, a);
-          t.Mz[a] = pick(pb, a);
+          put(t.Mx[a], pick(px, a));
+          put(t.My[a], pick(py, a));
+          put(t.Mz[a], pick(pb, a));
         }
-        t.m = sg < 2 ? marg4(J, sg) : marg4(J, 0) + marg4(J, 1);
-      };
+        put(t.m, sj < 2 ? marg4(J, sj) : marg4(J, 0) + marg4(J, 1));
+      } else {  // both marginalised: the table of (x, y, b)
 #pragma unroll
-      for (int sg = 0; sg < 2; ++sg) {
-        Tab3P o, t2;
-        own_at(sg, o);  // g_w = gl, g_j = sg
-        score_all(o);
-        star_at(sg, t2);  // g_w = 2: the table without w less both lanes' own
-        each2(t2, o, [](uint32_t &u, uint32_t ov) { u -= ov + xor1(ov); });
-        score_half(t2);
+        for (int a = 0; a < 2; ++a) {
+          const v4u e = triple(x, y, b, a);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) put(t.D[a][c >> 1][c & 1], e[c]);
+        }
+        const v4u exy = pair(x, y), exb = pair(x, b), eyb = pair(y, b);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          put(t.xy[c >> 1][c & 1], exy[c]);
+          put(t.xz[c >> 1][c & 1], exb[c]);
+          put(t.yz[c >> 1][c & 1], eyb[c]);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          put(t.Mx[a], marg4(x, a));
+          put(t.My[a], marg4(y, a));
+          put(t.Mz[a], marg4(b, a));
+        }
+        put(t.m, pack_x4(v.m0, v.m1));
       }
-      // g_j = 2: the prefix tables less the tables at g_j = 0, 1
-      {
-        Tab3P o, t2;
-        {
-          Tab3P d;
-          own_at(2, d);
+    };
+    // the table at (G, S), G, S in {0, 1, 2}: X(G, S) for G, S < 2; a 2
+    // takes that variant's marginal less its two other genotypes (one sum of
+    // inputs kept in registers, the others read again: measured fastest)
+    Tab3P R0;  // X(0, 0) + X(1, 0)
 #pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            const v4u e = quad(q, y, b, gl * 2 + a);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) o.D[a][c >> 1][c & 1] = e[c];
-          }
-          const v4u exy = triple(w, x, y, gl), exb = triple(w, x, b, gl), eyb = triple(w, y, b, gl);
-          const v4u px = pair(w, x), py = pair(w, y), pb = pair(w, b);
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            o.xy[c >> 1][c & 1] = exy[c];
-            o.xz[c >> 1][c & 1] = exb[c];
-            o.yz[c >> 1][c & 1] = eyb[c];
-          }
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            o.Mx[a] = px[gl * 2 + a];
-            o.My[a] = py[gl * 2 + a];
-            o.Mz[a] = pb[gl * 2 + a];
-          }
-          o.m = marg4(w, gl);
-          each2(o, d, [](uint32_t &u, uint32_t dv) { u -= dv; });
-        }
-        {
-          Tab3P d;
-          star_at(2, d);
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            const v4u e = triple(x, y, b, a);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) t2.D[a][c >> 1][c & 1] = e[c];
-          }
-          const v4u exy = pair(x, y), exb = pair(x, b), eyb = pair(y, b);
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            t2.xy[c >> 1][c & 1] = exy[c];
-            t2.xz[c >> 1][c & 1] = exb[c];
-            t2.yz[c >> 1][c & 1] = eyb[c];
-          }
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            t2.Mx[a] = marg4(x, a);
-            t2.My[a] = marg4(y, a);
-            t2.Mz[a] = marg4(b, a);
-          }
-          t2.m = pack_x4(v.m0, v.m1);
-          each2(t2, d, [](uint32_t &u, uint32_t dv) { u -= dv; });
-        }
-        each2(t2, o, [](uint32_t &u, uint32_t ov) { u -= ov + xor1(ov); });
-        score_all(o);
-        score_half(t2);
-      }
-      // both lanes' parts; the lane of g_j = 0 appends
-      const float total = fs + __uint_as_float(xor1(__float_as_uint(fs)));
-      const uint32_t pre[4] = {w, x, y, b};
-      if (emit_with(v, active && gl == 0, total * mc.inv_m,
-                    [&] { return lex_rank_prefix(g, n, 5, pre) + (u64)(j - b - 1); }, thr,
-                    lane) >= kRefreshAppends)
-        thr = current_threshold_lanes(v);
+    for (int gw = 0; gw < 2; ++gw) {
+      Tab3P t;
+      X(gw, 0, t, +1);
+      score(t);
+      if (gw == 0) R0 = t;
+      else each2(R0, t, [](uint32_t &u, uint32_t tv) { u += tv; });
+      X(gw, 1, t, +1);
+      score(t);
+      X(gw, 2, t, +1);  // (gw, 2)
+      X(gw, 3, t, -1);
+      score(t);
     }
+    {
+      Tab3P t;
+      X(2, 0, t, +1);  // (2, 0)
+      each2(t, R0, [](uint32_t &u, uint32_t rv) { u -= rv; });
+      score(t);
+      R0 = t;  // from here on the (2, 0) and (2, 1) inputs, summed
+      X(2, 1, t, +1);  // (2, 1)
+      X(0, 1, t, -1);
+      X(1, 1, t, -1);
+      score(t);
+      each2(R0, t, [](uint32_t &u, uint32_t tv) { u += tv; });
+      X(2, 2, t, +1);  // (2, 2) = X(2, 2) - X(0, 2) - X(1, 2) - (2, 0) - (2, 1)
+      X(0, 2, t, -1);
+      X(1, 2, t, -1);
+      each2(t, R0, [](uint32_t &u, uint32_t rv) { u -= rv; });
+      score(t);
+    }
+    const uint32_t pre[4] = {w, x, y, b};
+    if (emit_with(v, active, fs * mc.inv_m,
+                  [&] { return lex_rank_prefix(g, n, 5, pre) + (u64)(j - b - 1); }, thr,
+                  lane) >= kRefreshAppends)
+      thr = current_threshold_lanes(v);
   }
 }
 
