@@ -508,6 +508,21 @@ __device__ __forceinline__ uint32_t job_of_tile(const Globals &g, u64 t) {
   return uni(lo);
 }
 
+// Whether any job of a launch satisfies mine(m0, m1, m) (its class sizes,
+// known once the partition has run).  The dual and the two-accumulator
+// matrix-core kernels of a group are both launched over its tiles and split
+// its jobs by class sizes: a launch with none of its own exits at once
+// instead of drawing and skipping the tiles.
+template <typename Mine>
+__device__ __forceinline__ bool any_job(const Globals &g, Mine &&mine) {
+  for (uint32_t i = 0; i < g.n_jobs; ++i) {
+    const FI_CONST JobDesc *jd = as_const(g.jobs) + i;
+    const JobState *st = uni_ptr(jd->state);
+    if (mine(uni(st->m0), uni(st->m1), uni(jd->m))) return true;
+  }
+  return false;
+}
+
 // Row of tile-local index lt in a job's row table rows[0 .. nrows] (rows[0] =
 // 0 <= lt < rows[nrows]).  hint: the row of an earlier tile of the same job,
 // or 0; the tiles a workgroup draws only increase, and so do their local

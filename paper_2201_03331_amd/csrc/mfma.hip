@@ -1173,6 +1173,10 @@ __global__ __launch_bounds__(kMfmaWaves * 64, (rows_waves<K, DUAL>())) void mfma
   const FI_LDS float *Fl = (const FI_LDS float *)s_f;
   uint32_t f_job = ~0u;
   RowHint hint;  // the row of the workgroup's last tile
+  if (!any_job(g, [](uint32_t m0, uint32_t m1, uint32_t m) {
+        return (bit_len(m0) + bit_len(m1) <= 24 && m + 1 <= rows_f_entries<K, true>()) == DUAL;
+      }))
+    return;
   for (;;) {
     if (threadIdx.x == 0) s_tile = g.tile_base + atomicAdd(g.tile_counter, 1ull);
     __syncthreads();
@@ -1882,6 +1886,10 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_sub_kernel(Globals g)
   const FI_LDS float *Fl = (const FI_LDS float *)s_f;
   uint32_t f_job = ~0u;
   RowHint hint;  // the row of the workgroup's last tile
+  if (!any_job(g, [](uint32_t m0, uint32_t m1, uint32_t m) {
+        return (bit_len(m0) + bit_len(m1) <= 24 && m + 1 <= t4_f_entries<true>()) == DUAL;
+      }))
+    return;
   for (;;) {
     if (threadIdx.x == 0) s_tile = g.tile_base + atomicAdd(g.tile_counter, 1ull);
     __syncthreads();
@@ -2055,6 +2063,13 @@ __global__ __launch_bounds__(kMfmaWaves * 64, FMT == kMfmaF4Dual ? 3 : 2) void m
   uint32_t f_job = ~0u;  // job whose table s_f holds (same in every thread)
   bool f_lds = false;
   RowHint hint;  // the row of the workgroup's last tile
+  if (FMT == kMfmaF4Narrow || FMT == kMfmaF4Dual) {
+    if (!any_job(g, [](uint32_t m0, uint32_t m1, uint32_t m) {
+          return (bit_len(m0) + bit_len(m1) <= 24 && m + 1 <= mfma_f_entries(kMfmaF4Dual)) ==
+                 (FMT == kMfmaF4Dual);
+        }))
+      return;
+  }
   for (;;) {
     if (threadIdx.x == 0) s_tile = g.tile_base + atomicAdd(g.tile_counter, 1ull);
     __syncthreads();
