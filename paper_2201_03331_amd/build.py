@@ -5,6 +5,7 @@
 from __future__ import annotations
 
 import os
+import re
 import subprocess
 import sys
 
@@ -26,6 +27,31 @@ FLAGS = [
 ]
 
 
+# Kernels that address their dynamic LDS from address 0 (lds_window in
+# mfma.hip): they must declare no static LDS, which the compiler's resource
+# remarks for mfma.hip confirm at every build.
+LDS_WINDOW_KERNELS = re.compile(r"_ZN7fiuncho(11mfma_kernelILi[23]ELi[123]E|15mfma_sub_kernelI)")
+REMARKS = "-Rpass-analysis=kernel-resource-usage"
+
+
+def check_lds_window(text: str) -> None:
+    """Raises unless every kernel of LDS_WINDOW_KERNELS reports 0 bytes of static LDS."""
+    sizes, name = {}, None
+    for line in text.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+        m = re.search(r"LDS Size \[bytes/block\]: (\d+)", line)
+        if m and name:
+            sizes[name] = int(m.group(1))
+    checked = {k: v for k, v in sizes.items() if LDS_WINDOW_KERNELS.match(k)}
+    if not checked:
+        raise RuntimeError("no resource remarks for the kernels that address LDS from 0")
+    bad = {k: v for k, v in checked.items() if v != 0}
+    if bad:
+        raise RuntimeError(f"kernels addressing LDS from 0 declare static LDS: {bad}")
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
     procs = []
@@ -33,7 +59,8 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(OBJ, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *([REMARKS] if src == "mfma.hip" else []), "-c", os.path.join(CSRC, src),
+               "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -41,10 +68,13 @@ def build(verbose: bool = False) -> str:
     for src, p in procs:
         out, _ = p.communicate()
         text = out.decode(errors="replace")
-        lines = [l for l in text.splitlines() if "packed-fp32-ops" not in l and l.strip()]
+        lines = [l for l in text.splitlines()
+                 if "packed-fp32-ops" not in l and "kernel-resource-usage" not in l and l.strip()]
         if p.returncode != 0:
             failed.append(src)
             print("\n".join(lines), file=sys.stderr)
+        elif src == "mfma.hip":
+            check_lds_window(text)
         elif verbose and lines:
             print("\n".join(lines))
     if failed:

@@ -83,6 +83,24 @@ __host__ __device__ constexpr uint32_t mfma_f_entries(int fmt) {
   return fmt == kMfmaI8 ? 12280u : fmt == kMfmaF4Dual ? 8192u : 20448u;
 }
 
+// Dynamic LDS of a workgroup: the f table of E entries, then the 8-byte slot
+// of its current tile.
+__host__ __device__ constexpr size_t f_lds_bytes(uint32_t entries) {
+  return (size_t)entries * sizeof(float) + sizeof(u64);
+}
+template <uint32_t E>
+__device__ __forceinline__ FI_LDS u64 &tile_slot(FI_LDS float *f) {
+  static_assert(E % 2 == 0, "the tile slot needs 8-byte alignment");
+  return *reinterpret_cast<FI_LDS u64 *>(f + E);
+}
+
+// The dynamic LDS of the FP4 kernels, addressed from 0.  They declare no
+// static LDS (the build checks that each reports an LDS size of 0 bytes), so
+// their dynamic block starts at LDS address 0, and an f-table entry is read at
+// the count's byte offset alone: through the extern array's symbol, resolved
+// only when the code object is linked, every read would first add the base.
+__device__ __forceinline__ FI_LDS float *lds_window() { return (FI_LDS float *)(uintptr_t)0; }
+
 __device__ __forceinline__ u64 spread8(uint32_t e) {
   const uint32_t lo = ((e & 0xFu) * 0x00204081u) & 0x01010101u;
   const uint32_t hi = (((e >> 4) & 0xFu) * 0x00204081u) & 0x01010101u;
@@ -194,6 +212,18 @@ __device__ __forceinline__ v8i expand32_fp4_a(uint32_t b) {
   r[1] = (int)(b & 0x22222222u);
   r[2] = (int)(b & 0x44444444u);
   r[3] = (int)((b >> 2) & 0x22222222u);
+  r[4] = r[5] = r[6] = r[7] = 0;
+  return r;
+}
+// The A form of x AND y: each register one 3-input AND (x, y, the register's
+// nibble mask), register 3 masked before its shift
+__device__ __forceinline__ v8i expand32_fp4_and(uint32_t x, uint32_t y) {
+  constexpr uint32_t kAnd3 = 0x80;  // truth table of a & b & c
+  v8i r;
+  r[0] = __builtin_amdgcn_bitop3_b32(x, y, 0x11111111u, kAnd3);
+  r[1] = __builtin_amdgcn_bitop3_b32(x, y, 0x22222222u, kAnd3);
+  r[2] = __builtin_amdgcn_bitop3_b32(x, y, 0x44444444u, kAnd3);
+  r[3] = (int)((uint32_t)__builtin_amdgcn_bitop3_b32(x, y, 0x88888888u, kAnd3) >> 2);
   r[4] = r[5] = r[6] = r[7] = 0;
   return r;
 }
@@ -657,13 +687,12 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
       x[4] = ld32(sw, ob);
     };
     // A row = row of a AND row of b
-    auto prep = [](const uint32_t (&x)[5], uint32_t (&o)[4]) {
-      o[0] = x[0] & x[4];
-      o[1] = x[1] & x[4];
-      o[2] = x[2];
-      o[3] = x[3];
+    const auto ops = [](const uint32_t (&x)[5], v8i (&E)[4]) {
+      E[0] = expand32_fp4_and(x[0], x[4]);
+      E[1] = expand32_fp4_and(x[1], x[4]);
+      E[2] = expand32_fp4_b(x[2]);
+      E[3] = expand32_fp4_b(x[3]);
     };
-    const auto ops = expanded_ops<5>(prep);
     if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<4, 5>(load_words, ops, v.W0, v.W1, Q);
     else if constexpr (FMT == kMfmaF4Dual)
       contract_fp4_dual<4, 5>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
@@ -1466,19 +1495,18 @@ __device__ __forceinline__ void sub_contract(const JV &v, uint32_t b, u64 q0, u6
     xw[FA * NP + 1] = ld32(sw, ol);
     xw[FA * NP + 2] = ld32(sw, ol + 256);
   };
-  // A row = AND of the rows of the prefix variants
-  auto prep = [](const uint32_t (&xw)[kRaw], uint32_t (&o)[FA + 2]) {
+  // A row = AND of the rows of the prefix variants (the row of b last)
+  const auto ops = [](const uint32_t (&xw)[kRaw], v8i (&E)[FA + 2]) {
 #pragma unroll
     for (int fa = 0; fa < FA; ++fa) {
-      uint32_t a = xw[FA * NP];
+      uint32_t a = xw[fa * NP];
 #pragma unroll
-      for (int t = 0; t < NP; ++t) a &= xw[fa * NP + t];
-      o[fa] = a;
+      for (int t = 1; t < NP; ++t) a &= xw[fa * NP + t];
+      E[fa] = expand32_fp4_and(a, xw[FA * NP]);
     }
-    o[FA] = xw[FA * NP + 1];
-    o[FA + 1] = xw[FA * NP + 2];
+    E[FA] = expand32_fp4_b(xw[FA * NP + 1]);
+    E[FA + 1] = expand32_fp4_b(xw[FA * NP + 2]);
   };
-  const auto ops = expanded_ops<kRaw, decltype(prep), FA>(prep);
   if constexpr (DUAL)
     contract_fp4_dual<4, kRaw, decltype(load_words) &, decltype(ops) &, FA>(load_words, ops, v.W0, v.W1,
                                                                              bit_len(v.m0), Q);
@@ -1879,11 +1907,11 @@ constexpr uint32_t sub_tile_prefixes() { return K == 4 ? 16u : 8u; }
 // one wave per SIMD without spills)
 template <int K, bool DUAL>
 __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_sub_kernel(Globals g) {
-  __shared__ u64 s_tile;
-  extern __shared__ float s_f[];
+  FI_LDS float *s_f = lds_window();
+  FI_LDS u64 &s_tile = tile_slot<t4_f_entries<DUAL>()>(s_f);
   const uint32_t lane = lane_id();
   const uint32_t wave = uni(threadIdx.x >> 6);
-  const FI_LDS float *Fl = (const FI_LDS float *)s_f;
+  const FI_LDS float *Fl = s_f;
   uint32_t f_job = ~0u;
   RowHint hint;  // the row of the workgroup's last tile
   if (!any_job(g, [](uint32_t m0, uint32_t m1, uint32_t m) {
@@ -2019,7 +2047,7 @@ int mfma_sub_grid() {
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_sub_kernel<K, DUAL>, kMfmaWaves * 64,
-                                                     t4_f_entries<DUAL>() * sizeof(float));
+                                                     f_lds_bytes(t4_f_entries<DUAL>()));
   if (cus <= 0) cus = 256;
   if (per <= 0) per = 1;
   return cus * per;
@@ -2033,7 +2061,7 @@ uint32_t mfma_sub_dual_max_samples() { return t4_f_entries<true>() - 1; }
 
 void launch_mfma_sub(const Globals &g, int order, bool dual, int grid, hipStream_t s) {
   const dim3 gd(grid), bd(kMfmaWaves * 64);
-  const size_t lds = (dual ? t4_f_entries<true>() : t4_f_entries<false>()) * sizeof(float);
+  const size_t lds = f_lds_bytes(dual ? t4_f_entries<true>() : t4_f_entries<false>());
   if (order == 5) {
     if (dual) hipLaunchKernelGGL((mfma_sub_kernel<5, true>), gd, bd, lds, s, g);
     else hipLaunchKernelGGL((mfma_sub_kernel<5, false>), gd, bd, lds, s, g);
@@ -2049,17 +2077,18 @@ void launch_mfma_sub(const Globals &g, int order, bool dual, int grid, hipStream
 template <int ORDER, int FMT>
 __global__ __launch_bounds__(kMfmaWaves * 64, FMT == kMfmaF4Dual ? 3 : 2) void mfma_kernel(Globals g) {
   constexpr bool F4 = FMT != kMfmaI8;
-  __shared__ u64 s_tile;
   __shared__ u64 s_lut[F4 ? 1 : 256 * kLutCopies];
   // the f table of the current job, when it has at most mfma_f_entries(FMT)
-  // entries (dynamic LDS of that size)
-  extern __shared__ float s_f[];
+  // entries (dynamic LDS of that size), then the tile slot
+  extern __shared__ float s_dyn[];
+  FI_LDS float *s_f = F4 ? lds_window() : (FI_LDS float *)s_dyn;
+  FI_LDS u64 &s_tile = tile_slot<mfma_f_entries(FMT)>(s_f);
   const uint32_t lane = lane_id();
   const uint32_t wave = uni(threadIdx.x >> 6);
   if (!F4)
     for (uint32_t i = threadIdx.x; i < 256 * kLutCopies; i += blockDim.x) s_lut[i] = spread8(i / kLutCopies);
   const u64 *lut = s_lut + (F4 ? 0 : lane % kLutCopies);
-  const FI_LDS float *Fl = (const FI_LDS float *)s_f;
+  const FI_LDS float *Fl = s_f;
   uint32_t f_job = ~0u;  // job whose table s_f holds (same in every thread)
   bool f_lds = false;
   RowHint hint;  // the row of the workgroup's last tile
@@ -2151,7 +2180,7 @@ int mfma_grid() {
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mfma_kernel<ORDER, FMT>, kMfmaWaves * 64,
-                                                     mfma_f_entries(FMT) * sizeof(float));
+                                                     f_lds_bytes(mfma_f_entries(FMT)));
   if (cus <= 0) cus = 256;
   if (per <= 0) per = 1;
   return cus * per;
@@ -2169,7 +2198,7 @@ uint32_t mfma_narrow_max_samples() { return mfma_f_entries(kMfmaF4Narrow) - 1; }
 
 void launch_mfma(const Globals &g, int order, int fmt, int grid, hipStream_t s) {
   const dim3 gd(grid), bd(kMfmaWaves * 64);
-  const size_t lds = mfma_f_entries(fmt) * sizeof(float);
+  const size_t lds = f_lds_bytes(mfma_f_entries(fmt));
   if (order == 3) {
     if (fmt == kMfmaI8) hipLaunchKernelGGL((mfma_kernel<3, kMfmaI8>), gd, bd, lds, s, g);
     else if (fmt == kMfmaF4) hipLaunchKernelGGL((mfma_kernel<3, kMfmaF4>), gd, bd, lds, s, g);

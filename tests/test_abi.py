@@ -207,3 +207,20 @@ def test_kernel_choice_table(monkeypatch):
         fiuncho.set_config(300, 500, 2, fiuncho.KERNEL_AUTO, 0)
     assert fiuncho.get_config(300, 500, 2) == (fiuncho.KERNEL_POPCOUNT, 0)
     assert L.fiuncho_autotune(3, 500, 4, 1, ctypes.byref(k)) == fiuncho.E_ORDER
+
+
+def test_build_checks_lds_window_kernels_have_no_static_lds():
+    # the FP4 matrix-core kernels read their f table from LDS address 0, which
+    # holds only while they declare no static LDS; the build parses the
+    # compiler's resource remarks and refuses a library where one does
+    from paper_2201_03331_amd import build
+    name = "_ZN7fiuncho11mfma_kernelILi3ELi3EEEvNS_7GlobalsE"
+    ok = (f"mfma.hip:1:1: remark: Function Name: {name} [-Rpass-analysis=kernel-resource-usage]\n"
+          "mfma.hip:1:1: remark:     LDS Size [bytes/block]: 0 [-Rpass-analysis=kernel-resource-usage]\n")
+    build.check_lds_window(ok)
+    with pytest.raises(RuntimeError, match="static LDS"):
+        build.check_lds_window(ok.replace("block]: 0", "block]: 8"))
+    with pytest.raises(RuntimeError, match="no resource remarks"):
+        build.check_lds_window(ok.replace(name, "_ZN7fiuncho13select_kernelEv"))
+    # the int8 kernel keeps its static byte table and is not checked
+    assert not build.LDS_WINDOW_KERNELS.match("_ZN7fiuncho11mfma_kernelILi3ELi0EEEvNS_7GlobalsE")
