@@ -351,7 +351,7 @@ struct JobLayout {
   size_t off_G, off_y, off_idx, off_Bv, off_Bs, off_marg, off_hist, off_phist, off_cand, off_l1, off_sel,
       off_sel2, off_state, off_out, off_nout, off_status, off_pairs, off_pairs4, off_triples, off_triples4, off_quads4;
   // plan (uploaded)
-  size_t off_rows, off_F32, off_Fh, off_P64;
+  size_t off_rows, off_F32, off_Fh, off_Fq, off_P64;
   std::vector<u64> row_start;
   u64 tiles;
   uint32_t pilot_tiles, pilot_slots;
@@ -541,6 +541,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     J.off_rows = take(sizeof(u64) * J.row_start.size());
     J.off_F32 = take(sizeof(float2) * ((size_t)J.m + 1));
     J.off_Fh = take(sizeof(float) * ((size_t)J.m + 1));
+    J.off_Fq = take(sizeof(uint32_t) * ((size_t)J.m + 1));
     J.off_P64 = take(sizeof(double) * ((size_t)J.m + 1));
   }
   L.plan_end = off;
@@ -600,6 +601,16 @@ double estimate_bound(uint32_t k, uint32_t m) {
   return u * (6.0 * std::log((double)m) + (cells + 4.0) * std::log(2.0));
 }
 float fbound(uint32_t k, uint32_t m) { return (float)(2.0 * estimate_bound(k, m) * 1.0001); }
+
+// The shift of the fixed-point f table: the largest qs with 2^qs (m ln 2 + 1)
+// <= 2^30, so that 2^qs m MI (MI <= ln 2) and its rounding error stay far
+// inside a signed 32-bit integer
+int fixed_shift(uint32_t m) {
+  const double top = std::ldexp(1.0, 30), span = (double)m * std::log(2.0) + 1.0;
+  int qs = 0;
+  while (std::ldexp(span, qs + 1) <= top) ++qs;
+  return qs;
+}
 
 // ---------------------------------------------------------------------------
 // plan: descriptors and lookup tables, built on the host
@@ -665,6 +676,8 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
     d.marg = reinterpret_cast<uint32_t *>(ws + J.off_marg);
     d.F32 = reinterpret_cast<const float2 *>(ws + J.off_F32);
     d.Fh = reinterpret_cast<const float *>(ws + J.off_Fh);
+    d.Fq = reinterpret_cast<const uint32_t *>(ws + J.off_Fq);
+    d.qscale = (float)(std::ldexp(1.0, -fixed_shift(J.m)) / (double)J.m);
     d.fbound = fbound(J.k, J.m);
     d.P64 = reinterpret_cast<const double *>(ws + J.off_P64);
     d.row_start = reinterpret_cast<const u64 *>(ws + J.off_rows);
@@ -696,9 +709,12 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
     // f(t) = t ln t as a float pair, and (t/m) ln(t/m) in double
     float2 *F = reinterpret_cast<float2 *>(at(J.off_F32));
     float *Fh = reinterpret_cast<float *>(at(J.off_Fh));
+    uint32_t *Fq = reinterpret_cast<uint32_t *>(at(J.off_Fq));
     double *P = reinterpret_cast<double *>(at(J.off_P64));
+    const int qs = fixed_shift(J.m);
     F[0] = make_float2(0.f, 0.f);
     Fh[0] = 0.f;
+    Fq[0] = 0;
     P[0] = 0.0;
     for (uint32_t t = 1; t <= J.m; ++t) {
       const double f = (double)t * std::log((double)t);
@@ -706,6 +722,8 @@ void build_plan(const Layout &L, const fiuncho_job *jobs, uint8_t *ws, bool host
       const float lo = (float)(f - (double)hi);
       F[t] = make_float2(hi, lo);
       Fh[t] = hi;
+      // below 2^35 (f(t) 2^qs <= log2(m) 2^30): exact in a 64-bit integer
+      Fq[t] = (uint32_t)(unsigned long long)std::llround(std::ldexp(f, qs));
       const double p = (double)t / (double)J.m;
       P[t] = p * std::log(p);
     }

@@ -4,6 +4,8 @@
 // (Algorithm 1's sorted list, kept as a device-wide candidate buffer).
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.hpp"
 
 namespace fiuncho {
@@ -27,6 +29,8 @@ struct JV {
   uint32_t path;
   uint32_t fp4;               // matrix-core paths: FP4 operands (else int8)
   const float *Fh;
+  const uint32_t *Fq;
+  float qscale;
   float fbound;
   mutable uint32_t *pk;       // pilot launch: this wave's next 64 score slots
 };
@@ -61,6 +65,8 @@ __device__ __forceinline__ JV load_view(const JobDesc *jd) {
   v.path = uni(J->path);
   v.fp4 = uni(J->fp4);
   v.Fh = uni_ptr(J->Fh);
+  v.Fq = uni_ptr(J->Fq);
+  v.qscale = __uint_as_float(uni(__float_as_uint(J->qscale)));
   v.fbound = __uint_as_float(uni(__float_as_uint(J->fbound)));
   v.pk = nullptr;
   return v;
@@ -180,17 +186,57 @@ __device__ __forceinline__ uint32_t emit(const JV &v, bool active, float est, u6
 }
 
 // Constants of the score of a job: m * MI starts at f(m) - f(m0) - f(m1).
+// The FP4 matrix-core kernels of orders 3 to 5, with the f table in LDS, take
+// the same sum in fixed point: with Fq[t] = round(2^qs f(t)) modulo 2^32 (qs: the largest
+// shift with 2^qs (m ln 2 + 1) <= 2^30), D = Fq[m] - Fq[m0] - Fq[m1] +
+// sum_x (Fq[n_x0] + Fq[n_x1] - Fq[n_x]) in 32-bit integers modulo 2^32.  The
+// exact sum 2^qs m MI lies in [0, 2^30] and D is off by at most half a unit
+// per table entry (3 + 3^(k+1) of them), so D read as a signed integer is
+// that integer sum, and est = D x 2^-qs / m; each cell costs two integer
+// additions instead of three floating-point ones, and the error, at most
+// (3 + 3^(k+1)) 2^-(qs+1) / m + 3u ln 2 (u = 2^-24), is below the
+// single-precision bound the filters use, for k <= 5.
 struct MiConst {
   float c;
   float inv_m;
+  uint32_t q0;   // Fq[m] - Fq[m0] - Fq[m1] modulo 2^32
+  float qscale;  // 2^-qs / m
 };
 
 __device__ __forceinline__ MiConst mi_const(const JV &v) {
   const FI_CONST float *F = as_const(v.Fh);
+  const FI_CONST uint32_t *Fq = as_const(v.Fq);
   MiConst c;
   c.c = (F[v.m] - F[v.m0]) - F[v.m1];
   c.inv_m = 1.0f / (float)v.m;
+  c.q0 = Fq[v.m] - Fq[v.m0] - Fq[v.m1];
+  c.qscale = v.qscale;
   return c;
+}
+
+// Pins an integer running sum at this point of the program.  Integer
+// addition is associative, and left free the compiler regroups a walk's
+// additions and lifts its table reads far ahead, holding many more registers
+// (spilling) than the same walk in floating point; an empty statement that
+// may change the sum keeps each group of terms in its place.
+__device__ __forceinline__ void pin_sum(uint32_t &s) { asm volatile("" : "+v"(s)); }
+
+// The estimate from the fixed-point sum D (see MiConst)
+__device__ __forceinline__ float mi_fixed(uint32_t D, const MiConst &mc) {
+  return (float)(int32_t)D * mc.qscale;
+}
+
+// Start and result of a score accumulated in the table's element type:
+// float tables the single-precision form, uint32_t tables the fixed-point one
+template <typename E>
+__device__ __forceinline__ E mi_start(const MiConst &mc) {
+  if constexpr (std::is_same_v<E, uint32_t>) return mc.q0;
+  else return mc.c;
+}
+template <typename E>
+__device__ __forceinline__ float mi_finish(E s, const MiConst &mc) {
+  if constexpr (std::is_same_v<E, uint32_t>) return mi_fixed(s, mc);
+  else return s * mc.inv_m;
 }
 
 // Scores a complete table of NC cells x 2 classes and appends it if it may be

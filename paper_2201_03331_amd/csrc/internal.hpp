@@ -112,6 +112,9 @@ struct JobDesc {
   uint32_t *marg;             // [n][3][2] per-variant class marginals
   const float2 *F32;          // (hi, lo) of t ln t for t in [0, m]
   const float *Fh;            // t ln t rounded to float, t in [0, m]
+  const uint32_t *Fq;         // round(2^qs t ln t) mod 2^32, t in [0, m]: the fixed-point table of the
+                              // FP4 matrix-core kernels of orders 3 to 5 (qs: fixed_shift(m))
+  float qscale;               // 2^-qs / m rounded to float
   float fbound;               // bound of |plain single-precision MI - MI|
   const double *P64;          // (t/m) ln(t/m) for t in [0, m]
   const unsigned long long *row_start;  // [nrows + 1] tile offsets

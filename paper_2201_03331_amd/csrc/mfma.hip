@@ -101,6 +101,20 @@ __device__ __forceinline__ FI_LDS u64 &tile_slot(FI_LDS float *f) {
 // only when the code object is linked, every read would first add the base.
 __device__ __forceinline__ FI_LDS float *lds_window() { return (FI_LDS float *)(uintptr_t)0; }
 
+// Whether a matrix-core workgroup keeps the fixed-point table Fq in LDS (and
+// scores in fixed point) or the single-precision one: fixed point where it
+// measured faster, the order-3 FP4 kernels and the order-4/5 table kernels;
+// the order-2 FP4 kernels ran a few per cent slower with it.
+template <int ORDER, int FMT>
+constexpr bool lds_fixed() { return ORDER >= 3 && FMT != kMfmaI8; }
+
+// The f table a matrix-core workgroup keeps in LDS, as its scoring reads it
+template <int ORDER, int FMT>
+__device__ __forceinline__ auto lds_table(const FI_LDS float *Fl) {
+  if constexpr (lds_fixed<ORDER, FMT>()) return (const FI_LDS uint32_t *)Fl;
+  else return Fl;
+}
+
 __device__ __forceinline__ u64 spread8(uint32_t e) {
   const uint32_t lo = ((e & 0xFu) * 0x00204081u) & 0x01010101u;
   const uint32_t hi = (((e >> 4) & 0xFu) * 0x00204081u) & 0x01010101u;
@@ -195,6 +209,14 @@ __device__ __forceinline__ uint32_t ld32(const FI_GLOBAL char *base, uint32_t of
       __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, 0x7fffffff, kBufferWord3);
   return __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
 }
+// the same for a whole 64-bit word
+typedef uint32_t v2u32 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u64 ld64(const FI_GLOBAL char *base, uint32_t off) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, 0x7fffffff, kBufferWord3);
+  const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+  return (u64)v.x | ((u64)v.y << 32);
+}
 
 
 // 32 sample bits -> the 32 FP4 operand values of one lane.  Register d takes
@@ -257,37 +279,86 @@ __device__ __forceinline__ auto expanded_ops(Prep prep) {
 // operands.  load_words(w, x) fills x with the kRaw registers the lane loads
 // for word w; ops(x, E) makes the four operands (A fragments 0, 1, B
 // fragments 0, 1) from them when the word is used.
-template <int kDepth, int kRaw, typename Load, typename Ops, int FA = 2>
+//
+// X2: the words two at a time.  Lane half h loads word w + h whole (one
+// 64-bit load per row instead of two 32-bit ones), and the two instructions
+// of a step take the low, then the high 32-bit halves: each covers 32 samples
+// of word w (lanes 0-31) and 32 of word w + 1 (lanes 32-63), the same samples
+// for both operands.  load_words(w, tail, x) fills the kRaw 64-bit words
+// (tail: std::true_type for the last step of an odd count, whose lanes of
+// half 1 must load operands with vanishing products, else std::false_type);
+// ops(x, half, E) expands the given 32-bit half.
+template <int kDepth, int kRaw, int FA = 2, bool X2 = false, typename Load, typename Ops>
 __device__ __forceinline__ void mfma_class_fp4(Load &&load_words, Ops &&ops, uint32_t wbeg,
                                                uint32_t wend, v16f (&acc)[FA][2],
                                                int scale_a = kScaleOne) {
   if (wbeg >= wend) return;
-  const uint32_t wlast = wend - 1;
-  uint32_t X[kDepth][kRaw];
+  if constexpr (X2) {
+    auto step = [&](const u64 (&x)[kRaw]) {
 #pragma unroll
-  for (int u = 0; u < kDepth; ++u) load_words(min(wbeg + u, wlast), X[u]);
-  auto step = [&](int slot) {
-    v8i E[FA + 2];
-    ops(X[slot], E);
+      for (int half = 0; half < 2; ++half) {
+        v8i E[FA + 2];
+        ops(x, half, E);
 #pragma unroll
-    for (int x = 0; x < FA; ++x)
+        for (int i = 0; i < FA; ++i)
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
-        acc[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-            E[x], E[FA + y], acc[x][y], kFmtFp4, kFmtFp4, 0, scale_a, 0, kScaleOne);
-  };
-  uint32_t w = wbeg;
-  for (; w + kDepth <= wend; w += kDepth) {
+          for (int y = 0; y < 2; ++y)
+            acc[i][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                E[i], E[FA + y], acc[i][y], kFmtFp4, kFmtFp4, 0, scale_a, 0, kScaleOne);
+      }
+    };
+    const uint32_t nfull = (wend - wbeg) / 2;  // steps of two words
+    if (nfull > 0) {
+      const uint32_t plast = nfull - 1;
+      u64 X[kDepth][kRaw];
 #pragma unroll
-    for (int u = 0; u < kDepth; ++u) {
-      step(u);
-      load_words(min(w + u + kDepth, wlast), X[u]);
-      __builtin_amdgcn_sched_barrier(0);
+      for (int u = 0; u < kDepth; ++u) load_words(wbeg + 2 * min((uint32_t)u, plast), std::false_type{}, X[u]);
+      uint32_t p = 0;
+      for (; p + kDepth <= nfull; p += kDepth) {
+#pragma unroll
+        for (int u = 0; u < kDepth; ++u) {
+          step(X[u]);
+          load_words(wbeg + 2 * min(p + u + kDepth, plast), std::false_type{}, X[u]);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kDepth - 1; ++u)
+        if (p + u < nfull) step(X[u]);
     }
-  }
+    if ((wend - wbeg) & 1) {
+      u64 x[kRaw];
+      load_words(wend - 1, std::true_type{}, x);
+      step(x);
+    }
+  } else {
+    const uint32_t wlast = wend - 1;
+    uint32_t X[kDepth][kRaw];
 #pragma unroll
-  for (int u = 0; u < kDepth - 1; ++u)
-    if (w + u < wend) step(u);
+    for (int u = 0; u < kDepth; ++u) load_words(min(wbeg + u, wlast), X[u]);
+    auto step = [&](int slot) {
+      v8i E[FA + 2];
+      ops(X[slot], E);
+#pragma unroll
+      for (int x = 0; x < FA; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+              E[x], E[FA + y], acc[x][y], kFmtFp4, kFmtFp4, 0, scale_a, 0, kScaleOne);
+    };
+    uint32_t w = wbeg;
+    for (; w + kDepth <= wend; w += kDepth) {
+#pragma unroll
+      for (int u = 0; u < kDepth; ++u) {
+        step(u);
+        load_words(min(w + u + kDepth, wlast), X[u]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kDepth - 1; ++u)
+      if (w + u < wend) step(u);
+  }
 }
 
 __device__ __forceinline__ void zero_acc(v16i (&acc0)[2][2], v16i (&acc1)[2][2]) {
@@ -301,7 +372,7 @@ __device__ __forceinline__ void zero_acc(v16i (&acc0)[2][2], v16i (&acc1)[2][2])
 
 // Both classes with FP4 operands (class 0: words [0, W0), class 1: the next
 // W1), counts returned as integers: the FP32 sums are integers below 2^24
-template <int kDepth, int kRaw, typename Load, typename Ops>
+template <int kDepth, int kRaw, int FA = 2, bool X2 = false, typename Load, typename Ops>
 __device__ __forceinline__ void contract_fp4(Load &&load_words, Ops &&ops, uint32_t W0, uint32_t W1,
                                              v16i (&acc0)[2][2], v16i (&acc1)[2][2]) {
   v16f f0[2][2], f1[2][2];
@@ -311,8 +382,8 @@ __device__ __forceinline__ void contract_fp4(Load &&load_words, Ops &&ops, uint3
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) f0[x][y][e] = f1[x][y][e] = 0.f;
-  mfma_class_fp4<kDepth, kRaw>(load_words, ops, 0, W0, f0);
-  mfma_class_fp4<kDepth, kRaw>(load_words, ops, W0, W0 + W1, f1);
+  mfma_class_fp4<kDepth, kRaw, 2, X2>(load_words, ops, 0, W0, f0);
+  mfma_class_fp4<kDepth, kRaw, 2, X2>(load_words, ops, W0, W0 + W1, f1);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -328,7 +399,7 @@ __device__ __forceinline__ void contract_fp4(Load &&load_words, Ops &&ops, uint3
 // bits.  Class 0's counts wait as 16-bit pairs while class 1 accumulates;
 // the result Q holds class 0 in the low and class 1 in the high 16 bits of
 // each output element (register e of block (x, y)).
-template <int kDepth, int kRaw, typename Load, typename Ops, int FA = 2>
+template <int kDepth, int kRaw, int FA = 2, bool X2 = false, typename Load, typename Ops>
 __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Ops &&ops, uint32_t W0,
                                                     uint32_t W1, uint32_t (&Q)[FA][2][16]) {
   v16f f[FA][2];
@@ -338,7 +409,7 @@ __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Ops &&ops
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) f[x][y][e] = 0.f;
-  mfma_class_fp4<kDepth, kRaw, Load, Ops, FA>(load_words, ops, 0, W0, f);
+  mfma_class_fp4<kDepth, kRaw, FA, X2>(load_words, ops, 0, W0, f);
   uint32_t P0[FA][2][8];
 #pragma unroll
   for (int x = 0; x < FA; ++x)
@@ -349,7 +420,7 @@ __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Ops &&ops
         P0[x][y][i] = (uint32_t)f[x][y][2 * i] | ((uint32_t)f[x][y][2 * i + 1] << 16);
         f[x][y][2 * i] = f[x][y][2 * i + 1] = 0.f;
       }
-  mfma_class_fp4<kDepth, kRaw, Load, Ops, FA>(load_words, ops, W0, W0 + W1, f);
+  mfma_class_fp4<kDepth, kRaw, FA, X2>(load_words, ops, W0, W0 + W1, f);
 #pragma unroll
   for (int x = 0; x < FA; ++x)
 #pragma unroll
@@ -363,7 +434,7 @@ __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Ops &&ops
 // scaled by 2^s (s = bit length of m0, given by the caller), so the single
 // FP32 accumulator holds c0 + 2^s c1 < 2^24, an exact integer; Q as for the
 // narrow kernels.
-template <int kDepth, int kRaw, typename Load, typename Ops, int FA = 2>
+template <int kDepth, int kRaw, int FA = 2, bool X2 = false, typename Load, typename Ops>
 __device__ __forceinline__ void contract_fp4_dual(Load &&load_words, Ops &&ops, uint32_t W0,
                                                   uint32_t W1, uint32_t s,
                                                   uint32_t (&Q)[FA][2][16]) {
@@ -374,8 +445,8 @@ __device__ __forceinline__ void contract_fp4_dual(Load &&load_words, Ops &&ops, 
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) f[x][y][e] = 0.f;
-  mfma_class_fp4<kDepth, kRaw, Load, Ops, FA>(load_words, ops, 0, W0, f);
-  mfma_class_fp4<kDepth, kRaw, Load, Ops, FA>(load_words, ops, W0, W0 + W1, f, kScaleOne + (int)s);
+  mfma_class_fp4<kDepth, kRaw, FA, X2>(load_words, ops, 0, W0, f);
+  mfma_class_fp4<kDepth, kRaw, FA, X2>(load_words, ops, W0, W0 + W1, f, kScaleOne + (int)s);
   const uint32_t low = (1u << s) - 1;
 #pragma unroll
   for (int x = 0; x < FA; ++x)
@@ -455,24 +526,38 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
     // offset
     const FI_GLOBAL char *Bvc = reinterpret_cast<const FI_GLOBAL char *>(Bv);
     const size_t word_bytes = (size_t)v.n_pad * 16;  // one word of every variant
-    const uint32_t ol = r * 8 + 4 * h;
-    auto load_words = [&](uint32_t w, uint32_t (&x)[4]) {
+    // words in pairs: lane half h reads word w + h whole
+    const uint32_t hw = h * (uint32_t)word_bytes;
+    const uint32_t ol = r * 8 + hw;
+    // the last step of an odd word count: lanes of half 1 read word w itself,
+    // their A rows from the zero rows of padding variant n
+    const uint32_t oat = h ? (n - a0) * 16 : r * 8;
+    auto load_words = [&](uint32_t w, auto tail, u64 (&x)[4]) {
       const FI_GLOBAL char *sa = Bvc + (size_t)w * word_bytes + (size_t)a0 * 16;
       const FI_GLOBAL char *sj = Bvc + (size_t)w * word_bytes + (size_t)j0 * 16;
-      x[0] = ld32(sa, ol);
-      x[1] = ld32(sa, ol + 256);
-      x[2] = ld32(sj, ol);
-      x[3] = ld32(sj, ol + 256);
+      if constexpr (!decltype(tail)::value) {
+        x[0] = ld64(sa, ol);
+        x[1] = ld64(sa, ol + 256);
+        x[2] = ld64(sj, ol);
+        x[3] = ld64(sj, ol + 256);
+      } else {
+        x[0] = ld64(sa, oat);
+        x[1] = ld64(sa, h ? oat : oat + 256);
+        x[2] = ld64(sj, ol - hw);
+        x[3] = ld64(sj, ol - hw + 256);
+      }
     };
-    auto prep = [](const uint32_t (&x)[4], uint32_t (&o)[4]) {
-#pragma unroll
-      for (int f = 0; f < 4; ++f) o[f] = x[f];
+    const auto ops = [](const u64 (&x)[4], int half, v8i (&E)[4]) {
+      const int sh = 32 * half;
+      E[0] = expand32_fp4_a((uint32_t)(x[0] >> sh));
+      E[1] = expand32_fp4_a((uint32_t)(x[1] >> sh));
+      E[2] = expand32_fp4_b((uint32_t)(x[2] >> sh));
+      E[3] = expand32_fp4_b((uint32_t)(x[3] >> sh));
     };
-    const auto ops = expanded_ops<4>(prep);
-    if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<4, 4>(load_words, ops, v.W0, v.W1, Q);
+    if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<2, 4, 2, true>(load_words, ops, v.W0, v.W1, Q);
     else if constexpr (FMT == kMfmaF4Dual)
-      contract_fp4_dual<4, 4>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
-    else contract_fp4<4, 4>(load_words, ops, v.W0, v.W1, acc0, acc1);
+      contract_fp4_dual<2, 4, 2, true>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
+    else contract_fp4<2, 4, 2, true>(load_words, ops, v.W0, v.W1, acc0, acc1);
   } else {
     zero_acc(acc0, acc1);
     auto load_words = [&](uint32_t w, u64 (&x)[4]) {
@@ -590,7 +675,8 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
             }
           }
           const bool active = a < j && j < n;
-          float fs = mc.c;
+          using E = decltype(+F[0]);  // the table's element type, without its address space
+          E fs = mi_start<E>(mc);
           if (active) {
             uint32_t t9[9][2];
 #pragma unroll
@@ -615,7 +701,7 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
               }
             }
             // the 27 table reads issued together
-            float f0[9], f1[9], f01[9];
+            E f0[9], f1[9], f01[9];
 #pragma unroll
             for (int x = 0; x < 9; ++x) {
               f0[x] = F[t9[x][0]];
@@ -627,7 +713,7 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
           }
           // the rank is computed by appending lanes only: lexicographic rank of
           // (a, j) = sum over a' < a of (n - 1 - a'), plus j - a - 1
-          if (emit_with(v, active, fs * mc.inv_m,
+          if (emit_with(v, active, mi_finish(fs, mc),
                         [&] { return (u64)a * (n - 1) - (u64)a * (a - 1) / 2 + (j - a - 1); }, thr,
                         lane) >= kRefreshAppends)
             thr = current_threshold_lanes(v);
@@ -635,7 +721,7 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
       }
     }
   };
-  if constexpr (LDS_F) score(Fl);
+  if constexpr (LDS_F) score(lds_table<2, FMT>(Fl));
   else score(as_global(v.Fh));
 }
 
@@ -671,32 +757,47 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
     // prefixes a >= b read variant n, a padding variant whose words are zero.
     const FI_GLOBAL char *Bvc = reinterpret_cast<const FI_GLOBAL char *>(Bv);
     const size_t word_bytes = (size_t)v.n_pad * 16;  // Bv bytes of one word
+    // words in pairs: lane half h reads word w + h whole
+    const uint32_t hw = h * (uint32_t)word_bytes;
     uint32_t oa[2];
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
       const uint32_t a = a_first + 8 * f + (r >> 2);
-      oa[f] = (a < b ? a : n) * 16 + ga * 8 + 4 * h;
+      oa[f] = (a < b ? a : n) * 16 + ga * 8 + hw;
     }
-    const uint32_t ob = b * 16 + gb * 8 + 4 * h, ol = j0 * 16 + r * 8 + 4 * h;
-    auto load_words = [&](uint32_t w, uint32_t (&x)[5]) {
+    const uint32_t ob = b * 16 + gb * 8 + hw, ol = j0 * 16 + r * 8 + hw;
+    // the last step of an odd word count: lanes of half 1 read word w itself,
+    // with the row of b replaced by the zero row of padding variant n, so that
+    // their A operands (a row AND the row of b) vanish
+    const uint32_t obt = h ? n * 16 : ob;
+    auto load_words = [&](uint32_t w, auto tail, u64 (&x)[5]) {
       const FI_GLOBAL char *sw = Bvc + (size_t)w * word_bytes;
-      x[0] = ld32(sw, oa[0]);
-      x[1] = ld32(sw, oa[1]);
-      x[2] = ld32(sw, ol);
-      x[3] = ld32(sw, ol + 256);
-      x[4] = ld32(sw, ob);
+      if constexpr (!decltype(tail)::value) {
+        x[0] = ld64(sw, oa[0]);
+        x[1] = ld64(sw, oa[1]);
+        x[2] = ld64(sw, ol);
+        x[3] = ld64(sw, ol + 256);
+        x[4] = ld64(sw, ob);
+      } else {
+        x[0] = ld64(sw, oa[0] - hw);
+        x[1] = ld64(sw, oa[1] - hw);
+        x[2] = ld64(sw, ol - hw);
+        x[3] = ld64(sw, ol + 256 - hw);
+        x[4] = ld64(sw, obt);
+      }
     };
     // A row = row of a AND row of b
-    const auto ops = [](const uint32_t (&x)[5], v8i (&E)[4]) {
-      E[0] = expand32_fp4_and(x[0], x[4]);
-      E[1] = expand32_fp4_and(x[1], x[4]);
-      E[2] = expand32_fp4_b(x[2]);
-      E[3] = expand32_fp4_b(x[3]);
+    const auto ops = [](const u64 (&x)[5], int half, v8i (&E)[4]) {
+      const int sh = 32 * half;
+      E[0] = expand32_fp4_and((uint32_t)(x[0] >> sh), (uint32_t)(x[4] >> sh));
+      E[1] = expand32_fp4_and((uint32_t)(x[1] >> sh), (uint32_t)(x[4] >> sh));
+      E[2] = expand32_fp4_b((uint32_t)(x[2] >> sh));
+      E[3] = expand32_fp4_b((uint32_t)(x[3] >> sh));
     };
-    if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<4, 5>(load_words, ops, v.W0, v.W1, Q);
+    if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<2, 5, 2, true>(load_words, ops, v.W0, v.W1, Q);
     else if constexpr (FMT == kMfmaF4Dual)
-      contract_fp4_dual<4, 5>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
-    else contract_fp4<4, 5>(load_words, ops, v.W0, v.W1, acc0, acc1);
+      contract_fp4_dual<2, 5, 2, true>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
+    else contract_fp4<2, 5, 2, true>(load_words, ops, v.W0, v.W1, acc0, acc1);
   } else {
     zero_acc(acc0, acc1);
     auto load_words = [&](uint32_t w, u64 (&x)[5]) {
@@ -812,7 +913,7 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
           }
           const uint32_t j = jv[fb];
           const bool active = a < b && j < n;
-          float fs = mc.c;
+          uint32_t fs = mc.q0;  // fixed point: the LDS table holds Fq
           if (active) {
             constexpr int kGroup = 3;
             uint32_t o0[kGroup], o1[kGroup];
@@ -821,20 +922,21 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
               o0[nc] = p & 0xFFFFu;
               o1[nc] = p >> 16;
               if (++nc == kGroup) {
-                float f0[kGroup], f1[kGroup], f01[kGroup];
+                uint32_t f0[kGroup], f1[kGroup], f01[kGroup];
 #pragma unroll
                 for (int x = 0; x < kGroup; ++x) {
-                  f0[x] = *(const FI_LDS float *)(Fb + o0[x]);
-                  f1[x] = *(const FI_LDS float *)(Fb + o1[x]);
-                  f01[x] = *(const FI_LDS float *)(Fb + o0[x] + o1[x]);
+                  f0[x] = *(const FI_LDS uint32_t *)(Fb + o0[x]);
+                  f1[x] = *(const FI_LDS uint32_t *)(Fb + o1[x]);
+                  f01[x] = *(const FI_LDS uint32_t *)(Fb + o0[x] + o1[x]);
                 }
 #pragma unroll
-                for (int x = 0; x < kGroup; ++x) fs += (f0[x] + f1[x]) - f01[x];
+                for (int x = 0; x < kGroup; ++x) fs += f0[x] + f1[x] - f01[x];
+                pin_sum(fs);
                 nc = 0;
               }
             });
           }
-          if (emit_with(v, active, fs * mc.inv_m,
+          if (emit_with(v, active, mi_fixed(fs, mc),
                         [&] { return lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1); }, thr,
                         lane) >= kRefreshAppends)
             thr = current_threshold_lanes(v);
@@ -880,7 +982,8 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
 #pragma unroll
             for (int c = 0; c < 2; ++c) Ma[x][c] = marg[(size_t)aa * 6 + 2 * x + c];
           const Order3Parts parts = {D, ab, aj, bj, Ma, Mb, Mj, mcls};
-          float fs = mc.c;
+          using E = decltype(+F[0]);  // the table's element type, without its address space
+          E fs = mi_start<E>(mc);
           if (active) {
             // the cells in groups of 3, each group's 9 table reads issued
             // together rather than one cell at a time
@@ -894,7 +997,7 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
               c0[nc] = LDS_F ? n0 : min(n0, mcls[0]);
               c1[nc] = LDS_F ? n1 : min(n1, mcls[1]);
               if (++nc == kGroup) {
-                float f0[kGroup], f1[kGroup], f01[kGroup];
+                E f0[kGroup], f1[kGroup], f01[kGroup];
 #pragma unroll
                 for (int x = 0; x < kGroup; ++x) {
                   f0[x] = F[c0[x]];
@@ -903,12 +1006,13 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
                 }
 #pragma unroll
                 for (int x = 0; x < kGroup; ++x) fs += (f0[x] + f1[x]) - f01[x];
+                if constexpr (std::is_same_v<E, uint32_t>) pin_sum(fs);
                 nc = 0;
               }
             });
           }
           const uint32_t pre[2] = {aa, b};
-          if (emit_with(v, active, fs * mc.inv_m,
+          if (emit_with(v, active, mi_finish(fs, mc),
                         [&] { return lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1); }, thr,
                         lane) >= kRefreshAppends)
             thr = current_threshold_lanes(v);
@@ -922,7 +1026,7 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
       return;
     }
   }
-  if constexpr (LDS_F) score(Fl);
+  if constexpr (LDS_F) score(lds_table<3, FMT>(Fl));
   else score(as_global(v.Fh));
 }
 
@@ -1456,6 +1560,7 @@ __device__ __forceinline__ void sub_contract(const JV &v, uint32_t b, u64 q0, u6
   const uint32_t r = lane & 31, h = lane >> 5;
   const FI_GLOBAL char *Bvc = reinterpret_cast<const FI_GLOBAL char *>(as_global(v.Bv));
   const size_t word_bytes = (size_t)v.n_pad * 16;  // Bv bytes of one word
+  const uint32_t hw = h * (uint32_t)word_bytes;     // words in pairs: lane half h reads word w + h
   const uint32_t k = r >> 3, s = (r >> 2) & 1, i = r & 3;
   uint32_t gv[NP];  // genotype row of each lane-varying prefix variant
   if constexpr (K == 4) {
@@ -1482,36 +1587,42 @@ __device__ __forceinline__ void sub_contract(const JV &v, uint32_t b, u64 q0, u6
       else colex_triple(q, pv[0], pv[1], pv[2]);
     }
 #pragma unroll
-    for (int t = 0; t < NP; ++t) oa[fa][t] = pv[t] * 16 + gv[t] * 8 + 4 * h;
+    for (int t = 0; t < NP; ++t) oa[fa][t] = pv[t] * 16 + gv[t] * 8 + hw;
   }
-  const uint32_t ob = b * 16 + (i & 1) * 8 + 4 * h, ol = j0 * 16 + r * 8 + 4 * h;
-  auto load_words = [&](uint32_t w, uint32_t (&xw)[kRaw]) {
+  const uint32_t ob = b * 16 + (i & 1) * 8 + hw, ol = j0 * 16 + r * 8 + hw;
+  // the last step of an odd word count: lanes of half 1 read word w itself,
+  // with the row of b replaced by the zero row of padding variant n, so that
+  // their A operands vanish
+  const uint32_t obt = h ? n * 16 : ob;
+  auto load_words = [&](uint32_t w, auto tail, u64 (&xw)[kRaw]) {
     const FI_GLOBAL char *sw = Bvc + (size_t)w * word_bytes;
+    constexpr bool kTail = decltype(tail)::value;
+    const uint32_t d = kTail ? hw : 0u;
 #pragma unroll
     for (int fa = 0; fa < FA; ++fa)
 #pragma unroll
-      for (int t = 0; t < NP; ++t) xw[fa * NP + t] = ld32(sw, oa[fa][t]);
-    xw[FA * NP] = ld32(sw, ob);
-    xw[FA * NP + 1] = ld32(sw, ol);
-    xw[FA * NP + 2] = ld32(sw, ol + 256);
+      for (int t = 0; t < NP; ++t) xw[fa * NP + t] = ld64(sw, oa[fa][t] - d);
+    xw[FA * NP] = ld64(sw, kTail ? obt : ob);
+    xw[FA * NP + 1] = ld64(sw, ol - d);
+    xw[FA * NP + 2] = ld64(sw, ol + 256 - d);
   };
   // A row = AND of the rows of the prefix variants (the row of b last)
-  const auto ops = [](const uint32_t (&xw)[kRaw], v8i (&E)[FA + 2]) {
+  const auto ops = [](const u64 (&xw)[kRaw], int half, v8i (&E)[FA + 2]) {
+    const int sh = 32 * half;
 #pragma unroll
     for (int fa = 0; fa < FA; ++fa) {
-      uint32_t a = xw[fa * NP];
+      uint32_t a = (uint32_t)(xw[fa * NP] >> sh);
 #pragma unroll
-      for (int t = 1; t < NP; ++t) a &= xw[fa * NP + t];
-      E[fa] = expand32_fp4_and(a, xw[FA * NP]);
+      for (int t = 1; t < NP; ++t) a &= (uint32_t)(xw[fa * NP + t] >> sh);
+      E[fa] = expand32_fp4_and(a, (uint32_t)(xw[FA * NP] >> sh));
     }
-    E[FA] = expand32_fp4_b(xw[FA * NP + 1]);
-    E[FA + 1] = expand32_fp4_b(xw[FA * NP + 2]);
+    E[FA] = expand32_fp4_b((uint32_t)(xw[FA * NP + 1] >> sh));
+    E[FA + 1] = expand32_fp4_b((uint32_t)(xw[FA * NP + 2] >> sh));
   };
   if constexpr (DUAL)
-    contract_fp4_dual<4, kRaw, decltype(load_words) &, decltype(ops) &, FA>(load_words, ops, v.W0, v.W1,
-                                                                             bit_len(v.m0), Q);
+    contract_fp4_dual<2, kRaw, FA, true>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
   else
-    contract_fp4_narrow<4, kRaw, decltype(load_words) &, decltype(ops) &, FA>(load_words, ops, v.W0, v.W1, Q);
+    contract_fp4_narrow<2, kRaw, FA, true>(load_words, ops, v.W0, v.W1, Q);
 }
 
 // One wave of order 4: prefixes (x, y, b), (x, y) of colex indices q0 + [0, 8),
@@ -1534,12 +1645,13 @@ __device__ __forceinline__ void wave_t4(const Globals &g, const JV &v, uint32_t 
   const FI_GLOBAL v4u *PT4 = reinterpret_cast<const FI_GLOBAL v4u *>(as_global(v.pairs4));
   const FI_GLOBAL uint32_t *marg = as_global(v.marg);
   const FI_LDS char *Fb = (const FI_LDS char *)Fl;
+  // one cell's term of the fixed-point sum (the LDS table holds Fq)
   auto term = [&](uint32_t p) {
     const uint32_t o0 = p & 0xFFFFu, o1 = p >> 16;
-    const float f0 = *(const FI_LDS float *)(Fb + o0);
-    const float f1 = *(const FI_LDS float *)(Fb + o1);
-    const float f01 = *(const FI_LDS float *)(Fb + o0 + o1);
-    return (f0 + f1) - f01;
+    const uint32_t f0 = *(const FI_LDS uint32_t *)(Fb + o0);
+    const uint32_t f1 = *(const FI_LDS uint32_t *)(Fb + o1);
+    const uint32_t f01 = *(const FI_LDS uint32_t *)(Fb + o0 + o1);
+    return f0 + f1 - f01;
   };
   auto marg4 = [&](uint32_t var, int g4) { return pack_x4(marg[(size_t)var * 6 + 2 * g4], marg[(size_t)var * 6 + 2 * g4 + 1]); };
   // the lane's two last variants j (fb = 0, 1) and their class counts
@@ -1627,15 +1739,16 @@ __device__ __forceinline__ void wave_t4(const Globals &g, const JV &v, uint32_t 
       }
       const uint32_t j = jv[fb];
       const bool active = valid && j < n;
-      float fs = mc.c;
+      uint32_t fs = mc.q0;
       if (active)
         walk3_zip_packed<3>(t3, [&](const uint32_t (&cell)[3]) {
           fs += term(cell[1]);
           fs += term(cell[2]);
           fs += term(cell[0] - cell[1] - cell[2]);
+          pin_sum(fs);
         });
       const uint32_t pre[3] = {x, y, b};
-      if (emit_with(v, active, fs * mc.inv_m,
+      if (emit_with(v, active, mi_fixed(fs, mc),
                     [&] { return lex_rank_prefix(g, n, 4, pre) + (u64)(j - b - 1); }, thr,
                     lane) >= kRefreshAppends)
         thr = current_threshold_lanes(v);
@@ -1666,12 +1779,13 @@ __device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t 
   const FI_GLOBAL v4u *PT4 = reinterpret_cast<const FI_GLOBAL v4u *>(as_global(v.pairs4));
   const FI_GLOBAL uint32_t *marg = as_global(v.marg);
   const FI_LDS char *Fb = (const FI_LDS char *)Fl;
+  // one cell's term of the fixed-point sum (the LDS table holds Fq)
   auto term = [&](uint32_t p) {
     const uint32_t o0 = p & 0xFFFFu, o1 = p >> 16;
-    const float f0 = *(const FI_LDS float *)(Fb + o0);
-    const float f1 = *(const FI_LDS float *)(Fb + o1);
-    const float f01 = *(const FI_LDS float *)(Fb + o0 + o1);
-    return (f0 + f1) - f01;
+    const uint32_t f0 = *(const FI_LDS uint32_t *)(Fb + o0);
+    const uint32_t f1 = *(const FI_LDS uint32_t *)(Fb + o1);
+    const uint32_t f01 = *(const FI_LDS uint32_t *)(Fb + o0 + o1);
+    return f0 + f1 - f01;
   };
   auto marg4 = [&](uint32_t var, uint32_t g4) {
     return pack_x4(marg[(size_t)var * 6 + 2 * g4], marg[(size_t)var * 6 + 2 * g4 + 1]);
@@ -1743,9 +1857,13 @@ __device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t 
     const uint32_t j = j0 + 16 * gl + (r >> 1);
     const uint32_t J = j < n ? j : n - 1;
     const bool active = valid && j < n;
-    float fs = mc.c;
+    uint32_t fs = mc.q0;
     auto score = [&](const Tab3P &t) {
-      if (active) walk(t, [&](uint32_t p) { fs += term(p); });
+      if (active)
+        walk(t, [&](uint32_t p) {
+          fs += term(p);
+          pin_sum(fs);
+        });
     };
     // X(gw, sj): the inputs of the order-3 table over (x, y, b) with w at
     // genotype gw and j at sj, 2 meaning the variant marginalised (left out);
@@ -1882,7 +2000,7 @@ __device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t 
       score(t);
     }
     const uint32_t pre[4] = {w, x, y, b};
-    if (emit_with(v, active, fs * mc.inv_m,
+    if (emit_with(v, active, mi_fixed(fs, mc),
                   [&] { return lex_rank_prefix(g, n, 5, pre) + (u64)(j - b - 1); }, thr,
                   lane) >= kRefreshAppends)
       thr = current_threshold_lanes(v);
@@ -1947,8 +2065,9 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_sub_kernel(Globals g)
       // wave has finished the previous tile: the barriers above)
       const uint32_t jx = (uint32_t)(jd - as_const(g.jobs));
       if (jx != f_job) {
-        const FI_GLOBAL float *Fh = as_global(uni_ptr(jd->Fh));
-        for (uint32_t i = threadIdx.x; i <= v.m; i += blockDim.x) s_f[i] = Fh[i];
+        const FI_GLOBAL uint32_t *Fq = as_global(uni_ptr(jd->Fq));
+        FI_LDS uint32_t *q = (FI_LDS uint32_t *)s_f;
+        for (uint32_t i = threadIdx.x; i <= v.m; i += blockDim.x) q[i] = Fq[i];
         f_job = jx;
         __syncthreads();
       }
@@ -2135,8 +2254,14 @@ __global__ __launch_bounds__(kMfmaWaves * 64, FMT == kMfmaF4Dual ? 3 : 2) void m
       if (jx != f_job) {
         f_lds = fits;
         if (f_lds) {
-          const FI_GLOBAL float *Fh = as_global(uni_ptr(jd->Fh));
-          for (uint32_t i = threadIdx.x; i <= v.m; i += blockDim.x) s_f[i] = Fh[i];
+          if constexpr (lds_fixed<ORDER, FMT>()) {
+            const FI_GLOBAL uint32_t *Fq = as_global(uni_ptr(jd->Fq));
+            FI_LDS uint32_t *q = (FI_LDS uint32_t *)s_f;
+            for (uint32_t i = threadIdx.x; i <= v.m; i += blockDim.x) q[i] = Fq[i];
+          } else {
+            const FI_GLOBAL float *Fh = as_global(uni_ptr(jd->Fh));
+            for (uint32_t i = threadIdx.x; i <= v.m; i += blockDim.x) s_f[i] = Fh[i];
+          }
         }
         f_job = jx;
         __syncthreads();

@@ -52,6 +52,12 @@ CASES = [
     # FP4, both classes in one accumulator (bitlen(m0) + bitlen(m1) <= 24)
     ("fp4-dual", 2, 260, 1000, 0.5, K.KERNEL_MFMA_FP4),
     ("fp4-dual", 3, 70, 700, 0.5, K.KERNEL_MFMA_FP4),
+    # words in pairs: one word per class (the odd step alone), and an even
+    # class beside an odd one
+    ("fp4-dual", 2, 90, 120, 0.5, K.KERNEL_MFMA_FP4),
+    ("fp4-dual", 3, 45, 120, 0.5, K.KERNEL_MFMA_FP4),
+    ("fp4-dual", 2, 100, 330, 0.4, K.KERNEL_MFMA_FP4),
+    ("fp4-dual", 3, 55, 330, 0.4, K.KERNEL_MFMA_FP4),
     # orders 4 and 5, every prefix row on the matrix cores
     ("rows-dual", 4, 30, 400, 0.5, K.KERNEL_MFMA_FP4),
     ("rows-two-acc", 4, 20, 9000, 0.5, K.KERNEL_MFMA_FP4),
