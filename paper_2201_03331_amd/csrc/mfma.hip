@@ -260,104 +260,59 @@ __device__ __forceinline__ v8i fp4_operand(uint4 q) {
 }
 __device__ __forceinline__ v8i expand32_fp4_b(uint32_t b) { return fp4_operand(fp4_b_operand(b)); }
 
-// The operands of a word from the lane's four 32-bit half words O[4] (A
-// fragments 0, 1, B fragments 0, 1), expanded in registers
-// (FA A fragments: O[FA + 2], the A fragments first)
-template <int kRaw, typename Prep, int FA = 2>
-__device__ __forceinline__ auto expanded_ops(Prep prep) {
-  return [prep](const uint32_t (&x)[kRaw], v8i (&E)[FA + 2]) {
-    uint32_t O[FA + 2];
-    prep(x, O);
-#pragma unroll
-    for (int f = 0; f < FA + 2; ++f) E[f] = f < FA ? expand32_fp4_a(O[f]) : expand32_fp4_b(O[f]);
-  };
-}
-
-// Counts of one class with FP4 operands: words [wbeg, wend).  Lane l feeds
-// row l mod 32 of every fragment and the 32 samples of 32-bit half l / 32 of
-// each word; the instruction pairs the same lane half and nibble of both
-// operands.  load_words(w, x) fills x with the kRaw registers the lane loads
-// for word w; ops(x, E) makes the four operands (A fragments 0, 1, B
-// fragments 0, 1) from them when the word is used.
-//
-// X2: the words two at a time.  Lane half h loads word w + h whole (one
-// 64-bit load per row instead of two 32-bit ones), and the two instructions
-// of a step take the low, then the high 32-bit halves: each covers 32 samples
-// of word w (lanes 0-31) and 32 of word w + 1 (lanes 32-63), the same samples
-// for both operands.  load_words(w, tail, x) fills the kRaw 64-bit words
-// (tail: std::true_type for the last step of an odd count, whose lanes of
-// half 1 must load operands with vanishing products, else std::false_type);
-// ops(x, half, E) expands the given 32-bit half.
-template <int kDepth, int kRaw, int FA = 2, bool X2 = false, typename Load, typename Ops>
+// Counts of one class with FP4 operands: words [wbeg, wend), two at a time.
+// Lane l feeds row l mod 32 of every fragment; lane half h = l / 32 loads word
+// w + h whole (one 64-bit load per row), and the two instructions of a step
+// take the low, then the high 32-bit halves: each covers 32 samples of word w
+// (lanes 0-31) and 32 of word w + 1 (lanes 32-63), the same samples for both
+// operands, since the instruction pairs the same lane half and nibble of A
+// and B.  load_words(w, tail, x) fills the kRaw 64-bit words of the step at
+// word w (tail: std::true_type for the last step of an odd count, whose lanes
+// of half 1 must load operands with vanishing products, else
+// std::false_type); ops(x, half, E) expands the given 32-bit half into the A
+// fragments (FA of them) and the two B fragments.  The next kDepth steps'
+// loads stay in flight in a register ring.
+template <int kDepth, int kRaw, int FA = 2, typename Load, typename Ops>
 __device__ __forceinline__ void mfma_class_fp4(Load &&load_words, Ops &&ops, uint32_t wbeg,
                                                uint32_t wend, v16f (&acc)[FA][2],
                                                int scale_a = kScaleOne) {
   if (wbeg >= wend) return;
-  if constexpr (X2) {
-    auto step = [&](const u64 (&x)[kRaw]) {
+  auto step = [&](const u64 (&x)[kRaw]) {
 #pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        v8i E[FA + 2];
-        ops(x, half, E);
-#pragma unroll
-        for (int i = 0; i < FA; ++i)
-#pragma unroll
-          for (int y = 0; y < 2; ++y)
-            acc[i][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                E[i], E[FA + y], acc[i][y], kFmtFp4, kFmtFp4, 0, scale_a, 0, kScaleOne);
-      }
-    };
-    const uint32_t nfull = (wend - wbeg) / 2;  // steps of two words
-    if (nfull > 0) {
-      const uint32_t plast = nfull - 1;
-      u64 X[kDepth][kRaw];
-#pragma unroll
-      for (int u = 0; u < kDepth; ++u) load_words(wbeg + 2 * min((uint32_t)u, plast), std::false_type{}, X[u]);
-      uint32_t p = 0;
-      for (; p + kDepth <= nfull; p += kDepth) {
-#pragma unroll
-        for (int u = 0; u < kDepth; ++u) {
-          step(X[u]);
-          load_words(wbeg + 2 * min(p + u + kDepth, plast), std::false_type{}, X[u]);
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kDepth - 1; ++u)
-        if (p + u < nfull) step(X[u]);
-    }
-    if ((wend - wbeg) & 1) {
-      u64 x[kRaw];
-      load_words(wend - 1, std::true_type{}, x);
-      step(x);
-    }
-  } else {
-    const uint32_t wlast = wend - 1;
-    uint32_t X[kDepth][kRaw];
-#pragma unroll
-    for (int u = 0; u < kDepth; ++u) load_words(min(wbeg + u, wlast), X[u]);
-    auto step = [&](int slot) {
+    for (int half = 0; half < 2; ++half) {
       v8i E[FA + 2];
-      ops(X[slot], E);
+      ops(x, half, E);
 #pragma unroll
-      for (int x = 0; x < FA; ++x)
+      for (int i = 0; i < FA; ++i)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-              E[x], E[FA + y], acc[x][y], kFmtFp4, kFmtFp4, 0, scale_a, 0, kScaleOne);
-    };
-    uint32_t w = wbeg;
-    for (; w + kDepth <= wend; w += kDepth) {
+          acc[i][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+              E[i], E[FA + y], acc[i][y], kFmtFp4, kFmtFp4, 0, scale_a, 0, kScaleOne);
+    }
+  };
+  const uint32_t nfull = (wend - wbeg) / 2;  // steps of two words
+  if (nfull > 0) {
+    const uint32_t plast = nfull - 1;
+    u64 X[kDepth][kRaw];
+#pragma unroll
+    for (int u = 0; u < kDepth; ++u) load_words(wbeg + 2 * min((uint32_t)u, plast), std::false_type{}, X[u]);
+    uint32_t p = 0;
+    for (; p + kDepth <= nfull; p += kDepth) {
 #pragma unroll
       for (int u = 0; u < kDepth; ++u) {
-        step(u);
-        load_words(min(w + u + kDepth, wlast), X[u]);
+        step(X[u]);
+        load_words(wbeg + 2 * min(p + u + kDepth, plast), std::false_type{}, X[u]);
         __builtin_amdgcn_sched_barrier(0);
       }
     }
 #pragma unroll
     for (int u = 0; u < kDepth - 1; ++u)
-      if (w + u < wend) step(u);
+      if (p + u < nfull) step(X[u]);
+  }
+  if ((wend - wbeg) & 1) {
+    u64 x[kRaw];
+    load_words(wend - 1, std::true_type{}, x);
+    step(x);
   }
 }
 
@@ -372,7 +327,7 @@ __device__ __forceinline__ void zero_acc(v16i (&acc0)[2][2], v16i (&acc1)[2][2])
 
 // Both classes with FP4 operands (class 0: words [0, W0), class 1: the next
 // W1), counts returned as integers: the FP32 sums are integers below 2^24
-template <int kDepth, int kRaw, int FA = 2, bool X2 = false, typename Load, typename Ops>
+template <int kDepth, int kRaw, int FA = 2, typename Load, typename Ops>
 __device__ __forceinline__ void contract_fp4(Load &&load_words, Ops &&ops, uint32_t W0, uint32_t W1,
                                              v16i (&acc0)[2][2], v16i (&acc1)[2][2]) {
   v16f f0[2][2], f1[2][2];
@@ -382,8 +337,8 @@ __device__ __forceinline__ void contract_fp4(Load &&load_words, Ops &&ops, uint3
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) f0[x][y][e] = f1[x][y][e] = 0.f;
-  mfma_class_fp4<kDepth, kRaw, 2, X2>(load_words, ops, 0, W0, f0);
-  mfma_class_fp4<kDepth, kRaw, 2, X2>(load_words, ops, W0, W0 + W1, f1);
+  mfma_class_fp4<kDepth, kRaw, 2>(load_words, ops, 0, W0, f0);
+  mfma_class_fp4<kDepth, kRaw, 2>(load_words, ops, W0, W0 + W1, f1);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -399,7 +354,7 @@ __device__ __forceinline__ void contract_fp4(Load &&load_words, Ops &&ops, uint3
 // bits.  Class 0's counts wait as 16-bit pairs while class 1 accumulates;
 // the result Q holds class 0 in the low and class 1 in the high 16 bits of
 // each output element (register e of block (x, y)).
-template <int kDepth, int kRaw, int FA = 2, bool X2 = false, typename Load, typename Ops>
+template <int kDepth, int kRaw, int FA = 2, typename Load, typename Ops>
 __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Ops &&ops, uint32_t W0,
                                                     uint32_t W1, uint32_t (&Q)[FA][2][16]) {
   v16f f[FA][2];
@@ -409,7 +364,7 @@ __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Ops &&ops
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) f[x][y][e] = 0.f;
-  mfma_class_fp4<kDepth, kRaw, FA, X2>(load_words, ops, 0, W0, f);
+  mfma_class_fp4<kDepth, kRaw, FA>(load_words, ops, 0, W0, f);
   uint32_t P0[FA][2][8];
 #pragma unroll
   for (int x = 0; x < FA; ++x)
@@ -420,7 +375,7 @@ __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Ops &&ops
         P0[x][y][i] = (uint32_t)f[x][y][2 * i] | ((uint32_t)f[x][y][2 * i + 1] << 16);
         f[x][y][2 * i] = f[x][y][2 * i + 1] = 0.f;
       }
-  mfma_class_fp4<kDepth, kRaw, FA, X2>(load_words, ops, W0, W0 + W1, f);
+  mfma_class_fp4<kDepth, kRaw, FA>(load_words, ops, W0, W0 + W1, f);
 #pragma unroll
   for (int x = 0; x < FA; ++x)
 #pragma unroll
@@ -434,7 +389,7 @@ __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Ops &&ops
 // scaled by 2^s (s = bit length of m0, given by the caller), so the single
 // FP32 accumulator holds c0 + 2^s c1 < 2^24, an exact integer; Q as for the
 // narrow kernels.
-template <int kDepth, int kRaw, int FA = 2, bool X2 = false, typename Load, typename Ops>
+template <int kDepth, int kRaw, int FA = 2, typename Load, typename Ops>
 __device__ __forceinline__ void contract_fp4_dual(Load &&load_words, Ops &&ops, uint32_t W0,
                                                   uint32_t W1, uint32_t s,
                                                   uint32_t (&Q)[FA][2][16]) {
@@ -445,8 +400,8 @@ __device__ __forceinline__ void contract_fp4_dual(Load &&load_words, Ops &&ops, 
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) f[x][y][e] = 0.f;
-  mfma_class_fp4<kDepth, kRaw, FA, X2>(load_words, ops, 0, W0, f);
-  mfma_class_fp4<kDepth, kRaw, FA, X2>(load_words, ops, W0, W0 + W1, f, kScaleOne + (int)s);
+  mfma_class_fp4<kDepth, kRaw, FA>(load_words, ops, 0, W0, f);
+  mfma_class_fp4<kDepth, kRaw, FA>(load_words, ops, W0, W0 + W1, f, kScaleOne + (int)s);
   const uint32_t low = (1u << s) - 1;
 #pragma unroll
   for (int x = 0; x < FA; ++x)
@@ -554,10 +509,10 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
       E[2] = expand32_fp4_b((uint32_t)(x[2] >> sh));
       E[3] = expand32_fp4_b((uint32_t)(x[3] >> sh));
     };
-    if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<2, 4, 2, true>(load_words, ops, v.W0, v.W1, Q);
+    if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<2, 4>(load_words, ops, v.W0, v.W1, Q);
     else if constexpr (FMT == kMfmaF4Dual)
-      contract_fp4_dual<2, 4, 2, true>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
-    else contract_fp4<2, 4, 2, true>(load_words, ops, v.W0, v.W1, acc0, acc1);
+      contract_fp4_dual<2, 4>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
+    else contract_fp4<2, 4>(load_words, ops, v.W0, v.W1, acc0, acc1);
   } else {
     zero_acc(acc0, acc1);
     auto load_words = [&](uint32_t w, u64 (&x)[4]) {
@@ -794,10 +749,10 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
       E[2] = expand32_fp4_b((uint32_t)(x[2] >> sh));
       E[3] = expand32_fp4_b((uint32_t)(x[3] >> sh));
     };
-    if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<2, 5, 2, true>(load_words, ops, v.W0, v.W1, Q);
+    if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<2, 5>(load_words, ops, v.W0, v.W1, Q);
     else if constexpr (FMT == kMfmaF4Dual)
-      contract_fp4_dual<2, 5, 2, true>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
-    else contract_fp4<2, 5, 2, true>(load_words, ops, v.W0, v.W1, acc0, acc1);
+      contract_fp4_dual<2, 5>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
+    else contract_fp4<2, 5>(load_words, ops, v.W0, v.W1, acc0, acc1);
   } else {
     zero_acc(acc0, acc1);
     auto load_words = [&](uint32_t w, u64 (&x)[5]) {
@@ -1620,9 +1575,9 @@ __device__ __forceinline__ void sub_contract(const JV &v, uint32_t b, u64 q0, u6
     E[FA + 1] = expand32_fp4_b((uint32_t)(xw[FA * NP + 2] >> sh));
   };
   if constexpr (DUAL)
-    contract_fp4_dual<2, kRaw, FA, true>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
+    contract_fp4_dual<2, kRaw, FA>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
   else
-    contract_fp4_narrow<2, kRaw, FA, true>(load_words, ops, v.W0, v.W1, Q);
+    contract_fp4_narrow<2, kRaw, FA>(load_words, ops, v.W0, v.W1, Q);
 }
 
 // One wave of order 4: prefixes (x, y, b), (x, y) of colex indices q0 + [0, 8),
