@@ -209,6 +209,12 @@ __device__ __forceinline__ uint32_t ld32(const FI_GLOBAL char *base, uint32_t of
       __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, 0x7fffffff, kBufferWord3);
   return __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
 }
+// the same for 16 bytes
+__device__ __forceinline__ v4u ld128(const FI_GLOBAL char *base, uint32_t off) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, 0x7fffffff, kBufferWord3);
+  return __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+}
 // the same for a whole 64-bit word
 typedef uint32_t v2u32 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ u64 ld64(const FI_GLOBAL char *base, uint32_t off) {
@@ -690,17 +696,13 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
   const size_t word_stride = (size_t)v.n_pad * 2;
   const FI_GLOBAL u64 *Bv = as_global(v.Bv);
   const FI_GLOBAL u64 *Bs = as_global(v.Bs);
-  // A rows: lane r of fragment f is prefix a_first + 8 f + r / 4 with genotype
-  // rows g_a = (r >> 1) & 1, g_b = r & 1; prefixes a >= b count nothing: their
-  // lanes read the zero word that follows the three genotype words
-  const uint32_t ga = (r >> 1) & 1, gb = r & 1;
-  const FI_GLOBAL u64 *pb = Bs + (size_t)b * 4 * v.wcap + gb;
-  const FI_GLOBAL u64 *pa[2];
-#pragma unroll
-  for (int f = 0; f < 2; ++f) {
-    const uint32_t a = a_first + 8 * f + (r >> 2);
-    pa[f] = Bs + (size_t)min(a, b - 1) * 4 * v.wcap + (a < b ? ga : 3);
-  }
+  // A rows: lane r of fragment f is prefix a_first + r / 2 with its genotype
+  // row g_a = r & 1, AND-ed with row g_b = f of b (a fragment fixes g_b, so a
+  // lane's prefix row serves both fragments); prefixes a >= b count nothing:
+  // their lanes read a zero word
+  const uint32_t ga = r & 1, ar = a_first + (r >> 1);
+  const FI_GLOBAL u64 *pb = Bs + (size_t)b * 4 * v.wcap;
+  const FI_GLOBAL u64 *pa = Bs + (size_t)min(ar, b - 1) * 4 * v.wcap + (ar < b ? ga : 3);
   const FI_GLOBAL u64 *pj = Bv + (size_t)j0 * 2 + r;
   v16i acc0[2][2], acc1[2][2];  // int8, FP4: counts per class
   uint32_t Q[2][2][16];         // narrow FP4: both classes per register
@@ -714,40 +716,30 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
     const size_t word_bytes = (size_t)v.n_pad * 16;  // Bv bytes of one word
     // words in pairs: lane half h reads word w + h whole
     const uint32_t hw = h * (uint32_t)word_bytes;
-    uint32_t oa[2];
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      const uint32_t a = a_first + 8 * f + (r >> 2);
-      oa[f] = (a < b ? a : n) * 16 + ga * 8 + hw;
-    }
-    const uint32_t ob = b * 16 + gb * 8 + hw, ol = j0 * 16 + r * 8 + hw;
+    const uint32_t oa = (ar < b ? ar : n) * 16 + ga * 8 + hw;
+    const uint32_t ob = b * 16 + hw, ol = j0 * 16 + r * 8 + hw;
     // the last step of an odd word count: lanes of half 1 read word w itself,
-    // with the row of b replaced by the zero row of padding variant n, so that
-    // their A operands (a row AND the row of b) vanish
+    // with the rows of b replaced by the zero rows of padding variant n, so that
+    // their A operands (a row AND a row of b) vanish
     const uint32_t obt = h ? n * 16 : ob;
     auto load_words = [&](uint32_t w, auto tail, u64 (&x)[5]) {
       const FI_GLOBAL char *sw = Bvc + (size_t)w * word_bytes;
-      if constexpr (!decltype(tail)::value) {
-        x[0] = ld64(sw, oa[0]);
-        x[1] = ld64(sw, oa[1]);
-        x[2] = ld64(sw, ol);
-        x[3] = ld64(sw, ol + 256);
-        x[4] = ld64(sw, ob);
-      } else {
-        x[0] = ld64(sw, oa[0] - hw);
-        x[1] = ld64(sw, oa[1] - hw);
-        x[2] = ld64(sw, ol - hw);
-        x[3] = ld64(sw, ol + 256 - hw);
-        x[4] = ld64(sw, obt);
-      }
+      constexpr bool kTail = decltype(tail)::value;
+      const uint32_t d = kTail ? hw : 0u;
+      x[0] = ld64(sw, oa - d);
+      x[1] = ld64(sw, ol - d);
+      x[2] = ld64(sw, ol + 256 - d);
+      const v4u q = ld128(sw, kTail ? obt : ob);  // both rows of b
+      x[3] = (u64)q[0] | ((u64)q[1] << 32);
+      x[4] = (u64)q[2] | ((u64)q[3] << 32);
     };
-    // A row = row of a AND row of b
+    // A fragment f: row of a AND row f of b
     const auto ops = [](const u64 (&x)[5], int half, v8i (&E)[4]) {
       const int sh = 32 * half;
-      E[0] = expand32_fp4_and((uint32_t)(x[0] >> sh), (uint32_t)(x[4] >> sh));
-      E[1] = expand32_fp4_and((uint32_t)(x[1] >> sh), (uint32_t)(x[4] >> sh));
-      E[2] = expand32_fp4_b((uint32_t)(x[2] >> sh));
-      E[3] = expand32_fp4_b((uint32_t)(x[3] >> sh));
+      E[0] = expand32_fp4_and((uint32_t)(x[0] >> sh), (uint32_t)(x[3] >> sh));
+      E[1] = expand32_fp4_and((uint32_t)(x[0] >> sh), (uint32_t)(x[4] >> sh));
+      E[2] = expand32_fp4_b((uint32_t)(x[1] >> sh));
+      E[3] = expand32_fp4_b((uint32_t)(x[2] >> sh));
     };
     if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<2, 5>(load_words, ops, v.W0, v.W1, Q);
     else if constexpr (FMT == kMfmaF4Dual)
@@ -756,28 +748,28 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
   } else {
     zero_acc(acc0, acc1);
     auto load_words = [&](uint32_t w, u64 (&x)[5]) {
-      x[0] = pa[0][(size_t)w * 4];
-      x[1] = pa[1][(size_t)w * 4];
+      x[0] = pa[(size_t)w * 4];
       const size_t o = (size_t)w * word_stride;
-      x[2] = pj[o];
-      x[3] = pj[o + 32];
-      x[4] = pb[(size_t)w * 4];
+      x[1] = pj[o];
+      x[2] = pj[o + 32];
+      x[3] = pb[(size_t)w * 4];
+      x[4] = pb[(size_t)w * 4 + 1];
     };
     auto prep = [](const u64 (&x)[5], u64 (&o)[4]) {
-      o[0] = x[0] & x[4];
-      o[1] = x[1] & x[4];
-      o[2] = x[2];
-      o[3] = x[3];
+      o[0] = x[0] & x[3];
+      o[1] = x[0] & x[4];
+      o[2] = x[1];
+      o[3] = x[2];
     };
     mfma_class<3, 5>(load_words, prep, 0, v.W0, h, lut, acc0);
     mfma_class<3, 5>(load_words, prep, v.W0, v.W0 + v.W1, h, lut, acc1);
   }
 
   // Output block (f, fb): lane l holds column l mod 32 (last variant j0 + 16 fb
-  // + (l mod 32) / 2, genotype l mod 2); register e holds row 8 (e / 4) + 4 h +
-  // e mod 4, i.e. prefix a_first + 8 f + 2 (e / 4) + h with (g_a, g_b) = e mod 4
-  // in binary.  Lanes l and l ^ 1 hold the two genotypes of the same j; the
-  // lane of genotype bit gl scores the prefixes with e / 4 in {2 gl, 2 gl + 1}
+  // + (l mod 32) / 2, genotype l mod 2); register e = 4 q + 2 s + g_a holds row
+  // 8 q + 4 h + 2 s + g_a, i.e. prefix a_first + 4 q + 2 h + s at genotypes g_a
+  // and g_b = f.  Lanes l and l ^ 1 hold the two genotypes of the same j; the
+  // lane of genotype bit gl scores the prefixes with q in {2 gl, 2 gl + 1}
   // after taking the partner's counts for the other genotype of j.
   const uint32_t gl = lane & 1;
   const MiConst mc = mi_const(v);
@@ -811,10 +803,10 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
     jv[fb] = j0 + 16 * fb + (r >> 1);
     jj[fb] = jv[fb] < n ? jv[fb] : n - 1;
   }
-  // Each lane scores 4 prefixes a (e / 4 = 2 gl + t of blocks f = 0, 1) with
-  // its 2 last variants; the prefix's (a, b) pair table and class counts are
-  // read once for both, the (a, j) pair table from the same table row.
-  auto prefix_of = [&](int f, int t) { return a_first + 8 * f + 2 * (2 * gl + t) + h; };
+  // Each lane scores 4 prefixes a (q = 2 gl + t, s = 0, 1) with its 2 last
+  // variants; the prefix's (a, b) pair table and class counts are read once
+  // for both, the (a, j) pair table from the same table row.
+  auto prefix_of = [&](int s, int t) { return a_first + 4 * (2 * gl + t) + 2 * h + s; };
   auto score_packed = [&]() {
     const FI_GLOBAL v4u *PT4 = reinterpret_cast<const FI_GLOBAL v4u *>(as_global(v.pairs4));
     uint32_t Mj4[2][2], bj4[2][2][2];
@@ -831,10 +823,10 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
     }
     const FI_LDS char *Fb = (const FI_LDS char *)Fl;
 #pragma unroll
-    for (int f = 0; f < 2; ++f) {
+    for (int s = 0; s < 2; ++s) {
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        const uint32_t a = prefix_of(f, t);
+        const uint32_t a = prefix_of(s, t);
         const uint32_t aa = a < b ? a : b - 1;
         const FI_GLOBAL v4u *row = PT4 + (size_t)aa * v.n_pad;
         uint32_t ab4[2][2], Ma4[2];
@@ -852,12 +844,14 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
         for (int fb = 0; fb < 2; ++fb) {
           uint32_t D4[2][2][2];  // [g_a][g_b][g_j], packed x 4
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            uint32_t o[2];
-            partner_packed(Q, f, fb, 4 * t + i, 4 * (2 + t) + i, gl, o);
-            D4[i >> 1][i & 1][0] = o[0] << 2;
-            D4[i >> 1][i & 1][1] = o[1] << 2;
-          }
+          for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+              uint32_t o[2];
+              partner_packed(Q, f, fb, 4 * t + 2 * s + g, 4 * (2 + t) + 2 * s + g, gl, o);
+              D4[g][f][0] = o[0] << 2;
+              D4[g][f][1] = o[1] << 2;
+            }
           uint32_t aj4[2][2];
           {
             const v4u q = row[jj[fb]];
@@ -911,21 +905,23 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
         for (int c = 0; c < 2; ++c) Mj[x][c] = marg[(size_t)jj[fb] * 6 + 2 * x + c];
       load_pair(PT + ((size_t)b * v.n_pad + jj[fb]) * 8, bj);
 #pragma unroll
-      for (int f = 0; f < 2; ++f) {
+      for (int s = 0; s < 2; ++s) {
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          const uint32_t a = prefix_of(f, t);
+          const uint32_t a = prefix_of(s, t);
           uint32_t D[2][2][2][2];  // [class][g_a][g_b][g_j]
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            uint32_t o[2][2];
-            partner_counts<FMT>(acc0, acc1, Q, f, fb, 4 * t + i, 4 * (2 + t) + i, gl, o);
+          for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              D[c][i >> 1][i & 1][0] = o[c][0];
-              D[c][i >> 1][i & 1][1] = o[c][1];
+            for (int g = 0; g < 2; ++g) {
+              uint32_t o[2][2];
+              partner_counts<FMT>(acc0, acc1, Q, f, fb, 4 * t + 2 * s + g, 4 * (2 + t) + 2 * s + g, gl, o);
+#pragma unroll
+              for (int c = 0; c < 2; ++c) {
+                D[c][g][f][0] = o[c][0];
+                D[c][g][f][1] = o[c][1];
+              }
             }
-          }
           const uint32_t j = jv[fb];
           const bool active = a < b && j < n;
           const uint32_t aa = a < b ? a : b - 1;
@@ -2050,7 +2046,9 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void mfma_sub_kernel(Globals g)
 // [g_c][g_j]).  Grid: x = group of 16 pairs (a, b) below c in
 // colex order, y = c - 2, z = job; the workgroup walks the blocks of 64 last
 // variants (the order-4 kernel's tiles, counts stored instead of scored).
-__global__ __launch_bounds__(kMfmaWaves * 64) void quads_kernel(Globals g) {
+// (2 waves per SIMD: both contraction forms in one kernel would otherwise
+// take more than 256 registers and run one wave per SIMD)
+__global__ __launch_bounds__(kMfmaWaves * 64, 2) void quads_kernel(Globals g) {
   const JobDesc *jd = g.jobs + blockIdx.z;
   JV v = load_view(jd);
   v4u *QT = reinterpret_cast<v4u *>(uni_ptr(as_const(jd)->quads4));
