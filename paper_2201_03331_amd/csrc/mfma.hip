@@ -77,7 +77,7 @@ constexpr int kMfmaF4Dual = 3;
 // workgroups share a compute unit's 160 KB, 80 KB each with their static
 // LDS: up to 12,280 entries next to the 32 KB byte table with int8 operands,
 // 20,448 with FP4 operands (every job of a narrow launch has at most 20,447
-// samples); the dual kernels run 3 workgroups per compute unit, 8,192
+// samples); the dual kernels run 3 or 4 workgroups per compute unit, 8,192
 // entries each (jobs of at most 8,191 samples).
 __host__ __device__ constexpr uint32_t mfma_f_entries(int fmt) {
   return fmt == kMfmaI8 ? 12280u : fmt == kMfmaF4Dual ? 8192u : 20448u;
@@ -469,6 +469,21 @@ __device__ __forceinline__ void partner_counts(const v16i (&acc0)[2][2], const v
   }
 }
 
+// Counts of both classes of output register e of block (x, y), the lane's own
+// column: from the packed registers (narrow, dual) or the per-class ones
+template <int FMT>
+__device__ __forceinline__ void own_counts(const v16i (&acc0)[2][2], const v16i (&acc1)[2][2],
+                                           const uint32_t (&Q)[2][2][16], int x, int y, int e,
+                                           uint32_t (&o)[2]) {
+  if constexpr (FMT == kMfmaF4Narrow || FMT == kMfmaF4Dual) {
+    o[0] = Q[x][y][e] & 0xFFFFu;
+    o[1] = Q[x][y][e] >> 16;
+  } else {
+    o[0] = (uint32_t)acc0[x][y][e];
+    o[1] = (uint32_t)acc1[x][y][e];
+  }
+}
+
 // One wave: pairs (a0 + [0, 32)) x (j0 + [0, 32)).
 template <int FMT, bool LDS_F>
 __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0, uint32_t lane,
@@ -703,7 +718,8 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
   const uint32_t ga = r & 1, ar = a_first + (r >> 1);
   const FI_GLOBAL u64 *pb = Bs + (size_t)b * 4 * v.wcap;
   const FI_GLOBAL u64 *pa = Bs + (size_t)min(ar, b - 1) * 4 * v.wcap + (ar < b ? ga : 3);
-  const FI_GLOBAL u64 *pj = Bv + (size_t)j0 * 2 + r;
+  // B rows: lane r of fragment f is last variant j0 + r at genotype g_j = f
+  const FI_GLOBAL u64 *pj = Bv + (size_t)(j0 + r) * 2;
   v16i acc0[2][2], acc1[2][2];  // int8, FP4: counts per class
   uint32_t Q[2][2][16];         // narrow FP4: both classes per register
   if constexpr (FMT != kMfmaI8) {
@@ -717,7 +733,7 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
     // words in pairs: lane half h reads word w + h whole
     const uint32_t hw = h * (uint32_t)word_bytes;
     const uint32_t oa = (ar < b ? ar : n) * 16 + ga * 8 + hw;
-    const uint32_t ob = b * 16 + hw, ol = j0 * 16 + r * 8 + hw;
+    const uint32_t ob = b * 16 + hw, ol = (j0 + r) * 16 + hw;
     // the last step of an odd word count: lanes of half 1 read word w itself,
     // with the rows of b replaced by the zero rows of padding variant n, so that
     // their A operands (a row AND a row of b) vanish
@@ -727,13 +743,15 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
       constexpr bool kTail = decltype(tail)::value;
       const uint32_t d = kTail ? hw : 0u;
       x[0] = ld64(sw, oa - d);
-      x[1] = ld64(sw, ol - d);
-      x[2] = ld64(sw, ol + 256 - d);
+      const v4u qj = ld128(sw, ol - d);  // both rows of the lane's last variant
+      x[1] = (u64)qj[0] | ((u64)qj[1] << 32);
+      x[2] = (u64)qj[2] | ((u64)qj[3] << 32);
       const v4u q = ld128(sw, kTail ? obt : ob);  // both rows of b
       x[3] = (u64)q[0] | ((u64)q[1] << 32);
       x[4] = (u64)q[2] | ((u64)q[3] << 32);
     };
-    // A fragment f: row of a AND row f of b
+    // A fragment f: row of a AND row f of b; B fragment f: row f of the last
+    // variants
     const auto ops = [](const u64 (&x)[5], int half, v8i (&E)[4]) {
       const int sh = 32 * half;
       E[0] = expand32_fp4_and((uint32_t)(x[0] >> sh), (uint32_t)(x[3] >> sh));
@@ -751,7 +769,7 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
       x[0] = pa[(size_t)w * 4];
       const size_t o = (size_t)w * word_stride;
       x[1] = pj[o];
-      x[2] = pj[o + 32];
+      x[2] = pj[o + 1];
       x[3] = pb[(size_t)w * 4];
       x[4] = pb[(size_t)w * 4 + 1];
     };
@@ -765,13 +783,11 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
     mfma_class<3, 5>(load_words, prep, v.W0, v.W0 + v.W1, h, lut, acc1);
   }
 
-  // Output block (f, fb): lane l holds column l mod 32 (last variant j0 + 16 fb
-  // + (l mod 32) / 2, genotype l mod 2); register e = 4 q + 2 s + g_a holds row
-  // 8 q + 4 h + 2 s + g_a, i.e. prefix a_first + 4 q + 2 h + s at genotypes g_a
-  // and g_b = f.  Lanes l and l ^ 1 hold the two genotypes of the same j; the
-  // lane of genotype bit gl scores the prefixes with q in {2 gl, 2 gl + 1}
-  // after taking the partner's counts for the other genotype of j.
-  const uint32_t gl = lane & 1;
+  // Output block (f, fb): lane l holds column l mod 32, last variant j0 + (l
+  // mod 32) at genotype g_j = fb; register e = 4 q + 2 s + g_a holds row 8 q +
+  // 4 h + 2 s + g_a, i.e. prefix a_first + 4 q + 2 h + s at genotypes g_a and
+  // g_b = f.  So each lane holds all eight {0,1}^3 counts of its last variant
+  // with 8 prefixes (q = 0..3, s = 0, 1) and scores those combinations.
   const MiConst mc = mi_const(v);
   const FI_GLOBAL uint32_t *marg = as_global(v.marg);
   const FI_GLOBAL uint32_t *PT = as_global(v.pairs);
@@ -795,79 +811,60 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
 #pragma unroll
   for (int x = 0; x < 2; ++x) Mb4[x] = pack_x4(Mb[x][0], Mb[x][1]);
   const uint32_t m4 = pack_x4(v.m0, v.m1);
-  // the lane's two last variants j (fb = 0, 1): their class counts and (b, j)
-  // pair tables are read once for the four prefixes the lane scores
-  uint32_t jv[2], jj[2];
-#pragma unroll
-  for (int fb = 0; fb < 2; ++fb) {
-    jv[fb] = j0 + 16 * fb + (r >> 1);
-    jj[fb] = jv[fb] < n ? jv[fb] : n - 1;
-  }
-  // Each lane scores 4 prefixes a (q = 2 gl + t, s = 0, 1) with its 2 last
-  // variants; the prefix's (a, b) pair table and class counts are read once
-  // for both, the (a, j) pair table from the same table row.
-  auto prefix_of = [&](int s, int t) { return a_first + 4 * (2 * gl + t) + 2 * h + s; };
+  // the lane's last variant j: its class counts and (b, j) pair table are
+  // read once for the lane's 8 prefixes
+  const uint32_t j = j0 + r, jj = j < n ? j : n - 1;
+  auto prefix_of = [&](int q, int s) { return a_first + 4 * q + 2 * h + s; };
   auto score_packed = [&]() {
     const FI_GLOBAL v4u *PT4 = reinterpret_cast<const FI_GLOBAL v4u *>(as_global(v.pairs4));
-    uint32_t Mj4[2][2], bj4[2][2][2];
+    uint32_t Mj4[2], bj4[2][2];
+    {
+      const v4u qb = PT4[(size_t)b * v.n_pad + jj];
+      bj4[0][0] = qb[0];
+      bj4[0][1] = qb[1];
+      bj4[1][0] = qb[2];
+      bj4[1][1] = qb[3];
 #pragma unroll
-    for (int fb = 0; fb < 2; ++fb) {
-      const v4u q = PT4[(size_t)b * v.n_pad + jj[fb]];
-      bj4[fb][0][0] = q[0];
-      bj4[fb][0][1] = q[1];
-      bj4[fb][1][0] = q[2];
-      bj4[fb][1][1] = q[3];
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-        Mj4[fb][x] = pack_x4(marg[(size_t)jj[fb] * 6 + 2 * x], marg[(size_t)jj[fb] * 6 + 2 * x + 1]);
+      for (int x = 0; x < 2; ++x) Mj4[x] = pack_x4(marg[(size_t)jj * 6 + 2 * x], marg[(size_t)jj * 6 + 2 * x + 1]);
     }
     const FI_LDS char *Fb = (const FI_LDS char *)Fl;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int q = 0; q < 4; ++q) {
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const uint32_t a = prefix_of(s, t);
+      for (int s = 0; s < 2; ++s) {
+        const uint32_t a = prefix_of(q, s);
         const uint32_t aa = a < b ? a : b - 1;
         const FI_GLOBAL v4u *row = PT4 + (size_t)aa * v.n_pad;
-        uint32_t ab4[2][2], Ma4[2];
+        uint32_t ab4[2][2], Ma4[2], aj4[2][2];
         {
-          const v4u q = row[b];
-          ab4[0][0] = q[0];
-          ab4[0][1] = q[1];
-          ab4[1][0] = q[2];
-          ab4[1][1] = q[3];
+          const v4u qb = row[b], qj = row[jj];
+          ab4[0][0] = qb[0];
+          ab4[0][1] = qb[1];
+          ab4[1][0] = qb[2];
+          ab4[1][1] = qb[3];
+          aj4[0][0] = qj[0];
+          aj4[0][1] = qj[1];
+          aj4[1][0] = qj[2];
+          aj4[1][1] = qj[3];
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x) Ma4[x] = pack_x4(marg[(size_t)aa * 6 + 2 * x], marg[(size_t)aa * 6 + 2 * x + 1]);
         const uint32_t pre[2] = {aa, b};
-#pragma unroll
-        for (int fb = 0; fb < 2; ++fb) {
+        {
           uint32_t D4[2][2][2];  // [g_a][g_b][g_j], packed x 4
 #pragma unroll
           for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int g = 0; g < 2; ++g) {
-              uint32_t o[2];
-              partner_packed(Q, f, fb, 4 * t + 2 * s + g, 4 * (2 + t) + 2 * s + g, gl, o);
-              D4[g][f][0] = o[0] << 2;
-              D4[g][f][1] = o[1] << 2;
-            }
-          uint32_t aj4[2][2];
-          {
-            const v4u q = row[jj[fb]];
-            aj4[0][0] = q[0];
-            aj4[0][1] = q[1];
-            aj4[1][0] = q[2];
-            aj4[1][1] = q[3];
-          }
-          const uint32_t j = jv[fb];
+            for (int fb = 0; fb < 2; ++fb)
+#pragma unroll
+              for (int g = 0; g < 2; ++g) D4[g][f][fb] = Q[f][fb][4 * q + 2 * s + g] << 2;
           const bool active = a < b && j < n;
           uint32_t fs = mc.q0;  // fixed point: the LDS table holds Fq
           if (active) {
             constexpr int kGroup = 3;
             uint32_t o0[kGroup], o1[kGroup];
             int nc = 0;
-            walk_order3_packed(D4, ab4, aj4, bj4[fb], Ma4, Mb4, Mj4[fb], m4, [&](uint32_t p) {
+            walk_order3_packed(D4, ab4, aj4, bj4, Ma4, Mb4, Mj4, m4, [&](uint32_t p) {
               o0[nc] = p & 0xFFFFu;
               o1[nc] = p >> 16;
               if (++nc == kGroup) {
@@ -893,41 +890,37 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
       }
     }
   };
-  // the per-class walk (counts of 16 bits or more per class): last variants
-  // outermost, so that only one j's tables are live at a time
+  // the per-class walk (counts of 16 bits or more per class)
   auto score = [&](auto F) {
-#pragma unroll
-    for (int fb = 0; fb < 2; ++fb) {
+    {
       uint32_t Mj[2][2], bj[8];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) Mj[x][c] = marg[(size_t)jj[fb] * 6 + 2 * x + c];
-      load_pair(PT + ((size_t)b * v.n_pad + jj[fb]) * 8, bj);
+        for (int c = 0; c < 2; ++c) Mj[x][c] = marg[(size_t)jj * 6 + 2 * x + c];
+      load_pair(PT + ((size_t)b * v.n_pad + jj) * 8, bj);
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
+      for (int q = 0; q < 4; ++q) {
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const uint32_t a = prefix_of(s, t);
+        for (int s = 0; s < 2; ++s) {
+          const uint32_t a = prefix_of(q, s);
           uint32_t D[2][2][2][2];  // [class][g_a][g_b][g_j]
 #pragma unroll
           for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int g = 0; g < 2; ++g) {
-              uint32_t o[2][2];
-              partner_counts<FMT>(acc0, acc1, Q, f, fb, 4 * t + 2 * s + g, 4 * (2 + t) + 2 * s + g, gl, o);
+            for (int fb = 0; fb < 2; ++fb)
 #pragma unroll
-              for (int c = 0; c < 2; ++c) {
-                D[c][g][f][0] = o[c][0];
-                D[c][g][f][1] = o[c][1];
+              for (int g = 0; g < 2; ++g) {
+                uint32_t o[2];
+                own_counts<FMT>(acc0, acc1, Q, f, fb, 4 * q + 2 * s + g, o);
+                D[0][g][f][fb] = o[0];
+                D[1][g][f][fb] = o[1];
               }
-            }
-          const uint32_t j = jv[fb];
           const bool active = a < b && j < n;
           const uint32_t aa = a < b ? a : b - 1;
           uint32_t ab[8], aj[8], Ma[2][2];
           load_pair(PT + ((size_t)aa * v.n_pad + b) * 8, ab);
-          load_pair(PT + ((size_t)aa * v.n_pad + jj[fb]) * 8, aj);
+          load_pair(PT + ((size_t)aa * v.n_pad + jj) * 8, aj);
 #pragma unroll
           for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -2145,9 +2138,12 @@ void launch_mfma_sub(const Globals &g, int order, bool dual, int grid, hipStream
 
 // ORDER 2 or 3, FMT: operand format (kMfmaI8, kMfmaF4, kMfmaF4Narrow); the
 // kernel serves the jobs of that order and format (a batch with several
-// launches it once per group, each over the group's tiles)
+// launches it once per group, each over the group's tiles).  Waves per SIMD:
+// 2, the dual kernels 3, the order-3 dual kernel 4 (128 registers with a few
+// spilled, measured faster than 3 without spills; at order 2 the same bound
+// spills 24)
 template <int ORDER, int FMT>
-__global__ __launch_bounds__(kMfmaWaves * 64, FMT == kMfmaF4Dual ? 3 : 2) void mfma_kernel(Globals g) {
+__global__ __launch_bounds__(kMfmaWaves * 64, FMT == kMfmaF4Dual ? (ORDER == 3 ? 4 : 3) : 2) void mfma_kernel(Globals g) {
   constexpr bool F4 = FMT != kMfmaI8;
   __shared__ u64 s_lut[F4 ? 1 : 256 * kLutCopies];
   // the f table of the current job, when it has at most mfma_f_entries(FMT)
