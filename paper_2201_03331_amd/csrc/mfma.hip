@@ -492,8 +492,9 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
   const uint32_t r = lane & 31, h = lane >> 5;
   const size_t word_stride = (size_t)v.n_pad * 2;
   const FI_GLOBAL u64 *Bv = as_global(v.Bv);
-  const FI_GLOBAL u64 *pa = Bv + (size_t)a0 * 2 + r;
-  const FI_GLOBAL u64 *pj = Bv + (size_t)j0 * 2 + r;
+  // lane r of fragment f: variant a0 + r (A) and j0 + r (B) at genotype f
+  const FI_GLOBAL u64 *pa = Bv + (size_t)(a0 + r) * 2;
+  const FI_GLOBAL u64 *pj = Bv + (size_t)(j0 + r) * 2;
   v16i acc0[2][2], acc1[2][2];  // int8, FP4: counts per class
   uint32_t Q[2][2][16];         // narrow FP4: both classes per register
   if constexpr (FMT != kMfmaI8) {
@@ -504,24 +505,20 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
     const size_t word_bytes = (size_t)v.n_pad * 16;  // one word of every variant
     // words in pairs: lane half h reads word w + h whole
     const uint32_t hw = h * (uint32_t)word_bytes;
-    const uint32_t ol = r * 8 + hw;
+    const uint32_t ol = r * 16 + hw;
     // the last step of an odd word count: lanes of half 1 read word w itself,
     // their A rows from the zero rows of padding variant n
-    const uint32_t oat = h ? (n - a0) * 16 : r * 8;
+    const uint32_t oat = h ? (n - a0) * 16 : r * 16;
     auto load_words = [&](uint32_t w, auto tail, u64 (&x)[4]) {
       const FI_GLOBAL char *sa = Bvc + (size_t)w * word_bytes + (size_t)a0 * 16;
       const FI_GLOBAL char *sj = Bvc + (size_t)w * word_bytes + (size_t)j0 * 16;
-      if constexpr (!decltype(tail)::value) {
-        x[0] = ld64(sa, ol);
-        x[1] = ld64(sa, ol + 256);
-        x[2] = ld64(sj, ol);
-        x[3] = ld64(sj, ol + 256);
-      } else {
-        x[0] = ld64(sa, oat);
-        x[1] = ld64(sa, h ? oat : oat + 256);
-        x[2] = ld64(sj, ol - hw);
-        x[3] = ld64(sj, ol - hw + 256);
-      }
+      constexpr bool kTail = decltype(tail)::value;
+      const v4u qa = ld128(sa, kTail ? oat : ol);  // both rows of the lane's variants
+      const v4u qj = ld128(sj, kTail ? ol - hw : ol);
+      x[0] = (u64)qa[0] | ((u64)qa[1] << 32);
+      x[1] = (u64)qa[2] | ((u64)qa[3] << 32);
+      x[2] = (u64)qj[0] | ((u64)qj[1] << 32);
+      x[3] = (u64)qj[2] | ((u64)qj[3] << 32);
     };
     const auto ops = [](const u64 (&x)[4], int half, v8i (&E)[4]) {
       const int sh = 32 * half;
@@ -539,9 +536,9 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
     auto load_words = [&](uint32_t w, u64 (&x)[4]) {
       const size_t o = (size_t)w * word_stride;
       x[0] = pa[o];
-      x[1] = pa[o + 32];
+      x[1] = pa[o + 1];
       x[2] = pj[o];
-      x[3] = pj[o + 32];
+      x[3] = pj[o + 1];
     };
     auto prep = [](const u64 (&x)[4], u64 (&o)[4]) {
 #pragma unroll
@@ -551,13 +548,10 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
     mfma_class<3, 4>(load_words, prep, v.W0, v.W0 + v.W1, h, lut, acc1);
   }
 
-  // Output block layout: lane l holds column l mod 32 (variant j0' + (l mod
-  // 32) / 2, genotype l mod 2); register e holds row 8 (e / 4) + 4 h + e mod 4
-  // (variant a0' + 4 (e / 4) + 2 h + (e mod 4) / 2, genotype e mod 2).  Lanes
-  // l and l ^ 1 hold the two genotypes of the same j; each scores the pairs
-  // whose a-offset (e mod 4) / 2 equals its own genotype bit, after taking the
-  // partner's counts for the other genotype of j.
-  const uint32_t gl = lane & 1;
+  // Output block (fa, fb): lane l holds column l mod 32, variant j0 + (l mod
+  // 32) at genotype g_j = fb; register e = 4 q + i holds row 8 q + 4 h + i,
+  // variant a0 + 8 q + 4 h + i at genotype g_a = fa.  So each lane holds the
+  // four {0,1}^2 counts of its 16 pairs (q = 0..3, i = 0..3) and scores them.
   const MiConst mc = mi_const(v);
   const FI_GLOBAL uint32_t *marg = as_global(v.marg);
   const uint32_t mcls[2] = {v.m0, v.m1};
@@ -569,44 +563,37 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
   // the scoring reads the f table from the workgroup's LDS copy (LDS_F:
   // it holds this job's table) or from global memory
   float thr = current_threshold(v);
+  // class counts (rows 0 and 1 of a variant) in one 16-byte read
+  auto marg2 = [&](uint32_t var, uint32_t (&M)[2][2]) {
+    const FI_GLOBAL v2u32 *p = reinterpret_cast<const FI_GLOBAL v2u32 *>(marg + (size_t)var * 6);  // 8-byte aligned
+    const v2u32 u0 = p[0], u1 = p[1];
+    M[0][0] = u0.x;
+    M[0][1] = u0.y;
+    M[1][0] = u1.x;
+    M[1][1] = u1.y;
+  };
   auto score = [&](auto F) {
-    // the class counts of the lane's two last variants, then per first
-    // variant its class counts once for both
-    uint32_t jv[2], Mj[2][2][2];  // Mj[fb][g][class]
+    // the class counts of the lane's last variant, then per first variant
+    const uint32_t j = j0 + r, jj = j < n ? j : n - 1;
+    uint32_t Mj[2][2];  // [g][class]
+    marg2(jj, Mj);
 #pragma unroll
-    for (int fb = 0; fb < 2; ++fb) {
-      jv[fb] = j0 + 16 * fb + (r >> 1);
-      const uint32_t jj = jv[fb] < n ? jv[fb] : n - 1;
+    for (int q = 0; q < 4; ++q) {
 #pragma unroll
-      for (int gg = 0; gg < 2; ++gg)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) Mj[fb][gg][c] = marg[(size_t)jj * 6 + 2 * gg + c];
-    }
-#pragma unroll
-    for (int fa = 0; fa < 2; ++fa) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t a = a0 + 16 * fa + 4 * q + 2 * h + gl;
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t a = a0 + 8 * q + 4 * h + i;
         const uint32_t aa = a < n ? a : n - 1;
         uint32_t Ma[2][2];  // [g][class]
-#pragma unroll
-        for (int gg = 0; gg < 2; ++gg)
-#pragma unroll
-          for (int c = 0; c < 2; ++c) Ma[gg][c] = marg[(size_t)aa * 6 + 2 * gg + c];
-#pragma unroll
-        for (int fb = 0; fb < 2; ++fb) {
-          const uint32_t j = jv[fb];
+        marg2(aa, Ma);
+        {
           if (kPackable && packed) {
             // the 9 cells as packed byte offsets, 4 x count per class half,
             // as in the order-3 walk
             uint32_t C4[2][2];  // [g_a][g_j]
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-              uint32_t o[2];
-              partner_packed(Q, fa, fb, 4 * q + t, 4 * q + 2 + t, gl, o);
-              C4[t][0] = o[0] << 2;
-              C4[t][1] = o[1] << 2;
-            }
+            for (int fa = 0; fa < 2; ++fa)
+#pragma unroll
+              for (int fb = 0; fb < 2; ++fb) C4[fa][fb] = Q[fa][fb][4 * q + i] << 2;
             const bool active = a < j && j < n;
             float fs = mc.c;
             if (active) {
@@ -614,7 +601,7 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
 #pragma unroll
               for (int gg = 0; gg < 2; ++gg) {
                 Ma4[gg] = pack_x4(Ma[gg][0], Ma[gg][1]);
-                Mj4[gg] = pack_x4(Mj[fb][gg][0], Mj[fb][gg][1]);
+                Mj4[gg] = pack_x4(Mj[gg][0], Mj[gg][1]);
               }
               const uint32_t t9[9] = {C4[0][0], C4[0][1], Ma4[0] - C4[0][0] - C4[0][1],
                                       C4[1][0], C4[1][1], Ma4[1] - C4[1][0] - C4[1][1],
@@ -641,15 +628,14 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
           }
           uint32_t cnt[2][2][2];  // [g_a][g_j][class]
 #pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            uint32_t o[2][2];
-            partner_counts<FMT>(acc0, acc1, Q, fa, fb, 4 * q + t, 4 * q + 2 + t, gl, o);
+          for (int fa = 0; fa < 2; ++fa)
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              cnt[t][0][c] = o[c][0];
-              cnt[t][1][c] = o[c][1];
+            for (int fb = 0; fb < 2; ++fb) {
+              uint32_t o[2];
+              own_counts<FMT>(acc0, acc1, Q, fa, fb, 4 * q + i, o);
+              cnt[fa][fb][0] = o[0];
+              cnt[fa][fb][1] = o[1];
             }
-          }
           const bool active = a < j && j < n;
           using E = decltype(+F[0]);  // the table's element type, without its address space
           E fs = mi_start<E>(mc);
@@ -664,9 +650,9 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
               t9[3][c] = C[1][0][c];
               t9[4][c] = C[1][1][c];
               t9[5][c] = Ma[1][c] - C[1][0][c] - C[1][1][c];
-              t9[6][c] = Mj[fb][0][c] - C[0][0][c] - C[1][0][c];
-              t9[7][c] = Mj[fb][1][c] - C[0][1][c] - C[1][1][c];
-              t9[8][c] = mcls[c] - Ma[0][c] - Ma[1][c] - Mj[fb][0][c] - Mj[fb][1][c] + C[0][0][c] +
+              t9[6][c] = Mj[0][c] - C[0][0][c] - C[1][0][c];
+              t9[7][c] = Mj[1][c] - C[0][1][c] - C[1][1][c];
+              t9[8][c] = mcls[c] - Ma[0][c] - Ma[1][c] - Mj[0][c] - Mj[1][c] + C[0][0][c] +
                          C[0][1][c] + C[1][0][c] + C[1][1][c];
               // every count is at most the class size; in global memory the
               // clamp keeps the reads inside [0, m] whatever the counts hold
@@ -2052,7 +2038,7 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void quads_kernel(Globals g) {
   v.W1 = uni(st->W1);
   v.m0 = uni(st->m0);
   v.m1 = uni(st->m1);
-  const uint32_t n = v.n, np = v.n_pad;
+  const uint32_t n = v.n;
   const uint32_t c = blockIdx.y + 2;
   if (c + 1 >= n) return;
   const u64 nq = (u64)c * (c - 1) / 2;
