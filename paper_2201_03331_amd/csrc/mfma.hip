@@ -423,52 +423,6 @@ __device__ __forceinline__ void contract_fp4_dual(Load &&load_words, Ops &&ops, 
 // bit length of x (0 for 0)
 __device__ __forceinline__ uint32_t bit_len(uint32_t x) { return x ? 32u - __clz(x) : 0u; }
 
-// Counts of the lane's combination from output registers elo (the lane's own
-// genotype row gl of the last variant, if gl = 0) and ehi (if gl = 1) of
-// block (x, y): o[class][g_j] after taking the partner lane's (l ^ 1) counts
-// for the other genotype of j.  Static register indices only: a
-// lane-dependent index into a register array becomes a compare-and-select
-// over every element.  partner_packed: the same from packed registers (both
-// classes in one, class 0 low), o[g_j] packed.
-__device__ __forceinline__ void partner_packed(const uint32_t (&Q)[2][2][16], int x, int y, int elo,
-                                               int ehi, uint32_t gl, uint32_t (&o)[2]) {
-  const uint32_t lo = Q[x][y][elo], hi = Q[x][y][ehi];
-  const uint32_t own = gl ? hi : lo;
-  const uint32_t send = gl ? lo : hi;
-  const uint32_t recv = xor1(send);
-  o[0] = gl ? recv : own;
-  o[1] = gl ? own : recv;
-}
-
-template <int FMT>
-__device__ __forceinline__ void partner_counts(const v16i (&acc0)[2][2], const v16i (&acc1)[2][2],
-                                               const uint32_t (&Q)[2][2][16], int x, int y, int elo,
-                                               int ehi, uint32_t gl, uint32_t (&o)[2][2]) {
-  if constexpr (FMT == kMfmaF4Narrow || FMT == kMfmaF4Dual) {
-    // both classes in one register: one exchange
-    const uint32_t lo = Q[x][y][elo], hi = Q[x][y][ehi];
-    const uint32_t own = gl ? hi : lo;
-    const uint32_t send = gl ? lo : hi;
-    const uint32_t recv = xor1(send);
-    const uint32_t g0 = gl ? recv : own, g1 = gl ? own : recv;
-    o[0][0] = g0 & 0xFFFFu;
-    o[1][0] = g0 >> 16;
-    o[0][1] = g1 & 0xFFFFu;
-    o[1][1] = g1 >> 16;
-  } else {
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const v16i &A = c == 0 ? acc0[x][y] : acc1[x][y];
-      const uint32_t lo = (uint32_t)A[elo], hi = (uint32_t)A[ehi];
-      const uint32_t own = gl ? hi : lo;
-      const uint32_t send = gl ? lo : hi;
-      const uint32_t recv = xor1(send);
-      o[c][0] = gl ? recv : own;
-      o[c][1] = gl ? own : recv;
-    }
-  }
-}
-
 // Counts of both classes of output register e of block (x, y), the lane's own
 // column: from the packed registers (narrow, dual) or the per-class ones
 template <int FMT>
