@@ -77,7 +77,7 @@ constexpr int kMfmaF4Dual = 3;
 // workgroups share a compute unit's 160 KB, 80 KB each with their static
 // LDS: up to 12,280 entries next to the 32 KB byte table with int8 operands,
 // 20,448 with FP4 operands (every job of a narrow launch has at most 20,447
-// samples); the dual kernels run 3 or 4 workgroups per compute unit, 8,192
+// samples); the dual kernels run 3 workgroups per compute unit, 8,192
 // entries each (jobs of at most 8,191 samples).
 __host__ __device__ constexpr uint32_t mfma_f_entries(int fmt) {
   return fmt == kMfmaI8 ? 12280u : fmt == kMfmaF4Dual ? 8192u : 20448u;
@@ -2079,11 +2079,10 @@ void launch_mfma_sub(const Globals &g, int order, bool dual, int grid, hipStream
 // ORDER 2 or 3, FMT: operand format (kMfmaI8, kMfmaF4, kMfmaF4Narrow); the
 // kernel serves the jobs of that order and format (a batch with several
 // launches it once per group, each over the group's tiles).  Waves per SIMD:
-// 2, the dual kernels 3, the order-3 dual kernel 4 (128 registers with a few
-// spilled, measured faster than 3 without spills; at order 2 the same bound
-// spills 24)
+// 2, the dual kernels 3 (the order-3 dual kernel at 4 spills 10 registers:
+// 0.6 % faster, but its scratch traffic doubles the bytes it moves)
 template <int ORDER, int FMT>
-__global__ __launch_bounds__(kMfmaWaves * 64, FMT == kMfmaF4Dual ? (ORDER == 3 ? 4 : 3) : 2) void mfma_kernel(Globals g) {
+__global__ __launch_bounds__(kMfmaWaves * 64, FMT == kMfmaF4Dual ? 3 : 2) void mfma_kernel(Globals g) {
   constexpr bool F4 = FMT != kMfmaI8;
   __shared__ u64 s_lut[F4 ? 1 : 256 * kLutCopies];
   // the f table of the current job, when it has at most mfma_f_entries(FMT)
