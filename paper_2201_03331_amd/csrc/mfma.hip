@@ -6,9 +6,10 @@
 // at variant v, those cells are the entries of the Gram matrix X X^T: an
 // exact 0/1 contraction over the samples of the class, with int32
 // accumulation (counts stay below 2^24).  Here it runs on the int8 matrix
-// instruction v_mfma_i32_32x32x32_i8: rows 2v + g of a fragment are the two
-// genotype rows of 16 consecutive variants, so one 32 x 32 block holds every
-// {0,1} x {0,1} cell of 16 x 16 pairs.
+// instruction v_mfma_i32_32x32x32_i8: fragment g of either operand holds
+// genotype row g of 32 consecutive variants, so block (g_a, g_j) holds cell
+// (g_a, g_j) of 32 x 32 pairs, and the four blocks give each lane (one column,
+// a last variant) all four cells of its pairs.
 //
 // A workgroup owns 64 first variants x 64 last variants (tile of the upper
 // triangle of 64-variant blocks); each of its 4 waves owns 32 x 32 of them
@@ -25,11 +26,12 @@
 // takes 64 samples per row instead of 32, and a lane's 32 operand values come
 // from its 32-bit half word by one or two bit operations per register.
 //
-// Order 3 uses the same contraction with prefix pairs as rows: row 4p + 2 g_a
-// + g_b of a fragment is the AND of the genotype rows g_a of a_p and g_b of b
-// (8 prefix pairs (a_p, b) per fragment, b fixed for the tile), so a block
-// holds the {0,1}^3 cells of 8 prefixes x 16 last variants; the other cells
-// come from the pair tables by inclusion-exclusion, as in the popcount kernel.
+// Order 3 uses the same contraction with prefix pairs as rows: row 2p + g_a
+// of A fragment g_b is the AND of genotype row g_a of a_p and row g_b of b
+// (16 prefix pairs (a_p, b) per fragment, b fixed for the tile), so the four
+// blocks hold the {0,1}^3 cells of 16 prefixes x 32 last variants; the other
+// cells come from the pair tables by inclusion-exclusion, as in the popcount
+// kernel.
 #include "filter.hpp"
 
 namespace fiuncho {
@@ -63,7 +65,8 @@ constexpr uint32_t kRefreshAppends = 16;
 // f table fits in LDS ("narrow": their class counts fit 16 bits, so class-0
 // counts wait as 16-bit pairs while class 1 accumulates, and both classes of
 // a cell share one register afterwards: half the registers for finished
-// counts and one exchange between partner lanes instead of two).
+// counts, and one exchange between partner lanes instead of two where the
+// counts of a combination sit in two lanes).
 constexpr int kMfmaI8 = 0, kMfmaF4 = 1, kMfmaF4Narrow = 2;
 // FP4 for jobs whose two class sizes fit 24 bits together (bit length of m0
 // plus bit length of m1 at most 24, e.g. both below 4,096): class-1 products
