@@ -127,6 +127,33 @@ def host_cpus() -> int:
         return os.cpu_count() or 1
 
 
+def io_read_rate(d):
+    """The input stage (Fig. 1) on the workload's dataset: its genotypes and
+    classes written as text files (one line of digits per variant), then read
+    back by the library's reader on the host.  Not part of the timed step."""
+    import tempfile
+    from paper_2201_03331_amd import fiuncho
+    G = np.ascontiguousarray(d.genotypes, dtype=np.uint8)
+    y = np.ascontiguousarray(d.phenotype, dtype=np.uint8)
+    with tempfile.TemporaryDirectory() as tmp:
+        gp, yp = os.path.join(tmp, "genotypes.txt"), os.path.join(tmp, "phenotype.txt")
+        text = np.empty((G.shape[0], G.shape[1] + 1), dtype=np.uint8)
+        text[:, :-1] = G + ord("0")
+        text[:, -1] = ord("\n")
+        with open(gp, "wb") as f:
+            f.write(text.tobytes())
+        with open(yp, "wb") as f:
+            f.write((y + ord("0")).tobytes() + b"\n")
+        nbytes = os.path.getsize(gp) + os.path.getsize(yp)
+        fiuncho.lib()  # loaded before the clock starts
+        t0 = time.perf_counter()
+        G2, y2 = fiuncho.read_dataset(gp, yp)
+        dt = time.perf_counter() - t0
+    assert np.array_equal(G2, G) and np.array_equal(y2, y), "the reader changed the dataset"
+    return {"read_s": round(dt, 4), "bytes": nbytes, "MB_per_s": round(nbytes / dt / 1e6, 1),
+            "format": "text, one line of genotype digits per variant"}
+
+
 def cpu_baseline(d, budget_s: float = 15.0):
     """The oracle (plain per-sample counting, FP64 MI) timed on every host CPU
     this process may use, over a contiguous sample of ranks of the same
@@ -461,6 +488,9 @@ def main():
     if not args.no_cpu_baseline and len(d0.genotypes) and args.workload != "batch64" and \
             not args.workload.endswith("-plain") and shard is None:
         out["cpu_baseline"] = cpu_baseline(d0)
+    if len(d0.genotypes) and args.workload != "batch64" and not args.workload.endswith("-plain") and \
+            shard is None:
+        out["io"] = io_read_rate(d0)
     print(json.dumps(out), flush=True)
 
 

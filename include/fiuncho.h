@@ -58,11 +58,12 @@ enum {
                                candidates than the candidate buffer holds;
                                fiuncho_scan enlarges its buffer and retries */
   FIUNCHO_E_DEVICE = -9,    /* a HIP runtime error or no usable gfx950 device */
-  FIUNCHO_E_INTERNAL = -10  /* a self-check failed: the counting kernel's
-                               single-precision estimate of a rescored
-                               combination was farther from its exact MI than
-                               twice fiuncho_estimate_bound (never expected;
-                               the result is withheld) */
+  FIUNCHO_E_INTERNAL = -10, /* a self-check failed: the counting kernel's
+                               estimate of a rescored combination was
+                               farther from its exact MI than twice
+                               fiuncho_estimate_bound (never expected; the
+                               result is withheld) */
+  FIUNCHO_E_IO = -11        /* a file could not be opened, read or written */
 };
 
 /* Largest supported top_n.  The device workspace grows with it: the
@@ -77,11 +78,14 @@ typedef struct {
   double mi;                       /* mutual information, IEEE double, nats */
   float mi32;                      /* compensated single-precision MI of the exact table */
   float rel_err;                   /* |mi32 - mi| / mi, |mi32 - mi| when mi == 0 */
-  float est;                       /* the plain single-precision MI the counting
-                                      kernel computed from its own counts, the
-                                      score the search filtered on; within
-                                      fiuncho_estimate_bound(order, samples) of mi
-                                      (0 for a dataset with an empty class) */
+  float est;                       /* the MI estimate the counting kernel
+                                      computed from its own counts, the score the
+                                      search filtered on (single precision, or a
+                                      32-bit fixed-point sum in the FP4
+                                      matrix-core kernels of orders 3 to 5);
+                                      within fiuncho_estimate_bound(order,
+                                      samples) of mi (0 for a dataset with an
+                                      empty class) */
   uint32_t reserved;               /* 0 */
 } fiuncho_hit;
 
@@ -92,8 +96,10 @@ typedef struct {
  * [f(n0) + f(n1) - f(n0 + n1)], f(t) = t ln t from a float table):
  * u (6 ln m + (3^order + 4) ln 2), u = 2^-24.  The search keeps every
  * combination whose estimate lies within 4 times this bound of the top_n-th
- * best estimate, so none of the exact best top_n is lost.  Returns a negative
- * value for an order outside [1, 8] or samples == 0.
+ * best estimate, so none of the exact best top_n is lost.  The fixed-point
+ * form of the same sum (FP4 matrix-core kernels, orders 3 to 5) errs by less
+ * for every sample count.  Returns a negative value for an order outside
+ * [1, 8] or samples == 0.
  */
 double fiuncho_estimate_bound(int order, uint32_t samples);
 
@@ -330,6 +336,55 @@ int fiuncho_autotune(uint32_t snps, uint32_t samples, int order, uint32_t reps, 
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *fiuncho_last_error(void);
+
+/*
+ * The input and output stages of the search (Fig. 1: the variants read from
+ * a file, the saved combinations written to one).  The paper gives no file
+ * format; these read and write plain ASCII text, on the host (no device is
+ * needed):
+ *   genotype file  one line per variant: the genotype (0, 1 or 2) of every
+ *                  sample, in sample order, as digits, either contiguous or
+ *                  separated by spaces, tabs or commas; empty lines and lines
+ *                  whose first character is '#' are skipped; every variant
+ *                  has the same number of samples
+ *   phenotype file the class of every sample, 0 (control) or 1 (case), as
+ *                  digits separated the same way, on any number of lines
+ *   result file    a header line, then one line per hit, tab-separated: rank,
+ *                  the order's variant indices, mi (17 significant digits),
+ *                  mi32, rel_err, est
+ * The library never retains a path or a buffer past the call.
+ */
+
+/*
+ * fiuncho_read_genotypes -- reads a genotype file.  With genotypes NULL only
+ * measures it: *snps and *samples receive its shape.  Otherwise writes the
+ * [snps][samples] uint8 matrix (the layout fiuncho_scan takes) to genotypes,
+ * which holds capacity bytes.
+ * Errors: FIUNCHO_E_NULL (path, snps or samples NULL), FIUNCHO_E_IO (the file
+ * cannot be read), FIUNCHO_E_SHAPE (no variant, variants of different
+ * lengths, 2^24 samples or more, or capacity < snps * samples),
+ * FIUNCHO_E_GENOTYPE (a character other than 0, 1, 2 or a separator; the
+ * message names the line).
+ */
+int fiuncho_read_genotypes(const char *path, uint8_t *genotypes, size_t capacity, uint32_t *snps,
+                           uint32_t *samples);
+
+/*
+ * fiuncho_read_phenotype -- reads a phenotype file into phenotype (capacity
+ * bytes), or with phenotype NULL only counts its samples into *samples.
+ * Errors: FIUNCHO_E_NULL (path or samples NULL), FIUNCHO_E_IO,
+ * FIUNCHO_E_SHAPE (no sample, 2^24 samples or more, capacity too small),
+ * FIUNCHO_E_PHENOTYPE (a character other than 0, 1 or a separator).
+ */
+int fiuncho_read_phenotype(const char *path, uint8_t *phenotype, size_t capacity, uint32_t *samples);
+
+/*
+ * fiuncho_write_hits -- writes n hits (as fiuncho_scan returns them, best
+ * first) of the given order to a result file, replacing it.
+ * Errors: FIUNCHO_E_NULL (path NULL, or hits NULL with n > 0),
+ * FIUNCHO_E_ORDER (order outside [1, 8]), FIUNCHO_E_IO.
+ */
+int fiuncho_write_hits(const char *path, const fiuncho_hit *hits, uint32_t n, int order);
 
 /* Per-phase device times (milliseconds), averaged over the fiuncho_scan_batch
  * calls made on this thread with profiling enabled since the last

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfiuncho.so")
-SOURCES = ["api.hip", "pack.hip", "scan.hip", "mfma.hip", "select.hip"]
+SOURCES = ["api.hip", "pack.hip", "scan.hip", "mfma.hip", "select.hip", "io.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -57,7 +57,7 @@ def build(verbose: bool = False) -> str:
     procs = []
     objs = []
     for src in SOURCES:
-        obj = os.path.join(OBJ, src.replace(".hip", ".o"))
+        obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
         cmd = [HIPCC, *FLAGS, *([REMARKS] if src == "mfma.hip" else []), "-c", os.path.join(CSRC, src),
                "-o", obj]

@@ -1167,6 +1167,8 @@ int scratch_on_device(void **out) {
 
 }  // namespace
 
+int fiuncho::set_error(int code, const char *msg) { return fail(code, msg); }
+
 extern "C" {
 
 const char *fiuncho_last_error(void) { return t_err.c_str(); }

@@ -212,4 +212,8 @@ void launch_tables(const Globals &g, const unsigned long long *ranks, uint64_t n
                    hipStream_t s);
 int scan_grid_size(int ksel);
 
+// records msg as the calling thread's last error (fiuncho_last_error) and
+// returns code
+int set_error(int code, const char *msg);
+
 }  // namespace fiuncho

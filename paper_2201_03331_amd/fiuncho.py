@@ -27,6 +27,7 @@ E_OVERFLOW = -7
 E_WORKSPACE = -8
 E_DEVICE = -9
 E_INTERNAL = -10
+E_IO = -11
 MAX_ORDER = 8
 MAX_TOPN = 1 << 24
 DEVICE_PTRS = 1
@@ -58,6 +59,9 @@ EXPORTS = (
     "fiuncho_estimate_bound",
     "fiuncho_set_profiling",
     "fiuncho_get_profile",
+    "fiuncho_read_genotypes",
+    "fiuncho_read_phenotype",
+    "fiuncho_write_hits",
 )
 
 HIT_DTYPE = np.dtype([("snp", "<u4", (MAX_ORDER,)), ("rank", "<u8"), ("mi", "<f8"),
@@ -166,6 +170,13 @@ def lib() -> ctypes.CDLL:
         L.fiuncho_set_profiling.argtypes = [ctypes.c_int]
         L.fiuncho_get_profile.restype = ctypes.c_int
         L.fiuncho_get_profile.argtypes = [ctypes.POINTER(Profile)]
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.fiuncho_read_genotypes.restype = ctypes.c_int
+        L.fiuncho_read_genotypes.argtypes = [ctypes.c_char_p, ctypes.c_void_p, ctypes.c_size_t, u32p, u32p]
+        L.fiuncho_read_phenotype.restype = ctypes.c_int
+        L.fiuncho_read_phenotype.argtypes = [ctypes.c_char_p, ctypes.c_void_p, ctypes.c_size_t, u32p]
+        L.fiuncho_write_hits.restype = ctypes.c_int
+        L.fiuncho_write_hits.argtypes = [ctypes.c_char_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -183,6 +194,43 @@ def estimate_bound(order: int, samples: int) -> float:
 def _check(code: int):
     if code != OK:
         raise FiunchoError(code, last_error())
+
+
+def read_genotypes(path) -> np.ndarray:
+    """[snps][samples] uint8 genotypes of a genotype text file
+    (fiuncho_read_genotypes: measured, then read)."""
+    L, p = lib(), os.fsencode(path)
+    n, m = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(L.fiuncho_read_genotypes(p, None, 0, ctypes.byref(n), ctypes.byref(m)))
+    G = np.empty((n.value, m.value), dtype=np.uint8)
+    _check(L.fiuncho_read_genotypes(p, G.ctypes.data, G.nbytes, ctypes.byref(n), ctypes.byref(m)))
+    return G
+
+
+def read_phenotype(path) -> np.ndarray:
+    """[samples] uint8 classes of a phenotype text file (fiuncho_read_phenotype)."""
+    L, p = lib(), os.fsencode(path)
+    m = ctypes.c_uint32()
+    _check(L.fiuncho_read_phenotype(p, None, 0, ctypes.byref(m)))
+    y = np.empty(m.value, dtype=np.uint8)
+    _check(L.fiuncho_read_phenotype(p, y.ctypes.data, y.nbytes, ctypes.byref(m)))
+    return y
+
+
+def read_dataset(genotype_path, phenotype_path):
+    """(G, y) from a genotype and a phenotype file; ValueError if their sample
+    counts differ."""
+    G, y = read_genotypes(genotype_path), read_phenotype(phenotype_path)
+    if G.shape[1] != y.shape[0]:
+        raise ValueError(f"{G.shape[1]} samples in {genotype_path}, {y.shape[0]} in {phenotype_path}")
+    return G, y
+
+
+def write_hits(path, hits: np.ndarray, order: int) -> None:
+    """Writes hits (HIT_DTYPE, best first) to a result file (fiuncho_write_hits)."""
+    hits = np.ascontiguousarray(hits, dtype=HIT_DTYPE)
+    _check(lib().fiuncho_write_hits(os.fsencode(path), hits.ctypes.data if len(hits) else None, len(hits),
+                                    order))
 
 
 def _host_arrays(G, y):
