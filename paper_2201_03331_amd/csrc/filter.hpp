@@ -74,9 +74,10 @@ __device__ __forceinline__ JV load_view(const JobDesc *jd) {
 
 // m * MI = [f(m) - f(m0) - f(m1)] + sum_x [f(n_x0) + f(n_x1) - f(n_x0 + n_x1)]
 // with f(t) = t ln t: Eq. 1-3 with plug-in probabilities, multiplied out.
-// The scan evaluates it in plain single precision from a float table of f;
-// the job's fbound bounds the rounding error of the resulting MI, and every
-// filter below widens its threshold by twice that bound.
+// The scan evaluates it in plain single precision from a float table of f
+// (or in fixed point, see MiConst); the job's fbound bounds the rounding error
+// of the resulting MI, and every filter below widens its threshold by twice
+// that bound.
 // F is the table in global memory or a copy of it in LDS.
 template <typename FP>
 __device__ __forceinline__ float mi_term(FP F, uint32_t n0, uint32_t n1) {

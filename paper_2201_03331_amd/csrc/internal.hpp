@@ -73,7 +73,7 @@ constexpr uint32_t kFlagBound = 4u;           // |estimate - mi| exceeded the st
 struct Cand {                 // one appended candidate
   unsigned long long rank;
   uint32_t key;               // float bits of max(est, 0)
-  float est;                  // plain single-precision MI (within fbound of MI)
+  float est;                  // the scan's MI estimate (within fbound of MI)
 };
 
 // Exact scores of kept candidate i, written over entry i of the candidate

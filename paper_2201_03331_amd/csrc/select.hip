@@ -10,7 +10,8 @@
 //   3. rescore:  recount each kept combination's table and evaluate Eq. 1-3 in
 //                IEEE double, term by term in a fixed order;
 //   4. finish:   order by (MI descending, rank ascending), write top_n hits.
-// The scan's plain single-precision estimate is within fbound of the MI (a
+// The scan's estimate (plain single precision, or the 32-bit fixed-point sum
+// of the FP4 matrix-core kernels of orders 3-5) is within fbound of the MI (a
 // bound of its rounding error), so a combination is dropped only when its
 // estimate is more than 2 fbound below one that top_n others reach: it cannot
 // belong to the exact result.  The reported single-precision score is a
