@@ -373,7 +373,8 @@ int mfma_group(const JobLayout &J) {
 struct Layout {
   std::vector<JobLayout> jobs;
   std::vector<uint32_t> order;  // tile-space order of the jobs (costliest first)
-  uint32_t nmax, kmax, max_n_pad, max_wcap, max_cand_cap, max_sel, max_pairs_n, max_triples_n, max_quads_n;
+  uint32_t nmax, kmax, max_n_pad, max_wcap, max_cand_cap, max_sel, max_pairs_n, max_pairs4_n, max_triples_n,
+      max_quads_n;
   size_t plan_begin, plan_end;  // uploaded region
   size_t off_desc, off_jts, off_jps, off_binom, off_counter;
   // tile-space order: [0, n_scan) popcount kernel, then the jobs of each
@@ -394,6 +395,7 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
   L.max_cand_cap = 0;
   L.max_sel = 0;
   L.max_pairs_n = 0;
+  L.max_pairs4_n = 0;
   L.max_triples_n = 0;
   L.max_quads_n = 0;
   size_t off = 0;
@@ -481,7 +483,6 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
     const bool need_pairs = J.path == fiuncho::kPathPairs || J.path == fiuncho::kPathTriples ||
                             J.path == fiuncho::kPathMfma3 || J.path == fiuncho::kPathMfma4t ||
                             J.path == fiuncho::kPathMfma5q;
-    if (need_pairs) L.max_pairs_n = std::max(L.max_pairs_n, J.n);
     if (J.path == fiuncho::kPathTriples || J.path == fiuncho::kPathMfma4t || J.path == fiuncho::kPathMfma5q)
       L.max_triples_n = std::max(L.max_triples_n, J.n);
     if (J.path == fiuncho::kPathMfma5q) L.max_quads_n = std::max(L.max_quads_n, J.n);
@@ -519,6 +520,8 @@ int make_layout(const fiuncho_job *jobs, uint32_t n_jobs, bool host_inputs, uint
                               J.path == fiuncho::kPathMfma4t || J.path == fiuncho::kPathMfma5q;
     J.off_pairs = need_pairs && !packed_pairs ? take(sizeof(uint32_t) * 8 * (size_t)J.n * J.n_pad) : 0;
     J.off_pairs4 = packed_pairs ? take(sizeof(uint32_t) * 4 * (size_t)J.n * J.n_pad) : 0;
+    if (J.off_pairs) L.max_pairs_n = std::max(L.max_pairs_n, J.n);
+    if (J.off_pairs4) L.max_pairs4_n = std::max(L.max_pairs4_n, J.n);
     J.off_triples = J.path == fiuncho::kPathTriples ? take((size_t)triple_table_bytes(J.n)) : 0;
     J.off_triples4 = J.path == fiuncho::kPathMfma4t || J.path == fiuncho::kPathMfma5q
                          ? take((size_t)triple_table_bytes(J.n, true))
@@ -889,6 +892,7 @@ int run_pipeline(const Layout &L, uint8_t *ws, hipStream_t s) {
   fiuncho::launch_init(g, s);
   fiuncho::launch_pack(g, L.max_n_pad, L.max_wcap, s);
   if (L.max_pairs_n) fiuncho::launch_pairs(g, L.max_pairs_n, s);
+  if (L.max_pairs4_n) fiuncho::launch_pairs4(g, L.max_pairs4_n, s);
   if (L.max_triples_n) fiuncho::launch_triples(g, L.max_triples_n, s);
   if (L.max_quads_n) fiuncho::launch_quads(g, L.max_quads_n, s);
   if ((st = prof_record(1, s))) return st;

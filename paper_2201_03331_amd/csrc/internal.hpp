@@ -200,6 +200,9 @@ int mfma_sub_grid_size(int order, bool dual);
 uint32_t mfma_sub_dual_max_samples();
 // the quad tables of the order-5 jobs with lower-order tables
 void launch_quads(const Globals &g, uint32_t max_n, hipStream_t s);
+// the packed pair tables (pairs4) of the jobs that have them, on the matrix
+// cores; the other jobs' pair tables come from launch_pairs
+void launch_pairs4(const Globals &g, uint32_t max_n, hipStream_t s);
 void launch_select(const Globals &g, uint32_t max_cand_cap, hipStream_t s);
 void launch_pilot_select(const Globals &g, uint32_t max_pilot_slots, hipStream_t s);
 void launch_rescore(const Globals &g, uint32_t max_k, hipStream_t s);

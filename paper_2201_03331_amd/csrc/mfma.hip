@@ -441,6 +441,49 @@ __device__ __forceinline__ void own_counts(const v16i (&acc0)[2][2], const v16i 
   }
 }
 
+// The order-2 FP4 contraction of one wave: pairs (a0 + [0, 32)) x (j0 +
+// [0, 32)), fragment g of either operand genotype row g of 32 variants.  A
+// lane loads both rows of its variant on each side in one 16-byte load per
+// word pair (lane half h: word w + h).  Counts in Q (narrow, dual: both
+// classes per register) or acc0, acc1 (per class).
+template <int FMT>
+__device__ __forceinline__ void pairs_contract_fp4(const JV &v, uint32_t a0, uint32_t j0, uint32_t lane,
+                                                   v16i (&acc0)[2][2], v16i (&acc1)[2][2],
+                                                   uint32_t (&Q)[2][2][16]) {
+  const uint32_t n = v.n;
+  const uint32_t r = lane & 31, h = lane >> 5;
+  const FI_GLOBAL char *Bvc = reinterpret_cast<const FI_GLOBAL char *>(as_global(v.Bv));
+  const size_t word_bytes = (size_t)v.n_pad * 16;  // one word of every variant
+  // words in pairs: lane half h reads word w + h whole
+  const uint32_t hw = h * (uint32_t)word_bytes;
+  const uint32_t ol = r * 16 + hw;
+  // the last step of an odd word count: lanes of half 1 read word w itself,
+  // their A rows from the zero rows of padding variant n
+  const uint32_t oat = h ? (n - a0) * 16 : r * 16;
+  auto load_words = [&](uint32_t w, auto tail, u64 (&x)[4]) {
+    const FI_GLOBAL char *sa = Bvc + (size_t)w * word_bytes + (size_t)a0 * 16;
+    const FI_GLOBAL char *sj = Bvc + (size_t)w * word_bytes + (size_t)j0 * 16;
+    constexpr bool kTail = decltype(tail)::value;
+    const v4u qa = ld128(sa, kTail ? oat : ol);  // both rows of the lane's variants
+    const v4u qj = ld128(sj, kTail ? ol - hw : ol);
+    x[0] = (u64)qa[0] | ((u64)qa[1] << 32);
+    x[1] = (u64)qa[2] | ((u64)qa[3] << 32);
+    x[2] = (u64)qj[0] | ((u64)qj[1] << 32);
+    x[3] = (u64)qj[2] | ((u64)qj[3] << 32);
+  };
+  const auto ops = [](const u64 (&x)[4], int half, v8i (&E)[4]) {
+    const int sh = 32 * half;
+    E[0] = expand32_fp4_a((uint32_t)(x[0] >> sh));
+    E[1] = expand32_fp4_a((uint32_t)(x[1] >> sh));
+    E[2] = expand32_fp4_b((uint32_t)(x[2] >> sh));
+    E[3] = expand32_fp4_b((uint32_t)(x[3] >> sh));
+  };
+  if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<2, 4>(load_words, ops, v.W0, v.W1, Q);
+  else if constexpr (FMT == kMfmaF4Dual)
+    contract_fp4_dual<2, 4>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
+  else contract_fp4<2, 4>(load_words, ops, v.W0, v.W1, acc0, acc1);
+}
+
 // One wave: pairs (a0 + [0, 32)) x (j0 + [0, 32)).
 template <int FMT, bool LDS_F>
 __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0, uint32_t lane,
@@ -455,39 +498,7 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
   v16i acc0[2][2], acc1[2][2];  // int8, FP4: counts per class
   uint32_t Q[2][2][16];         // narrow FP4: both classes per register
   if constexpr (FMT != kMfmaI8) {
-    // the lane's 32-bit half of each word: wave-uniform bases of the
-    // fragments' words (advanced by scalar arithmetic) plus a 32-bit lane
-    // offset
-    const FI_GLOBAL char *Bvc = reinterpret_cast<const FI_GLOBAL char *>(Bv);
-    const size_t word_bytes = (size_t)v.n_pad * 16;  // one word of every variant
-    // words in pairs: lane half h reads word w + h whole
-    const uint32_t hw = h * (uint32_t)word_bytes;
-    const uint32_t ol = r * 16 + hw;
-    // the last step of an odd word count: lanes of half 1 read word w itself,
-    // their A rows from the zero rows of padding variant n
-    const uint32_t oat = h ? (n - a0) * 16 : r * 16;
-    auto load_words = [&](uint32_t w, auto tail, u64 (&x)[4]) {
-      const FI_GLOBAL char *sa = Bvc + (size_t)w * word_bytes + (size_t)a0 * 16;
-      const FI_GLOBAL char *sj = Bvc + (size_t)w * word_bytes + (size_t)j0 * 16;
-      constexpr bool kTail = decltype(tail)::value;
-      const v4u qa = ld128(sa, kTail ? oat : ol);  // both rows of the lane's variants
-      const v4u qj = ld128(sj, kTail ? ol - hw : ol);
-      x[0] = (u64)qa[0] | ((u64)qa[1] << 32);
-      x[1] = (u64)qa[2] | ((u64)qa[3] << 32);
-      x[2] = (u64)qj[0] | ((u64)qj[1] << 32);
-      x[3] = (u64)qj[2] | ((u64)qj[3] << 32);
-    };
-    const auto ops = [](const u64 (&x)[4], int half, v8i (&E)[4]) {
-      const int sh = 32 * half;
-      E[0] = expand32_fp4_a((uint32_t)(x[0] >> sh));
-      E[1] = expand32_fp4_a((uint32_t)(x[1] >> sh));
-      E[2] = expand32_fp4_b((uint32_t)(x[2] >> sh));
-      E[3] = expand32_fp4_b((uint32_t)(x[3] >> sh));
-    };
-    if constexpr (FMT == kMfmaF4Narrow) contract_fp4_narrow<2, 4>(load_words, ops, v.W0, v.W1, Q);
-    else if constexpr (FMT == kMfmaF4Dual)
-      contract_fp4_dual<2, 4>(load_words, ops, v.W0, v.W1, bit_len(v.m0), Q);
-    else contract_fp4<2, 4>(load_words, ops, v.W0, v.W1, acc0, acc1);
+    pairs_contract_fp4<FMT>(v, a0, j0, lane, acc0, acc1, Q);
   } else {
     zero_acc(acc0, acc1);
     auto load_words = [&](uint32_t w, u64 (&x)[4]) {
@@ -2226,6 +2237,56 @@ void launch_mfma(const Globals &g, int order, int fmt, int grid, hipStream_t s) 
     else if (fmt == kMfmaF4Narrow) hipLaunchKernelGGL((mfma_kernel<2, kMfmaF4Narrow>), gd, bd, lds, s, g);
     else hipLaunchKernelGGL((mfma_kernel<2, kMfmaF4Dual>), gd, bd, lds, s, g);
   }
+}
+
+// The packed pair tables (orders 3-5 on the matrix cores, jobs of fewer than
+// 16,384 samples) by the order-2 contraction: for every pair a < j, its four
+// {0,1}^2 counts of both classes, 4 c0 | 4 c1 << 16 each, at pairs4[a][j] as
+// [g_a][g_j].  Grid: x = tile of the upper triangle of 64-variant blocks
+// (row A, column B >= A, row by row), z = job; a wave takes 32 x 32 pairs.
+// Two-accumulator contraction for every job (counts below 2^14 per class).
+__global__ __launch_bounds__(kMfmaWaves * 64, 2) void pairs4_kernel(Globals g) {
+  const JobDesc *jd = g.jobs + blockIdx.z;
+  JV v = load_view(jd);
+  uint4 *PT4 = uni_ptr(as_const(jd)->pairs4);
+  if (PT4 == nullptr) return;
+  const JobState *st = v.st;
+  if (uni((uint32_t)st->status) != 0) return;
+  v.W0 = uni(st->W0);
+  v.W1 = uni(st->W1);
+  const uint32_t n = v.n, nb = (n + 63) / 64;
+  uint32_t t = blockIdx.x, A = 0;
+  while (A < nb && t >= nb - A) {
+    t -= nb - A;
+    ++A;
+  }
+  if (A >= nb) return;
+  const uint32_t B = A + t;
+  const uint32_t wave = uni(threadIdx.x >> 6), lane = lane_id();
+  const uint32_t a0 = 64 * A + 32 * (wave >> 1), j0 = 64 * B + 32 * (wave & 1);
+  // a wave without a pair a < j < n has nothing to store
+  if (a0 + 1 >= n || j0 >= n || j0 + 31 <= a0) return;
+  v16i acc0[2][2], acc1[2][2];
+  uint32_t Q[2][2][16];
+  pairs_contract_fp4<kMfmaF4Narrow>(v, a0, j0, lane, acc0, acc1, Q);
+  // lane: column j = j0 + (lane mod 32); register e = 4 q + i: row a = a0 +
+  // 8 q + 4 h + i; block (g_a, g_j)
+  const uint32_t r = lane & 31, h = lane >> 5, j = j0 + r;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t a = a0 + 8 * q + 4 * h + i;
+      const int e = 4 * q + i;
+      if (a < j && j < n)
+        PT4[(size_t)a * v.n_pad + j] =
+            make_uint4(Q[0][0][e] << 2, Q[0][1][e] << 2, Q[1][0][e] << 2, Q[1][1][e] << 2);
+    }
+}
+
+void launch_pairs4(const Globals &g, uint32_t max_n, hipStream_t s) {
+  const uint32_t nb = (max_n + 63) / 64;
+  hipLaunchKernelGGL(pairs4_kernel, dim3(nb * (nb + 1) / 2, 1, g.n_jobs), dim3(kMfmaWaves * 64), 0, s, g);
 }
 
 }  // namespace fiuncho

@@ -310,8 +310,7 @@ __global__ __launch_bounds__(kScanWaves * 64) void pairs_kernel(Globals g) {
   const JobDesc *jd = g.jobs + blockIdx.z;
   JV v = load_view(jd);
   uint32_t *PT = uni_ptr(as_const(jd)->pairs);
-  uint4 *PT4 = uni_ptr(as_const(jd)->pairs4);
-  if (PT == nullptr && PT4 == nullptr) return;
+  if (PT == nullptr) return;  // packed tables (pairs4) come from pairs4_kernel
   const JobState *st = v.st;
   if (uni((uint32_t)st->status) != 0) return;
   v.W0 = uni(st->W0);
@@ -339,15 +338,9 @@ __global__ __launch_bounds__(kScanWaves * 64) void pairs_kernel(Globals g) {
   for (int p = 0; p < 8; ++p) {
     const uint32_t ap = a_first + p;
     if (ap <= n - 2 && j < n && j > ap) {
-      if (PT4) {
-        PT4[(size_t)ap * v.n_pad + j] =
-            make_uint4(pack_x4(acc[p][0][0][0], acc[p][1][0][0]), pack_x4(acc[p][0][0][1], acc[p][1][0][1]),
-                       pack_x4(acc[p][0][1][0], acc[p][1][1][0]), pack_x4(acc[p][0][1][1], acc[p][1][1][1]));
-      } else {
-        uint4 *dst = reinterpret_cast<uint4 *>(PT + ((size_t)ap * v.n_pad + j) * 8);
-        dst[0] = make_uint4(acc[p][0][0][0], acc[p][1][0][0], acc[p][0][0][1], acc[p][1][0][1]);
-        dst[1] = make_uint4(acc[p][0][1][0], acc[p][1][1][0], acc[p][0][1][1], acc[p][1][1][1]);
-      }
+      uint4 *dst = reinterpret_cast<uint4 *>(PT + ((size_t)ap * v.n_pad + j) * 8);
+      dst[0] = make_uint4(acc[p][0][0][0], acc[p][1][0][0], acc[p][0][0][1], acc[p][1][0][1]);
+      dst[1] = make_uint4(acc[p][0][1][0], acc[p][1][1][0], acc[p][0][1][1], acc[p][1][1][1]);
     }
   }
 }
