@@ -410,13 +410,8 @@ struct Order3Parts {
 
 template <typename Visit>
 __device__ __forceinline__ void walk_order3(const Order3Parts &q, Visit &&visit) {
-  uint32_t sum[2] = {0, 0};
-  uint32_t x2z[2][2][2], t2yz[2][2][2];  // [c][x or y][z]
-  auto cell = [&](uint32_t n0, uint32_t n1) {
-    sum[0] += n0;
-    sum[1] += n1;
-    visit(n0, n1);
-  };
+  uint32_t x2z[2][2][2], t2yz[2][2][2], x22[2][2];  // [c][x or y][z], [c][x]
+  auto cell = [&](uint32_t n0, uint32_t n1) { visit(n0, n1); };
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -455,8 +450,8 @@ __device__ __forceinline__ void walk_order3(const Order3Parts &q, Visit &&visit)
     uint32_t t[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c)
-      t[c] = q.Ma[x][c] - q.ab[x * 4 + c] - q.ab[x * 4 + 2 + c] - x2z[c][x][0] - x2z[c][x][1];
-    cell(t[0], t[1]);  // (x, 2, 2)
+      x22[c][x] = q.Ma[x][c] - q.ab[x * 4 + c] - q.ab[x * 4 + 2 + c] - x2z[c][x][0] - x2z[c][x][1];
+    cell(x22[0][x], x22[1][x]);  // (x, 2, 2)
   }
 #pragma unroll
   for (int y = 0; y < 2; ++y) {
@@ -474,7 +469,15 @@ __device__ __forceinline__ void walk_order3(const Order3Parts &q, Visit &&visit)
       t[c] = q.Mj[z][c] - q.aj[z * 2 + c] - q.aj[4 + z * 2 + c] - t2yz[c][0][z] - t2yz[c][1][z];
     cell(t[0], t[1]);  // (2, 2, z)
   }
-  visit(q.m[0] - sum[0], q.m[1] - sum[1]);  // (2, 2, 2)
+  // (2, 2, 2): the cells (x, 2, 2), x = 0, 1, 2, add up to the (b, j) pair's
+  // count at (2, 2), which is the class size less the variants' {0,1} counts
+  // plus the pair's {0,1}^2 counts
+  uint32_t t[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+    t[c] = q.m[c] - q.Mb[0][c] - q.Mb[1][c] - q.Mj[0][c] - q.Mj[1][c] + q.bj[c] + q.bj[2 + c] +
+           q.bj[4 + c] + q.bj[6 + c] - x22[c][0] - x22[c][1];
+  visit(t[0], t[1]);
 }
 
 // The same walk on packed counts: both classes of every count in one
@@ -493,12 +496,8 @@ __device__ __forceinline__ void walk_order3_packed(const uint32_t (&D)[2][2][2],
                                                    const uint32_t (&Ma)[2], const uint32_t (&Mb)[2],
                                                    const uint32_t (&Mj)[2], uint32_t m,
                                                    Visit &&visit) {
-  uint32_t sum = 0;
-  auto cell = [&](uint32_t p) {
-    sum += p;
-    visit(p);
-  };
-  uint32_t x2z[2][2], t2yz[2][2];
+  auto cell = [&](uint32_t p) { visit(p); };
+  uint32_t x2z[2][2], t2yz[2][2], x22[2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -524,12 +523,16 @@ __device__ __forceinline__ void walk_order3_packed(const uint32_t (&D)[2][2][2],
       cell(t2yz[y][z]);  // (2, y, z)
     }
 #pragma unroll
-  for (int x = 0; x < 2; ++x) cell(Ma[x] - ab[x][0] - ab[x][1] - x2z[x][0] - x2z[x][1]);  // (x, 2, 2)
+  for (int x = 0; x < 2; ++x) {
+    x22[x] = Ma[x] - ab[x][0] - ab[x][1] - x2z[x][0] - x2z[x][1];
+    cell(x22[x]);  // (x, 2, 2)
+  }
 #pragma unroll
   for (int y = 0; y < 2; ++y) cell(Mb[y] - ab[0][y] - ab[1][y] - t2yz[y][0] - t2yz[y][1]);  // (2, y, 2)
 #pragma unroll
   for (int z = 0; z < 2; ++z) cell(Mj[z] - aj[0][z] - aj[1][z] - t2yz[0][z] - t2yz[1][z]);  // (2, 2, z)
-  visit(m - sum);  // (2, 2, 2)
+  // (2, 2, 2) from the (b, j) pair's count at (2, 2), as in walk_order3
+  visit(m - Mb[0] - Mb[1] - Mj[0] - Mj[1] + bj[0][0] + bj[0][1] + bj[1][0] + bj[1][1] - x22[0] - x22[1]);
 }
 
 // Class counts (c0, c1) as one packed register of byte offsets 4 c0 | 4 c1 << 16

@@ -394,10 +394,13 @@ __device__ __forceinline__ void contract_fp4_narrow(Load &&load_words, Ops &&ops
         Q[x][y][e] = ((P0[x][y][e >> 1] >> (16 * (e & 1))) & 0xFFFFu) | ((uint32_t)f[x][y][e] << 16);
 }
 
-// Both classes with FP4 operands for the dual kernels: class-1 products are
-// scaled by 2^s (s = bit length of m0, given by the caller), so the single
-// FP32 accumulator holds c0 + 2^s c1 < 2^24, an exact integer; Q as for the
-// narrow kernels.
+// Both classes with FP4 operands for the dual kernels: class-0 products are
+// scaled by 2^2 and class-1 products by 2^(s+2) (s = bit length of m0, given
+// by the caller), so the single FP32 accumulator holds u = 4 (c0 + 2^s c1), a
+// multiple of 4 below 2^26 and so an exact integer like c0 + 2^s c1 < 2^24.
+// Q holds 4 c0 | 4 c1 << 16 (the scoring's byte offsets; c0, c1 < 2^13):
+// u >> (s + 2) = c1 since 4 c0 < 2^(s+2), and u + c1 (2^18 - 2^(s+2)) moves
+// 4 c1 to bit 16.
 template <int kDepth, int kRaw, int FA = 2, typename Load, typename Ops>
 __device__ __forceinline__ void contract_fp4_dual(Load &&load_words, Ops &&ops, uint32_t W0,
                                                   uint32_t W1, uint32_t s,
@@ -409,9 +412,9 @@ __device__ __forceinline__ void contract_fp4_dual(Load &&load_words, Ops &&ops, 
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) f[x][y][e] = 0.f;
-  mfma_class_fp4<kDepth, kRaw, FA>(load_words, ops, 0, W0, f);
-  mfma_class_fp4<kDepth, kRaw, FA>(load_words, ops, W0, W0 + W1, f, kScaleOne + (int)s);
-  const uint32_t low = (1u << s) - 1;
+  mfma_class_fp4<kDepth, kRaw, FA>(load_words, ops, 0, W0, f, kScaleOne + 2);
+  mfma_class_fp4<kDepth, kRaw, FA>(load_words, ops, W0, W0 + W1, f, kScaleOne + 2 + (int)s);
+  const uint32_t k = (1u << 18) - (1u << (s + 2));
 #pragma unroll
   for (int x = 0; x < FA; ++x)
 #pragma unroll
@@ -419,8 +422,15 @@ __device__ __forceinline__ void contract_fp4_dual(Load &&load_words, Ops &&ops, 
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const uint32_t u = (uint32_t)f[x][y][e];
-        Q[x][y][e] = (u & low) | ((u >> s) << 16);
+        Q[x][y][e] = u + (u >> (s + 2)) * k;
       }
+}
+
+// A count register of the packed contractions as 4 c0 | 4 c1 << 16: the dual
+// kernels' registers already are, the narrow kernels' hold c0 | c1 << 16
+template <bool kDual>
+__device__ __forceinline__ uint32_t packed_x4(uint32_t q) {
+  return kDual ? q : q << 2;
 }
 
 // bit length of x (0 for 0)
@@ -432,7 +442,10 @@ template <int FMT>
 __device__ __forceinline__ void own_counts(const v16i (&acc0)[2][2], const v16i (&acc1)[2][2],
                                            const uint32_t (&Q)[2][2][16], int x, int y, int e,
                                            uint32_t (&o)[2]) {
-  if constexpr (FMT == kMfmaF4Narrow || FMT == kMfmaF4Dual) {
+  if constexpr (FMT == kMfmaF4Dual) {
+    o[0] = (Q[x][y][e] & 0xFFFFu) >> 2;
+    o[1] = Q[x][y][e] >> 18;
+  } else if constexpr (FMT == kMfmaF4Narrow) {
     o[0] = Q[x][y][e] & 0xFFFFu;
     o[1] = Q[x][y][e] >> 16;
   } else {
@@ -561,7 +574,7 @@ __device__ __forceinline__ void wave_pairs(const JV &v, uint32_t a0, uint32_t j0
 #pragma unroll
             for (int fa = 0; fa < 2; ++fa)
 #pragma unroll
-              for (int fb = 0; fb < 2; ++fb) C4[fa][fb] = Q[fa][fb][4 * q + i] << 2;
+              for (int fb = 0; fb < 2; ++fb) C4[fa][fb] = packed_x4<FMT == kMfmaF4Dual>(Q[fa][fb][4 * q + i]);
             const bool active = a < j && j < n;
             float fs = mc.c;
             if (active) {
@@ -811,9 +824,12 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
 #pragma unroll
             for (int fb = 0; fb < 2; ++fb)
 #pragma unroll
-              for (int g = 0; g < 2; ++g) D4[g][f][fb] = Q[f][fb][4 * q + 2 * s + g] << 2;
+              for (int g = 0; g < 2; ++g) D4[g][f][fb] = packed_x4<FMT == kMfmaF4Dual>(Q[f][fb][4 * q + 2 * s + g]);
           const bool active = a < b && j < n;
-          uint32_t fs = mc.q0;  // fixed point: the LDS table holds Fq
+          // fixed point (the LDS table holds Fq): the class terms f(n0) + f(n1)
+          // added to fs, the f(n0 + n1) terms to fm (three-input adds take two
+          // terms at a time), the score is fs - fm
+          uint32_t fs = mc.q0, fm = 0;
           if (active) {
             constexpr int kGroup = 3;
             uint32_t o0[kGroup], o1[kGroup];
@@ -830,13 +846,15 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
                   f01[x] = *(const FI_LDS uint32_t *)(Fb + o0[x] + o1[x]);
                 }
 #pragma unroll
-                for (int x = 0; x < kGroup; ++x) fs += f0[x] + f1[x] - f01[x];
+                for (int x = 0; x < kGroup; ++x) fs += f0[x] + f1[x];
+                fm += f01[0] + f01[1] + f01[2];
                 pin_sum(fs);
+                pin_sum(fm);
                 nc = 0;
               }
             });
           }
-          if (emit_with(v, active, mi_fixed(fs, mc),
+          if (emit_with(v, active, mi_fixed(fs - fm, mc),
                         [&] { return lex_rank_prefix(g, n, 3, pre) + (u64)(j - b - 1); }, thr,
                         lane) >= kRefreshAppends)
             thr = current_threshold_lanes(v);
@@ -1602,8 +1620,8 @@ __device__ __forceinline__ void wave_t4(const Globals &g, const JV &v, uint32_t 
         const uint32_t lo = Q[f][fb][a], hi = Q[f][fb][8 + a];
         const uint32_t own = gl ? hi : lo;
         const uint32_t recv = xor1(gl ? lo : hi);
-        t3[1].D[a >> 2][(a >> 1) & 1][a & 1] = (gl ? recv : own) << 2;
-        t3[2].D[a >> 2][(a >> 1) & 1][a & 1] = (gl ? own : recv) << 2;
+        t3[1].D[a >> 2][(a >> 1) & 1][a & 1] = packed_x4<DUAL>(gl ? recv : own);
+        t3[2].D[a >> 2][(a >> 1) & 1][a & 1] = packed_x4<DUAL>(gl ? own : recv);
       }
       {
         const uint32_t J = jj[fb];
@@ -1637,16 +1655,25 @@ __device__ __forceinline__ void wave_t4(const Globals &g, const JV &v, uint32_t 
       }
       const uint32_t j = jv[fb];
       const bool active = valid && j < n;
-      uint32_t fs = mc.q0;
+      // the f(n0) + f(n1) terms to fs, the f(n0 + n1) terms to fm, three at
+      // a time: the score is fs - fm
+      uint32_t fs = mc.q0, fm = 0;
       if (active)
         walk3_zip_packed<3>(t3, [&](const uint32_t (&cell)[3]) {
-          fs += term(cell[1]);
-          fs += term(cell[2]);
-          fs += term(cell[0] - cell[1] - cell[2]);
+          const uint32_t p[3] = {cell[1], cell[2], cell[0] - cell[1] - cell[2]};
+          uint32_t f01[3];
+#pragma unroll
+          for (int x = 0; x < 3; ++x) {
+            const uint32_t o0 = p[x] & 0xFFFFu, o1 = p[x] >> 16;
+            fs += *(const FI_LDS uint32_t *)(Fb + o0) + *(const FI_LDS uint32_t *)(Fb + o1);
+            f01[x] = *(const FI_LDS uint32_t *)(Fb + o0 + o1);
+          }
+          fm += f01[0] + f01[1] + f01[2];
           pin_sum(fs);
+          pin_sum(fm);
         });
       const uint32_t pre[3] = {x, y, b};
-      if (emit_with(v, active, mi_fixed(fs, mc),
+      if (emit_with(v, active, mi_fixed(fs - fm, mc),
                     [&] { return lex_rank_prefix(g, n, 4, pre) + (u64)(j - b - 1); }, thr,
                     lane) >= kRefreshAppends)
         thr = current_threshold_lanes(v);
@@ -1739,8 +1766,8 @@ __device__ __forceinline__ void wave_t5(const Globals &g, const JV &v, uint32_t 
       for (int e = 0; e < 16; ++e) {
         const uint32_t own = gl ? Q[0][1][e] : Q[0][0][e];
         const uint32_t recv = xor1(gl ? Q[0][0][e] : Q[0][1][e]);
-        cells[e >> 3][0][e & 7] = (gl ? recv : own) << 2;
-        cells[e >> 3][1][e & 7] = (gl ? own : recv) << 2;
+        cells[e >> 3][0][e & 7] = packed_x4<DUAL>(gl ? recv : own);
+        cells[e >> 3][1][e & 7] = packed_x4<DUAL>(gl ? own : recv);
       }
     }
     // (a lane past the last prefix scores nothing; it reads the tables of
@@ -2033,8 +2060,8 @@ __global__ __launch_bounds__(kMfmaWaves * 64, 2) void quads_kernel(Globals g) {
           const uint32_t lo = Q[f][fb][a], hi = Q[f][fb][8 + a];
           const uint32_t own = gl ? hi : lo;
           const uint32_t recv = xor1(gl ? lo : hi);
-          cell[a][0] = (gl ? recv : own) << 2;
-          cell[a][1] = (gl ? own : recv) << 2;
+          cell[a][0] = dual ? packed_x4<true>(gl ? recv : own) : packed_x4<false>(gl ? recv : own);
+          cell[a][1] = dual ? packed_x4<true>(gl ? own : recv) : packed_x4<false>(gl ? own : recv);
         }
         if (q < nq && j < n) {
           v4u *dst = QT + quad_entry(n, hc + q, c, j) * 4;
