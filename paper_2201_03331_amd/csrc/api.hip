@@ -114,10 +114,23 @@ void build_rows(uint32_t n, uint32_t k, uint32_t path, std::vector<u64> &row_sta
     }
     return;
   }
-  if (path == fiuncho::kPathPairs || path == fiuncho::kPathMfma3) {
-    // rows b = 1 .. n-2; groups of first variants (kScanWaves * kOrder3Prefixes
-    // on the popcount kernel, 32 on the matrix cores) x blocks of 64 last variants
-    const u64 G = path == fiuncho::kPathPairs ? (u64)fiuncho::kScanWaves * fiuncho::kOrder3Prefixes : 32;
+  if (path == fiuncho::kPathMfma3) {
+    // rows (jb, b), jb-major: block jb of 64 last variants j = b + 1 + 64 jb
+    // + [0, 64) of middle variant b = 1 .. n-2-64 jb; a row's tiles are its
+    // groups of 32 first variants.  Tiles taken in this order work on a
+    // narrow band of last variants at a time, so the pair-table entries and
+    // bitset rows in use stay within each XCD's L2
+    for (u64 jb = 0; 64 * jb + 3 <= n; ++jb)
+      for (u64 b = 1; b + 2 + 64 * jb <= n; ++b) {
+        acc += ceil_div(b, 32);
+        row_start.push_back(acc);
+      }
+    return;
+  }
+  if (path == fiuncho::kPathPairs) {
+    // rows b = 1 .. n-2; groups of kScanWaves * kOrder3Prefixes first
+    // variants x blocks of 64 last variants
+    const u64 G = (u64)fiuncho::kScanWaves * fiuncho::kOrder3Prefixes;
     for (u64 b = 1; b + 2 <= n; ++b) {
       const u64 groups = ceil_div(b, G);
       acc += groups * ceil_div(n - 1 - b, 64);
@@ -178,10 +191,18 @@ void for_each_tile(uint32_t n, uint32_t k, uint32_t path, Fn fn) {
     }
     return;
   }
+  if (path == fiuncho::kPathMfma3) {
+    // rows (jb, b) jb-major, a row's tiles its groups of 32 first variants
+    for (u64 jb = 0; 64 * jb + 3 <= N; ++jb)
+      for (u64 b = 1; b + 2 + 64 * jb <= N; ++b) {
+        const u64 j0 = b + 1 + 64 * jb;
+        for (u64 p0 = 0; p0 < b; p0 += 32) fn(lt++, std::min<u64>(32, b - p0) * std::min<u64>(64, N - j0));
+      }
+    return;
+  }
   // rows b (second-to-last variant): groups of prefixes x blocks of 64 last variants
-  const bool by_pairs = path == fiuncho::kPathPairs || path == fiuncho::kPathMfma3;
+  const bool by_pairs = path == fiuncho::kPathPairs;
   const u64 G = path == fiuncho::kPathPairs    ? (u64)fiuncho::kScanWaves * fiuncho::kOrder3Prefixes
-                : path == fiuncho::kPathMfma3  ? 32
                 : path == fiuncho::kPathMfma4t ? 16
                 : path == fiuncho::kPathMfma5q ? 8
                                                : (u64)fiuncho::kScanWaves;

@@ -2211,11 +2211,20 @@ __global__ __launch_bounds__(kMfmaWaves * 64, FMT == kMfmaF4Dual ? 3 : 2) void m
     const u64 local = uni64(lt - rows[rl]);
     if (ORDER == 3) {
       if (v.path != kPathMfma3) continue;
-      // row b = rl + 1: groups of 32 first variants x blocks of 64 last variants
-      const uint32_t b = rl + 1;
-      const uint32_t nj = (v.n - 1 - b + 63) / 64;
-      const u64 grp = local / nj;
-      const uint32_t jb = (uint32_t)(local - grp * nj);
+      // rows (jb, b), jb-major: jb's rows are b = 1 .. n - 2 - 64 jb, so the
+      // rows before jb number C(jb) = jb (n - 2) - 32 jb (jb - 1) = (n + 30)
+      // jb - 32 jb^2; the row's tiles are its groups of 32 first variants
+      const uint32_t n = v.n;
+      auto rows_before = [&](uint32_t x) { return (u64)x * (n + 30) - 32 * (u64)x * x; };
+      const double disc = (double)(n + 30) * (n + 30) - 128.0 * (double)rl;
+      uint32_t jb = (uint32_t)max(0.0, ((double)(n + 30) - sqrt(max(disc, 0.0))) / 64.0);
+      while (jb > 0 && rows_before(jb) > rl) --jb;
+      while (64 * (jb + 1) + 3 <= n && rows_before(jb + 1) <= rl) ++jb;
+      jb = uni(jb);
+      const uint32_t b = uni(rl - (uint32_t)rows_before(jb) + 1);
+      // (never taken: the decode above keeps b in [1, n - 2 - 64 jb])
+      if (b + 2 + 64 * jb > n) continue;
+      const u64 grp = local;
       const uint32_t a_first = (uint32_t)grp * 32 + 16 * (wave >> 1);
       const uint32_t j0 = b + 1 + 64 * jb + 32 * (wave & 1);
       // a wave without a prefix a < b or a last variant j < n has nothing to
