@@ -65,6 +65,16 @@ def test_matrix_core_tiles_partition_order2(n, monkeypatch):
         assert int(c.sum()) == math.comb(n, 2)
 
 
+@pytest.mark.parametrize("n", [3, 4, 66, 67, 130, 131, 300])
+def test_matrix_core_tiles_partition_order3(n, monkeypatch):
+    """Order-3 matrix-core tiles (rows of (block of last variants, middle
+    variant)) hold every triple once: the shards' counts add up to C(n, 3)."""
+    monkeypatch.setenv("FIUNCHO_ORDER3_MFMA", "4")
+    for p in (1, 3, 8):
+        c = fiuncho.shard_counts(n, 1000, 3, p, fiuncho.TILE_ROUND_ROBIN)
+        assert int(c.sum()) == math.comb(n, 3)
+
+
 def test_balance_of_section_5_1():
     """Eq. 4 over the configurations of section 5.1 (units in multiples of 18
     from 18 to 522).  Recomputed, the paper's scheme peaks at 3.08 percent
