@@ -881,6 +881,15 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
 #pragma unroll
         for (int c = 0; c < 2; ++c) Mj[x][c] = marg[(size_t)jj * 6 + 2 * x + c];
       load_pair(PT + ((size_t)b * v.n_pad + jj) * 8, bj);
+      // the narrow kernel (registers to spare at 2 waves per SIMD) loads each
+      // prefix's (a, j) pair entry one prefix ahead, as the packed walk does
+      constexpr bool kAhead = FMT == kMfmaF4Narrow;
+      auto load_aj = [&](int i, uint32_t (&o)[8]) {
+        const uint32_t a = prefix_of(i >> 1, i & 1);
+        load_pair(PT + ((size_t)(a < b ? a : b - 1) * v.n_pad + jj) * 8, o);
+      };
+      uint32_t aj_next[8];
+      if constexpr (kAhead) load_aj(0, aj_next);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
 #pragma unroll
@@ -902,7 +911,13 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
           const uint32_t aa = a < b ? a : b - 1;
           uint32_t ab[8], aj[8], Ma[2][2];
           load_pair(PT + ((size_t)aa * v.n_pad + b) * 8, ab);
-          load_pair(PT + ((size_t)aa * v.n_pad + jj) * 8, aj);
+          if constexpr (kAhead) {
+#pragma unroll
+            for (int x = 0; x < 8; ++x) aj[x] = aj_next[x];
+            if (2 * q + s < 7) load_aj(2 * q + s + 1, aj_next);
+          } else {
+            load_pair(PT + ((size_t)aa * v.n_pad + jj) * 8, aj);
+          }
 #pragma unroll
           for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -2150,6 +2165,9 @@ __global__ __launch_bounds__(kMfmaWaves * 64, FMT == kMfmaF4Dual ? 3 : 2) void m
   uint32_t f_job = ~0u;  // job whose table s_f holds (same in every thread)
   bool f_lds = false;
   RowHint hint;  // the row of the workgroup's last tile
+  // order 3: the block of last variants of the workgroup's last tile, and its job
+  const FI_CONST JobDesc *jb_job = nullptr;
+  uint32_t jb_hint = 0;
   if (FMT == kMfmaF4Narrow || FMT == kMfmaF4Dual) {
     if (!any_job(g, [](uint32_t m0, uint32_t m1, uint32_t m) {
           return (bit_len(m0) + bit_len(m1) <= 24 && m + 1 <= mfma_f_entries(kMfmaF4Dual)) ==
@@ -2214,13 +2232,19 @@ __global__ __launch_bounds__(kMfmaWaves * 64, FMT == kMfmaF4Dual ? 3 : 2) void m
       // rows (jb, b), jb-major: jb's rows are b = 1 .. n - 2 - 64 jb, so the
       // rows before jb number C(jb) = jb (n - 2) - 32 jb (jb - 1) = (n + 30)
       // jb - 32 jb^2; the row's tiles are its groups of 32 first variants
+      // jb is searched from the workgroup's last one (its tiles mostly come
+      // in increasing order)
       const uint32_t n = v.n;
       auto rows_before = [&](uint32_t x) { return (u64)x * (n + 30) - 32 * (u64)x * x; };
-      const double disc = (double)(n + 30) * (n + 30) - 128.0 * (double)rl;
-      uint32_t jb = (uint32_t)max(0.0, ((double)(n + 30) - sqrt(max(disc, 0.0))) / 64.0);
+      if (jd != jb_job) {
+        jb_job = jd;
+        jb_hint = 0;
+      }
+      uint32_t jb = jb_hint;
       while (jb > 0 && rows_before(jb) > rl) --jb;
       while (64 * (jb + 1) + 3 <= n && rows_before(jb + 1) <= rl) ++jb;
       jb = uni(jb);
+      jb_hint = jb;
       const uint32_t b = uni(rl - (uint32_t)rows_before(jb) + 1);
       // (never taken: the decode above keeps b in [1, n - 2 - 64 jb])
       if (b + 2 + 64 * jb > n) continue;
