@@ -798,23 +798,24 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
     // a prefix's (a, j) pair-table entry (a lane's own: the pair-table reads
     // least likely to hit in L2) is loaded one prefix ahead of its scoring,
     // so that its latency overlaps the previous prefix's
-    auto entry_aj = [&](int i) {
+    auto entry = [&](int i, uint32_t col) {
       const uint32_t a = prefix_of(i >> 1, i & 1);
-      return PT4[(size_t)(a < b ? a : b - 1) * v.n_pad + jj];
+      return PT4[(size_t)(a < b ? a : b - 1) * v.n_pad + col];
     };
-    v4u qj_next = entry_aj(0);
+    v4u qj_next = entry(0, jj), qb_next = entry(0, b);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        const v4u qj = qj_next;
-        if (2 * q + s < 7) qj_next = entry_aj(2 * q + s + 1);
+        const v4u qj = qj_next, qb = qb_next;
+        if (2 * q + s < 7) {
+          qj_next = entry(2 * q + s + 1, jj);
+          qb_next = entry(2 * q + s + 1, b);
+        }
         const uint32_t a = prefix_of(q, s);
         const uint32_t aa = a < b ? a : b - 1;
-        const FI_GLOBAL v4u *row = PT4 + (size_t)aa * v.n_pad;
         uint32_t ab4[2][2], Ma4[2], aj4[2][2];
         {
-          const v4u qb = row[b];
           ab4[0][0] = qb[0];
           ab4[0][1] = qb[1];
           ab4[1][0] = qb[2];
