@@ -795,9 +795,9 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
       for (int x = 0; x < 2; ++x) Mj4[x] = pack_x4(marg[(size_t)jj * 6 + 2 * x], marg[(size_t)jj * 6 + 2 * x + 1]);
     }
     const FI_LDS char *Fb = (const FI_LDS char *)Fl;
-    // a prefix's (a, j) pair-table entry (a lane's own: the pair-table reads
-    // least likely to hit in L2) is loaded one prefix ahead of its scoring,
-    // so that its latency overlaps the previous prefix's
+    // a prefix's (a, j) and (a, b) pair-table entries are loaded one prefix
+    // ahead of its scoring, so that their latency overlaps the previous
+    // prefix's
     auto entry = [&](int i, uint32_t col) {
       const uint32_t a = prefix_of(i >> 1, i & 1);
       return PT4[(size_t)(a < b ? a : b - 1) * v.n_pad + col];
