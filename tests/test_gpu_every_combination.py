@@ -52,6 +52,10 @@ CASES = [
     # FP4, both classes in one accumulator (bitlen(m0) + bitlen(m1) <= 24)
     ("fp4-dual", 2, 260, 1000, 0.5, K.KERNEL_MFMA_FP4),
     ("fp4-dual", 3, 70, 700, 0.5, K.KERNEL_MFMA_FP4),
+    # order-3 tiles by block of last variants first: three blocks (jb = 0..2)
+    # and a ragged last one
+    ("fp4-dual", 3, 150, 200, 0.5, K.KERNEL_MFMA_FP4),
+    ("fp4-narrow", 3, 135, 9001, 0.5, K.KERNEL_MFMA_FP4),
     # words in pairs: one word per class (the odd step alone), and an even
     # class beside an odd one
     ("fp4-dual", 2, 90, 120, 0.5, K.KERNEL_MFMA_FP4),
