@@ -858,7 +858,8 @@ __device__ __forceinline__ void wave_prefix3(const Globals &g, const JV &v, uint
                 }
 #pragma unroll
                 for (int x = 0; x < kGroup; ++x) fs += f0[x] + f1[x];
-                fm += f01[0] + f01[1] + f01[2];
+#pragma unroll
+                for (int x = 0; x < kGroup; ++x) fm += f01[x];
                 // fs is kept in order (pin_sum); fm's additions are left to
                 // the compiler, which here saves instructions without spilling
                 pin_sum(fs);
